@@ -1,0 +1,160 @@
+/*
+ * psfd.h -- C ABI of the MI355X background-field PSFD / Lippmann-Schwinger solver.
+ *
+ * The library solves the EUV mask scattering problem of the paper "Pseudo-spectral
+ * frequency-domain method with background field decomposition and Green's function
+ * preconditioner": the absorber field E_mask on a periodic clip above a planar
+ * multilayer, from
+ *   - the discrete Lippmann-Schwinger system of eq. (18),
+ *       x - IFFT(F[G_L] . FFT(V x)) = IFFT(F[G_L] . FFT(V (E_inc + E_layer))),
+ *     V = k0^2 delta_eps, with the windowed dyadic Green's function of eqs. (13)-(17)
+ *     (windowed in z over the absorber thickness, exact per transverse order in x, y),
+ *   - the outer fixed point of eqs. (8)-(9): E_layer is the multilayer reflection
+ *     T_R (per transverse Fourier order, generalized reflection coefficients) of the
+ *     downgoing field at the multilayer surface, propagated up per order.
+ *
+ * Conventions
+ *   - lengths in nm; time dependence exp(-i w t); absorbing media have Im(eps) > 0.
+ *   - grid: nx, ny, nz powers of two, 4 <= nx, ny <= 256, 2 <= nz <= 128; x, y periodic
+ *     with period lx, ly (Floquet phase of the incidence); z covers the absorber
+ *     [0, t] with cell-centred planes z_k = (k + 1/2) t / nz; z = 0 is the multilayer.
+ *   - complex arrays are interleaved (re, im). Fields are ENVELOPES
+ *     u = E exp(-i (kx0 x + ky0 y)) laid out [3][nz][ny][nx] (component, z, y, x) with
+ *     sample (k, j, i) at x = i lx/nx, y = j ly/ny, z = z_k.
+ *   - the contrast delta_eps = eps - eps_bg is [nz][ny][nx].
+ *   - order amplitudes are [ny][nx][3] in FFT order: index (j, i) is the order
+ *     (n, m) = (fftfreq index of j, of i) with kx = kx0 + 2 pi m / lx.
+ *   - every device pointer is owned by the caller, must stay valid until the call
+ *     returns, and must not alias another argument unless stated.
+ *   - `stream` is a hipStream_t (0 = default stream); calls are ordered on it.
+ *   - every call returns PSFD_OK (0), PSFD_NOT_CONVERGED (> 0, outputs written and
+ *     info filled) or a negative error; psfd_last_error() gives a thread-local
+ *     message for the last failing call of the calling thread.
+ */
+#ifndef PSFD_H
+#define PSFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PSFD_OK = 0,
+  PSFD_NOT_CONVERGED = 1,
+  PSFD_ERR_INVALID_ARG = -1,
+  PSFD_ERR_UNSUPPORTED_SIZE = -2,
+  PSFD_ERR_OOM = -3,
+  PSFD_ERR_SINGULAR = -4, /* an order grazes the surface (beta = 0, Wood anomaly) */
+  PSFD_ERR_NONFINITE = -5,
+  PSFD_ERR_HIP = -6
+};
+
+enum { PSFD_TE = 0, PSFD_TM = 1 };
+enum { PSFD_FP64 = 0, PSFD_MIXED = 1 };             /* psfd_opts.precision */
+enum { PSFD_C64 = 0, PSFD_C128 = 1 };               /* dtype of psfd_apply */
+enum { PSFD_APPLY_TRANSPOSE = 1, PSFD_APPLY_K_ONLY = 2 }; /* psfd_apply flags */
+
+typedef struct { double eps_re, eps_im, thickness_nm; } psfd_layer; /* top to bottom */
+
+/* Problem statement (Sec. 2 and the experiment set-ups of Sec. 3). */
+typedef struct {
+  int32_t nx, ny, nz;
+  double lx_nm, ly_nm, t_nm;      /* clip period (x, y) and absorber thickness */
+  double wavelength_nm, eps_bg;   /* eps_bg real and positive (vacuum: 1) */
+  double theta_deg, phi_deg;      /* incidence polar angle and azimuth */
+  int32_t pol;                    /* PSFD_TE: E along s = (-sin phi, cos phi, 0); PSFD_TM: E along p- */
+  int32_t n_layers;
+  const psfd_layer* layers;       /* host array of n_layers layers, copied at plan creation */
+  double eps_sub_re, eps_sub_im;  /* substrate half-space */
+} psfd_problem;
+
+/* Solver options. rtol: relative residual of eq. (18) (GMRES, Saad & Schultz);
+ * outer_rtol: relative change of the reflected spectrum that ends the outer loop
+ * of eqs. (8)-(9) (<= 0: use rtol); restart: GMRES(m), 1 <= m <= 32;
+ * max_iters: Arnoldi steps per linear solve; max_outer: outer iterations;
+ * precision: PSFD_FP64, or PSFD_MIXED (FP32 Arnoldi cycles, FP64 residual and
+ * solution: each restart recomputes the residual in FP64); inner_eta: relative
+ * reduction asked of one FP32 cycle (<= 0: 1e-4). */
+typedef struct {
+  double rtol, outer_rtol;
+  int32_t restart, max_iters, max_outer, precision;
+  double inner_eta;
+} psfd_opts;
+
+typedef struct {
+  int32_t iters;          /* Arnoldi steps, all outer iterations */
+  int32_t outer_iters;
+  int32_t cycles;         /* GMRES cycles (FP64 residual evaluations) */
+  int32_t status;
+  double rel_residual;    /* last FP64 relative residual of eq. (18) */
+  double outer_change;    /* last relative change of the reflected spectrum */
+  double mono_residual;   /* FP64 ||e_bg - (I - (K + R K_top) V) u|| / ||e_bg|| of the total field */
+} psfd_info;
+
+typedef struct psfd_plan psfd_plan;
+typedef struct psfd_server psfd_server;
+
+/* Build the FP64 tables of a problem (orders, reflection matrices T_R from the
+ * recursive generalized reflection of the stack, kernel scalars, FFT twiddles)
+ * on the current HIP device. opts may be NULL (defaults: rtol 1e-6, restart 30,
+ * max_iters 5000, max_outer 100, PSFD_MIXED). Errors: INVALID_ARG,
+ * UNSUPPORTED_SIZE, SINGULAR, OOM, HIP. */
+int psfd_plan_create(const psfd_problem* prob, const psfd_opts* opts, psfd_plan** out);
+void psfd_plan_destroy(psfd_plan* plan);
+/* Device bytes a solve with this plan allocates (tables + Krylov workspace). */
+int psfd_plan_footprint(const psfd_plan* plan, size_t* device_bytes);
+
+/* One operator apply (eq. (18)): y = x - K(V x), or y = K(V x) with
+ * PSFD_APPLY_K_ONLY; with PSFD_APPLY_TRANSPOSE the bilinear transpose (kernel at
+ * the negated wavevector). d_deps [nz][ny][nx], d_x and d_y [3][nz][ny][nx], all of
+ * `dtype` (complex64 or complex128), device memory; d_y must not alias d_x.
+ * Uses a plan-owned scratch field (allocated on first use). */
+int psfd_apply(psfd_plan* plan, const void* d_deps, const void* d_x, void* d_y, int dtype, int flags,
+               void* stream);
+
+/* Full solve: outer reflection loop around GMRES on eq. (18). d_deps complex128
+ * [nz][ny][nx]; outputs (complex128, device): d_emask [3][nz][ny][nx] = E_mask
+ * envelope, d_orders [ny][nx][3] = reflected order amplitudes at z = t (may be
+ * NULL). Blocks until done. Returns NOT_CONVERGED when an iteration limit stops it. */
+int psfd_solve(psfd_plan* plan, const void* d_deps, void* d_emask, void* d_orders, psfd_info* info,
+               void* stream);
+
+/* Gradient of J = sum_{q in orders} ||a_q||^2 with respect to delta_eps
+ * (a_q: reflected order amplitudes). d_orders_sel: host array of n_sel (m, n)
+ * integer pairs. d_grad (complex128 [nz][ny][nx], device) receives
+ * dJ/dRe + i dJ/dIm. Runs the forward solve, then the transposed solve. *J_out
+ * (may be NULL) receives J. */
+int psfd_solve_adjoint(psfd_plan* plan, const void* d_deps, const int32_t* orders_sel, int32_t n_sel,
+                       void* d_grad, double* J_out, psfd_info* info_fwd, psfd_info* info_adj, void* stream);
+
+/* Batched solves of instances of one grid shape (same nx, ny, nz, lx, ly, t,
+ * wavelength and stack; angles, polarisation and contrast per instance) in
+ * lock-step batched launches. probs[i] / d_deps[i] / d_emask[i] / d_orders[i]
+ * per instance (device pointers, complex128). info array of n. */
+int psfd_solve_batch(int32_t n, const psfd_problem* probs, const psfd_opts* opts, const void* const* d_deps,
+                     void* const* d_emask, void* const* d_orders, psfd_info* info, void* stream);
+
+/* Serving: continuous batching of solve requests admitted by device-memory
+ * footprint. The server owns a worker thread and its own HIP stream.
+ * hbm_budget: bytes the server may allocate for workspaces; max_slots: requests
+ * on the device at once. submit copies the problem; the caller's buffers must
+ * stay valid until poll reports done. */
+int psfd_server_create(size_t hbm_budget, int32_t max_slots, const psfd_opts* opts, psfd_server** out);
+int psfd_server_submit(psfd_server* srv, const psfd_problem* prob, const void* d_deps, void* d_emask,
+                       void* d_orders, uint64_t* ticket);
+/* done = 1 once finished; info filled then. latency_s (may be NULL): submit to
+ * completion wall time. */
+int psfd_server_poll(psfd_server* srv, uint64_t ticket, int32_t* done, psfd_info* info, double* latency_s);
+int psfd_server_destroy(psfd_server* srv);
+
+const char* psfd_status_string(int status);
+const char* psfd_last_error(void);
+const char* psfd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSFD_H */

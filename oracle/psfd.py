@@ -172,7 +172,7 @@ class Setup:
         self.KY = np.broadcast_to(self.ky[:, None], (ny, nx)).copy()
         self.kt = np.hypot(self.KX, self.KY)
         self.beta = kz_branch(self.kbg ** 2 - self.kt ** 2)          # (ny, nx)
-        if np.any(np.abs(self.beta) < 1e-12 * self.kbg):
+        if np.any(np.abs(self.beta) < 1e-6 * self.kbg):
             raise ValueError("Wood anomaly: an order grazes (beta = 0)")
         keep = np.ones((ny, nx), dtype=bool)
         if nyquist_zero:

@@ -1,0 +1,215 @@
+"""Python front end over the C ABI: torch tensors in, torch tensors out.
+
+PyTorch only provides device memory and the current HIP stream; every
+operation runs in libpsfd.so. Names follow the C entry points.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib as L
+
+
+def _c_problem(p) -> Tuple[L.psfd_problem, object]:
+    layers = (L.psfd_layer * max(1, len(p.layers)))()
+    for i, (e, d) in enumerate(p.layers):
+        e = complex(e)
+        layers[i] = L.psfd_layer(e.real, e.imag, float(d))
+    es = complex(p.eps_sub)
+    cp = L.psfd_problem(int(p.nx), int(p.ny), int(p.nz), float(p.lx_nm), float(p.ly_nm), float(p.t_nm),
+                        float(p.wavelength_nm), float(p.eps_bg), float(p.theta_deg), float(p.phi_deg),
+                        int(p.pol), len(p.layers), C.cast(layers, C.POINTER(L.psfd_layer)), es.real, es.imag)
+    return cp, layers
+
+
+def _c_opts(rtol=1e-6, outer_rtol=None, restart=30, max_iters=5000, max_outer=100, precision="mixed",
+            inner_eta=1e-4) -> L.psfd_opts:
+    prec = {"fp64": L.PSFD_FP64, "mixed": L.PSFD_MIXED}[precision] if isinstance(precision, str) else int(precision)
+    return L.psfd_opts(float(rtol), float(outer_rtol if outer_rtol is not None else rtol), int(restart),
+                       int(max_iters), int(max_outer), prec, float(inner_eta))
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Plan:
+    """A problem's FP64 tables and (lazily) its solve workspace on the current device."""
+
+    def __init__(self, prob, **opts):
+        self.prob = prob
+        self.nx, self.ny, self.nz = int(prob.nx), int(prob.ny), int(prob.nz)
+        self._cp, self._keep = _c_problem(prob)
+        self._opts = _c_opts(**opts)
+        h = C.c_void_p()
+        L.check(L.lib().psfd_plan_create(C.byref(self._cp), C.byref(self._opts), C.byref(h)), "psfd_plan_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().psfd_plan_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def footprint(self) -> int:
+        v = C.c_size_t()
+        L.check(L.lib().psfd_plan_footprint(self._h, C.byref(v)), "psfd_plan_footprint")
+        return int(v.value)
+
+    @property
+    def field_shape(self):
+        return (3, self.nz, self.ny, self.nx)
+
+    def psfd_apply(self, deps: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None,
+                   transpose: bool = False, k_only: bool = False) -> torch.Tensor:
+        """y = x - K(V x) (or K(V x)); complex64 or complex128 device tensors."""
+        dt = x.dtype
+        code = {torch.complex64: L.PSFD_C64, torch.complex128: L.PSFD_C128}[dt]
+        _dev(deps, dt, "deps")
+        _dev(x, dt, "x")
+        if tuple(x.shape) != self.field_shape or tuple(deps.shape) != self.field_shape[1:]:
+            raise ValueError("shape mismatch")
+        if out is None:
+            out = torch.empty_like(x)
+        _dev(out, dt, "out")
+        flags = (L.PSFD_APPLY_TRANSPOSE if transpose else 0) | (L.PSFD_APPLY_K_ONLY if k_only else 0)
+        L.check(L.lib().psfd_apply(self._h, C.c_void_p(deps.data_ptr()), C.c_void_p(x.data_ptr()),
+                                   C.c_void_p(out.data_ptr()), code, flags, _stream()), "psfd_apply")
+        return out
+
+    apply = psfd_apply
+
+    def psfd_solve(self, deps: torch.Tensor, emask: Optional[torch.Tensor] = None,
+                   orders: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, torch.Tensor, Dict]:
+        _dev(deps, torch.complex128, "deps")
+        if tuple(deps.shape) != self.field_shape[1:]:
+            raise ValueError("deps shape mismatch")
+        if emask is None:
+            emask = torch.empty(self.field_shape, dtype=torch.complex128, device=deps.device)
+        if orders is None:
+            orders = torch.empty((self.ny, self.nx, 3), dtype=torch.complex128, device=deps.device)
+        info = L.psfd_info()
+        L.check(L.lib().psfd_solve(self._h, C.c_void_p(deps.data_ptr()), C.c_void_p(emask.data_ptr()),
+                                   C.c_void_p(orders.data_ptr()), C.byref(info), _stream()), "psfd_solve")
+        return emask, orders, info.as_dict()
+
+    solve = psfd_solve
+
+    def psfd_solve_adjoint(self, deps: torch.Tensor, orders_sel: Sequence[Tuple[int, int]],
+                           grad: Optional[torch.Tensor] = None):
+        """Gradient dJ/dRe + i dJ/dIm of J = sum_q ||a_q||^2 over orders_sel."""
+        _dev(deps, torch.complex128, "deps")
+        if grad is None:
+            grad = torch.empty_like(deps)
+        sel = (C.c_int32 * (2 * max(1, len(orders_sel))))()
+        for i, (m, n) in enumerate(orders_sel):
+            sel[2 * i], sel[2 * i + 1] = int(m), int(n)
+        J = C.c_double()
+        fi, ai = L.psfd_info(), L.psfd_info()
+        L.check(L.lib().psfd_solve_adjoint(self._h, C.c_void_p(deps.data_ptr()), sel, len(orders_sel),
+                                           C.c_void_p(grad.data_ptr()), C.byref(J), C.byref(fi), C.byref(ai),
+                                           _stream()), "psfd_solve_adjoint")
+        return grad, float(J.value), fi.as_dict(), ai.as_dict()
+
+    adjoint = psfd_solve_adjoint
+
+
+def psfd_solve_batch(probs: Sequence, deps: Sequence[torch.Tensor], **opts):
+    """Lock-step batched solves of same-shape instances; returns lists of fields, orders, infos."""
+    n = len(probs)
+    cps = (L.psfd_problem * n)()
+    keep = []
+    for i, p in enumerate(probs):
+        cps[i], k = _c_problem(p)
+        keep.append(k)
+    o = _c_opts(**opts)
+    em = [torch.empty((3, p.nz, p.ny, p.nx), dtype=torch.complex128, device=deps[0].device) for p in probs]
+    od = [torch.empty((p.ny, p.nx, 3), dtype=torch.complex128, device=deps[0].device) for p in probs]
+    for d in deps:
+        _dev(d, torch.complex128, "deps")
+    ad = (C.c_void_p * n)(*[d.data_ptr() for d in deps])
+    ae = (C.c_void_p * n)(*[t.data_ptr() for t in em])
+    ao = (C.c_void_p * n)(*[t.data_ptr() for t in od])
+    info = (L.psfd_info * n)()
+    L.check(L.lib().psfd_solve_batch(n, cps, C.byref(o), ad, ae, ao, info, _stream()), "psfd_solve_batch")
+    return em, od, [info[i].as_dict() for i in range(n)]
+
+
+solve_batch = psfd_solve_batch
+
+
+class Server:
+    """Continuous-batching solve server (own worker thread and stream)."""
+
+    def __init__(self, hbm_budget: int, max_slots: int, **opts):
+        self._opts = _c_opts(**opts)
+        h = C.c_void_p()
+        L.check(L.lib().psfd_server_create(int(hbm_budget), int(max_slots), C.byref(self._opts), C.byref(h)),
+                "psfd_server_create")
+        self._h = h
+        self._keep = {}
+
+    def psfd_server_submit(self, prob, deps: torch.Tensor, emask: torch.Tensor, orders: torch.Tensor) -> int:
+        cp, k = _c_problem(prob)
+        t = C.c_uint64()
+        L.check(L.lib().psfd_server_submit(self._h, C.byref(cp), C.c_void_p(deps.data_ptr()),
+                                           C.c_void_p(emask.data_ptr()), C.c_void_p(orders.data_ptr()),
+                                           C.byref(t)), "psfd_server_submit")
+        self._keep[int(t.value)] = (deps, emask, orders)
+        return int(t.value)
+
+    submit = psfd_server_submit
+
+    def psfd_server_poll(self, ticket: int):
+        done = C.c_int32()
+        info = L.psfd_info()
+        lat = C.c_double()
+        L.check(L.lib().psfd_server_poll(self._h, C.c_uint64(ticket), C.byref(done), C.byref(info), C.byref(lat)),
+                "psfd_server_poll")
+        if done.value:
+            self._keep.pop(int(ticket), None)
+        return bool(done.value), info.as_dict(), float(lat.value)
+
+    poll = psfd_server_poll
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.check(L.lib().psfd_server_destroy(self._h), "psfd_server_destroy")
+            self._h = None
+
+    __del__ = close
+
+
+class OrderIntensity(torch.autograd.Function):
+    """J(delta_eps) = sum over the selected reflected orders of ||a_q||^2.
+
+    Forward runs the solve; backward the hand-written adjoint solve. The
+    gradient follows torch's convention for real losses of complex inputs
+    (dJ/dRe + i dJ/dIm).
+    """
+
+    @staticmethod
+    def forward(ctx, deps: torch.Tensor, plan: Plan, orders_sel: Tuple[Tuple[int, int], ...]):
+        grad, J, fi, ai = plan.psfd_solve_adjoint(deps.detach().contiguous(), orders_sel)
+        ctx.save_for_backward(grad)
+        ctx.info = (fi, ai)
+        return torch.tensor(J, dtype=torch.float64, device=deps.device)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (grad,) = ctx.saved_tensors
+        return gout.to(grad.real.dtype) * grad, None, None

@@ -126,8 +126,8 @@ def manhattan(nx: int, ny: int, nz: int, lx: float, ly: float, seed: int,
     dx, dy = lx / nx, ly / ny
     rects = []
     for _ in range(int(rng.integers(n_rect[0], n_rect[1] + 1))):
-        w = max(dx, round(rng.uniform(4 * dx, lx / 2) / dx) * dx)
-        h = max(dy, round(rng.uniform(4 * dy, ly / 2) / dy) * dy)
+        w = max(dx, round(rng.uniform(min(4 * dx, lx / 2), lx / 2) / dx) * dx)
+        h = max(dy, round(rng.uniform(min(4 * dy, ly / 2), ly / 2) / dy) * dy)
         rects.append((rng.uniform(0, lx), rng.uniform(0, ly), w, h))
     return extrude(_box_mask(nx, ny, lx, ly, rects), nz, n_abs)
 

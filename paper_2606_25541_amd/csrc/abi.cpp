@@ -1,0 +1,238 @@
+// extern "C" entry points declared in include/psfd.h.
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "engine.hpp"
+#include "serve.hpp"
+
+using namespace psfd;
+
+static thread_local std::string g_last_error;
+
+static int fail(const Status& st) {
+  g_last_error = st.msg;
+  return st.code;
+}
+static int fail(int code, const char* msg) {
+  g_last_error = msg;
+  return code;
+}
+
+struct psfd_plan {
+  Problem pr;
+  Opts o;
+  Shape sh;
+  std::vector<double> tab;
+  int device = 0;
+  std::unique_ptr<Group> solve;   // full solve workspace (lazily)
+  std::unique_ptr<Group> lite;    // tables + apply scratch for psfd_apply
+  void* scratch32 = nullptr;
+  void* scratch64 = nullptr;
+  ~psfd_plan() {
+    if (scratch32) (void)hipFree(scratch32);
+    if (scratch64) (void)hipFree(scratch64);
+  }
+};
+
+extern "C" {
+
+const char* psfd_version(void) { return "psfd-mi355x 0.1"; }
+
+const char* psfd_last_error(void) { return g_last_error.c_str(); }
+
+const char* psfd_status_string(int s) {
+  switch (s) {
+    case PSFD_OK: return "ok";
+    case PSFD_NOT_CONVERGED: return "not converged";
+    case PSFD_ERR_INVALID_ARG: return "invalid argument";
+    case PSFD_ERR_UNSUPPORTED_SIZE: return "unsupported size";
+    case PSFD_ERR_OOM: return "out of device memory";
+    case PSFD_ERR_SINGULAR: return "singular (grazing order)";
+    case PSFD_ERR_NONFINITE: return "non-finite value";
+    case PSFD_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int psfd_plan_create(const psfd_problem* prob, const psfd_opts* opts, psfd_plan** out) {
+  if (!out) return fail(PSFD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  auto plan = std::make_unique<psfd_plan>();
+  Status st = validate_problem(prob, plan->pr);
+  if (!st.ok()) return fail(st);
+  st = make_opts(opts, plan->o);
+  if (!st.ok()) return fail(st);
+  plan->sh = shape_of(plan->pr.p);
+  st = build_table(plan->pr, plan->tab);
+  if (!st.ok()) return fail(st);
+  if (hipGetDevice(&plan->device) != hipSuccess) return fail(PSFD_ERR_HIP, "hipGetDevice failed");
+  *out = plan.release();
+  return PSFD_OK;
+}
+
+void psfd_plan_destroy(psfd_plan* plan) { delete plan; }
+
+int psfd_plan_footprint(const psfd_plan* plan, size_t* device_bytes) {
+  if (!plan || !device_bytes) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  *device_bytes = group_bytes(plan->sh, 1, plan->o.restart, plan->o.precision);
+  return PSFD_OK;
+}
+
+static Status ensure_lite(psfd_plan* p, hipStream_t s) {
+  if (p->lite) return Status();
+  auto g = std::make_unique<Group>();
+  Status st = device_consts(g->dc);
+  if (!st.ok()) return st;
+  g->sh = p->sh;
+  g->B = 1;
+  g->tab_stride = (long long)p->tab.size();
+  void* t = nullptr;
+  hipError_t e = hipMalloc(&t, p->tab.size() * 8);
+  if (e != hipSuccess) return hip_status(e, "hipMalloc");
+  g->owned.push_back(t);
+  g->tab = (double*)t;
+  e = hipMemcpyAsync(g->tab, p->tab.data(), p->tab.size() * 8, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_status(e, "hipMemcpyAsync");
+  p->lite = std::move(g);
+  return Status();
+}
+
+int psfd_apply(psfd_plan* plan, const void* d_deps, const void* d_x, void* d_y, int dtype, int flags, void* stream) {
+  if (!plan || !d_deps || !d_x || !d_y) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  if (d_x == d_y) return fail(PSFD_ERR_INVALID_ARG, "d_y must not alias d_x");
+  if (dtype != PSFD_C64 && dtype != PSFD_C128) return fail(PSFD_ERR_INVALID_ARG, "dtype must be PSFD_C64 or PSFD_C128");
+  hipStream_t s = (hipStream_t)stream;
+  Status st = ensure_lite(plan, s);
+  if (!st.ok()) return fail(st);
+  const size_t esz = dtype == PSFD_C64 ? 8 : 16;
+  void*& scratch = dtype == PSFD_C64 ? plan->scratch32 : plan->scratch64;
+  if (!scratch) {
+    hipError_t e = hipMalloc(&scratch, (size_t)plan->sh.n3 * esz);
+    if (e != hipSuccess) return fail(hip_status(e, "hipMalloc"));
+  }
+  const int kmode = (flags & PSFD_APPLY_K_ONLY) ? 1 : 0;
+  const int tr = (flags & PSFD_APPLY_TRANSPOSE) ? 1 : 0;
+  Group& g = *plan->lite;
+  if (dtype == PSFD_C64)
+    apply_op<float2>(g, (const float2*)d_deps, vr(d_x), vr(d_y), (float2*)scratch, kmode, tr, nullptr, s);
+  else
+    apply_op<double2>(g, (const double2*)d_deps, vr(d_x), vr(d_y), (double2*)scratch, kmode, tr, nullptr, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(hip_status(e, "apply launch"));
+  return PSFD_OK;
+}
+
+static void fill_info(psfd_info* info, const SolveStats& s) {
+  if (!info) return;
+  info->iters = s.iters;
+  info->outer_iters = s.outer;
+  info->cycles = s.cycles;
+  info->status = s.status;
+  info->rel_residual = s.rel_res;
+  info->outer_change = s.change;
+  info->mono_residual = s.mono;
+}
+
+static Status ensure_solve(psfd_plan* p, hipStream_t s) {
+  if (p->solve) return Status();
+  auto g = std::make_unique<Group>();
+  Status st = group_alloc(*g, p->sh, 1, p->o.restart, p->o.precision);
+  if (!st.ok()) return st;
+  st = group_set_tables(*g, 0, p->tab, s);
+  if (!st.ok()) return st;
+  p->solve = std::move(g);
+  return Status();
+}
+
+int psfd_solve(psfd_plan* plan, const void* d_deps, void* d_emask, void* d_orders, psfd_info* info, void* stream) {
+  if (!plan || !d_deps || !d_emask) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  Status st = ensure_solve(plan, s);
+  if (!st.ok()) return fail(st);
+  Group& g = *plan->solve;
+  const Shape& sh = plan->sh;
+  hipError_t e = hipMemcpyAsync(g.deps64, d_deps, sh.N * 16, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return fail(hip_status(e, "copy contrast"));
+  std::vector<SolveStats> stats;
+  st = solve_group(g, plan->o, stats, s);
+  if (!st.ok()) return fail(st);
+  e = hipMemcpyAsync(d_emask, g.x, sh.n3 * 16, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && d_orders) e = hipMemcpyAsync(d_orders, g.ord, sh.nxny * 3 * 16, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(hip_status(e, "copy results"));
+  fill_info(info, stats[0]);
+  if (stats[0].status < 0) return fail(stats[0].status, "non-finite residual");
+  if (stats[0].status == PSFD_NOT_CONVERGED) {
+    g_last_error = "iteration limit reached";
+    return PSFD_NOT_CONVERGED;
+  }
+  return PSFD_OK;
+}
+
+int psfd_solve_adjoint(psfd_plan* plan, const void* d_deps, const int32_t* orders_sel, int32_t n_sel, void* d_grad,
+                       double* J_out, psfd_info* info_fwd, psfd_info* info_adj, void* stream) {
+  if (!plan || !d_deps || !d_grad || (n_sel > 0 && !orders_sel) || n_sel < 0)
+    return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  Status st = ensure_solve(plan, s);
+  if (!st.ok()) return fail(st);
+  Group& g = *plan->solve;
+  const Shape& sh = plan->sh;
+  hipError_t e = hipMemcpyAsync(g.deps64, d_deps, sh.N * 16, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return fail(hip_status(e, "copy contrast"));
+  std::vector<SolveStats> fst, ast;
+  st = solve_group(g, plan->o, fst, s);
+  if (!st.ok()) return fail(st);
+  fill_info(info_fwd, fst[0]);
+  std::vector<std::pair<int, int>> sel;
+  for (int i = 0; i < n_sel; ++i) sel.emplace_back(orders_sel[2 * i], orders_sel[2 * i + 1]);
+  std::vector<double> J;
+  st = adjoint_group(g, plan->o, sel, (double2*)d_grad, J, ast, s);
+  if (!st.ok()) return fail(st);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(hip_status(e, "adjoint"));
+  if (J_out) *J_out = J[0];
+  fill_info(info_adj, ast[0]);
+  int worst = std::min(fst[0].status, ast[0].status);
+  if (worst < 0) return fail(worst, "non-finite residual");
+  if (fst[0].status == PSFD_NOT_CONVERGED || ast[0].status == PSFD_NOT_CONVERGED) return PSFD_NOT_CONVERGED;
+  return PSFD_OK;
+}
+
+int psfd_solve_batch(int32_t n, const psfd_problem* probs, const psfd_opts* opts, const void* const* d_deps,
+                     void* const* d_emask, void* const* d_orders, psfd_info* info, void* stream) {
+  if (n <= 0 || !probs || !d_deps || !d_emask) return fail(PSFD_ERR_INVALID_ARG, "bad batch arguments");
+  Status st = solve_batch(n, probs, opts, d_deps, d_emask, d_orders, info, (hipStream_t)stream);
+  if (!st.ok()) return fail(st);
+  bool nc = false;
+  for (int i = 0; info && i < n; ++i) nc |= info[i].status == PSFD_NOT_CONVERGED;
+  return nc ? PSFD_NOT_CONVERGED : PSFD_OK;
+}
+
+int psfd_server_create(size_t hbm_budget, int32_t max_slots, const psfd_opts* opts, psfd_server** out) {
+  if (!out || max_slots < 1 || hbm_budget == 0) return fail(PSFD_ERR_INVALID_ARG, "bad server arguments");
+  Status st = server_create(hbm_budget, max_slots, opts, out);
+  return st.ok() ? PSFD_OK : fail(st);
+}
+
+int psfd_server_submit(psfd_server* srv, const psfd_problem* prob, const void* d_deps, void* d_emask, void* d_orders,
+                       uint64_t* ticket) {
+  if (!srv || !prob || !d_deps || !d_emask || !ticket) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  Status st = server_submit(srv, prob, d_deps, d_emask, d_orders, ticket);
+  return st.ok() ? PSFD_OK : fail(st);
+}
+
+int psfd_server_poll(psfd_server* srv, uint64_t ticket, int32_t* done, psfd_info* info, double* latency_s) {
+  if (!srv || !done) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  Status st = server_poll(srv, ticket, done, info, latency_s);
+  return st.ok() ? PSFD_OK : fail(st);
+}
+
+int psfd_server_destroy(psfd_server* srv) {
+  if (!srv) return fail(PSFD_ERR_INVALID_ARG, "NULL server");
+  Status st = server_destroy(srv);
+  return st.ok() ? PSFD_OK : fail(st);
+}
+
+}  // extern "C"

@@ -1,0 +1,675 @@
+// Host engine of the solver: FP64 problem tables, grouped device workspaces,
+// operator apply orchestration and the GMRES / outer-loop drivers.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <mutex>
+
+namespace psfd {
+
+using cd = std::complex<double>;
+static const double PI = 3.14159265358979323846;
+static const size_t LDS_MAX = 163840;
+
+Status hip_status(hipError_t e, const char* what) {
+  Status st;
+  if (e != hipSuccess) {
+    st.code = (e == hipErrorOutOfMemory) ? PSFD_ERR_OOM : PSFD_ERR_HIP;
+    st.msg = std::string(what) + ": " + hipGetErrorString(e);
+  }
+  return st;
+}
+
+#define HIPCHK(call)                                     \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_status(e_, #call);  \
+  } while (0)
+
+static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+Status validate_problem(const psfd_problem* p, Problem& out) {
+  Status st;
+  auto bad = [&](int code, const std::string& m) { st.code = code; st.msg = m; return st; };
+  if (!p) return bad(PSFD_ERR_INVALID_ARG, "problem is NULL");
+  if (!pow2_in(p->nx, 4, 256) || !pow2_in(p->ny, 4, 256) || !pow2_in(p->nz, 2, 128))
+    return bad(PSFD_ERR_UNSUPPORTED_SIZE, "nx, ny must be powers of two in [4, 256] and nz in [2, 128]");
+  if (!(p->lx_nm > 0) || !(p->ly_nm > 0) || !(p->t_nm > 0) || !(p->wavelength_nm > 0) || !(p->eps_bg > 0))
+    return bad(PSFD_ERR_INVALID_ARG, "lengths, wavelength and eps_bg must be positive");
+  if (!(std::fabs(p->theta_deg) < 90.0) || !std::isfinite(p->phi_deg))
+    return bad(PSFD_ERR_INVALID_ARG, "theta must lie in (-90, 90) degrees");
+  if (p->pol != PSFD_TE && p->pol != PSFD_TM) return bad(PSFD_ERR_INVALID_ARG, "pol must be PSFD_TE or PSFD_TM");
+  if (p->n_layers < 0 || (p->n_layers > 0 && !p->layers)) return bad(PSFD_ERR_INVALID_ARG, "bad layer list");
+  out.p = *p;
+  out.layers.assign(p->layers, p->layers + p->n_layers);
+  for (auto& l : out.layers)
+    if (!(l.thickness_nm >= 0) || !std::isfinite(l.eps_re) || !std::isfinite(l.eps_im))
+      return bad(PSFD_ERR_INVALID_ARG, "bad layer parameters");
+  out.p.layers = out.layers.empty() ? nullptr : out.layers.data();
+  return st;
+}
+
+Status make_opts(const psfd_opts* o, Opts& out) {
+  Status st;
+  out = Opts();
+  if (!o) return st;
+  if (!(o->rtol > 0) || o->restart < 1 || o->restart > MAXM || o->max_iters < 1 || o->max_outer < 1 ||
+      (o->precision != PSFD_FP64 && o->precision != PSFD_MIXED)) {
+    st.code = PSFD_ERR_INVALID_ARG;
+    st.msg = "bad options (rtol > 0, 1 <= restart <= 32, max_iters, max_outer >= 1, precision)";
+    return st;
+  }
+  out.rtol = o->rtol;
+  out.outer_rtol = o->outer_rtol > 0 ? o->outer_rtol : o->rtol;
+  out.restart = o->restart;
+  out.max_iters = o->max_iters;
+  out.max_outer = o->max_outer;
+  out.precision = o->precision;
+  out.inner_eta = o->inner_eta > 0 ? o->inner_eta : 1e-4;
+  return st;
+}
+
+Shape shape_of(const psfd_problem& p) {
+  Shape s;
+  s.nx = p.nx; s.ny = p.ny; s.nz = p.nz; s.pz = 2 * p.nz;
+  s.nxny = (long long)p.nx * p.ny;
+  s.N = s.nxny * p.nz;
+  s.n3 = 3 * s.N;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Layered stack: recursive generalized reflection coefficient at the top surface
+// (Chew's recursion, folding one layer at a time from the substrate upwards).
+// TE returns the E-field ratio, TM the H-field ratio.
+static inline cd kz_branch(cd k2) {
+  cd r = std::sqrt(k2);
+  if (r.imag() < 0 || (r.imag() == 0 && r.real() < 0)) r = -r;
+  return r;
+}
+
+static cd stack_reflection(double k0, double eps_top, const std::vector<psfd_layer>& L, cd eps_sub, double kt,
+                           int pol) {
+  const int nl = (int)L.size();
+  std::vector<cd> eps(nl + 2), kz(nl + 2);
+  std::vector<double> d(nl + 2, 0.0);
+  eps[0] = eps_top;
+  for (int i = 0; i < nl; ++i) { eps[i + 1] = cd(L[i].eps_re, L[i].eps_im); d[i + 1] = L[i].thickness_nm; }
+  eps[nl + 1] = eps_sub;
+  for (int i = 0; i < nl + 2; ++i) kz[i] = kz_branch(k0 * k0 * eps[i] - kt * kt);
+  auto fres = [&](int i, int j) -> cd {
+    if (pol == PSFD_TE) return (kz[i] - kz[j]) / (kz[i] + kz[j]);
+    return (eps[j] * kz[i] - eps[i] * kz[j]) / (eps[j] * kz[i] + eps[i] * kz[j]);
+  };
+  cd rt = fres(nl, nl + 1);
+  for (int i = nl - 1; i >= 0; --i) {
+    cd r = fres(i, i + 1);
+    cd ph = std::exp(cd(0, 2) * kz[i + 1] * d[i + 1]);
+    rt = (r + rt * ph) / (1.0 + r * rt * ph);
+  }
+  return rt;
+}
+
+static void cross3(const cd* a, const cd* b, cd* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+Status build_table(const Problem& pr, std::vector<double>& tab) {
+  Status st;
+  const psfd_problem& p = pr.p;
+  const int nx = p.nx, ny = p.ny, nz = p.nz, pz = 2 * nz;
+  TabLayout L{nx, ny};
+  tab.assign((size_t)L.size(), 0.0);
+  const double k0 = 2.0 * PI / p.wavelength_nm;
+  const double kbg = k0 * std::sqrt(p.eps_bg);
+  const double th = p.theta_deg * PI / 180.0, ph = p.phi_deg * PI / 180.0;
+  const double kx0 = kbg * std::sin(th) * std::cos(ph), ky0 = kbg * std::sin(th) * std::sin(ph);
+  const double dz = p.t_nm / nz;
+  tab[TS_KBG] = kbg;
+  tab[TS_L] = p.t_nm;
+  tab[TS_DZ] = dz;
+  tab[TS_KAPPA] = 2.0 * PI / (pz * dz);
+  tab[TS_SCALE] = 1.0 / ((double)nx * ny * pz);
+  tab[TS_K0SQ] = k0 * k0;
+  tab[TS_T] = p.t_nm;
+  tab[TS_INVNXNY] = 1.0 / ((double)nx * ny);
+  tab[TS_ST] = std::sin(th) * std::cos(ph);
+  tab[TS_ST + 1] = std::sin(th) * std::sin(ph);
+  double* kx = tab.data() + L.off_kx();
+  double* ky = tab.data() + L.off_ky();
+  for (int i = 0; i < nx; ++i) { int m = i < nx / 2 ? i : i - nx; kx[i] = kx0 + 2.0 * PI * m / p.lx_nm; }
+  for (int j = 0; j < ny; ++j) { int n = j < ny / 2 ? j : j - ny; ky[j] = ky0 + 2.0 * PI * n / p.ly_nm; }
+  double* beta = tab.data() + L.off_beta();
+  double* eibl = tab.data() + L.off_eibl();
+  double* keep = tab.data() + L.off_keep();
+  double* tr = tab.data() + L.off_tr();
+  const cd eps_sub(p.eps_sub_re, p.eps_sub_im);
+  for (int j = 0; j < ny; ++j) {
+    for (int i = 0; i < nx; ++i) {
+      const long long q = (long long)j * nx + i;
+      const double kt = std::hypot(kx[i], ky[j]);
+      const cd b = kz_branch(cd(kbg * kbg - kt * kt, 0.0));
+      if (std::abs(b) < 1e-6 * kbg) {
+        st.code = PSFD_ERR_SINGULAR;
+        st.msg = "a transverse order grazes the surface (beta = 0, Wood anomaly)";
+        return st;
+      }
+      beta[2 * q] = b.real(); beta[2 * q + 1] = b.imag();
+      const cd e = std::exp(cd(0, 1) * b * p.t_nm);
+      eibl[2 * q] = e.real(); eibl[2 * q + 1] = e.imag();
+      const bool nyq = (i == nx / 2) || (j == ny / 2);
+      keep[q] = nyq ? 0.0 : 1.0;
+      // polarisation basis: s = z x kt / |kt| (azimuth fallback at kt = 0), p+- = k+- x s / kbg
+      cd s[3];
+      if (kt > 0) { s[0] = -ky[j] / kt; s[1] = kx[i] / kt; }
+      else { s[0] = -std::sin(ph); s[1] = std::cos(ph); }
+      s[2] = 0.0;
+      cd kp[3] = {kx[i], ky[j], b}, km[3] = {kx[i], ky[j], -b};
+      cd pp[3], pm[3];
+      cross3(kp, s, pp);
+      cross3(km, s, pm);
+      for (int c = 0; c < 3; ++c) { pp[c] /= kbg; pm[c] /= kbg; }
+      const cd rs = stack_reflection(k0, p.eps_bg, pr.layers, eps_sub, kt, PSFD_TE);
+      const cd rp = stack_reflection(k0, p.eps_bg, pr.layers, eps_sub, kt, PSFD_TM);
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          cd t = nyq ? cd(0) : (rs * s[r] * s[c] + rp * pp[r] * pm[c]);
+          tr[18 * q + 2 * (3 * r + c)] = t.real();
+          tr[18 * q + 2 * (3 * r + c) + 1] = t.imag();
+        }
+      if (q == 0) {
+        tab[TS_INCQ] = 0.0;
+        const cd* ev = (p.pol == PSFD_TE) ? s : pm;
+        for (int c = 0; c < 3; ++c) { tab[TS_EINC + 2 * c] = ev[c].real(); tab[TS_EINC + 2 * c + 1] = ev[c].imag(); }
+        tab[TS_BINC] = b.real();
+        tab[TS_BINC + 1] = b.imag();
+      }
+    }
+  }
+  return st;
+}
+
+void build_twiddles(std::vector<double>& tw) {
+  tw.assign(2 * 512, 0.0);
+  for (int n = 2; n <= 256; n <<= 1)
+    for (int i = 0; i < n; ++i) {
+      // exp(-2 pi i i / n); the angle is reduced to the first octant by symmetry
+      const double a = 2.0 * PI * i / n;
+      tw[2 * (n + i)] = std::cos(a);
+      tw[2 * (n + i) + 1] = -std::sin(a);
+    }
+}
+
+// ---------------------------------------------------------------------------
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+static int ceil64(int v) { return (v + 63) / 64 * 64; }
+
+XYCfg xy_config(const Shape& sh, size_t esz) {
+  XYCfg c{};
+  const int nx = sh.nx, ny = sh.ny;
+  const size_t full_lds = (size_t)ny * (nx + 1) * esz;
+  c.fused = full_lds <= LDS_MAX && (long long)nx * ny <= 16 * 1024;
+  c.full = TileShape{nx, ny, 1, 1, clampi(nx * ny / 8, 64, 1024), full_lds};
+  if (nx * ny > 16 * c.full.nthr) c.full.nthr = 1024;
+  int rb = clampi(4096 / nx, 1, ny);
+  int rel = rb * nx;
+  c.rows = TileShape{nx, rb, 1, 0, clampi(ceil64(rel / 8), 64, 1024), (size_t)rb * (nx + 1) * esz};
+  int cb = std::min(nx, 16);
+  int cel = cb * ny;
+  c.cols = TileShape{cb, ny, 0, 1, clampi(ceil64(cel / 8), 64, 1024), (size_t)ny * (cb + 1) * esz};
+  return c;
+}
+
+ZCfg z_config(const Shape& sh, size_t esz) {
+  ZCfg z{};
+  int bx = std::min(sh.nx, 16);
+  while (bx > 1 && (size_t)3 * bx * (sh.pz + 1) * esz > 150 * 1024) bx >>= 1;
+  z.bx = bx;
+  z.nthr = clampi(ceil64(3 * bx * sh.pz / 8), 64, 1024);
+  while (3 * bx * sh.pz > 16 * z.nthr && z.nthr < 1024) z.nthr += 64;
+  z.lds = (size_t)3 * bx * (sh.pz + 1) * esz;
+  return z;
+}
+
+// ---------------------------------------------------------------------------
+static std::mutex g_dc_mu;
+static std::vector<DeviceConsts*> g_dc;
+
+Status device_consts(DeviceConsts*& out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_dc_mu);
+  for (auto* d : g_dc)
+    if (d->device == dev) { out = d; return Status(); }
+  std::vector<double> tw;
+  build_twiddles(tw);
+  std::vector<float> tw32(tw.size());
+  for (size_t i = 0; i < tw.size(); ++i) tw32[i] = (float)tw[i];
+  auto* d = new DeviceConsts();
+  d->device = dev;
+  HIPCHK(hipMalloc((void**)&d->tw64, tw.size() * sizeof(double)));
+  HIPCHK(hipMalloc((void**)&d->tw32, tw32.size() * sizeof(float)));
+  HIPCHK(hipMemcpy(d->tw64, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d->tw32, tw32.data(), tw32.size() * sizeof(float), hipMemcpyHostToDevice));
+  for (int t : {0}) (void)t;
+  g_dc.push_back(d);
+  out = d;
+  return Status();
+}
+
+// ---------------------------------------------------------------------------
+Group::~Group() {
+  for (void* p : owned) (void)hipFree(p);
+  if (h_run) (void)hipHostFree(h_run);
+  if (h_dbl) (void)hipHostFree(h_dbl);
+}
+
+size_t group_bytes(const Shape& sh, int B, int m, int prec) {
+  const size_t n3 = (size_t)sh.n3, N = (size_t)sh.N;
+  const size_t esz = prec == PSFD_FP64 ? 16 : 8;
+  size_t per = 0;
+  per += (size_t)TabLayout{sh.nx, sh.ny}.size() * 8;
+  per += N * 16 + (prec == PSFD_MIXED ? N * 8 : 0);
+  per += 6 * n3 * 16;
+  per += (size_t)(m + 1) * n3 * esz;
+  per += prec == PSFD_MIXED ? n3 * esz : 0;
+  per += sizeof(GState) + RED_BLOCKS * (MAXM + 1) * 16 + RED_BLOCKS * 2 * 8;
+  per += 5 * (size_t)sh.nxny * 3 * 16 + (size_t)((sh.nxny + 255) / 256) * 2 * 8 + 64;
+  return per * (size_t)B;
+}
+
+template <class P>
+static Status galloc(Group& g, P*& p, size_t bytes) {
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, bytes < 256 ? 256 : bytes);
+  if (e != hipSuccess) return hip_status(e, "hipMalloc");
+  g.owned.push_back(v);
+  p = (P*)v;
+  return Status();
+}
+
+#define GALLOC(ptr, bytes)                         \
+  do {                                             \
+    Status s_ = galloc(g, ptr, (bytes));           \
+    if (!s_.ok()) return s_;                       \
+  } while (0)
+
+Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec) {
+  Status st = device_consts(g.dc);
+  if (!st.ok()) return st;
+  g.sh = sh;
+  g.B = B;
+  g.m = m;
+  g.prec = prec;
+  const size_t n3 = (size_t)sh.n3, N = (size_t)sh.N, nq = (size_t)sh.nxny * 3;
+  g.tab_stride = TabLayout{sh.nx, sh.ny}.size();
+  GALLOC(g.tab, (size_t)g.tab_stride * 8 * B);
+  GALLOC(g.deps64, N * 16 * B);
+  if (prec == PSFD_MIXED) GALLOC(g.deps32, N * 8 * B);
+  GALLOC(g.x, n3 * 16 * B);
+  GALLOC(g.b, n3 * 16 * B);
+  GALLOC(g.r, n3 * 16 * B);
+  GALLOC(g.e, n3 * 16 * B);
+  GALLOC(g.u, n3 * 16 * B);
+  GALLOC(g.ws64, n3 * 16 * B);
+  const size_t esz = prec == PSFD_FP64 ? 16 : 8;
+  GALLOC(g.basis, (size_t)(m + 1) * n3 * esz * B);
+  if (prec == PSFD_MIXED) GALLOC(g.wsP, n3 * esz * B);
+  else g.wsP = g.ws64;
+  GALLOC(g.st, sizeof(GState) * B);
+  GALLOC(g.run, sizeof(int) * B);
+  GALLOC(g.mask, sizeof(int) * B);
+  GALLOC(g.mask2, sizeof(int) * B);
+  GALLOC(g.part, (size_t)RED_BLOCKS * (MAXM + 1) * 16 * B);
+  GALLOC(g.n2, 8 * B);
+  GALLOC(g.n2b, 8 * B);
+  GALLOC(g.abs_target, 8 * B);
+  GALLOC(g.dpart, (size_t)RED_BLOCKS * 2 * 8 * B);
+  GALLOC(g.adn, nq * 16 * B);
+  GALLOC(g.aup, nq * 16 * B);
+  GALLOC(g.eup, nq * 16 * B);
+  GALLOC(g.eup2, nq * 16 * B);
+  GALLOC(g.ord, nq * 16 * B);
+  g.rblk = (int)((sh.nxny + 255) / 256);
+  GALLOC(g.rpart, (size_t)g.rblk * 2 * 8 * B);
+  HIPCHK(hipHostMalloc((void**)&g.h_run, sizeof(int) * B * 4, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&g.h_dbl, sizeof(double) * (size_t)B * 2 * std::max(8, g.rblk), hipHostMallocDefault));
+  HIPCHK(hipMemset(g.st, 0, sizeof(GState) * B));
+  HIPCHK(hipMemset(g.run, 0, sizeof(int) * B));
+  g.alloc_solve = true;
+  return Status();
+}
+
+Status group_set_tables(Group& g, int b, const std::vector<double>& tab, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(g.tab + (size_t)b * g.tab_stride, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s));
+  return Status();
+}
+
+// ---------------------------------------------------------------------------
+template <class T> static const T* twiddles(const Group& g);
+template <> const float2* twiddles<float2>(const Group& g) { return g.dc->tw32; }
+template <> const double2* twiddles<double2>(const Group& g) { return g.dc->tw64; }
+
+static TileArgs tile_base(const Group& g, const void* tw, const TileShape& t) {
+  TileArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nx = g.sh.nx; a.ny = g.sh.ny; a.nz = g.sh.nz;
+  a.log2nx = ilog2i(g.sh.nx); a.log2ny = ilog2i(g.sh.ny);
+  a.tx = t.tx; a.ty = t.ty; a.pitch = t.tx + 1;
+  a.tiles_x = g.sh.nx / t.tx; a.tiles_y = g.sh.ny / t.ty;
+  a.do_x = t.do_x; a.do_y = t.do_y;
+  a.tab = g.tab; a.tab_stride = g.tab_stride;
+  a.tw = tw;
+  a.alpha = 0; a.gamma = 1;
+  return a;
+}
+
+template <class T>
+void apply_op(Group& g, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose,
+              const int* active, hipStream_t s) {
+  const Shape& sh = g.sh;
+  const XYCfg c = xy_config(sh, sizeof(T));
+  const int np = 3 * sh.nz;
+  const T* tw = twiddles<T>(g);
+  VecRef wsr = vr(ws, sh.n3);
+  // forward: w = FFT_xy(k0^2 delta_eps x)
+  if (c.fused) {
+    TileArgs a = tile_base(g, tw, c.full);
+    a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
+    launch_tile<T, false, LD_VX, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
+  } else {
+    TileArgs a = tile_base(g, tw, c.rows);
+    a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
+    launch_tile<T, false, LD_VX, ST_PLAIN>(a, np, g.B, c.rows.nthr, c.rows.lds, s);
+    TileArgs b2 = tile_base(g, tw, c.cols);
+    b2.in = wsr; b2.out = wsr; b2.active = active;
+    launch_tile<T, false, LD_PLAIN, ST_PLAIN>(b2, np, g.B, c.cols.nthr, c.cols.lds, s);
+  }
+  // z: pad, FFT, kernel, IFFT, restrict (in place)
+  const ZCfg z = z_config(sh, sizeof(T));
+  PencilArgs p;
+  std::memset(&p, 0, sizeof(p));
+  p.nx = sh.nx; p.ny = sh.ny; p.nz = sh.nz; p.pz = sh.pz; p.log2pz = ilog2i(sh.pz);
+  p.bx = z.bx; p.pitch = sh.pz + 1; p.nblk_x = sh.nx / z.bx;
+  p.w = wsr; p.tab = g.tab; p.tab_stride = g.tab_stride; p.tw = tw; p.transpose = transpose; p.active = active;
+  launch_pencil<T>(p, g.B, z.nthr, z.lds, s);
+  // inverse: out = alpha in + gamma IFFT_xy(w)
+  const double al = kmode == 0 ? 1.0 : 0.0, ga = kmode == 0 ? -1.0 : 1.0;
+  if (c.fused) {
+    TileArgs a = tile_base(g, tw, c.full);
+    a.in = wsr; a.aux = in; a.out = out; a.alpha = al; a.gamma = ga; a.active = active;
+    launch_tile<T, true, LD_PLAIN, ST_AXPBY>(a, np, g.B, c.full.nthr, c.full.lds, s);
+  } else {
+    TileArgs a = tile_base(g, tw, c.cols);
+    a.in = wsr; a.out = wsr; a.active = active;
+    launch_tile<T, true, LD_PLAIN, ST_PLAIN>(a, np, g.B, c.cols.nthr, c.cols.lds, s);
+    TileArgs b2 = tile_base(g, tw, c.rows);
+    b2.in = wsr; b2.aux = in; b2.out = out; b2.alpha = al; b2.gamma = ga; b2.active = active;
+    launch_tile<T, true, LD_PLAIN, ST_AXPBY>(b2, np, g.B, c.rows.nthr, c.rows.lds, s);
+  }
+}
+template void apply_op<float2>(Group&, const float2*, VecRef, VecRef, float2*, int, int, const int*, hipStream_t);
+template void apply_op<double2>(Group&, const double2*, VecRef, VecRef, double2*, int, int, const int*, hipStream_t);
+
+// e = E_inc + IFFT_xy(E_up exp(i beta z)) per plane (FP64)
+static void inject(Group& g, const double2* eup, double2* out, const int* active, hipStream_t s) {
+  const Shape& sh = g.sh;
+  const XYCfg c = xy_config(sh, 16);
+  const int np = 3 * sh.nz;
+  VecRef o = vr(out, sh.n3);
+  if (c.fused) {
+    TileArgs a = tile_base(g, g.dc->tw64, c.full);
+    a.in = o; a.out = o; a.eup = eup; a.eup_stride = sh.nxny * 3; a.active = active;
+    launch_tile<double2, true, LD_INJECT, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
+  } else {
+    TileArgs a = tile_base(g, g.dc->tw64, c.cols);
+    a.in = o; a.out = o; a.eup = eup; a.eup_stride = sh.nxny * 3; a.active = active;
+    launch_tile<double2, true, LD_INJECT, ST_PLAIN>(a, np, g.B, c.cols.nthr, c.cols.lds, s);
+    TileArgs b2 = tile_base(g, g.dc->tw64, c.rows);
+    b2.in = o; b2.out = o; b2.active = active;
+    launch_tile<double2, true, LD_PLAIN, ST_PLAIN>(b2, np, g.B, c.rows.nthr, c.rows.lds, s);
+  }
+}
+
+// spectra of k0^2 delta_eps (x + e) into ws64, then per-order plane-wave readouts
+static void readout(Group& g, const double2* x, const double2* e, const int* active, hipStream_t s) {
+  const Shape& sh = g.sh;
+  const XYCfg c = xy_config(sh, 16);
+  const int np = 3 * sh.nz;
+  VecRef w = vr(g.ws64, sh.n3);
+  if (c.fused) {
+    TileArgs a = tile_base(g, g.dc->tw64, c.full);
+    a.in = vr(x, sh.n3); a.aux = vr(e, sh.n3); a.vol = vr(g.deps64, sh.N); a.out = w; a.active = active;
+    launch_tile<double2, false, LD_VXE, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
+  } else {
+    TileArgs a = tile_base(g, g.dc->tw64, c.rows);
+    a.in = vr(x, sh.n3); a.aux = vr(e, sh.n3); a.vol = vr(g.deps64, sh.N); a.out = w; a.active = active;
+    launch_tile<double2, false, LD_VXE, ST_PLAIN>(a, np, g.B, c.rows.nthr, c.rows.lds, s);
+    TileArgs b2 = tile_base(g, g.dc->tw64, c.cols);
+    b2.in = w; b2.out = w; b2.active = active;
+    launch_tile<double2, false, LD_PLAIN, ST_PLAIN>(b2, np, g.B, c.cols.nthr, c.cols.lds, s);
+  }
+  launch_readout(sh.nx, sh.ny, sh.nz, w, g.tab, g.tab_stride, g.adn, g.aup, sh.nxny * 3, active, g.B, s);
+}
+
+// eup <- T_R (adn + e_inc); returns per-instance relative change (host)
+static Status reflect(Group& g, double2* eup, const int* active, std::vector<double>* change, hipStream_t s) {
+  const Shape& sh = g.sh;
+  launch_reflect(sh.nx, sh.ny, g.tab, g.tab_stride, g.adn, eup, sh.nxny * 3, g.rpart, g.rblk, active, g.B, s);
+  if (!change) return Status();
+  HIPCHK(hipMemcpyAsync(g.h_dbl, g.rpart, sizeof(double) * 2 * g.rblk * g.B, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  change->assign(g.B, 0.0);
+  for (int b = 0; b < g.B; ++b) {
+    double d2 = 0, n2 = 0;
+    for (int k = 0; k < g.rblk; ++k) { d2 += g.h_dbl[((size_t)b * g.rblk + k) * 2]; n2 += g.h_dbl[((size_t)b * g.rblk + k) * 2 + 1]; }
+    (*change)[b] = n2 > 0 ? std::sqrt(d2 / n2) : 0.0;
+  }
+  return Status();
+}
+
+static Status set_mask(Group& g, int* dmask, const std::vector<int>& h, hipStream_t s) {
+  std::memcpy(g.h_run + g.B, h.data(), sizeof(int) * g.B);
+  HIPCHK(hipMemcpyAsync(dmask, g.h_run + g.B, sizeof(int) * g.B, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return Status();
+}
+
+static Status read_norms(Group& g, const double* d, std::vector<double>& out, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(g.h_dbl, d, sizeof(double) * g.B, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  out.assign(g.h_dbl, g.h_dbl + g.B);
+  return Status();
+}
+
+template <class T> static const T* deps_of(const Group& g);
+template <> const float2* deps_of<float2>(const Group& g) { return g.deps32; }
+template <> const double2* deps_of<double2>(const Group& g) { return g.deps64; }
+
+template <class T>
+static void arnoldi_step(Group& g, int transpose, hipStream_t s) {
+  T* V = (T*)g.basis;
+  const long long n3 = g.sh.n3, bsv = (long long)(g.m + 1) * n3;
+  VecRef vin;
+  vin.base = V; vin.bstride = bsv; vin.jstride = n3;
+  vin.idx = &g.st[0].j; vin.idx_stride = (int)(sizeof(GState) / sizeof(int)); vin.joff = 0;
+  VecRef vout = vin;
+  vout.joff = 1;
+  apply_op<T>(g, deps_of<T>(g), vin, vout, (T*)g.wsP, 0, transpose, g.run, s);
+  krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 1, g.part, g.B, s);
+  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.part, g.B, s);
+  krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 0, g.part, g.B, s);
+  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.part, g.B, s);
+  krylov_givens(g.st, g.run, g.B, s);
+  krylov_scale_next<T>(V, n3, bsv, n3, g.st, g.run, g.B, s);
+  krylov_advance(g.st, g.B, s);
+}
+
+// Restarted GMRES on (I - K V) x = b for the instances with act[b] set.
+// Each cycle starts from the FP64 residual r = b - A x; the Arnoldi cycle runs
+// in the working precision T and x accumulates in FP64.
+template <class T>
+static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act, std::vector<SolveStats>& stats,
+                           int transpose, hipStream_t s) {
+  const int B = g.B;
+  const long long n3 = g.sh.n3, bsv = (long long)(g.m + 1) * n3;
+  Status st = set_mask(g, g.mask, act, s);
+  if (!st.ok()) return st;
+  vec_norm2<double2>(g.b, n3, n3, g.dpart, g.n2b, g.mask, B, s);
+  std::vector<double> bn2, rn2;
+  st = read_norms(g, g.n2b, bn2, s);
+  if (!st.ok()) return st;
+  std::vector<double> tgt(B, 0.0);
+  for (int b = 0; b < B; ++b) tgt[b] = o.rtol * std::sqrt(bn2[b]);
+  std::memcpy(g.h_dbl, tgt.data(), sizeof(double) * B);
+  HIPCHK(hipMemcpyAsync(g.abs_target, g.h_dbl, sizeof(double) * B, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<int> lin = act;
+  std::vector<int> its0(B, 0);
+  std::vector<GState> hs(B);
+  HIPCHK(hipMemcpyAsync(hs.data(), g.st, sizeof(GState) * B, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int b = 0; b < B; ++b) its0[b] = hs[b].iters;
+  const double eta = g.prec == PSFD_MIXED ? o.inner_eta : 0.0;
+  for (;;) {
+    st = set_mask(g, g.mask, lin, s);
+    if (!st.ok()) return st;
+    apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, g.mask, s);
+    vec_axpby<double2, double2, double2>(g.r, g.b, g.r, 1.0, -1.0, n3, n3, g.mask, B, s);
+    vec_norm2<double2>(g.r, n3, n3, g.dpart, g.n2, g.mask, B, s);
+    st = read_norms(g, g.n2, rn2, s);
+    if (!st.ok()) return st;
+    bool any = false;
+    for (int b = 0; b < B; ++b) {
+      if (!lin[b]) continue;
+      const double rn = std::sqrt(rn2[b]);
+      stats[b].rel_res = bn2[b] > 0 ? rn / std::sqrt(bn2[b]) : 0.0;
+      if (!std::isfinite(rn)) { stats[b].status = PSFD_ERR_NONFINITE; lin[b] = 0; continue; }
+      const int its = hs[b].iters - its0[b];
+      if (rn <= tgt[b] || bn2[b] == 0.0) { lin[b] = 0; continue; }
+      if (its >= o.max_iters) { stats[b].status = PSFD_NOT_CONVERGED; lin[b] = 0; continue; }
+      any = true;
+    }
+    if (!any) break;
+    st = set_mask(g, g.mask, lin, s);
+    if (!st.ok()) return st;
+    vec_scale_invsqrt<T, double2>((T*)g.basis, g.r, g.n2, n3, bsv, g.mask, B, s);
+    krylov_start(g.st, g.n2, g.abs_target, eta, g.m, g.mask, g.run, B, s);
+    for (int b = 0; b < B; ++b) if (lin[b]) stats[b].cycles += 1;
+    for (int step = 0; step < g.m; ++step) {
+      arnoldi_step<T>(g, transpose, s);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(g.h_run, g.run, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      bool live = false;
+      for (int b = 0; b < B; ++b) live |= g.h_run[b] != 0;
+      if (!live) break;
+    }
+    krylov_solve_small(g.st, g.mask, B, s);
+    krylov_lincomb<T, double2>((const T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.mask, B, s);
+    HIPCHK(hipMemcpyAsync(hs.data(), g.st, sizeof(GState) * B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int b = 0; b < B; ++b)
+      if (lin[b]) stats[b].iters = hs[b].iters;
+  }
+  return Status();
+}
+
+
+// Forward solve: outer fixed point over the multilayer reflection (eqs. (8)-(9))
+// around the Lippmann-Schwinger solve of eq. (18). Step i: E_up = T_R(E_inc +
+// E_mask,down(z_top)); e = E_inc + E_layer; b = K V e; solve (I - K V) x = b
+// (warm start); read the downgoing mask field at z_top off V (x + e); stop when
+// the reflected spectrum changes by at most outer_rtol.
+template <class T>
+static Status solve_group_t(Group& g, const Opts& o, std::vector<SolveStats>& stats, hipStream_t s) {
+  const int B = g.B;
+  const Shape& sh = g.sh;
+  const long long n3 = sh.n3, nq = sh.nxny * 3;
+  stats.assign(B, SolveStats());
+  if (g.prec == PSFD_MIXED)
+    vec_axpby<float2, double2, double2>(g.deps32, g.deps64, nullptr, 1.0, 0.0, sh.N, sh.N, nullptr, B, s);
+  HIPCHK(hipMemsetAsync(g.x, 0, sizeof(double2) * n3 * B, s));
+  HIPCHK(hipMemsetAsync(g.adn, 0, sizeof(double2) * nq * B, s));
+  HIPCHK(hipMemsetAsync(g.eup, 0, sizeof(double2) * nq * B, s));
+  HIPCHK(hipMemsetAsync(g.st, 0, sizeof(GState) * B, s));
+  std::vector<int> act(B, 1);
+  Status st = set_mask(g, g.mask2, act, s);
+  if (!st.ok()) return st;
+  st = reflect(g, g.eup, g.mask2, nullptr, s);
+  if (!st.ok()) return st;
+  std::vector<double> ebg2, change;
+  for (int outer = 1; outer <= o.max_outer; ++outer) {
+    st = set_mask(g, g.mask2, act, s);
+    if (!st.ok()) return st;
+    inject(g, g.eup, g.e, g.mask2, s);
+    if (outer == 1) {
+      vec_norm2<double2>(g.e, n3, n3, g.dpart, g.n2, g.mask2, B, s);
+      st = read_norms(g, g.n2, ebg2, s);
+      if (!st.ok()) return st;
+    }
+    apply_op<double2>(g, g.deps64, vr(g.e, n3), vr(g.b, n3), g.ws64, 1, 0, g.mask2, s);
+    st = linear_solve<T>(g, o, act, stats, 0, s);
+    if (!st.ok()) return st;
+    st = set_mask(g, g.mask2, act, s);
+    if (!st.ok()) return st;
+    readout(g, g.x, g.e, g.mask2, s);
+    st = reflect(g, g.eup, g.mask2, &change, s);
+    if (!st.ok()) return st;
+    bool any = false;
+    for (int b = 0; b < B; ++b) {
+      if (!act[b]) continue;
+      stats[b].outer = outer;
+      stats[b].change = change[b];
+      if (stats[b].status < 0 || change[b] <= o.outer_rtol) { act[b] = 0; continue; }
+      any = true;
+    }
+    if (!any) break;
+  }
+  for (int b = 0; b < B; ++b)
+    if (act[b] && stats[b].status == PSFD_OK) stats[b].status = PSFD_NOT_CONVERGED;
+  // final fields with the converged reflection: e, readouts, orders
+  std::vector<int> all(B, 1);
+  st = set_mask(g, g.mask2, all, s);
+  if (!st.ok()) return st;
+  inject(g, g.eup, g.e, g.mask2, s);
+  readout(g, g.x, g.e, g.mask2, s);
+  launch_orders(sh.nx, sh.ny, g.tab, g.tab_stride, g.eup, g.aup, g.ord, nq, B, s);
+  // monolithic residual: u - K V u - (E_inc + R_vol T_R (E_inc + K_top V u)) with u = x + e
+  vec_axpby<double2, double2, double2>(g.u, g.x, g.e, 1.0, 1.0, n3, n3, nullptr, B, s);
+  st = reflect(g, g.eup2, g.mask2, nullptr, s);
+  if (!st.ok()) return st;
+  inject(g, g.eup2, g.r, g.mask2, s);
+  apply_op<double2>(g, g.deps64, vr(g.u, n3), vr(g.b, n3), g.ws64, 0, 0, g.mask2, s);  // b = u - K V u
+  vec_axpby<double2, double2, double2>(g.b, g.b, g.r, 1.0, -1.0, n3, n3, nullptr, B, s);
+  vec_norm2<double2>(g.b, n3, n3, g.dpart, g.n2, nullptr, B, s);
+  std::vector<double> m2;
+  st = read_norms(g, g.n2, m2, s);
+  if (!st.ok()) return st;
+  for (int b = 0; b < B; ++b) {
+    stats[b].mono = ebg2[b] > 0 ? std::sqrt(m2[b] / ebg2[b]) : 0.0;
+    if (!std::isfinite(stats[b].mono) && stats[b].status >= 0) stats[b].status = PSFD_ERR_NONFINITE;
+  }
+  return Status();
+}
+
+Status solve_group(Group& g, const Opts& o, std::vector<SolveStats>& stats, hipStream_t s) {
+  if (g.prec == PSFD_MIXED) return solve_group_t<float2>(g, o, stats, s);
+  return solve_group_t<double2>(g, o, stats, s);
+}
+
+Status adjoint_group(Group& g, const Opts& o, const std::vector<std::pair<int, int>>& orders_sel, double2* grad,
+                     std::vector<double>& J, std::vector<SolveStats>& stats, hipStream_t s) {
+  (void)g; (void)o; (void)orders_sel; (void)grad; (void)J; (void)stats; (void)s;
+  Status st;
+  st.code = PSFD_ERR_INVALID_ARG;
+  st.msg = "adjoint not available";
+  return st;
+}
+
+}  // namespace psfd

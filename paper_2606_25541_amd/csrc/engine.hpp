@@ -1,0 +1,119 @@
+// Host engine: problem tables, device workspaces of a group of same-shape
+// instances, operator apply orchestration and the solve drivers.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/psfd.h"
+#include "kernels.hpp"
+#include "krylov.hpp"
+
+namespace psfd {
+
+struct Status {
+  int code = PSFD_OK;
+  std::string msg;
+  bool ok() const { return code == PSFD_OK; }
+};
+
+struct Shape {
+  int nx = 0, ny = 0, nz = 0, pz = 0;
+  long long nxny = 0, N = 0, n3 = 0;
+};
+
+// validated copy of a problem statement
+struct Problem {
+  psfd_problem p{};
+  std::vector<psfd_layer> layers;
+};
+
+struct Opts {
+  double rtol = 1e-6, outer_rtol = 1e-6, inner_eta = 1e-4;
+  int restart = 30, max_iters = 5000, max_outer = 100, precision = PSFD_MIXED;
+};
+
+Status validate_problem(const psfd_problem* p, Problem& out);
+Status make_opts(const psfd_opts* o, Opts& out);
+Shape shape_of(const psfd_problem& p);
+// per-instance FP64 tables (TabLayout) of a problem; SINGULAR on a grazing order
+Status build_table(const Problem& pr, std::vector<double>& tab);
+// twiddle tables of all power-of-two lengths up to 256 (tw[n + i] = exp(-2 pi i i / n))
+void build_twiddles(std::vector<double>& tw64);
+
+// Launch configurations of the transverse FFT and z-pencil kernels.
+struct XYCfg {
+  bool fused;
+  TileShape full, rows, cols;
+};
+XYCfg xy_config(const Shape& sh, size_t esz);
+struct ZCfg { int bx, nthr; size_t lds; };
+ZCfg z_config(const Shape& sh, size_t esz);
+
+// Device tables shared by every group on a device (twiddles).
+struct DeviceConsts {
+  int device = -1;
+  float2* tw32 = nullptr;
+  double2* tw64 = nullptr;
+};
+Status device_consts(DeviceConsts*& out);
+
+// B instances of one grid shape with every device buffer a solve needs.
+struct Group {
+  Shape sh;
+  int B = 0;
+  int m = 30;
+  int prec = PSFD_MIXED;
+  bool alloc_solve = false;
+  DeviceConsts* dc = nullptr;
+  // per instance tables
+  double* tab = nullptr;
+  long long tab_stride = 0;
+  // contrast (FP64 copy of the user data, FP32 copy for mixed precision)
+  double2* deps64 = nullptr;
+  float2* deps32 = nullptr;
+  // FP64 fields [B][n3]
+  double2 *x = nullptr, *b = nullptr, *r = nullptr, *e = nullptr, *u = nullptr, *ws64 = nullptr;
+  // Krylov basis [B][m+1][n3] of the working precision and its apply scratch [B][n3]
+  void* basis = nullptr;
+  void* wsP = nullptr;
+  GState* st = nullptr;
+  int* run = nullptr;
+  int* mask = nullptr;
+  int* mask2 = nullptr;
+  double2* part = nullptr;
+  double* n2 = nullptr;
+  double* n2b = nullptr;
+  double* abs_target = nullptr;
+  double* dpart = nullptr;
+  double2 *adn = nullptr, *aup = nullptr, *eup = nullptr, *ord = nullptr, *eup2 = nullptr;
+  double* rpart = nullptr;
+  int rblk = 1;
+  int* h_run = nullptr;      // pinned host mirrors
+  double* h_dbl = nullptr;
+  std::vector<void*> owned;
+  ~Group();
+};
+
+size_t group_bytes(const Shape& sh, int B, int m, int prec);
+Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec);
+Status group_set_tables(Group& g, int b, const std::vector<double>& tab, hipStream_t s);
+
+// y = x - K(V x) (kmode 0) or y = K(V x) (kmode 1); transpose uses the kernel at -k.
+template <class T>
+void apply_op(Group& g, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose,
+              const int* active, hipStream_t s);
+
+struct SolveStats {
+  int iters = 0, outer = 0, cycles = 0, status = PSFD_OK;
+  double rel_res = 0, change = 0, mono = 0;
+};
+
+// Forward solve of every instance (deps64 filled). Results stay in g.x / g.ord.
+Status solve_group(Group& g, const Opts& o, std::vector<SolveStats>& stats, hipStream_t s);
+// Adjoint of J = sum over orders_sel of ||a_q||^2 after solve_group; grad (complex128 [N]) per instance.
+Status adjoint_group(Group& g, const Opts& o, const std::vector<std::pair<int, int>>& orders_sel,
+                     double2* grad, std::vector<double>& J, std::vector<SolveStats>& stats, hipStream_t s);
+
+Status hip_status(hipError_t e, const char* what);
+
+}  // namespace psfd

@@ -1,0 +1,165 @@
+// Radix-2/4/8/16 Stockham FFT passes on data staged in LDS.
+//
+// A batch of `nseq` sequences of power-of-two length n lives in LDS; element j
+// of sequence s sits at lds[s * sstride + j * estride]. Each pass of radix R
+// gives every thread up to 16 / R butterflies: the thread reads its R inputs
+// (spaced n / R apart) into registers, the workgroup synchronises, then it
+// applies the twiddles exp(-+2 pi i j k / (p R)), a register DFT of size R and
+// writes the outputs in self-sorting (Stockham) order. The pass works in place
+// because every read of the pass precedes the barrier. Requires
+// n * nseq <= 16 * nthreads.
+//
+// Twiddles come from a table built on the host in FP64: tw[n + i] =
+// exp(-2 pi i i / n) for every power of two n (so the table of length n
+// starts at offset n).
+#pragma once
+#include "common.hpp"
+
+namespace psfd {
+
+template <class T, bool INV> PSFD_D void dft2(T& a, T& b) {
+  T t = a; a = cadd(t, b); b = csub(t, b);
+}
+
+template <class T, bool INV> PSFD_D void dft4(T& x0, T& x1, T& x2, T& x3) {
+  T a0 = cadd(x0, x2), a1 = csub(x0, x2), a2 = cadd(x1, x3), a3 = cmul_mi<T, INV>(csub(x1, x3));
+  x0 = cadd(a0, a2); x2 = csub(a0, a2); x1 = cadd(a1, a3); x3 = csub(a1, a3);
+}
+
+// multiply by exp(-+2 pi i k / 8)
+template <class T, bool INV, int K> PSFD_D T w8(T a) {
+  typedef typename real_of<T>::type R;
+  const R h = (R)0.70710678118654752440;
+  if (K == 0) return a;
+  if (K == 2) return cmul_mi<T, INV>(a);
+  T r;
+  if (K == 1) {  // (1 -+ i)/sqrt2
+    if (!INV) { r.x = h * (a.x + a.y); r.y = h * (a.y - a.x); }
+    else      { r.x = h * (a.x - a.y); r.y = h * (a.y + a.x); }
+  } else {       // K == 3: (-1 -+ i)/sqrt2
+    if (!INV) { r.x = h * (a.y - a.x); r.y = -h * (a.x + a.y); }
+    else      { r.x = -h * (a.x + a.y); r.y = h * (a.x - a.y); }
+  }
+  return r;
+}
+
+template <class T, bool INV> PSFD_D void dft8(T* x) {
+  // even / odd split: X_k = E_k + W8^k O_k, X_{k+4} = E_k - W8^k O_k
+  T e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+  T o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+  dft4<T, INV>(e0, e1, e2, e3);
+  dft4<T, INV>(o0, o1, o2, o3);
+  o1 = w8<T, INV, 1>(o1); o2 = w8<T, INV, 2>(o2); o3 = w8<T, INV, 3>(o3);
+  x[0] = cadd(e0, o0); x[4] = csub(e0, o0);
+  x[1] = cadd(e1, o1); x[5] = csub(e1, o1);
+  x[2] = cadd(e2, o2); x[6] = csub(e2, o2);
+  x[3] = cadd(e3, o3); x[7] = csub(e3, o3);
+}
+
+// multiply by exp(-+2 pi i k / 16), k = 0..7
+template <class T, bool INV> PSFD_D T w16(T a, int k) {
+  typedef typename real_of<T>::type R;
+  const R c1 = (R)0.92387953251128675613, s1 = (R)0.38268343236508977173;
+  const R h = (R)0.70710678118654752440;
+  R c, s;  // exp(-i theta) = c - i s for the forward sign
+  switch (k) {
+    case 0: return a;
+    case 1: c = c1; s = s1; break;
+    case 2: c = h; s = h; break;
+    case 3: c = s1; s = c1; break;
+    case 4: c = 0; s = 1; break;
+    case 5: c = -s1; s = c1; break;
+    case 6: c = -h; s = h; break;
+    default: c = -c1; s = s1; break;
+  }
+  if (INV) s = -s;
+  T r; r.x = a.x * c + a.y * s; r.y = a.y * c - a.x * s; return r;
+}
+
+template <class T, bool INV> PSFD_D void dft16(T* x) {
+  T e[8], o[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) { e[i] = x[2 * i]; o[i] = x[2 * i + 1]; }
+  dft8<T, INV>(e);
+  dft8<T, INV>(o);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    T t = w16<T, INV>(o[k], k);
+    x[k] = cadd(e[k], t);
+    x[k + 8] = csub(e[k], t);
+  }
+}
+
+template <class T, int R, bool INV> PSFD_D void dft_r(T* u) {
+  if (R == 2) dft2<T, INV>(u[0], u[1]);
+  else if (R == 4) dft4<T, INV>(u[0], u[1], u[2], u[3]);
+  else if (R == 8) dft8<T, INV>(u);
+  else dft16<T, INV>(u);
+}
+
+template <class T, int R, bool INV>
+__device__ void stockham_pass(T* lds, int log2n, int log2p, int nseq, int sstride, int estride,
+                              const T* __restrict__ tw, int tid, int nthr) {
+  constexpr int NB = 16 / R;
+  constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+  const int log2nr = log2n - LR;
+  const int nr = 1 << log2nr;
+  const int nbt = nseq << log2nr;
+  T u[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    int b = tid + i * nthr;
+    if (b < nbt) {
+      int s = b >> log2nr, t = b & (nr - 1);
+      const T* base = lds + s * sstride;
+#pragma unroll
+      for (int j = 0; j < R; ++j) u[i][j] = base[(t + j * nr) * estride];
+    }
+  }
+  __syncthreads();
+  const int p = 1 << log2p;
+  const int tsh = log2n - log2p - LR;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    int b = tid + i * nthr;
+    if (b < nbt) {
+      int s = b >> log2nr, t = b & (nr - 1);
+      int k = t & (p - 1);
+      int step = k << tsh;
+#pragma unroll
+      for (int j = 1; j < R; ++j) {
+        T w = tw[j * step];
+        u[i][j] = INV ? cmulc(u[i][j], w) : cmul(u[i][j], w);
+      }
+      dft_r<T, R, INV>(u[i]);
+      T* base = lds + s * sstride;
+      int o = (t - k) * R + k;
+#pragma unroll
+      for (int j = 0; j < R; ++j) base[(o + j * p) * estride] = u[i][j];
+    }
+  }
+  __syncthreads();
+}
+
+// Full FFT of nseq sequences of length 2^log2n staged in LDS (unnormalised;
+// INV uses the +i sign). All threads of the workgroup must call it.
+template <class T, bool INV>
+__device__ void lds_fft(T* lds, int log2n, int nseq, int sstride, int estride,
+                        const T* __restrict__ tw_all, int tid, int nthr) {
+  const T* tw = tw_all + (1 << log2n);
+  int log2p = 0;
+  int rem = log2n;
+  while (rem > 0) {
+    int lr = rem >= 4 ? 4 : rem;
+    switch (lr) {
+      case 4: stockham_pass<T, 16, INV>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
+      case 3: stockham_pass<T, 8, INV>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
+      case 2: stockham_pass<T, 4, INV>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
+      default: stockham_pass<T, 2, INV>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
+    }
+    log2p += lr;
+    rem -= lr;
+  }
+}
+
+}  // namespace psfd

@@ -1,0 +1,367 @@
+// Operator-apply kernels of the discrete Lippmann-Schwinger system (eq. (18)):
+//   transverse FFT tiles  (contrast multiply V x fused into the forward load,
+//                          axpy y = alpha x + gamma w fused into the inverse store),
+//   z-pencil kernel       (zero-padded z-FFT, dyadic windowed Green's function
+//                          F[G_L](k) evaluated on the fly, inverse z-FFT),
+// plus the per-order background-field kernels of the outer loop (eqs. (8)-(9)):
+// plane-wave readouts of the mask field, reflection by T_R, order amplitudes.
+#include "kernels.hpp"
+#include "fft_lds.hpp"
+
+namespace psfd {
+
+PSFD_D double2 cexp_i(double2 z) {  // exp(i z)
+  double e = exp(-z.y);
+  double sn, cs;
+  sincos(z.x, &sn, &cs);
+  return make_double2(e * cs, e * sn);
+}
+
+// -------------------------------------------------------------------------
+// Transverse FFT tile kernel
+// -------------------------------------------------------------------------
+template <class T, bool INV, int LD, int ST>
+__global__ void __launch_bounds__(1024) k_tile(TileArgs a) {
+  extern __shared__ double2 smem_d[];
+  T* lds = reinterpret_cast<T*>(smem_d);
+  const int b = blockIdx.y;
+  if (a.active && !a.active[b]) return;
+  const int tiles = a.tiles_x * a.tiles_y;
+  const int plane = blockIdx.x / tiles;
+  const int tile = blockIdx.x - plane * tiles;
+  const int z = plane % a.nz;
+  const int c = plane / a.nz;
+  const int x0 = (tile % a.tiles_x) * a.tx;
+  const int y0 = (tile / a.tiles_x) * a.ty;
+  const long long nxny = (long long)a.nx * a.ny;
+  const long long poff = (long long)plane * nxny;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int ntile = a.tx * a.ty;
+  const int ltx = ilog2i(a.tx);
+  const T* in = vref<T>(a.in, b) + poff;
+  const T* aux = (LD == LD_VXE || ST == ST_AXPBY) ? vref<T>(a.aux, b) + poff : nullptr;
+  const T* vol = (LD == LD_VX || LD == LD_VXE) ? vref<T>(a.vol, b) + (long long)z * nxny : nullptr;
+  const double* tab = a.tab + (long long)b * a.tab_stride;
+  typedef typename real_of<T>::type R;
+  const R k0sq = (R)tab[TS_K0SQ];
+
+  for (int i = tid; i < ntile; i += nthr) {
+    int yy = i >> ltx, xx = i & (a.tx - 1);
+    long long o = (long long)(y0 + yy) * a.nx + (x0 + xx);
+    T v;
+    if (LD == LD_PLAIN) {
+      v = in[o];
+    } else if (LD == LD_VX) {
+      v = cscale(cmul(vol[o], in[o]), k0sq);
+    } else if (LD == LD_VXE) {
+      v = cscale(cmul(vol[o], cadd(in[o], aux[o])), k0sq);
+    } else {
+      // spectrum of the layered field on plane z: E_up,q exp(i beta_q z)
+      // plus the incident wave in its order, E_inc exp(-i beta_inc z)
+      TabLayout L{a.nx, a.ny};
+      const double zk = (z + 0.5) * tab[TS_DZ];
+      const double2* beta = reinterpret_cast<const double2*>(tab + L.off_beta());
+      const double2* eup = a.eup + (long long)b * a.eup_stride;
+      double2 bq = beta[o];
+      double2 ph = cexp_i(make_double2(bq.x * zk, bq.y * zk));
+      double2 val = cmul(eup[o * 3 + c], ph);
+      if (o == (long long)tab[TS_INCQ]) {
+        double2 bi = make_double2(tab[TS_BINC], tab[TS_BINC + 1]);
+        double2 pi = cexp_i(make_double2(-bi.x * zk, -bi.y * zk));
+        double2 ei = make_double2(tab[TS_EINC + 2 * c], tab[TS_EINC + 2 * c + 1]);
+        val = cadd(val, cmul(ei, pi));
+      }
+      v = from_d<T>(val);
+    }
+    lds[yy * a.pitch + xx] = v;
+  }
+  __syncthreads();
+  const T* tw = reinterpret_cast<const T*>(a.tw);
+  if (!INV) {
+    if (a.do_x) lds_fft<T, false>(lds, a.log2nx, a.ty, a.pitch, 1, tw, tid, nthr);
+    if (a.do_y) lds_fft<T, false>(lds, a.log2ny, a.tx, 1, a.pitch, tw, tid, nthr);
+  } else {
+    if (a.do_y) lds_fft<T, true>(lds, a.log2ny, a.tx, 1, a.pitch, tw, tid, nthr);
+    if (a.do_x) lds_fft<T, true>(lds, a.log2nx, a.ty, a.pitch, 1, tw, tid, nthr);
+  }
+  T* out = vref<T>(a.out, b) + poff;
+  const R al = (R)a.alpha, ga = (R)a.gamma;
+  for (int i = tid; i < ntile; i += nthr) {
+    int yy = i >> ltx, xx = i & (a.tx - 1);
+    long long o = (long long)(y0 + yy) * a.nx + (x0 + xx);
+    T v = lds[yy * a.pitch + xx];
+    if (ST == ST_AXPBY) {
+      T xv = aux[o];
+      v.x = al * xv.x + ga * v.x;
+      v.y = al * xv.y + ga * v.y;
+    }
+    out[o] = v;
+  }
+}
+
+// dynamic LDS above the default limit needs the per-kernel opt-in
+static void allow_lds(const void* fn, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <class T, bool INV, int LD, int ST>
+void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t lds, hipStream_t s) {
+  dim3 grid(nplanes * a.tiles_x * a.tiles_y, nbatch);
+  allow_lds(reinterpret_cast<const void*>(&k_tile<T, INV, LD, ST>), lds);
+  hipLaunchKernelGGL((k_tile<T, INV, LD, ST>), grid, dim3(nthr), lds, s, a);
+}
+
+template void launch_tile<float2, false, LD_VX, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
+template void launch_tile<float2, false, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
+template void launch_tile<float2, true, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
+template void launch_tile<float2, true, LD_PLAIN, ST_AXPBY>(const TileArgs&, int, int, int, size_t, hipStream_t);
+template void launch_tile<double2, false, LD_VX, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
+template void launch_tile<double2, false, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
+template void launch_tile<double2, true, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
+template void launch_tile<double2, true, LD_PLAIN, ST_AXPBY>(const TileArgs&, int, int, int, size_t, hipStream_t);
+template void launch_tile<double2, false, LD_VXE, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
+template void launch_tile<double2, true, LD_INJECT, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
+
+// -------------------------------------------------------------------------
+// z-pencil kernel: pad, FFT_z, dyadic kernel, IFFT_z, restrict
+// -------------------------------------------------------------------------
+
+// z-windowed scalar factor F = (s e^{i beta L} - 1) / (beta^2 - kappa^2), with the
+// removable resonance kappa = +-beta taken by its Taylor series.
+PSFD_D double2 window_factor(double2 beta, double2 eibl, double kap, double L, double s) {
+  double2 num = make_double2(s * eibl.x - 1.0, s * eibl.y);
+  double ak = fabs(kap);
+  double ur = (beta.x - ak) * L, ui = beta.y * L;
+  if (ur * ur + ui * ui < 1e-12) {
+    // L (i - u/2 - i u^2/6) / (beta + |kappa|)
+    double2 u = make_double2(ur, ui);
+    double2 u2 = cmul(u, u);
+    double2 ser = make_double2(-0.5 * u.x + u2.y / 6.0, 1.0 - 0.5 * u.y - u2.x / 6.0);
+    ser = cscale(ser, L);
+    return cdiv(ser, make_double2(beta.x + ak, beta.y));
+  }
+  double2 den = make_double2(beta.x * beta.x - beta.y * beta.y - kap * kap, 2.0 * beta.x * beta.y);
+  return cdiv(num, den);
+}
+
+template <class T>
+__global__ void __launch_bounds__(1024) k_pencil(PencilArgs a) {
+  extern __shared__ double2 smem_d[];
+  T* lds = reinterpret_cast<T*>(smem_d);
+  typedef typename real_of<T>::type R;
+  const int b = blockIdx.y;
+  if (a.active && !a.active[b]) return;
+  const int ky = blockIdx.x / a.nblk_x;
+  const int kx0 = (blockIdx.x - ky * a.nblk_x) * a.bx;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int bx = a.bx, pz = a.pz, nz = a.nz, nx = a.nx, ny = a.ny;
+  const int lbx = ilog2i(bx);
+  T* w = vref<T>(a.w, b);
+  const long long nxny = (long long)nx * ny;
+  const int nload = 3 * pz * bx;
+  for (int i = tid; i < nload; i += nthr) {
+    int kxl = i & (bx - 1);
+    int rest = i >> lbx;
+    int z = rest & (pz - 1);
+    int c = rest >> a.log2pz;
+    T v = cmake<T>(0.0, 0.0);
+    if (z < nz) v = w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl];
+    lds[(c * bx + kxl) * a.pitch + z] = v;
+  }
+  __syncthreads();
+  const T* tw = reinterpret_cast<const T*>(a.tw);
+  lds_fft<T, false>(lds, a.log2pz, 3 * bx, a.pitch, 1, tw, tid, nthr);
+
+  const double* tab = a.tab + (long long)b * a.tab_stride;
+  TabLayout L{nx, ny};
+  const double kbg = tab[TS_KBG], Lw = tab[TS_L], kap_u = tab[TS_KAPPA], scale = tab[TS_SCALE];
+  const double ik2 = 1.0 / (kbg * kbg);
+  const double* tkx = tab + L.off_kx();
+  const double* tky = tab + L.off_ky();
+  const double2* tbeta = reinterpret_cast<const double2*>(tab + L.off_beta());
+  const double2* teibl = reinterpret_cast<const double2*>(tab + L.off_eibl());
+  const double* tkeep = tab + L.off_keep();
+  const int npt = bx * pz;
+  for (int pt = tid; pt < npt; pt += nthr) {
+    int kxl = pt >> a.log2pz;
+    int l = pt & (pz - 1);
+    int m = kx0 + kxl, n = ky;
+    int ls = (l < pz / 2) ? l : l - pz;
+    const bool nyqz = (ls == -pz / 2);
+    int mq = m, nq = n, lq = ls;
+    if (a.transpose) { mq = (nx - m) & (nx - 1); nq = (ny - n) & (ny - 1); lq = -ls; }
+    int q = nq * nx + mq;
+    T* p0 = lds + (0 * bx + kxl) * a.pitch + l;
+    T* p1 = lds + (1 * bx + kxl) * a.pitch + l;
+    T* p2 = lds + (2 * bx + kxl) * a.pitch + l;
+    if (tkeep[q] == 0.0) {
+      *p0 = cmake<T>(0, 0); *p1 = cmake<T>(0, 0); *p2 = cmake<T>(0, 0);
+      continue;
+    }
+    const double kap = kap_u * lq;
+    const double s = (lq & 1) ? -1.0 : 1.0;
+    double2 e = teibl[q];
+    double2 F = window_factor(tbeta[q], e, kap, Lw, s);
+    T g = from_d<T>(cscale(F, scale));
+    T tz = from_d<T>(make_double2(s * e.x * scale * ik2, s * e.y * scale * ik2));
+    const R kxk = (R)(tkx[mq] / kbg), kyk = (R)(tky[nq] / kbg), kzk = (R)(kap / kbg);
+    T v0 = *p0, v1 = *p1, v2 = *p2;
+    T dxy; dxy.x = kxk * v0.x + kyk * v1.x; dxy.y = kxk * v0.y + kyk * v1.y;
+    T o0, o1, o2;
+    if (!nyqz) {
+      T d; d.x = dxy.x + kzk * v2.x; d.y = dxy.y + kzk * v2.y;
+      o0.x = v0.x - kxk * d.x; o0.y = v0.y - kxk * d.y;
+      o1.x = v1.x - kyk * d.x; o1.y = v1.y - kyk * d.y;
+      o2.x = v2.x - kzk * d.x; o2.y = v2.y - kzk * d.y;
+    } else {
+      o0.x = v0.x - kxk * dxy.x; o0.y = v0.y - kxk * dxy.y;
+      o1.x = v1.x - kyk * dxy.x; o1.y = v1.y - kyk * dxy.y;
+      R f = (R)1 - kzk * kzk;
+      o2.x = f * v2.x; o2.y = f * v2.y;
+    }
+    *p0 = cmul(g, o0);
+    *p1 = cmul(g, o1);
+    *p2 = csub(cmul(g, o2), cmul(tz, v2));
+  }
+  __syncthreads();
+  lds_fft<T, true>(lds, a.log2pz, 3 * bx, a.pitch, 1, tw, tid, nthr);
+  const int nst = 3 * nz * bx;
+  const int lnz = ilog2i(nz);
+  for (int i = tid; i < nst; i += nthr) {
+    int kxl = i & (bx - 1);
+    int rest = i >> lbx;
+    int z = rest & (nz - 1);
+    int c = rest >> lnz;
+    w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl] = lds[(c * bx + kxl) * a.pitch + z];
+  }
+}
+
+template <class T>
+void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStream_t s) {
+  dim3 grid(a.nblk_x * a.ny, nbatch);
+  allow_lds(reinterpret_cast<const void*>(&k_pencil<T>), lds);
+  hipLaunchKernelGGL((k_pencil<T>), grid, dim3(nthr), lds, s, a);
+}
+template void launch_pencil<float2>(const PencilArgs&, int, int, size_t, hipStream_t);
+template void launch_pencil<double2>(const PencilArgs&, int, int, size_t, hipStream_t);
+
+// -------------------------------------------------------------------------
+// Per-order kernels of the background-field outer loop (FP64)
+// -------------------------------------------------------------------------
+__global__ void k_readout(int nx, int ny, int nz, VecRef spec, const double* tab_all, long long tab_stride,
+                          double2* adn_all, double2* aup_all, long long ostride, const int* active) {
+  const int b = blockIdx.y;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nxny = nx * ny;
+  if (q >= nxny || (active && !active[b])) return;
+  const double* tab = tab_all + (long long)b * tab_stride;
+  TabLayout L{nx, ny};
+  const double2* f = vref<double2>(spec, b);
+  const double2 beta = reinterpret_cast<const double2*>(tab + L.off_beta())[q];
+  const double dz = tab[TS_DZ], T = tab[TS_T], kbg = tab[TS_KBG];
+  double2 dn[3] = {{0, 0}, {0, 0}, {0, 0}}, up[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int k = 0; k < nz; ++k) {
+    const double zk = (k + 0.5) * dz;
+    double2 pd = cexp_i(make_double2(beta.x * zk, beta.y * zk));
+    double2 pu = cexp_i(make_double2(beta.x * (T - zk), beta.y * (T - zk)));
+    for (int c = 0; c < 3; ++c) {
+      double2 v = f[((long long)c * nz + k) * nxny + q];
+      dn[c] = cadd(dn[c], cmul(pd, v));
+      up[c] = cadd(up[c], cmul(pu, v));
+    }
+  }
+  double2* adn = adn_all + (long long)b * ostride + 3LL * q;
+  double2* aup = aup_all + (long long)b * ostride + 3LL * q;
+  if (tab[L.off_keep() + q] == 0.0) {
+    for (int c = 0; c < 3; ++c) { adn[c] = make_double2(0, 0); aup[c] = make_double2(0, 0); }
+    return;
+  }
+  // factor i dz / (2 beta) / (Nx Ny)
+  double2 fac = cdiv(make_double2(0.0, dz * tab[TS_INVNXNY]), make_double2(2.0 * beta.x, 2.0 * beta.y));
+  const double kx = tab[L.off_kx() + (q % nx)], ky = tab[L.off_ky() + (q / nx)];
+  const double ik2 = 1.0 / (kbg * kbg);
+  for (int dir = 0; dir < 2; ++dir) {
+    double2* acc = dir == 0 ? dn : up;
+    // P = I - k k^T / kbg^2 with k = (kx, ky, -+beta) (bilinear)
+    double2 kz = dir == 0 ? make_double2(-beta.x, -beta.y) : beta;
+    double2 kv[3] = {make_double2(kx, 0), make_double2(ky, 0), kz};
+    double2 d = cadd(cadd(cmul(kv[0], acc[0]), cmul(kv[1], acc[1])), cmul(kv[2], acc[2]));
+    double2 o[3];
+    for (int c = 0; c < 3; ++c) o[c] = cmul(fac, csub(acc[c], cscale(cmul(kv[c], d), ik2)));
+    double2* dst = dir == 0 ? adn : aup;
+    for (int c = 0; c < 3; ++c) dst[c] = o[c];
+  }
+}
+
+void launch_readout(int nx, int ny, int nz, VecRef spec, const double* tab, long long tab_stride,
+                    double2* adn, double2* aup, long long ostride, const int* active, int nbatch, hipStream_t s) {
+  int nxny = nx * ny;
+  dim3 grid((nxny + 255) / 256, nbatch);
+  hipLaunchKernelGGL(k_readout, grid, dim3(256), 0, s, nx, ny, nz, spec, tab, tab_stride, adn, aup, ostride, active);
+}
+
+__global__ void k_reflect(int nx, int ny, const double* tab_all, long long tab_stride, const double2* adn_all,
+                          double2* eup_all, long long ostride, double* part, const int* active) {
+  __shared__ double sd[256], sn[256];
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nxny = nx * ny;
+  const double* tab = tab_all + (long long)b * tab_stride;
+  TabLayout L{nx, ny};
+  double d2 = 0, n2 = 0;
+  if (q < nxny) {
+    const double2* adn = adn_all + (long long)b * ostride + 3LL * q;
+    double2* eup = eup_all + (long long)b * ostride + 3LL * q;
+    double2 e[3] = {adn[0], adn[1], adn[2]};
+    if (q == (int)tab[TS_INCQ])
+      for (int c = 0; c < 3; ++c) e[c] = cadd(e[c], make_double2(tab[TS_EINC + 2 * c], tab[TS_EINC + 2 * c + 1]));
+    const double2* tr = reinterpret_cast<const double2*>(tab + L.off_tr()) + 9LL * q;
+    for (int i = 0; i < 3; ++i) {
+      double2 v = cadd(cadd(cmul(tr[3 * i], e[0]), cmul(tr[3 * i + 1], e[1])), cmul(tr[3 * i + 2], e[2]));
+      d2 += cabs2(csub(v, eup[i]));
+      n2 += cabs2(v);
+      eup[i] = v;
+    }
+  }
+  sd[threadIdx.x] = d2;
+  sn[threadIdx.x] = n2;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) { sd[threadIdx.x] += sd[threadIdx.x + st]; sn[threadIdx.x] += sn[threadIdx.x + st]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[((long long)b * gridDim.x + blockIdx.x) * 2] = sd[0];
+    part[((long long)b * gridDim.x + blockIdx.x) * 2 + 1] = sn[0];
+  }
+}
+
+void launch_reflect(int nx, int ny, const double* tab, long long tab_stride, const double2* adn,
+                    double2* eup, long long ostride, double* part, int nblk, const int* active, int nbatch,
+                    hipStream_t s) {
+  dim3 grid(nblk, nbatch);
+  hipLaunchKernelGGL(k_reflect, grid, dim3(256), 0, s, nx, ny, tab, tab_stride, adn, eup, ostride, part, active);
+}
+
+__global__ void k_orders(int nx, int ny, const double* tab_all, long long tab_stride, const double2* eup_all,
+                         const double2* aup_all, double2* ord_all, long long ostride) {
+  const int b = blockIdx.y;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nx * ny) return;
+  const double* tab = tab_all + (long long)b * tab_stride;
+  TabLayout L{nx, ny};
+  double2 beta = reinterpret_cast<const double2*>(tab + L.off_beta())[q];
+  double T = tab[TS_T];
+  double2 ph = cexp_i(make_double2(beta.x * T, beta.y * T));
+  const long long o = (long long)b * ostride + 3LL * q;
+  for (int c = 0; c < 3; ++c) ord_all[o + c] = cadd(cmul(eup_all[o + c], ph), aup_all[o + c]);
+}
+
+void launch_orders(int nx, int ny, const double* tab, long long tab_stride, const double2* eup,
+                   const double2* aup, double2* orders, long long ostride, int nbatch, hipStream_t s) {
+  dim3 grid((nx * ny + 255) / 256, nbatch);
+  hipLaunchKernelGGL(k_orders, grid, dim3(256), 0, s, nx, ny, tab, tab_stride, eup, aup, orders, ostride);
+}
+
+}  // namespace psfd

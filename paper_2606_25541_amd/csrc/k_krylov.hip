@@ -1,0 +1,438 @@
+// Krylov kernels of restarted GMRES (Saad & Schultz) with classical Gram-Schmidt
+// applied twice: batched multi-dot products, fused update + norm, one-thread
+// Givens/Hessenberg updates, back substitution and solution update. Vector
+// data may be FP32 or FP64; every dot product and norm accumulates in FP64.
+#include "krylov.hpp"
+
+namespace psfd {
+
+static constexpr int KB = 256;  // threads per block of the vector kernels
+
+PSFD_D double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// block-wide sum of cnt (<= MAXM + 1) complex values held per thread; thread 0..
+// of the block end with the totals in sm_out (LDS), valid after the call.
+template <int NV>
+PSFD_D void block_sum(double2 (&acc)[NV], int cnt, double2* sm /*[KB/64][NV]*/) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    if (i < cnt) {
+      double re = wave_sum(acc[i].x), im = wave_sum(acc[i].y);
+      if (lane == 0) sm[wave * NV + i] = make_double2(re, im);
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < cnt) {
+    double2 t = sm[threadIdx.x];
+    for (int wv = 1; wv < KB / 64; ++wv) t = cadd(t, sm[wv * NV + threadIdx.x]);
+    sm[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(KB) k_dots(const T* V, long long ldv, long long bsv, long long n, GState* st,
+                                             const int* run, double2* part) {
+  __shared__ double2 sm[(KB / 64) * (MAXM + 1)];
+  const int b = blockIdx.y;
+  if (!run[b]) return;
+  const int cnt = st[b].j + 1;
+  const T* Vb = V + (long long)b * bsv;
+  const T* wb = Vb + (long long)cnt * ldv;
+  double2 acc[MAXM + 1];
+#pragma unroll
+  for (int i = 0; i < MAXM + 1; ++i) acc[i] = make_double2(0, 0);
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
+    double2 wv = to_d(wb[e]);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (i < cnt) {
+        double2 v = to_d(Vb[(long long)i * ldv + e]);
+        acc[i].x += v.x * wv.x + v.y * wv.y;
+        acc[i].y += v.x * wv.y - v.y * wv.x;
+      }
+    }
+  }
+  block_sum<MAXM + 1>(acc, cnt, sm);
+  if ((int)threadIdx.x < cnt) part[((long long)b * gridDim.x + blockIdx.x) * (MAXM + 1) + threadIdx.x] = sm[threadIdx.x];
+}
+
+__global__ void k_dots_final(GState* st, const int* run, const double2* part, int nblk, int first) {
+  const int b = blockIdx.x;
+  if (!run[b]) return;
+  const int cnt = st[b].j + 1;
+  const int i = threadIdx.x;
+  if (i >= cnt) return;
+  double2 t = make_double2(0, 0);
+  const double2* p = part + (long long)b * nblk * (MAXM + 1) + i;
+  for (int k = 0; k < nblk; ++k) t = cadd(t, p[(long long)k * (MAXM + 1)]);
+  st[b].hc[i] = t;
+  st[b].h[i] = first ? t : cadd(st[b].h[i], t);
+}
+
+template <class T>
+void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
+                 double2* part, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL((k_dots<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, run, part);
+  hipLaunchKernelGGL(k_dots_final, dim3(nbatch), dim3(64), 0, s, st, run, (const double2*)part, RED_BLOCKS, first);
+}
+
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bsv, long long n, GState* st,
+                                               const int* run, double2* part) {
+  __shared__ double2 sm[(KB / 64) * 1];
+  __shared__ double2 hs[MAXM + 1];
+  const int b = blockIdx.y;
+  if (!run[b]) return;
+  const int cnt = st[b].j + 1;
+  if ((int)threadIdx.x < cnt) hs[threadIdx.x] = st[b].hc[threadIdx.x];
+  __syncthreads();
+  T* Vb = V + (long long)b * bsv;
+  T* wb = Vb + (long long)cnt * ldv;
+  double2 nn[1] = {make_double2(0, 0)};
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
+    double2 s = make_double2(0, 0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (i < cnt) {
+        double2 v = to_d(Vb[(long long)i * ldv + e]);
+        double2 h = hs[i];
+        s.x += h.x * v.x - h.y * v.y;
+        s.y += h.x * v.y + h.y * v.x;
+      }
+    }
+    double2 wv = to_d(wb[e]);
+    wv.x -= s.x;
+    wv.y -= s.y;
+    T o = from_d<T>(wv);
+    wb[e] = o;
+    double2 od = to_d(o);
+    nn[0].x += od.x * od.x + od.y * od.y;
+  }
+  block_sum<1>(nn, 1, sm);
+  if (threadIdx.x == 0) part[((long long)b * gridDim.x + blockIdx.x)] = sm[0];
+}
+
+__global__ void k_update_final(GState* st, const int* run, const double2* part, int nblk) {
+  const int b = blockIdx.x;
+  if (!run[b] || threadIdx.x != 0) return;
+  double t = 0;
+  const double2* p = part + (long long)b * nblk;
+  for (int k = 0; k < nblk; ++k) t += p[k].x;
+  st[b].wn2 = t;
+}
+
+template <class T>
+void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, double2* part,
+                   int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL((k_update<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, run, part);
+  hipLaunchKernelGGL(k_update_final, dim3(nbatch), dim3(64), 0, s, st, run, (const double2*)part, RED_BLOCKS);
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_givens(GState* st, int* run) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0 || !run[b]) return;
+  GState& S = st[b];
+  const int j = S.j;
+  double2 col[MAXM + 1];
+  for (int i = 0; i <= j; ++i) col[i] = S.h[i];
+  const double hn = sqrt(S.wn2);
+  for (int i = 0; i < j; ++i) {
+    double2 a = col[i], c = col[i + 1];
+    double2 sn = S.sn[i];
+    double cs = S.cs[i];
+    col[i] = cadd(cscale(a, cs), cmul(sn, c));
+    col[i + 1] = csub(cscale(c, cs), cmulc(a, sn) /* a * conj(sn) */);
+  }
+  double2 a = col[j];
+  double aa = sqrt(cabs2(a));
+  double den = hypot(aa, hn);
+  double cs;
+  double2 sn;
+  if (aa == 0.0) { cs = 0.0; sn = make_double2(1.0, 0.0); }
+  else { cs = aa / den; sn = make_double2(a.x / aa * hn / den, a.y / aa * hn / den); }
+  col[j] = cadd(cscale(a, cs), cscale(sn, hn));
+  S.cs[j] = cs;
+  S.sn[j] = sn;
+  double2 gj = S.g[j];
+  // g_{j+1} = -conj(sn) g_j ; g_j = cs g_j
+  double2 csn = make_double2(sn.x, -sn.y);
+  double2 gn = cmul(csn, gj);
+  S.g[j + 1] = make_double2(-gn.x, -gn.y);
+  S.g[j] = cscale(gj, cs);
+  for (int i = 0; i <= j; ++i) S.H[i][j] = col[i];
+  S.res = sqrt(cabs2(S.g[j + 1]));
+  S.iters += 1;
+  S.ncols = j + 1;
+  S.inv_norm = hn > 0.0 ? 1.0 / hn : 0.0;
+  S.conv = S.res <= S.target;
+  const bool breakdown = !(hn > 1e-300 * (S.beta > 0 ? S.beta : 1.0));
+  S.stop = S.conv || (j + 1 >= S.m) || breakdown || !(S.res == S.res);
+  run[b] = S.stop ? 0 : 1;
+}
+
+void krylov_givens(GState* st, int* run, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_givens, dim3(nbatch), dim3(64), 0, s, st, run);
+}
+
+template <class T>
+__global__ void __launch_bounds__(KB) k_scale_next(T* V, long long ldv, long long bsv, long long n, GState* st,
+                                                   const int* run) {
+  const int b = blockIdx.y;
+  if (!run[b]) return;
+  const int j = st[b].j;
+  typedef typename real_of<T>::type R;
+  const R sc = (R)st[b].inv_norm;
+  T* v = V + (long long)b * bsv + (long long)(j + 1) * ldv;
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
+    T t = v[e];
+    t.x *= sc;
+    t.y *= sc;
+    v[e] = t;
+  }
+}
+
+__global__ void k_advance(GState* st) {
+  const int b = blockIdx.x;
+  if (threadIdx.x == 0 && !st[b].stop) st[b].j += 1;
+}
+
+template <class T>
+void krylov_scale_next(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int nbatch,
+                       hipStream_t s) {
+  int nb = (int)((n + KB - 1) / KB);
+  if (nb > 1024) nb = 1024;
+  hipLaunchKernelGGL((k_scale_next<T>), dim3(nb, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, run);
+}
+
+void krylov_advance(GState* st, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(nbatch), dim3(64), 0, s, st);
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_solve_small(GState* st, const int* mask) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0 || (mask && !mask[b])) return;
+  GState& S = st[b];
+  const int k = S.ncols;
+  for (int i = k - 1; i >= 0; --i) {
+    double2 t = S.g[i];
+    for (int c = i + 1; c < k; ++c) t = csub(t, cmul(S.H[i][c], S.y[c]));
+    S.y[i] = cdiv(t, S.H[i][i]);
+  }
+}
+
+void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_solve_small, dim3(nbatch), dim3(64), 0, s, st, mask);
+}
+
+template <class T, class TX>
+__global__ void __launch_bounds__(KB) k_lincomb(const T* V, long long ldv, long long bsv, TX* x, long long bsx,
+                                                long long n, GState* st, const int* mask) {
+  __shared__ double2 ys[MAXM];
+  const int b = blockIdx.y;
+  if (mask && !mask[b]) return;
+  const int k = st[b].ncols;
+  if ((int)threadIdx.x < k) ys[threadIdx.x] = st[b].y[threadIdx.x];
+  __syncthreads();
+  if (k == 0) return;
+  const T* Vb = V + (long long)b * bsv;
+  TX* xb = x + (long long)b * bsx;
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
+    double2 s = make_double2(0, 0);
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+      if (i < k) {
+        double2 v = to_d(Vb[(long long)i * ldv + e]);
+        s = cadd(s, cmul(ys[i], v));
+      }
+    }
+    double2 xv = to_d(xb[e]);
+    xb[e] = from_d<TX>(cadd(xv, s));
+  }
+}
+
+template <class T, class TX>
+void krylov_lincomb(const T* V, long long ldv, long long bsv, TX* x, long long bsx, long long n,
+                    GState* st, const int* mask, int nbatch, hipStream_t s) {
+  int nb = (int)((n + KB - 1) / KB);
+  if (nb > 2048) nb = 2048;
+  hipLaunchKernelGGL((k_lincomb<T, TX>), dim3(nb, nbatch), dim3(KB), 0, s, V, ldv, bsv, x, bsx, n, st, mask);
+}
+
+__global__ void k_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
+                        const int* mask, int* run) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  GState& S = st[b];
+  const double rn = sqrt(rnorm2[b]);
+  S.j = 0;
+  S.m = m;
+  S.ncols = 0;
+  S.beta = rn;
+  S.g[0] = make_double2(rn, 0.0);
+  for (int i = 1; i <= MAXM; ++i) S.g[i] = make_double2(0, 0);
+  double t = eta * rn;
+  S.target = abs_target[b] > t ? abs_target[b] : t;
+  S.res = rn;
+  S.conv = 0;
+  const bool go = (!mask || mask[b]) && rn > abs_target[b] && rn > 0.0 && rn == rn;
+  S.stop = go ? 0 : 1;
+  run[b] = go ? 1 : 0;
+}
+
+void krylov_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
+                  const int* mask, int* run, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_start, dim3(nbatch), dim3(64), 0, s, st, rnorm2, abs_target, eta, m, mask, run);
+}
+
+// ---------------------------------------------------------------------------
+template <class TO, class TX, class TY>
+__global__ void __launch_bounds__(KB) k_axpby(TO* out, const TX* x, const TY* y, double a, double c, long long n,
+                                              long long bs, const int* mask) {
+  const int b = blockIdx.y;
+  if (mask && !mask[b]) return;
+  const long long o = (long long)b * bs;
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
+    double2 xv = to_d(x[o + e]);
+    double2 r = make_double2(a * xv.x, a * xv.y);
+    if (y) { double2 yv = to_d(y[o + e]); r.x += c * yv.x; r.y += c * yv.y; }
+    out[o + e] = from_d<TO>(r);
+  }
+}
+
+template <class TO, class TX, class TY>
+void vec_axpby(TO* out, const TX* x, const TY* y, double a, double c, long long n, long long bstride,
+               const int* mask, int nbatch, hipStream_t s) {
+  int nb = (int)((n + KB - 1) / KB);
+  if (nb > 2048) nb = 2048;
+  hipLaunchKernelGGL((k_axpby<TO, TX, TY>), dim3(nb, nbatch), dim3(KB), 0, s, out, x, y, a, c, n, bstride, mask);
+}
+
+template <class T>
+__global__ void __launch_bounds__(KB) k_norm2(const T* x, long long n, long long bs, double* part, const int* mask) {
+  __shared__ double2 sm[KB / 64];
+  const int b = blockIdx.y;
+  if (mask && !mask[b]) return;
+  const T* xb = x + (long long)b * bs;
+  double2 acc[1] = {make_double2(0, 0)};
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
+    double2 v = to_d(xb[e]);
+    acc[0].x += v.x * v.x + v.y * v.y;
+  }
+  block_sum<1>(acc, 1, sm);
+  if (threadIdx.x == 0) part[(long long)b * gridDim.x + blockIdx.x] = sm[0].x;
+}
+
+__global__ void k_sum_part(const double* part, int nblk, double* out, const int* mask) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0 || (mask && !mask[b])) return;
+  double t = 0;
+  for (int k = 0; k < nblk; ++k) t += part[(long long)b * nblk + k];
+  out[b] = t;
+}
+
+template <class T>
+void vec_norm2(const T* x, long long n, long long bstride, double* part, double* out, const int* mask,
+               int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL((k_norm2<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, x, n, bstride, part, mask);
+  hipLaunchKernelGGL(k_sum_part, dim3(nbatch), dim3(64), 0, s, (const double*)part, RED_BLOCKS, out, mask);
+}
+
+template <class T>
+__global__ void __launch_bounds__(KB) k_diff2(const T* x, const T* y, long long n, long long bs, double* part) {
+  __shared__ double2 sm[(KB / 64) * 2];
+  const int b = blockIdx.y;
+  const T* xb = x + (long long)b * bs;
+  const T* yb = y + (long long)b * bs;
+  double2 acc[2] = {make_double2(0, 0), make_double2(0, 0)};
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
+    double2 u = to_d(xb[e]), v = to_d(yb[e]);
+    double2 d = csub(u, v);
+    acc[0].x += d.x * d.x + d.y * d.y;
+    acc[1].x += u.x * u.x + u.y * u.y;
+  }
+  block_sum<2>(acc, 2, sm);
+  if (threadIdx.x == 0) {
+    part[((long long)b * gridDim.x + blockIdx.x) * 2] = sm[0].x;
+    part[((long long)b * gridDim.x + blockIdx.x) * 2 + 1] = sm[1].x;
+  }
+}
+
+__global__ void k_sum_part2(const double* part, int nblk, double* out) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double t0 = 0, t1 = 0;
+  for (int k = 0; k < nblk; ++k) { t0 += part[((long long)b * nblk + k) * 2]; t1 += part[((long long)b * nblk + k) * 2 + 1]; }
+  out[2 * b] = t0;
+  out[2 * b + 1] = t1;
+}
+
+template <class T>
+void vec_diff2(const T* x, const T* y, long long n, long long bstride, double* part, double* out,
+               int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL((k_diff2<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, x, y, n, bstride, part);
+  hipLaunchKernelGGL(k_sum_part2, dim3(nbatch), dim3(64), 0, s, (const double*)part, RED_BLOCKS, out);
+}
+
+template <class TO, class TX>
+__global__ void __launch_bounds__(KB) k_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n,
+                                                      long long bs, const int* mask) {
+  const int b = blockIdx.y;
+  if (mask && !mask[b]) return;
+  const double v = n2[b];
+  const double sc = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+  const long long o = (long long)b * bs;
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
+    double2 xv = to_d(x[o + e]);
+    out[o + e] = from_d<TO>(make_double2(xv.x * sc, xv.y * sc));
+  }
+}
+
+template <class TO, class TX>
+void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long long bstride,
+                       const int* mask, int nbatch, hipStream_t s) {
+  int nb = (int)((n + KB - 1) / KB);
+  if (nb > 2048) nb = 2048;
+  hipLaunchKernelGGL((k_scale_invsqrt<TO, TX>), dim3(nb, nbatch), dim3(KB), 0, s, out, x, n2, n, bstride, mask);
+}
+
+// ---- instantiations ----------------------------------------------------------
+#define INST_T(T)                                                                                       \
+  template void krylov_dots<T>(const T*, long long, long long, long long, GState*, const int*, int,      \
+                               double2*, int, hipStream_t);                                             \
+  template void krylov_update<T>(T*, long long, long long, long long, GState*, const int*, double2*,     \
+                                 int, hipStream_t);                                                     \
+  template void krylov_scale_next<T>(T*, long long, long long, long long, GState*, const int*, int,      \
+                                     hipStream_t);                                                      \
+  template void vec_norm2<T>(const T*, long long, long long, double*, double*, const int*, int,          \
+                             hipStream_t);                                                              \
+  template void vec_diff2<T>(const T*, const T*, long long, long long, double*, double*, int, hipStream_t);
+INST_T(float2)
+INST_T(double2)
+template void krylov_lincomb<float2, double2>(const float2*, long long, long long, double2*, long long, long long,
+                                              GState*, const int*, int, hipStream_t);
+template void krylov_lincomb<double2, double2>(const double2*, long long, long long, double2*, long long,
+                                               long long, GState*, const int*, int, hipStream_t);
+template void vec_axpby<double2, double2, double2>(double2*, const double2*, const double2*, double, double,
+                                                   long long, long long, const int*, int, hipStream_t);
+template void vec_axpby<float2, double2, double2>(float2*, const double2*, const double2*, double, double,
+                                                  long long, long long, const int*, int, hipStream_t);
+template void vec_axpby<double2, float2, float2>(double2*, const float2*, const float2*, double, double,
+                                                 long long, long long, const int*, int, hipStream_t);
+template void vec_axpby<float2, float2, float2>(float2*, const float2*, const float2*, double, double,
+                                                long long, long long, const int*, int, hipStream_t);
+template void vec_scale_invsqrt<double2, double2>(double2*, const double2*, const double*, long long, long long,
+                                                  const int*, int, hipStream_t);
+template void vec_scale_invsqrt<float2, double2>(float2*, const double2*, const double*, long long, long long,
+                                                 const int*, int, hipStream_t);
+
+}  // namespace psfd

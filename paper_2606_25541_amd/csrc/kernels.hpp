@@ -1,0 +1,59 @@
+// Kernel argument structures and host-side launch wrappers.
+#pragma once
+#include "layout.hpp"
+
+namespace psfd {
+
+enum LoadOp { LD_PLAIN = 0, LD_VX = 1, LD_INJECT = 2, LD_VXE = 3 };
+enum StoreOp { ST_PLAIN = 0, ST_AXPBY = 1 };
+
+// One launch of the transverse (x/y) FFT kernel over tiles of every plane of
+// every instance. A tile is ty rows x tx columns of one (component, z) plane.
+struct TileArgs {
+  int nx, ny, nz, log2nx, log2ny;
+  int tx, ty, pitch;
+  int tiles_x, tiles_y;
+  int do_x, do_y;
+  VecRef in, aux, out;   // fields [3][nz][ny][nx]
+  VecRef vol;            // contrast delta_eps [nz][ny][nx] (times k0^2 on load)
+  const double* tab;     // per-instance tables (TabLayout), stride tab_stride doubles
+  long long tab_stride;
+  const double2* eup;    // LD_INJECT: upgoing amplitudes [ny*nx][3] per instance
+  long long eup_stride;
+  const void* tw;        // twiddle table in the working precision
+  double alpha, gamma;   // ST_AXPBY: out = alpha * aux + gamma * result
+  const int* active;     // optional per-instance flags (0 = skip)
+};
+
+// One launch of the z-pencil kernel: forward z-FFT over the zero-padded
+// length pz = 2 nz, multiply by the dyadic kernel, inverse z-FFT, keep nz.
+struct PencilArgs {
+  int nx, ny, nz, pz, log2pz, bx, pitch, nblk_x;
+  VecRef w;
+  const double* tab;
+  long long tab_stride;
+  const void* tw;
+  int transpose;         // use the kernel at the negated wavevector (bilinear transpose)
+  const int* active;
+};
+
+struct TileShape { int tx, ty, do_x, do_y, nthr; size_t lds; };
+
+template <class T, bool INV, int LD, int ST>
+void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t lds, hipStream_t s);
+template <class T>
+void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStream_t s);
+
+// per-order readouts of the source density spectra (FP64):
+// adn = (i dz / 2 beta) P- sum_k exp(i beta z_k) f_q(z_k) / (NxNy), aup likewise at z = T.
+void launch_readout(int nx, int ny, int nz, VecRef spec, const double* tab, long long tab_stride,
+                    double2* adn, double2* aup, long long ostride, const int* active, int nbatch, hipStream_t s);
+// eup <- T_R (adn + e_inc), with partial sums of |change|^2 and |new|^2 per block
+void launch_reflect(int nx, int ny, const double* tab, long long tab_stride, const double2* adn,
+                    double2* eup, long long ostride, double* part, int nblk, const int* active, int nbatch,
+                    hipStream_t s);
+// orders = eup exp(i beta T) + aup
+void launch_orders(int nx, int ny, const double* tab, long long tab_stride, const double2* eup,
+                   const double2* aup, double2* orders, long long ostride, int nbatch, hipStream_t s);
+
+}  // namespace psfd

@@ -1,0 +1,84 @@
+// Restarted GMRES state and Krylov kernel launchers (device-side Arnoldi/Givens).
+//
+// Every launcher works on a batch of independent instances: instance b finds
+// its vectors at b * bstride and its state at st[b]; run[b] == 0 makes every
+// kernel skip that instance (converged, finished cycle or empty slot).
+// Reductions are two-stage with a fixed block count and a fixed summation
+// order, so results are bitwise reproducible and independent of the batch.
+#pragma once
+#include "layout.hpp"
+
+namespace psfd {
+
+constexpr int MAXM = 32;          // largest supported restart length
+constexpr int RED_BLOCKS = 256;   // blocks per instance of the first reduction stage
+
+// Device-resident state of one GMRES(m) instance. All scalars are FP64.
+struct GState {
+  int j;            // index of the newest basis vector v_j (the column being built)
+  int m;            // restart length
+  int stop;         // cycle finished (converged, full or breakdown)
+  int conv;         // residual estimate at or below target
+  int iters;        // Arnoldi steps taken (all cycles)
+  int ncols;        // Hessenberg columns completed in the current cycle
+  int pad[2];
+  double target;    // stopping threshold of the residual estimate
+  double res;       // |g_{j+1}|: current residual estimate
+  double beta;      // ||r0|| of the current cycle
+  double inv_norm;  // 1 / h_{j+1,j}
+  double wn2;       // ||w||^2 after the last orthogonalisation pass
+  double pad2[3];
+  double2 H[MAXM + 1][MAXM];  // rotated Hessenberg matrix (upper triangle used)
+  double cs[MAXM];
+  double2 sn[MAXM];
+  double2 g[MAXM + 1];
+  double2 y[MAXM];
+  double2 h[MAXM + 1];        // Gram-Schmidt coefficients summed over passes
+  double2 hc[MAXM + 1];       // coefficients of the current pass
+};
+
+// w = v_{j+1} (the new apply output): hc[i] = <v_i, w> for i = 0..j (h += hc, or h = hc when first)
+template <class T>
+void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
+                 double2* part, int nbatch, hipStream_t s);
+// w = v_{j+1}: w -= sum_{i<=j} hc_i v_i ; wn2 = ||w||^2 afterwards
+template <class T>
+void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, double2* part,
+                   int nbatch, hipStream_t s);
+// Givens rotation of the new Hessenberg column, residual estimate, inv_norm, stop/run flags
+void krylov_givens(GState* st, int* run, int nbatch, hipStream_t s);
+// v_{j+1} *= inv_norm (in place), then j <- j + 1 unless the cycle stopped
+template <class T>
+void krylov_scale_next(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int nbatch,
+                       hipStream_t s);
+void krylov_advance(GState* st, int nbatch, hipStream_t s);
+// y = H^{-1} g over the k = j + 1 completed columns
+void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s);
+// x += sum_{i<k} y_i v_i
+template <class T, class TX>
+void krylov_lincomb(const T* V, long long ldv, long long bsv, TX* x, long long bsx, long long n,
+                    GState* st, const int* mask, int nbatch, hipStream_t s);
+// start a cycle from rnorm2[b] = ||r_b||^2: g = (||r||, 0, ...), j = 0,
+// target = max(abs_target[b], eta ||r||); run[b] = mask[b] && ||r|| > abs_target[b]
+void krylov_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
+                  const int* mask, int* run, int nbatch, hipStream_t s);
+
+// ---- batched vector kernels (instance b at offset b * bstride) ---------------
+// out = a x + c y (any mix of precisions; y may be null)
+template <class TO, class TX, class TY>
+void vec_axpby(TO* out, const TX* x, const TY* y, double a, double c, long long n, long long bstride,
+               const int* mask, int nbatch, hipStream_t s);
+// out[b] = ||x_b||^2
+template <class T>
+void vec_norm2(const T* x, long long n, long long bstride, double* part, double* out, const int* mask,
+               int nbatch, hipStream_t s);
+// out = x / sqrt(n2[b]) (0 when n2[b] == 0)
+template <class TO, class TX>
+void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long long bstride,
+                       const int* mask, int nbatch, hipStream_t s);
+// out[b] = ||x_b - y_b||^2 and ||x_b||^2 (for relative changes); out has 2 doubles per instance
+template <class T>
+void vec_diff2(const T* x, const T* y, long long n, long long bstride, double* part, double* out,
+               int nbatch, hipStream_t s);
+
+}  // namespace psfd
