@@ -55,7 +55,8 @@ enum {
 enum { PSFD_TE = 0, PSFD_TM = 1 };
 enum { PSFD_FP64 = 0, PSFD_MIXED = 1 };             /* psfd_opts.precision */
 enum { PSFD_C64 = 0, PSFD_C128 = 1 };               /* dtype of psfd_apply */
-enum { PSFD_APPLY_TRANSPOSE = 1, PSFD_APPLY_K_ONLY = 2 }; /* psfd_apply flags */
+enum { PSFD_APPLY_TRANSPOSE = 1, PSFD_APPLY_K_ONLY = 2, PSFD_APPLY_REFLECT = 4 }; /* psfd_apply flags */
+enum { PSFD_COUPLING_OUTER = 0, PSFD_COUPLING_MONO = 1 };  /* psfd_opts.coupling */
 
 typedef struct { double eps_re, eps_im, thickness_nm; } psfd_layer; /* top to bottom */
 
@@ -77,11 +78,16 @@ typedef struct {
  * max_iters: Arnoldi steps per linear solve; max_outer: outer iterations;
  * precision: PSFD_FP64, or PSFD_MIXED (FP32 Arnoldi cycles, FP64 residual and
  * solution: each restart recomputes the residual in FP64); inner_eta: relative
- * reduction asked of one FP32 cycle (<= 0: 1e-4). */
+ * reduction asked of one FP32 cycle (<= 0: 1e-4); coupling: PSFD_COUPLING_OUTER
+ * runs the outer fixed point of eqs. (8)-(9) (each step a GMRES solve of eq. (18),
+ * rtol tightened to 0.1 rtol as the reflection settles), PSFD_COUPLING_MONO runs
+ * GMRES once on (I - (K + R_vol T_R K_top) V) u = e_bg, whose solution is that
+ * fixed point (default). */
 typedef struct {
   double rtol, outer_rtol;
   int32_t restart, max_iters, max_outer, precision;
   double inner_eta;
+  int32_t coupling;
 } psfd_opts;
 
 typedef struct {
@@ -109,7 +115,8 @@ int psfd_plan_footprint(const psfd_plan* plan, size_t* device_bytes);
 
 /* One operator apply (eq. (18)): y = x - K(V x), or y = K(V x) with
  * PSFD_APPLY_K_ONLY; with PSFD_APPLY_TRANSPOSE the bilinear transpose (kernel at
- * the negated wavevector). d_deps [nz][ny][nx], d_x and d_y [3][nz][ny][nx], all of
+ * the negated wavevector); with PSFD_APPLY_REFLECT, K is replaced by the coupled
+ * M = K + R_vol T_R K_top (free space plus the multilayer response of eq. (9)). d_deps [nz][ny][nx], d_x and d_y [3][nz][ny][nx], all of
  * `dtype` (complex64 or complex128), device memory; d_y must not alias d_x.
  * Uses a plan-owned scratch field (allocated on first use). */
 int psfd_apply(psfd_plan* plan, const void* d_deps, const void* d_x, void* d_y, int dtype, int flags,
@@ -149,6 +156,15 @@ int psfd_server_submit(psfd_server* srv, const psfd_problem* prob, const void* d
  * completion wall time. */
 int psfd_server_poll(psfd_server* srv, uint64_t ticket, int32_t* done, psfd_info* info, double* latency_s);
 int psfd_server_destroy(psfd_server* srv);
+
+/* Diagnostics: run stage `stage` of psfd_apply (0: transverse forward FFT with
+ * the contrast multiply, 1: z-pencil FFT / dyadic kernel / inverse, 2: transverse
+ * inverse FFT with the axpy) `reps` times back to back between two HIP events on
+ * `stream` and store the mean time per launch in *ms. Same buffers as psfd_apply
+ * (d_y receives stage 2's output; the plan scratch holds stages 0-1). For
+ * throughput measurements; results of a lone stage are not an operator apply. */
+int psfd_bench_stage(psfd_plan* plan, int stage, const void* d_deps, const void* d_x, void* d_y, int dtype,
+                     int reps, float* ms, void* stream);
 
 const char* psfd_status_string(int status);
 const char* psfd_last_error(void);

@@ -22,7 +22,8 @@ PSFD_ERR_HIP = -6
 PSFD_TE, PSFD_TM = 0, 1
 PSFD_FP64, PSFD_MIXED = 0, 1
 PSFD_C64, PSFD_C128 = 0, 1
-PSFD_APPLY_TRANSPOSE, PSFD_APPLY_K_ONLY = 1, 2
+PSFD_APPLY_TRANSPOSE, PSFD_APPLY_K_ONLY, PSFD_APPLY_REFLECT = 1, 2, 4
+PSFD_COUPLING_OUTER, PSFD_COUPLING_MONO = 0, 1
 
 
 class psfd_layer(C.Structure):
@@ -41,7 +42,7 @@ class psfd_problem(C.Structure):
 class psfd_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("outer_rtol", C.c_double), ("restart", C.c_int32),
                 ("max_iters", C.c_int32), ("max_outer", C.c_int32), ("precision", C.c_int32),
-                ("inner_eta", C.c_double)]
+                ("inner_eta", C.c_double), ("coupling", C.c_int32)]
 
 
 class psfd_info(C.Structure):
@@ -70,6 +71,8 @@ EXPORTS = {
     "psfd_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(psfd_info),
                                    C.POINTER(C.c_double)]),
     "psfd_server_destroy": (C.c_int, [C.c_void_p]),
+    "psfd_bench_stage": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                   C.POINTER(C.c_float), C.c_void_p]),
     "psfd_status_string": (C.c_char_p, [C.c_int]),
     "psfd_last_error": (C.c_char_p, []),
     "psfd_version": (C.c_char_p, []),

@@ -26,10 +26,12 @@ def _c_problem(p) -> Tuple[L.psfd_problem, object]:
 
 
 def _c_opts(rtol=1e-6, outer_rtol=None, restart=30, max_iters=5000, max_outer=100, precision="mixed",
-            inner_eta=1e-4) -> L.psfd_opts:
+            inner_eta=1e-4, coupling="mono") -> L.psfd_opts:
     prec = {"fp64": L.PSFD_FP64, "mixed": L.PSFD_MIXED}[precision] if isinstance(precision, str) else int(precision)
+    cpl = {"outer": L.PSFD_COUPLING_OUTER, "mono": L.PSFD_COUPLING_MONO}[coupling] if isinstance(coupling, str) \
+        else int(coupling)
     return L.psfd_opts(float(rtol), float(outer_rtol if outer_rtol is not None else rtol), int(restart),
-                       int(max_iters), int(max_outer), prec, float(inner_eta))
+                       int(max_iters), int(max_outer), prec, float(inner_eta), cpl)
 
 
 def _stream() -> C.c_void_p:
@@ -75,8 +77,8 @@ class Plan:
         return (3, self.nz, self.ny, self.nx)
 
     def psfd_apply(self, deps: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None,
-                   transpose: bool = False, k_only: bool = False) -> torch.Tensor:
-        """y = x - K(V x) (or K(V x)); complex64 or complex128 device tensors."""
+                   transpose: bool = False, k_only: bool = False, reflect: bool = False) -> torch.Tensor:
+        """y = x - K(V x) (or K(V x)); reflect: K -> M = K + R_vol T_R K_top."""
         dt = x.dtype
         code = {torch.complex64: L.PSFD_C64, torch.complex128: L.PSFD_C128}[dt]
         _dev(deps, dt, "deps")
@@ -86,7 +88,8 @@ class Plan:
         if out is None:
             out = torch.empty_like(x)
         _dev(out, dt, "out")
-        flags = (L.PSFD_APPLY_TRANSPOSE if transpose else 0) | (L.PSFD_APPLY_K_ONLY if k_only else 0)
+        flags = (L.PSFD_APPLY_TRANSPOSE if transpose else 0) | (L.PSFD_APPLY_K_ONLY if k_only else 0) | \
+            (L.PSFD_APPLY_REFLECT if reflect else 0)
         L.check(L.lib().psfd_apply(self._h, C.c_void_p(deps.data_ptr()), C.c_void_p(x.data_ptr()),
                                    C.c_void_p(out.data_ptr()), code, flags, _stream()), "psfd_apply")
         return out

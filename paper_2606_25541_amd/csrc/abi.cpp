@@ -113,13 +113,52 @@ int psfd_apply(psfd_plan* plan, const void* d_deps, const void* d_x, void* d_y, 
   }
   const int kmode = (flags & PSFD_APPLY_K_ONLY) ? 1 : 0;
   const int tr = (flags & PSFD_APPLY_TRANSPOSE) ? 1 : 0;
+  const int rf = (flags & PSFD_APPLY_REFLECT) ? 1 : 0;
   Group& g = *plan->lite;
   if (dtype == PSFD_C64)
-    apply_op<float2>(g, (const float2*)d_deps, vr(d_x), vr(d_y), (float2*)scratch, kmode, tr, nullptr, s);
+    apply_op<float2>(g, (const float2*)d_deps, vr(d_x), vr(d_y), (float2*)scratch, kmode, tr, rf, nullptr, s);
   else
-    apply_op<double2>(g, (const double2*)d_deps, vr(d_x), vr(d_y), (double2*)scratch, kmode, tr, nullptr, s);
+    apply_op<double2>(g, (const double2*)d_deps, vr(d_x), vr(d_y), (double2*)scratch, kmode, tr, rf, nullptr, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(hip_status(e, "apply launch"));
+  return PSFD_OK;
+}
+
+int psfd_bench_stage(psfd_plan* plan, int stage, const void* d_deps, const void* d_x, void* d_y, int dtype,
+                     int reps, float* ms, void* stream) {
+  if (!plan || !d_deps || !d_x || !d_y || !ms || reps < 1 || stage < 0 || stage > 2)
+    return fail(PSFD_ERR_INVALID_ARG, "bad arguments");
+  if (dtype != PSFD_C64 && dtype != PSFD_C128) return fail(PSFD_ERR_INVALID_ARG, "bad dtype");
+  hipStream_t s = (hipStream_t)stream;
+  Status st = ensure_lite(plan, s);
+  if (!st.ok()) return fail(st);
+  const size_t esz = dtype == PSFD_C64 ? 8 : 16;
+  void*& scratch = dtype == PSFD_C64 ? plan->scratch32 : plan->scratch64;
+  if (!scratch) {
+    hipError_t e = hipMalloc(&scratch, (size_t)plan->sh.n3 * esz);
+    if (e != hipSuccess) return fail(hip_status(e, "hipMalloc"));
+    (void)hipMemsetAsync(scratch, 0, (size_t)plan->sh.n3 * esz, s);
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(PSFD_ERR_HIP, "hipEventCreate");
+  Group& g = *plan->lite;
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < reps; ++r) {
+    if (dtype == PSFD_C64)
+      apply_stage<float2>(g, stage, (const float2*)d_deps, vr(d_x), vr(d_y), (float2*)scratch, 0, 0, 1, nullptr, s);
+    else
+      apply_stage<double2>(g, stage, (const double2*)d_deps, vr(d_x), vr(d_y), (double2*)scratch, 0, 0, 1,
+                           nullptr, s);
+  }
+  (void)hipEventRecord(e1, s);
+  hipError_t e = hipEventSynchronize(e1);
+  float t = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(hip_status(e, "stage timing"));
+  *ms = t / reps;
   return PSFD_OK;
 }
 

@@ -13,6 +13,10 @@ namespace psfd {
 using cd = std::complex<double>;
 static const double PI = 3.14159265358979323846;
 static const size_t LDS_MAX = 163840;
+// inner (eq. (18)) tolerance policy of the outer loop
+static const double INNER_FACTOR = 0.1;     // final inner rtol = INNER_FACTOR * rtol
+static const double FIRST_INNER_TOL = 1e-3; // first outer step
+static const double OUTER_TO_INNER = 0.1;   // inner rtol <= OUTER_TO_INNER * last outer change
 
 Status hip_status(hipError_t e, const char* what) {
   Status st;
@@ -69,6 +73,12 @@ Status make_opts(const psfd_opts* o, Opts& out) {
   out.max_outer = o->max_outer;
   out.precision = o->precision;
   out.inner_eta = o->inner_eta > 0 ? o->inner_eta : 1e-4;
+  if (o->coupling != PSFD_COUPLING_OUTER && o->coupling != PSFD_COUPLING_MONO) {
+    st.code = PSFD_ERR_INVALID_ARG;
+    st.msg = "coupling must be PSFD_COUPLING_OUTER or PSFD_COUPLING_MONO";
+    return st;
+  }
+  out.coupling = o->coupling;
   return st;
 }
 
@@ -228,11 +238,13 @@ XYCfg xy_config(const Shape& sh, size_t esz) {
 ZCfg z_config(const Shape& sh, size_t esz) {
   ZCfg z{};
   int bx = std::min(sh.nx, 16);
-  while (bx > 1 && (size_t)3 * bx * (sh.pz + 1) * esz > 150 * 1024) bx >>= 1;
+  while (bx > 1 && (size_t)3 * bx * (sh.pz + 1) * esz + (size_t)bx * sh.nz * esz + 3 * bx * 16 + 16 > 150 * 1024)
+    bx >>= 1;
   z.bx = bx;
   z.nthr = clampi(ceil64(3 * bx * sh.pz / 8), 64, 1024);
   while (3 * bx * sh.pz > 16 * z.nthr && z.nthr < 1024) z.nthr += 64;
-  z.lds = (size_t)3 * bx * (sh.pz + 1) * esz;
+  // pencil data, per-plane phases exp(i beta z_k) and the per-order layered response
+  z.lds = (size_t)3 * bx * (sh.pz + 1) * esz + (size_t)bx * sh.nz * esz + 16 + (size_t)3 * bx * 16;
   return z;
 }
 
@@ -278,7 +290,7 @@ size_t group_bytes(const Shape& sh, int B, int m, int prec) {
   per += 6 * n3 * 16;
   per += (size_t)(m + 1) * n3 * esz;
   per += prec == PSFD_MIXED ? n3 * esz : 0;
-  per += sizeof(GState) + RED_BLOCKS * (MAXM + 1) * 16 + RED_BLOCKS * 2 * 8;
+  per += sizeof(GState) + RED_BLOCKS * (MAXM + 2) * 16 + RED_BLOCKS * 2 * 8;
   per += 5 * (size_t)sh.nxny * 3 * 16 + (size_t)((sh.nxny + 255) / 256) * 2 * 8 + 64;
   return per * (size_t)B;
 }
@@ -325,7 +337,7 @@ Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec) {
   GALLOC(g.run, sizeof(int) * B);
   GALLOC(g.mask, sizeof(int) * B);
   GALLOC(g.mask2, sizeof(int) * B);
-  GALLOC(g.part, (size_t)RED_BLOCKS * (MAXM + 1) * 16 * B);
+  GALLOC(g.part, (size_t)RED_BLOCKS * (MAXM + 2) * 16 * B);
   GALLOC(g.n2, 8 * B);
   GALLOC(g.n2b, 8 * B);
   GALLOC(g.abs_target, 8 * B);
@@ -370,51 +382,69 @@ static TileArgs tile_base(const Group& g, const void* tw, const TileShape& t) {
 }
 
 template <class T>
-void apply_op(Group& g, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose,
-              const int* active, hipStream_t s) {
+void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose,
+                 int refl, const int* active, hipStream_t s) {
   const Shape& sh = g.sh;
   const XYCfg c = xy_config(sh, sizeof(T));
   const int np = 3 * sh.nz;
   const T* tw = twiddles<T>(g);
   VecRef wsr = vr(ws, sh.n3);
-  // forward: w = FFT_xy(k0^2 delta_eps x)
-  if (c.fused) {
-    TileArgs a = tile_base(g, tw, c.full);
-    a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
-    launch_tile<T, false, LD_VX, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
+  if (stage == 0) {
+    // forward: w = FFT_xy(k0^2 delta_eps x)
+    if (c.fused) {
+      TileArgs a = tile_base(g, tw, c.full);
+      a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
+      launch_tile<T, false, LD_VX, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
+    } else {
+      TileArgs a = tile_base(g, tw, c.rows);
+      a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
+      launch_tile<T, false, LD_VX, ST_PLAIN>(a, np, g.B, c.rows.nthr, c.rows.lds, s);
+      TileArgs b2 = tile_base(g, tw, c.cols);
+      b2.in = wsr; b2.out = wsr; b2.active = active;
+      launch_tile<T, false, LD_PLAIN, ST_PLAIN>(b2, np, g.B, c.cols.nthr, c.cols.lds, s);
+    }
+  } else if (stage == 1) {
+    // z: pad, FFT, kernel, IFFT, restrict (in place)
+    const ZCfg z = z_config(sh, sizeof(T));
+    PencilArgs p;
+    std::memset(&p, 0, sizeof(p));
+    p.nx = sh.nx; p.ny = sh.ny; p.nz = sh.nz; p.pz = sh.pz; p.log2pz = ilog2i(sh.pz);
+    p.bx = z.bx; p.pitch = sh.pz + 1; p.nblk_x = sh.nx / z.bx;
+    p.w = wsr; p.tab = g.tab; p.tab_stride = g.tab_stride; p.tw = tw; p.transpose = transpose; p.reflect = refl;
+    p.active = active;
+    launch_pencil<T>(p, g.B, z.nthr, z.lds, s);
   } else {
-    TileArgs a = tile_base(g, tw, c.rows);
-    a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
-    launch_tile<T, false, LD_VX, ST_PLAIN>(a, np, g.B, c.rows.nthr, c.rows.lds, s);
-    TileArgs b2 = tile_base(g, tw, c.cols);
-    b2.in = wsr; b2.out = wsr; b2.active = active;
-    launch_tile<T, false, LD_PLAIN, ST_PLAIN>(b2, np, g.B, c.cols.nthr, c.cols.lds, s);
-  }
-  // z: pad, FFT, kernel, IFFT, restrict (in place)
-  const ZCfg z = z_config(sh, sizeof(T));
-  PencilArgs p;
-  std::memset(&p, 0, sizeof(p));
-  p.nx = sh.nx; p.ny = sh.ny; p.nz = sh.nz; p.pz = sh.pz; p.log2pz = ilog2i(sh.pz);
-  p.bx = z.bx; p.pitch = sh.pz + 1; p.nblk_x = sh.nx / z.bx;
-  p.w = wsr; p.tab = g.tab; p.tab_stride = g.tab_stride; p.tw = tw; p.transpose = transpose; p.active = active;
-  launch_pencil<T>(p, g.B, z.nthr, z.lds, s);
-  // inverse: out = alpha in + gamma IFFT_xy(w)
-  const double al = kmode == 0 ? 1.0 : 0.0, ga = kmode == 0 ? -1.0 : 1.0;
-  if (c.fused) {
-    TileArgs a = tile_base(g, tw, c.full);
-    a.in = wsr; a.aux = in; a.out = out; a.alpha = al; a.gamma = ga; a.active = active;
-    launch_tile<T, true, LD_PLAIN, ST_AXPBY>(a, np, g.B, c.full.nthr, c.full.lds, s);
-  } else {
-    TileArgs a = tile_base(g, tw, c.cols);
-    a.in = wsr; a.out = wsr; a.active = active;
-    launch_tile<T, true, LD_PLAIN, ST_PLAIN>(a, np, g.B, c.cols.nthr, c.cols.lds, s);
-    TileArgs b2 = tile_base(g, tw, c.rows);
-    b2.in = wsr; b2.aux = in; b2.out = out; b2.alpha = al; b2.gamma = ga; b2.active = active;
-    launch_tile<T, true, LD_PLAIN, ST_AXPBY>(b2, np, g.B, c.rows.nthr, c.rows.lds, s);
+    // inverse: out = alpha in + gamma IFFT_xy(w)
+    const double al = kmode == 0 ? 1.0 : 0.0, ga = kmode == 0 ? -1.0 : 1.0;
+    if (c.fused) {
+      TileArgs a = tile_base(g, tw, c.full);
+      a.in = wsr; a.aux = in; a.out = out; a.alpha = al; a.gamma = ga; a.active = active;
+      launch_tile<T, true, LD_PLAIN, ST_AXPBY>(a, np, g.B, c.full.nthr, c.full.lds, s);
+    } else {
+      TileArgs a = tile_base(g, tw, c.cols);
+      a.in = wsr; a.out = wsr; a.active = active;
+      launch_tile<T, true, LD_PLAIN, ST_PLAIN>(a, np, g.B, c.cols.nthr, c.cols.lds, s);
+      TileArgs b2 = tile_base(g, tw, c.rows);
+      b2.in = wsr; b2.aux = in; b2.out = out; b2.alpha = al; b2.gamma = ga; b2.active = active;
+      launch_tile<T, true, LD_PLAIN, ST_AXPBY>(b2, np, g.B, c.rows.nthr, c.rows.lds, s);
+    }
   }
 }
-template void apply_op<float2>(Group&, const float2*, VecRef, VecRef, float2*, int, int, const int*, hipStream_t);
-template void apply_op<double2>(Group&, const double2*, VecRef, VecRef, double2*, int, int, const int*, hipStream_t);
+template void apply_stage<float2>(Group&, int, const float2*, VecRef, VecRef, float2*, int, int, int, const int*,
+                                  hipStream_t);
+template void apply_stage<double2>(Group&, int, const double2*, VecRef, VecRef, double2*, int, int, int,
+                                   const int*, hipStream_t);
+
+template <class T>
+void apply_op(Group& g, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose, int refl,
+              const int* active, hipStream_t s) {
+  for (int stage = 0; stage < 3; ++stage)
+    apply_stage<T>(g, stage, deps, in, out, ws, kmode, transpose, refl, active, s);
+}
+template void apply_op<float2>(Group&, const float2*, VecRef, VecRef, float2*, int, int, int, const int*,
+                               hipStream_t);
+template void apply_op<double2>(Group&, const double2*, VecRef, VecRef, double2*, int, int, int, const int*,
+                                hipStream_t);
 
 // e = E_inc + IFFT_xy(E_up exp(i beta z)) per plane (FP64)
 static void inject(Group& g, const double2* eup, double2* out, const int* active, hipStream_t s) {
@@ -492,7 +522,7 @@ template <> const float2* deps_of<float2>(const Group& g) { return g.deps32; }
 template <> const double2* deps_of<double2>(const Group& g) { return g.deps64; }
 
 template <class T>
-static void arnoldi_step(Group& g, int transpose, hipStream_t s) {
+static void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s) {
   T* V = (T*)g.basis;
   const long long n3 = g.sh.n3, bsv = (long long)(g.m + 1) * n3;
   VecRef vin;
@@ -500,11 +530,11 @@ static void arnoldi_step(Group& g, int transpose, hipStream_t s) {
   vin.idx = &g.st[0].j; vin.idx_stride = (int)(sizeof(GState) / sizeof(int)); vin.joff = 0;
   VecRef vout = vin;
   vout.joff = 1;
-  apply_op<T>(g, deps_of<T>(g), vin, vout, (T*)g.wsP, 0, transpose, g.run, s);
+  apply_op<T>(g, deps_of<T>(g), vin, vout, (T*)g.wsP, 0, transpose, refl, g.run, s);
   krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 1, g.part, g.B, s);
-  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.part, g.B, s);
+  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 1, g.part, g.B, s);
   krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 0, g.part, g.B, s);
-  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.part, g.B, s);
+  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 0, g.part, g.B, s);
   krylov_givens(g.st, g.run, g.B, s);
   krylov_scale_next<T>(V, n3, bsv, n3, g.st, g.run, g.B, s);
   krylov_advance(g.st, g.B, s);
@@ -514,8 +544,8 @@ static void arnoldi_step(Group& g, int transpose, hipStream_t s) {
 // Each cycle starts from the FP64 residual r = b - A x; the Arnoldi cycle runs
 // in the working precision T and x accumulates in FP64.
 template <class T>
-static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act, std::vector<SolveStats>& stats,
-                           int transpose, hipStream_t s) {
+static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act, const std::vector<double>& rtol,
+                           std::vector<SolveStats>& stats, int transpose, int refl, hipStream_t s) {
   const int B = g.B;
   const long long n3 = g.sh.n3, bsv = (long long)(g.m + 1) * n3;
   Status st = set_mask(g, g.mask, act, s);
@@ -525,7 +555,7 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   st = read_norms(g, g.n2b, bn2, s);
   if (!st.ok()) return st;
   std::vector<double> tgt(B, 0.0);
-  for (int b = 0; b < B; ++b) tgt[b] = o.rtol * std::sqrt(bn2[b]);
+  for (int b = 0; b < B; ++b) tgt[b] = rtol[b] * std::sqrt(bn2[b]);
   std::memcpy(g.h_dbl, tgt.data(), sizeof(double) * B);
   HIPCHK(hipMemcpyAsync(g.abs_target, g.h_dbl, sizeof(double) * B, hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -539,7 +569,7 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   for (;;) {
     st = set_mask(g, g.mask, lin, s);
     if (!st.ok()) return st;
-    apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, g.mask, s);
+    apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, refl, g.mask, s);
     vec_axpby<double2, double2, double2>(g.r, g.b, g.r, 1.0, -1.0, n3, n3, g.mask, B, s);
     vec_norm2<double2>(g.r, n3, n3, g.dpart, g.n2, g.mask, B, s);
     st = read_norms(g, g.n2, rn2, s);
@@ -562,7 +592,7 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
     krylov_start(g.st, g.n2, g.abs_target, eta, g.m, g.mask, g.run, B, s);
     for (int b = 0; b < B; ++b) if (lin[b]) stats[b].cycles += 1;
     for (int step = 0; step < g.m; ++step) {
-      arnoldi_step<T>(g, transpose, s);
+      arnoldi_step<T>(g, transpose, refl, s);
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(g.h_run, g.run, sizeof(int) * B, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -604,6 +634,11 @@ static Status solve_group_t(Group& g, const Opts& o, std::vector<SolveStats>& st
   st = reflect(g, g.eup, g.mask2, nullptr, s);
   if (!st.ok()) return st;
   std::vector<double> ebg2, change;
+  // Inexact outer iteration: the first solves only need to resolve the current
+  // change of the reflected spectrum; the last ones run at INNER_FACTOR * rtol so
+  // that solver noise stays below the outer tolerance.
+  const double final_tol = INNER_FACTOR * o.rtol;
+  std::vector<double> tol(B, std::max(final_tol, FIRST_INNER_TOL));
   for (int outer = 1; outer <= o.max_outer; ++outer) {
     st = set_mask(g, g.mask2, act, s);
     if (!st.ok()) return st;
@@ -613,8 +648,8 @@ static Status solve_group_t(Group& g, const Opts& o, std::vector<SolveStats>& st
       st = read_norms(g, g.n2, ebg2, s);
       if (!st.ok()) return st;
     }
-    apply_op<double2>(g, g.deps64, vr(g.e, n3), vr(g.b, n3), g.ws64, 1, 0, g.mask2, s);
-    st = linear_solve<T>(g, o, act, stats, 0, s);
+    apply_op<double2>(g, g.deps64, vr(g.e, n3), vr(g.b, n3), g.ws64, 1, 0, 0, g.mask2, s);
+    st = linear_solve<T>(g, o, act, tol, stats, 0, 0, s);
     if (!st.ok()) return st;
     st = set_mask(g, g.mask2, act, s);
     if (!st.ok()) return st;
@@ -626,7 +661,8 @@ static Status solve_group_t(Group& g, const Opts& o, std::vector<SolveStats>& st
       if (!act[b]) continue;
       stats[b].outer = outer;
       stats[b].change = change[b];
-      if (stats[b].status < 0 || change[b] <= o.outer_rtol) { act[b] = 0; continue; }
+      if (stats[b].status < 0 || (change[b] <= o.outer_rtol && tol[b] <= final_tol)) { act[b] = 0; continue; }
+      tol[b] = std::max(final_tol, std::min(tol[b], OUTER_TO_INNER * change[b]));
       any = true;
     }
     if (!any) break;
@@ -645,7 +681,7 @@ static Status solve_group_t(Group& g, const Opts& o, std::vector<SolveStats>& st
   st = reflect(g, g.eup2, g.mask2, nullptr, s);
   if (!st.ok()) return st;
   inject(g, g.eup2, g.r, g.mask2, s);
-  apply_op<double2>(g, g.deps64, vr(g.u, n3), vr(g.b, n3), g.ws64, 0, 0, g.mask2, s);  // b = u - K V u
+  apply_op<double2>(g, g.deps64, vr(g.u, n3), vr(g.b, n3), g.ws64, 0, 0, 0, g.mask2, s);  // b = u - K V u
   vec_axpby<double2, double2, double2>(g.b, g.b, g.r, 1.0, -1.0, n3, n3, nullptr, B, s);
   vec_norm2<double2>(g.b, n3, n3, g.dpart, g.n2, nullptr, B, s);
   std::vector<double> m2;
@@ -658,7 +694,51 @@ static Status solve_group_t(Group& g, const Opts& o, std::vector<SolveStats>& st
   return Status();
 }
 
+// Monolithic coupling: GMRES directly on (I - (K + R_vol T_R K_top) V) u = e_bg for
+// the total field u in the slab, e_bg = E_inc + R_vol T_R E_inc. Its solution is
+// the fixed point of the outer loop above; E_mask = u - E_inc - E_layer(u).
+template <class T>
+static Status solve_group_mono_t(Group& g, const Opts& o, std::vector<SolveStats>& stats, hipStream_t s) {
+  const int B = g.B;
+  const Shape& sh = g.sh;
+  const long long n3 = sh.n3, nq = sh.nxny * 3;
+  stats.assign(B, SolveStats());
+  if (g.prec == PSFD_MIXED)
+    vec_axpby<float2, double2, double2>(g.deps32, g.deps64, nullptr, 1.0, 0.0, sh.N, sh.N, nullptr, B, s);
+  HIPCHK(hipMemsetAsync(g.adn, 0, sizeof(double2) * nq * B, s));
+  HIPCHK(hipMemsetAsync(g.eup, 0, sizeof(double2) * nq * B, s));
+  HIPCHK(hipMemsetAsync(g.st, 0, sizeof(GState) * B, s));
+  std::vector<int> all(B, 1);
+  Status st = set_mask(g, g.mask2, all, s);
+  if (!st.ok()) return st;
+  st = reflect(g, g.eup, g.mask2, nullptr, s);  // E_up of the incident wave alone
+  if (!st.ok()) return st;
+  inject(g, g.eup, g.b, g.mask2, s);             // b = e_bg
+  HIPCHK(hipMemcpyAsync(g.x, g.b, sizeof(double2) * n3 * B, hipMemcpyDeviceToDevice, s));  // u0 = e_bg
+  std::vector<double> tol(B, o.rtol);
+  st = linear_solve<T>(g, o, all, tol, stats, 0, 1, s);
+  if (!st.ok()) return st;
+  // E_up = T_R (E_inc + K_top V u), E_layer, E_mask = u - e, orders
+  apply_stage<double2>(g, 0, g.deps64, vr(g.x, n3), vr(g.x, n3), g.ws64, 0, 0, 0, g.mask2, s);
+  launch_readout(sh.nx, sh.ny, sh.nz, vr(g.ws64, n3), g.tab, g.tab_stride, g.adn, g.aup, nq, g.mask2, B, s);
+  st = reflect(g, g.eup, g.mask2, nullptr, s);
+  if (!st.ok()) return st;
+  inject(g, g.eup, g.e, g.mask2, s);
+  launch_orders(sh.nx, sh.ny, g.tab, g.tab_stride, g.eup, g.aup, g.ord, nq, B, s);
+  vec_axpby<double2, double2, double2>(g.x, g.x, g.e, 1.0, -1.0, n3, n3, nullptr, B, s);
+  for (int b = 0; b < B; ++b) {
+    stats[b].outer = 1;
+    stats[b].mono = stats[b].rel_res;
+  }
+  HIPCHK(hipGetLastError());
+  return Status();
+}
+
 Status solve_group(Group& g, const Opts& o, std::vector<SolveStats>& stats, hipStream_t s) {
+  if (o.coupling == PSFD_COUPLING_MONO) {
+    if (g.prec == PSFD_MIXED) return solve_group_mono_t<float2>(g, o, stats, s);
+    return solve_group_mono_t<double2>(g, o, stats, s);
+  }
   if (g.prec == PSFD_MIXED) return solve_group_t<float2>(g, o, stats, s);
   return solve_group_t<double2>(g, o, stats, s);
 }

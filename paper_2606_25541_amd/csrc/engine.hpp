@@ -30,6 +30,7 @@ struct Problem {
 struct Opts {
   double rtol = 1e-6, outer_rtol = 1e-6, inner_eta = 1e-4;
   int restart = 30, max_iters = 5000, max_outer = 100, precision = PSFD_MIXED;
+  int coupling = PSFD_COUPLING_MONO;
 };
 
 Status validate_problem(const psfd_problem* p, Problem& out);
@@ -99,9 +100,14 @@ Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec);
 Status group_set_tables(Group& g, int b, const std::vector<double>& tab, hipStream_t s);
 
 // y = x - K(V x) (kmode 0) or y = K(V x) (kmode 1); transpose uses the kernel at -k.
+// refl adds the layered-stack response R_vol T_R K_top to K (monolithic operator M).
 template <class T>
-void apply_op(Group& g, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose,
+void apply_op(Group& g, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose, int refl,
               const int* active, hipStream_t s);
+// one of the three launches of apply_op: 0 transverse forward, 1 z-pencil, 2 transverse inverse
+template <class T>
+void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose,
+                 int refl, const int* active, hipStream_t s);
 
 struct SolveStats {
   int iters = 0, outer = 0, cycles = 0, status = PSFD_OK;

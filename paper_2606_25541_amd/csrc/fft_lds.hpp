@@ -98,7 +98,7 @@ template <class T, int R, bool INV> PSFD_D void dft_r(T* u) {
 }
 
 template <class T, int R, bool INV>
-__device__ void stockham_pass(T* lds, int log2n, int log2p, int nseq, int sstride, int estride,
+__device__ __forceinline__ void stockham_pass(T* lds, int log2n, int log2p, int nseq, int sstride, int estride,
                               const T* __restrict__ tw, int tid, int nthr) {
   constexpr int NB = 16 / R;
   constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
@@ -144,7 +144,7 @@ __device__ void stockham_pass(T* lds, int log2n, int log2p, int nseq, int sstrid
 // Full FFT of nseq sequences of length 2^log2n staged in LDS (unnormalised;
 // INV uses the +i sign). All threads of the workgroup must call it.
 template <class T, bool INV>
-__device__ void lds_fft(T* lds, int log2n, int nseq, int sstride, int estride,
+__device__ __forceinline__ void lds_fft(T* lds, int log2n, int nseq, int sstride, int estride,
                         const T* __restrict__ tw_all, int tid, int nthr) {
   const T* tw = tw_all + (1 << log2n);
   int log2p = 0;

@@ -168,12 +168,71 @@ __global__ void __launch_bounds__(1024) k_pencil(PencilArgs a) {
     if (z < nz) v = w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl];
     lds[(c * bx + kxl) * a.pitch + z] = v;
   }
+  const int lnz = ilog2i(nz);
+  const double* tab = a.tab + (long long)b * a.tab_stride;
+  TabLayout L{nx, ny};
+  // Layered-stack response of this block's orders (monolithic coupling):
+  // E_up,q = T_R (i dz / 2 beta) P- sum_k exp(i beta z_k) f_q(z_k) / (Nx Ny), added
+  // back as E_up,q exp(i beta z_k) on every plane. The transposed operator uses the
+  // negated order and the transposed 3x3 block.
+  T* ph = lds + 3 * bx * a.pitch;                                            // [bx][nz]
+  double2* eup = reinterpret_cast<double2*>(lds + ((3 * bx * a.pitch + bx * nz + 1) & ~1));  // [bx][3]
+  if (a.reflect) {
+    const double2* tb = reinterpret_cast<const double2*>(tab + L.off_beta());
+    const double dz = tab[TS_DZ];
+    for (int i = tid; i < bx * nz; i += nthr) {
+      const int kxl = i >> lnz, z = i & (nz - 1);
+      int mq = kx0 + kxl, nq = ky;
+      if (a.transpose) { mq = (nx - mq) & (nx - 1); nq = (ny - nq) & (ny - 1); }
+      const double2 bq = tb[nq * nx + mq];
+      const double zk = (z + 0.5) * dz;
+      ph[i] = from_d<T>(cexp_i(make_double2(bq.x * zk, bq.y * zk)));
+    }
+    __syncthreads();
+    if (tid < 3 * bx) {
+      const int c = tid / bx, kxl = tid - c * bx;
+      double2 acc = make_double2(0, 0);
+      for (int z = 0; z < nz; ++z)
+        acc = cadd(acc, cmul(to_d(ph[kxl * nz + z]), to_d(lds[(c * bx + kxl) * a.pitch + z])));
+      eup[kxl * 3 + c] = acc;
+    }
+    __syncthreads();
+    if (tid < bx) {
+      const int kxl = tid;
+      int mq = kx0 + kxl, nq = ky;
+      if (a.transpose) { mq = (nx - mq) & (nx - 1); nq = (ny - nq) & (ny - 1); }
+      const int q = nq * nx + mq;
+      double2 o[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+      if (tab[L.off_keep() + q] != 0.0) {
+        const double2 bq = tb[q];
+        const double kbg = tab[TS_KBG];
+        const double2 fac = cscale(cdiv(make_double2(0.0, dz), make_double2(2.0 * bq.x, 2.0 * bq.y)), tab[TS_INVNXNY]);
+        const double2 km[3] = {make_double2(tab[L.off_kx() + mq], 0), make_double2(tab[L.off_ky() + nq], 0),
+                               make_double2(-bq.x, -bq.y)};
+        const double2* tr = reinterpret_cast<const double2*>(tab + L.off_tr()) + 9LL * q;
+        double2 v[3] = {eup[kxl * 3], eup[kxl * 3 + 1], eup[kxl * 3 + 2]};
+        double2 t[3];
+        if (!a.transpose) {
+          // P- v then T_R
+          double2 d = cadd(cadd(cmul(km[0], v[0]), cmul(km[1], v[1])), cmul(km[2], v[2]));
+          for (int c = 0; c < 3; ++c) t[c] = cmul(fac, csub(v[c], cscale(cmul(km[c], d), 1.0 / (kbg * kbg))));
+          for (int r = 0; r < 3; ++r)
+            o[r] = cadd(cadd(cmul(tr[3 * r], t[0]), cmul(tr[3 * r + 1], t[1])), cmul(tr[3 * r + 2], t[2]));
+        } else {
+          // T_R^T v then P-
+          for (int r = 0; r < 3; ++r)
+            t[r] = cadd(cadd(cmul(tr[r], v[0]), cmul(tr[3 + r], v[1])), cmul(tr[6 + r], v[2]));
+          double2 d = cadd(cadd(cmul(km[0], t[0]), cmul(km[1], t[1])), cmul(km[2], t[2]));
+          for (int c = 0; c < 3; ++c) o[c] = cmul(fac, csub(t[c], cscale(cmul(km[c], d), 1.0 / (kbg * kbg))));
+        }
+      }
+      for (int c = 0; c < 3; ++c) eup[kxl * 3 + c] = o[c];  // own entries only: no cross-thread hazard
+    }
+  }
   __syncthreads();
   const T* tw = reinterpret_cast<const T*>(a.tw);
   lds_fft<T, false>(lds, a.log2pz, 3 * bx, a.pitch, 1, tw, tid, nthr);
 
-  const double* tab = a.tab + (long long)b * a.tab_stride;
-  TabLayout L{nx, ny};
   const double kbg = tab[TS_KBG], Lw = tab[TS_L], kap_u = tab[TS_KAPPA], scale = tab[TS_SCALE];
   const double ik2 = 1.0 / (kbg * kbg);
   const double* tkx = tab + L.off_kx();
@@ -226,13 +285,14 @@ __global__ void __launch_bounds__(1024) k_pencil(PencilArgs a) {
   __syncthreads();
   lds_fft<T, true>(lds, a.log2pz, 3 * bx, a.pitch, 1, tw, tid, nthr);
   const int nst = 3 * nz * bx;
-  const int lnz = ilog2i(nz);
   for (int i = tid; i < nst; i += nthr) {
     int kxl = i & (bx - 1);
     int rest = i >> lbx;
     int z = rest & (nz - 1);
     int c = rest >> lnz;
-    w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl] = lds[(c * bx + kxl) * a.pitch + z];
+    T v = lds[(c * bx + kxl) * a.pitch + z];
+    if (a.reflect) v = cadd(v, from_d<T>(cmul(eup[kxl * 3 + c], to_d(ph[kxl * nz + z]))));
+    w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl] = v;
   }
 }
 

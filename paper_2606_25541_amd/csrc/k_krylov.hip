@@ -35,43 +35,88 @@ PSFD_D void block_sum(double2 (&acc)[NV], int cnt, double2* sm /*[KB/64][NV]*/) 
   __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
+// block-wide sums in the vector precision (wave shuffles), combined across the
+// waves of the block in FP64; totals land in sm[0..cnt)
+template <class T> PSFD_D T wave_sum_c(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
+template <class T, int NV>
+PSFD_D void block_sum_c(T (&acc)[NV], int cnt, double2* sm /*[KB/64][NV]*/) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    if (i < cnt) {
+      T r = wave_sum_c(acc[i]);
+      if (lane == 0) sm[wave * NV + i] = to_d(r);
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < cnt) {
+    double2 t = sm[threadIdx.x];
+    for (int wv = 1; wv < KB / 64; ++wv) t = cadd(t, sm[wv * NV + threadIdx.x]);
+    sm[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// sum over the partial blocks of one value, fixed order (deterministic)
+PSFD_D double2 sum_partials(const double2* p, long long stride, int nblk, double2* sm) {
+  double2 t = make_double2(0, 0);
+  for (int k = threadIdx.x; k < nblk; k += KB) t = cadd(t, p[(long long)k * stride]);
+  double2 acc[1] = {t};
+  block_sum<1>(acc, 1, sm);
+  return sm[0];
+}
+
+constexpr int PSTR = MAXM + 2;  // partial stride: up to MAXM dots + ||w||^2
+
 template <class T>
 __global__ void __launch_bounds__(KB) k_dots(const T* V, long long ldv, long long bsv, long long n, GState* st,
-                                             const int* run, double2* part) {
+                                             const int* run, int first, double2* part) {
   __shared__ double2 sm[(KB / 64) * (MAXM + 1)];
   const int b = blockIdx.y;
-  if (!run[b]) return;
+  if (!run[b] || (!first && !st[b].reorth)) return;
   const int cnt = st[b].j + 1;
   const T* Vb = V + (long long)b * bsv;
   const T* wb = Vb + (long long)cnt * ldv;
-  double2 acc[MAXM + 1];
+  T acc[MAXM + 1];
 #pragma unroll
-  for (int i = 0; i < MAXM + 1; ++i) acc[i] = make_double2(0, 0);
+  for (int i = 0; i < MAXM + 1; ++i) acc[i] = cmake<T>(0, 0);
   for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
-    double2 wv = to_d(wb[e]);
+    const T wv = wb[e];
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (i < cnt) {
-        double2 v = to_d(Vb[(long long)i * ldv + e]);
+        const T v = Vb[(long long)i * ldv + e];
         acc[i].x += v.x * wv.x + v.y * wv.y;
         acc[i].y += v.x * wv.y - v.y * wv.x;
       }
     }
+    // ||w||^2 in the slot after the last dot
+#pragma unroll
+    for (int i = 1; i < MAXM + 1; ++i)
+      if (i == cnt) acc[i].x += wv.x * wv.x + wv.y * wv.y;
   }
-  block_sum<MAXM + 1>(acc, cnt, sm);
-  if ((int)threadIdx.x < cnt) part[((long long)b * gridDim.x + blockIdx.x) * (MAXM + 1) + threadIdx.x] = sm[threadIdx.x];
+  block_sum_c<T, MAXM + 1>(acc, cnt + 1, sm);
+  if ((int)threadIdx.x <= cnt) part[((long long)b * gridDim.x + blockIdx.x) * PSTR + threadIdx.x] = sm[threadIdx.x];
 }
 
-__global__ void k_dots_final(GState* st, const int* run, const double2* part, int nblk, int first) {
-  const int b = blockIdx.x;
-  if (!run[b]) return;
+__global__ void __launch_bounds__(KB) k_dots_final(GState* st, const int* run, const double2* part, int nblk,
+                                                   int first) {
+  __shared__ double2 sm[KB / 64];
+  const int i = blockIdx.x, b = blockIdx.y;
+  if (!run[b] || (!first && !st[b].reorth)) return;
   const int cnt = st[b].j + 1;
-  const int i = threadIdx.x;
-  if (i >= cnt) return;
-  double2 t = make_double2(0, 0);
-  const double2* p = part + (long long)b * nblk * (MAXM + 1) + i;
-  for (int k = 0; k < nblk; ++k) t = cadd(t, p[(long long)k * (MAXM + 1)]);
+  if (i > cnt) return;
+  const double2 t = sum_partials(part + (long long)b * nblk * PSTR + i, PSTR, nblk, sm);
+  if (threadIdx.x != 0) return;
+  if (i == cnt) { st[b].wn2_in = t.x; return; }
   st[b].hc[i] = t;
   st[b].h[i] = first ? t : cadd(st[b].h[i], t);
 }
@@ -79,61 +124,71 @@ __global__ void k_dots_final(GState* st, const int* run, const double2* part, in
 template <class T>
 void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
                  double2* part, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL((k_dots<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, run, part);
-  hipLaunchKernelGGL(k_dots_final, dim3(nbatch), dim3(64), 0, s, st, run, (const double2*)part, RED_BLOCKS, first);
+  hipLaunchKernelGGL((k_dots<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, run, first, part);
+  hipLaunchKernelGGL(k_dots_final, dim3(MAXM + 1, nbatch), dim3(KB), 0, s, st, run, (const double2*)part,
+                     RED_BLOCKS, first);
 }
 
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bsv, long long n, GState* st,
-                                               const int* run, double2* part) {
+                                               const int* run, int first, double2* part) {
   __shared__ double2 sm[(KB / 64) * 1];
-  __shared__ double2 hs[MAXM + 1];
+  __shared__ T hs[MAXM + 1];
+  typedef typename real_of<T>::type R;
   const int b = blockIdx.y;
-  if (!run[b]) return;
+  if (!run[b] || (!first && !st[b].reorth)) return;
   const int cnt = st[b].j + 1;
-  if ((int)threadIdx.x < cnt) hs[threadIdx.x] = st[b].hc[threadIdx.x];
+  if ((int)threadIdx.x < cnt) hs[threadIdx.x] = from_d<T>(st[b].hc[threadIdx.x]);
   __syncthreads();
   T* Vb = V + (long long)b * bsv;
   T* wb = Vb + (long long)cnt * ldv;
-  double2 nn[1] = {make_double2(0, 0)};
+  T nn[1] = {cmake<T>(0, 0)};
   for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
-    double2 s = make_double2(0, 0);
+    T acc = cmake<T>(0, 0);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (i < cnt) {
-        double2 v = to_d(Vb[(long long)i * ldv + e]);
-        double2 h = hs[i];
-        s.x += h.x * v.x - h.y * v.y;
-        s.y += h.x * v.y + h.y * v.x;
+        const T v = Vb[(long long)i * ldv + e];
+        const T h = hs[i];
+        acc.x += h.x * v.x - h.y * v.y;
+        acc.y += h.x * v.y + h.y * v.x;
       }
     }
-    double2 wv = to_d(wb[e]);
-    wv.x -= s.x;
-    wv.y -= s.y;
-    T o = from_d<T>(wv);
-    wb[e] = o;
-    double2 od = to_d(o);
-    nn[0].x += od.x * od.x + od.y * od.y;
+    T wv = wb[e];
+    wv.x -= acc.x;
+    wv.y -= acc.y;
+    wb[e] = wv;
+    nn[0].x += wv.x * wv.x + wv.y * wv.y;
   }
-  block_sum<1>(nn, 1, sm);
+  (void)sizeof(R);
+  block_sum_c<T, 1>(nn, 1, sm);
   if (threadIdx.x == 0) part[((long long)b * gridDim.x + blockIdx.x)] = sm[0];
 }
 
-__global__ void k_update_final(GState* st, const int* run, const double2* part, int nblk) {
+__global__ void __launch_bounds__(KB) k_update_final(GState* st, const int* run, const double2* part, int nblk,
+                                                     int first) {
+  __shared__ double2 sm[KB / 64];
   const int b = blockIdx.x;
-  if (!run[b] || threadIdx.x != 0) return;
-  double t = 0;
-  const double2* p = part + (long long)b * nblk;
-  for (int k = 0; k < nblk; ++k) t += p[k].x;
-  st[b].wn2 = t;
+  if (!run[b] || (!first && !st[b].reorth)) return;
+  const double2 t = sum_partials(part + (long long)b * nblk, 1, nblk, sm);
+  if (threadIdx.x != 0) return;
+  GState& S = st[b];
+  S.wn2 = t.x;
+  if (first) {
+    // second pass when the projection removed more than half of ||w||^2
+    S.reorth = (t.x < 0.5 * S.wn2_in) ? 1 : 0;
+    S.nreorth += S.reorth;
+  } else {
+    S.reorth = 0;
+  }
 }
 
 template <class T>
-void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, double2* part,
-                   int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL((k_update<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, run, part);
-  hipLaunchKernelGGL(k_update_final, dim3(nbatch), dim3(64), 0, s, st, run, (const double2*)part, RED_BLOCKS);
+void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
+                   double2* part, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL((k_update<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, run, first, part);
+  hipLaunchKernelGGL(k_update_final, dim3(nbatch), dim3(KB), 0, s, st, run, (const double2*)part, RED_BLOCKS, first);
 }
 
 // ---------------------------------------------------------------------------
@@ -409,7 +464,7 @@ void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long
 #define INST_T(T)                                                                                       \
   template void krylov_dots<T>(const T*, long long, long long, long long, GState*, const int*, int,      \
                                double2*, int, hipStream_t);                                             \
-  template void krylov_update<T>(T*, long long, long long, long long, GState*, const int*, double2*,     \
+  template void krylov_update<T>(T*, long long, long long, long long, GState*, const int*, int, double2*,\
                                  int, hipStream_t);                                                     \
   template void krylov_scale_next<T>(T*, long long, long long, long long, GState*, const int*, int,      \
                                      hipStream_t);                                                      \

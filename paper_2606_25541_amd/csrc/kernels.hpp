@@ -34,6 +34,7 @@ struct PencilArgs {
   long long tab_stride;
   const void* tw;
   int transpose;         // use the kernel at the negated wavevector (bilinear transpose)
+  int reflect;           // add the layered-stack response R_vol T_R K_top (monolithic coupling)
   const int* active;
 };
 

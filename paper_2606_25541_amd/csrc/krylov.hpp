@@ -11,7 +11,7 @@
 namespace psfd {
 
 constexpr int MAXM = 32;          // largest supported restart length
-constexpr int RED_BLOCKS = 256;   // blocks per instance of the first reduction stage
+constexpr int RED_BLOCKS = 512;   // blocks per instance of the first reduction stage
 
 // Device-resident state of one GMRES(m) instance. All scalars are FP64.
 struct GState {
@@ -21,13 +21,15 @@ struct GState {
   int conv;         // residual estimate at or below target
   int iters;        // Arnoldi steps taken (all cycles)
   int ncols;        // Hessenberg columns completed in the current cycle
-  int pad[2];
+  int reorth;       // the second Gram-Schmidt pass is needed for the current column
+  int nreorth;      // second passes taken (all cycles)
   double target;    // stopping threshold of the residual estimate
   double res;       // |g_{j+1}|: current residual estimate
   double beta;      // ||r0|| of the current cycle
   double inv_norm;  // 1 / h_{j+1,j}
   double wn2;       // ||w||^2 after the last orthogonalisation pass
-  double pad2[3];
+  double wn2_in;    // ||w||^2 before the pass
+  double pad2[2];
   double2 H[MAXM + 1][MAXM];  // rotated Hessenberg matrix (upper triangle used)
   double cs[MAXM];
   double2 sn[MAXM];
@@ -37,14 +39,17 @@ struct GState {
   double2 hc[MAXM + 1];       // coefficients of the current pass
 };
 
-// w = v_{j+1} (the new apply output): hc[i] = <v_i, w> for i = 0..j (h += hc, or h = hc when first)
+// Classical Gram-Schmidt pass on w = v_{j+1} (the new apply output):
+// hc[i] = <v_i, w> for i = 0..j and wn2_in = ||w||^2 (h = hc on the first
+// pass, h += hc on the second). The second pass (first == 0) runs only when the
+// first left ||w|| below ||w_in|| / sqrt(2) ("twice is enough").
 template <class T>
 void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
                  double2* part, int nbatch, hipStream_t s);
-// w = v_{j+1}: w -= sum_{i<=j} hc_i v_i ; wn2 = ||w||^2 afterwards
+// w = v_{j+1}: w -= sum_{i<=j} hc_i v_i ; wn2 = ||w||^2 afterwards; decides reorth
 template <class T>
-void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, double2* part,
-                   int nbatch, hipStream_t s);
+void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
+                   double2* part, int nbatch, hipStream_t s);
 // Givens rotation of the new Hessenberg column, residual estimate, inv_norm, stop/run flags
 void krylov_givens(GState* st, int* run, int nbatch, hipStream_t s);
 // v_{j+1} *= inv_norm (in place), then j <- j + 1 unless the cycle stopped

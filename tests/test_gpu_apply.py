@@ -56,6 +56,32 @@ def test_apply_matches_oracle(shape, dtype):
         assert np.max(np.abs(y - ref)) < 1e-11 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("shape", [(8, 8, 4), (16, 8, 8), (32, 32, 16), (128, 128, 4), (64, 256, 2)])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_coupled_apply_matches_oracle(shape, dtype):
+    """y = u - M V u with M = K + R_vol T_R K_top (and its bilinear transpose)."""
+    from paper_2606_25541_amd import api
+    dev = device()
+    nx, ny, nz = shape
+    say("coupled apply", shape, dtype)
+    p = make(nx, ny, nz, phi=10.0, pol=1)
+    de = clips.manhattan(nx, ny, nz, p.lx_nm, p.ly_nm, seed=3 * nx + nz)
+    u = clips.random_complex((3, nz, ny, nx), seed=23)
+    S = O.Setup(p)
+    Vu = O.potential(S, de)[None] * u
+    ref = u - O.apply_M(S, Vu)
+    reft = u - O.apply_M_T(S, Vu)
+    td = torch.complex128 if dtype == "c128" else torch.complex64
+    tol = 1e-12 if dtype == "c128" else 3e-6
+    plan = api.Plan(p)
+    dd = torch.from_numpy(de).to(dev, td)
+    uu = torch.from_numpy(u).to(dev, td)
+    y = plan.psfd_apply(dd, uu, reflect=True).cpu().numpy()
+    yt = plan.psfd_apply(dd, uu, reflect=True, transpose=True).cpu().numpy()
+    assert rel(y, ref) < tol, rel(y, ref)
+    assert rel(yt, reft) < tol, rel(yt, reft)
+
+
 def test_apply_is_deterministic():
     from paper_2606_25541_amd import api
     dev = device()
