@@ -55,6 +55,19 @@ __global__ void __launch_bounds__(1024) k_tile(TileArgs a) {
       v = cscale(cmul(vol[o], in[o]), k0sq);
     } else if (LD == LD_VXE) {
       v = cscale(cmul(vol[o], cadd(in[o], aux[o])), k0sq);
+    } else if (LD == LD_INJECT_T) {
+      // transposed plane-wave readouts: position o carries order q = -o with
+      // b_dn,q exp(i beta_q z) + b_up,q exp(i beta_q (T - z))
+      TabLayout L{a.nx, a.ny};
+      const int io = (int)(o % a.nx), jo = (int)(o / a.nx);
+      const long long q = (long long)((a.ny - jo) & (a.ny - 1)) * a.nx + ((a.nx - io) & (a.nx - 1));
+      const double zk = (z + 0.5) * tab[TS_DZ], Tt = tab[TS_T];
+      const double2 bq = reinterpret_cast<const double2*>(tab + L.off_beta())[q];
+      const double2* bdn = a.eup + (long long)b * a.eup_stride;
+      const double2* bup = a.eup2 + (long long)b * a.eup_stride;
+      double2 val = cadd(cmul(bdn[q * 3 + c], cexp_i(make_double2(bq.x * zk, bq.y * zk))),
+                         cmul(bup[q * 3 + c], cexp_i(make_double2(bq.x * (Tt - zk), bq.y * (Tt - zk)))));
+      v = from_d<T>(val);
     } else {
       // spectrum of the layered field on plane z: E_up,q exp(i beta_q z)
       // plus the incident wave in its order, E_inc exp(-i beta_inc z)
@@ -121,6 +134,7 @@ template void launch_tile<double2, true, LD_PLAIN, ST_PLAIN>(const TileArgs&, in
 template void launch_tile<double2, true, LD_PLAIN, ST_AXPBY>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<double2, false, LD_VXE, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<double2, true, LD_INJECT, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
+template void launch_tile<double2, true, LD_INJECT_T, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
 
 // -------------------------------------------------------------------------
 // z-pencil kernel: pad, FFT_z, dyadic kernel, IFFT_z, restrict
@@ -402,6 +416,68 @@ void launch_reflect(int nx, int ny, const double* tab, long long tab_stride, con
                     hipStream_t s) {
   dim3 grid(nblk, nbatch);
   hipLaunchKernelGGL(k_reflect, grid, dim3(256), 0, s, nx, ny, tab, tab_stride, adn, eup, ostride, part, active);
+}
+
+__global__ void k_adjoint_source(int nx, int ny, const double* tab_all, long long tab_stride, const double2* c_all,
+                                 double2* bdn_all, double2* bup_all, long long ostride) {
+  const int b = blockIdx.y;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nx * ny) return;
+  const double* tab = tab_all + (long long)b * tab_stride;
+  TabLayout L{nx, ny};
+  const long long o = (long long)b * ostride + 3LL * q;
+  double2* bdn = bdn_all + o;
+  double2* bup = bup_all + o;
+  if (tab[L.off_keep() + q] == 0.0) {
+    for (int i = 0; i < 3; ++i) { bdn[i] = make_double2(0, 0); bup[i] = make_double2(0, 0); }
+    return;
+  }
+  const double2 beta = reinterpret_cast<const double2*>(tab + L.off_beta())[q];
+  const double T = tab[TS_T], dz = tab[TS_DZ], kbg = tab[TS_KBG];
+  const double2 fac = cscale(cdiv(make_double2(0.0, dz), make_double2(2.0 * beta.x, 2.0 * beta.y)), tab[TS_INVNXNY]);
+  const double2 ph = cexp_i(make_double2(beta.x * T, beta.y * T));
+  const double2* tr = reinterpret_cast<const double2*>(tab + L.off_tr()) + 9LL * q;
+  const double2* c = c_all + o;
+  double2 v[3], t[3];
+  for (int i = 0; i < 3; ++i) v[i] = cmul(ph, c[i]);
+  for (int r = 0; r < 3; ++r) t[r] = cadd(cadd(cmul(tr[r], v[0]), cmul(tr[3 + r], v[1])), cmul(tr[6 + r], v[2]));
+  const double ik2 = 1.0 / (kbg * kbg);
+  const double kx = tab[L.off_kx() + (q % nx)], ky = tab[L.off_ky() + (q / nx)];
+  for (int dir = 0; dir < 2; ++dir) {
+    const double2* in = dir == 0 ? t : c;
+    double2 kz = dir == 0 ? make_double2(-beta.x, -beta.y) : beta;
+    double2 kv[3] = {make_double2(kx, 0), make_double2(ky, 0), kz};
+    double2 d = cadd(cadd(cmul(kv[0], in[0]), cmul(kv[1], in[1])), cmul(kv[2], in[2]));
+    double2* dst = dir == 0 ? bdn : bup;
+    for (int i = 0; i < 3; ++i) dst[i] = cmul(fac, csub(in[i], cscale(cmul(kv[i], d), ik2)));
+  }
+}
+
+void launch_adjoint_source(int nx, int ny, const double* tab, long long tab_stride, const double2* c,
+                           double2* bdn, double2* bup, long long ostride, int nbatch, hipStream_t s) {
+  dim3 grid((nx * ny + 255) / 256, nbatch);
+  hipLaunchKernelGGL(k_adjoint_source, grid, dim3(256), 0, s, nx, ny, tab, tab_stride, c, bdn, bup, ostride);
+}
+
+__global__ void k_gradient(long long N, const double* tab_all, long long tab_stride, const double2* lam_all,
+                           const double2* u_all, long long n3stride, double2* grad_all, long long gstride) {
+  const int b = blockIdx.y;
+  const double k0sq = tab_all[(long long)b * tab_stride + TS_K0SQ];
+  const double2* lam = lam_all + (long long)b * n3stride;
+  const double2* u = u_all + (long long)b * n3stride;
+  double2* g = grad_all + (long long)b * gstride;
+  for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (long long)gridDim.x * blockDim.x) {
+    double2 t = make_double2(0, 0);
+    for (int c = 0; c < 3; ++c) t = cadd(t, cmul(lam[c * N + r], u[c * N + r]));
+    g[r] = make_double2(2.0 * k0sq * t.x, -2.0 * k0sq * t.y);
+  }
+}
+
+void launch_gradient(long long N, const double* tab, long long tab_stride, const double2* lam, const double2* u,
+                     long long n3stride, double2* grad, long long gstride, int nbatch, hipStream_t s) {
+  int nb = (int)((N + 255) / 256);
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_gradient, dim3(nb, nbatch), dim3(256), 0, s, N, tab, tab_stride, lam, u, n3stride, grad, gstride);
 }
 
 __global__ void k_orders(int nx, int ny, const double* tab_all, long long tab_stride, const double2* eup_all,

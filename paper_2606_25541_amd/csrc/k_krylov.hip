@@ -76,6 +76,35 @@ PSFD_D double2 sum_partials(const double2* p, long long stride, int nblk, double
 
 constexpr int PSTR = MAXM + 2;  // partial stride: up to MAXM dots + ||w||^2
 
+// element pairs: FP32 complex bases are read two at a time (16-byte loads)
+template <class T> struct Pair { T a, b; };
+template <class T> PSFD_D Pair<T> ld2(const T* p, long long e2) {
+  Pair<T> r;
+  if constexpr (sizeof(T) == 8) {
+    const float4 v = reinterpret_cast<const float4*>(p)[e2];
+    r.a = make_float2(v.x, v.y);
+    r.b = make_float2(v.z, v.w);
+  } else {
+    r.a = p[2 * e2];
+    r.b = p[2 * e2 + 1];
+  }
+  return r;
+}
+template <class T> PSFD_D void st2(T* p, long long e2, Pair<T> v) {
+  if constexpr (sizeof(T) == 8) {
+    reinterpret_cast<float4*>(p)[e2] = make_float4(v.a.x, v.a.y, v.b.x, v.b.y);
+  } else {
+    p[2 * e2] = v.a;
+    p[2 * e2 + 1] = v.b;
+  }
+}
+// acc += conj(v) w
+template <class T> PSFD_D void cfma_conj(T& acc, T v, T w) {
+  acc.x += v.x * w.x + v.y * w.y;
+  acc.y += v.x * w.y - v.y * w.x;
+}
+
+// n must be even (fields are 3 nx ny nz complex with nx >= 4)
 template <class T>
 __global__ void __launch_bounds__(KB) k_dots(const T* V, long long ldv, long long bsv, long long n, GState* st,
                                              const int* run, int first, double2* part) {
@@ -88,20 +117,21 @@ __global__ void __launch_bounds__(KB) k_dots(const T* V, long long ldv, long lon
   T acc[MAXM + 1];
 #pragma unroll
   for (int i = 0; i < MAXM + 1; ++i) acc[i] = cmake<T>(0, 0);
-  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
-    const T wv = wb[e];
+  const long long n2 = n >> 1;
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n2; e += (long long)gridDim.x * KB) {
+    const Pair<T> wv = ld2(wb, e);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (i < cnt) {
-        const T v = Vb[(long long)i * ldv + e];
-        acc[i].x += v.x * wv.x + v.y * wv.y;
-        acc[i].y += v.x * wv.y - v.y * wv.x;
+        const Pair<T> v = ld2(Vb + (long long)i * ldv, e);
+        cfma_conj(acc[i], v.a, wv.a);
+        cfma_conj(acc[i], v.b, wv.b);
       }
     }
     // ||w||^2 in the slot after the last dot
 #pragma unroll
     for (int i = 1; i < MAXM + 1; ++i)
-      if (i == cnt) acc[i].x += wv.x * wv.x + wv.y * wv.y;
+      if (i == cnt) acc[i].x += wv.a.x * wv.a.x + wv.a.y * wv.a.y + wv.b.x * wv.b.x + wv.b.y * wv.b.y;
   }
   block_sum_c<T, MAXM + 1>(acc, cnt + 1, sm);
   if ((int)threadIdx.x <= cnt) part[((long long)b * gridDim.x + blockIdx.x) * PSTR + threadIdx.x] = sm[threadIdx.x];
@@ -135,7 +165,6 @@ __global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bs
                                                const int* run, int first, double2* part) {
   __shared__ double2 sm[(KB / 64) * 1];
   __shared__ T hs[MAXM + 1];
-  typedef typename real_of<T>::type R;
   const int b = blockIdx.y;
   if (!run[b] || (!first && !st[b].reorth)) return;
   const int cnt = st[b].j + 1;
@@ -144,24 +173,26 @@ __global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bs
   T* Vb = V + (long long)b * bsv;
   T* wb = Vb + (long long)cnt * ldv;
   T nn[1] = {cmake<T>(0, 0)};
-  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
-    T acc = cmake<T>(0, 0);
+  const long long n2 = n >> 1;
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n2; e += (long long)gridDim.x * KB) {
+    T a0 = cmake<T>(0, 0), a1 = cmake<T>(0, 0);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       if (i < cnt) {
-        const T v = Vb[(long long)i * ldv + e];
+        const Pair<T> v = ld2(Vb + (long long)i * ldv, e);
         const T h = hs[i];
-        acc.x += h.x * v.x - h.y * v.y;
-        acc.y += h.x * v.y + h.y * v.x;
+        a0.x += h.x * v.a.x - h.y * v.a.y;
+        a0.y += h.x * v.a.y + h.y * v.a.x;
+        a1.x += h.x * v.b.x - h.y * v.b.y;
+        a1.y += h.x * v.b.y + h.y * v.b.x;
       }
     }
-    T wv = wb[e];
-    wv.x -= acc.x;
-    wv.y -= acc.y;
-    wb[e] = wv;
-    nn[0].x += wv.x * wv.x + wv.y * wv.y;
+    Pair<T> wv = ld2(wb, e);
+    wv.a.x -= a0.x; wv.a.y -= a0.y;
+    wv.b.x -= a1.x; wv.b.y -= a1.y;
+    st2(wb, e, wv);
+    nn[0].x += wv.a.x * wv.a.x + wv.a.y * wv.a.y + wv.b.x * wv.b.x + wv.b.y * wv.b.y;
   }
-  (void)sizeof(R);
   block_sum_c<T, 1>(nn, 1, sm);
   if (threadIdx.x == 0) part[((long long)b * gridDim.x + blockIdx.x)] = sm[0];
 }
@@ -177,7 +208,7 @@ __global__ void __launch_bounds__(KB) k_update_final(GState* st, const int* run,
   S.wn2 = t.x;
   if (first) {
     // second pass when the projection removed more than half of ||w||^2
-    S.reorth = (t.x < 0.5 * S.wn2_in) ? 1 : 0;
+    S.reorth = (t.x < S.reorth_thr * S.wn2_in) ? 1 : 0;
     S.nreorth += S.reorth;
   } else {
     S.reorth = 0;
@@ -197,8 +228,10 @@ __global__ void k_givens(GState* st, int* run) {
   if (threadIdx.x != 0 || !run[b]) return;
   GState& S = st[b];
   const int j = S.j;
+  // Arnoldi runs on B with A = I - B: column j of A's Hessenberg is e_j - h,
+  // and v_{j+1} = -(B v_j - V h) / ||.|| keeps the subdiagonal positive
   double2 col[MAXM + 1];
-  for (int i = 0; i <= j; ++i) col[i] = S.h[i];
+  for (int i = 0; i <= j; ++i) col[i] = make_double2((i == j ? 1.0 : 0.0) - S.h[i].x, -S.h[i].y);
   const double hn = sqrt(S.wn2);
   for (int i = 0; i < j; ++i) {
     double2 a = col[i], c = col[i + 1];
@@ -227,8 +260,9 @@ __global__ void k_givens(GState* st, int* run) {
   S.res = sqrt(cabs2(S.g[j + 1]));
   S.iters += 1;
   S.ncols = j + 1;
-  S.inv_norm = hn > 0.0 ? 1.0 / hn : 0.0;
+  S.inv_norm = hn > 0.0 ? -1.0 / hn : 0.0;
   S.conv = S.res <= S.target;
+  S.jcur = j;
   const bool breakdown = !(hn > 1e-300 * (S.beta > 0 ? S.beta : 1.0));
   S.stop = S.conv || (j + 1 >= S.m) || breakdown || !(S.res == S.res);
   run[b] = S.stop ? 0 : 1;
@@ -238,12 +272,15 @@ void krylov_givens(GState* st, int* run, int nbatch, hipStream_t s) {
   hipLaunchKernelGGL(k_givens, dim3(nbatch), dim3(64), 0, s, st, run);
 }
 
+// v_{j+1} *= inv_norm. The index j is read from jcur (a copy made by the Givens
+// step) so that block 0 can advance st[b].j without racing the other blocks.
 template <class T>
 __global__ void __launch_bounds__(KB) k_scale_next(T* V, long long ldv, long long bsv, long long n, GState* st,
                                                    const int* run) {
   const int b = blockIdx.y;
   if (!run[b]) return;
-  const int j = st[b].j;
+  const int j = st[b].jcur;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st[b].j = j + 1;
   typedef typename real_of<T>::type R;
   const R sc = (R)st[b].inv_norm;
   T* v = V + (long long)b * bsv + (long long)(j + 1) * ldv;
@@ -324,13 +361,14 @@ void krylov_lincomb(const T* V, long long ldv, long long bsv, TX* x, long long b
 }
 
 __global__ void k_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                        const int* mask, int* run) {
+                        double reorth_thr, const int* mask, int* run) {
   const int b = blockIdx.x;
   if (threadIdx.x != 0) return;
   GState& S = st[b];
   const double rn = sqrt(rnorm2[b]);
   S.j = 0;
   S.m = m;
+  S.reorth_thr = reorth_thr;
   S.ncols = 0;
   S.beta = rn;
   S.g[0] = make_double2(rn, 0.0);
@@ -345,8 +383,8 @@ __global__ void k_start(GState* st, const double* rnorm2, const double* abs_targ
 }
 
 void krylov_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                  const int* mask, int* run, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL(k_start, dim3(nbatch), dim3(64), 0, s, st, rnorm2, abs_target, eta, m, mask, run);
+                  double reorth_thr, const int* mask, int* run, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_start, dim3(nbatch), dim3(64), 0, s, st, rnorm2, abs_target, eta, m, reorth_thr, mask, run);
 }
 
 // ---------------------------------------------------------------------------

@@ -4,7 +4,7 @@
 
 namespace psfd {
 
-enum LoadOp { LD_PLAIN = 0, LD_VX = 1, LD_INJECT = 2, LD_VXE = 3 };
+enum LoadOp { LD_PLAIN = 0, LD_VX = 1, LD_INJECT = 2, LD_VXE = 3, LD_INJECT_T = 4 };
 enum StoreOp { ST_PLAIN = 0, ST_AXPBY = 1 };
 
 // One launch of the transverse (x/y) FFT kernel over tiles of every plane of
@@ -19,7 +19,8 @@ struct TileArgs {
   const double* tab;     // per-instance tables (TabLayout), stride tab_stride doubles
   long long tab_stride;
   const double2* eup;    // LD_INJECT: upgoing amplitudes [ny*nx][3] per instance
-  long long eup_stride;
+  long long eup_stride;  //   (LD_INJECT_T: eup = b_dn, eup2 = b_up, see launch_adjoint_source)
+  const double2* eup2;
   const void* tw;        // twiddle table in the working precision
   double alpha, gamma;   // ST_AXPBY: out = alpha * aux + gamma * result
   const int* active;     // optional per-instance flags (0 = skip)
@@ -53,6 +54,13 @@ void launch_readout(int nx, int ny, int nz, VecRef spec, const double* tab, long
 void launch_reflect(int nx, int ny, const double* tab, long long tab_stride, const double2* adn,
                     double2* eup, long long ostride, double* part, int nblk, const int* active, int nbatch,
                     hipStream_t s);
+// Adjoint source per order from c = dJ/da (conj of the selected amplitudes):
+// b_dn = (i dz / 2 beta)(1/NxNy) P- T_R^T (exp(i beta T) c), b_up = (i dz / 2 beta)(1/NxNy) P+ c
+void launch_adjoint_source(int nx, int ny, const double* tab, long long tab_stride, const double2* c,
+                           double2* bdn, double2* bup, long long ostride, int nbatch, hipStream_t s);
+// grad = 2 conj(k0^2 sum_c lam_c u_c) per voxel (complex128 [nz][ny][nx]); out[b] at outs[b]
+void launch_gradient(long long N, const double* tab, long long tab_stride, const double2* lam, const double2* u,
+                     long long n3stride, double2* grad, long long gstride, int nbatch, hipStream_t s);
 // orders = eup exp(i beta T) + aup
 void launch_orders(int nx, int ny, const double* tab, long long tab_stride, const double2* eup,
                    const double2* aup, double2* orders, long long ostride, int nbatch, hipStream_t s);

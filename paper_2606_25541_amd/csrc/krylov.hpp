@@ -11,7 +11,7 @@
 namespace psfd {
 
 constexpr int MAXM = 32;          // largest supported restart length
-constexpr int RED_BLOCKS = 512;   // blocks per instance of the first reduction stage
+constexpr int RED_BLOCKS = 1024;  // blocks per instance of the first reduction stage
 
 // Device-resident state of one GMRES(m) instance. All scalars are FP64.
 struct GState {
@@ -29,7 +29,9 @@ struct GState {
   double inv_norm;  // 1 / h_{j+1,j}
   double wn2;       // ||w||^2 after the last orthogonalisation pass
   double wn2_in;    // ||w||^2 before the pass
-  double pad2[2];
+  double reorth_thr;  // second pass when ||w||^2 after the first < reorth_thr * ||w||^2 before
+  int jcur;         // column index of the step in flight (read by the scale kernel)
+  int pad3;
   double2 H[MAXM + 1][MAXM];  // rotated Hessenberg matrix (upper triangle used)
   double cs[MAXM];
   double2 sn[MAXM];
@@ -39,6 +41,10 @@ struct GState {
   double2 hc[MAXM + 1];       // coefficients of the current pass
 };
 
+// The Arnoldi process runs on B for systems A = I - B (B = K V or M V): the apply
+// writes B v_j into slot j+1, Gram-Schmidt orthogonalises it, and the Givens step
+// forms column j of A's Hessenberg as e_j - h (same Krylov space, no cancellation
+// against the identity part).
 // Classical Gram-Schmidt pass on w = v_{j+1} (the new apply output):
 // hc[i] = <v_i, w> for i = 0..j and wn2_in = ||w||^2 (h = hc on the first
 // pass, h += hc on the second). The second pass (first == 0) runs only when the
@@ -52,7 +58,7 @@ void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, 
                    double2* part, int nbatch, hipStream_t s);
 // Givens rotation of the new Hessenberg column, residual estimate, inv_norm, stop/run flags
 void krylov_givens(GState* st, int* run, int nbatch, hipStream_t s);
-// v_{j+1} *= inv_norm (in place), then j <- j + 1 unless the cycle stopped
+// v_{j+1} *= inv_norm (in place) and j <- j + 1, for instances still running
 template <class T>
 void krylov_scale_next(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int nbatch,
                        hipStream_t s);
@@ -66,7 +72,7 @@ void krylov_lincomb(const T* V, long long ldv, long long bsv, TX* x, long long b
 // start a cycle from rnorm2[b] = ||r_b||^2: g = (||r||, 0, ...), j = 0,
 // target = max(abs_target[b], eta ||r||); run[b] = mask[b] && ||r|| > abs_target[b]
 void krylov_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                  const int* mask, int* run, int nbatch, hipStream_t s);
+                  double reorth_thr, const int* mask, int* run, int nbatch, hipStream_t s);
 
 // ---- batched vector kernels (instance b at offset b * bstride) ---------------
 // out = a x + c y (any mix of precisions; y may be null)
