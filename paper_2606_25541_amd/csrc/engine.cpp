@@ -448,7 +448,7 @@ template void apply_op<double2>(Group&, const double2*, VecRef, VecRef, double2*
                                 hipStream_t);
 
 // e = E_inc + IFFT_xy(E_up exp(i beta z)) per plane (FP64)
-static void inject(Group& g, const double2* eup, double2* out, const int* active, hipStream_t s) {
+void inject(Group& g, const double2* eup, double2* out, const int* active, hipStream_t s) {
   const Shape& sh = g.sh;
   const XYCfg c = xy_config(sh, 16);
   const int np = 3 * sh.nz;
@@ -468,7 +468,7 @@ static void inject(Group& g, const double2* eup, double2* out, const int* active
 }
 
 // spectra of k0^2 delta_eps (x + e) into ws64, then per-order plane-wave readouts
-static void readout(Group& g, const double2* x, const double2* e, const int* active, hipStream_t s) {
+void readout(Group& g, const double2* x, const double2* e, const int* active, hipStream_t s) {
   const Shape& sh = g.sh;
   const XYCfg c = xy_config(sh, 16);
   const int np = 3 * sh.nz;
@@ -489,7 +489,7 @@ static void readout(Group& g, const double2* x, const double2* e, const int* act
 }
 
 // eup <- T_R (adn + e_inc); returns per-instance relative change (host)
-static Status reflect(Group& g, double2* eup, const int* active, std::vector<double>* change, hipStream_t s) {
+Status reflect(Group& g, double2* eup, const int* active, std::vector<double>* change, hipStream_t s) {
   const Shape& sh = g.sh;
   launch_reflect(sh.nx, sh.ny, g.tab, g.tab_stride, g.adn, eup, sh.nxny * 3, g.rpart, g.rblk, active, g.B, s);
   if (!change) return Status();
@@ -504,14 +504,14 @@ static Status reflect(Group& g, double2* eup, const int* active, std::vector<dou
   return Status();
 }
 
-static Status set_mask(Group& g, int* dmask, const std::vector<int>& h, hipStream_t s) {
+Status set_mask(Group& g, int* dmask, const std::vector<int>& h, hipStream_t s) {
   std::memcpy(g.h_run + g.B, h.data(), sizeof(int) * g.B);
   HIPCHK(hipMemcpyAsync(dmask, g.h_run + g.B, sizeof(int) * g.B, hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   return Status();
 }
 
-static Status read_norms(Group& g, const double* d, std::vector<double>& out, hipStream_t s) {
+Status read_norms(Group& g, const double* d, std::vector<double>& out, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(g.h_dbl, d, sizeof(double) * g.B, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   out.assign(g.h_dbl, g.h_dbl + g.B);
@@ -523,7 +523,7 @@ static Status read_norms(Group& g, const double* d, std::vector<double>& out, hi
 // 0.5; with the Arnoldi process on B (A = I - B) the iteration counts of the
 // solver workloads do not change between 0.5 and 0, so only severe
 // cancellation pays for a second pass. PSFD_REORTH overrides it for experiments.
-static double reorth_threshold() {
+double reorth_threshold() {
   static double v = [] {
     const char* e = std::getenv("PSFD_REORTH");
     return e ? std::atof(e) : 0.1;
@@ -533,14 +533,14 @@ static double reorth_threshold() {
 
 // Arnoldi steps issued per host check of the run flags; steps issued after an
 // instance stops are no-ops (every kernel tests run[b]).
-static const int STEPS_PER_SYNC = 4;
+const int STEPS_PER_SYNC = 4;
 
 template <class T> static const T* deps_of(const Group& g);
 template <> const float2* deps_of<float2>(const Group& g) { return g.deps32; }
 template <> const double2* deps_of<double2>(const Group& g) { return g.deps64; }
 
 template <class T>
-static void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s) {
+void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s) {
   T* V = (T*)g.basis;
   const long long n3 = g.sh.n3, bsv = (long long)(g.m + 1) * n3;
   VecRef vin;
@@ -556,6 +556,9 @@ static void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s) {
   krylov_givens(g.st, g.run, g.B, s);
   krylov_scale_next<T>(V, n3, bsv, n3, g.st, g.run, g.B, s);  // also advances j
 }
+
+template void arnoldi_step<float2>(Group&, int, int, hipStream_t);
+template void arnoldi_step<double2>(Group&, int, int, hipStream_t);
 
 // Restarted GMRES on (I - K V) x = b for the instances with act[b] set.
 // Each cycle starts from the FP64 residual r = b - A x; the Arnoldi cycle runs
@@ -605,7 +608,8 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
     if (!any) break;
     st = set_mask(g, g.mask, lin, s);
     if (!st.ok()) return st;
-    vec_scale_invsqrt<T, double2>((T*)g.basis, g.r, g.n2, n3, bsv, g.mask, B, s);
+    vec_scale_invsqrt<T, double2>((T*)g.basis, g.r, g.n2, n3, bsv, n3, g.mask, B, s);
+    HIPCHK(hipMemsetAsync(g.run, 0, sizeof(int) * B, s));
     krylov_start(g.st, g.n2, g.abs_target, eta, g.m, reorth_threshold(), g.mask, g.run, B, s);
     for (int b = 0; b < B; ++b) if (lin[b]) stats[b].cycles += 1;
     for (int step = 0; step < g.m;) {

@@ -122,4 +122,19 @@ Status adjoint_group(Group& g, const Opts& o, const std::vector<std::pair<int, i
 
 Status hip_status(hipError_t e, const char* what);
 
+// ---- building blocks shared with the serving runtime (all masked per instance) ----
+// e = E_inc + IFFT_xy(E_up exp(i beta z)) on every plane (FP64)
+void inject(Group& g, const double2* eup, double2* out, const int* active, hipStream_t s);
+// per-order plane-wave readouts adn / aup of V (x + e) (e may be null only through apply_stage)
+void readout(Group& g, const double2* x, const double2* e, const int* active, hipStream_t s);
+// eup <- T_R (adn + e_inc); relative change per instance when change != null
+Status reflect(Group& g, double2* eup, const int* active, std::vector<double>* change, hipStream_t s);
+Status set_mask(Group& g, int* dmask, const std::vector<int>& h, hipStream_t s);
+Status read_norms(Group& g, const double* d, std::vector<double>& out, hipStream_t s);
+double reorth_threshold();
+extern const int STEPS_PER_SYNC;
+// one Arnoldi step (apply of B, Gram-Schmidt, Givens, scale) for every instance with run[b]
+template <class T>
+void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s);
+
 }  // namespace psfd

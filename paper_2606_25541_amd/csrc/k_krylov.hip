@@ -363,7 +363,7 @@ void krylov_lincomb(const T* V, long long ldv, long long bsv, TX* x, long long b
 __global__ void k_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
                         double reorth_thr, const int* mask, int* run) {
   const int b = blockIdx.x;
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || (mask && !mask[b])) return;  // other instances keep their state
   GState& S = st[b];
   const double rn = sqrt(rnorm2[b]);
   S.j = 0;
@@ -377,7 +377,7 @@ __global__ void k_start(GState* st, const double* rnorm2, const double* abs_targ
   S.target = abs_target[b] > t ? abs_target[b] : t;
   S.res = rn;
   S.conv = 0;
-  const bool go = (!mask || mask[b]) && rn > abs_target[b] && rn > 0.0 && rn == rn;
+  const bool go = rn > abs_target[b] && rn > 0.0 && rn == rn;
   S.stop = go ? 0 : 1;
   run[b] = go ? 1 : 0;
 }
@@ -478,24 +478,26 @@ void vec_diff2(const T* x, const T* y, long long n, long long bstride, double* p
 
 template <class TO, class TX>
 __global__ void __launch_bounds__(KB) k_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n,
-                                                      long long bs, const int* mask) {
+                                                      long long bs_out, long long bs_x, const int* mask) {
   const int b = blockIdx.y;
   if (mask && !mask[b]) return;
   const double v = n2[b];
   const double sc = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
-  const long long o = (long long)b * bs;
+  TO* ob = out + (long long)b * bs_out;
+  const TX* xb = x + (long long)b * bs_x;
   for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
-    double2 xv = to_d(x[o + e]);
-    out[o + e] = from_d<TO>(make_double2(xv.x * sc, xv.y * sc));
+    double2 xv = to_d(xb[e]);
+    ob[e] = from_d<TO>(make_double2(xv.x * sc, xv.y * sc));
   }
 }
 
 template <class TO, class TX>
-void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long long bstride,
+void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long long bs_out, long long bs_x,
                        const int* mask, int nbatch, hipStream_t s) {
   int nb = (int)((n + KB - 1) / KB);
   if (nb > 2048) nb = 2048;
-  hipLaunchKernelGGL((k_scale_invsqrt<TO, TX>), dim3(nb, nbatch), dim3(KB), 0, s, out, x, n2, n, bstride, mask);
+  hipLaunchKernelGGL((k_scale_invsqrt<TO, TX>), dim3(nb, nbatch), dim3(KB), 0, s, out, x, n2, n, bs_out, bs_x,
+                     mask);
 }
 
 // ---- instantiations ----------------------------------------------------------
@@ -524,8 +526,8 @@ template void vec_axpby<double2, float2, float2>(double2*, const float2*, const 
 template void vec_axpby<float2, float2, float2>(float2*, const float2*, const float2*, double, double,
                                                 long long, long long, const int*, int, hipStream_t);
 template void vec_scale_invsqrt<double2, double2>(double2*, const double2*, const double*, long long, long long,
-                                                  const int*, int, hipStream_t);
+                                                  long long, const int*, int, hipStream_t);
 template void vec_scale_invsqrt<float2, double2>(float2*, const double2*, const double*, long long, long long,
-                                                 const int*, int, hipStream_t);
+                                                 long long, const int*, int, hipStream_t);
 
 }  // namespace psfd

@@ -83,9 +83,9 @@ void vec_axpby(TO* out, const TX* x, const TY* y, double a, double c, long long 
 template <class T>
 void vec_norm2(const T* x, long long n, long long bstride, double* part, double* out, const int* mask,
                int nbatch, hipStream_t s);
-// out = x / sqrt(n2[b]) (0 when n2[b] == 0)
+// out = x / sqrt(n2[b]) (0 when n2[b] == 0); out and x have their own instance strides
 template <class TO, class TX>
-void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long long bstride,
+void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long long bs_out, long long bs_x,
                        const int* mask, int nbatch, hipStream_t s);
 // out[b] = ||x_b - y_b||^2 and ||x_b||^2 (for relative changes); out has 2 doubles per instance
 template <class T>

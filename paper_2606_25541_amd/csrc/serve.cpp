@@ -2,8 +2,15 @@
 // continuous-batching solve server.
 #include "serve.hpp"
 
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 
 namespace psfd {
 
@@ -64,17 +71,389 @@ Status solve_batch(int n, const psfd_problem* probs, const psfd_opts* opts, cons
   return st;
 }
 
-Status server_create(size_t, int, const psfd_opts*, psfd_server**) {
-  Status st; st.code = PSFD_ERR_INVALID_ARG; st.msg = "server not available"; return st;
+// ---------------------------------------------------------------------------
+// Continuous-batching solve server.
+//
+// Requests are grouped by grid shape. Each shape owns a slot group (a Group of
+// `cap` instances) allocated the first time the shape appears, sized so that
+// the groups' device footprint stays within the budget. A worker thread runs
+// ticks; every tick advances every occupied slot by one phase of its own
+// coupled solve (monolithic coupling, GMRES(m) with FP64 residuals):
+//   INIT  tables, contrast, e_bg, x0 = e_bg, ||b||
+//   START FP64 residual r = b - A x: done, or start an Arnoldi cycle
+//   ARN   Arnoldi steps (all running slots share each launch)
+//   END   y = H^-1 g, x += V y
+//   FIN   readouts, E_up, E_layer, E_mask = u - e, orders, copy-out
+// Requests that arrive while others run are admitted into free slots at the
+// next tick and share the launches from then on. Every kernel works per
+// instance with a fixed reduction layout, so a result does not depend on which
+// other requests share the group.
+// ---------------------------------------------------------------------------
+using clk = std::chrono::steady_clock;
+
+enum Phase { P_FREE = 0, P_INIT, P_START, P_ARN, P_END, P_FIN };
+
+struct Req {
+  uint64_t ticket = 0;
+  Problem pr;
+  Shape sh;
+  std::vector<double> tab;
+  const void* d_deps = nullptr;
+  void* d_emask = nullptr;
+  void* d_orders = nullptr;
+  clk::time_point t_submit, t_done;
+  bool done = false;
+  int status = PSFD_OK;
+  psfd_info info{};
+};
+
+struct SlotGroup {
+  Shape sh;
+  std::unique_ptr<Group> g;
+  int cap = 0;
+  std::vector<Req*> req;
+  std::vector<int> phase;
+  std::vector<int> cycles;
+  std::vector<double> bn, tgt, res;
+  int occupied() const {
+    int n = 0;
+    for (auto* r : req) n += r != nullptr;
+    return n;
+  }
+};
+
+}  // namespace psfd
+
+struct psfd_server {
+  size_t budget = 0;
+  int max_slots = 1;
+  psfd::Opts o;
+  int device = 0;
+  hipStream_t s = nullptr;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<psfd::Req*> queue;
+  std::unordered_map<uint64_t, std::unique_ptr<psfd::Req>> reqs;
+  uint64_t next = 1;
+  bool stop = false;
+  size_t allocated = 0;
+  std::vector<std::unique_ptr<psfd::SlotGroup>> groups;
+  psfd::Status err;
+};
+
+namespace psfd {
+
+static bool shape_eq(const Shape& a, const Shape& b) { return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz; }
+
+static void finish_req(psfd_server* S, Req* r, int status) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  r->status = status;
+  r->info.status = status;
+  r->t_done = clk::now();
+  r->done = true;
 }
-Status server_submit(psfd_server*, const psfd_problem*, const void*, void*, void*, uint64_t*) {
-  Status st; st.code = PSFD_ERR_INVALID_ARG; st.msg = "server not available"; return st;
+
+template <class T>
+static Status tick_group(psfd_server* S, SlotGroup& G) {
+  Group& g = *G.g;
+  hipStream_t s = S->s;
+  const Opts& o = S->o;
+  const int B = G.cap;
+  const Shape& sh = G.sh;
+  const long long n3 = sh.n3, nq = sh.nxny * 3, N = sh.N, bsv = (long long)(g.m + 1) * n3;
+  auto mask_of = [&](int ph) {
+    std::vector<int> m(B, 0);
+    bool any = false;
+    for (int b = 0; b < B; ++b) if (G.phase[b] == ph) { m[b] = 1; any = true; }
+    return std::make_pair(m, any);
+  };
+  Status st;
+  // INIT
+  {
+    auto mk = mask_of(P_INIT);
+    if (mk.second) {
+      for (int b = 0; b < B; ++b) {
+        if (!mk.first[b]) continue;
+        Req* r = G.req[b];
+        st = group_set_tables(g, b, r->tab, s);
+        if (!st.ok()) return st;
+        hipError_t e = hipMemcpyAsync(g.deps64 + (size_t)b * N, r->d_deps, N * 16, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemsetAsync(g.adn + (size_t)b * nq, 0, nq * 16, s);
+        if (e == hipSuccess) e = hipMemsetAsync(g.st + b, 0, sizeof(GState), s);
+        if (e != hipSuccess) return hip_status(e, "server init");
+        G.cycles[b] = 0;
+      }
+      st = set_mask(g, g.mask2, mk.first, s);
+      if (!st.ok()) return st;
+      if (g.prec == PSFD_MIXED)
+        vec_axpby<float2, double2, double2>(g.deps32, g.deps64, nullptr, 1.0, 0.0, N, N, g.mask2, B, s);
+      st = reflect(g, g.eup, g.mask2, nullptr, s);
+      if (!st.ok()) return st;
+      inject(g, g.eup, g.b, g.mask2, s);
+      vec_axpby<double2, double2, double2>(g.x, g.b, (const double2*)nullptr, 1.0, 0.0, n3, n3, g.mask2, B, s);
+      vec_norm2<double2>(g.b, n3, n3, g.dpart, g.n2b, g.mask2, B, s);
+      std::vector<double> bn2;
+      st = read_norms(g, g.n2b, bn2, s);
+      if (!st.ok()) return st;
+      for (int b = 0; b < B; ++b)
+        if (mk.first[b]) { G.bn[b] = std::sqrt(bn2[b]); G.tgt[b] = o.rtol * G.bn[b]; G.phase[b] = P_START; }
+      std::memcpy(g.h_dbl, G.tgt.data(), sizeof(double) * B);
+      hipError_t e = hipMemcpyAsync(g.abs_target, g.h_dbl, sizeof(double) * B, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_status(e, "server targets");
+    }
+  }
+  // START: FP64 residual, convergence test, cycle start
+  {
+    auto mk = mask_of(P_START);
+    if (mk.second) {
+      st = set_mask(g, g.mask, mk.first, s);
+      if (!st.ok()) return st;
+      apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, 0, 1, g.mask, s);
+      vec_axpby<double2, double2, double2>(g.r, g.b, g.r, 1.0, -1.0, n3, n3, g.mask, B, s);
+      vec_norm2<double2>(g.r, n3, n3, g.dpart, g.n2, g.mask, B, s);
+      std::vector<double> rn2;
+      st = read_norms(g, g.n2, rn2, s);
+      if (!st.ok()) return st;
+      std::vector<GState> hs(B);
+      hipError_t e = hipMemcpyAsync(hs.data(), g.st, sizeof(GState) * B, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_status(e, "server state");
+      std::vector<int> go(B, 0);
+      bool any = false;
+      for (int b = 0; b < B; ++b) {
+        if (!mk.first[b]) continue;
+        const double rn = std::sqrt(rn2[b]);
+        Req* r = G.req[b];
+        r->info.rel_residual = G.bn[b] > 0 ? rn / G.bn[b] : 0.0;
+        r->info.iters = hs[b].iters;
+        r->info.cycles = G.cycles[b];
+        if (!std::isfinite(rn)) { r->status = PSFD_ERR_NONFINITE; G.phase[b] = P_FIN; continue; }
+        if (rn <= G.tgt[b] || G.bn[b] == 0.0) { G.phase[b] = P_FIN; continue; }
+        if (hs[b].iters >= o.max_iters) { r->status = PSFD_NOT_CONVERGED; G.phase[b] = P_FIN; continue; }
+        go[b] = 1;
+        any = true;
+        G.phase[b] = P_ARN;
+        G.cycles[b] += 1;
+      }
+      if (any) {
+        st = set_mask(g, g.mask, go, s);
+        if (!st.ok()) return st;
+        vec_scale_invsqrt<T, double2>((T*)g.basis, g.r, g.n2, n3, bsv, n3, g.mask, B, s);
+        krylov_start(g.st, g.n2, g.abs_target, g.prec == PSFD_MIXED ? o.inner_eta : 0.0, g.m, reorth_threshold(),
+                     g.mask, g.run, B, s);
+      }
+    }
+  }
+  // FIN: fields and orders, copy-out
+  {
+    auto mk = mask_of(P_FIN);
+    if (mk.second) {
+      st = set_mask(g, g.mask2, mk.first, s);
+      if (!st.ok()) return st;
+      apply_stage<double2>(g, 0, g.deps64, vr(g.x, n3), vr(g.x, n3), g.ws64, 0, 0, 0, g.mask2, s);
+      launch_readout(sh.nx, sh.ny, sh.nz, vr(g.ws64, n3), g.tab, g.tab_stride, g.adn, g.aup, nq, g.mask2, B, s);
+      st = reflect(g, g.eup, g.mask2, nullptr, s);
+      if (!st.ok()) return st;
+      inject(g, g.eup, g.e, g.mask2, s);
+      launch_orders(sh.nx, sh.ny, g.tab, g.tab_stride, g.eup, g.aup, g.ord, nq, B, s);
+      vec_axpby<double2, double2, double2>(g.x, g.x, g.e, 1.0, -1.0, n3, n3, g.mask2, B, s);
+      for (int b = 0; b < B; ++b) {
+        if (!mk.first[b]) continue;
+        Req* r = G.req[b];
+        hipError_t e = hipMemcpyAsync(r->d_emask, g.x + (size_t)b * n3, n3 * 16, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && r->d_orders)
+          e = hipMemcpyAsync(r->d_orders, g.ord + (size_t)b * nq, nq * 16, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_status(e, "server copy-out");
+      }
+      hipError_t e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_status(e, "server finish");
+      for (int b = 0; b < B; ++b) {
+        if (!mk.first[b]) continue;
+        Req* r = G.req[b];
+        r->info.outer_iters = 1;
+        r->info.mono_residual = r->info.rel_residual;
+        finish_req(S, r, r->status);
+        G.req[b] = nullptr;
+        G.phase[b] = P_FREE;
+      }
+    }
+  }
+  // ARN: Arnoldi steps of every running slot
+  {
+    bool any = false;
+    for (int b = 0; b < B; ++b) any |= G.phase[b] == P_ARN;
+    if (any) {
+      for (int k = 0; k < STEPS_PER_SYNC; ++k) arnoldi_step<T>(g, 0, 1, s);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = hipMemcpyAsync(g.h_run, g.run, sizeof(int) * B, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_status(e, "server arnoldi");
+      std::vector<int> end(B, 0);
+      bool anyend = false;
+      for (int b = 0; b < B; ++b)
+        if (G.phase[b] == P_ARN && g.h_run[b] == 0) { end[b] = 1; anyend = true; G.phase[b] = P_END; }
+      // END: solution update of the finished cycles
+      if (anyend) {
+        st = set_mask(g, g.mask, end, s);
+        if (!st.ok()) return st;
+        krylov_solve_small(g.st, g.mask, B, s);
+        krylov_lincomb<T, double2>((const T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.mask, B, s);
+        for (int b = 0; b < B; ++b) if (end[b]) G.phase[b] = P_START;
+      }
+    }
+  }
+  return Status();
 }
-Status server_poll(psfd_server*, uint64_t, int*, psfd_info*, double*) {
-  Status st; st.code = PSFD_ERR_INVALID_ARG; st.msg = "server not available"; return st;
+
+static void admit(psfd_server* S) {
+  // move queued requests into free slots of their shape group (no head-of-line blocking across shapes)
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (auto it = S->queue.begin(); it != S->queue.end();) {
+    Req* r = *it;
+    SlotGroup* G = nullptr;
+    for (auto& gp : S->groups)
+      if (shape_eq(gp->sh, r->sh)) G = gp.get();
+    if (!G) {
+      const size_t per = group_bytes(r->sh, 1, S->o.restart, S->o.precision);
+      const size_t avail = S->budget > S->allocated ? S->budget - S->allocated : 0;
+      const int cap = (int)std::min<size_t>((size_t)S->max_slots, avail / per);
+      if (cap < 1) {
+        r->status = PSFD_ERR_OOM;
+        r->info.status = PSFD_ERR_OOM;
+        r->t_done = clk::now();
+        r->done = true;
+        it = S->queue.erase(it);
+        continue;
+      }
+      auto ng = std::make_unique<SlotGroup>();
+      ng->sh = r->sh;
+      ng->g = std::make_unique<Group>();
+      Status st = group_alloc(*ng->g, r->sh, cap, S->o.restart, S->o.precision);
+      if (!st.ok()) {
+        r->status = st.code;
+        r->info.status = st.code;
+        r->t_done = clk::now();
+        r->done = true;
+        it = S->queue.erase(it);
+        continue;
+      }
+      ng->cap = cap;
+      ng->req.assign(cap, nullptr);
+      ng->phase.assign(cap, P_FREE);
+      ng->cycles.assign(cap, 0);
+      ng->bn.assign(cap, 0.0);
+      ng->tgt.assign(cap, 0.0);
+      ng->res.assign(cap, 0.0);
+      S->allocated += per * (size_t)cap;
+      G = ng.get();
+      S->groups.push_back(std::move(ng));
+    }
+    int slot = -1;
+    for (int b = 0; b < G->cap; ++b)
+      if (!G->req[b]) { slot = b; break; }
+    if (slot < 0) { ++it; continue; }
+    G->req[slot] = r;
+    G->phase[slot] = P_INIT;
+    it = S->queue.erase(it);
+  }
 }
-Status server_destroy(psfd_server*) {
-  Status st; st.code = PSFD_ERR_INVALID_ARG; st.msg = "server not available"; return st;
+
+static void worker_main(psfd_server* S) {
+  (void)hipSetDevice(S->device);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      bool busy = false;
+      for (auto& G : S->groups) busy |= G->occupied() > 0;
+      if (!busy) {
+        S->cv.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+        if (S->stop && S->queue.empty()) return;
+      }
+    }
+    admit(S);
+    for (auto& G : S->groups) {
+      if (G->occupied() == 0) continue;
+      Status st = S->o.precision == PSFD_MIXED ? tick_group<float2>(S, *G) : tick_group<double2>(S, *G);
+      if (!st.ok()) {
+        // a runtime failure ends every request of the group
+        {
+          std::lock_guard<std::mutex> lk(S->mu);
+          S->err = st;
+        }
+        for (int b = 0; b < G->cap; ++b)
+          if (G->req[b]) { finish_req(S, G->req[b], st.code); G->req[b] = nullptr; G->phase[b] = P_FREE; }
+      }
+    }
+  }
+}
+
+Status server_create(size_t hbm_budget, int max_slots, const psfd_opts* opts, psfd_server** out) {
+  Status st;
+  auto S = std::make_unique<psfd_server>();
+  st = make_opts(opts, S->o);
+  if (!st.ok()) return st;
+  S->o.coupling = PSFD_COUPLING_MONO;
+  S->budget = hbm_budget;
+  S->max_slots = max_slots;
+  hipError_t e = hipGetDevice(&S->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_status(e, "server stream");
+  psfd_server* raw = S.get();
+  S->worker = std::thread(worker_main, raw);
+  *out = S.release();
+  return st;
+}
+
+Status server_submit(psfd_server* S, const psfd_problem* prob, const void* d_deps, void* d_emask, void* d_orders,
+                     uint64_t* ticket) {
+  auto r = std::make_unique<Req>();
+  Status st = validate_problem(prob, r->pr);
+  if (!st.ok()) return st;
+  st = build_table(r->pr, r->tab);
+  if (!st.ok()) return st;
+  r->sh = shape_of(r->pr.p);
+  r->d_deps = d_deps;
+  r->d_emask = d_emask;
+  r->d_orders = d_orders;
+  r->t_submit = clk::now();
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->stop) { st.code = PSFD_ERR_INVALID_ARG; st.msg = "server is shutting down"; return st; }
+  r->ticket = S->next++;
+  *ticket = r->ticket;
+  S->queue.push_back(r.get());
+  S->reqs.emplace(r->ticket, std::move(r));
+  S->cv.notify_one();
+  return st;
+}
+
+Status server_poll(psfd_server* S, uint64_t ticket, int* done, psfd_info* info, double* latency_s) {
+  Status st;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) { st.code = PSFD_ERR_INVALID_ARG; st.msg = "unknown ticket"; return st; }
+  Req* r = it->second.get();
+  *done = r->done ? 1 : 0;
+  if (!r->done) return st;
+  if (info) *info = r->info;
+  if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+  S->reqs.erase(it);
+  return st;
+}
+
+Status server_destroy(psfd_server* S) {
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  S->groups.clear();
+  if (S->s) (void)hipStreamDestroy(S->s);
+  Status st = S->err;
+  delete S;
+  return st;
 }
 
 }  // namespace psfd

@@ -1,0 +1,141 @@
+"""Batched solves and the continuous-batching server.
+
+* A batch of instances (different angles, polarisations, clips) gives the same
+  result per instance as solving each alone (bitwise: every reduction runs per
+  instance with a fixed layout).
+* Requests submitted while others are running are admitted as slots free up;
+  each served result equals the same problem solved alone, and agrees with the
+  oracle.
+* Admission respects the device-memory budget.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_25541_amd import clips
+
+from gpu_util import device, rel, say, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def prob(n, nz, theta, phi, pol, pairs=20):
+    layers, es = clips.mo_si_stack(pairs)
+    return clips.Problem(nx=n, ny=n, nz=nz, lx_nm=2.0 * n, ly_nm=2.0 * n, t_nm=30.0, theta_deg=theta,
+                         phi_deg=phi, pol=pol, layers=layers, eps_sub=es)
+
+
+def cases():
+    out = []
+    angles = clips.pupil_angles()
+    for i in range(6):
+        n, nz = (16, 8) if i % 2 == 0 else (32, 8)
+        th, ph = angles[(7 * i) % len(angles)]
+        p = prob(n, nz, th, ph, i % 2 if i < 4 else 0)
+        out.append((p, clips.manhattan(n, n, nz, p.lx_nm, p.ly_nm, seed=100 + i)))
+    return out
+
+
+OPTS = dict(rtol=1e-9, precision="mixed", restart=16)
+
+
+def alone(p, de, dev):
+    from paper_2606_25541_amd import api
+    plan = api.Plan(p, **OPTS)
+    em, od, info = plan.psfd_solve(torch.from_numpy(de).to(dev))
+    torch.cuda.synchronize()
+    return em.cpu().numpy(), od.cpu().numpy(), info
+
+
+def test_batch_equals_single():
+    from paper_2606_25541_amd import api
+    dev = device()
+    cs = [c for c in cases() if c[0].nx == 16]
+    say("batch of", len(cs))
+    em, od, infos = api.psfd_solve_batch([c[0] for c in cs], [torch.from_numpy(c[1]).to(dev) for c in cs], **OPTS)
+    torch.cuda.synchronize()
+    for (p, de), e, o, inf in zip(cs, em, od, infos):
+        e1, o1, i1 = alone(p, de, dev)
+        assert inf["status"] == 0
+        assert np.array_equal(e.cpu().numpy(), e1), rel(e.cpu().numpy(), e1)
+        assert np.array_equal(o.cpu().numpy(), o1)
+        assert inf["iters"] == i1["iters"]
+
+
+def test_server_mix_equals_alone_and_oracle():
+    from paper_2606_25541_amd import api
+    dev = device()
+    cs = cases()
+    srv = api.Server(hbm_budget=8 << 30, max_slots=2, **OPTS)
+    outs, tickets = [], []
+    for k, (p, de) in enumerate(cs):
+        d = torch.from_numpy(de).to(dev)
+        e = torch.empty((3, p.nz, p.ny, p.nx), dtype=torch.complex128, device=dev)
+        o = torch.empty((p.ny, p.nx, 3), dtype=torch.complex128, device=dev)
+        torch.cuda.synchronize()
+        tickets.append(srv.submit(p, d, e, o))
+        outs.append((d, e, o))
+        if k == 2:
+            time.sleep(0.05)  # later requests arrive while the first ones run
+    results = {}
+    t0 = time.time()
+    while len(results) < len(tickets) and time.time() - t0 < 120:
+        for t in tickets:
+            if t in results:
+                continue
+            done, info, lat = srv.poll(t)
+            if done:
+                results[t] = (info, lat)
+        time.sleep(0.002)
+    srv.close()
+    assert len(results) == len(tickets)
+    for (p, de), t, (d, e, o) in zip(cs, tickets, outs):
+        info, lat = results[t]
+        say("served", p.nx, info, "latency %.3f s" % lat)
+        assert info["status"] == 0 and lat > 0
+        e1, o1, i1 = alone(p, de, dev)
+        assert np.array_equal(e.cpu().numpy(), e1), rel(e.cpu().numpy(), e1)
+        assert np.array_equal(o.cpu().numpy(), o1)
+    p, de = cs[1]
+    ref = O.solve(p, de, rtol=1e-11)
+    assert rel(outs[1][1].cpu().numpy(), ref["emask"]) < 1e-7
+
+
+def test_server_budget_admission():
+    from paper_2606_25541_amd import api
+    dev = device()
+    p, de = cases()[0]
+    plan = api.Plan(p, **OPTS)
+    per_slot = plan.footprint()
+    # budget below one slot: the request is refused with an out-of-memory status
+    srv = api.Server(hbm_budget=per_slot // 2, max_slots=4, **OPTS)
+    d = torch.from_numpy(de).to(dev)
+    e = torch.empty((3, p.nz, p.ny, p.nx), dtype=torch.complex128, device=dev)
+    o = torch.empty((p.ny, p.nx, 3), dtype=torch.complex128, device=dev)
+    t = srv.submit(p, d, e, o)
+    for _ in range(2000):
+        done, info, lat = srv.poll(t)
+        if done:
+            break
+        time.sleep(0.005)
+    assert done and info["status"] == -3
+    srv.close()
+    # budget for one slot: three requests run one after another, all complete
+    srv = api.Server(hbm_budget=int(per_slot * 1.5), max_slots=4, **OPTS)
+    bufs = [(torch.empty_like(e), torch.empty_like(o)) for _ in range(3)]
+    ts = [srv.submit(p, d, bb[0], bb[1]) for bb in bufs]
+    lats = []
+    for t in ts:
+        for _ in range(20000):
+            done, info, lat = srv.poll(t)
+            if done:
+                break
+            time.sleep(0.001)
+        assert done and info["status"] == 0
+        lats.append(lat)
+    srv.close()
+    assert lats[0] < lats[1] < lats[2]
+    for bb in bufs[1:]:
+        assert torch.equal(bb[0], bufs[0][0])
