@@ -218,34 +218,62 @@ void build_twiddles(std::vector<double>& tw) {
 
 // ---------------------------------------------------------------------------
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+// launch-shape overrides for tuning sweeps (read once)
+static int env_int(const char* name, int dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::atoi(e) : dflt;
+}
+// complex values per thread of an LDS FFT pass (see FftBudget)
+static int fft_elems(size_t esz) { return esz == 8 ? 16 : 8; }
+
+// LDS row pitch of a transverse tile: consecutive rows start 8 (FP32) or 4 (FP64)
+// elements apart modulo the 256-byte bank period, so a radix-16 or radix-8 pass
+// over rows or columns hits each bank at most twice per wavefront access.
+static int tile_pitch(int tx, size_t esz) {
+  const int period = (int)(256 / esz);       // elements per bank period
+  const int want = esz == 8 ? 8 : 4;
+  if (tx < period) return tx + 1;
+  return tx + want;
+}
 static int ceil64(int v) { return (v + 63) / 64 * 64; }
 
 XYCfg xy_config(const Shape& sh, size_t esz) {
   XYCfg c{};
   const int nx = sh.nx, ny = sh.ny;
-  const size_t full_lds = (size_t)ny * (nx + 1) * esz;
+  const size_t full_lds = (size_t)ny * tile_pitch(nx, esz) * esz;
   c.fused = full_lds <= LDS_MAX && (long long)nx * ny <= 16 * 1024;
-  c.full = TileShape{nx, ny, 1, 1, clampi(nx * ny / 8, 64, 1024), full_lds};
-  if (nx * ny > 16 * c.full.nthr) c.full.nthr = 1024;
+  c.full = TileShape{nx, ny, 1, 1, clampi(nx * ny / 8, 64, 1024), full_lds, tile_pitch(nx, esz)};
+  if (nx * ny > fft_elems(esz) * c.full.nthr) c.fused = false;
+  if (env_int("PSFD_XY_SPLIT", 0)) c.fused = false;
   int rb = clampi(4096 / nx, 1, ny);
   int rel = rb * nx;
-  c.rows = TileShape{nx, rb, 1, 0, clampi(ceil64(rel / 8), 64, 1024), (size_t)rb * (nx + 1) * esz};
+  c.rows = TileShape{nx, rb, 1, 0, clampi(ceil64(rel / 8), 64, 1024), (size_t)rb * tile_pitch(nx, esz) * esz,
+                     tile_pitch(nx, esz)};
   int cb = std::min(nx, 16);
   int cel = cb * ny;
-  c.cols = TileShape{cb, ny, 0, 1, clampi(ceil64(cel / 8), 64, 1024), (size_t)ny * (cb + 1) * esz};
+  c.cols = TileShape{cb, ny, 0, 1, clampi(ceil64(cel / 8), 64, 1024), (size_t)ny * tile_pitch(cb, esz) * esz,
+                     tile_pitch(cb, esz)};
   return c;
+}
+
+// LDS of a pencil block: interleaved pencil data (pz x 3 bx), per-plane phases
+// (nz x bx), the per-order layered response (bx x 3) and the readout partial
+// sums (4 chunks x 3 bx), the last two in FP64.
+static size_t pencil_lds(const Shape& sh, int bx, size_t esz) {
+  size_t d = (size_t)sh.pz * 3 * bx * esz + (size_t)sh.nz * bx * esz;
+  d = (d + 15) / 16 * 16;
+  return d + (size_t)3 * bx * 16 + (size_t)4 * 3 * bx * 16;
 }
 
 ZCfg z_config(const Shape& sh, size_t esz) {
   ZCfg z{};
-  int bx = std::min(sh.nx, 16);
-  while (bx > 1 && (size_t)3 * bx * (sh.pz + 1) * esz + (size_t)bx * sh.nz * esz + 3 * bx * 16 + 16 > 150 * 1024)
-    bx >>= 1;
+  int bx = std::min(sh.nx, env_int("PSFD_ZBX", 16));
+  while (bx > 1 && pencil_lds(sh, bx, esz) > 150 * 1024) bx >>= 1;
   z.bx = bx;
   z.nthr = clampi(ceil64(3 * bx * sh.pz / 8), 64, 1024);
-  while (3 * bx * sh.pz > 16 * z.nthr && z.nthr < 1024) z.nthr += 64;
-  // pencil data, per-plane phases exp(i beta z_k) and the per-order layered response
-  z.lds = (size_t)3 * bx * (sh.pz + 1) * esz + (size_t)bx * sh.nz * esz + 16 + (size_t)3 * bx * 16;
+  while (3 * bx * sh.pz > fft_elems(esz) * z.nthr && z.nthr < 1024) z.nthr += 64;
+  if (z.nthr < 4 * 3 * bx) z.nthr = ceil64(4 * 3 * bx);  // one thread per readout partial sum
+  z.lds = pencil_lds(sh, bx, esz);
   return z;
 }
 
@@ -373,7 +401,7 @@ static TileArgs tile_base(const Group& g, const void* tw, const TileShape& t) {
   std::memset(&a, 0, sizeof(a));
   a.nx = g.sh.nx; a.ny = g.sh.ny; a.nz = g.sh.nz;
   a.log2nx = ilog2i(g.sh.nx); a.log2ny = ilog2i(g.sh.ny);
-  a.tx = t.tx; a.ty = t.ty; a.pitch = t.tx + 1;
+  a.tx = t.tx; a.ty = t.ty; a.pitch = t.pitch;
   a.tiles_x = g.sh.nx / t.tx; a.tiles_y = g.sh.ny / t.ty;
   a.do_x = t.do_x; a.do_y = t.do_y;
   a.tab = g.tab; a.tab_stride = g.tab_stride;

@@ -1,13 +1,13 @@
-// Radix-2/4/8/16 Stockham FFT passes on data staged in LDS.
+// Radix-2/4/8 Stockham FFT passes on data staged in LDS.
 //
 // A batch of `nseq` sequences of power-of-two length n lives in LDS; element j
 // of sequence s sits at lds[s * sstride + j * estride]. Each pass of radix R
-// gives every thread up to 16 / R butterflies: the thread reads its R inputs
+// gives every thread up to E / R butterflies: the thread reads its R inputs
 // (spaced n / R apart) into registers, the workgroup synchronises, then it
 // applies the twiddles exp(-+2 pi i j k / (p R)), a register DFT of size R and
 // writes the outputs in self-sorting (Stockham) order. The pass works in place
 // because every read of the pass precedes the barrier. Requires
-// n * nseq <= 16 * nthreads.
+// n * nseq <= E * nthreads (E = 16 for FP32, 8 for FP64).
 //
 // Twiddles come from a table built on the host in FP64: tw[n + i] =
 // exp(-2 pi i i / n) for every power of two n (so the table of length n
@@ -56,51 +56,34 @@ template <class T, bool INV> PSFD_D void dft8(T* x) {
   x[3] = cadd(e3, o3); x[7] = csub(e3, o3);
 }
 
-// multiply by exp(-+2 pi i k / 16), k = 0..7
-template <class T, bool INV> PSFD_D T w16(T a, int k) {
-  typedef typename real_of<T>::type R;
-  const R c1 = (R)0.92387953251128675613, s1 = (R)0.38268343236508977173;
-  const R h = (R)0.70710678118654752440;
-  R c, s;  // exp(-i theta) = c - i s for the forward sign
-  switch (k) {
-    case 0: return a;
-    case 1: c = c1; s = s1; break;
-    case 2: c = h; s = h; break;
-    case 3: c = s1; s = c1; break;
-    case 4: c = 0; s = 1; break;
-    case 5: c = -s1; s = c1; break;
-    case 6: c = -h; s = h; break;
-    default: c = -c1; s = s1; break;
-  }
-  if (INV) s = -s;
-  T r; r.x = a.x * c + a.y * s; r.y = a.y * c - a.x * s; return r;
-}
-
-template <class T, bool INV> PSFD_D void dft16(T* x) {
-  T e[8], o[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) { e[i] = x[2 * i]; o[i] = x[2 * i + 1]; }
-  dft8<T, INV>(e);
-  dft8<T, INV>(o);
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    T t = w16<T, INV>(o[k], k);
-    x[k] = cadd(e[k], t);
-    x[k + 8] = csub(e[k], t);
-  }
-}
-
 template <class T, int R, bool INV> PSFD_D void dft_r(T* u) {
   if (R == 2) dft2<T, INV>(u[0], u[1]);
   else if (R == 4) dft4<T, INV>(u[0], u[1], u[2], u[3]);
-  else if (R == 8) dft8<T, INV>(u);
-  else dft16<T, INV>(u);
+  else dft8<T, INV>(u);
 }
 
-template <class T, int R, bool INV>
+// SF (sequence-fastest): consecutive threads take consecutive sequences at the
+// same butterfly index, the conflict-free mapping when sequences are
+// interleaved in LDS (sstride 1); otherwise consecutive threads take
+// consecutive butterflies of one sequence.
+template <bool SF>
+PSFD_D void bfly_index(int b, int log2nr, int nseq, int& s, int& t) {
+  if (SF) { t = b / nseq; s = b - t * nseq; }
+  else { s = b >> log2nr; t = b & ((1 << log2nr) - 1); }
+}
+
+// Per-thread element budget of a pass (16 FP32 / 8 FP64 complex values) and the
+// largest radix: radix-8 butterflies keep a 1024-thread workgroup inside its 128
+// registers per lane; a radix-16 butterfly with its twiddles does not.
+template <class T> struct FftBudget {
+  static constexpr int E = sizeof(T) == 8 ? 16 : 8;
+  static constexpr int LRMAX = 3;
+};
+
+template <class T, int R, bool INV, bool SF>
 __device__ __forceinline__ void stockham_pass(T* lds, int log2n, int log2p, int nseq, int sstride, int estride,
                               const T* __restrict__ tw, int tid, int nthr) {
-  constexpr int NB = 16 / R;
+  constexpr int NB = FftBudget<T>::E / R;
   constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
   const int log2nr = log2n - LR;
   const int nr = 1 << log2nr;
@@ -110,7 +93,8 @@ __device__ __forceinline__ void stockham_pass(T* lds, int log2n, int log2p, int 
   for (int i = 0; i < NB; ++i) {
     int b = tid + i * nthr;
     if (b < nbt) {
-      int s = b >> log2nr, t = b & (nr - 1);
+      int s, t;
+      bfly_index<SF>(b, log2nr, nseq, s, t);
       const T* base = lds + s * sstride;
 #pragma unroll
       for (int j = 0; j < R; ++j) u[i][j] = base[(t + j * nr) * estride];
@@ -123,7 +107,8 @@ __device__ __forceinline__ void stockham_pass(T* lds, int log2n, int log2p, int 
   for (int i = 0; i < NB; ++i) {
     int b = tid + i * nthr;
     if (b < nbt) {
-      int s = b >> log2nr, t = b & (nr - 1);
+      int s, t;
+      bfly_index<SF>(b, log2nr, nseq, s, t);
       int k = t & (p - 1);
       int step = k << tsh;
 #pragma unroll
@@ -143,19 +128,18 @@ __device__ __forceinline__ void stockham_pass(T* lds, int log2n, int log2p, int 
 
 // Full FFT of nseq sequences of length 2^log2n staged in LDS (unnormalised;
 // INV uses the +i sign). All threads of the workgroup must call it.
-template <class T, bool INV>
+template <class T, bool INV, bool SF = false>
 __device__ __forceinline__ void lds_fft(T* lds, int log2n, int nseq, int sstride, int estride,
                         const T* __restrict__ tw_all, int tid, int nthr) {
   const T* tw = tw_all + (1 << log2n);
   int log2p = 0;
   int rem = log2n;
   while (rem > 0) {
-    int lr = rem >= 4 ? 4 : rem;
+    int lr = rem >= FftBudget<T>::LRMAX ? FftBudget<T>::LRMAX : rem;
     switch (lr) {
-      case 4: stockham_pass<T, 16, INV>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
-      case 3: stockham_pass<T, 8, INV>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
-      case 2: stockham_pass<T, 4, INV>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
-      default: stockham_pass<T, 2, INV>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
+      case 3: stockham_pass<T, 8, INV, SF>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
+      case 2: stockham_pass<T, 4, INV, SF>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
+      default: stockham_pass<T, 2, INV, SF>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
     }
     log2p += lr;
     rem -= lr;

@@ -158,6 +158,9 @@ PSFD_D double2 window_factor(double2 beta, double2 eibl, double kap, double L, d
   return cdiv(num, den);
 }
 
+// LDS layout of a pencil block: element z of sequence (c, kxl) at z * LS + c * bx + kxl
+// (sequences interleaved, LS = 3 bx), so every FFT pass, the kernel multiply and
+// the global load/store touch consecutive LDS words across a wavefront.
 template <class T>
 __global__ void __launch_bounds__(1024) k_pencil(PencilArgs a) {
   extern __shared__ double2 smem_d[];
@@ -169,46 +172,59 @@ __global__ void __launch_bounds__(1024) k_pencil(PencilArgs a) {
   const int kx0 = (blockIdx.x - ky * a.nblk_x) * a.bx;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int bx = a.bx, pz = a.pz, nz = a.nz, nx = a.nx, ny = a.ny;
+  const int LS = 3 * bx;
   const int lbx = ilog2i(bx);
+  const int lnz = ilog2i(nz);
   T* w = vref<T>(a.w, b);
-  const long long nxny = (long long)nx * ny;
   const int nload = 3 * pz * bx;
   for (int i = tid; i < nload; i += nthr) {
-    int kxl = i & (bx - 1);
-    int rest = i >> lbx;
-    int z = rest & (pz - 1);
-    int c = rest >> a.log2pz;
+    const int kxl = i & (bx - 1);
+    const int rest = i >> lbx;
+    const int c = rest % 3;
+    const int z = rest / 3;
     T v = cmake<T>(0.0, 0.0);
     if (z < nz) v = w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl];
-    lds[(c * bx + kxl) * a.pitch + z] = v;
+    lds[z * LS + c * bx + kxl] = v;
   }
-  const int lnz = ilog2i(nz);
   const double* tab = a.tab + (long long)b * a.tab_stride;
   TabLayout L{nx, ny};
   // Layered-stack response of this block's orders (monolithic coupling):
   // E_up,q = T_R (i dz / 2 beta) P- sum_k exp(i beta z_k) f_q(z_k) / (Nx Ny), added
   // back as E_up,q exp(i beta z_k) on every plane. The transposed operator uses the
   // negated order and the transposed 3x3 block.
-  T* ph = lds + 3 * bx * a.pitch;                                            // [bx][nz]
-  double2* eup = reinterpret_cast<double2*>(lds + ((3 * bx * a.pitch + bx * nz + 1) & ~1));  // [bx][3]
+  constexpr int CH = 4;  // z-chunks of the readout sums
+  const int nch = nz < CH ? nz : CH;
+  const int zc = nz / nch;
+  T* ph = lds + pz * LS;                                                      // [nz][bx]
+  const size_t off_e = ((size_t)(pz * LS + nz * bx) * sizeof(T) + 15) / 16;   // in double2
+  double2* eup = smem_d + off_e;                                              // [bx][3]
+  double2* part = eup + 3 * bx;                                               // [nch][3 bx]
   if (a.reflect) {
     const double2* tb = reinterpret_cast<const double2*>(tab + L.off_beta());
     const double dz = tab[TS_DZ];
-    for (int i = tid; i < bx * nz; i += nthr) {
-      const int kxl = i >> lnz, z = i & (nz - 1);
+    // phases by chunks: exp(i beta z_k) = exp(i beta z_k0) exp(i beta dz)^(k - k0)
+    if (tid < bx * nch) {
+      const int kxl = tid % bx, ch = tid / bx;
       int mq = kx0 + kxl, nq = ky;
       if (a.transpose) { mq = (nx - mq) & (nx - 1); nq = (ny - nq) & (ny - 1); }
       const double2 bq = tb[nq * nx + mq];
-      const double zk = (z + 0.5) * dz;
-      ph[i] = from_d<T>(cexp_i(make_double2(bq.x * zk, bq.y * zk)));
+      const int z0 = ch * zc;
+      const double zk = (z0 + 0.5) * dz;
+      double2 p0 = cexp_i(make_double2(bq.x * zk, bq.y * zk));
+      const double2 st = cexp_i(make_double2(bq.x * dz, bq.y * dz));
+      for (int z = z0; z < z0 + zc; ++z) {
+        ph[z * bx + kxl] = from_d<T>(p0);
+        p0 = cmul(p0, st);
+      }
     }
     __syncthreads();
-    if (tid < 3 * bx) {
-      const int c = tid / bx, kxl = tid - c * bx;
+    if (tid < LS * nch) {
+      const int sq = tid % LS, ch = tid / LS;
+      const int kxl = sq & (bx - 1);
       double2 acc = make_double2(0, 0);
-      for (int z = 0; z < nz; ++z)
-        acc = cadd(acc, cmul(to_d(ph[kxl * nz + z]), to_d(lds[(c * bx + kxl) * a.pitch + z])));
-      eup[kxl * 3 + c] = acc;
+      for (int z = ch * zc; z < (ch + 1) * zc; ++z)
+        acc = cadd(acc, cmul(to_d(ph[z * bx + kxl]), to_d(lds[z * LS + sq])));
+      part[ch * LS + sq] = acc;
     }
     __syncthreads();
     if (tid < bx) {
@@ -224,7 +240,11 @@ __global__ void __launch_bounds__(1024) k_pencil(PencilArgs a) {
         const double2 km[3] = {make_double2(tab[L.off_kx() + mq], 0), make_double2(tab[L.off_ky() + nq], 0),
                                make_double2(-bq.x, -bq.y)};
         const double2* tr = reinterpret_cast<const double2*>(tab + L.off_tr()) + 9LL * q;
-        double2 v[3] = {eup[kxl * 3], eup[kxl * 3 + 1], eup[kxl * 3 + 2]};
+        double2 v[3];
+        for (int c = 0; c < 3; ++c) {
+          v[c] = make_double2(0, 0);
+          for (int ch = 0; ch < nch; ++ch) v[c] = cadd(v[c], part[ch * LS + c * bx + kxl]);
+        }
         double2 t[3];
         if (!a.transpose) {
           // P- v then T_R
@@ -240,12 +260,12 @@ __global__ void __launch_bounds__(1024) k_pencil(PencilArgs a) {
           for (int c = 0; c < 3; ++c) o[c] = cmul(fac, csub(t[c], cscale(cmul(km[c], d), 1.0 / (kbg * kbg))));
         }
       }
-      for (int c = 0; c < 3; ++c) eup[kxl * 3 + c] = o[c];  // own entries only: no cross-thread hazard
+      for (int c = 0; c < 3; ++c) eup[kxl * 3 + c] = o[c];
     }
   }
   __syncthreads();
   const T* tw = reinterpret_cast<const T*>(a.tw);
-  lds_fft<T, false>(lds, a.log2pz, 3 * bx, a.pitch, 1, tw, tid, nthr);
+  lds_fft<T, false, true>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
 
   const double kbg = tab[TS_KBG], Lw = tab[TS_L], kap_u = tab[TS_KAPPA], scale = tab[TS_SCALE];
   const double ik2 = 1.0 / (kbg * kbg);
@@ -256,17 +276,17 @@ __global__ void __launch_bounds__(1024) k_pencil(PencilArgs a) {
   const double* tkeep = tab + L.off_keep();
   const int npt = bx * pz;
   for (int pt = tid; pt < npt; pt += nthr) {
-    int kxl = pt >> a.log2pz;
-    int l = pt & (pz - 1);
+    const int kxl = pt & (bx - 1);
+    const int l = pt >> lbx;
     int m = kx0 + kxl, n = ky;
     int ls = (l < pz / 2) ? l : l - pz;
     const bool nyqz = (ls == -pz / 2);
     int mq = m, nq = n, lq = ls;
     if (a.transpose) { mq = (nx - m) & (nx - 1); nq = (ny - n) & (ny - 1); lq = -ls; }
     int q = nq * nx + mq;
-    T* p0 = lds + (0 * bx + kxl) * a.pitch + l;
-    T* p1 = lds + (1 * bx + kxl) * a.pitch + l;
-    T* p2 = lds + (2 * bx + kxl) * a.pitch + l;
+    T* p0 = lds + l * LS + 0 * bx + kxl;
+    T* p1 = p0 + bx;
+    T* p2 = p0 + 2 * bx;
     if (tkeep[q] == 0.0) {
       *p0 = cmake<T>(0, 0); *p1 = cmake<T>(0, 0); *p2 = cmake<T>(0, 0);
       continue;
@@ -297,17 +317,18 @@ __global__ void __launch_bounds__(1024) k_pencil(PencilArgs a) {
     *p2 = csub(cmul(g, o2), cmul(tz, v2));
   }
   __syncthreads();
-  lds_fft<T, true>(lds, a.log2pz, 3 * bx, a.pitch, 1, tw, tid, nthr);
+  lds_fft<T, true, true>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
   const int nst = 3 * nz * bx;
   for (int i = tid; i < nst; i += nthr) {
-    int kxl = i & (bx - 1);
-    int rest = i >> lbx;
-    int z = rest & (nz - 1);
-    int c = rest >> lnz;
-    T v = lds[(c * bx + kxl) * a.pitch + z];
-    if (a.reflect) v = cadd(v, from_d<T>(cmul(eup[kxl * 3 + c], to_d(ph[kxl * nz + z]))));
+    const int kxl = i & (bx - 1);
+    const int rest = i >> lbx;
+    const int c = rest % 3;
+    const int z = rest / 3;
+    T v = lds[z * LS + c * bx + kxl];
+    if (a.reflect) v = cadd(v, from_d<T>(cmul(eup[kxl * 3 + c], to_d(ph[z * bx + kxl]))));
     w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl] = v;
   }
+  (void)lnz;
 }
 
 template <class T>

@@ -39,7 +39,7 @@ struct PencilArgs {
   const int* active;
 };
 
-struct TileShape { int tx, ty, do_x, do_y, nthr; size_t lds; };
+struct TileShape { int tx, ty, do_x, do_y, nthr; size_t lds; int pitch; };
 
 template <class T, bool INV, int LD, int ST>
 void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t lds, hipStream_t s);
