@@ -59,10 +59,12 @@ class Plan:
         h = C.c_void_p()
         L.check(L.lib().psfd_plan_create(C.byref(self._cp), C.byref(self._opts), C.byref(h)), "psfd_plan_create")
         self._h = h
+        # held here so that a plan collected at interpreter exit can still be freed
+        self._destroy = L.lib().psfd_plan_destroy
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
-            L.lib().psfd_plan_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
     __del__ = close
@@ -191,8 +193,9 @@ class Server:
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
-            L.check(L.lib().psfd_server_destroy(self._h), "psfd_server_destroy")
-            self._h = None
+            h, self._h = self._h, None
+            if L is not None:
+                L.check(L.lib().psfd_server_destroy(h), "psfd_server_destroy")
 
     __del__ = close
 

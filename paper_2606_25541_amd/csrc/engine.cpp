@@ -226,14 +226,13 @@ static int env_int(const char* name, int dflt) {
 // complex values per thread of an LDS FFT pass (see FftBudget)
 static int fft_elems(size_t esz) { return esz == 8 ? 16 : 8; }
 
-// LDS row pitch of a transverse tile: consecutive rows start 8 (FP32) or 4 (FP64)
-// elements apart modulo the 256-byte bank period, so a radix-16 or radix-8 pass
-// over rows or columns hits each bank at most twice per wavefront access.
+// LDS row pitch of a transverse tile. The LDS serves a 64-bit access 16 lanes at a
+// time (a 128-bit one 8 lanes at a time); an odd pitch puts the 16 (8) rows that a
+// column pass touches at the same column into distinct banks, and row passes read
+// consecutive words, so neither pass conflicts.
 static int tile_pitch(int tx, size_t esz) {
-  const int period = (int)(256 / esz);       // elements per bank period
-  const int want = esz == 8 ? 8 : 4;
-  if (tx < period) return tx + 1;
-  return tx + want;
+  (void)esz;
+  return tx + 1;
 }
 static int ceil64(int v) { return (v + 63) / 64 * 64; }
 
@@ -257,21 +256,21 @@ XYCfg xy_config(const Shape& sh, size_t esz) {
 }
 
 // LDS of a pencil block: interleaved pencil data (pz x 3 bx), per-plane phases
-// (nz x bx), the per-order layered response (bx x 3) and the readout partial
-// sums (4 chunks x 3 bx), the last two in FP64.
+// (nz x bx), the per-order layered response (bx x 3), the readout partial sums
+// (4 chunks x 3 bx) and the per-order kernel scalars (bx x 4), the last three in FP64.
 static size_t pencil_lds(const Shape& sh, int bx, size_t esz) {
   size_t d = (size_t)sh.pz * 3 * bx * esz + (size_t)sh.nz * bx * esz;
   d = (d + 15) / 16 * 16;
-  return d + (size_t)3 * bx * 16 + (size_t)4 * 3 * bx * 16;
+  return d + (size_t)3 * bx * 16 + (size_t)4 * 3 * bx * 16 + (size_t)4 * bx * 16;
 }
 
 ZCfg z_config(const Shape& sh, size_t esz) {
   ZCfg z{};
   int bx = std::min(sh.nx, env_int("PSFD_ZBX", 16));
-  while (bx > 1 && pencil_lds(sh, bx, esz) > 150 * 1024) bx >>= 1;
+  // pencil FFT passes take at most 8 values per thread and 768 threads per block
+  while (bx > 1 && (pencil_lds(sh, bx, esz) > 150 * 1024 || 3 * bx * sh.pz > 8 * 768)) bx >>= 1;
   z.bx = bx;
-  z.nthr = clampi(ceil64(3 * bx * sh.pz / 8), 64, 1024);
-  while (3 * bx * sh.pz > fft_elems(esz) * z.nthr && z.nthr < 1024) z.nthr += 64;
+  z.nthr = clampi(ceil64(3 * bx * sh.pz / 8), 64, 768);
   if (z.nthr < 4 * 3 * bx) z.nthr = ceil64(4 * 3 * bx);  // one thread per readout partial sum
   z.lds = pencil_lds(sh, bx, esz);
   return z;

@@ -66,10 +66,34 @@ template <class T, int R, bool INV> PSFD_D void dft_r(T* u) {
 // same butterfly index, the conflict-free mapping when sequences are
 // interleaved in LDS (sstride 1); otherwise consecutive threads take
 // consecutive butterflies of one sequence.
+// b / nseq through a float reciprocal (exact for b < 2^22 and nseq <= 4096)
 template <bool SF>
-PSFD_D void bfly_index(int b, int log2nr, int nseq, int& s, int& t) {
-  if (SF) { t = b / nseq; s = b - t * nseq; }
+PSFD_D void bfly_index(int b, int log2nr, int nseq, float inv_nseq, int& s, int& t) {
+  if (SF) { t = (int)(((float)b + 0.5f) * inv_nseq); s = b - t * nseq; }
   else { s = b >> log2nr; t = b & ((1 << log2nr) - 1); }
+}
+
+// twiddles w^j (j = 1..R-1) of one butterfly from w^1, w^2, w^4 (table reads) and
+// single products for the others, so each value carries at most one rounding
+// more than the table
+template <class T, int R, bool INV>
+PSFD_D void twiddle_apply(T* u, const T* __restrict__ tw, int step) {
+  if (R == 2) {
+    const T w1 = tw[step];
+    u[1] = INV ? cmulc(u[1], w1) : cmul(u[1], w1);
+  } else if (R == 4) {
+    const T w1 = tw[step], w2 = tw[2 * step];
+    const T w3 = cmul(w1, w2);
+    u[1] = INV ? cmulc(u[1], w1) : cmul(u[1], w1);
+    u[2] = INV ? cmulc(u[2], w2) : cmul(u[2], w2);
+    u[3] = INV ? cmulc(u[3], w3) : cmul(u[3], w3);
+  } else {
+    const T w1 = tw[step], w2 = tw[2 * step], w4 = tw[4 * step];
+    const T w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
+    const T w[8] = {w1, w1, w2, w3, w4, w5, w6, w7};
+#pragma unroll
+    for (int j = 1; j < 8; ++j) u[j] = INV ? cmulc(u[j], w[j]) : cmul(u[j], w[j]);
+  }
 }
 
 // Per-thread element budget of a pass (16 FP32 / 8 FP64 complex values) and the
@@ -80,21 +104,22 @@ template <class T> struct FftBudget {
   static constexpr int LRMAX = 3;
 };
 
-template <class T, int R, bool INV, bool SF>
+template <class T, int R, bool INV, bool SF, int E>
 __device__ __forceinline__ void stockham_pass(T* lds, int log2n, int log2p, int nseq, int sstride, int estride,
                               const T* __restrict__ tw, int tid, int nthr) {
-  constexpr int NB = FftBudget<T>::E / R;
+  constexpr int NB = E / R;
   constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
   const int log2nr = log2n - LR;
   const int nr = 1 << log2nr;
   const int nbt = nseq << log2nr;
+  const float inv_nseq = 1.0f / (float)nseq;
   T u[NB][R];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     int b = tid + i * nthr;
     if (b < nbt) {
       int s, t;
-      bfly_index<SF>(b, log2nr, nseq, s, t);
+      bfly_index<SF>(b, log2nr, nseq, inv_nseq, s, t);
       const T* base = lds + s * sstride;
 #pragma unroll
       for (int j = 0; j < R; ++j) u[i][j] = base[(t + j * nr) * estride];
@@ -108,14 +133,10 @@ __device__ __forceinline__ void stockham_pass(T* lds, int log2n, int log2p, int 
     int b = tid + i * nthr;
     if (b < nbt) {
       int s, t;
-      bfly_index<SF>(b, log2nr, nseq, s, t);
+      bfly_index<SF>(b, log2nr, nseq, inv_nseq, s, t);
       int k = t & (p - 1);
       int step = k << tsh;
-#pragma unroll
-      for (int j = 1; j < R; ++j) {
-        T w = tw[j * step];
-        u[i][j] = INV ? cmulc(u[i][j], w) : cmul(u[i][j], w);
-      }
+      if (k != 0) twiddle_apply<T, R, INV>(u[i], tw, step);
       dft_r<T, R, INV>(u[i]);
       T* base = lds + s * sstride;
       int o = (t - k) * R + k;
@@ -128,7 +149,7 @@ __device__ __forceinline__ void stockham_pass(T* lds, int log2n, int log2p, int 
 
 // Full FFT of nseq sequences of length 2^log2n staged in LDS (unnormalised;
 // INV uses the +i sign). All threads of the workgroup must call it.
-template <class T, bool INV, bool SF = false>
+template <class T, bool INV, bool SF = false, int E = FftBudget<T>::E>
 __device__ __forceinline__ void lds_fft(T* lds, int log2n, int nseq, int sstride, int estride,
                         const T* __restrict__ tw_all, int tid, int nthr) {
   const T* tw = tw_all + (1 << log2n);
@@ -137,9 +158,9 @@ __device__ __forceinline__ void lds_fft(T* lds, int log2n, int nseq, int sstride
   while (rem > 0) {
     int lr = rem >= FftBudget<T>::LRMAX ? FftBudget<T>::LRMAX : rem;
     switch (lr) {
-      case 3: stockham_pass<T, 8, INV, SF>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
-      case 2: stockham_pass<T, 4, INV, SF>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
-      default: stockham_pass<T, 2, INV, SF>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
+      case 3: stockham_pass<T, 8, INV, SF, E>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
+      case 2: stockham_pass<T, 4, INV, SF, E>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
+      default: stockham_pass<T, 2, INV, SF, E>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
     }
     log2p += lr;
     rem -= lr;

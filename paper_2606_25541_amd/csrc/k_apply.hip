@@ -161,8 +161,10 @@ PSFD_D double2 window_factor(double2 beta, double2 eibl, double kap, double L, d
 // LDS layout of a pencil block: element z of sequence (c, kxl) at z * LS + c * bx + kxl
 // (sequences interleaved, LS = 3 bx), so every FFT pass, the kernel multiply and
 // the global load/store touch consecutive LDS words across a wavefront.
+// At most 8 values per thread in the pencil FFTs (the launch gives 3 bx pz / 8
+// threads, at most 768), which halves the register arrays of the FP32 passes.
 template <class T>
-__global__ void __launch_bounds__(1024) k_pencil(PencilArgs a) {
+__global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   extern __shared__ double2 smem_d[];
   T* lds = reinterpret_cast<T*>(smem_d);
   typedef typename real_of<T>::type R;
@@ -199,6 +201,17 @@ __global__ void __launch_bounds__(1024) k_pencil(PencilArgs a) {
   const size_t off_e = ((size_t)(pz * LS + nz * bx) * sizeof(T) + 15) / 16;   // in double2
   double2* eup = smem_d + off_e;                                              // [bx][3]
   double2* part = eup + 3 * bx;                                               // [nch][3 bx]
+  double2* ptab = part + 4 * 3 * bx;  // [bx][4]: beta, e^{i beta L}, (kx, ky) / k_bg, (keep, 0)
+  if (tid < bx) {
+    int mq = kx0 + tid, nq = ky;
+    if (a.transpose) { mq = (nx - mq) & (nx - 1); nq = (ny - nq) & (ny - 1); }
+    const int q = nq * nx + mq;
+    const double ikb = 1.0 / tab[TS_KBG];
+    ptab[tid * 4 + 0] = reinterpret_cast<const double2*>(tab + L.off_beta())[q];
+    ptab[tid * 4 + 1] = reinterpret_cast<const double2*>(tab + L.off_eibl())[q];
+    ptab[tid * 4 + 2] = make_double2(tab[L.off_kx() + mq] * ikb, tab[L.off_ky() + nq] * ikb);
+    ptab[tid * 4 + 3] = make_double2(tab[L.off_keep() + q], 0.0);
+  }
   if (a.reflect) {
     const double2* tb = reinterpret_cast<const double2*>(tab + L.off_beta());
     const double dz = tab[TS_DZ];
@@ -265,39 +278,32 @@ __global__ void __launch_bounds__(1024) k_pencil(PencilArgs a) {
   }
   __syncthreads();
   const T* tw = reinterpret_cast<const T*>(a.tw);
-  lds_fft<T, false, true>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
+  lds_fft<T, false, true, 8>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
 
   const double kbg = tab[TS_KBG], Lw = tab[TS_L], kap_u = tab[TS_KAPPA], scale = tab[TS_SCALE];
   const double ik2 = 1.0 / (kbg * kbg);
-  const double* tkx = tab + L.off_kx();
-  const double* tky = tab + L.off_ky();
-  const double2* tbeta = reinterpret_cast<const double2*>(tab + L.off_beta());
-  const double2* teibl = reinterpret_cast<const double2*>(tab + L.off_eibl());
-  const double* tkeep = tab + L.off_keep();
   const int npt = bx * pz;
   for (int pt = tid; pt < npt; pt += nthr) {
     const int kxl = pt & (bx - 1);
     const int l = pt >> lbx;
-    int m = kx0 + kxl, n = ky;
     int ls = (l < pz / 2) ? l : l - pz;
     const bool nyqz = (ls == -pz / 2);
-    int mq = m, nq = n, lq = ls;
-    if (a.transpose) { mq = (nx - m) & (nx - 1); nq = (ny - n) & (ny - 1); lq = -ls; }
-    int q = nq * nx + mq;
+    const int lq = a.transpose ? -ls : ls;
     T* p0 = lds + l * LS + 0 * bx + kxl;
     T* p1 = p0 + bx;
     T* p2 = p0 + 2 * bx;
-    if (tkeep[q] == 0.0) {
+    const double2* pt4 = ptab + kxl * 4;
+    if (pt4[3].x == 0.0) {
       *p0 = cmake<T>(0, 0); *p1 = cmake<T>(0, 0); *p2 = cmake<T>(0, 0);
       continue;
     }
     const double kap = kap_u * lq;
     const double s = (lq & 1) ? -1.0 : 1.0;
-    double2 e = teibl[q];
-    double2 F = window_factor(tbeta[q], e, kap, Lw, s);
+    const double2 e = pt4[1];
+    const double2 F = window_factor(pt4[0], e, kap, Lw, s);
     T g = from_d<T>(cscale(F, scale));
     T tz = from_d<T>(make_double2(s * e.x * scale * ik2, s * e.y * scale * ik2));
-    const R kxk = (R)(tkx[mq] / kbg), kyk = (R)(tky[nq] / kbg), kzk = (R)(kap / kbg);
+    const R kxk = (R)pt4[2].x, kyk = (R)pt4[2].y, kzk = (R)(kap / kbg);
     T v0 = *p0, v1 = *p1, v2 = *p2;
     T dxy; dxy.x = kxk * v0.x + kyk * v1.x; dxy.y = kxk * v0.y + kyk * v1.y;
     T o0, o1, o2;
@@ -317,7 +323,7 @@ __global__ void __launch_bounds__(1024) k_pencil(PencilArgs a) {
     *p2 = csub(cmul(g, o2), cmul(tz, v2));
   }
   __syncthreads();
-  lds_fft<T, true, true>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
+  lds_fft<T, true, true, 8>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
   const int nst = 3 * nz * bx;
   for (int i = tid; i < nst; i += nthr) {
     const int kxl = i & (bx - 1);
