@@ -1,23 +1,38 @@
 """Benchmark: solves/s of the background-field LS solver on one MI355X.
 
 A step is one full solve of the hot path (layered-stack tables, background
-source, outer reflection loop, GMRES on eq. (18) with the operator apply,
-readouts) of the 128 x 128 x 64 contact-hole clip (256 nm, 8 holes, 20-40 nm,
-60 nm absorber n = 0.95 + 0.031i on 40 Mo/Si pairs, TE, 6 deg) to a relative
-residual of 1e-6, mixed precision (FP32 Arnoldi cycles, FP64 residual,
-solution and reflection). Inputs are resident in HBM before timing starts.
+source, monolithic coupling of the multilayer response, GMRES on eq. (18) with
+the operator apply, readouts) of the 128 x 128 x 64 contact-hole clip (256 nm,
+8 holes, 20-40 nm, 60 nm absorber n = 0.95 + 0.031i on 40 Mo/Si pairs, TE,
+6 deg) to a relative residual of 1e-6, mixed precision (FP32 Arnoldi cycles,
+FP64 residual, solution and reflection). Inputs are resident in HBM before
+timing starts.
 
-Printed JSON line: the driver's contract plus operator applies/s, the FP64
-solve rate, the TM solve, the field error of the mixed result against the
-FP64 GPU solve, the roofline of the dominant apply kernel (live HIP-event
-timing) and the CPU oracle timed on a bounded sample.
+Printed JSON line: the solve rate, plus
+  fp64 / tm_mixed   the plain FP64 solve and the TM solve of the same clip,
+                    field errors against a tight FP64 solve;
+  apply             operator applies/s and per-stage bandwidth (HIP events on
+                    the library's stream), with the roofline of the dominant
+                    kernel and its measured HBM traffic where the stored
+                    counter summary matches the current kernel sources;
+  batched           64 instances (pupil angles x {64x64x32, 128x128x64}
+                    Manhattan clips) in lock-step batched solves, against the
+                    same instances solved one by one;
+  serving           Poisson arrivals over {64x64x32, 128x128x64, 256x256x64}
+                    at 0.7 of the saturated rate: p50 / p99 latency, solves/s;
+  adjoint           forward + adjoint gradient on a 256x256x64 smooth clip;
+  cpu_baseline      the CPU oracle on a bounded sample of the headline solve.
+
+--only SECTION runs one section (profiling); --quick runs the headline only.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -25,6 +40,336 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SECTIONS = ("solve", "fp64", "apply", "batched", "serving", "adjoint", "cpu")
+# sources that decide the code of the apply kernels (hashed into the counter summary)
+KERNEL_SOURCES = ("common.hpp", "layout.hpp", "kernels.hpp", "fft_lds.hpp", "k_apply.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "apply_G3_fp32_hbm_traffic.md")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2606_25541_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(stage: int):
+    """HBM bytes per launch of an apply stage from the committed counter summary.
+
+    None when the summary is missing or was taken on other kernel sources.
+    """
+    try:
+        txt = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel source hash: `([0-9a-f]+)`", txt)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(r"traffic stage %d: (\d+) bytes" % stage, txt)
+    return int(m.group(1)) if m else None
+
+
+def timed(fn, n):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = None
+    for _ in range(n):
+        r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / n, r
+
+
+def sec_solve(ctx, args, out):
+    api, torch = ctx["api"], ctx["torch"]
+    prob, deps = ctx["prob"], ctx["deps"]
+    plan = api.Plan(prob, rtol=1e-6, precision="mixed", restart=args.restart, max_iters=20000, max_outer=200)
+    em = torch.empty((3, prob.nz, prob.ny, prob.nx), dtype=torch.complex128, device=ctx["dev"])
+    orders = torch.empty((prob.ny, prob.nx, 3), dtype=torch.complex128, device=ctx["dev"])
+    log("bench: warmup", args.warmup)
+    for _ in range(args.warmup):
+        plan.psfd_solve(deps, em, orders)
+    log("bench: timed", args.steps, "steps")
+    dt, (_, _, info) = timed(lambda: plan.psfd_solve(deps, em, orders), args.steps)
+    log("bench: mixed", info)
+    out.update({
+        "value": 1.0 / dt, "ms_per_step": 1e3 * dt,
+        "mixed": {"iters": info["iters"], "outer_iters": info["outer_iters"], "cycles": info["cycles"],
+                  "rel_residual": info["rel_residual"], "mono_residual": info["mono_residual"]},
+    })
+    ctx["plan"], ctx["em_mixed"], ctx["t_mixed"] = plan, em, dt
+
+
+def sec_fp64(ctx, args, out):
+    api, torch = ctx["api"], ctx["torch"]
+    prob, deps = ctx["prob"], ctx["deps"]
+    em = torch.empty((3, prob.nz, prob.ny, prob.nx), dtype=torch.complex128, device=ctx["dev"])
+    orders = torch.empty((prob.ny, prob.nx, 3), dtype=torch.complex128, device=ctx["dev"])
+    plan64 = api.Plan(prob, rtol=1e-6, precision="fp64", restart=args.restart, max_iters=20000, max_outer=200)
+    plan64.psfd_solve(deps, em, orders)
+    t64, (_, _, i64) = timed(lambda: plan64.psfd_solve(deps, em, orders), max(1, args.steps // 2))
+    log("bench: fp64", i64)
+    # tight FP64 reference for the field error of both results
+    planref = api.Plan(prob, rtol=1e-10, precision="fp64", restart=args.restart, max_iters=40000, max_outer=400)
+    emr = torch.empty_like(em)
+    planref.psfd_solve(deps, emr, orders)
+    torch.cuda.synchronize()
+    nr = torch.linalg.vector_norm(emr).item()
+    out["fp64"] = {"solves_per_s": 1.0 / t64, "ms_per_solve": 1e3 * t64, "iters": i64["iters"],
+                   "outer_iters": i64["outer_iters"], "mono_residual": i64["mono_residual"],
+                   "field_err_vs_fp64_1e-10": torch.linalg.vector_norm(em - emr).item() / nr}
+    if "em_mixed" in ctx:
+        out["mixed"]["field_err_vs_fp64_1e-10"] = torch.linalg.vector_norm(ctx["em_mixed"] - emr).item() / nr
+        out["mixed_over_fp64"] = t64 / ctx["t_mixed"]
+    # the mixed solve to the tolerance that brings its field error to 1e-6
+    plant = api.Plan(prob, rtol=3e-7, precision="mixed", restart=args.restart, max_iters=20000, max_outer=200)
+    emt = torch.empty_like(em)
+    plant.psfd_solve(deps, emt, orders)
+    tt, (_, _, it) = timed(lambda: plant.psfd_solve(deps, emt, orders), max(1, args.steps // 2))
+    out["mixed_rtol_3e-7"] = {"ms_per_solve": 1e3 * tt, "iters": it["iters"],
+                              "field_err_vs_fp64_1e-10": torch.linalg.vector_norm(emt - emr).item() / nr}
+    # TM
+    prob_tm = ctx["clips"].config_problem("G3", pol=ctx["clips"].TM)
+    plantm = api.Plan(prob_tm, rtol=1e-6, precision="mixed", restart=args.restart, max_iters=20000, max_outer=200)
+    plantm.psfd_solve(deps, em, orders)
+    ttm, (_, _, itm) = timed(lambda: plantm.psfd_solve(deps, em, orders), 1)
+    out["tm_mixed"] = {"ms_per_solve": 1e3 * ttm, "iters": itm["iters"], "outer_iters": itm["outer_iters"],
+                       "mono_residual": itm["mono_residual"]}
+
+
+def sec_apply(ctx, args, out):
+    """Operator applies/s and per-stage bandwidth, timed with HIP events on the launch stream."""
+    import ctypes as C
+    api, torch, clips, _lib = ctx["api"], ctx["torch"], ctx["clips"], ctx["_lib"]
+    prob, deps, dev = ctx["prob"], ctx["deps"], ctx["dev"]
+    N = prob.nx * prob.ny * prob.nz
+    plan = ctx.get("plan") or api.Plan(prob, rtol=1e-6, precision="mixed", restart=args.restart)
+    L = _lib.lib()
+    stream = torch.cuda.current_stream()
+    x = torch.from_numpy(clips.random_complex((3, prob.nz, prob.ny, prob.nx), 7)).to(dev)
+    reps = 20 if args.only == "apply" else 200
+    res = {}
+    for name, dt_, code, esz in (("fp32", torch.complex64, _lib.PSFD_C64, 8),
+                                 ("fp64", torch.complex128, _lib.PSFD_C128, 16)):
+        xx, dd = x.to(dt_), deps.to(dt_)
+        y = torch.empty_like(xx)
+        for _ in range(3):
+            plan.psfd_apply(dd, xx, y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.psfd_apply(dd, xx, y)
+        e1.record(stream)
+        e1.synchronize()
+        t_apply = e0.elapsed_time(e1) / reps * 1e-3
+        # algorithmic bytes per voxel (esz = bytes per complex value): stage 0 reads x (3 esz) and
+        # delta_eps (esz), writes w (3 esz); stage 1 reads and writes w; stage 2 reads w and x, writes y
+        per_vox = {0: 7 * esz, 1: 6 * esz, 2: 9 * esz}
+        stages = {}
+        for st in (0, 1, 2):
+            ms = C.c_float()
+            _lib.check(L.psfd_bench_stage(plan._h, st, C.c_void_p(dd.data_ptr()), C.c_void_p(xx.data_ptr()),
+                                          C.c_void_p(y.data_ptr()), code, reps, C.byref(ms),
+                                          C.c_void_p(stream.cuda_stream)), "psfd_bench_stage")
+            t = ms.value * 1e-3
+            stages[st] = {"us": 1e3 * ms.value, "bytes": per_vox[st] * N, "gbs": per_vox[st] * N / t / 1e9}
+        b_apply = 22 * esz * N
+        res[name] = {"applies_per_s": 1.0 / t_apply, "us_per_apply": 1e6 * t_apply, "apply_bytes": b_apply,
+                     "apply_gbs": b_apply / t_apply / 1e9, "apply_frac_hbm": b_apply / t_apply / 1e9 / HBM_PEAK_GBS,
+                     "stages": stages}
+    out["apply"] = res
+    st32 = res["fp32"]["stages"]
+    dom = max(st32, key=lambda k: st32[k]["us"])
+    names = {0: "k_tile<float2,fwd,V*x> (transverse FFT forward)", 1: "k_pencil<float2> (z FFT, dyadic kernel)",
+             2: "k_tile<float2,inv,axpby> (transverse FFT inverse)"}
+    out["roofline"] = {"bound": "hbm", "kernel": names[dom], "achieved": st32[dom]["gbs"], "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": st32[dom]["gbs"] / HBM_PEAK_GBS, "traffic": stored_traffic(dom),
+                       "bytes_per_launch": st32[dom]["bytes"], "us_per_launch": st32[dom]["us"],
+                       "kernel_source_hash": kernel_source_hash()}
+    if args.only == "apply":
+        # plain copy of known size: the scale of the FETCH_SIZE / WRITE_SIZE counters
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_bytes"] = a.numel() * 4
+
+
+def _manhattan_set(clips, grid_seq, seed0, angles, rng):
+    """(grid, problem, delta_eps) triples: given grids, a pupil angle each (seeded), Manhattan clips."""
+    items = []
+    for i, g in enumerate(grid_seq):
+        th, ph = angles[int(rng.integers(len(angles))) if rng is not None else (7 * i) % len(angles)]
+        p = clips.config_problem(g, theta_deg=th, phi_deg=ph)
+        d = clips.manhattan(p.nx, p.ny, p.nz, p.lx_nm, p.ly_nm, seed=seed0 + i)
+        items.append((g, p, d))
+    return items
+
+
+def sec_batched(ctx, args, out):
+    """64 instances over pupil angles and two grids: batched lock-step solves vs one by one."""
+    import numpy as np
+    api, torch, clips, dev = ctx["api"], ctx["torch"], ctx["clips"], ctx["dev"]
+    rng = np.random.default_rng(3000)
+    items = _manhattan_set(clips, ["G2", "G3"] * 32, 3000, clips.pupil_angles(), rng)
+    opts = dict(rtol=1e-6, precision="mixed", restart=args.restart, max_iters=20000)
+    groups = {}
+    for g, p, d in items:
+        groups.setdefault(g, []).append((p, torch.from_numpy(d).to(dev)))
+    # warm-up of both shapes
+    for g, lst in groups.items():
+        api.psfd_solve_batch([lst[0][0]], [lst[0][1]], **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = {}
+    for g, lst in groups.items():
+        _, _, infos = api.psfd_solve_batch([p for p, _ in lst], [d for _, d in lst], **opts)
+        iters[g] = [i["iters"] for i in infos]
+        assert all(i["status"] == 0 for i in infos), infos
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    # the same instances one by one (plans built and their workspaces allocated before timing)
+    plans = [(api.Plan(p, **opts), d) for lst in groups.values() for p, d in lst]
+    for pl, d in plans:
+        pl.psfd_solve(d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pl, d in plans:
+        pl.psfd_solve(d)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    del plans
+    out["batched"] = {"instances": len(items), "per_grid": {g: len(v) for g, v in groups.items()},
+                      "solves_per_s": len(items) / t_batch, "sequential_solves_per_s": len(items) / t_seq,
+                      "speedup_vs_sequential": t_seq / t_batch,
+                      "iters_mean": {g: float(np.mean(v)) for g, v in iters.items()},
+                      "iters_max": {g: int(np.max(v)) for g, v in iters.items()}}
+    log("bench: batched", out["batched"])
+
+
+def sec_serving(ctx, args, out):
+    """Poisson arrivals over three grids at 0.7 of the saturated rate; p50/p99 latency."""
+    import numpy as np
+    api, torch, clips, dev = ctx["api"], ctx["torch"], ctx["clips"], ctx["dev"]
+    grids = ("G2", "G3", "G4")
+    opts = dict(rtol=1e-6, precision="mixed", restart=args.restart, max_iters=20000)
+    rng = np.random.default_rng(4000)
+    pool = _manhattan_set(clips, list(grids) * 4, 4000, clips.pupil_angles(), None)
+    pool = [(g, p, torch.from_numpy(d).to(dev)) for g, p, d in pool]
+
+    def outputs(p):
+        return (torch.empty((3, p.nz, p.ny, p.nx), dtype=torch.complex128, device=dev),
+                torch.empty((p.ny, p.nx, 3), dtype=torch.complex128, device=dev))
+
+    srv = api.Server(hbm_budget=96 << 30, max_slots=8, **opts)
+
+    def drain(tickets, deadline):
+        lat = {}
+        while len(lat) < len(tickets) and time.perf_counter() < deadline:
+            for t in tickets:
+                if t not in lat:
+                    done, info, l = srv.poll(t)
+                    if done:
+                        assert info["status"] == 0, info
+                        lat[t] = (l, time.perf_counter())
+            time.sleep(0.0005)
+        return lat
+
+    # warm-up: one request per grid allocates the slot groups
+    warm = [srv.submit(p, d, *outputs(p)) for g, p, d in pool[:3]]
+    drain(warm, time.perf_counter() + 120)
+    # saturated rate: a burst of requests all at once
+    burst = [pool[int(rng.integers(len(pool)))] for _ in range(args.serve_burst)]
+    bufs = [outputs(p) for _, p, _ in burst]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ts = [srv.submit(p, d, *b) for (_, p, d), b in zip(burst, bufs)]
+    lat = drain(ts, t0 + 300)
+    t_sat = max(v[1] for v in lat.values()) - t0
+    sat = len(ts) / t_sat
+    log("bench: serving saturated %.2f solves/s" % sat)
+    # Poisson stream at 0.7 S
+    qps = 0.7 * sat
+    reqs = [pool[int(rng.integers(len(pool)))] for _ in range(args.serve_requests)]
+    gaps = rng.exponential(1.0 / qps, size=len(reqs))
+    bufs = [outputs(p) for _, p, _ in reqs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_next = t0
+    tickets, kinds = [], []
+    for (g, p, d), b, gap in zip(reqs, bufs, gaps):
+        t_next += gap
+        while time.perf_counter() < t_next:
+            time.sleep(0.0002)
+        tickets.append(srv.submit(p, d, *b))
+        kinds.append(g)
+    lat = drain(tickets, time.perf_counter() + 600)
+    t_end = max(v[1] for v in lat.values())
+    srv.close()
+    ls = np.array([lat[t][0] for t in tickets])
+    per = {g: np.array([lat[t][0] for t, k in zip(tickets, kinds) if k == g]) for g in grids}
+    out["serving"] = {"requests": len(tickets), "saturated_solves_per_s": sat, "qps": qps,
+                      "solves_per_s": len(tickets) / (t_end - t0),
+                      "p50_ms": 1e3 * float(np.percentile(ls, 50)), "p99_ms": 1e3 * float(np.percentile(ls, 99)),
+                      "per_grid_p50_ms": {g: 1e3 * float(np.percentile(v, 50)) for g, v in per.items() if len(v)},
+                      "per_grid_p99_ms": {g: 1e3 * float(np.percentile(v, 99)) for g, v in per.items() if len(v)}}
+    # the plain FP64 GPU solve of one request per grid, for comparison
+    fp64 = {}
+    for g, p, d in pool[:3]:
+        pl = api.Plan(p, rtol=1e-6, precision="fp64", restart=args.restart, max_iters=20000)
+        pl.psfd_solve(d)
+        t, _ = timed(lambda: pl.psfd_solve(d), 1)
+        fp64[g] = 1e3 * t
+        del pl
+    out["serving"]["fp64_single_solve_ms"] = fp64
+    log("bench: serving", out["serving"])
+
+
+def sec_adjoint(ctx, args, out):
+    """Forward + adjoint gradient of the 0 and +-1 order intensities on a 256x256x64 smooth clip."""
+    api, torch, clips, dev = ctx["api"], ctx["torch"], ctx["clips"], ctx["dev"]
+    p = clips.config_problem("G4")
+    de, _ = clips.smooth_density_eps(p.nx, p.ny, p.nz, p.lx_nm, p.ly_nm, p.t_nm, seed=5001)
+    d = torch.from_numpy(de).to(dev)
+    orders = [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)]
+    plan = api.Plan(p, rtol=1e-6, precision="mixed", restart=args.restart, max_iters=20000)
+    plan.psfd_solve_adjoint(d, orders)
+    t, (g, J, fi, ai) = timed(lambda: plan.psfd_solve_adjoint(d, orders), 1)
+    out["adjoint"] = {"grid": [p.nx, p.ny, p.nz], "ms_forward_plus_adjoint": 1e3 * t, "J": J,
+                      "forward_iters": fi["iters"], "adjoint_iters": ai["iters"],
+                      "grad_finite": bool(torch.isfinite(torch.view_as_real(g)).all().item())}
+    log("bench: adjoint", out["adjoint"])
+
+
+def sec_cpu(ctx, args, out):
+    import oracle as O
+    clips, prob, deps_np = ctx["clips"], ctx["prob"], ctx["deps_np"]
+    ncores = os.cpu_count() or 1
+    O.set_workers(ncores)
+    t0 = time.perf_counter()
+    S = O.Setup(prob)
+    _ = S.G
+    t_setup = time.perf_counter() - t0
+    V = O.potential(S, deps_np)
+    e = O.background_field(S)
+    rhs = O.conv_K(S, V[None] * e)
+    k = 8
+    t0 = time.perf_counter()
+    O.gmres(lambda v: O.apply_A(S, deps_np, v), rhs, None, 1e-30, args.restart, k)
+    t_it = (time.perf_counter() - t0) / k
+    its = out.get("mixed", {}).get("iters", 269)
+    t_solve = t_setup + its * t_it
+    out["cpu_baseline"] = {"value": 1.0 / t_solve, "unit": "solves/s", "cores": ncores, "kind": "oracle",
+                           "sample": f"{k} FP64 GMRES({args.restart}) iterations of the same solve "
+                                     f"(scipy.fft workers={ncores}) plus table set-up, extrapolated to the "
+                                     f"{its} iterations the GPU solve takes; {t_it:.2f} s/iteration",
+                           "s_per_iteration": t_it}
 
 
 def main():
@@ -34,166 +379,45 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--quick", action="store_true", help="skip the FP64 / TM / apply extras")
+    ap.add_argument("--quick", action="store_true", help="headline solve only")
+    ap.add_argument("--only", choices=SECTIONS, default=None, help="run one section")
+    ap.add_argument("--serve-requests", type=int, default=90)
+    ap.add_argument("--serve-burst", type=int, default=24)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (no multi-GPU path)"}))
         sys.exit(2)
 
-    import ctypes as C
-    import numpy as np
     import torch
     from paper_2606_25541_amd import api, clips, _lib
 
     dev = torch.device("cuda:0")
     prob = clips.config_problem("G3", pol=clips.TE)
     deps_np = clips.contact_holes(128, 128, 64, 256.0, 256.0, 8, seed=2001)
-    deps = torch.from_numpy(deps_np).to(dev)
-    N = prob.nx * prob.ny * prob.nz
-    rtol = 1e-6
-    plan = api.Plan(prob, rtol=rtol, precision="mixed", restart=args.restart, max_iters=20000, max_outer=200)
-    em = torch.empty((3, prob.nz, prob.ny, prob.nx), dtype=torch.complex128, device=dev)
-    orders = torch.empty((prob.ny, prob.nx, 3), dtype=torch.complex128, device=dev)
-
-    def log(*a):
-        print(*a, file=sys.stderr, flush=True)
-
-    log("bench: warmup", args.warmup)
-    info = None
-    for _ in range(args.warmup):
-        _, _, info = plan.psfd_solve(deps, em, orders)
-    torch.cuda.synchronize()
-    log("bench: timed", args.steps, "steps")
-    t0 = time.perf_counter()
-    infos = []
-    for _ in range(args.steps):
-        _, _, info = plan.psfd_solve(deps, em, orders)
-        infos.append(info)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    solves_s = args.steps / dt
-    log("bench: mixed", info)
+    ctx = {"api": api, "torch": torch, "clips": clips, "_lib": _lib, "dev": dev, "prob": prob,
+           "deps_np": deps_np, "deps": torch.from_numpy(deps_np).to(dev)}
     out = {
         "metric": "solves/s at 1e-6 rel. residual (mixed vs FP64) + operator applies/s + p99",
-        "value": solves_s, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
+        "value": None, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "c64+c128 (mixed)", "data": "synthetic",
         "config": {"workload": "contact-hole clip 128x128x64, 256 nm, 8 holes 20-40 nm, 60 nm absorber, "
                                "40 Mo/Si pairs, TE 6 deg, rtol 1e-6, mixed FP32/FP64",
-                   "grid": [prob.nx, prob.ny, prob.nz], "restart": args.restart, "rtol": rtol,
+                   "grid": [prob.nx, prob.ny, prob.nz], "restart": args.restart, "rtol": 1e-6,
                    "parallelism": "single GPU"},
-        "mixed": {"iters": info["iters"], "outer_iters": info["outer_iters"], "cycles": info["cycles"],
-                  "rel_residual": info["rel_residual"], "mono_residual": info["mono_residual"]},
     }
-    em_mixed = em.clone()
-
-    if not args.quick:
-        # FP64 solve of the same clip
-        plan64 = api.Plan(prob, rtol=rtol, precision="fp64", restart=args.restart, max_iters=20000, max_outer=200)
-        em64 = torch.empty_like(em)
-        plan64.psfd_solve(deps, em64, orders)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        n64 = max(1, args.steps // 2)
-        for _ in range(n64):
-            _, _, i64 = plan64.psfd_solve(deps, em64, orders)
-        torch.cuda.synchronize()
-        t64 = (time.perf_counter() - t0) / n64
-        log("bench: fp64", i64)
-        # tight FP64 reference for the field error of both results
-        planref = api.Plan(prob, rtol=1e-10, precision="fp64", restart=args.restart, max_iters=40000,
-                           max_outer=400)
-        emr = torch.empty_like(em)
-        _, _, iref = planref.psfd_solve(deps, emr, orders)
-        torch.cuda.synchronize()
-        nr = torch.linalg.vector_norm(emr).item()
-        out["fp64"] = {"solves_per_s": 1.0 / t64, "ms_per_solve": 1e3 * t64, "iters": i64["iters"],
-                       "outer_iters": i64["outer_iters"], "mono_residual": i64["mono_residual"],
-                       "field_err_vs_fp64_1e-10": torch.linalg.vector_norm(em64 - emr).item() / nr}
-        out["mixed"]["field_err_vs_fp64_1e-10"] = torch.linalg.vector_norm(em_mixed - emr).item() / nr
-        out["mixed_over_fp64"] = solves_s * t64
-        # TM
-        prob_tm = clips.config_problem("G3", pol=clips.TM)
-        plantm = api.Plan(prob_tm, rtol=rtol, precision="mixed", restart=args.restart, max_iters=20000,
-                          max_outer=200)
-        plantm.psfd_solve(deps, em, orders)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, _, itm = plantm.psfd_solve(deps, em, orders)
-        torch.cuda.synchronize()
-        out["tm_mixed"] = {"ms_per_solve": 1e3 * (time.perf_counter() - t0), "iters": itm["iters"],
-                           "outer_iters": itm["outer_iters"], "mono_residual": itm["mono_residual"]}
-
-        # operator applies/s and per-stage roofline (live HIP events on the library's stream)
-        L = _lib.lib()
-        stream = torch.cuda.current_stream()
-        x = torch.from_numpy(clips.random_complex((3, prob.nz, prob.ny, prob.nx), 7)).to(dev)
-        res = {}
-        for name, dt_, code, esz in (("fp32", torch.complex64, _lib.PSFD_C64, 8),
-                                     ("fp64", torch.complex128, _lib.PSFD_C128, 16)):
-            xx = x.to(dt_)
-            dd = deps.to(dt_)
-            y = torch.empty_like(xx)
-            for _ in range(3):
-                plan.psfd_apply(dd, xx, y)
-            reps = 200
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
-                plan.psfd_apply(dd, xx, y)
-            e1.record(stream)
-            e1.synchronize()
-            t_apply = e0.elapsed_time(e1) / reps * 1e-3
-            # bytes per unit (voxel): stage 0 reads x, delta_eps, writes w; stage 1 reads and writes w;
-            # stage 2 reads w, x, writes y
-            per_vox = {0: 6 * esz + esz, 1: 6 * esz, 2: 9 * esz}
-            stages = {}
-            for st in (0, 1, 2):
-                ms = C.c_float()
-                _lib.check(L.psfd_bench_stage(plan._h, st, C.c_void_p(dd.data_ptr()), C.c_void_p(xx.data_ptr()),
-                                              C.c_void_p(y.data_ptr()), code, 100, C.byref(ms),
-                                              C.c_void_p(stream.cuda_stream)), "psfd_bench_stage")
-                t = ms.value * 1e-3
-                stages[st] = {"ms": ms.value, "bytes": per_vox[st] * N, "gbs": per_vox[st] * N / t / 1e9}
-            b_apply = 22 * esz * N
-            res[name] = {"applies_per_s": 1.0 / t_apply, "us_per_apply": 1e6 * t_apply,
-                         "apply_bytes": b_apply, "apply_gbs": b_apply / t_apply / 1e9,
-                         "apply_frac_hbm": b_apply / t_apply / 1e9 / HBM_PEAK_GBS, "stages": stages}
-        out["apply"] = res
-        st32 = res["fp32"]["stages"]
-        dom = max(st32, key=lambda k: st32[k]["ms"])
-        names = {0: "k_tile<float2,fwd,V*x> (transverse FFT forward)", 1: "k_pencil<float2> (z FFT, dyadic kernel)",
-                 2: "k_tile<float2,inv,axpby> (transverse FFT inverse)"}
-        out["roofline"] = {"bound": "hbm", "kernel": names[dom], "achieved": st32[dom]["gbs"],
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": st32[dom]["gbs"] / HBM_PEAK_GBS,
-                           "traffic": None, "bytes_per_launch": st32[dom]["bytes"],
-                           "us_per_launch": 1e3 * st32[dom]["ms"]}
-
-    if not args.no_cpu:
-        import oracle as O
-        ncores = os.cpu_count() or 1
-        O.set_workers(ncores)
-        t0 = time.perf_counter()
-        S = O.Setup(prob)
-        _ = S.G
-        t_setup = time.perf_counter() - t0
-        xs = clips.random_complex((3, prob.nz, prob.ny, prob.nx), 3)
-        V = O.potential(S, deps_np)
-        e = O.background_field(S)
-        rhs = O.conv_K(S, V[None] * e)
-        k = 8
-        t0 = time.perf_counter()
-        O.gmres(lambda v: O.apply_A(S, deps_np, v), rhs, None, 1e-30, args.restart, k)
-        t_it = (time.perf_counter() - t0) / k
-        its = out["mixed"]["iters"]
-        t_solve = t_setup + its * t_it
-        out["cpu_baseline"] = {"value": 1.0 / t_solve, "unit": "solves/s", "cores": ncores, "kind": "oracle",
-                               "sample": f"{k} FP64 GMRES({args.restart}) iterations of the same solve "
-                                         f"(scipy.fft workers={ncores}) plus table set-up, extrapolated to the "
-                                         f"{its} iterations the GPU solve takes; {t_it:.2f} s/iteration",
-                               "s_per_iteration": t_it}
-    print(json.dumps(out))
+    if args.only:
+        todo = [args.only]
+    elif args.quick:
+        todo = ["solve"]
+    else:
+        todo = [s for s in SECTIONS if s != "cpu" or not args.no_cpu]
+    fns = {"solve": sec_solve, "fp64": sec_fp64, "apply": sec_apply, "batched": sec_batched,
+           "serving": sec_serving, "adjoint": sec_adjoint, "cpu": sec_cpu}
+    for s in todo:
+        log("bench: section", s)
+        fns[s](ctx, args, out)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
