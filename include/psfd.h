@@ -144,6 +144,12 @@ int psfd_solve_adjoint(psfd_plan* plan, const void* d_deps, const int32_t* order
 int psfd_solve_batch(int32_t n, const psfd_problem* probs, const psfd_opts* opts, const void* const* d_deps,
                      void* const* d_emask, void* const* d_orders, psfd_info* info, void* stream);
 
+/* psfd_solve_batch keeps the device workspace of its last calls (at most 4, per
+ * device, shape, batch size, restart length and precision; least recently used
+ * freed first) and reuses it for the next call of the same kind. This frees
+ * every kept workspace; calls running in other threads keep theirs. */
+int psfd_release_cached_workspaces(void);
+
 /* Serving: continuous batching of solve requests admitted by device-memory
  * footprint. The server owns a worker thread and its own HIP stream.
  * hbm_budget: bytes the server may allocate for workspaces; max_slots: requests

@@ -65,6 +65,7 @@ EXPORTS = {
     "psfd_solve_batch": (C.c_int, [C.c_int32, C.POINTER(psfd_problem), C.POINTER(psfd_opts),
                                    C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                    C.POINTER(psfd_info), C.c_void_p]),
+    "psfd_release_cached_workspaces": (C.c_int, []),
     "psfd_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.POINTER(psfd_opts), C.POINTER(C.c_void_p)]),
     "psfd_server_submit": (C.c_int, [C.c_void_p, C.POINTER(psfd_problem), C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.POINTER(C.c_uint64)]),

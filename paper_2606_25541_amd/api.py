@@ -157,6 +157,11 @@ def psfd_solve_batch(probs: Sequence, deps: Sequence[torch.Tensor], **opts):
 solve_batch = psfd_solve_batch
 
 
+def psfd_release_cached_workspaces() -> None:
+    """Free the device workspaces psfd_solve_batch keeps for reuse."""
+    L.check(L.lib().psfd_release_cached_workspaces(), "psfd_release_cached_workspaces")
+
+
 class Server:
     """Continuous-batching solve server (own worker thread and stream)."""
 

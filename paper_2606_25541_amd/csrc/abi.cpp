@@ -92,8 +92,12 @@ static Status ensure_lite(psfd_plan* p, hipStream_t s) {
   if (e != hipSuccess) return hip_status(e, "hipMalloc");
   g->owned.push_back(t);
   g->tab = (double*)t;
-  e = hipMemcpyAsync(g->tab, p->tab.data(), p->tab.size() * 8, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return hip_status(e, "hipMemcpyAsync");
+  e = hipMalloc(&t, (LAYER_CAP + 2) * sizeof(double4));
+  if (e != hipSuccess) return hip_status(e, "hipMalloc");
+  g->owned.push_back(t);
+  g->lay = (double4*)t;
+  st = group_set_tables(*g, 0, p->pr, p->tab, s);
+  if (!st.ok()) return st;
   p->lite = std::move(g);
   return Status();
 }
@@ -178,7 +182,7 @@ static Status ensure_solve(psfd_plan* p, hipStream_t s) {
   auto g = std::make_unique<Group>();
   Status st = group_alloc(*g, p->sh, 1, p->o.restart, p->o.precision);
   if (!st.ok()) return st;
-  st = group_set_tables(*g, 0, p->tab, s);
+  st = group_set_tables(*g, 0, p->pr, p->tab, s);
   if (!st.ok()) return st;
   p->solve = std::move(g);
   return Status();
@@ -247,6 +251,11 @@ int psfd_solve_batch(int32_t n, const psfd_problem* probs, const psfd_opts* opts
   bool nc = false;
   for (int i = 0; info && i < n; ++i) nc |= info[i].status == PSFD_NOT_CONVERGED;
   return nc ? PSFD_NOT_CONVERGED : PSFD_OK;
+}
+
+int psfd_release_cached_workspaces(void) {
+  release_cached_groups();
+  return PSFD_OK;
 }
 
 int psfd_server_create(size_t hbm_budget, int32_t max_slots, const psfd_opts* opts, psfd_server** out) {

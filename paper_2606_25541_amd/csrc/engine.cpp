@@ -48,6 +48,7 @@ Status validate_problem(const psfd_problem* p, Problem& out) {
     return bad(PSFD_ERR_INVALID_ARG, "theta must lie in (-90, 90) degrees");
   if (p->pol != PSFD_TE && p->pol != PSFD_TM) return bad(PSFD_ERR_INVALID_ARG, "pol must be PSFD_TE or PSFD_TM");
   if (p->n_layers < 0 || (p->n_layers > 0 && !p->layers)) return bad(PSFD_ERR_INVALID_ARG, "bad layer list");
+  if (p->n_layers > LAYER_CAP) return bad(PSFD_ERR_UNSUPPORTED_SIZE, "at most 2048 layers");
   out.p = *p;
   out.layers.assign(p->layers, p->layers + p->n_layers);
   for (auto& l : out.layers)
@@ -93,35 +94,11 @@ Shape shape_of(const psfd_problem& p) {
 }
 
 // ---------------------------------------------------------------------------
-// Layered stack: recursive generalized reflection coefficient at the top surface
-// (Chew's recursion, folding one layer at a time from the substrate upwards).
-// TE returns the E-field ratio, TM the H-field ratio.
+// z-wavenumber branch with Im >= 0 (outgoing or decaying for e^{-i omega t})
 static inline cd kz_branch(cd k2) {
   cd r = std::sqrt(k2);
   if (r.imag() < 0 || (r.imag() == 0 && r.real() < 0)) r = -r;
   return r;
-}
-
-static cd stack_reflection(double k0, double eps_top, const std::vector<psfd_layer>& L, cd eps_sub, double kt,
-                           int pol) {
-  const int nl = (int)L.size();
-  std::vector<cd> eps(nl + 2), kz(nl + 2);
-  std::vector<double> d(nl + 2, 0.0);
-  eps[0] = eps_top;
-  for (int i = 0; i < nl; ++i) { eps[i + 1] = cd(L[i].eps_re, L[i].eps_im); d[i + 1] = L[i].thickness_nm; }
-  eps[nl + 1] = eps_sub;
-  for (int i = 0; i < nl + 2; ++i) kz[i] = kz_branch(k0 * k0 * eps[i] - kt * kt);
-  auto fres = [&](int i, int j) -> cd {
-    if (pol == PSFD_TE) return (kz[i] - kz[j]) / (kz[i] + kz[j]);
-    return (eps[j] * kz[i] - eps[i] * kz[j]) / (eps[j] * kz[i] + eps[i] * kz[j]);
-  };
-  cd rt = fres(nl, nl + 1);
-  for (int i = nl - 1; i >= 0; --i) {
-    cd r = fres(i, i + 1);
-    cd ph = std::exp(cd(0, 2) * kz[i + 1] * d[i + 1]);
-    rt = (r + rt * ph) / (1.0 + r * rt * ph);
-  }
-  return rt;
 }
 
 static void cross3(const cd* a, const cd* b, cd* o) {
@@ -155,54 +132,54 @@ Status build_table(const Problem& pr, std::vector<double>& tab) {
   double* ky = tab.data() + L.off_ky();
   for (int i = 0; i < nx; ++i) { int m = i < nx / 2 ? i : i - nx; kx[i] = kx0 + 2.0 * PI * m / p.lx_nm; }
   for (int j = 0; j < ny; ++j) { int n = j < ny / 2 ? j : j - ny; ky[j] = ky0 + 2.0 * PI * n / p.ly_nm; }
-  double* beta = tab.data() + L.off_beta();
-  double* eibl = tab.data() + L.off_eibl();
-  double* keep = tab.data() + L.off_keep();
-  double* tr = tab.data() + L.off_tr();
-  const cd eps_sub(p.eps_sub_re, p.eps_sub_im);
-  for (int j = 0; j < ny; ++j) {
+  // Wood anomaly check: every order needs |beta| > 0 (the kernel and the
+  // readouts divide by beta). The per-order tables themselves (beta, exp(i beta L),
+  // keep mask, T_R) are computed on the device by upload_table.
+  for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
-      const long long q = (long long)j * nx + i;
       const double kt = std::hypot(kx[i], ky[j]);
-      const cd b = kz_branch(cd(kbg * kbg - kt * kt, 0.0));
-      if (std::abs(b) < 1e-6 * kbg) {
+      if (std::abs(kz_branch(cd(kbg * kbg - kt * kt, 0.0))) < 1e-6 * kbg) {
         st.code = PSFD_ERR_SINGULAR;
         st.msg = "a transverse order grazes the surface (beta = 0, Wood anomaly)";
         return st;
       }
-      beta[2 * q] = b.real(); beta[2 * q + 1] = b.imag();
-      const cd e = std::exp(cd(0, 1) * b * p.t_nm);
-      eibl[2 * q] = e.real(); eibl[2 * q + 1] = e.imag();
-      const bool nyq = (i == nx / 2) || (j == ny / 2);
-      keep[q] = nyq ? 0.0 : 1.0;
-      // polarisation basis: s = z x kt / |kt| (azimuth fallback at kt = 0), p+- = k+- x s / kbg
-      cd s[3];
-      if (kt > 0) { s[0] = -ky[j] / kt; s[1] = kx[i] / kt; }
-      else { s[0] = -std::sin(ph); s[1] = std::cos(ph); }
-      s[2] = 0.0;
-      cd kp[3] = {kx[i], ky[j], b}, km[3] = {kx[i], ky[j], -b};
-      cd pp[3], pm[3];
-      cross3(kp, s, pp);
-      cross3(km, s, pm);
-      for (int c = 0; c < 3; ++c) { pp[c] /= kbg; pm[c] /= kbg; }
-      const cd rs = stack_reflection(k0, p.eps_bg, pr.layers, eps_sub, kt, PSFD_TE);
-      const cd rp = stack_reflection(k0, p.eps_bg, pr.layers, eps_sub, kt, PSFD_TM);
-      for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) {
-          cd t = nyq ? cd(0) : (rs * s[r] * s[c] + rp * pp[r] * pm[c]);
-          tr[18 * q + 2 * (3 * r + c)] = t.real();
-          tr[18 * q + 2 * (3 * r + c) + 1] = t.imag();
-        }
-      if (q == 0) {
-        tab[TS_INCQ] = 0.0;
-        const cd* ev = (p.pol == PSFD_TE) ? s : pm;
-        for (int c = 0; c < 3; ++c) { tab[TS_EINC + 2 * c] = ev[c].real(); tab[TS_EINC + 2 * c + 1] = ev[c].imag(); }
-        tab[TS_BINC] = b.real();
-        tab[TS_BINC + 1] = b.imag();
-      }
     }
+  // incident order (0, 0): polarisation vector s (TE) or p- (TM) and its beta
+  {
+    const double kt = std::hypot(kx[0], ky[0]);
+    const cd b = kz_branch(cd(kbg * kbg - kt * kt, 0.0));
+    cd sv[3];
+    if (kt > 0) { sv[0] = -ky[0] / kt; sv[1] = kx[0] / kt; }
+    else { sv[0] = -std::sin(ph); sv[1] = std::cos(ph); }
+    sv[2] = 0.0;
+    cd km[3] = {kx[0], ky[0], -b}, pm[3];
+    cross3(km, sv, pm);
+    for (int c = 0; c < 3; ++c) pm[c] /= kbg;
+    tab[TS_INCQ] = 0.0;
+    const cd* ev = (p.pol == PSFD_TE) ? sv : pm;
+    for (int c = 0; c < 3; ++c) { tab[TS_EINC + 2 * c] = ev[c].real(); tab[TS_EINC + 2 * c + 1] = ev[c].imag(); }
+    tab[TS_BINC] = b.real();
+    tab[TS_BINC + 1] = b.imag();
   }
   return st;
+}
+
+Status upload_table(double* d_tab, double4* d_lay, const Problem& pr, const std::vector<double>& tab,
+                    hipStream_t s) {
+  const psfd_problem& p = pr.p;
+  const int nl = (int)pr.layers.size();
+  std::vector<double4> lay(nl + 2);
+  lay[0] = make_double4(p.eps_bg, 0.0, 0.0, 0.0);
+  for (int i = 0; i < nl; ++i)
+    lay[i + 1] = make_double4(pr.layers[i].eps_re, pr.layers[i].eps_im, pr.layers[i].thickness_nm, 0.0);
+  lay[nl + 1] = make_double4(p.eps_sub_re, p.eps_sub_im, 0.0, 0.0);
+  const TabLayout L{p.nx, p.ny};
+  HIPCHK(hipMemcpyAsync(d_tab, tab.data(), (size_t)L.off_beta() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d_lay, lay.data(), lay.size() * sizeof(double4), hipMemcpyHostToDevice, s));
+  const double k0 = 2.0 * PI / p.wavelength_nm;
+  launch_stack_table(p.nx, p.ny, d_tab, d_lay, nl, k0 * k0, p.phi_deg * PI / 180.0, s);
+  HIPCHK(hipGetLastError());
+  return Status();
 }
 
 void build_twiddles(std::vector<double>& tw) {
@@ -320,6 +297,7 @@ size_t group_bytes(const Shape& sh, int B, int m, int prec) {
   per += prec == PSFD_MIXED ? n3 * esz : 0;
   per += sizeof(GState) + RED_BLOCKS * (MAXM + 2) * 16 + RED_BLOCKS * 2 * 8;
   per += 5 * (size_t)sh.nxny * 3 * 16 + (size_t)((sh.nxny + 255) / 256) * 2 * 8 + 64;
+  per += (size_t)(LAYER_CAP + 2) * sizeof(double4);
   return per * (size_t)B;
 }
 
@@ -349,6 +327,7 @@ Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec) {
   const size_t n3 = (size_t)sh.n3, N = (size_t)sh.N, nq = (size_t)sh.nxny * 3;
   g.tab_stride = TabLayout{sh.nx, sh.ny}.size();
   GALLOC(g.tab, (size_t)g.tab_stride * 8 * B);
+  GALLOC(g.lay, (size_t)(LAYER_CAP + 2) * sizeof(double4) * B);
   GALLOC(g.deps64, N * 16 * B);
   if (prec == PSFD_MIXED) GALLOC(g.deps32, N * 8 * B);
   GALLOC(g.x, n3 * 16 * B);
@@ -385,9 +364,8 @@ Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec) {
   return Status();
 }
 
-Status group_set_tables(Group& g, int b, const std::vector<double>& tab, hipStream_t s) {
-  HIPCHK(hipMemcpyAsync(g.tab + (size_t)b * g.tab_stride, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s));
-  return Status();
+Status group_set_tables(Group& g, int b, const Problem& pr, const std::vector<double>& tab, hipStream_t s) {
+  return upload_table(g.tab + (size_t)b * g.tab_stride, g.lay + (size_t)b * (LAYER_CAP + 2), pr, tab, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -37,7 +37,15 @@ Status validate_problem(const psfd_problem* p, Problem& out);
 Status make_opts(const psfd_opts* o, Opts& out);
 Shape shape_of(const psfd_problem& p);
 // per-instance FP64 tables (TabLayout) of a problem; SINGULAR on a grazing order
+// Host part of an instance table (scalars, kx, ky, incident order); fails with
+// SINGULAR at a Wood anomaly.
 Status build_table(const Problem& pr, std::vector<double>& tab);
+// Copies the host part to d_tab and computes the per-order part on the device
+// (d_lay: scratch for LAYER_CAP + 2 layers).
+Status upload_table(double* d_tab, double4* d_lay, const Problem& pr, const std::vector<double>& tab,
+                    hipStream_t s);
+// largest layer count of a stack
+const int LAYER_CAP = 2048;
 // twiddle tables of all power-of-two lengths up to 256 (tw[n + i] = exp(-2 pi i i / n))
 void build_twiddles(std::vector<double>& tw64);
 
@@ -69,6 +77,7 @@ struct Group {
   // per instance tables
   double* tab = nullptr;
   long long tab_stride = 0;
+  double4* lay = nullptr;  // layer stack per instance (LAYER_CAP + 2 entries), table input
   // contrast (FP64 copy of the user data, FP32 copy for mixed precision)
   double2* deps64 = nullptr;
   float2* deps32 = nullptr;
@@ -97,7 +106,7 @@ struct Group {
 
 size_t group_bytes(const Shape& sh, int B, int m, int prec);
 Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec);
-Status group_set_tables(Group& g, int b, const std::vector<double>& tab, hipStream_t s);
+Status group_set_tables(Group& g, int b, const Problem& pr, const std::vector<double>& tab, hipStream_t s);
 
 // y = x - K(V x) (kmode 0) or y = K(V x) (kmode 1); transpose uses the kernel at -k.
 // refl adds the layered-stack response R_vol T_R K_top to K (monolithic operator M).

@@ -61,6 +61,10 @@ void launch_adjoint_source(int nx, int ny, const double* tab, long long tab_stri
 // grad = 2 conj(k0^2 sum_c lam_c u_c) per voxel (complex128 [nz][ny][nx]); out[b] at outs[b]
 void launch_gradient(long long N, const double* tab, long long tab_stride, const double2* lam, const double2* u,
                      long long n3stride, double2* grad, long long gstride, int nbatch, hipStream_t s);
+// per-order part of an instance table (beta, exp(i beta L), keep, T_R) from kx, ky,
+// the scalars in tab and the stack lay[0..nl+1] = ambient, layers, substrate
+void launch_stack_table(int nx, int ny, double* tab, const double4* lay, int nl, double k0sq, double phi,
+                        hipStream_t s);
 // orders = eup exp(i beta T) + aup
 void launch_orders(int nx, int ny, const double* tab, long long tab_stride, const double2* eup,
                    const double2* aup, double2* orders, long long ostride, int nbatch, hipStream_t s);

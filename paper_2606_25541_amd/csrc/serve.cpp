@@ -19,6 +19,51 @@ static bool same_shape(const psfd_problem& a, const psfd_problem& b) {
          a.t_nm == b.t_nm;
 }
 
+// Workspaces of finished batched solves, kept for the next call with the same
+// device, shape, batch size, restart length and precision: fresh device memory
+// costs about as much to map and clear as a solve of the same size, so a batch
+// that allocated its own workspace on every call would spend most of its time
+// there. At most BATCH_CACHE_GROUPS groups are kept (least recently used are
+// freed first); psfd_release_cached_workspaces frees them all.
+static const size_t BATCH_CACHE_GROUPS = 4;
+struct CachedGroup {
+  int device;
+  std::unique_ptr<Group> g;
+};
+static std::mutex g_cache_mu;
+// never destroyed: at process exit the runtime may be gone before static destructors run
+static std::deque<CachedGroup>& g_cache = *new std::deque<CachedGroup>();
+
+static std::unique_ptr<Group> take_group(int device, const Shape& sh, int B, int m, int prec) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
+    const Group& g = *it->g;
+    if (it->device == device && g.sh.nx == sh.nx && g.sh.ny == sh.ny && g.sh.nz == sh.nz && g.B == B &&
+        g.m == m && g.prec == prec) {
+      std::unique_ptr<Group> out = std::move(it->g);
+      g_cache.erase(it);
+      return out;
+    }
+  }
+  return nullptr;
+}
+
+static void return_group(int device, std::unique_ptr<Group> g) {
+  std::unique_ptr<Group> drop;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache.push_front(CachedGroup{device, std::move(g)});
+  if (g_cache.size() > BATCH_CACHE_GROUPS) {
+    drop = std::move(g_cache.back().g);
+    g_cache.pop_back();
+  }
+}
+
+void release_cached_groups() {
+  std::deque<CachedGroup> drop;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  drop.swap(g_cache);
+}
+
 Status solve_batch(int n, const psfd_problem* probs, const psfd_opts* opts, const void* const* d_deps,
                    void* const* d_emask, void* const* d_orders, psfd_info* info, hipStream_t s) {
   Status st;
@@ -36,14 +81,21 @@ Status solve_batch(int n, const psfd_problem* probs, const psfd_opts* opts, cons
     }
   }
   const Shape sh = shape_of(pr[0].p);
-  Group g;
-  st = group_alloc(g, sh, n, o.restart, o.precision);
-  if (!st.ok()) return st;
+  int device = 0;
+  hipError_t de = hipGetDevice(&device);
+  if (de != hipSuccess) return hip_status(de, "batch device");
+  std::unique_ptr<Group> gp = take_group(device, sh, n, o.restart, o.precision);
+  if (!gp) {
+    gp = std::make_unique<Group>();
+    st = group_alloc(*gp, sh, n, o.restart, o.precision);
+    if (!st.ok()) return st;
+  }
+  Group& g = *gp;
   std::vector<double> tab;
   for (int i = 0; i < n; ++i) {
     st = build_table(pr[i], tab);
     if (!st.ok()) return st;
-    st = group_set_tables(g, i, tab, s);
+    st = group_set_tables(g, i, pr[i], tab, s);
     if (!st.ok()) return st;
     hipError_t e = hipMemcpyAsync(g.deps64 + (size_t)i * sh.N, d_deps[i], sh.N * 16, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_status(e, "copy contrast");
@@ -68,6 +120,7 @@ Status solve_batch(int n, const psfd_problem* probs, const psfd_opts* opts, cons
   }
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_status(e, "batch");
+  return_group(device, std::move(gp));
   return st;
 }
 
@@ -176,7 +229,7 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
       for (int b = 0; b < B; ++b) {
         if (!mk.first[b]) continue;
         Req* r = G.req[b];
-        st = group_set_tables(g, b, r->tab, s);
+        st = group_set_tables(g, b, r->pr, r->tab, s);
         if (!st.ok()) return st;
         hipError_t e = hipMemcpyAsync(g.deps64 + (size_t)b * N, r->d_deps, N * 16, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipMemsetAsync(g.adn + (size_t)b * nq, 0, nq * 16, s);

@@ -6,6 +6,7 @@ namespace psfd {
 
 Status solve_batch(int n, const psfd_problem* probs, const psfd_opts* opts, const void* const* d_deps,
                    void* const* d_emask, void* const* d_orders, psfd_info* info, hipStream_t s);
+void release_cached_groups();
 
 Status server_create(size_t hbm_budget, int max_slots, const psfd_opts* opts, psfd_server** out);
 Status server_submit(psfd_server* srv, const psfd_problem* prob, const void* d_deps, void* d_emask, void* d_orders,

@@ -97,3 +97,8 @@ def test_plan_create_and_footprint_on_host(lib):
     assert lib.psfd_plan_footprint(h, C.byref(v)) == 0
     assert v.value > 31 * 3 * 8 * 8 * 4 * 8
     lib.psfd_plan_destroy(h)
+
+
+def test_release_cached_workspaces_without_cache(lib):
+    # only the host-side cache is touched: returns OK with nothing kept
+    assert lib.psfd_release_cached_workspaces() == 0

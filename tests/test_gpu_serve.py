@@ -64,6 +64,28 @@ def test_batch_equals_single():
         assert inf["iters"] == i1["iters"]
 
 
+def test_batch_reuses_cached_workspace():
+    # a second call of the same kind runs in the kept workspace: same results;
+    # after the cache is released the call allocates afresh, same results again
+    from paper_2606_25541_amd import api
+    dev = device()
+    cs = [c for c in cases() if c[0].nx == 32][:2]
+    ds = [torch.from_numpy(c[1]).to(dev) for c in cs]
+    runs = []
+    for k in range(3):
+        if k == 2:
+            api.psfd_release_cached_workspaces()
+        em, od, infos = api.psfd_solve_batch([c[0] for c in cs], ds, **OPTS)
+        torch.cuda.synchronize()
+        assert all(i["status"] == 0 for i in infos)
+        runs.append(([e.cpu().numpy() for e in em], [o.cpu().numpy() for o in od], [i["iters"] for i in infos]))
+    for r in runs[1:]:
+        assert r[2] == runs[0][2]
+        for a, b in zip(r[0] + r[1], runs[0][0] + runs[0][1]):
+            assert np.array_equal(a, b)
+    api.psfd_release_cached_workspaces()
+
+
 def test_server_mix_equals_alone_and_oracle():
     from paper_2606_25541_amd import api
     dev = device()
