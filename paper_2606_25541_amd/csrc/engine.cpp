@@ -232,24 +232,29 @@ XYCfg xy_config(const Shape& sh, size_t esz) {
   return c;
 }
 
-// LDS of a pencil block: interleaved pencil data (pz x 3 bx), per-plane phases
-// (nz x bx), the per-order layered response (bx x 3), the readout partial sums
-// (4 chunks x 3 bx) and the per-order kernel scalars (bx x 4), the last three in FP64.
-static size_t pencil_lds(const Shape& sh, int bx, size_t esz) {
+// Threads of a pencil block: at most 8 values per thread in its FFT passes.
+static int pencil_threads(const Shape& sh, int bx) {
+  int nthr = clampi(ceil64(3 * bx * sh.pz / 8), 64, 768);
+  if (nthr < 4 * 3 * bx) nthr = ceil64(4 * 3 * bx);  // at least four readout partial sums per sequence
+  return nthr;
+}
+
+// data [pz][3 bx], phases [nz][bx], E_up [bx][3], partial sums [nthr], order constants [bx][6]
+static size_t pencil_lds(const Shape& sh, int bx, int nthr, size_t esz) {
   size_t d = (size_t)sh.pz * 3 * bx * esz + (size_t)sh.nz * bx * esz;
   d = (d + 15) / 16 * 16;
-  return d + (size_t)3 * bx * 16 + (size_t)4 * 3 * bx * 16 + (size_t)4 * bx * 16;
+  return d + (size_t)3 * bx * 16 + (size_t)nthr * 16 + (size_t)6 * bx * 16;
 }
 
 ZCfg z_config(const Shape& sh, size_t esz) {
   ZCfg z{};
   int bx = std::min(sh.nx, env_int("PSFD_ZBX", 16));
   // pencil FFT passes take at most 8 values per thread and 768 threads per block
-  while (bx > 1 && (pencil_lds(sh, bx, esz) > 150 * 1024 || 3 * bx * sh.pz > 8 * 768)) bx >>= 1;
+  while (bx > 1 && (pencil_lds(sh, bx, pencil_threads(sh, bx), esz) > 150 * 1024 || 3 * bx * sh.pz > 8 * 768))
+    bx >>= 1;
   z.bx = bx;
-  z.nthr = clampi(ceil64(3 * bx * sh.pz / 8), 64, 768);
-  if (z.nthr < 4 * 3 * bx) z.nthr = ceil64(4 * 3 * bx);  // one thread per readout partial sum
-  z.lds = pencil_lds(sh, bx, esz);
+  z.nthr = pencil_threads(sh, bx);
+  z.lds = pencil_lds(sh, bx, z.nthr, esz);
   return z;
 }
 

@@ -62,11 +62,33 @@ template <class T, int R, bool INV> PSFD_D void dft_r(T* u) {
   else dft8<T, INV>(u);
 }
 
+// Shape of a batch of sequences in LDS: length 2^ln(), ns() sequences, element
+// j of sequence s at s * ss() + j * es(), nt() threads. FftRT carries run-time
+// values; FftCT fixes them at compile time, which turns every LDS address of a
+// butterfly into one register plus immediate offsets and removes the integer
+// multiplies of the index arithmetic.
+struct FftRT {
+  int log2n, nseq, sstride, estride, nthreads;
+  PSFD_D int ln() const { return log2n; }
+  PSFD_D int ns() const { return nseq; }
+  PSFD_D int ss() const { return sstride; }
+  PSFD_D int es() const { return estride; }
+  PSFD_D int nt() const { return nthreads; }
+};
+template <int LN, int NS, int SS, int ES, int NT> struct FftCT {
+  PSFD_D static constexpr int ln() { return LN; }
+  PSFD_D static constexpr int ns() { return NS; }
+  PSFD_D static constexpr int ss() { return SS; }
+  PSFD_D static constexpr int es() { return ES; }
+  PSFD_D static constexpr int nt() { return NT; }
+};
+
+// Butterfly b of a pass -> (sequence s, butterfly t within the sequence).
 // SF (sequence-fastest): consecutive threads take consecutive sequences at the
 // same butterfly index, the conflict-free mapping when sequences are
 // interleaved in LDS (sstride 1); otherwise consecutive threads take
-// consecutive butterflies of one sequence.
-// b / nseq through a float reciprocal (exact for b < 2^22 and nseq <= 4096)
+// consecutive butterflies of one sequence. b / nseq goes through a float
+// reciprocal (exact for b < 2^22 and nseq <= 4096).
 template <bool SF>
 PSFD_D void bfly_index(int b, int log2nr, int nseq, float inv_nseq, int& s, int& t) {
   if (SF) { t = (int)(((float)b + 0.5f) * inv_nseq); s = b - t * nseq; }
@@ -104,67 +126,79 @@ template <class T> struct FftBudget {
   static constexpr int LRMAX = 3;
 };
 
-template <class T, int R, bool INV, bool SF, int E>
-__device__ __forceinline__ void stockham_pass(T* lds, int log2n, int log2p, int nseq, int sstride, int estride,
-                              const T* __restrict__ tw, int tid, int nthr) {
-  constexpr int NB = E / R;
+template <class T, int R, bool INV, bool SF, int E, class D>
+__device__ __forceinline__ void stockham_pass(T* lds, const D& d, int log2p, const T* __restrict__ tw, int tid) {
+  constexpr int NB = E >= R ? E / R : 1;  // E < R: one butterfly on the first threads
   constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
-  const int log2nr = log2n - LR;
+  const int log2nr = d.ln() - LR;
   const int nr = 1 << log2nr;
-  const int nbt = nseq << log2nr;
-  const float inv_nseq = 1.0f / (float)nseq;
+  const int nbt = d.ns() << log2nr;
+  const int nthr = d.nt();
+  const float inv_nseq = 1.0f / (float)d.ns();
   T u[NB][R];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     int b = tid + i * nthr;
     if (b < nbt) {
       int s, t;
-      bfly_index<SF>(b, log2nr, nseq, inv_nseq, s, t);
-      const T* base = lds + s * sstride;
+      bfly_index<SF>(b, log2nr, d.ns(), inv_nseq, s, t);
+      const T* base = lds + s * d.ss() + t * d.es();
 #pragma unroll
-      for (int j = 0; j < R; ++j) u[i][j] = base[(t + j * nr) * estride];
+      for (int j = 0; j < R; ++j) u[i][j] = base[j * nr * d.es()];
     }
   }
   __syncthreads();
   const int p = 1 << log2p;
-  const int tsh = log2n - log2p - LR;
+  const int tsh = d.ln() - log2p - LR;
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     int b = tid + i * nthr;
     if (b < nbt) {
       int s, t;
-      bfly_index<SF>(b, log2nr, nseq, inv_nseq, s, t);
+      bfly_index<SF>(b, log2nr, d.ns(), inv_nseq, s, t);
       int k = t & (p - 1);
       int step = k << tsh;
       if (k != 0) twiddle_apply<T, R, INV>(u[i], tw, step);
       dft_r<T, R, INV>(u[i]);
-      T* base = lds + s * sstride;
-      int o = (t - k) * R + k;
+      T* base = lds + s * d.ss() + ((t - k) * R + k) * d.es();
 #pragma unroll
-      for (int j = 0; j < R; ++j) base[(o + j * p) * estride] = u[i][j];
+      for (int j = 0; j < R; ++j) base[j * p * d.es()] = u[i][j];
     }
   }
   __syncthreads();
 }
 
-// Full FFT of nseq sequences of length 2^log2n staged in LDS (unnormalised;
-// INV uses the +i sign). All threads of the workgroup must call it.
+// Full FFT of the batch described by d (unnormalised; INV uses the +i sign).
+// All threads of the workgroup must call it. With a compile-time shape the pass
+// sequence unrolls and log2p is a constant in every pass.
+// tw: the twiddle table of this length, tw[i] = exp(-2 pi i i / n), i < n
+// (global memory or LDS).
+template <class T, bool INV, bool SF, int E, class D>
+__device__ __forceinline__ void lds_fft_tab(T* lds, const D& d, const T* __restrict__ tw, int tid) {
+  constexpr int LRM = FftBudget<T>::LRMAX;
+#pragma unroll
+  for (int log2p = 0; log2p < d.ln();) {
+    const int rem = d.ln() - log2p;
+    const int lr = rem >= LRM ? LRM : rem;
+    if (lr == 3) stockham_pass<T, 8, INV, SF, E>(lds, d, log2p, tw, tid);
+    else if (lr == 2) stockham_pass<T, 4, INV, SF, E>(lds, d, log2p, tw, tid);
+    else stockham_pass<T, 2, INV, SF, E>(lds, d, log2p, tw, tid);
+    log2p += lr;
+  }
+}
+
+// tw_all: the table of every length (tw_all[n + i] = exp(-2 pi i i / n))
+template <class T, bool INV, bool SF, int E, class D>
+__device__ __forceinline__ void lds_fft_d(T* lds, const D& d, const T* __restrict__ tw_all, int tid) {
+  lds_fft_tab<T, INV, SF, E>(lds, d, tw_all + (1 << d.ln()), tid);
+}
+
+// Run-time shape: nseq sequences of length 2^log2n, element j of sequence s at
+// s * sstride + j * estride.
 template <class T, bool INV, bool SF = false, int E = FftBudget<T>::E>
 __device__ __forceinline__ void lds_fft(T* lds, int log2n, int nseq, int sstride, int estride,
                         const T* __restrict__ tw_all, int tid, int nthr) {
-  const T* tw = tw_all + (1 << log2n);
-  int log2p = 0;
-  int rem = log2n;
-  while (rem > 0) {
-    int lr = rem >= FftBudget<T>::LRMAX ? FftBudget<T>::LRMAX : rem;
-    switch (lr) {
-      case 3: stockham_pass<T, 8, INV, SF, E>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
-      case 2: stockham_pass<T, 4, INV, SF, E>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
-      default: stockham_pass<T, 2, INV, SF, E>(lds, log2n, log2p, nseq, sstride, estride, tw, tid, nthr); break;
-    }
-    log2p += lr;
-    rem -= lr;
-  }
+  lds_fft_d<T, INV, SF, E>(lds, FftRT{log2n, nseq, sstride, estride, nthr}, tw_all, tid);
 }
 
 }  // namespace psfd

@@ -31,22 +31,53 @@ __global__ void __launch_bounds__(1024) k_tile(TileArgs a) {
   const int tile = blockIdx.x - plane * tiles;
   const int z = plane % a.nz;
   const int c = plane / a.nz;
-  const int x0 = (tile % a.tiles_x) * a.tx;
-  const int y0 = (tile / a.tiles_x) * a.ty;
+  const int tx = a.tx, ty = a.ty, nxa = a.nx, pitch = a.pitch;
+  const int nthr = blockDim.x;
+  const int ltx = ilog2i(a.tx);
+  const int x0 = (tile % a.tiles_x) * tx;
+  const int y0 = (tile / a.tiles_x) * ty;
   const long long nxny = (long long)a.nx * a.ny;
   const long long poff = (long long)plane * nxny;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int ntile = a.tx * a.ty;
-  const int ltx = ilog2i(a.tx);
+  const int tid = threadIdx.x;
+  const int ntile = tx * ty;
   const T* in = vref<T>(a.in, b) + poff;
   const T* aux = (LD == LD_VXE || ST == ST_AXPBY) ? vref<T>(a.aux, b) + poff : nullptr;
   const T* vol = (LD == LD_VX || LD == LD_VXE) ? vref<T>(a.vol, b) + (long long)z * nxny : nullptr;
   const double* tab = a.tab + (long long)b * a.tab_stride;
   typedef typename real_of<T>::type R;
   const R k0sq = (R)tab[TS_K0SQ];
-
-  for (int i = tid; i < ntile; i += nthr) {
-    int yy = i >> ltx, xx = i & (a.tx - 1);
+  // A thread handles elements tid + k nthr, k < KT (the launch keeps tx ty <= KT nthr).
+  // Global loads are issued in groups of KG before their LDS writes (the loop
+  // would otherwise wait on every load), within the register budget of the FFT.
+  constexpr int KT = FftBudget<T>::E;
+  constexpr int KG = 8;
+  // in-plane offset of element i (32-bit: a plane holds at most 2^16 elements)
+  auto off_of = [&](int i) -> int { return (y0 + (i >> ltx)) * nxa + (x0 + (i & (tx - 1))); };
+  if (LD == LD_PLAIN || LD == LD_VX) {
+#pragma unroll 1
+    for (int g = 0; g < KT; g += KG) {
+      T va[KG], vb[KG];
+#pragma unroll
+      for (int k = 0; k < KG; ++k) {
+        // unconditional loads (clamped index): a load under a branch would be waited
+        // for before the next one is issued
+        const int i = min(tid + (g + k) * nthr, ntile - 1);
+        const int o = off_of(i);
+        va[k] = in[o];
+        if (LD == LD_VX) vb[k] = vol[o];
+      }
+#pragma unroll
+      for (int k = 0; k < KG; ++k) {
+        const int i = tid + (g + k) * nthr;
+        if (i < ntile) {
+          const T v = LD == LD_VX ? cscale(cmul(vb[k], va[k]), k0sq) : va[k];
+          lds[(i >> ltx) * pitch + (i & (tx - 1))] = v;
+        }
+      }
+    }
+  }
+  for (int i = tid; i < ntile && LD != LD_PLAIN && LD != LD_VX; i += nthr) {
+    int yy = i >> ltx, xx = i & (tx - 1);
     long long o = (long long)(y0 + yy) * a.nx + (x0 + xx);
     T v;
     if (LD == LD_PLAIN) {
@@ -86,29 +117,38 @@ __global__ void __launch_bounds__(1024) k_tile(TileArgs a) {
       }
       v = from_d<T>(val);
     }
-    lds[yy * a.pitch + xx] = v;
+    lds[yy * pitch + xx] = v;
   }
   __syncthreads();
   const T* tw = reinterpret_cast<const T*>(a.tw);
   if (!INV) {
-    if (a.do_x) lds_fft<T, false>(lds, a.log2nx, a.ty, a.pitch, 1, tw, tid, nthr);
-    if (a.do_y) lds_fft<T, false>(lds, a.log2ny, a.tx, 1, a.pitch, tw, tid, nthr);
+    if (a.do_x) lds_fft<T, false>(lds, a.log2nx, ty, pitch, 1, tw, tid, nthr);
+    if (a.do_y) lds_fft<T, false>(lds, a.log2ny, tx, 1, pitch, tw, tid, nthr);
   } else {
-    if (a.do_y) lds_fft<T, true>(lds, a.log2ny, a.tx, 1, a.pitch, tw, tid, nthr);
-    if (a.do_x) lds_fft<T, true>(lds, a.log2nx, a.ty, a.pitch, 1, tw, tid, nthr);
+    if (a.do_y) lds_fft<T, true>(lds, a.log2ny, tx, 1, pitch, tw, tid, nthr);
+    if (a.do_x) lds_fft<T, true>(lds, a.log2nx, ty, pitch, 1, tw, tid, nthr);
   }
   T* out = vref<T>(a.out, b) + poff;
   const R al = (R)a.alpha, ga = (R)a.gamma;
-  for (int i = tid; i < ntile; i += nthr) {
-    int yy = i >> ltx, xx = i & (a.tx - 1);
-    long long o = (long long)(y0 + yy) * a.nx + (x0 + xx);
-    T v = lds[yy * a.pitch + xx];
+#pragma unroll 1
+  for (int g = 0; g < KT; g += KG) {
+    T xa[KG];
     if (ST == ST_AXPBY) {
-      T xv = aux[o];
-      v.x = al * xv.x + ga * v.x;
-      v.y = al * xv.y + ga * v.y;
+#pragma unroll
+      for (int k = 0; k < KG; ++k) xa[k] = aux[off_of(min(tid + (g + k) * nthr, ntile - 1))];
     }
-    out[o] = v;
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      const int i = tid + (g + k) * nthr;
+      if (i < ntile) {
+        T v = lds[(i >> ltx) * pitch + (i & (tx - 1))];
+        if (ST == ST_AXPBY) {
+          v.x = al * xa[k].x + ga * v.x;
+          v.y = al * xa[k].y + ga * v.y;
+        }
+        out[off_of(i)] = v;
+      }
+    }
   }
 }
 
@@ -117,9 +157,101 @@ static void allow_lds(const void* fn, size_t bytes) {
   if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// -------------------------------------------------------------------------
+// Square-plane kernel: one N x N plane (N = 2^LN) per block with the shapes
+// fixed at compile time, for the contrast-multiply + forward and the inverse +
+// axpy stages of the fused transverse FFT. Every global load of a thread,
+// including the axpy operand of the store, is issued at the start. The
+// twiddles sit in LDS so that their reads never wait on the vector-memory
+// counter of those loads. Rows are transformed first in both directions (the
+// 2-D transform is separable).
+// -------------------------------------------------------------------------
+__host__ __device__ constexpr int plane_threads(int ln) { return (1 << (2 * ln)) / 8 < 1024 ? (1 << (2 * ln)) / 8 : 1024; }
+__host__ __device__ constexpr size_t plane_lds(int ln, size_t esz) {
+  return ((size_t)(1 << ln) * ((1 << ln) + 1) + (1 << ln)) * esz;
+}
+
+template <class T, bool INV, int LD, int ST, int LN>
+__global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
+  constexpr int N = 1 << LN, P = N + 1, NT = plane_threads(LN);
+  constexpr int KT = N * N / NT;  // elements per thread
+  static_assert(KT * NT == N * N, "plane split");
+  extern __shared__ double2 smem_d[];
+  T* lds = reinterpret_cast<T*>(smem_d);
+  T* twl = lds + N * P;
+  const int b = blockIdx.y;
+  if (a.active && !a.active[b]) return;
+  const int plane = blockIdx.x;
+  const int z = plane % a.nz;
+  const long long poff = (long long)plane * N * N;
+  const int tid = threadIdx.x;
+  const T* in = vref<T>(a.in, b) + poff;
+  const T* vol = LD == LD_VX ? vref<T>(a.vol, b) + (long long)z * N * N : nullptr;
+  const T* aux = ST == ST_AXPBY ? vref<T>(a.aux, b) + poff : nullptr;
+  typedef typename real_of<T>::type R;
+  const T* twg = reinterpret_cast<const T*>(a.tw) + N;
+  // element i = tid + k NT is (row i >> LN, column i & (N - 1)), plane offset i
+  const T tw0 = twg[tid & (N - 1)];
+  // keep the twiddle load ahead of the data loads: its LDS write below then waits
+  // for it alone
+  __builtin_amdgcn_sched_barrier(0);
+  T va[KT], vb[LD == LD_VX ? KT : 1], xa[ST == ST_AXPBY ? KT : 1];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    va[k] = in[tid + k * NT];
+    if (LD == LD_VX) vb[k] = vol[tid + k * NT];
+  }
+  if (ST == ST_AXPBY) {
+#pragma unroll
+    for (int k = 0; k < KT; ++k) xa[k] = aux[tid + k * NT];
+  }
+  const double* tab = a.tab + (long long)b * a.tab_stride;
+  const R k0sq = (R)tab[TS_K0SQ];
+  if (tid < N) twl[tid] = tw0;
+  auto put = [&](int k) {
+    const int i = tid + k * NT;
+    const T v = LD == LD_VX ? cscale(cmul(vb[LD == LD_VX ? k : 0], va[k]), k0sq) : va[k];
+    lds[(i >> LN) * P + (i & (N - 1))] = v;
+  };
+  typedef FftCT<LN, N, P, 1, NT> Rows;
+  typedef FftCT<LN, N, 1, P, NT> Cols;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) put(k);
+  __syncthreads();
+  lds_fft_tab<T, INV, false, KT>(lds, Rows(), twl, tid);
+  lds_fft_tab<T, INV, false, KT>(lds, Cols(), twl, tid);
+  T* out = vref<T>(a.out, b) + poff;
+  const R al = (R)a.alpha, ga = (R)a.gamma;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int i = tid + k * NT;
+    T v = lds[(i >> LN) * P + (i & (N - 1))];
+    if (ST == ST_AXPBY) {
+      const T xv = xa[ST == ST_AXPBY ? k : 0];
+      v.x = al * xv.x + ga * v.x;
+      v.y = al * xv.y + ga * v.y;
+    }
+    out[tid + k * NT] = v;
+  }
+}
+
+// fused square planes of 64 x 64 (and 128 x 128 in FP32) with plain or
+// contrast-multiply loads take the square-plane kernel
 template <class T, bool INV, int LD, int ST>
 void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t lds, hipStream_t s) {
   dim3 grid(nplanes * a.tiles_x * a.tiles_y, nbatch);
+  const bool sq = (LD == LD_PLAIN || LD == LD_VX) && a.do_x && a.do_y && a.tx == a.nx && a.ty == a.ny &&
+                  a.nx == a.ny;
+  auto plane = [&](auto kern, int ln) {
+    const size_t l = plane_lds(ln, sizeof(T));
+    allow_lds(reinterpret_cast<const void*>(kern), l);
+    hipLaunchKernelGGL(kern, grid, dim3(plane_threads(ln)), l, s, a);
+  };
+  if constexpr (LD == LD_PLAIN || LD == LD_VX) {
+    if (sq && a.nx == 64) return plane(k_plane<T, INV, LD, ST, 6>, 6);
+    if constexpr (sizeof(T) == 8)
+      if (sq && a.nx == 128) return plane(k_plane<T, INV, LD, ST, 7>, 7);
+  }
   allow_lds(reinterpret_cast<const void*>(&k_tile<T, INV, LD, ST>), lds);
   hipLaunchKernelGGL((k_tile<T, INV, LD, ST>), grid, dim3(nthr), lds, s, a);
 }
@@ -158,129 +290,169 @@ PSFD_D double2 window_factor(double2 beta, double2 eibl, double kap, double L, d
   return cdiv(num, den);
 }
 
+// exp(i beta z) in the working precision. FP64: direct. FP32: the phase is
+// reduced modulo 2 pi in FP64 and the sine, cosine and decay taken in FP32.
+template <class T> PSFD_D T phase_exp(double2 beta, double z);
+template <> PSFD_D double2 phase_exp<double2>(double2 beta, double z) {
+  return cexp_i(make_double2(beta.x * z, beta.y * z));
+}
+template <> PSFD_D float2 phase_exp<float2>(double2 beta, double z) {
+  const double th = beta.x * z;
+  const double red = th - 6.283185307179586 * rint(th * 0.15915494309189535);
+  float sn, cs;
+  sincosf((float)red, &sn, &cs);
+  const float m = expf((float)(-beta.y * z));
+  return make_float2(m * cs, m * sn);
+}
+
+// F scale for one (order, kappa) point: the denominator beta^2 - kappa^2 and the
+// numerator s e^{i beta L} - 1 are formed in FP64 (the cancellation is there);
+// their quotient is taken in the working precision. Near the resonance
+// kappa = +-beta the series of window_factor is used.
+template <class T>
+PSFD_D T window_factor_fast(double2 beta, double2 beta2, double2 num, double kap, double L, double s, double scale) {
+  const double ak = fabs(kap);
+  const double ur = (beta.x - ak) * L, ui = beta.y * L;
+  if (ur * ur + ui * ui < 1e-12) {
+    const double2 e = make_double2(s * (num.x + 1.0), s * (num.y));  // e^{i beta L}
+    return from_d<T>(cscale(window_factor(beta, e, kap, L, s), scale));
+  }
+  const double2 den = make_double2(beta2.x - kap * kap, beta2.y);
+  const T n = from_d<T>(make_double2(num.x * scale, num.y * scale));
+  const T d = from_d<T>(den);
+  typedef typename real_of<T>::type R;
+  const R inv = (R)1 / (d.x * d.x + d.y * d.y);
+  T r;
+  r.x = (n.x * d.x + n.y * d.y) * inv;
+  r.y = (n.y * d.x - n.x * d.y) * inv;
+  return r;
+}
+
 // LDS layout of a pencil block: element z of sequence (c, kxl) at z * LS + c * bx + kxl
 // (sequences interleaved, LS = 3 bx), so every FFT pass, the kernel multiply and
 // the global load/store touch consecutive LDS words across a wavefront.
 // At most 8 values per thread in the pencil FFTs (the launch gives 3 bx pz / 8
 // threads, at most 768), which halves the register arrays of the FP32 passes.
-template <class T>
+// Threads of a pencil block with 16 columns and padded length 2^LPZ: at most 8
+// values per thread in the FFT passes, at least four readout partial sums per
+// sequence (the host's pencil_threads gives the same count).
+__host__ __device__ constexpr int pencil_threads_ct(int lpz) {
+  return (3 * 16 * (1 << lpz) / 8 + 63) / 64 * 64 > 192 ? (3 * 16 * (1 << lpz) / 8 + 63) / 64 * 64 : 192;
+}
+
+// LPZ > 0: 16 columns and padded length 2^LPZ fixed at compile time (the FFT
+// index arithmetic folds to constants); LPZ = 0: shapes from the arguments.
+template <class T, int LPZ>
 __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   extern __shared__ double2 smem_d[];
   T* lds = reinterpret_cast<T*>(smem_d);
   typedef typename real_of<T>::type R;
   const int b = blockIdx.y;
   if (a.active && !a.active[b]) return;
+  const int bx = LPZ ? 16 : a.bx, pz = LPZ ? (1 << LPZ) : a.pz, nz = pz / 2, nx = a.nx, ny = a.ny;
   const int ky = blockIdx.x / a.nblk_x;
-  const int kx0 = (blockIdx.x - ky * a.nblk_x) * a.bx;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int bx = a.bx, pz = a.pz, nz = a.nz, nx = a.nx, ny = a.ny;
+  const int kx0 = (blockIdx.x - ky * a.nblk_x) * bx;
+  const int tid = threadIdx.x, nthr = LPZ ? pencil_threads_ct(LPZ) : (int)blockDim.x;
   const int LS = 3 * bx;
-  const int lbx = ilog2i(bx);
-  const int lnz = ilog2i(nz);
+  const int lbx = LPZ ? 4 : ilog2i(bx);
   T* w = vref<T>(a.w, b);
-  const int nload = 3 * pz * bx;
-  for (int i = tid; i < nload; i += nthr) {
-    const int kxl = i & (bx - 1);
-    const int rest = i >> lbx;
-    const int c = rest % 3;
-    const int z = rest / 3;
-    T v = cmake<T>(0.0, 0.0);
-    if (z < nz) v = w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl];
-    lds[z * LS + c * bx + kxl] = v;
+  // The data half (z < nz) is LDS elements [0, nz LS): i = z LS + c bx + kxl, at
+  // most 4 per thread (3 pz bx <= 8 nthr). Loads are unconditional (clamped index)
+  // and all issued before the LDS writes; the padded half is zero.
+  const int nload = 3 * pz * bx, nval = nz * LS;
+  {
+    T buf[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = min(tid + k * nthr, nval - 1);
+      const int kxl = i & (bx - 1), rest = i >> lbx;
+      const int c = rest % 3, z = rest / 3;
+      buf[k] = w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = tid + k * nthr;
+      if (i < nval) lds[i] = buf[k];
+    }
+    for (int i = nval + tid; i < nload; i += nthr) lds[i] = cmake<T>(0.0, 0.0);
   }
   const double* tab = a.tab + (long long)b * a.tab_stride;
   TabLayout L{nx, ny};
-  // Layered-stack response of this block's orders (monolithic coupling):
-  // E_up,q = T_R (i dz / 2 beta) P- sum_k exp(i beta z_k) f_q(z_k) / (Nx Ny), added
-  // back as E_up,q exp(i beta z_k) on every plane. The transposed operator uses the
-  // negated order and the transposed 3x3 block.
-  constexpr int CH = 4;  // z-chunks of the readout sums
-  const int nch = nz < CH ? nz : CH;
-  const int zc = nz / nch;
-  T* ph = lds + pz * LS;                                                      // [nz][bx]
-  const size_t off_e = ((size_t)(pz * LS + nz * bx) * sizeof(T) + 15) / 16;   // in double2
-  double2* eup = smem_d + off_e;                                              // [bx][3]
-  double2* part = eup + 3 * bx;                                               // [nch][3 bx]
-  double2* ptab = part + 4 * 3 * bx;  // [bx][4]: beta, e^{i beta L}, (kx, ky) / k_bg, (keep, 0)
-  if (tid < bx) {
-    int mq = kx0 + tid, nq = ky;
+  // LDS after the data: phases exp(i beta z_k) [nz][bx] (T), the stack response
+  // E_up [bx][3], readout partial sums [nthr], per-column order constants [bx][6]
+  T* ph = lds + pz * LS;
+  const size_t off_e = ((size_t)(pz * LS + nz * bx) * sizeof(T) + 15) / 16;  // in double2
+  double2* eup = smem_d + off_e;
+  double2* part = eup + 3 * bx;
+  double2* ptab = part + nthr;
+  // order of column kxl (the transposed operator reads the kernel at the negated order)
+  auto order_of = [&](int kxl, int& mq, int& nq) {
+    mq = kx0 + kxl; nq = ky;
     if (a.transpose) { mq = (nx - mq) & (nx - 1); nq = (ny - nq) & (ny - 1); }
+  };
+  if (tid < bx) {
+    int mq, nq;
+    order_of(tid, mq, nq);
     const int q = nq * nx + mq;
     const double ikb = 1.0 / tab[TS_KBG];
-    ptab[tid * 4 + 0] = reinterpret_cast<const double2*>(tab + L.off_beta())[q];
-    ptab[tid * 4 + 1] = reinterpret_cast<const double2*>(tab + L.off_eibl())[q];
-    ptab[tid * 4 + 2] = make_double2(tab[L.off_kx() + mq] * ikb, tab[L.off_ky() + nq] * ikb);
-    ptab[tid * 4 + 3] = make_double2(tab[L.off_keep() + q], 0.0);
+    const double2 bq = reinterpret_cast<const double2*>(tab + L.off_beta())[q];
+    const double2 e = reinterpret_cast<const double2*>(tab + L.off_eibl())[q];
+    ptab[tid * 6 + 0] = bq;
+    ptab[tid * 6 + 1] = cmul(bq, bq);
+    ptab[tid * 6 + 2] = make_double2(e.x - 1.0, e.y);    // s e^{i beta L} - 1 at s = +1
+    ptab[tid * 6 + 3] = make_double2(-e.x - 1.0, -e.y);  // and at s = -1
+    ptab[tid * 6 + 4] = make_double2(tab[L.off_kx() + mq] * ikb, tab[L.off_ky() + nq] * ikb);
+    ptab[tid * 6 + 5] = make_double2(tab[L.off_keep() + q], 0.0);
   }
   if (a.reflect) {
+    // Layered-stack response of this block's orders (monolithic coupling):
+    // E_up,q = M_q sum_k exp(i beta_q z_k) f_q(z_k), M_q = T_R (i dz / 2 beta) P- / (Nx Ny)
+    // from the table, added back as E_up,q exp(i beta_q z_k) on every plane. The
+    // transposed operator uses the negated order and M_q^T.
     const double2* tb = reinterpret_cast<const double2*>(tab + L.off_beta());
     const double dz = tab[TS_DZ];
-    // phases by chunks: exp(i beta z_k) = exp(i beta z_k0) exp(i beta dz)^(k - k0)
-    if (tid < bx * nch) {
-      const int kxl = tid % bx, ch = tid / bx;
-      int mq = kx0 + kxl, nq = ky;
-      if (a.transpose) { mq = (nx - mq) & (nx - 1); nq = (ny - nq) & (ny - 1); }
+    for (int i = tid; i < nz * bx; i += nthr) {
+      const int kxl = i & (bx - 1), z = i >> lbx;
+      int mq, nq;
+      order_of(kxl, mq, nq);
       const double2 bq = tb[nq * nx + mq];
-      const int z0 = ch * zc;
-      const double zk = (z0 + 0.5) * dz;
-      double2 p0 = cexp_i(make_double2(bq.x * zk, bq.y * zk));
-      const double2 st = cexp_i(make_double2(bq.x * dz, bq.y * dz));
-      for (int z = z0; z < z0 + zc; ++z) {
-        ph[z * bx + kxl] = from_d<T>(p0);
-        p0 = cmul(p0, st);
-      }
+      ph[i] = phase_exp<T>(bq, (z + 0.5) * dz);
     }
     __syncthreads();
-    if (tid < LS * nch) {
+    // partial sums over z: thread (ch, sq) takes planes ch, ch + nch, ...
+    const int nch = nthr / LS;
+    if (tid < nch * LS) {
       const int sq = tid % LS, ch = tid / LS;
       const int kxl = sq & (bx - 1);
-      double2 acc = make_double2(0, 0);
-      for (int z = ch * zc; z < (ch + 1) * zc; ++z)
-        acc = cadd(acc, cmul(to_d(ph[z * bx + kxl]), to_d(lds[z * LS + sq])));
-      part[ch * LS + sq] = acc;
+      T acc = cmake<T>(0, 0);
+      for (int z = ch; z < nz; z += nch) acc = cadd(acc, cmul(ph[z * bx + kxl], lds[z * LS + sq]));
+      part[tid] = to_d(acc);
     }
     __syncthreads();
-    if (tid < bx) {
-      const int kxl = tid;
-      int mq = kx0 + kxl, nq = ky;
-      if (a.transpose) { mq = (nx - mq) & (nx - 1); nq = (ny - nq) & (ny - 1); }
-      const int q = nq * nx + mq;
-      double2 o[3] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
-      if (tab[L.off_keep() + q] != 0.0) {
-        const double2 bq = tb[q];
-        const double kbg = tab[TS_KBG];
-        const double2 fac = cscale(cdiv(make_double2(0.0, dz), make_double2(2.0 * bq.x, 2.0 * bq.y)), tab[TS_INVNXNY]);
-        const double2 km[3] = {make_double2(tab[L.off_kx() + mq], 0), make_double2(tab[L.off_ky() + nq], 0),
-                               make_double2(-bq.x, -bq.y)};
-        const double2* tr = reinterpret_cast<const double2*>(tab + L.off_tr()) + 9LL * q;
-        double2 v[3];
-        for (int c = 0; c < 3; ++c) {
-          v[c] = make_double2(0, 0);
-          for (int ch = 0; ch < nch; ++ch) v[c] = cadd(v[c], part[ch * LS + c * bx + kxl]);
-        }
-        double2 t[3];
-        if (!a.transpose) {
-          // P- v then T_R
-          double2 d = cadd(cadd(cmul(km[0], v[0]), cmul(km[1], v[1])), cmul(km[2], v[2]));
-          for (int c = 0; c < 3; ++c) t[c] = cmul(fac, csub(v[c], cscale(cmul(km[c], d), 1.0 / (kbg * kbg))));
-          for (int r = 0; r < 3; ++r)
-            o[r] = cadd(cadd(cmul(tr[3 * r], t[0]), cmul(tr[3 * r + 1], t[1])), cmul(tr[3 * r + 2], t[2]));
-        } else {
-          // T_R^T v then P-
-          for (int r = 0; r < 3; ++r)
-            t[r] = cadd(cadd(cmul(tr[r], v[0]), cmul(tr[3 + r], v[1])), cmul(tr[6 + r], v[2]));
-          double2 d = cadd(cadd(cmul(km[0], t[0]), cmul(km[1], t[1])), cmul(km[2], t[2]));
-          for (int c = 0; c < 3; ++c) o[c] = cmul(fac, csub(t[c], cscale(cmul(km[c], d), 1.0 / (kbg * kbg))));
-        }
-      }
-      for (int c = 0; c < 3; ++c) eup[kxl * 3 + c] = o[c];
+    if (tid < LS) {
+      double2 v = make_double2(0, 0);
+      for (int ch = 0; ch < nch; ++ch) v = cadd(v, part[ch * LS + tid]);
+      part[tid] = v;  // slot 0 of this thread's own sequence, which no other thread reads
+    }
+    __syncthreads();
+    if (tid < 3 * bx) {
+      // row r of M (or of M^T) times the summed readouts of column kxl
+      const int kxl = tid % bx, r = tid / bx;
+      int mq, nq;
+      order_of(kxl, mq, nq);
+      const double2* M = reinterpret_cast<const double2*>(tab + L.off_mono()) + 9LL * (nq * nx + mq);
+      double2 o = make_double2(0, 0);
+      for (int c = 0; c < 3; ++c) o = cadd(o, cmul(a.transpose ? M[3 * c + r] : M[3 * r + c], part[c * bx + kxl]));
+      eup[kxl * 3 + r] = o;
     }
   }
   __syncthreads();
   const T* tw = reinterpret_cast<const T*>(a.tw);
-  lds_fft<T, false, true, 8>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
+  typedef FftCT<LPZ, 48, 1, 48, pencil_threads_ct(LPZ)> ZCT;
+  if constexpr (LPZ > 0) lds_fft_d<T, false, true, 8>(lds, ZCT(), tw, tid);
+  else lds_fft<T, false, true, 8>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
 
-  const double kbg = tab[TS_KBG], Lw = tab[TS_L], kap_u = tab[TS_KAPPA], scale = tab[TS_SCALE];
+  const double Lw = tab[TS_L], kap_u = tab[TS_KAPPA], scale = tab[TS_SCALE], kbg = tab[TS_KBG];
   const double ik2 = 1.0 / (kbg * kbg);
   const int npt = bx * pz;
   for (int pt = tid; pt < npt; pt += nthr) {
@@ -292,18 +464,17 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     T* p0 = lds + l * LS + 0 * bx + kxl;
     T* p1 = p0 + bx;
     T* p2 = p0 + 2 * bx;
-    const double2* pt4 = ptab + kxl * 4;
-    if (pt4[3].x == 0.0) {
+    const double2* pt6 = ptab + kxl * 6;
+    if (pt6[5].x == 0.0) {
       *p0 = cmake<T>(0, 0); *p1 = cmake<T>(0, 0); *p2 = cmake<T>(0, 0);
       continue;
     }
     const double kap = kap_u * lq;
-    const double s = (lq & 1) ? -1.0 : 1.0;
-    const double2 e = pt4[1];
-    const double2 F = window_factor(pt4[0], e, kap, Lw, s);
-    T g = from_d<T>(cscale(F, scale));
-    T tz = from_d<T>(make_double2(s * e.x * scale * ik2, s * e.y * scale * ik2));
-    const R kxk = (R)pt4[2].x, kyk = (R)pt4[2].y, kzk = (R)(kap / kbg);
+    const bool odd = (lq & 1) != 0;
+    const T F = window_factor_fast<T>(pt6[0], pt6[1], pt6[odd ? 3 : 2], kap, Lw, odd ? -1.0 : 1.0, scale);
+    const double2 e = cadd(pt6[odd ? 3 : 2], make_double2(1.0, 0.0));  // s e^{i beta L}
+    T tz = from_d<T>(make_double2(e.x * scale * ik2, e.y * scale * ik2));
+    const R kxk = (R)pt6[4].x, kyk = (R)pt6[4].y, kzk = (R)(kap / kbg);
     T v0 = *p0, v1 = *p1, v2 = *p2;
     T dxy; dxy.x = kxk * v0.x + kyk * v1.x; dxy.y = kxk * v0.y + kyk * v1.y;
     T o0, o1, o2;
@@ -318,12 +489,13 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
       R f = (R)1 - kzk * kzk;
       o2.x = f * v2.x; o2.y = f * v2.y;
     }
-    *p0 = cmul(g, o0);
-    *p1 = cmul(g, o1);
-    *p2 = csub(cmul(g, o2), cmul(tz, v2));
+    *p0 = cmul(F, o0);
+    *p1 = cmul(F, o1);
+    *p2 = csub(cmul(F, o2), cmul(tz, v2));
   }
   __syncthreads();
-  lds_fft<T, true, true, 8>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
+  if constexpr (LPZ > 0) lds_fft_d<T, true, true, 8>(lds, ZCT(), tw, tid);
+  else lds_fft<T, true, true, 8>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
   const int nst = 3 * nz * bx;
   for (int i = tid; i < nst; i += nthr) {
     const int kxl = i & (bx - 1);
@@ -331,17 +503,21 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     const int c = rest % 3;
     const int z = rest / 3;
     T v = lds[z * LS + c * bx + kxl];
-    if (a.reflect) v = cadd(v, from_d<T>(cmul(eup[kxl * 3 + c], to_d(ph[z * bx + kxl]))));
+    if (a.reflect) v = cadd(v, cmul(from_d<T>(eup[kxl * 3 + c]), ph[z * bx + kxl]));
     w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl] = v;
   }
-  (void)lnz;
 }
 
 template <class T>
 void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStream_t s) {
   dim3 grid(a.nblk_x * a.ny, nbatch);
-  allow_lds(reinterpret_cast<const void*>(&k_pencil<T>), lds);
-  hipLaunchKernelGGL((k_pencil<T>), grid, dim3(nthr), lds, s, a);
+  auto go = [&](auto kern) {
+    allow_lds(reinterpret_cast<const void*>(kern), lds);
+    hipLaunchKernelGGL(kern, grid, dim3(nthr), lds, s, a);
+  };
+  if (a.bx == 16 && a.pz == 128 && nthr == pencil_threads_ct(7)) return go(k_pencil<T, 7>);
+  if (a.bx == 16 && a.pz == 64 && nthr == pencil_threads_ct(6)) return go(k_pencil<T, 6>);
+  go(k_pencil<T, 0>);
 }
 template void launch_pencil<float2>(const PencilArgs&, int, int, size_t, hipStream_t);
 template void launch_pencil<double2>(const PencilArgs&, int, int, size_t, hipStream_t);

@@ -82,13 +82,14 @@ __global__ void __launch_bounds__(256) k_stack_table(int nx, int ny, double* __r
   double* eibl = tab + Lt.off_eibl();
   double* keep = tab + Lt.off_keep();
   double* tr = tab + Lt.off_tr() + 18LL * q;
+  double* mono = tab + Lt.off_mono() + 18LL * q;
   beta[2 * q] = b.x; beta[2 * q + 1] = b.y;
   const double2 e = cexp_d(make_double2(-b.y * T, b.x * T));
   eibl[2 * q] = e.x; eibl[2 * q + 1] = e.y;
   const bool nyq = (i == nx / 2) || (j == ny / 2);
   keep[q] = nyq ? 0.0 : 1.0;
   if (nyq) {
-    for (int k = 0; k < 18; ++k) tr[k] = 0.0;
+    for (int k = 0; k < 18; ++k) { tr[k] = 0.0; mono[k] = 0.0; }
     return;
   }
   // s = z x kt / |kt| (azimuth of the incidence at kt = 0); p+- = k+- x s / kbg
@@ -107,11 +108,25 @@ __global__ void __launch_bounds__(256) k_stack_table(int nx, int ny, double* __r
   const double2 rs = stack_r(false, k0sq, kt2, lay, nl);
   const double2 rp = stack_r(true, k0sq, kt2, lay, nl);
   const double sv[3] = {s0, s1, 0.0};
+  double2 T_R[9];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) {
       const double2 t = cadd(cscale(rs, sv[r] * sv[c]), cmul(rp, cmul(pp[r], pm[c])));
+      T_R[3 * r + c] = t;
       tr[2 * (3 * r + c)] = t.x;
       tr[2 * (3 * r + c) + 1] = t.y;
+    }
+  // M = T_R fac P-, fac = (i dz / 2 beta) / (Nx Ny), P- = I - k- k-^T / k_bg^2, k- = (kx, ky, -beta)
+  const double2 fac = cscale(cdiv(make_double2(0.0, tab[TS_DZ]), make_double2(2.0 * b.x, 2.0 * b.y)), tab[TS_INVNXNY]);
+  const double2 km[3] = {make_double2(kx, 0.0), make_double2(ky, 0.0), make_double2(-b.x, -b.y)};
+  const double ik2 = 1.0 / (kbg * kbg);
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      // (T_R P-)_{rc} = T_R,rc - sum_k T_R,rk km_k km_c / k_bg^2
+      const double2 tk = cadd(cadd(cmul(T_R[3 * r], km[0]), cmul(T_R[3 * r + 1], km[1])), cmul(T_R[3 * r + 2], km[2]));
+      const double2 m = cmul(fac, csub(T_R[3 * r + c], cscale(cmul(tk, km[c]), ik2)));
+      mono[2 * (3 * r + c)] = m.x;
+      mono[2 * (3 * r + c) + 1] = m.y;
     }
 }
 

@@ -29,7 +29,10 @@ struct TabLayout {
   __host__ __device__ long long off_eibl() const { return off_beta() + 2LL * nx * ny; }
   __host__ __device__ long long off_keep() const { return off_eibl() + 2LL * nx * ny; }
   __host__ __device__ long long off_tr() const { return off_keep() + 1LL * nx * ny; }
-  __host__ __device__ long long size() const { return off_tr() + 18LL * nx * ny; }
+  // stack response of an order in the coupled operator: M_q = T_R (i dz / 2 beta) P- / (Nx Ny),
+  // P- = I - k- k-^T / k_bg^2 with k- = (kx, ky, -beta); 3x3 complex, row-major
+  __host__ __device__ long long off_mono() const { return off_tr() + 18LL * nx * ny; }
+  __host__ __device__ long long size() const { return off_mono() + 18LL * nx * ny; }
 };
 
 // A vector of one instance: base + b * bstride + j * jstride elements, where j is
