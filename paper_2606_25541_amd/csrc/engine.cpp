@@ -300,7 +300,7 @@ size_t group_bytes(const Shape& sh, int B, int m, int prec) {
   per += 6 * n3 * 16;
   per += (size_t)(m + 1) * n3 * esz;
   per += prec == PSFD_MIXED ? n3 * esz : 0;
-  per += sizeof(GState) + RED_BLOCKS * (MAXM + 2) * 16 + RED_BLOCKS * 2 * 8;
+  per += sizeof(GState) + RED_BLOCKS * PSTR * 16 + RED_BLOCKS * 2 * 8;
   per += 5 * (size_t)sh.nxny * 3 * 16 + (size_t)((sh.nxny + 255) / 256) * 2 * 8 + 64;
   per += (size_t)(LAYER_CAP + 2) * sizeof(double4);
   return per * (size_t)B;
@@ -349,7 +349,9 @@ Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec) {
   GALLOC(g.run, sizeof(int) * B);
   GALLOC(g.mask, sizeof(int) * B);
   GALLOC(g.mask2, sizeof(int) * B);
-  GALLOC(g.part, (size_t)RED_BLOCKS * (MAXM + 2) * 16 * B);
+  GALLOC(g.cyc, sizeof(int) * B);
+  GALLOC(g.rtol, sizeof(double) * B);
+  GALLOC(g.part, (size_t)RED_BLOCKS * PSTR * 16 * B);
   GALLOC(g.n2, 8 * B);
   GALLOC(g.n2b, 8 * B);
   GALLOC(g.abs_target, 8 * B);
@@ -541,8 +543,10 @@ double reorth_threshold() {
   return v;
 }
 
-// Arnoldi steps issued per host check of the run flags; steps issued after an
-// instance stops are no-ops (every kernel tests run[b]).
+// Arnoldi steps between host checks of the solve flags (whole cycles); kernels
+// launched for finished instances are no-ops (every kernel tests its flags).
+const int CHECK_STEPS = 40;
+// Arnoldi steps the server issues per host check of the run flags.
 const int STEPS_PER_SYNC = 4;
 
 template <class T> static const T* deps_of(const Group& g);
@@ -562,17 +566,20 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s) {
   krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 1, g.part, g.B, s);
   krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 1, g.part, g.B, s);
   krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 0, g.part, g.B, s);
-  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 0, g.part, g.B, s);
-  krylov_givens(g.st, g.run, g.B, s);
+  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 0, g.part, g.B, s);  // and the Givens step
   krylov_scale_next<T>(V, n3, bsv, n3, g.st, g.run, g.B, s);  // also advances j
 }
 
 template void arnoldi_step<float2>(Group&, int, int, hipStream_t);
 template void arnoldi_step<double2>(Group&, int, int, hipStream_t);
 
-// Restarted GMRES on (I - K V) x = b for the instances with act[b] set.
-// Each cycle starts from the FP64 residual r = b - A x; the Arnoldi cycle runs
-// in the working precision T and x accumulates in FP64.
+// Restarted GMRES on (I - K V) x = b for the instances with act[b] set, driven
+// from the device: each cycle computes the FP64 residual r = b - A x of the
+// active instances, krylov_cycle_start ends the solve of the converged (or
+// failed) ones and starts a cycle of the others (its Arnoldi cycle runs in the
+// working precision T, x accumulates in FP64). The host only launches cycles
+// and reads the active flags every few cycles; launches for finished instances
+// are no-ops.
 template <class T>
 static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act, const std::vector<double>& rtol,
                            std::vector<SolveStats>& stats, int transpose, int refl, hipStream_t s) {
@@ -580,63 +587,41 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   const long long n3 = g.sh.n3, bsv = (long long)(g.m + 1) * n3;
   Status st = set_mask(g, g.mask, act, s);
   if (!st.ok()) return st;
+  std::memcpy(g.h_dbl, rtol.data(), sizeof(double) * B);
+  HIPCHK(hipMemcpyAsync(g.rtol, g.h_dbl, sizeof(double) * B, hipMemcpyHostToDevice, s));
   vec_norm2<double2>(g.b, n3, n3, g.dpart, g.n2b, g.mask, B, s);
-  std::vector<double> bn2, rn2;
-  st = read_norms(g, g.n2b, bn2, s);
-  if (!st.ok()) return st;
-  std::vector<double> tgt(B, 0.0);
-  for (int b = 0; b < B; ++b) tgt[b] = rtol[b] * std::sqrt(bn2[b]);
-  std::memcpy(g.h_dbl, tgt.data(), sizeof(double) * B);
-  HIPCHK(hipMemcpyAsync(g.abs_target, g.h_dbl, sizeof(double) * B, hipMemcpyHostToDevice, s));
-  HIPCHK(hipStreamSynchronize(s));
-  std::vector<int> lin = act;
-  std::vector<int> its0(B, 0);
-  std::vector<GState> hs(B);
-  HIPCHK(hipMemcpyAsync(hs.data(), g.st, sizeof(GState) * B, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  for (int b = 0; b < B; ++b) its0[b] = hs[b].iters;
+  krylov_solve_init(g.st, g.n2b, g.rtol, g.abs_target, o.max_iters, g.mask, B, s);
   const double eta = g.prec == PSFD_MIXED ? o.inner_eta : 0.0;
-  for (;;) {
-    st = set_mask(g, g.mask, lin, s);
-    if (!st.ok()) return st;
+  // cycles between host checks: about CHECK_STEPS Arnoldi steps
+  const int check_every = std::max(1, CHECK_STEPS / g.m);
+  const int max_cycles = o.max_iters + 2;  // every cycle that starts takes at least one step
+  for (int cyc = 0; cyc < max_cycles; ++cyc) {
     apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, refl, g.mask, s);
     vec_axpby<double2, double2, double2>(g.r, g.b, g.r, 1.0, -1.0, n3, n3, g.mask, B, s);
     vec_norm2<double2>(g.r, n3, n3, g.dpart, g.n2, g.mask, B, s);
-    st = read_norms(g, g.n2, rn2, s);
-    if (!st.ok()) return st;
-    bool any = false;
-    for (int b = 0; b < B; ++b) {
-      if (!lin[b]) continue;
-      const double rn = std::sqrt(rn2[b]);
-      stats[b].rel_res = bn2[b] > 0 ? rn / std::sqrt(bn2[b]) : 0.0;
-      if (!std::isfinite(rn)) { stats[b].status = PSFD_ERR_NONFINITE; lin[b] = 0; continue; }
-      const int its = hs[b].iters - its0[b];
-      if (rn <= tgt[b] || bn2[b] == 0.0) { lin[b] = 0; continue; }
-      if (its >= o.max_iters) { stats[b].status = PSFD_NOT_CONVERGED; lin[b] = 0; continue; }
-      any = true;
-    }
-    if (!any) break;
-    st = set_mask(g, g.mask, lin, s);
-    if (!st.ok()) return st;
-    vec_scale_invsqrt<T, double2>((T*)g.basis, g.r, g.n2, n3, bsv, n3, g.mask, B, s);
-    HIPCHK(hipMemsetAsync(g.run, 0, sizeof(int) * B, s));
-    krylov_start(g.st, g.n2, g.abs_target, eta, g.m, reorth_threshold(), g.mask, g.run, B, s);
-    for (int b = 0; b < B; ++b) if (lin[b]) stats[b].cycles += 1;
-    for (int step = 0; step < g.m;) {
-      for (int k = 0; k < STEPS_PER_SYNC && step < g.m; ++k, ++step) arnoldi_step<T>(g, transpose, refl, s);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(g.h_run, g.run, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+    krylov_cycle_start(g.st, g.n2, g.abs_target, eta, g.m, reorth_threshold(), g.mask, g.run, g.cyc, B, s);
+    if (cyc % check_every == 0) {
+      HIPCHK(hipMemcpyAsync(g.h_run, g.mask, sizeof(int) * B, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       bool live = false;
       for (int b = 0; b < B; ++b) live |= g.h_run[b] != 0;
       if (!live) break;
     }
-    krylov_solve_small(g.st, g.mask, B, s);
-    krylov_lincomb<T, double2>((const T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.mask, B, s);
-    HIPCHK(hipMemcpyAsync(hs.data(), g.st, sizeof(GState) * B, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int b = 0; b < B; ++b)
-      if (lin[b]) stats[b].iters = hs[b].iters;
+    vec_scale_invsqrt<T, double2>((T*)g.basis, g.r, g.n2, n3, bsv, n3, g.cyc, B, s);
+    for (int step = 0; step < g.m; ++step) arnoldi_step<T>(g, transpose, refl, s);
+    krylov_solve_small(g.st, g.cyc, B, s);
+    krylov_lincomb<T, double2>((const T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.cyc, B, s);
+    HIPCHK(hipGetLastError());
+  }
+  std::vector<GState> hs(B);
+  HIPCHK(hipMemcpyAsync(hs.data(), g.st, sizeof(GState) * B, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int b = 0; b < B; ++b) {
+    if (!act[b]) continue;
+    stats[b].iters = hs[b].iters;
+    stats[b].cycles += hs[b].cycles;
+    stats[b].rel_res = hs[b].rel_res;
+    if (hs[b].status != PSFD_OK) stats[b].status = hs[b].status;
   }
   return Status();
 }

@@ -90,6 +90,8 @@ struct Group {
   int* run = nullptr;
   int* mask = nullptr;
   int* mask2 = nullptr;
+  int* cyc = nullptr;        // a restart cycle started for the instance (device-driven solve)
+  double* rtol = nullptr;    // relative tolerance per instance of the current linear solve
   double2* part = nullptr;
   double* n2 = nullptr;
   double* n2b = nullptr;

@@ -1,12 +1,17 @@
 // Krylov kernels of restarted GMRES (Saad & Schultz) with classical Gram-Schmidt
-// applied twice: batched multi-dot products, fused update + norm, one-thread
-// Givens/Hessenberg updates, back substitution and solution update. Vector
-// data may be FP32 or FP64; every dot product and norm accumulates in FP64.
+// and a conditional second pass: multi-dot products of the basis against the
+// new vector, fused update + norm, the Givens step of the new Hessenberg column,
+// back substitution, the solution update and the device-side cycle control.
+// Vector data may be FP32 or FP64; per-thread and per-wavefront partial sums
+// are in the vector precision, every sum across wavefronts and blocks is in
+// FP64 and in a fixed order (bitwise reproducible, independent of the batch).
 #include "krylov.hpp"
+#include "../../include/psfd.h"
 
 namespace psfd {
 
 static constexpr int KB = 256;  // threads per block of the vector kernels
+static constexpr int VG = 4;    // basis vectors loaded together in the Gram-Schmidt passes
 
 PSFD_D double wave_sum(double v) {
 #pragma unroll
@@ -74,8 +79,6 @@ PSFD_D double2 sum_partials(const double2* p, long long stride, int nblk, double
   return sm[0];
 }
 
-constexpr int PSTR = MAXM + 2;  // partial stride: up to MAXM dots + ||w||^2
-
 // element pairs: FP32 complex bases are read two at a time (16-byte loads)
 template <class T> struct Pair { T a, b; };
 template <class T> PSFD_D Pair<T> ld2(const T* p, long long e2) {
@@ -104,7 +107,61 @@ template <class T> PSFD_D void cfma_conj(T& acc, T v, T w) {
   acc.y += v.x * w.y - v.y * w.x;
 }
 
-// n must be even (fields are 3 nx ny nz complex with nx >= 4)
+// Givens step of column j of A's Hessenberg after the last Gram-Schmidt pass of
+// the step (run by one block). Arnoldi runs on B with A = I - B: column j of
+// A's Hessenberg is e_j - h, and v_{j+1} = -(B v_j - V h) / ||.|| keeps the
+// subdiagonal positive. The rotations of the earlier columns are staged in LDS
+// by the whole block, so the single-thread recurrence reads no global memory.
+PSFD_D void givens_step(GState& S, int* run_b) {
+  __shared__ double2 col[MAXM + 1], snl[MAXM];
+  __shared__ double csl[MAXM];
+  const int tid = threadIdx.x;
+  const int j = S.j;
+  if (tid <= j) col[tid] = make_double2((tid == j ? 1.0 : 0.0) - S.h[tid].x, -S.h[tid].y);
+  if (tid < j) { csl[tid] = S.cs[tid]; snl[tid] = S.sn[tid]; }
+  __syncthreads();
+  if (tid == 0) {
+    const double hn = sqrt(S.wn2);
+    for (int i = 0; i < j; ++i) {
+      const double2 a = col[i], c = col[i + 1];
+      const double2 sn = snl[i];
+      const double cs = csl[i];
+      col[i] = cadd(cscale(a, cs), cmul(sn, c));
+      col[i + 1] = csub(cscale(c, cs), cmulc(a, sn) /* a * conj(sn) */);
+    }
+    const double2 a = col[j];
+    const double aa = sqrt(cabs2(a));
+    const double den = hypot(aa, hn);
+    double cs;
+    double2 sn;
+    if (aa == 0.0) { cs = 0.0; sn = make_double2(1.0, 0.0); }
+    else { cs = aa / den; sn = make_double2(a.x / aa * hn / den, a.y / aa * hn / den); }
+    col[j] = cadd(cscale(a, cs), cscale(sn, hn));
+    S.cs[j] = cs;
+    S.sn[j] = sn;
+    const double2 gj = S.g[j];
+    // g_{j+1} = -conj(sn) g_j ; g_j = cs g_j
+    const double2 gn = cmul(make_double2(sn.x, -sn.y), gj);
+    S.g[j + 1] = make_double2(-gn.x, -gn.y);
+    S.g[j] = cscale(gj, cs);
+    S.res = sqrt(cabs2(S.g[j + 1]));
+    S.iters += 1;
+    S.ncols = j + 1;
+    S.inv_norm = hn > 0.0 ? -1.0 / hn : 0.0;
+    S.conv = S.res <= S.target;
+    S.jcur = j;
+    const bool breakdown = !(hn > 1e-300 * (S.beta > 0 ? S.beta : 1.0));
+    S.stop = S.conv || (j + 1 >= S.m) || breakdown || !(S.res == S.res);
+    *run_b = S.stop ? 0 : 1;
+  }
+  __syncthreads();
+  if (tid <= j) S.H[tid][j] = col[tid];
+}
+
+// Classical Gram-Schmidt pass, projections: per-block partial sums of
+// hc_i = <v_i, w> (i <= j) and of ||w||^2 for the new vector w = v_{j+1}. The
+// second pass runs only for instances whose first pass set reorth. n must be
+// even (fields are 3 nx ny nz complex with nx >= 4).
 template <class T>
 __global__ void __launch_bounds__(KB) k_dots(const T* V, long long ldv, long long bsv, long long n, GState* st,
                                              const int* run, int first, double2* part) {
@@ -120,12 +177,21 @@ __global__ void __launch_bounds__(KB) k_dots(const T* V, long long ldv, long lon
   const long long n2 = n >> 1;
   for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n2; e += (long long)gridDim.x * KB) {
     const Pair<T> wv = ld2(wb, e);
+    // basis vectors in groups of VG: the loads of a group are unconditional
+    // (index clamped to the last vector) so that they are all in flight together
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-      if (i < cnt) {
-        const Pair<T> v = ld2(Vb + (long long)i * ldv, e);
-        cfma_conj(acc[i], v.a, wv.a);
-        cfma_conj(acc[i], v.b, wv.b);
+    for (int i0 = 0; i0 < MAXM; i0 += VG) {
+      if (i0 < cnt) {
+        Pair<T> v[VG];
+#pragma unroll
+        for (int u = 0; u < VG; ++u) v[u] = ld2(Vb + (long long)min(i0 + u, cnt - 1) * ldv, e);
+#pragma unroll
+        for (int u = 0; u < VG; ++u) {
+          if (i0 + u < cnt) {
+            cfma_conj(acc[i0 + u], v[u].a, wv.a);
+            cfma_conj(acc[i0 + u], v[u].b, wv.b);
+          }
+        }
       }
     }
     // ||w||^2 in the slot after the last dot
@@ -137,6 +203,8 @@ __global__ void __launch_bounds__(KB) k_dots(const T* V, long long ldv, long lon
   if ((int)threadIdx.x <= cnt) part[((long long)b * gridDim.x + blockIdx.x) * PSTR + threadIdx.x] = sm[threadIdx.x];
 }
 
+// totals of the projections over the nblk partials, fixed order (deterministic):
+// h = hc on the first pass, h += hc on the second; wn2_in = ||w||^2
 __global__ void __launch_bounds__(KB) k_dots_final(GState* st, const int* run, const double2* part, int nblk,
                                                    int first) {
   __shared__ double2 sm[KB / 64];
@@ -154,12 +222,16 @@ __global__ void __launch_bounds__(KB) k_dots_final(GState* st, const int* run, c
 template <class T>
 void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
                  double2* part, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL((k_dots<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, run, first, part);
-  hipLaunchKernelGGL(k_dots_final, dim3(MAXM + 1, nbatch), dim3(KB), 0, s, st, run, (const double2*)part,
-                     RED_BLOCKS, first);
+  // the second pass is rare: a smaller grid keeps its launches cheap when they have nothing to do
+  const int nblk = first ? RED_BLOCKS : RED_BLOCKS / 4;
+  hipLaunchKernelGGL((k_dots<T>), dim3(nblk, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, run, first, part);
+  hipLaunchKernelGGL(k_dots_final, dim3(MAXM + 1, nbatch), dim3(KB), 0, s, st, run, (const double2*)part, nblk,
+                     first);
 }
 
 // ---------------------------------------------------------------------------
+// Classical Gram-Schmidt pass, update: w -= sum_{i<=j} hc_i v_i, with per-block
+// partial sums of ||w||^2 afterwards.
 template <class T>
 __global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bsv, long long n, GState* st,
                                                const int* run, int first, double2* part) {
@@ -176,18 +248,25 @@ __global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bs
   const long long n2 = n >> 1;
   for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n2; e += (long long)gridDim.x * KB) {
     T a0 = cmake<T>(0, 0), a1 = cmake<T>(0, 0);
+    Pair<T> wv = ld2(wb, e);
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-      if (i < cnt) {
-        const Pair<T> v = ld2(Vb + (long long)i * ldv, e);
-        const T h = hs[i];
-        a0.x += h.x * v.a.x - h.y * v.a.y;
-        a0.y += h.x * v.a.y + h.y * v.a.x;
-        a1.x += h.x * v.b.x - h.y * v.b.y;
-        a1.y += h.x * v.b.y + h.y * v.b.x;
+    for (int i0 = 0; i0 < MAXM; i0 += VG) {
+      if (i0 < cnt) {
+        Pair<T> v[VG];
+#pragma unroll
+        for (int u = 0; u < VG; ++u) v[u] = ld2(Vb + (long long)min(i0 + u, cnt - 1) * ldv, e);
+#pragma unroll
+        for (int u = 0; u < VG; ++u) {
+          if (i0 + u < cnt) {
+            const T h = hs[i0 + u];
+            a0.x += h.x * v[u].a.x - h.y * v[u].a.y;
+            a0.y += h.x * v[u].a.y + h.y * v[u].a.x;
+            a1.x += h.x * v[u].b.x - h.y * v[u].b.y;
+            a1.y += h.x * v[u].b.y + h.y * v[u].b.x;
+          }
+        }
       }
     }
-    Pair<T> wv = ld2(wb, e);
     wv.a.x -= a0.x; wv.a.y -= a0.y;
     wv.b.x -= a1.x; wv.b.y -= a1.y;
     st2(wb, e, wv);
@@ -197,81 +276,41 @@ __global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bs
   if (threadIdx.x == 0) part[((long long)b * gridDim.x + blockIdx.x)] = sm[0];
 }
 
-__global__ void __launch_bounds__(KB) k_update_final(GState* st, const int* run, const double2* part, int nblk,
+// ||w||^2 over the nblk partials (fixed order). After the first pass: decide the
+// second (||w||^2 fell below reorth_thr times its value before the pass); after
+// the last pass of the step: the Givens step.
+__global__ void __launch_bounds__(KB) k_update_final(GState* st, int* run, const double2* part, int nblk,
                                                      int first) {
   __shared__ double2 sm[KB / 64];
+  __shared__ int do_givens;
   const int b = blockIdx.x;
   if (!run[b] || (!first && !st[b].reorth)) return;
   const double2 t = sum_partials(part + (long long)b * nblk, 1, nblk, sm);
-  if (threadIdx.x != 0) return;
   GState& S = st[b];
-  S.wn2 = t.x;
-  if (first) {
-    // second pass when the projection removed more than half of ||w||^2
-    S.reorth = (t.x < S.reorth_thr * S.wn2_in) ? 1 : 0;
-    S.nreorth += S.reorth;
-  } else {
-    S.reorth = 0;
+  if (threadIdx.x == 0) {
+    S.wn2 = t.x;
+    if (first) {
+      S.reorth = (t.x < S.reorth_thr * S.wn2_in) ? 1 : 0;
+      S.nreorth += S.reorth;
+    } else {
+      S.reorth = 0;
+    }
+    do_givens = !first || !S.reorth;
   }
+  __syncthreads();
+  if (do_givens) givens_step(S, run + b);
 }
 
 template <class T>
-void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
-                   double2* part, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL((k_update<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, run, first, part);
-  hipLaunchKernelGGL(k_update_final, dim3(nbatch), dim3(KB), 0, s, st, run, (const double2*)part, RED_BLOCKS, first);
+void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run, int first, double2* part,
+                   int nbatch, hipStream_t s) {
+  const int nblk = first ? RED_BLOCKS : RED_BLOCKS / 4;
+  hipLaunchKernelGGL((k_update<T>), dim3(nblk, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, (const int*)run, first,
+                     part);
+  hipLaunchKernelGGL(k_update_final, dim3(nbatch), dim3(KB), 0, s, st, run, (const double2*)part, nblk, first);
 }
 
 // ---------------------------------------------------------------------------
-__global__ void k_givens(GState* st, int* run) {
-  const int b = blockIdx.x;
-  if (threadIdx.x != 0 || !run[b]) return;
-  GState& S = st[b];
-  const int j = S.j;
-  // Arnoldi runs on B with A = I - B: column j of A's Hessenberg is e_j - h,
-  // and v_{j+1} = -(B v_j - V h) / ||.|| keeps the subdiagonal positive
-  double2 col[MAXM + 1];
-  for (int i = 0; i <= j; ++i) col[i] = make_double2((i == j ? 1.0 : 0.0) - S.h[i].x, -S.h[i].y);
-  const double hn = sqrt(S.wn2);
-  for (int i = 0; i < j; ++i) {
-    double2 a = col[i], c = col[i + 1];
-    double2 sn = S.sn[i];
-    double cs = S.cs[i];
-    col[i] = cadd(cscale(a, cs), cmul(sn, c));
-    col[i + 1] = csub(cscale(c, cs), cmulc(a, sn) /* a * conj(sn) */);
-  }
-  double2 a = col[j];
-  double aa = sqrt(cabs2(a));
-  double den = hypot(aa, hn);
-  double cs;
-  double2 sn;
-  if (aa == 0.0) { cs = 0.0; sn = make_double2(1.0, 0.0); }
-  else { cs = aa / den; sn = make_double2(a.x / aa * hn / den, a.y / aa * hn / den); }
-  col[j] = cadd(cscale(a, cs), cscale(sn, hn));
-  S.cs[j] = cs;
-  S.sn[j] = sn;
-  double2 gj = S.g[j];
-  // g_{j+1} = -conj(sn) g_j ; g_j = cs g_j
-  double2 csn = make_double2(sn.x, -sn.y);
-  double2 gn = cmul(csn, gj);
-  S.g[j + 1] = make_double2(-gn.x, -gn.y);
-  S.g[j] = cscale(gj, cs);
-  for (int i = 0; i <= j; ++i) S.H[i][j] = col[i];
-  S.res = sqrt(cabs2(S.g[j + 1]));
-  S.iters += 1;
-  S.ncols = j + 1;
-  S.inv_norm = hn > 0.0 ? -1.0 / hn : 0.0;
-  S.conv = S.res <= S.target;
-  S.jcur = j;
-  const bool breakdown = !(hn > 1e-300 * (S.beta > 0 ? S.beta : 1.0));
-  S.stop = S.conv || (j + 1 >= S.m) || breakdown || !(S.res == S.res);
-  run[b] = S.stop ? 0 : 1;
-}
-
-void krylov_givens(GState* st, int* run, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL(k_givens, dim3(nbatch), dim3(64), 0, s, st, run);
-}
-
 // v_{j+1} *= inv_norm. The index j is read from jcur (a copy made by the Givens
 // step) so that block 0 can advance st[b].j without racing the other blocks.
 template <class T>
@@ -292,21 +331,12 @@ __global__ void __launch_bounds__(KB) k_scale_next(T* V, long long ldv, long lon
   }
 }
 
-__global__ void k_advance(GState* st) {
-  const int b = blockIdx.x;
-  if (threadIdx.x == 0 && !st[b].stop) st[b].j += 1;
-}
-
 template <class T>
 void krylov_scale_next(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int nbatch,
                        hipStream_t s) {
   int nb = (int)((n + KB - 1) / KB);
   if (nb > 1024) nb = 1024;
   hipLaunchKernelGGL((k_scale_next<T>), dim3(nb, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, run);
-}
-
-void krylov_advance(GState* st, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL(k_advance, dim3(nbatch), dim3(64), 0, s, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -340,14 +370,19 @@ __global__ void __launch_bounds__(KB) k_lincomb(const T* V, long long ldv, long 
   TX* xb = x + (long long)b * bsx;
   for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
     double2 s = make_double2(0, 0);
+    const double2 xv = to_d(xb[e]);
+    // basis vectors in groups of VG with unconditional (clamped) loads, all in flight together
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-      if (i < k) {
-        double2 v = to_d(Vb[(long long)i * ldv + e]);
-        s = cadd(s, cmul(ys[i], v));
+    for (int i0 = 0; i0 < MAXM; i0 += VG) {
+      if (i0 < k) {
+        T v[VG];
+#pragma unroll
+        for (int u = 0; u < VG; ++u) v[u] = Vb[(long long)min(i0 + u, k - 1) * ldv + e];
+#pragma unroll
+        for (int u = 0; u < VG; ++u)
+          if (i0 + u < k) s = cadd(s, cmul(ys[i0 + u], to_d(v[u])));
       }
     }
-    double2 xv = to_d(xb[e]);
     xb[e] = from_d<TX>(cadd(xv, s));
   }
 }
@@ -380,6 +415,60 @@ __global__ void k_start(GState* st, const double* rnorm2, const double* abs_targ
   const bool go = rn > abs_target[b] && rn > 0.0 && rn == rn;
   S.stop = go ? 0 : 1;
   run[b] = go ? 1 : 0;
+}
+
+__global__ void k_solve_init(GState* st, const double* bnorm2, const double* rtol, double* abs_target, int max_iters,
+                             const int* act) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0 || !act[b]) return;
+  GState& S = st[b];
+  S.bnorm = sqrt(bnorm2[b]);
+  abs_target[b] = rtol[b] * S.bnorm;
+  S.iter_limit = S.iters + max_iters;
+  S.cycles = 0;
+  S.status = PSFD_OK;
+  S.rel_res = 0.0;
+}
+
+void krylov_solve_init(GState* st, const double* bnorm2, const double* rtol, double* abs_target, int max_iters,
+                       const int* act, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_solve_init, dim3(nbatch), dim3(64), 0, s, st, bnorm2, rtol, abs_target, max_iters, act);
+}
+
+__global__ void k_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
+                              double reorth_thr, int* act, int* run, int* cyc) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  cyc[b] = 0;
+  run[b] = 0;
+  if (!act[b]) return;
+  GState& S = st[b];
+  const double rn = sqrt(rnorm2[b]);
+  S.rel_res = S.bnorm > 0 ? rn / S.bnorm : 0.0;
+  if (!(rn == rn) || isinf(rn)) { S.status = PSFD_ERR_NONFINITE; act[b] = 0; return; }
+  if (rn <= abs_target[b] || S.bnorm == 0.0) { act[b] = 0; return; }
+  if (S.iters >= S.iter_limit) { S.status = PSFD_NOT_CONVERGED; act[b] = 0; return; }
+  S.j = 0;
+  S.m = m;
+  S.reorth_thr = reorth_thr;
+  S.ncols = 0;
+  S.beta = rn;
+  S.g[0] = make_double2(rn, 0.0);
+  for (int i = 1; i <= MAXM; ++i) S.g[i] = make_double2(0, 0);
+  const double t = eta * rn;
+  S.target = abs_target[b] > t ? abs_target[b] : t;
+  S.res = rn;
+  S.conv = 0;
+  S.stop = 0;
+  S.cycles += 1;
+  cyc[b] = 1;
+  run[b] = 1;
+}
+
+void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
+                        double reorth_thr, int* act, int* run, int* cyc, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_start, dim3(nbatch), dim3(64), 0, s, st, rnorm2, abs_target, eta, m, reorth_thr, act, run,
+                     cyc);
 }
 
 void krylov_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
@@ -425,19 +514,24 @@ __global__ void __launch_bounds__(KB) k_norm2(const T* x, long long n, long long
   if (threadIdx.x == 0) part[(long long)b * gridDim.x + blockIdx.x] = sm[0].x;
 }
 
-__global__ void k_sum_part(const double* part, int nblk, double* out, const int* mask) {
+// sum of the nblk partials of instance b, fixed order (thread t adds partials
+// t, t + KB, ..., then a fixed block tree)
+__global__ void __launch_bounds__(KB) k_sum_part(const double* part, int nblk, double* out, const int* mask) {
+  __shared__ double2 sm[KB / 64];
   const int b = blockIdx.x;
-  if (threadIdx.x != 0 || (mask && !mask[b])) return;
+  if (mask && !mask[b]) return;
   double t = 0;
-  for (int k = 0; k < nblk; ++k) t += part[(long long)b * nblk + k];
-  out[b] = t;
+  for (int k = threadIdx.x; k < nblk; k += KB) t += part[(long long)b * nblk + k];
+  double2 acc[1] = {make_double2(t, 0.0)};
+  block_sum<1>(acc, 1, sm);
+  if (threadIdx.x == 0) out[b] = sm[0].x;
 }
 
 template <class T>
 void vec_norm2(const T* x, long long n, long long bstride, double* part, double* out, const int* mask,
                int nbatch, hipStream_t s) {
   hipLaunchKernelGGL((k_norm2<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, x, n, bstride, part, mask);
-  hipLaunchKernelGGL(k_sum_part, dim3(nbatch), dim3(64), 0, s, (const double*)part, RED_BLOCKS, out, mask);
+  hipLaunchKernelGGL(k_sum_part, dim3(nbatch), dim3(KB), 0, s, (const double*)part, RED_BLOCKS, out, mask);
 }
 
 template <class T>
@@ -460,20 +554,28 @@ __global__ void __launch_bounds__(KB) k_diff2(const T* x, const T* y, long long 
   }
 }
 
-__global__ void k_sum_part2(const double* part, int nblk, double* out) {
+// the two sums of k_diff2's partials, fixed order
+__global__ void __launch_bounds__(KB) k_sum_part2(const double* part, int nblk, double* out) {
+  __shared__ double2 sm[(KB / 64) * 2];
   const int b = blockIdx.x;
-  if (threadIdx.x != 0) return;
   double t0 = 0, t1 = 0;
-  for (int k = 0; k < nblk; ++k) { t0 += part[((long long)b * nblk + k) * 2]; t1 += part[((long long)b * nblk + k) * 2 + 1]; }
-  out[2 * b] = t0;
-  out[2 * b + 1] = t1;
+  for (int k = threadIdx.x; k < nblk; k += KB) {
+    t0 += part[((long long)b * nblk + k) * 2];
+    t1 += part[((long long)b * nblk + k) * 2 + 1];
+  }
+  double2 acc[2] = {make_double2(t0, 0.0), make_double2(t1, 0.0)};
+  block_sum<2>(acc, 2, sm);
+  if (threadIdx.x == 0) {
+    out[2 * b] = sm[0].x;
+    out[2 * b + 1] = sm[1].x;
+  }
 }
 
 template <class T>
 void vec_diff2(const T* x, const T* y, long long n, long long bstride, double* part, double* out,
                int nbatch, hipStream_t s) {
   hipLaunchKernelGGL((k_diff2<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, x, y, n, bstride, part);
-  hipLaunchKernelGGL(k_sum_part2, dim3(nbatch), dim3(64), 0, s, (const double*)part, RED_BLOCKS, out);
+  hipLaunchKernelGGL(k_sum_part2, dim3(nbatch), dim3(KB), 0, s, (const double*)part, RED_BLOCKS, out);
 }
 
 template <class TO, class TX>
@@ -504,8 +606,8 @@ void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long
 #define INST_T(T)                                                                                       \
   template void krylov_dots<T>(const T*, long long, long long, long long, GState*, const int*, int,      \
                                double2*, int, hipStream_t);                                             \
-  template void krylov_update<T>(T*, long long, long long, long long, GState*, const int*, int, double2*,\
-                                 int, hipStream_t);                                                     \
+  template void krylov_update<T>(T*, long long, long long, long long, GState*, int*, int, double2*, int, \
+                                 hipStream_t);                                                          \
   template void krylov_scale_next<T>(T*, long long, long long, long long, GState*, const int*, int,      \
                                      hipStream_t);                                                      \
   template void vec_norm2<T>(const T*, long long, long long, double*, double*, const int*, int,          \

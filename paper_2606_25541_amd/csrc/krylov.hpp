@@ -12,6 +12,7 @@ namespace psfd {
 
 constexpr int MAXM = 32;          // largest supported restart length
 constexpr int RED_BLOCKS = 1024;  // blocks per instance of the first reduction stage
+constexpr int PSTR = MAXM + 2;    // partial stride: up to MAXM + 1 dots and ||w||^2
 
 // Device-resident state of one GMRES(m) instance. All scalars are FP64.
 struct GState {
@@ -31,7 +32,11 @@ struct GState {
   double wn2_in;    // ||w||^2 before the pass
   double reorth_thr;  // second pass when ||w||^2 after the first < reorth_thr * ||w||^2 before
   int jcur;         // column index of the step in flight (read by the scale kernel)
-  int pad3;
+  int cycles;       // restart cycles of the current linear solve
+  int status;       // PSFD_OK, PSFD_NOT_CONVERGED or PSFD_ERR_NONFINITE (linear solve)
+  int iter_limit;   // the linear solve stops once iters reaches it
+  double bnorm;     // ||b|| of the current linear solve
+  double rel_res;   // ||b - A x|| / ||b|| at the last FP64 residual
   double2 H[MAXM + 1][MAXM];  // rotated Hessenberg matrix (upper triangle used)
   double cs[MAXM];
   double2 sn[MAXM];
@@ -47,28 +52,41 @@ struct GState {
 // against the identity part).
 // Classical Gram-Schmidt pass on w = v_{j+1} (the new apply output):
 // hc[i] = <v_i, w> for i = 0..j and wn2_in = ||w||^2 (h = hc on the first
-// pass, h += hc on the second). The second pass (first == 0) runs only when the
-// first left ||w|| below ||w_in|| / sqrt(2) ("twice is enough").
+// pass, h += hc on the second). The second pass (first == 0) runs only for
+// instances whose first pass left ||w||^2 below reorth_thr times its value
+// before the pass. part: RED_BLOCKS * PSTR complex values per instance.
 template <class T>
 void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
                  double2* part, int nbatch, hipStream_t s);
-// w = v_{j+1}: w -= sum_{i<=j} hc_i v_i ; wn2 = ||w||^2 afterwards; decides reorth
+// w = v_{j+1}: w -= sum_{i<=j} hc_i v_i ; wn2 = ||w||^2 afterwards; after the
+// first pass decides the second; after the last pass of the step takes the
+// Givens step (rotated Hessenberg column, residual estimate, inv_norm, stop/run)
 template <class T>
-void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
+void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run, int first,
                    double2* part, int nbatch, hipStream_t s);
-// Givens rotation of the new Hessenberg column, residual estimate, inv_norm, stop/run flags
-void krylov_givens(GState* st, int* run, int nbatch, hipStream_t s);
 // v_{j+1} *= inv_norm (in place) and j <- j + 1, for instances still running
 template <class T>
 void krylov_scale_next(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int nbatch,
                        hipStream_t s);
-void krylov_advance(GState* st, int nbatch, hipStream_t s);
 // y = H^{-1} g over the k = j + 1 completed columns
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s);
 // x += sum_{i<k} y_i v_i
 template <class T, class TX>
 void krylov_lincomb(const T* V, long long ldv, long long bsv, TX* x, long long bsx, long long n,
                     GState* st, const int* mask, int nbatch, hipStream_t s);
+// Device-driven restarted solve of the instances with act[b] set.
+// krylov_solve_init: bnorm = sqrt(bnorm2[b]), abs_target[b] = rtol[b] bnorm,
+// iter_limit = iters + max_iters, cycles = 0, status = PSFD_OK.
+void krylov_solve_init(GState* st, const double* bnorm2, const double* rtol, double* abs_target, int max_iters,
+                       const int* act, int nbatch, hipStream_t s);
+// krylov_cycle_start, after the FP64 residual of an active instance (rnorm2[b]):
+// records rel_res, then ends the instance's solve (act[b] = 0) when the residual
+// meets abs_target[b] (or b = 0), is not finite (status NONFINITE) or the
+// iteration limit is reached (status NOT_CONVERGED); otherwise starts a cycle
+// like krylov_start. cyc[b] and run[b] are set for the instances whose cycle
+// starts and cleared for all others.
+void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
+                        double reorth_thr, int* act, int* run, int* cyc, int nbatch, hipStream_t s);
 // start a cycle from rnorm2[b] = ||r_b||^2: g = (||r||, 0, ...), j = 0,
 // target = max(abs_target[b], eta ||r||); run[b] = mask[b] && ||r|| > abs_target[b]
 void krylov_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
