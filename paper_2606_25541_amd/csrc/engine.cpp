@@ -396,7 +396,7 @@ static TileArgs tile_base(const Group& g, const void* tw, const TileShape& t) {
 
 template <class T>
 void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose,
-                 int refl, const int* active, hipStream_t s) {
+                 int refl, const int* active, hipStream_t s, const double* in_scale, long long scale_stride) {
   const Shape& sh = g.sh;
   const XYCfg c = xy_config(sh, sizeof(T));
   const int np = 3 * sh.nz;
@@ -407,10 +407,12 @@ void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* w
     if (c.fused) {
       TileArgs a = tile_base(g, tw, c.full);
       a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
+      a.in_scale = in_scale; a.scale_stride = scale_stride;
       launch_tile<T, false, LD_VX, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
     } else {
       TileArgs a = tile_base(g, tw, c.rows);
       a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
+      a.in_scale = in_scale; a.scale_stride = scale_stride;
       launch_tile<T, false, LD_VX, ST_PLAIN>(a, np, g.B, c.rows.nthr, c.rows.lds, s);
       TileArgs b2 = tile_base(g, tw, c.cols);
       b2.in = wsr; b2.out = wsr; b2.active = active;
@@ -427,37 +429,38 @@ void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* w
     p.active = active;
     launch_pencil<T>(p, g.B, z.nthr, z.lds, s);
   } else {
-    // inverse: out = alpha in + gamma IFFT_xy(w)
-    const double al = kmode == 0 ? 1.0 : 0.0, ga = kmode == 0 ? -1.0 : 1.0;
+    // inverse: out = in - IFFT_xy(w) (kmode 0) or out = IFFT_xy(w) (kmode 1, no read of in)
     if (c.fused) {
       TileArgs a = tile_base(g, tw, c.full);
-      a.in = wsr; a.aux = in; a.out = out; a.alpha = al; a.gamma = ga; a.active = active;
-      launch_tile<T, true, LD_PLAIN, ST_AXPBY>(a, np, g.B, c.full.nthr, c.full.lds, s);
+      a.in = wsr; a.aux = in; a.out = out; a.alpha = 1.0; a.gamma = -1.0; a.active = active;
+      if (kmode == 0) launch_tile<T, true, LD_PLAIN, ST_AXPBY>(a, np, g.B, c.full.nthr, c.full.lds, s);
+      else launch_tile<T, true, LD_PLAIN, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
     } else {
       TileArgs a = tile_base(g, tw, c.cols);
       a.in = wsr; a.out = wsr; a.active = active;
       launch_tile<T, true, LD_PLAIN, ST_PLAIN>(a, np, g.B, c.cols.nthr, c.cols.lds, s);
       TileArgs b2 = tile_base(g, tw, c.rows);
-      b2.in = wsr; b2.aux = in; b2.out = out; b2.alpha = al; b2.gamma = ga; b2.active = active;
-      launch_tile<T, true, LD_PLAIN, ST_AXPBY>(b2, np, g.B, c.rows.nthr, c.rows.lds, s);
+      b2.in = wsr; b2.aux = in; b2.out = out; b2.alpha = 1.0; b2.gamma = -1.0; b2.active = active;
+      if (kmode == 0) launch_tile<T, true, LD_PLAIN, ST_AXPBY>(b2, np, g.B, c.rows.nthr, c.rows.lds, s);
+      else launch_tile<T, true, LD_PLAIN, ST_PLAIN>(b2, np, g.B, c.rows.nthr, c.rows.lds, s);
     }
   }
 }
 template void apply_stage<float2>(Group&, int, const float2*, VecRef, VecRef, float2*, int, int, int, const int*,
-                                  hipStream_t);
+                                  hipStream_t, const double*, long long);
 template void apply_stage<double2>(Group&, int, const double2*, VecRef, VecRef, double2*, int, int, int,
-                                   const int*, hipStream_t);
+                                   const int*, hipStream_t, const double*, long long);
 
 template <class T>
 void apply_op(Group& g, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose, int refl,
-              const int* active, hipStream_t s) {
+              const int* active, hipStream_t s, const double* in_scale, long long scale_stride) {
   for (int stage = 0; stage < 3; ++stage)
-    apply_stage<T>(g, stage, deps, in, out, ws, kmode, transpose, refl, active, s);
+    apply_stage<T>(g, stage, deps, in, out, ws, kmode, transpose, refl, active, s, in_scale, scale_stride);
 }
 template void apply_op<float2>(Group&, const float2*, VecRef, VecRef, float2*, int, int, int, const int*,
-                               hipStream_t);
+                               hipStream_t, const double*, long long);
 template void apply_op<double2>(Group&, const double2*, VecRef, VecRef, double2*, int, int, int, const int*,
-                                hipStream_t);
+                                hipStream_t, const double*, long long);
 
 // e = E_inc + IFFT_xy(E_up exp(i beta z)) per plane (FP64)
 void inject(Group& g, const double2* eup, double2* out, const int* active, hipStream_t s) {
@@ -562,12 +565,14 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s) {
   vin.idx = &g.st[0].j; vin.idx_stride = (int)(sizeof(GState) / sizeof(int)); vin.joff = 0;
   VecRef vout = vin;
   vout.joff = 1;
-  apply_op<T>(g, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s);  // B v_j
+  // B v_j; slot j still holds the unnormalised vector of the previous step: the
+  // first apply kernel scales it by inv_norm on load and writes v_j back
+  apply_op<T>(g, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, &g.st[0].inv_norm,
+              (long long)(sizeof(GState) / sizeof(double)));
   krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 1, g.part, g.B, s);
   krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 1, g.part, g.B, s);
   krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 0, g.part, g.B, s);
-  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 0, g.part, g.B, s);  // and the Givens step
-  krylov_scale_next<T>(V, n3, bsv, n3, g.st, g.run, g.B, s);  // also advances j
+  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 0, g.part, g.B, s);  // Givens step, j <- j + 1
 }
 
 template void arnoldi_step<float2>(Group&, int, int, hipStream_t);

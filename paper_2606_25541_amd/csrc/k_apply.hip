@@ -53,6 +53,9 @@ __global__ void __launch_bounds__(1024) k_tile(TileArgs a) {
   constexpr int KG = 8;
   // in-plane offset of element i (32-bit: a plane holds at most 2^16 elements)
   auto off_of = [&](int i) -> int { return (y0 + (i >> ltx)) * nxa + (x0 + (i & (tx - 1))); };
+  // normalisation on load of the newest Arnoldi vector, written back (skipped at scale 1)
+  const R sc = (LD == LD_VX && a.in_scale) ? (R)a.in_scale[(long long)b * a.scale_stride] : (R)1;
+  T* inw = vref<T>(a.in, b) + poff;
   if (LD == LD_PLAIN || LD == LD_VX) {
 #pragma unroll 1
     for (int g = 0; g < KT; g += KG) {
@@ -70,7 +73,12 @@ __global__ void __launch_bounds__(1024) k_tile(TileArgs a) {
       for (int k = 0; k < KG; ++k) {
         const int i = tid + (g + k) * nthr;
         if (i < ntile) {
-          const T v = LD == LD_VX ? cscale(cmul(vb[k], va[k]), k0sq) : va[k];
+          T x = va[k];
+          if (LD == LD_VX && sc != (R)1) {
+            x.x *= sc; x.y *= sc;
+            inw[off_of(i)] = x;
+          }
+          const T v = LD == LD_VX ? cscale(cmul(vb[k], x), k0sq) : x;
           lds[(i >> ltx) * pitch + (i & (tx - 1))] = v;
         }
       }
@@ -207,10 +215,18 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   }
   const double* tab = a.tab + (long long)b * a.tab_stride;
   const R k0sq = (R)tab[TS_K0SQ];
+  // normalisation on load of the newest Arnoldi vector, written back (skipped at scale 1)
+  const R sc = (LD == LD_VX && a.in_scale) ? (R)a.in_scale[(long long)b * a.scale_stride] : (R)1;
+  T* inw = vref<T>(a.in, b) + poff;
   if (tid < N) twl[tid] = tw0;
   auto put = [&](int k) {
     const int i = tid + k * NT;
-    const T v = LD == LD_VX ? cscale(cmul(vb[LD == LD_VX ? k : 0], va[k]), k0sq) : va[k];
+    T x = va[k];
+    if (LD == LD_VX && sc != (R)1) {
+      x.x *= sc; x.y *= sc;
+      inw[i] = x;
+    }
+    const T v = LD == LD_VX ? cscale(cmul(vb[LD == LD_VX ? k : 0], x), k0sq) : x;
     lds[(i >> LN) * P + (i & (N - 1))] = v;
   };
   typedef FftCT<LN, N, P, 1, NT> Rows;

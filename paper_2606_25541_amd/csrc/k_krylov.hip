@@ -150,6 +150,7 @@ PSFD_D void givens_step(GState& S, int* run_b) {
     S.inv_norm = hn > 0.0 ? -1.0 / hn : 0.0;
     S.conv = S.res <= S.target;
     S.jcur = j;
+    S.j = j + 1;  // slot j + 1 holds the unnormalised new vector; the next apply scales it
     const bool breakdown = !(hn > 1e-300 * (S.beta > 0 ? S.beta : 1.0));
     S.stop = S.conv || (j + 1 >= S.m) || breakdown || !(S.res == S.res);
     *run_b = S.stop ? 0 : 1;
@@ -311,34 +312,6 @@ void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, 
 }
 
 // ---------------------------------------------------------------------------
-// v_{j+1} *= inv_norm. The index j is read from jcur (a copy made by the Givens
-// step) so that block 0 can advance st[b].j without racing the other blocks.
-template <class T>
-__global__ void __launch_bounds__(KB) k_scale_next(T* V, long long ldv, long long bsv, long long n, GState* st,
-                                                   const int* run) {
-  const int b = blockIdx.y;
-  if (!run[b]) return;
-  const int j = st[b].jcur;
-  if (blockIdx.x == 0 && threadIdx.x == 0) st[b].j = j + 1;
-  typedef typename real_of<T>::type R;
-  const R sc = (R)st[b].inv_norm;
-  T* v = V + (long long)b * bsv + (long long)(j + 1) * ldv;
-  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
-    T t = v[e];
-    t.x *= sc;
-    t.y *= sc;
-    v[e] = t;
-  }
-}
-
-template <class T>
-void krylov_scale_next(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int nbatch,
-                       hipStream_t s) {
-  int nb = (int)((n + KB - 1) / KB);
-  if (nb > 1024) nb = 1024;
-  hipLaunchKernelGGL((k_scale_next<T>), dim3(nb, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, run);
-}
-
 // ---------------------------------------------------------------------------
 __global__ void k_solve_small(GState* st, const int* mask) {
   const int b = blockIdx.x;
@@ -412,6 +385,7 @@ __global__ void k_start(GState* st, const double* rnorm2, const double* abs_targ
   S.target = abs_target[b] > t ? abs_target[b] : t;
   S.res = rn;
   S.conv = 0;
+  S.inv_norm = 1.0;  // v_0 is stored normalised
   const bool go = rn > abs_target[b] && rn > 0.0 && rn == rn;
   S.stop = go ? 0 : 1;
   run[b] = go ? 1 : 0;
@@ -460,6 +434,7 @@ __global__ void k_cycle_start(GState* st, const double* rnorm2, const double* ab
   S.res = rn;
   S.conv = 0;
   S.stop = 0;
+  S.inv_norm = 1.0;  // v_0 is stored normalised
   S.cycles += 1;
   cyc[b] = 1;
   run[b] = 1;
@@ -608,8 +583,6 @@ void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long
                                double2*, int, hipStream_t);                                             \
   template void krylov_update<T>(T*, long long, long long, long long, GState*, int*, int, double2*, int, \
                                  hipStream_t);                                                          \
-  template void krylov_scale_next<T>(T*, long long, long long, long long, GState*, const int*, int,      \
-                                     hipStream_t);                                                      \
   template void vec_norm2<T>(const T*, long long, long long, double*, double*, const int*, int,          \
                              hipStream_t);                                                              \
   template void vec_diff2<T>(const T*, const T*, long long, long long, double*, double*, int, hipStream_t);

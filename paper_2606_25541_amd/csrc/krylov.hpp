@@ -27,11 +27,11 @@ struct GState {
   double target;    // stopping threshold of the residual estimate
   double res;       // |g_{j+1}|: current residual estimate
   double beta;      // ||r0|| of the current cycle
-  double inv_norm;  // 1 / h_{j+1,j}
+  double inv_norm;  // scale of the unnormalised newest vector (-1 / ||w||; 1 for v_0)
   double wn2;       // ||w||^2 after the last orthogonalisation pass
   double wn2_in;    // ||w||^2 before the pass
   double reorth_thr;  // second pass when ||w||^2 after the first < reorth_thr * ||w||^2 before
-  int jcur;         // column index of the step in flight (read by the scale kernel)
+  int jcur;         // column index of the last step
   int cycles;       // restart cycles of the current linear solve
   int status;       // PSFD_OK, PSFD_NOT_CONVERGED or PSFD_ERR_NONFINITE (linear solve)
   int iter_limit;   // the linear solve stops once iters reaches it
@@ -64,10 +64,6 @@ void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* 
 template <class T>
 void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run, int first,
                    double2* part, int nbatch, hipStream_t s);
-// v_{j+1} *= inv_norm (in place) and j <- j + 1, for instances still running
-template <class T>
-void krylov_scale_next(T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int nbatch,
-                       hipStream_t s);
 // y = H^{-1} g over the k = j + 1 completed columns
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s);
 // x += sum_{i<k} y_i v_i
