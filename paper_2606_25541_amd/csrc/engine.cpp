@@ -2,6 +2,8 @@
 // operator apply orchestration and the GMRES / outer-loop drivers.
 #include "engine.hpp"
 
+#include <deque>
+
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -287,6 +289,9 @@ Status device_consts(DeviceConsts*& out) {
 // ---------------------------------------------------------------------------
 Group::~Group() {
   for (void* p : owned) (void)hipFree(p);
+  for (hipEvent_t e : flag_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (h_flags) (void)hipHostFree(h_flags);
   if (h_run) (void)hipHostFree(h_run);
   if (h_dbl) (void)hipHostFree(h_dbl);
 }
@@ -364,6 +369,8 @@ Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec) {
   g.rblk = (int)((sh.nxny + 255) / 256);
   GALLOC(g.rpart, (size_t)g.rblk * 2 * 8 * B);
   HIPCHK(hipHostMalloc((void**)&g.h_run, sizeof(int) * B * 4, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&g.h_flags, sizeof(int) * B * FLAG_SLOTS, hipHostMallocDefault));
+  for (int i = 0; i < FLAG_SLOTS; ++i) HIPCHK(hipEventCreateWithFlags(&g.flag_ev[i], hipEventDisableTiming));
   HIPCHK(hipHostMalloc((void**)&g.h_dbl, sizeof(double) * (size_t)B * 2 * std::max(8, g.rblk), hipHostMallocDefault));
   HIPCHK(hipMemset(g.st, 0, sizeof(GState) * B));
   HIPCHK(hipMemset(g.run, 0, sizeof(int) * B));
@@ -546,9 +553,6 @@ double reorth_threshold() {
   return v;
 }
 
-// Arnoldi steps between host checks of the solve flags (whole cycles); kernels
-// launched for finished instances are no-ops (every kernel tests its flags).
-const int CHECK_STEPS = 40;
 // Arnoldi steps the server issues per host check of the run flags.
 const int STEPS_PER_SYNC = 4;
 
@@ -597,21 +601,36 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   vec_norm2<double2>(g.b, n3, n3, g.dpart, g.n2b, g.mask, B, s);
   krylov_solve_init(g.st, g.n2b, g.rtol, g.abs_target, o.max_iters, g.mask, B, s);
   const double eta = g.prec == PSFD_MIXED ? o.inner_eta : 0.0;
-  // cycles between host checks: about CHECK_STEPS Arnoldi steps
-  const int check_every = std::max(1, CHECK_STEPS / g.m);
+  // After each cycle start the active flags travel to pinned host memory behind
+  // an event; the host polls the events without blocking and stops launching
+  // once a snapshot shows no active instance. It blocks only when more than
+  // FLAG_LAG snapshots are outstanding, so the GPU queue stays full.
   const int max_cycles = o.max_iters + 2;  // every cycle that starts takes at least one step
-  for (int cyc = 0; cyc < max_cycles; ++cyc) {
+  std::deque<int> pending;                 // snapshot slots in flight, oldest first
+  bool done = false;
+  auto snapshot_live = [&](int slot) {
+    for (int b = 0; b < B; ++b)
+      if (g.h_flags[slot * B + b]) return true;
+    return false;
+  };
+  for (int cyc = 0; cyc < max_cycles && !done; ++cyc) {
     apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, refl, g.mask, s);
     vec_axpby<double2, double2, double2>(g.r, g.b, g.r, 1.0, -1.0, n3, n3, g.mask, B, s);
     vec_norm2<double2>(g.r, n3, n3, g.dpart, g.n2, g.mask, B, s);
     krylov_cycle_start(g.st, g.n2, g.abs_target, eta, g.m, reorth_threshold(), g.mask, g.run, g.cyc, B, s);
-    if (cyc % check_every == 0) {
-      HIPCHK(hipMemcpyAsync(g.h_run, g.mask, sizeof(int) * B, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      bool live = false;
-      for (int b = 0; b < B; ++b) live |= g.h_run[b] != 0;
-      if (!live) break;
+    const int slot = cyc % FLAG_SLOTS;
+    HIPCHK(hipMemcpyAsync(g.h_flags + slot * B, g.mask, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(g.flag_ev[slot], s));
+    pending.push_back(slot);
+    while (!pending.empty()) {
+      const int old = pending.front();
+      hipError_t q = pending.size() > FLAG_LAG ? hipEventSynchronize(g.flag_ev[old]) : hipEventQuery(g.flag_ev[old]);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) return hip_status(q, "solve flags");
+      pending.pop_front();
+      if (!snapshot_live(old)) { done = true; break; }
     }
+    if (done) break;
     vec_scale_invsqrt<T, double2>((T*)g.basis, g.r, g.n2, n3, bsv, n3, g.cyc, B, s);
     for (int step = 0; step < g.m; ++step) arnoldi_step<T>(g, transpose, refl, s);
     krylov_solve_small(g.st, g.cyc, B, s);

@@ -66,6 +66,12 @@ struct DeviceConsts {
 };
 Status device_consts(DeviceConsts*& out);
 
+// Snapshots of the solve flags in flight: ring slots, and how many may be
+// outstanding before the host waits for the oldest. Kernels launched for
+// finished instances are no-ops (every kernel tests its flags).
+constexpr int FLAG_SLOTS = 4;
+constexpr int FLAG_LAG = 2;
+
 // B instances of one grid shape with every device buffer a solve needs.
 struct Group {
   Shape sh;
@@ -100,6 +106,8 @@ struct Group {
   double2 *adn = nullptr, *aup = nullptr, *eup = nullptr, *ord = nullptr, *eup2 = nullptr;
   double* rpart = nullptr;
   int rblk = 1;
+  int* h_flags = nullptr;    // pinned snapshots of the solve flags (FLAG_SLOTS x B)
+  hipEvent_t flag_ev[FLAG_SLOTS] = {};
   int* h_run = nullptr;      // pinned host mirrors
   double* h_dbl = nullptr;
   std::vector<void*> owned;

@@ -56,10 +56,86 @@ template <class T, bool INV> PSFD_D void dft8(T* x) {
   x[3] = cadd(e3, o3); x[7] = csub(e3, o3);
 }
 
+// multiply by exp(-+2 pi i k / 16) for k = 1, 3 (the other odd powers follow by
+// symmetry); cos(pi/8) and sin(pi/8)
+template <class T, bool INV, int K> PSFD_D T w16(T a) {
+  typedef typename real_of<T>::type R;
+  const R c = (R)0.92387953251128675613, sn = (R)0.38268343236508977173;
+  // exp(-i pi/8) = c - i s, exp(-3 i pi/8) = s - i c (conjugates for INV)
+  const R wr = K == 1 ? c : sn, wi = INV ? (K == 1 ? sn : c) : -(K == 1 ? sn : c);
+  T r;
+  r.x = a.x * wr - a.y * wi;
+  r.y = a.x * wi + a.y * wr;
+  return r;
+}
+
+// 16-point DFT as 4 x 4: DFT4 over n1 of x[4 n1 + n2], twiddle W16^(n2 k1),
+// DFT4 over n2; output k1 + 4 k2 in natural order
+template <class T, bool INV> PSFD_D void dft16(T* x) {
+  T y[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    T a = x[n2], b = x[4 + n2], c = x[8 + n2], d = x[12 + n2];
+    dft4<T, INV>(a, b, c, d);
+    y[4 * n2 + 0] = a; y[4 * n2 + 1] = b; y[4 * n2 + 2] = c; y[4 * n2 + 3] = d;
+  }
+  // W16^(n2 k1): n2 = 1: k1 = 1, 2, 3 -> W^1, W^2, W^3; n2 = 2: W^2, W^4, W^6; n2 = 3: W^3, W^6, W^9
+  y[5] = w16<T, INV, 1>(y[5]);
+  y[6] = w8<T, INV, 1>(y[6]);
+  y[7] = w16<T, INV, 3>(y[7]);
+  y[9] = w8<T, INV, 1>(y[9]);
+  y[10] = cmul_mi<T, INV>(y[10]);
+  y[11] = w8<T, INV, 3>(y[11]);
+  y[13] = w16<T, INV, 3>(y[13]);
+  y[14] = w8<T, INV, 3>(y[14]);
+  {  // W16^9 = -W16^1
+    T t = w16<T, INV, 1>(y[15]);
+    t.x = -t.x; t.y = -t.y;
+    y[15] = t;
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    T a = y[k1], b = y[4 + k1], c = y[8 + k1], d = y[12 + k1];
+    dft4<T, INV>(a, b, c, d);
+    x[k1] = a; x[k1 + 4] = b; x[k1 + 8] = c; x[k1 + 12] = d;
+  }
+}
+
 template <class T, int R, bool INV> PSFD_D void dft_r(T* u) {
   if (R == 2) dft2<T, INV>(u[0], u[1]);
   else if (R == 4) dft4<T, INV>(u[0], u[1], u[2], u[3]);
-  else dft8<T, INV>(u);
+  else if (R == 8) dft8<T, INV>(u);
+  else dft16<T, INV>(u);
+}
+
+// DFT of size R whose inputs R/2 .. R-1 are zero (first pass over a sequence
+// zero-padded to twice its length): only the non-zero half is read.
+template <class T, int R, bool INV> PSFD_D void dft_r_half(T* u) {
+  if (R == 2) {
+    u[1] = u[0];
+  } else if (R == 4) {
+    const T a = u[0], b = u[1];
+    const T c = cmul_mi<T, INV>(b);
+    u[0] = cadd(a, b); u[2] = csub(a, b); u[1] = cadd(a, c); u[3] = csub(a, c);
+  } else if (R == 16) {
+#pragma unroll
+    for (int j = 8; j < 16; ++j) u[j] = cmake<T>(0, 0);
+    dft16<T, INV>(u);
+  } else {
+    // even part (x0, x2, 0, 0) and odd part (x1, x3, 0, 0) as 4-point DFTs
+    const T x0 = u[0], x1 = u[1], x2 = u[2], x3 = u[3];
+    const T e0 = cadd(x0, x2), e2 = csub(x0, x2), ex = cmul_mi<T, INV>(x2);
+    const T e1 = cadd(x0, ex), e3 = csub(x0, ex);
+    const T o0 = cadd(x1, x3), o2 = csub(x1, x3), ox = cmul_mi<T, INV>(x3);
+    T o1 = cadd(x1, ox), o3 = csub(x1, ox);
+    o1 = w8<T, INV, 1>(o1);
+    const T o2w = w8<T, INV, 2>(o2);
+    o3 = w8<T, INV, 3>(o3);
+    u[0] = cadd(e0, o0); u[4] = csub(e0, o0);
+    u[1] = cadd(e1, o1); u[5] = csub(e1, o1);
+    u[2] = cadd(e2, o2w); u[6] = csub(e2, o2w);
+    u[3] = cadd(e3, o3); u[7] = csub(e3, o3);
+  }
 }
 
 // Shape of a batch of sequences in LDS: length 2^ln(), ns() sequences, element
@@ -109,12 +185,20 @@ PSFD_D void twiddle_apply(T* u, const T* __restrict__ tw, int step) {
     u[1] = INV ? cmulc(u[1], w1) : cmul(u[1], w1);
     u[2] = INV ? cmulc(u[2], w2) : cmul(u[2], w2);
     u[3] = INV ? cmulc(u[3], w3) : cmul(u[3], w3);
-  } else {
+  } else if (R == 8) {
     const T w1 = tw[step], w2 = tw[2 * step], w4 = tw[4 * step];
     const T w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
     const T w[8] = {w1, w1, w2, w3, w4, w5, w6, w7};
 #pragma unroll
     for (int j = 1; j < 8; ++j) u[j] = INV ? cmulc(u[j], w[j]) : cmul(u[j], w[j]);
+  } else {
+    // radix 16: every power read from the table (an LDS table in the kernels
+    // that use this radix)
+#pragma unroll
+    for (int j = 1; j < 16; ++j) {
+      const T w = tw[j * step];
+      u[j] = INV ? cmulc(u[j], w) : cmul(u[j], w);
+    }
   }
 }
 
@@ -126,10 +210,14 @@ template <class T> struct FftBudget {
   static constexpr int LRMAX = 3;
 };
 
-template <class T, int R, bool INV, bool SF, int E, class D>
+// ZIN (first pass only): the second half of every sequence is zero and is
+// neither read nor needed in LDS. ZOUT (last pass only): only the first half of
+// every sequence is stored.
+template <class T, int R, bool INV, bool SF, int E, class D, bool ZIN = false, bool ZOUT = false>
 __device__ __forceinline__ void stockham_pass(T* lds, const D& d, int log2p, const T* __restrict__ tw, int tid) {
   constexpr int NB = E >= R ? E / R : 1;  // E < R: one butterfly on the first threads
   constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+  static_assert(R == 2 || R == 4 || R == 8 || R == 16, "radix");
   const int log2nr = d.ln() - LR;
   const int nr = 1 << log2nr;
   const int nbt = d.ns() << log2nr;
@@ -144,7 +232,7 @@ __device__ __forceinline__ void stockham_pass(T* lds, const D& d, int log2p, con
       bfly_index<SF>(b, log2nr, d.ns(), inv_nseq, s, t);
       const T* base = lds + s * d.ss() + t * d.es();
 #pragma unroll
-      for (int j = 0; j < R; ++j) u[i][j] = base[j * nr * d.es()];
+      for (int j = 0; j < (ZIN ? R / 2 : R); ++j) u[i][j] = base[j * nr * d.es()];
     }
   }
   __syncthreads();
@@ -158,11 +246,16 @@ __device__ __forceinline__ void stockham_pass(T* lds, const D& d, int log2p, con
       bfly_index<SF>(b, log2nr, d.ns(), inv_nseq, s, t);
       int k = t & (p - 1);
       int step = k << tsh;
-      if (k != 0) twiddle_apply<T, R, INV>(u[i], tw, step);
-      dft_r<T, R, INV>(u[i]);
+      if (ZIN) {
+        dft_r_half<T, R, INV>(u[i]);  // first pass: p = 1, no twiddles
+      } else {
+        if (k != 0) twiddle_apply<T, R, INV>(u[i], tw, step);
+        dft_r<T, R, INV>(u[i]);
+      }
       T* base = lds + s * d.ss() + ((t - k) * R + k) * d.es();
+      // last pass: output j of butterfly t lands at t + j n / R, in the first half for j < R / 2
 #pragma unroll
-      for (int j = 0; j < R; ++j) base[j * p * d.es()] = u[i][j];
+      for (int j = 0; j < (ZOUT ? R / 2 : R); ++j) base[j * p * d.es()] = u[i][j];
     }
   }
   __syncthreads();
@@ -173,32 +266,48 @@ __device__ __forceinline__ void stockham_pass(T* lds, const D& d, int log2p, con
 // sequence unrolls and log2p is a constant in every pass.
 // tw: the twiddle table of this length, tw[i] = exp(-2 pi i i / n), i < n
 // (global memory or LDS).
-template <class T, bool INV, bool SF, int E, class D>
+// ZIN: every sequence is zero in its second half (which need not be set in
+// LDS); ZOUT: only the first half of every result is needed (the second half
+// of LDS is left unspecified).
+// LRM: largest radix as log2 (3: radix 8, 4: radix 16 with every twiddle read
+// from the table). The passes take the largest radix first.
+template <class T, bool INV, bool SF, int E, class D, bool ZIN, bool ZOUT, int R>
+__device__ __forceinline__ void pass_r(T* lds, const D& d, int log2p, const T* __restrict__ tw, int tid,
+                                       bool first, bool last) {
+  if (ZIN && first) stockham_pass<T, R, INV, SF, E, D, true, false>(lds, d, log2p, tw, tid);
+  else if (ZOUT && last) stockham_pass<T, R, INV, SF, E, D, false, true>(lds, d, log2p, tw, tid);
+  else stockham_pass<T, R, INV, SF, E, D, false, false>(lds, d, log2p, tw, tid);
+}
+
+template <class T, bool INV, bool SF, int E, class D, bool ZIN = false, bool ZOUT = false,
+          int LRM = FftBudget<T>::LRMAX>
 __device__ __forceinline__ void lds_fft_tab(T* lds, const D& d, const T* __restrict__ tw, int tid) {
-  constexpr int LRM = FftBudget<T>::LRMAX;
 #pragma unroll
   for (int log2p = 0; log2p < d.ln();) {
     const int rem = d.ln() - log2p;
     const int lr = rem >= LRM ? LRM : rem;
-    if (lr == 3) stockham_pass<T, 8, INV, SF, E>(lds, d, log2p, tw, tid);
-    else if (lr == 2) stockham_pass<T, 4, INV, SF, E>(lds, d, log2p, tw, tid);
-    else stockham_pass<T, 2, INV, SF, E>(lds, d, log2p, tw, tid);
+    const bool first = log2p == 0, last = lr == rem;
+    if (LRM >= 4 && lr == 4) pass_r<T, INV, SF, E, D, ZIN, ZOUT, 16>(lds, d, log2p, tw, tid, first, last);
+    else if (lr == 3) pass_r<T, INV, SF, E, D, ZIN, ZOUT, 8>(lds, d, log2p, tw, tid, first, last);
+    else if (lr == 2) pass_r<T, INV, SF, E, D, ZIN, ZOUT, 4>(lds, d, log2p, tw, tid, first, last);
+    else pass_r<T, INV, SF, E, D, ZIN, ZOUT, 2>(lds, d, log2p, tw, tid, first, last);
     log2p += lr;
   }
 }
 
 // tw_all: the table of every length (tw_all[n + i] = exp(-2 pi i i / n))
-template <class T, bool INV, bool SF, int E, class D>
+template <class T, bool INV, bool SF, int E, class D, bool ZIN = false, bool ZOUT = false,
+          int LRM = FftBudget<T>::LRMAX>
 __device__ __forceinline__ void lds_fft_d(T* lds, const D& d, const T* __restrict__ tw_all, int tid) {
-  lds_fft_tab<T, INV, SF, E>(lds, d, tw_all + (1 << d.ln()), tid);
+  lds_fft_tab<T, INV, SF, E, D, ZIN, ZOUT, LRM>(lds, d, tw_all + (1 << d.ln()), tid);
 }
 
 // Run-time shape: nseq sequences of length 2^log2n, element j of sequence s at
 // s * sstride + j * estride.
-template <class T, bool INV, bool SF = false, int E = FftBudget<T>::E>
+template <class T, bool INV, bool SF = false, int E = FftBudget<T>::E, bool ZIN = false, bool ZOUT = false>
 __device__ __forceinline__ void lds_fft(T* lds, int log2n, int nseq, int sstride, int estride,
                         const T* __restrict__ tw_all, int tid, int nthr) {
-  lds_fft_d<T, INV, SF, E>(lds, FftRT{log2n, nseq, sstride, estride, nthr}, tw_all, tid);
+  lds_fft_d<T, INV, SF, E, FftRT, ZIN, ZOUT>(lds, FftRT{log2n, nseq, sstride, estride, nthr}, tw_all, tid);
 }
 
 }  // namespace psfd

@@ -234,8 +234,8 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
 #pragma unroll
   for (int k = 0; k < KT; ++k) put(k);
   __syncthreads();
-  lds_fft_tab<T, INV, false, KT>(lds, Rows(), twl, tid);
-  lds_fft_tab<T, INV, false, KT>(lds, Cols(), twl, tid);
+  lds_fft_tab<T, INV, false, KT, Rows, false, false, 4>(lds, Rows(), twl, tid);
+  lds_fft_tab<T, INV, false, KT, Cols, false, false, 4>(lds, Cols(), twl, tid);
   T* out = vref<T>(a.out, b) + poff;
   const R al = (R)a.alpha, ga = (R)a.gamma;
 #pragma unroll
@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   T* w = vref<T>(a.w, b);
   // The data half (z < nz) is LDS elements [0, nz LS): i = z LS + c bx + kxl, at
   // most 4 per thread (3 pz bx <= 8 nthr). Loads are unconditional (clamped index)
-  // and all issued before the LDS writes; the padded half is zero.
+  // and all issued before the LDS writes; the padded half (z >= nz) is not stored.
   const int nload = 3 * pz * bx, nval = nz * LS;
   {
     T buf[4];
@@ -390,8 +390,8 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
       const int i = tid + k * nthr;
       if (i < nval) lds[i] = buf[k];
     }
-    for (int i = nval + tid; i < nload; i += nthr) lds[i] = cmake<T>(0.0, 0.0);
   }
+  (void)nload;  // the padded half is never read: the first forward pass treats it as zero
   const double* tab = a.tab + (long long)b * a.tab_stride;
   TabLayout L{nx, ny};
   // LDS after the data: phases exp(i beta z_k) [nz][bx] (T), the stack response
@@ -465,8 +465,8 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   __syncthreads();
   const T* tw = reinterpret_cast<const T*>(a.tw);
   typedef FftCT<LPZ, 48, 1, 48, pencil_threads_ct(LPZ)> ZCT;
-  if constexpr (LPZ > 0) lds_fft_d<T, false, true, 8>(lds, ZCT(), tw, tid);
-  else lds_fft<T, false, true, 8>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
+  if constexpr (LPZ > 0) lds_fft_d<T, false, true, 8, ZCT, true, false, 4>(lds, ZCT(), tw, tid);
+  else lds_fft<T, false, true, 8, true, false>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
 
   const double Lw = tab[TS_L], kap_u = tab[TS_KAPPA], scale = tab[TS_SCALE], kbg = tab[TS_KBG];
   const double ik2 = 1.0 / (kbg * kbg);
@@ -510,8 +510,8 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     *p2 = csub(cmul(F, o2), cmul(tz, v2));
   }
   __syncthreads();
-  if constexpr (LPZ > 0) lds_fft_d<T, true, true, 8>(lds, ZCT(), tw, tid);
-  else lds_fft<T, true, true, 8>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
+  if constexpr (LPZ > 0) lds_fft_d<T, true, true, 8, ZCT, false, true, 4>(lds, ZCT(), tw, tid);
+  else lds_fft<T, true, true, 8, false, true>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
   const int nst = 3 * nz * bx;
   for (int i = tid; i < nst; i += nthr) {
     const int kxl = i & (bx - 1);
