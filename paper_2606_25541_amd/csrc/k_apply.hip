@@ -251,8 +251,93 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   }
 }
 
+// -------------------------------------------------------------------------
+// Strip kernel: for square N x N planes too large for LDS, the x-FFT of
+// TY = 4096 / N full rows (ROWS) or the y-FFT of 16 full columns of one plane,
+// with the shapes fixed at compile time; 8 elements per thread, twiddles in
+// LDS, every global load of a thread issued before its LDS writes.
+// -------------------------------------------------------------------------
+template <int LN, bool ROWS> struct StripShape {
+  static constexpr int N = 1 << LN;
+  static constexpr int TX = ROWS ? N : 16, TY = ROWS ? 4096 / N : N, LTX = ROWS ? LN : 4;
+  static constexpr int P = TX + 1, ELEM = TX * TY, KT = 8, NT = ELEM / KT;
+  static constexpr int TILES = ROWS ? N / TY : N / 16;
+};
+template <int LN, bool ROWS> __host__ constexpr size_t strip_lds(size_t esz) {
+  return ((size_t)StripShape<LN, ROWS>::TY * StripShape<LN, ROWS>::P + StripShape<LN, ROWS>::N) * esz;
+}
+
+template <class T, bool INV, int LD, int ST, int LN, bool ROWS>
+__global__ void __launch_bounds__(512) k_strip(TileArgs a) {
+  typedef StripShape<LN, ROWS> S;
+  constexpr int N = S::N, TX = S::TX, TY = S::TY, LTX = S::LTX, P = S::P, KT = S::KT, NT = S::NT;
+  extern __shared__ double2 smem_d[];
+  T* lds = reinterpret_cast<T*>(smem_d);
+  T* twl = lds + TY * P;
+  const int b = blockIdx.y;
+  if (a.active && !a.active[b]) return;
+  const int plane = blockIdx.x / S::TILES, tile = blockIdx.x % S::TILES;
+  const int z = plane % a.nz;
+  const int x0 = ROWS ? 0 : tile * TX, y0 = ROWS ? tile * TY : 0;
+  const long long poff = (long long)plane * N * N;
+  const int tid = threadIdx.x;
+  const T* in = vref<T>(a.in, b) + poff;
+  const T* vol = LD == LD_VX ? vref<T>(a.vol, b) + (long long)z * N * N : nullptr;
+  const T* aux = ST == ST_AXPBY ? vref<T>(a.aux, b) + poff : nullptr;
+  typedef typename real_of<T>::type R;
+  auto off_of = [&](int i) -> int { return (y0 + (i >> LTX)) * N + (x0 + (i & (TX - 1))); };
+  const T tw0 = reinterpret_cast<const T*>(a.tw)[N + (tid & (N - 1))];
+  __builtin_amdgcn_sched_barrier(0);
+  T va[KT], vb[LD == LD_VX ? KT : 1], xa[ST == ST_AXPBY ? KT : 1];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int o = off_of(tid + k * NT);
+    va[k] = in[o];
+    if (LD == LD_VX) vb[k] = vol[o];
+  }
+  if (ST == ST_AXPBY) {
+#pragma unroll
+    for (int k = 0; k < KT; ++k) xa[k] = aux[off_of(tid + k * NT)];
+  }
+  const double* tab = a.tab + (long long)b * a.tab_stride;
+  const R k0sq = (R)tab[TS_K0SQ];
+  // normalisation on load of the newest Arnoldi vector, written back (skipped at scale 1)
+  const R sc = (LD == LD_VX && a.in_scale) ? (R)a.in_scale[(long long)b * a.scale_stride] : (R)1;
+  T* inw = vref<T>(a.in, b) + poff;
+  static_assert(NT >= N, "one twiddle per thread");
+  if (tid < N) twl[tid] = tw0;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int i = tid + k * NT;
+    T x = va[k];
+    if (LD == LD_VX && sc != (R)1) {
+      x.x *= sc; x.y *= sc;
+      inw[off_of(i)] = x;
+    }
+    const T v = LD == LD_VX ? cscale(cmul(vb[LD == LD_VX ? k : 0], x), k0sq) : x;
+    lds[(i >> LTX) * P + (i & (TX - 1))] = v;
+  }
+  __syncthreads();
+  if constexpr (ROWS) lds_fft_tab<T, INV, false, KT, FftCT<LN, TY, P, 1, NT>>(lds, FftCT<LN, TY, P, 1, NT>(), twl, tid);
+  else lds_fft_tab<T, INV, false, KT, FftCT<LN, 16, 1, P, NT>>(lds, FftCT<LN, 16, 1, P, NT>(), twl, tid);
+  T* out = vref<T>(a.out, b) + poff;
+  const R al = (R)a.alpha, ga = (R)a.gamma;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int i = tid + k * NT;
+    T v = lds[(i >> LTX) * P + (i & (TX - 1))];
+    if (ST == ST_AXPBY) {
+      const T xv = xa[ST == ST_AXPBY ? k : 0];
+      v.x = al * xv.x + ga * v.x;
+      v.y = al * xv.y + ga * v.y;
+    }
+    out[off_of(i)] = v;
+  }
+}
+
 // fused square planes of 64 x 64 (and 128 x 128 in FP32) with plain or
-// contrast-multiply loads take the square-plane kernel
+// contrast-multiply loads take the square-plane kernel; the row and column
+// passes of square 128 x 128 and 256 x 256 planes take the strip kernel
 template <class T, bool INV, int LD, int ST>
 void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t lds, hipStream_t s) {
   dim3 grid(nplanes * a.tiles_x * a.tiles_y, nbatch);
@@ -267,6 +352,22 @@ void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t ld
     if (sq && a.nx == 64) return plane(k_plane<T, INV, LD, ST, 6>, 6);
     if constexpr (sizeof(T) == 8)
       if (sq && a.nx == 128) return plane(k_plane<T, INV, LD, ST, 7>, 7);
+    // strips of square planes: rows (TY = 4096 / N full rows) or 16-column strips
+    auto strip = [&](auto kern, int nt, size_t l) {
+      allow_lds(reinterpret_cast<const void*>(kern), l);
+      hipLaunchKernelGGL(kern, grid, dim3(nt), l, s, a);
+    };
+    const bool square = a.nx == a.ny && (a.nx == 128 || a.nx == 256);
+    const bool rows = square && a.do_x && !a.do_y && a.tx == a.nx && a.ty == 4096 / a.nx;
+    const bool cols = square && !a.do_x && a.do_y && a.tx == 16 && a.ty == a.ny;
+    if (rows && a.nx == 128)
+      return strip(k_strip<T, INV, LD, ST, 7, true>, StripShape<7, true>::NT, strip_lds<7, true>(sizeof(T)));
+    if (rows && a.nx == 256)
+      return strip(k_strip<T, INV, LD, ST, 8, true>, StripShape<8, true>::NT, strip_lds<8, true>(sizeof(T)));
+    if (cols && a.nx == 128)
+      return strip(k_strip<T, INV, LD, ST, 7, false>, StripShape<7, false>::NT, strip_lds<7, false>(sizeof(T)));
+    if (cols && a.nx == 256)
+      return strip(k_strip<T, INV, LD, ST, 8, false>, StripShape<8, false>::NT, strip_lds<8, false>(sizeof(T)));
   }
   allow_lds(reinterpret_cast<const void*>(&k_tile<T, INV, LD, ST>), lds);
   hipLaunchKernelGGL((k_tile<T, INV, LD, ST>), grid, dim3(nthr), lds, s, a);
@@ -401,11 +502,13 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   double2* eup = smem_d + off_e;
   double2* part = eup + 3 * bx;
   double2* ptab = part + nthr;
+  T* twl = reinterpret_cast<T*>(ptab + 6 * bx);  // twiddles of length pz (compile-time shapes)
   // order of column kxl (the transposed operator reads the kernel at the negated order)
   auto order_of = [&](int kxl, int& mq, int& nq) {
     mq = kx0 + kxl; nq = ky;
     if (a.transpose) { mq = (nx - mq) & (nx - 1); nq = (ny - nq) & (ny - 1); }
   };
+  if (LPZ > 0 && tid < pz) twl[tid] = reinterpret_cast<const T*>(a.tw)[pz + tid];
   if (tid < bx) {
     int mq, nq;
     order_of(tid, mq, nq);
@@ -465,7 +568,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   __syncthreads();
   const T* tw = reinterpret_cast<const T*>(a.tw);
   typedef FftCT<LPZ, 48, 1, 48, pencil_threads_ct(LPZ)> ZCT;
-  if constexpr (LPZ > 0) lds_fft_d<T, false, true, 8, ZCT, true, false, 4>(lds, ZCT(), tw, tid);
+  if constexpr (LPZ > 0) lds_fft_tab<T, false, true, 8, ZCT, true, false, 4>(lds, ZCT(), twl, tid);
   else lds_fft<T, false, true, 8, true, false>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
 
   const double Lw = tab[TS_L], kap_u = tab[TS_KAPPA], scale = tab[TS_SCALE], kbg = tab[TS_KBG];
@@ -510,7 +613,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     *p2 = csub(cmul(F, o2), cmul(tz, v2));
   }
   __syncthreads();
-  if constexpr (LPZ > 0) lds_fft_d<T, true, true, 8, ZCT, false, true, 4>(lds, ZCT(), tw, tid);
+  if constexpr (LPZ > 0) lds_fft_tab<T, true, true, 8, ZCT, false, true, 4>(lds, ZCT(), twl, tid);
   else lds_fft<T, true, true, 8, false, true>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
   const int nst = 3 * nz * bx;
   for (int i = tid; i < nst; i += nthr) {

@@ -16,8 +16,12 @@ from gpu_util import device, rel, say, torch
 
 pytestmark = pytest.mark.gpu
 
+# (128, 128, 4): square-plane kernel in FP32, row/column strips in FP64;
+# (256, 256, 2): strips in both precisions; (16, 16, 32) and (16, 8, 64): the
+# z-pencil with compile-time padded lengths 64 and 128
 SHAPES = [
     (4, 4, 2), (8, 8, 4), (16, 8, 8), (32, 32, 16), (64, 32, 8), (128, 128, 4), (256, 64, 2), (64, 256, 2),
+    (256, 256, 2), (16, 16, 32), (16, 8, 64),
 ]
 
 
