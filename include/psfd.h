@@ -151,10 +151,14 @@ int psfd_solve_batch(int32_t n, const psfd_problem* probs, const psfd_opts* opts
 int psfd_release_cached_workspaces(void);
 
 /* Serving: continuous batching of solve requests admitted by device-memory
- * footprint. The server owns a worker thread and its own HIP stream.
- * hbm_budget: bytes the server may allocate for workspaces; max_slots: requests
- * on the device at once. submit copies the problem; the caller's buffers must
- * stay valid until poll reports done. */
+ * footprint. Requests of one grid shape share a slot group of up to max_slots
+ * instances, created on the first request of that shape while it fits the
+ * remaining hbm_budget (bytes of device workspace the server may allocate);
+ * a request whose shape cannot get a group completes at once with
+ * PSFD_ERR_OOM. Every group has its own worker thread and HIP stream, so the
+ * groups run concurrently. submit copies the problem; the caller's buffers
+ * must stay valid until poll reports done. destroy finishes every submitted
+ * request, then frees the workspaces. */
 int psfd_server_create(size_t hbm_budget, int32_t max_slots, const psfd_opts* opts, psfd_server** out);
 int psfd_server_submit(psfd_server* srv, const psfd_problem* prob, const void* d_deps, void* d_emask,
                        void* d_orders, uint64_t* ticket);

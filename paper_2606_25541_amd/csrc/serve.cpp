@@ -129,9 +129,12 @@ Status solve_batch(int n, const psfd_problem* probs, const psfd_opts* opts, cons
 //
 // Requests are grouped by grid shape. Each shape owns a slot group (a Group of
 // `cap` instances) allocated the first time the shape appears, sized so that
-// the groups' device footprint stays within the budget. A worker thread runs
-// ticks; every tick advances every occupied slot by one phase of its own
-// coupled solve (monolithic coupling, GMRES(m) with FP64 residuals):
+// the groups' device footprint stays within the budget. Every slot group has
+// its own worker thread and HIP stream, so the groups of different shapes run
+// concurrently on the device and small requests never wait behind the launches
+// of large ones. A worker runs ticks; every tick advances every occupied slot
+// of its group by one phase of its own coupled solve (monolithic coupling,
+// GMRES(m) with FP64 residuals):
 //   INIT  tables, contrast, e_bg, x0 = e_bg, ||b||
 //   START FP64 residual r = b - A x: done, or start an Arnoldi cycle
 //   ARN   Arnoldi steps (all running slots share each launch)
@@ -164,6 +167,10 @@ struct SlotGroup {
   Shape sh;
   std::unique_ptr<Group> g;
   int cap = 0;
+  hipStream_t s = nullptr;
+  std::thread worker;
+  std::condition_variable cv;
+  std::deque<Req*> queue;  // waiting for a free slot of this group (guarded by the server mutex)
   std::vector<Req*> req;
   std::vector<int> phase;
   std::vector<int> cycles;
@@ -182,11 +189,7 @@ struct psfd_server {
   int max_slots = 1;
   psfd::Opts o;
   int device = 0;
-  hipStream_t s = nullptr;
-  std::thread worker;
-  std::mutex mu;
-  std::condition_variable cv;
-  std::deque<psfd::Req*> queue;
+  std::mutex mu;  // guards reqs, groups, every group queue, next, stop, allocated, err
   std::unordered_map<uint64_t, std::unique_ptr<psfd::Req>> reqs;
   uint64_t next = 1;
   bool stop = false;
@@ -210,7 +213,7 @@ static void finish_req(psfd_server* S, Req* r, int status) {
 template <class T>
 static Status tick_group(psfd_server* S, SlotGroup& G) {
   Group& g = *G.g;
-  hipStream_t s = S->s;
+  hipStream_t s = G.s;
   const Opts& o = S->o;
   const int B = G.cap;
   const Shape& sh = G.sh;
@@ -360,84 +363,34 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
   return Status();
 }
 
-static void admit(psfd_server* S) {
-  // move queued requests into free slots of their shape group (no head-of-line blocking across shapes)
-  std::lock_guard<std::mutex> lk(S->mu);
-  for (auto it = S->queue.begin(); it != S->queue.end();) {
-    Req* r = *it;
-    SlotGroup* G = nullptr;
-    for (auto& gp : S->groups)
-      if (shape_eq(gp->sh, r->sh)) G = gp.get();
-    if (!G) {
-      const size_t per = group_bytes(r->sh, 1, S->o.restart, S->o.precision);
-      const size_t avail = S->budget > S->allocated ? S->budget - S->allocated : 0;
-      const int cap = (int)std::min<size_t>((size_t)S->max_slots, avail / per);
-      if (cap < 1) {
-        r->status = PSFD_ERR_OOM;
-        r->info.status = PSFD_ERR_OOM;
-        r->t_done = clk::now();
-        r->done = true;
-        it = S->queue.erase(it);
-        continue;
-      }
-      auto ng = std::make_unique<SlotGroup>();
-      ng->sh = r->sh;
-      ng->g = std::make_unique<Group>();
-      Status st = group_alloc(*ng->g, r->sh, cap, S->o.restart, S->o.precision);
-      if (!st.ok()) {
-        r->status = st.code;
-        r->info.status = st.code;
-        r->t_done = clk::now();
-        r->done = true;
-        it = S->queue.erase(it);
-        continue;
-      }
-      ng->cap = cap;
-      ng->req.assign(cap, nullptr);
-      ng->phase.assign(cap, P_FREE);
-      ng->cycles.assign(cap, 0);
-      ng->bn.assign(cap, 0.0);
-      ng->tgt.assign(cap, 0.0);
-      ng->res.assign(cap, 0.0);
-      S->allocated += per * (size_t)cap;
-      G = ng.get();
-      S->groups.push_back(std::move(ng));
-    }
-    int slot = -1;
-    for (int b = 0; b < G->cap; ++b)
-      if (!G->req[b]) { slot = b; break; }
-    if (slot < 0) { ++it; continue; }
-    G->req[slot] = r;
-    G->phase[slot] = P_INIT;
-    it = S->queue.erase(it);
-  }
-}
-
-static void worker_main(psfd_server* S) {
+// Worker of one slot group: admits its queued requests into free slots and
+// ticks while any slot is occupied; sleeps otherwise. On shutdown it finishes
+// every request already submitted, then exits.
+static void group_worker(psfd_server* S, SlotGroup* G) {
   (void)hipSetDevice(S->device);
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      bool busy = false;
-      for (auto& G : S->groups) busy |= G->occupied() > 0;
-      if (!busy) {
-        S->cv.wait(lk, [&] { return S->stop || !S->queue.empty(); });
-        if (S->stop && S->queue.empty()) return;
+      if (G->occupied() == 0) {
+        G->cv.wait(lk, [&] { return S->stop || !G->queue.empty(); });
+        if (S->stop && G->queue.empty()) return;
+      }
+      for (int b = 0; b < G->cap && !G->queue.empty(); ++b) {
+        if (G->req[b]) continue;
+        G->req[b] = G->queue.front();
+        G->phase[b] = P_INIT;
+        G->queue.pop_front();
       }
     }
-    admit(S);
-    for (auto& G : S->groups) {
-      if (G->occupied() == 0) continue;
-      Status st = S->o.precision == PSFD_MIXED ? tick_group<float2>(S, *G) : tick_group<double2>(S, *G);
-      if (!st.ok()) {
-        // a runtime failure ends every request of the group
-        {
-          std::lock_guard<std::mutex> lk(S->mu);
-          S->err = st;
-        }
-        for (int b = 0; b < G->cap; ++b)
-          if (G->req[b]) { finish_req(S, G->req[b], st.code); G->req[b] = nullptr; G->phase[b] = P_FREE; }
+    Status st = S->o.precision == PSFD_MIXED ? tick_group<float2>(S, *G) : tick_group<double2>(S, *G);
+    if (!st.ok()) {
+      // a runtime failure ends every request of the group
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->err = st;
       }
+      for (int b = 0; b < G->cap; ++b)
+        if (G->req[b]) { finish_req(S, G->req[b], st.code); G->req[b] = nullptr; G->phase[b] = P_FREE; }
     }
   }
 }
@@ -451,12 +404,43 @@ Status server_create(size_t hbm_budget, int max_slots, const psfd_opts* opts, ps
   S->budget = hbm_budget;
   S->max_slots = max_slots;
   hipError_t e = hipGetDevice(&S->device);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking);
-  if (e != hipSuccess) return hip_status(e, "server stream");
-  psfd_server* raw = S.get();
-  S->worker = std::thread(worker_main, raw);
+  if (e != hipSuccess) return hip_status(e, "server device");
   *out = S.release();
   return st;
+}
+
+// The slot group of a shape, created (workspace, stream, worker) on first use
+// within the remaining budget; nullptr with status OOM when not even one slot fits.
+static SlotGroup* group_for(psfd_server* S, const Shape& sh, Status& st) {
+  for (auto& gp : S->groups)
+    if (shape_eq(gp->sh, sh)) return gp.get();
+  const size_t per = group_bytes(sh, 1, S->o.restart, S->o.precision);
+  const size_t avail = S->budget > S->allocated ? S->budget - S->allocated : 0;
+  const int cap = (int)std::min<size_t>((size_t)S->max_slots, avail / per);
+  if (cap < 1) {
+    st.code = PSFD_ERR_OOM;
+    st.msg = "the request does not fit the server's device-memory budget";
+    return nullptr;
+  }
+  auto ng = std::make_unique<SlotGroup>();
+  ng->sh = sh;
+  ng->g = std::make_unique<Group>();
+  st = group_alloc(*ng->g, sh, cap, S->o.restart, S->o.precision);
+  if (!st.ok()) return nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&ng->s, hipStreamNonBlocking);
+  if (e != hipSuccess) { st = hip_status(e, "server stream"); return nullptr; }
+  ng->cap = cap;
+  ng->req.assign(cap, nullptr);
+  ng->phase.assign(cap, P_FREE);
+  ng->cycles.assign(cap, 0);
+  ng->bn.assign(cap, 0.0);
+  ng->tgt.assign(cap, 0.0);
+  ng->res.assign(cap, 0.0);
+  S->allocated += per * (size_t)cap;
+  SlotGroup* G = ng.get();
+  S->groups.push_back(std::move(ng));
+  G->worker = std::thread(group_worker, S, G);
+  return G;
 }
 
 Status server_submit(psfd_server* S, const psfd_problem* prob, const void* d_deps, void* d_emask, void* d_orders,
@@ -475,10 +459,21 @@ Status server_submit(psfd_server* S, const psfd_problem* prob, const void* d_dep
   if (S->stop) { st.code = PSFD_ERR_INVALID_ARG; st.msg = "server is shutting down"; return st; }
   r->ticket = S->next++;
   *ticket = r->ticket;
-  S->queue.push_back(r.get());
+  Req* raw = r.get();
   S->reqs.emplace(r->ticket, std::move(r));
-  S->cv.notify_one();
-  return st;
+  Status gst;
+  SlotGroup* G = group_for(S, raw->sh, gst);
+  if (!G) {
+    // refused by admission: the ticket completes at once with the status
+    raw->status = gst.code;
+    raw->info.status = gst.code;
+    raw->t_done = clk::now();
+    raw->done = true;
+    return Status();
+  }
+  G->queue.push_back(raw);
+  G->cv.notify_one();
+  return Status();
 }
 
 Status server_poll(psfd_server* S, uint64_t ticket, int* done, psfd_info* info, double* latency_s) {
@@ -499,11 +494,13 @@ Status server_destroy(psfd_server* S) {
   {
     std::lock_guard<std::mutex> lk(S->mu);
     S->stop = true;
+    for (auto& G : S->groups) G->cv.notify_all();
   }
-  S->cv.notify_all();
-  if (S->worker.joinable()) S->worker.join();
+  for (auto& G : S->groups)
+    if (G->worker.joinable()) G->worker.join();
+  for (auto& G : S->groups)
+    if (G->s) (void)hipStreamDestroy(G->s);
   S->groups.clear();
-  if (S->s) (void)hipStreamDestroy(S->s);
   Status st = S->err;
   delete S;
   return st;
