@@ -306,7 +306,7 @@ size_t group_bytes(const Shape& sh, int B, int m, int prec) {
   per += 6 * n3 * 16;
   per += (size_t)(m + 1) * n3 * esz;
   per += prec == PSFD_MIXED ? n3 * esz : 0;
-  per += sizeof(GState) + RED_BLOCKS * PSTR * 16 + RED_BLOCKS * 2 * 8;
+  per += sizeof(GState) + RED_BLOCKS * PSTR * 16 + DOT_BLOCKS_MAX * PSTR * 16 + RED_BLOCKS * 2 * 8;
   per += 5 * (size_t)sh.nxny * 3 * 16 + (size_t)((sh.nxny + 255) / 256) * 2 * 8 + 64;
   per += (size_t)(LAYER_CAP + 2) * sizeof(double4);
   return per * (size_t)B;
@@ -358,6 +358,7 @@ Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec) {
   GALLOC(g.cyc, sizeof(int) * B);
   GALLOC(g.rtol, sizeof(double) * B);
   GALLOC(g.part, (size_t)RED_BLOCKS * PSTR * 16 * B);
+  GALLOC(g.dpart2, (size_t)DOT_BLOCKS_MAX * PSTR * 16 * B);
   GALLOC(g.n2, 8 * B);
   GALLOC(g.n2b, 8 * B);
   GALLOC(g.abs_target, 8 * B);
@@ -574,10 +575,10 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s) {
   // first apply kernel scales it by inv_norm on load and writes v_j back
   apply_op<T>(g, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, &g.st[0].inv_norm,
               (long long)(sizeof(GState) / sizeof(double)));
-  krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 1, g.part, g.B, s);
-  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 1, g.part, g.B, s);
-  krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 0, g.part, g.B, s);
-  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 0, g.part, g.B, s);  // Givens step, j <- j + 1
+  krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 1, g.dpart2, g.B, s);
+  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 1, g.dpart2, g.part, g.B, s);
+  krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 0, g.dpart2, g.B, s);
+  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 0, g.dpart2, g.part, g.B, s);  // Givens step, j <- j + 1
 }
 
 template void arnoldi_step<float2>(Group&, int, int, hipStream_t);

@@ -99,6 +99,7 @@ struct Group {
   int* cyc = nullptr;        // a restart cycle started for the instance (device-driven solve)
   double* rtol = nullptr;    // relative tolerance per instance of the current linear solve
   double2* part = nullptr;
+  double2* dpart2 = nullptr;  // projection partials of the Gram-Schmidt passes (value-major)
   double* n2 = nullptr;
   double* n2b = nullptr;
   double* abs_target = nullptr;

@@ -12,6 +12,10 @@ namespace psfd {
 
 static constexpr int KB = 256;  // threads per block of the vector kernels
 static constexpr int VG = 4;    // basis vectors loaded together in the Gram-Schmidt passes
+// threads per block of the projection pass: its accumulators fill 66 registers
+// in FP32 (1024 threads fit) and 132 in FP64 (512 threads); DotBlocks<T> blocks
+// per instance keep the thread count the same
+template <class T> struct DotThreads { static constexpr int value = sizeof(T) == 8 ? 1024 : 512; };
 
 PSFD_D double wave_sum(double v) {
 #pragma unroll
@@ -51,8 +55,8 @@ template <class T> PSFD_D T wave_sum_c(T v) {
   return v;
 }
 
-template <class T, int NV>
-PSFD_D void block_sum_c(T (&acc)[NV], int cnt, double2* sm /*[KB/64][NV]*/) {
+template <class T, int NV, int NW = KB / 64>
+PSFD_D void block_sum_c(T (&acc)[NV], int cnt, double2* sm /*[NW][NV]*/) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
@@ -64,7 +68,7 @@ PSFD_D void block_sum_c(T (&acc)[NV], int cnt, double2* sm /*[KB/64][NV]*/) {
   __syncthreads();
   if ((int)threadIdx.x < cnt) {
     double2 t = sm[threadIdx.x];
-    for (int wv = 1; wv < KB / 64; ++wv) t = cadd(t, sm[wv * NV + threadIdx.x]);
+    for (int wv = 1; wv < NW; ++wv) t = cadd(t, sm[wv * NV + threadIdx.x]);
     sm[threadIdx.x] = t;
   }
   __syncthreads();
@@ -160,13 +164,15 @@ PSFD_D void givens_step(GState& S, int* run_b) {
 }
 
 // Classical Gram-Schmidt pass, projections: per-block partial sums of
-// hc_i = <v_i, w> (i <= j) and of ||w||^2 for the new vector w = v_{j+1}. The
-// second pass runs only for instances whose first pass set reorth. n must be
-// even (fields are 3 nx ny nz complex with nx >= 4).
+// hc_i = <v_i, w> (i <= j) and of ||w||^2 for the new vector w = v_{j+1},
+// stored value-major (part[b][i][block]) for the update kernel, whose blocks
+// each sum them. The second pass runs only for instances whose first pass set
+// reorth. n must be even (fields are 3 nx ny nz complex with nx >= 4).
 template <class T>
-__global__ void __launch_bounds__(KB) k_dots(const T* V, long long ldv, long long bsv, long long n, GState* st,
-                                             const int* run, int first, double2* part) {
-  __shared__ double2 sm[(KB / 64) * (MAXM + 1)];
+__global__ void __launch_bounds__(DotThreads<T>::value) k_dots(const T* V, long long ldv, long long bsv, long long n,
+                                                               GState* st, const int* run, int first, double2* part) {
+  constexpr int KBD = DotThreads<T>::value;
+  __shared__ double2 sm[(KBD / 64) * (MAXM + 1)];
   const int b = blockIdx.y;
   if (!run[b] || (!first && !st[b].reorth)) return;
   const int cnt = st[b].j + 1;
@@ -176,7 +182,7 @@ __global__ void __launch_bounds__(KB) k_dots(const T* V, long long ldv, long lon
 #pragma unroll
   for (int i = 0; i < MAXM + 1; ++i) acc[i] = cmake<T>(0, 0);
   const long long n2 = n >> 1;
-  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n2; e += (long long)gridDim.x * KB) {
+  for (long long e = (long long)blockIdx.x * KBD + threadIdx.x; e < n2; e += (long long)gridDim.x * KBD) {
     const Pair<T> wv = ld2(wb, e);
     // basis vectors in groups of VG: the loads of a group are unconditional
     // (index clamped to the last vector) so that they are all in flight together
@@ -200,34 +206,16 @@ __global__ void __launch_bounds__(KB) k_dots(const T* V, long long ldv, long lon
     for (int i = 1; i < MAXM + 1; ++i)
       if (i == cnt) acc[i].x += wv.a.x * wv.a.x + wv.a.y * wv.a.y + wv.b.x * wv.b.x + wv.b.y * wv.b.y;
   }
-  block_sum_c<T, MAXM + 1>(acc, cnt + 1, sm);
-  if ((int)threadIdx.x <= cnt) part[((long long)b * gridDim.x + blockIdx.x) * PSTR + threadIdx.x] = sm[threadIdx.x];
-}
-
-// totals of the projections over the nblk partials, fixed order (deterministic):
-// h = hc on the first pass, h += hc on the second; wn2_in = ||w||^2
-__global__ void __launch_bounds__(KB) k_dots_final(GState* st, const int* run, const double2* part, int nblk,
-                                                   int first) {
-  __shared__ double2 sm[KB / 64];
-  const int i = blockIdx.x, b = blockIdx.y;
-  if (!run[b] || (!first && !st[b].reorth)) return;
-  const int cnt = st[b].j + 1;
-  if (i > cnt) return;
-  const double2 t = sum_partials(part + (long long)b * nblk * PSTR + i, PSTR, nblk, sm);
-  if (threadIdx.x != 0) return;
-  if (i == cnt) { st[b].wn2_in = t.x; return; }
-  st[b].hc[i] = t;
-  st[b].h[i] = first ? t : cadd(st[b].h[i], t);
+  block_sum_c<T, MAXM + 1, KBD / 64>(acc, cnt + 1, sm);
+  if ((int)threadIdx.x <= cnt)
+    part[((long long)b * PSTR + threadIdx.x) * gridDim.x + blockIdx.x] = sm[threadIdx.x];
 }
 
 template <class T>
 void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
                  double2* part, int nbatch, hipStream_t s) {
-  // the second pass is rare: a smaller grid keeps its launches cheap when they have nothing to do
-  const int nblk = first ? RED_BLOCKS : RED_BLOCKS / 4;
-  hipLaunchKernelGGL((k_dots<T>), dim3(nblk, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, run, first, part);
-  hipLaunchKernelGGL(k_dots_final, dim3(MAXM + 1, nbatch), dim3(KB), 0, s, st, run, (const double2*)part, nblk,
-                     first);
+  hipLaunchKernelGGL((k_dots<T>), dim3(DotBlocks<T>::value, nbatch), dim3(DotThreads<T>::value), 0, s, V, ldv, bsv, n,
+                     st, run, first, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -235,13 +223,41 @@ void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* 
 // partial sums of ||w||^2 afterwards.
 template <class T>
 __global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bsv, long long n, GState* st,
-                                               const int* run, int first, double2* part) {
+                                               const int* run, int first, const double2* dpart, double2* part) {
   __shared__ double2 sm[(KB / 64) * 1];
+  __shared__ double2 hsum[MAXM + 2];
   __shared__ T hs[MAXM + 1];
   const int b = blockIdx.y;
   if (!run[b] || (!first && !st[b].reorth)) return;
   const int cnt = st[b].j + 1;
-  if ((int)threadIdx.x < cnt) hs[threadIdx.x] = from_d<T>(st[b].hc[threadIdx.x]);
+  // projections: every block sums the DotBlocks<T> partials of k_dots itself, in
+  // a fixed order (wave w takes values w, w + 4, ...; lane l partials l, l + 64, ...)
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NBD = DotBlocks<T>::value;
+    const double2* pb = dpart + (long long)b * PSTR * NBD;
+    for (int i = wave; i <= cnt; i += KB / 64) {
+      double2 t = make_double2(0, 0);
+#pragma unroll 4
+      for (int k = lane; k < NBD; k += 64) t = cadd(t, pb[(long long)i * NBD + k]);
+      t.x = wave_sum(t.x);
+      t.y = wave_sum(t.y);
+      if (lane == 0) hsum[i] = t;
+    }
+  }
+  __syncthreads();
+  GState& S = st[b];
+  if ((int)threadIdx.x < cnt) hs[threadIdx.x] = from_d<T>(hsum[threadIdx.x]);
+  if (blockIdx.x == 0) {
+    // h = hc on the first pass, h += hc on the second; ||w||^2 before the pass
+    const int i = threadIdx.x;
+    if (i < cnt) {
+      S.hc[i] = hsum[i];
+      S.h[i] = first ? hsum[i] : cadd(S.h[i], hsum[i]);
+    } else if (i == cnt) {
+      S.wn2_in = hsum[i].x;
+    }
+  }
   __syncthreads();
   T* Vb = V + (long long)b * bsv;
   T* wb = Vb + (long long)cnt * ldv;
@@ -303,11 +319,11 @@ __global__ void __launch_bounds__(KB) k_update_final(GState* st, int* run, const
 }
 
 template <class T>
-void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run, int first, double2* part,
-                   int nbatch, hipStream_t s) {
+void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run, int first,
+                   const double2* dpart, double2* part, int nbatch, hipStream_t s) {
   const int nblk = first ? RED_BLOCKS : RED_BLOCKS / 4;
   hipLaunchKernelGGL((k_update<T>), dim3(nblk, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, (const int*)run, first,
-                     part);
+                     dpart, part);
   hipLaunchKernelGGL(k_update_final, dim3(nbatch), dim3(KB), 0, s, st, run, (const double2*)part, nblk, first);
 }
 
@@ -581,8 +597,8 @@ void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long
 #define INST_T(T)                                                                                       \
   template void krylov_dots<T>(const T*, long long, long long, long long, GState*, const int*, int,      \
                                double2*, int, hipStream_t);                                             \
-  template void krylov_update<T>(T*, long long, long long, long long, GState*, int*, int, double2*, int, \
-                                 hipStream_t);                                                          \
+  template void krylov_update<T>(T*, long long, long long, long long, GState*, int*, int,                \
+                                 const double2*, double2*, int, hipStream_t);                           \
   template void vec_norm2<T>(const T*, long long, long long, double*, double*, const int*, int,          \
                              hipStream_t);                                                              \
   template void vec_diff2<T>(const T*, const T*, long long, long long, double*, double*, int, hipStream_t);

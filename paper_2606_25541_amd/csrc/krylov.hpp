@@ -12,6 +12,10 @@ namespace psfd {
 
 constexpr int MAXM = 32;          // largest supported restart length
 constexpr int RED_BLOCKS = 1024;  // blocks per instance of the first reduction stage
+// blocks per instance of the projection pass: 256 of 1024 threads (FP32 vectors)
+// or 512 of 512 threads (FP64)
+template <class T> struct DotBlocks { static constexpr int value = sizeof(T) == 8 ? 256 : 512; };
+constexpr int DOT_BLOCKS_MAX = 512;
 constexpr int PSTR = MAXM + 2;    // partial stride: up to MAXM + 1 dots and ||w||^2
 
 // Device-resident state of one GMRES(m) instance. All scalars are FP64.
@@ -54,16 +58,19 @@ struct GState {
 // hc[i] = <v_i, w> for i = 0..j and wn2_in = ||w||^2 (h = hc on the first
 // pass, h += hc on the second). The second pass (first == 0) runs only for
 // instances whose first pass left ||w||^2 below reorth_thr times its value
-// before the pass. part: RED_BLOCKS * PSTR complex values per instance.
+// before the pass. The projection pass leaves per-block partials in dpart
+// (PSTR * DotBlocks<T> complex values per instance); the update pass sums them.
 template <class T>
 void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
-                 double2* part, int nbatch, hipStream_t s);
-// w = v_{j+1}: w -= sum_{i<=j} hc_i v_i ; wn2 = ||w||^2 afterwards; after the
-// first pass decides the second; after the last pass of the step takes the
-// Givens step (rotated Hessenberg column, residual estimate, inv_norm, stop/run)
+                 double2* dpart, int nbatch, hipStream_t s);
+// w = v_{j+1}: hc from the projection partials (h = hc on the first pass, h += hc
+// on the second), w -= sum_{i<=j} hc_i v_i, wn2 = ||w||^2 afterwards (partials in
+// part, RED_BLOCKS * PSTR per instance); after the first pass decides the
+// second; after the last pass of the step takes the Givens step (rotated
+// Hessenberg column, residual estimate, inv_norm, stop/run)
 template <class T>
 void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run, int first,
-                   double2* part, int nbatch, hipStream_t s);
+                   const double2* dpart, double2* part, int nbatch, hipStream_t s);
 // y = H^{-1} g over the k = j + 1 completed columns
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s);
 // x += sum_{i<k} y_i v_i
