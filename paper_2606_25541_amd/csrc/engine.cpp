@@ -616,9 +616,8 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
     return false;
   };
   for (int cyc = 0; cyc < max_cycles && !done; ++cyc) {
-    apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, refl, g.mask, s);
-    vec_axpby<double2, double2, double2>(g.r, g.b, g.r, 1.0, -1.0, n3, n3, g.mask, B, s);
-    vec_norm2<double2>(g.r, n3, n3, g.dpart, g.n2, g.mask, B, s);
+    apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, refl, g.mask, s);  // A x
+    krylov_residual<T>(g.b, g.r, (T*)g.basis, n3, n3, bsv, g.dpart, g.n2, g.mask, B, s);
     krylov_cycle_start(g.st, g.n2, g.abs_target, eta, g.m, reorth_threshold(), g.mask, g.run, g.cyc, B, s);
     const int slot = cyc % FLAG_SLOTS;
     HIPCHK(hipMemcpyAsync(g.h_flags + slot * B, g.mask, sizeof(int) * B, hipMemcpyDeviceToHost, s));
@@ -633,7 +632,6 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
       if (!snapshot_live(old)) { done = true; break; }
     }
     if (done) break;
-    vec_scale_invsqrt<T, double2>((T*)g.basis, g.r, g.n2, n3, bsv, n3, g.cyc, B, s);
     for (int step = 0; step < g.m; ++step) arnoldi_step<T>(g, transpose, refl, s);
     krylov_solve_small(g.st, g.cyc, B, s);
     krylov_lincomb<T, double2>((const T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.cyc, B, s);

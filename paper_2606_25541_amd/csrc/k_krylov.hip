@@ -329,20 +329,34 @@ void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, 
 
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
-__global__ void k_solve_small(GState* st, const int* mask) {
+// back substitution y = R^{-1} g on the upper triangle of the rotated
+// Hessenberg matrix; the block stages R and g in LDS so that the single-thread
+// recurrence reads no global memory
+__global__ void __launch_bounds__(KB) k_solve_small(GState* st, const int* mask) {
+  __shared__ double2 R[MAXM][MAXM], gl[MAXM], yl[MAXM];
   const int b = blockIdx.x;
-  if (threadIdx.x != 0 || (mask && !mask[b])) return;
+  if (mask && !mask[b]) return;
   GState& S = st[b];
   const int k = S.ncols;
-  for (int i = k - 1; i >= 0; --i) {
-    double2 t = S.g[i];
-    for (int c = i + 1; c < k; ++c) t = csub(t, cmul(S.H[i][c], S.y[c]));
-    S.y[i] = cdiv(t, S.H[i][i]);
+  for (int e = threadIdx.x; e < k * k; e += KB) {
+    const int i = e / k, c = e - i * k;
+    if (c >= i) R[i][c] = S.H[i][c];
   }
+  if ((int)threadIdx.x < k) gl[threadIdx.x] = S.g[threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = k - 1; i >= 0; --i) {
+      double2 t = gl[i];
+      for (int c = i + 1; c < k; ++c) t = csub(t, cmul(R[i][c], yl[c]));
+      yl[i] = cdiv(t, R[i][i]);
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < k) S.y[threadIdx.x] = yl[threadIdx.x];
 }
 
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL(k_solve_small, dim3(nbatch), dim3(64), 0, s, st, mask);
+  hipLaunchKernelGGL(k_solve_small, dim3(nbatch), dim3(KB), 0, s, st, mask);
 }
 
 template <class T, class TX>
@@ -401,7 +415,7 @@ __global__ void k_start(GState* st, const double* rnorm2, const double* abs_targ
   S.target = abs_target[b] > t ? abs_target[b] : t;
   S.res = rn;
   S.conv = 0;
-  S.inv_norm = 1.0;  // v_0 is stored normalised
+  S.inv_norm = rn > 0.0 ? 1.0 / rn : 0.0;  // v_0 holds r unnormalised; the first apply scales it
   const bool go = rn > abs_target[b] && rn > 0.0 && rn == rn;
   S.stop = go ? 0 : 1;
   run[b] = go ? 1 : 0;
@@ -450,7 +464,7 @@ __global__ void k_cycle_start(GState* st, const double* rnorm2, const double* ab
   S.res = rn;
   S.conv = 0;
   S.stop = 0;
-  S.inv_norm = 1.0;  // v_0 is stored normalised
+  S.inv_norm = 1.0 / rn;  // v_0 holds r unnormalised; the first apply scales it
   S.cycles += 1;
   cyc[b] = 1;
   run[b] = 1;
@@ -569,6 +583,34 @@ void vec_diff2(const T* x, const T* y, long long n, long long bstride, double* p
   hipLaunchKernelGGL(k_sum_part2, dim3(nbatch), dim3(KB), 0, s, (const double*)part, RED_BLOCKS, out);
 }
 
+// r = b - Ax in FP64 with per-block partial sums of ||r||^2, stored only as the
+// unnormalised first basis vector v0 in the working precision
+template <class T>
+__global__ void __launch_bounds__(KB) k_resid(const double2* bv, const double2* ax, T* v0, long long n, long long bs,
+                                              long long bsv, double* part, const int* mask) {
+  __shared__ double2 sm[KB / 64];
+  const int b = blockIdx.y;
+  if (mask && !mask[b]) return;
+  const double2* bb = bv + (long long)b * bs;
+  const double2* ab = ax + (long long)b * bs;
+  T* vb = v0 + (long long)b * bsv;
+  double2 acc[1] = {make_double2(0, 0)};
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
+    const double2 r = csub(bb[e], ab[e]);
+    vb[e] = from_d<T>(r);
+    acc[0].x += r.x * r.x + r.y * r.y;
+  }
+  block_sum<1>(acc, 1, sm);
+  if (threadIdx.x == 0) part[(long long)b * gridDim.x + blockIdx.x] = sm[0].x;
+}
+
+template <class T>
+void krylov_residual(const double2* bv, const double2* ax, T* v0, long long n, long long bs, long long bsv,
+                     double* part, double* n2, const int* mask, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL((k_resid<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, bv, ax, v0, n, bs, bsv, part, mask);
+  hipLaunchKernelGGL(k_sum_part, dim3(nbatch), dim3(KB), 0, s, (const double*)part, RED_BLOCKS, n2, mask);
+}
+
 template <class TO, class TX>
 __global__ void __launch_bounds__(KB) k_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n,
                                                       long long bs_out, long long bs_x, const int* mask) {
@@ -601,6 +643,8 @@ void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long
                                  const double2*, double2*, int, hipStream_t);                           \
   template void vec_norm2<T>(const T*, long long, long long, double*, double*, const int*, int,          \
                              hipStream_t);                                                              \
+  template void krylov_residual<T>(const double2*, const double2*, T*, long long, long long, long long,  \
+                                   double*, double*, const int*, int, hipStream_t);                     \
   template void vec_diff2<T>(const T*, const T*, long long, long long, double*, double*, int, hipStream_t);
 INST_T(float2)
 INST_T(double2)

@@ -82,15 +82,23 @@ void krylov_lincomb(const T* V, long long ldv, long long bsv, TX* x, long long b
 // iter_limit = iters + max_iters, cycles = 0, status = PSFD_OK.
 void krylov_solve_init(GState* st, const double* bnorm2, const double* rtol, double* abs_target, int max_iters,
                        const int* act, int nbatch, hipStream_t s);
-// krylov_cycle_start, after the FP64 residual of an active instance (rnorm2[b]):
+// r = b - ax (FP64) for the instances with mask[b]: ||r||^2 to n2[b] (partials
+// in part, RED_BLOCKS per instance) and r, unnormalised, to the first basis
+// vector v0 (instance stride bsv) in the working precision
+template <class T>
+void krylov_residual(const double2* b, const double2* ax, T* v0, long long n, long long bs, long long bsv,
+                     double* part, double* n2, const int* mask, int nbatch, hipStream_t s);
+// krylov_cycle_start, after krylov_residual for an active instance (rnorm2[b]):
 // records rel_res, then ends the instance's solve (act[b] = 0) when the residual
 // meets abs_target[b] (or b = 0), is not finite (status NONFINITE) or the
 // iteration limit is reached (status NOT_CONVERGED); otherwise starts a cycle
-// like krylov_start. cyc[b] and run[b] are set for the instances whose cycle
-// starts and cleared for all others.
+// like krylov_start with inv_norm = 1 / ||r|| for the unnormalised v0. cyc[b]
+// and run[b] are set for the instances whose cycle starts and cleared for all
+// others.
 void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
                         double reorth_thr, int* act, int* run, int* cyc, int nbatch, hipStream_t s);
-// start a cycle from rnorm2[b] = ||r_b||^2: g = (||r||, 0, ...), j = 0,
+// start a cycle from rnorm2[b] = ||r_b||^2 (v0 = r unnormalised, as left by
+// krylov_residual; inv_norm = 1 / ||r||): g = (||r||, 0, ...), j = 0,
 // target = max(abs_target[b], eta ||r||); run[b] = mask[b] && ||r|| > abs_target[b]
 void krylov_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
                   double reorth_thr, const int* mask, int* run, int nbatch, hipStream_t s);

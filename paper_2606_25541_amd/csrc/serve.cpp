@@ -266,9 +266,9 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
     if (mk.second) {
       st = set_mask(g, g.mask, mk.first, s);
       if (!st.ok()) return st;
-      apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, 0, 1, g.mask, s);
-      vec_axpby<double2, double2, double2>(g.r, g.b, g.r, 1.0, -1.0, n3, n3, g.mask, B, s);
-      vec_norm2<double2>(g.r, n3, n3, g.dpart, g.n2, g.mask, B, s);
+      apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, 0, 1, g.mask, s);  // A x
+      // r = b - A x to the first basis vector (unnormalised) and ||r||^2
+      krylov_residual<T>(g.b, g.r, (T*)g.basis, n3, n3, bsv, g.dpart, g.n2, g.mask, B, s);
       std::vector<double> rn2;
       st = read_norms(g, g.n2, rn2, s);
       if (!st.ok()) return st;
@@ -296,7 +296,6 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
       if (any) {
         st = set_mask(g, g.mask, go, s);
         if (!st.ok()) return st;
-        vec_scale_invsqrt<T, double2>((T*)g.basis, g.r, g.n2, n3, bsv, n3, g.mask, B, s);
         krylov_start(g.st, g.n2, g.abs_target, g.prec == PSFD_MIXED ? o.inner_eta : 0.0, g.m, reorth_threshold(),
                      g.mask, g.run, B, s);
       }
