@@ -241,12 +241,13 @@ static int pencil_threads(const Shape& sh, int bx) {
   return nthr;
 }
 
-// data [pz][3 bx], phases [nz][bx], E_up [bx][3], partial sums [nthr], order
-// constants [bx][6], twiddles [pz]
+// data [pz][3 bx], phases [nz][bx], E_up [bx][3], shared region (partial sums,
+// phase factors, window factors), order constants [bx][7], twiddles [pz]
 static size_t pencil_lds(const Shape& sh, int bx, int nthr, size_t esz) {
   size_t d = (size_t)sh.pz * 3 * bx * esz + (size_t)sh.nz * bx * esz;
   d = (d + 15) / 16 * 16;
-  return d + (size_t)3 * bx * 16 + (size_t)nthr * 16 + (size_t)6 * bx * 16 + (size_t)sh.pz * esz;
+  return d + (size_t)3 * bx * 16 + (size_t)pencil_part_words(sh.pz, bx, nthr, (int)esz) * 16 +
+         (size_t)7 * bx * 16 + (size_t)sh.pz * esz;
 }
 
 ZCfg z_config(const Shape& sh, size_t esz) {

@@ -501,8 +501,12 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   const size_t off_e = ((size_t)(pz * LS + nz * bx) * sizeof(T) + 15) / 16;  // in double2
   double2* eup = smem_d + off_e;
   double2* part = eup + 3 * bx;
-  double2* ptab = part + nthr;
-  T* twl = reinterpret_cast<T*>(ptab + 6 * bx);  // twiddles of length pz (compile-time shapes)
+  double2* ptab = part + pencil_part_words(pz, bx, nthr, (int)sizeof(T));
+  T* twl = reinterpret_cast<T*>(ptab + 7 * bx);  // twiddles of length pz (compile-time shapes)
+  // the partial-sum region also holds the phase factors and, after the stack
+  // response, the window factors F(|l|) of the kernel multiply
+  T* ab = reinterpret_cast<T*>(part);
+  T* ftab = reinterpret_cast<T*>(part);
   // order of column kxl (the transposed operator reads the kernel at the negated order)
   auto order_of = [&](int kxl, int& mq, int& nq) {
     mq = kx0 + kxl; nq = ky;
@@ -516,12 +520,14 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     const double ikb = 1.0 / tab[TS_KBG];
     const double2 bq = reinterpret_cast<const double2*>(tab + L.off_beta())[q];
     const double2 e = reinterpret_cast<const double2*>(tab + L.off_eibl())[q];
-    ptab[tid * 6 + 0] = bq;
-    ptab[tid * 6 + 1] = cmul(bq, bq);
-    ptab[tid * 6 + 2] = make_double2(e.x - 1.0, e.y);    // s e^{i beta L} - 1 at s = +1
-    ptab[tid * 6 + 3] = make_double2(-e.x - 1.0, -e.y);  // and at s = -1
-    ptab[tid * 6 + 4] = make_double2(tab[L.off_kx() + mq] * ikb, tab[L.off_ky() + nq] * ikb);
-    ptab[tid * 6 + 5] = make_double2(tab[L.off_keep() + q], 0.0);
+    const double sik = tab[TS_SCALE] * ikb * ikb;
+    ptab[tid * 7 + 0] = bq;
+    ptab[tid * 7 + 1] = cmul(bq, bq);
+    ptab[tid * 7 + 2] = make_double2(e.x - 1.0, e.y);    // s e^{i beta L} - 1 at s = +1
+    ptab[tid * 7 + 3] = make_double2(-e.x - 1.0, -e.y);  // and at s = -1
+    ptab[tid * 7 + 4] = make_double2(tab[L.off_kx() + mq] * ikb, tab[L.off_ky() + nq] * ikb);
+    ptab[tid * 7 + 5] = make_double2(tab[L.off_keep() + q], 0.0);
+    ptab[tid * 7 + 6] = make_double2(e.x * sik, e.y * sik);  // e^{i beta L} scale / k_bg^2 (zz term at s = +1)
   }
   if (a.reflect) {
     // Layered-stack response of this block's orders (monolithic coupling):
@@ -530,12 +536,20 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     // transposed operator uses the negated order and M_q^T.
     const double2* tb = reinterpret_cast<const double2*>(tab + L.off_beta());
     const double dz = tab[TS_DZ];
-    for (int i = tid; i < nz * bx; i += nthr) {
-      const int kxl = i & (bx - 1), z = i >> lbx;
+    // phases exp(i beta z_k), z_k = (k + 1/2) dz, as products of two factors:
+    // k = Q a + c: exp(i beta (c + 1/2) dz) exp(i beta Q a dz)
+    const int Q = nz < 8 ? nz : 8, NA = nz / Q, NF = Q + NA;
+    for (int i = tid; i < NF * bx; i += nthr) {
+      const int kxl = i % bx, f = i / bx;
       int mq, nq;
       order_of(kxl, mq, nq);
       const double2 bq = tb[nq * nx + mq];
-      ph[i] = phase_exp<T>(bq, (z + 0.5) * dz);
+      ab[f * bx + kxl] = phase_exp<T>(bq, f < Q ? (f + 0.5) * dz : (double)(Q * (f - Q)) * dz);
+    }
+    __syncthreads();
+    for (int i = tid; i < nz * bx; i += nthr) {
+      const int kxl = i & (bx - 1), z = i >> lbx;
+      ph[i] = cmul(ab[(z % Q) * bx + kxl], ab[(Q + z / Q) * bx + kxl]);
     }
     __syncthreads();
     // partial sums over z: thread (ch, sq) takes planes ch, ch + nch, ...
@@ -566,13 +580,24 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     }
   }
   __syncthreads();
+  // window factors F(|l|) of every column (F is even in l): the FP64 work of the
+  // kernel multiply once per |l| instead of once per point
+  {
+    const double Lw = tab[TS_L], kap_u = tab[TS_KAPPA], scale = tab[TS_SCALE];
+    for (int i = tid; i < (pz / 2 + 1) * bx; i += nthr) {
+      const int kxl = i % bx, la = i / bx;
+      const double2* pt7 = ptab + kxl * 7;
+      const bool odd = (la & 1) != 0;
+      ftab[la * bx + kxl] =
+          window_factor_fast<T>(pt7[0], pt7[1], pt7[odd ? 3 : 2], kap_u * la, Lw, odd ? -1.0 : 1.0, scale);
+    }
+  }
   const T* tw = reinterpret_cast<const T*>(a.tw);
   typedef FftCT<LPZ, 48, 1, 48, pencil_threads_ct(LPZ)> ZCT;
   if constexpr (LPZ > 0) lds_fft_tab<T, false, true, 8, ZCT, true, false, 4>(lds, ZCT(), twl, tid);
   else lds_fft<T, false, true, 8, true, false>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
 
-  const double Lw = tab[TS_L], kap_u = tab[TS_KAPPA], scale = tab[TS_SCALE], kbg = tab[TS_KBG];
-  const double ik2 = 1.0 / (kbg * kbg);
+  const double kap_u = tab[TS_KAPPA], kbg = tab[TS_KBG];
   const int npt = bx * pz;
   for (int pt = tid; pt < npt; pt += nthr) {
     const int kxl = pt & (bx - 1);
@@ -583,17 +608,17 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     T* p0 = lds + l * LS + 0 * bx + kxl;
     T* p1 = p0 + bx;
     T* p2 = p0 + 2 * bx;
-    const double2* pt6 = ptab + kxl * 6;
-    if (pt6[5].x == 0.0) {
+    const double2* pt7 = ptab + kxl * 7;
+    if (pt7[5].x == 0.0) {
       *p0 = cmake<T>(0, 0); *p1 = cmake<T>(0, 0); *p2 = cmake<T>(0, 0);
       continue;
     }
     const double kap = kap_u * lq;
     const bool odd = (lq & 1) != 0;
-    const T F = window_factor_fast<T>(pt6[0], pt6[1], pt6[odd ? 3 : 2], kap, Lw, odd ? -1.0 : 1.0, scale);
-    const double2 e = cadd(pt6[odd ? 3 : 2], make_double2(1.0, 0.0));  // s e^{i beta L}
-    T tz = from_d<T>(make_double2(e.x * scale * ik2, e.y * scale * ik2));
-    const R kxk = (R)pt6[4].x, kyk = (R)pt6[4].y, kzk = (R)(kap / kbg);
+    const T F = ftab[(lq < 0 ? -lq : lq) * bx + kxl];
+    T tz = from_d<T>(pt7[6]);  // s e^{i beta L} scale / k_bg^2 with s = (-1)^l
+    if (odd) { tz.x = -tz.x; tz.y = -tz.y; }
+    const R kxk = (R)pt7[4].x, kyk = (R)pt7[4].y, kzk = (R)(kap / kbg);
     T v0 = *p0, v1 = *p1, v2 = *p2;
     T dxy; dxy.x = kxk * v0.x + kyk * v1.x; dxy.y = kxk * v0.y + kyk * v1.y;
     T o0, o1, o2;

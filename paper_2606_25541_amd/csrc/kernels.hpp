@@ -43,6 +43,18 @@ struct PencilArgs {
 
 struct TileShape { int tx, ty, do_x, do_y, nthr; size_t lds; int pitch; };
 
+// LDS words (16 bytes) of the pencil's shared region: readout partial sums
+// (nthr), the phase factors (bx (Q + nz / Q), Q = min(8, nz)) and the window
+// factors (bx (pz / 2 + 1)), in elements of esz bytes
+__host__ __device__ inline int pencil_part_words(int pz, int bx, int nthr, int esz) {
+  const int nz = pz / 2, q = nz < 8 ? nz : 8;
+  const int fac = bx * (q + nz / q) * esz, win = bx * (pz / 2 + 1) * esz;
+  int words = nthr;
+  if ((fac + 15) / 16 > words) words = (fac + 15) / 16;
+  if ((win + 15) / 16 > words) words = (win + 15) / 16;
+  return words;
+}
+
 template <class T, bool INV, int LD, int ST>
 void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t lds, hipStream_t s);
 template <class T>
