@@ -115,7 +115,7 @@ def sec_fp64(ctx, args, out):
     t64, (_, _, i64) = timed(lambda: plan64.psfd_solve(deps, em, orders), max(1, args.steps // 2))
     log("bench: fp64", i64)
     # tight FP64 reference for the field error of both results
-    planref = api.Plan(prob, rtol=1e-10, precision="fp64", restart=args.restart, max_iters=40000, max_outer=400)
+    planref = api.Plan(prob, rtol=1e-10, precision="fp64", restart=30, max_iters=40000, max_outer=400)
     emr = torch.empty_like(em)
     planref.psfd_solve(deps, emr, orders)
     torch.cuda.synchronize()
