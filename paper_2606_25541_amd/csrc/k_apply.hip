@@ -234,8 +234,10 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
 #pragma unroll
   for (int k = 0; k < KT; ++k) put(k);
   __syncthreads();
-  lds_fft_tab<T, INV, false, KT, Rows, false, false, 4>(lds, Rows(), twl, tid);
-  lds_fft_tab<T, INV, false, KT, Cols, false, false, 4>(lds, Cols(), twl, tid);
+  // sequence-fastest butterflies: consecutive lanes take consecutive rows (or
+  // columns), so with the odd pitch every LDS access of a pass is conflict-free
+  lds_fft_tab<T, INV, true, KT, Rows, false, false, 4>(lds, Rows(), twl, tid);
+  lds_fft_tab<T, INV, true, KT, Cols, false, false, 4>(lds, Cols(), twl, tid);
   T* out = vref<T>(a.out, b) + poff;
   const R al = (R)a.alpha, ga = (R)a.gamma;
 #pragma unroll
@@ -318,8 +320,9 @@ __global__ void __launch_bounds__(512) k_strip(TileArgs a) {
     lds[(i >> LTX) * P + (i & (TX - 1))] = v;
   }
   __syncthreads();
-  if constexpr (ROWS) lds_fft_tab<T, INV, false, KT, FftCT<LN, TY, P, 1, NT>>(lds, FftCT<LN, TY, P, 1, NT>(), twl, tid);
-  else lds_fft_tab<T, INV, false, KT, FftCT<LN, 16, 1, P, NT>>(lds, FftCT<LN, 16, 1, P, NT>(), twl, tid);
+  // sequence-fastest butterflies (conflict-free LDS accesses through the odd pitch)
+  if constexpr (ROWS) lds_fft_tab<T, INV, true, KT, FftCT<LN, TY, P, 1, NT>>(lds, FftCT<LN, TY, P, 1, NT>(), twl, tid);
+  else lds_fft_tab<T, INV, true, KT, FftCT<LN, 16, 1, P, NT>>(lds, FftCT<LN, 16, 1, P, NT>(), twl, tid);
   T* out = vref<T>(a.out, b) + poff;
   const R al = (R)a.alpha, ga = (R)a.gamma;
 #pragma unroll
