@@ -206,9 +206,10 @@ static int env_int(const char* name, int dflt) {
 static int fft_elems(size_t esz) { return esz == 8 ? 16 : 8; }
 
 // LDS row pitch of a transverse tile. The LDS serves a 64-bit access 16 lanes at a
-// time (a 128-bit one 8 lanes at a time); an odd pitch puts the 16 (8) rows that a
-// column pass touches at the same column into distinct banks, and row passes read
-// consecutive words, so neither pass conflicts.
+// time (a 128-bit one 8 lanes at a time). The FFT passes give consecutive lanes
+// consecutive sequences at the same butterfly: a column pass then reads
+// consecutive words, and with an odd pitch the 16 (8) rows of a row pass fall
+// into distinct banks, so neither pass conflicts.
 static int tile_pitch(int tx, size_t esz) {
   (void)esz;
   return tx + 1;

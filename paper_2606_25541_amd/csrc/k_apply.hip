@@ -129,12 +129,14 @@ __global__ void __launch_bounds__(1024) k_tile(TileArgs a) {
   }
   __syncthreads();
   const T* tw = reinterpret_cast<const T*>(a.tw);
+  // sequence-fastest butterflies (consecutive lanes take consecutive rows or
+  // columns at the same butterfly)
   if (!INV) {
-    if (a.do_x) lds_fft<T, false>(lds, a.log2nx, ty, pitch, 1, tw, tid, nthr);
-    if (a.do_y) lds_fft<T, false>(lds, a.log2ny, tx, 1, pitch, tw, tid, nthr);
+    if (a.do_x) lds_fft<T, false, true>(lds, a.log2nx, ty, pitch, 1, tw, tid, nthr);
+    if (a.do_y) lds_fft<T, false, true>(lds, a.log2ny, tx, 1, pitch, tw, tid, nthr);
   } else {
-    if (a.do_y) lds_fft<T, true>(lds, a.log2ny, tx, 1, pitch, tw, tid, nthr);
-    if (a.do_x) lds_fft<T, true>(lds, a.log2nx, ty, pitch, 1, tw, tid, nthr);
+    if (a.do_y) lds_fft<T, true, true>(lds, a.log2ny, tx, 1, pitch, tw, tid, nthr);
+    if (a.do_x) lds_fft<T, true, true>(lds, a.log2nx, ty, pitch, 1, tw, tid, nthr);
   }
   T* out = vref<T>(a.out, b) + poff;
   const R al = (R)a.alpha, ga = (R)a.gamma;

@@ -74,15 +74,6 @@ PSFD_D void block_sum_c(T (&acc)[NV], int cnt, double2* sm /*[NW][NV]*/) {
   __syncthreads();
 }
 
-// sum over the partial blocks of one value, fixed order (deterministic)
-PSFD_D double2 sum_partials(const double2* p, long long stride, int nblk, double2* sm) {
-  double2 t = make_double2(0, 0);
-  for (int k = threadIdx.x; k < nblk; k += KB) t = cadd(t, p[(long long)k * stride]);
-  double2 acc[1] = {t};
-  block_sum<1>(acc, 1, sm);
-  return sm[0];
-}
-
 // element pairs: FP32 complex bases are read two at a time (16-byte loads)
 template <class T> struct Pair { T a, b; };
 template <class T> PSFD_D Pair<T> ld2(const T* p, long long e2) {
@@ -109,58 +100,6 @@ template <class T> PSFD_D void st2(T* p, long long e2, Pair<T> v) {
 template <class T> PSFD_D void cfma_conj(T& acc, T v, T w) {
   acc.x += v.x * w.x + v.y * w.y;
   acc.y += v.x * w.y - v.y * w.x;
-}
-
-// Givens step of column j of A's Hessenberg after the last Gram-Schmidt pass of
-// the step (run by one block). Arnoldi runs on B with A = I - B: column j of
-// A's Hessenberg is e_j - h, and v_{j+1} = -(B v_j - V h) / ||.|| keeps the
-// subdiagonal positive. The rotations of the earlier columns are staged in LDS
-// by the whole block, so the single-thread recurrence reads no global memory.
-PSFD_D void givens_step(GState& S, int* run_b) {
-  __shared__ double2 col[MAXM + 1], snl[MAXM];
-  __shared__ double csl[MAXM];
-  const int tid = threadIdx.x;
-  const int j = S.j;
-  if (tid <= j) col[tid] = make_double2((tid == j ? 1.0 : 0.0) - S.h[tid].x, -S.h[tid].y);
-  if (tid < j) { csl[tid] = S.cs[tid]; snl[tid] = S.sn[tid]; }
-  __syncthreads();
-  if (tid == 0) {
-    const double hn = sqrt(S.wn2);
-    for (int i = 0; i < j; ++i) {
-      const double2 a = col[i], c = col[i + 1];
-      const double2 sn = snl[i];
-      const double cs = csl[i];
-      col[i] = cadd(cscale(a, cs), cmul(sn, c));
-      col[i + 1] = csub(cscale(c, cs), cmulc(a, sn) /* a * conj(sn) */);
-    }
-    const double2 a = col[j];
-    const double aa = sqrt(cabs2(a));
-    const double den = hypot(aa, hn);
-    double cs;
-    double2 sn;
-    if (aa == 0.0) { cs = 0.0; sn = make_double2(1.0, 0.0); }
-    else { cs = aa / den; sn = make_double2(a.x / aa * hn / den, a.y / aa * hn / den); }
-    col[j] = cadd(cscale(a, cs), cscale(sn, hn));
-    S.cs[j] = cs;
-    S.sn[j] = sn;
-    const double2 gj = S.g[j];
-    // g_{j+1} = -conj(sn) g_j ; g_j = cs g_j
-    const double2 gn = cmul(make_double2(sn.x, -sn.y), gj);
-    S.g[j + 1] = make_double2(-gn.x, -gn.y);
-    S.g[j] = cscale(gj, cs);
-    S.res = sqrt(cabs2(S.g[j + 1]));
-    S.iters += 1;
-    S.ncols = j + 1;
-    S.inv_norm = hn > 0.0 ? -1.0 / hn : 0.0;
-    S.conv = S.res <= S.target;
-    S.jcur = j;
-    S.j = j + 1;  // slot j + 1 holds the unnormalised new vector; the next apply scales it
-    const bool breakdown = !(hn > 1e-300 * (S.beta > 0 ? S.beta : 1.0));
-    S.stop = S.conv || (j + 1 >= S.m) || breakdown || !(S.res == S.res);
-    *run_b = S.stop ? 0 : 1;
-  }
-  __syncthreads();
-  if (tid <= j) S.H[tid][j] = col[tid];
 }
 
 // Classical Gram-Schmidt pass, projections: per-block partial sums of
@@ -295,27 +234,94 @@ __global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bs
 
 // ||w||^2 over the nblk partials (fixed order). After the first pass: decide the
 // second (||w||^2 fell below reorth_thr times its value before the pass); after
-// the last pass of the step: the Givens step.
+// the last pass of the step: the Givens step of column j of A's Hessenberg.
+// Arnoldi runs on B with A = I - B: column j of A's Hessenberg is e_j - h, and
+// v_{j+1} = -(B v_j - V h) / ||.|| keeps the subdiagonal positive.
+// Every global read is issued at the start, before the first wait (flags,
+// partials, this column's Givens inputs, the scalars), so the kernel pays one
+// memory latency; the rotations of the earlier columns are staged in LDS, so
+// the single-thread recurrence reads no global memory.
 __global__ void __launch_bounds__(KB) k_update_final(GState* st, int* run, const double2* part, int nblk,
                                                      int first) {
+  static_assert(KB > MAXM, "one thread per Hessenberg row");
   __shared__ double2 sm[KB / 64];
-  __shared__ int do_givens;
-  const int b = blockIdx.x;
-  if (!run[b] || (!first && !st[b].reorth)) return;
-  const double2 t = sum_partials(part + (long long)b * nblk, 1, nblk, sm);
+  __shared__ double2 col[MAXM + 1], snl[MAXM], gj_s;
+  __shared__ double csl[MAXM];
+  const int b = blockIdx.x, tid = threadIdx.x;
   GState& S = st[b];
-  if (threadIdx.x == 0) {
-    S.wn2 = t.x;
-    if (first) {
-      S.reorth = (t.x < S.reorth_thr * S.wn2_in) ? 1 : 0;
-      S.nreorth += S.reorth;
-    } else {
-      S.reorth = 0;
+  const int runb = run[b], reo = S.reorth, j = S.j;
+  const double2* pb = part + (long long)b * nblk;
+  constexpr int PK = RED_BLOCKS / KB;  // partials per thread (nblk <= RED_BLOCKS)
+  double2 pv[PK];
+#pragma unroll
+  for (int k = 0; k < PK; ++k) pv[k] = pb[min(tid + k * KB, nblk - 1)];
+  const double2 hv = S.h[min(tid, MAXM)], gv = S.g[min(tid, MAXM)], snv = S.sn[min(tid, MAXM - 1)];
+  const double csv = S.cs[min(tid, MAXM - 1)];
+  const double thr = S.reorth_thr, wn2in = S.wn2_in, beta = S.beta, target = S.target;
+  const int m = S.m, iters = S.iters, nreorth = S.nreorth;
+  // values used only under a branch below: tie them here, or the compiler sinks
+  // their loads into the branch, each then costing a full memory latency
+  asm volatile("" ::"v"(hv.x), "v"(hv.y), "v"(gv.x), "v"(gv.y), "v"(snv.x), "v"(snv.y), "v"(csv));
+  asm volatile("" ::"s"(thr), "s"(wn2in), "s"(beta), "s"(target), "s"(m), "s"(iters), "s"(nreorth));
+  if (!runb || (!first && !reo)) return;
+  double2 acc[1] = {make_double2(0, 0)};
+#pragma unroll
+  for (int k = 0; k < PK; ++k)
+    if (tid + k * KB < nblk) acc[0] = cadd(acc[0], pv[k]);
+  block_sum<1>(acc, 1, sm);
+  const double wn2 = sm[0].x;
+  // every thread takes the same decision from the same values
+  const int reorth = first ? (wn2 < thr * wn2in ? 1 : 0) : 0;
+  if (tid == 0) {
+    S.wn2 = wn2;
+    S.reorth = reorth;
+    if (first) S.nreorth = nreorth + reorth;
+  }
+  if (reorth) return;  // the second pass follows; the Givens step waits for it
+  if (tid <= j) col[tid] = make_double2((tid == j ? 1.0 : 0.0) - hv.x, -hv.y);
+  if (tid < j) { csl[tid] = csv; snl[tid] = snv; }
+  if (tid == j) gj_s = gv;
+  __syncthreads();
+  if (tid == 0) {
+    const double hn = sqrt(wn2);
+    for (int i = 0; i < j; ++i) {
+      const double2 a = col[i], c = col[i + 1];
+      const double2 sn = snl[i];
+      const double cs = csl[i];
+      col[i] = cadd(cscale(a, cs), cmul(sn, c));
+      col[i + 1] = csub(cscale(c, cs), cmulc(a, sn) /* a * conj(sn) */);
     }
-    do_givens = !first || !S.reorth;
+    const double2 a = col[j];
+    const double aa = sqrt(cabs2(a));
+    const double den = hypot(aa, hn);
+    double cs;
+    double2 sn;
+    if (aa == 0.0) { cs = 0.0; sn = make_double2(1.0, 0.0); }
+    else { cs = aa / den; sn = make_double2(a.x / aa * hn / den, a.y / aa * hn / den); }
+    col[j] = cadd(cscale(a, cs), cscale(sn, hn));
+    S.cs[j] = cs;
+    S.sn[j] = sn;
+    const double2 gj = gj_s;
+    // g_{j+1} = -conj(sn) g_j ; g_j = cs g_j
+    const double2 gn = cmul(make_double2(sn.x, -sn.y), gj);
+    S.g[j + 1] = make_double2(-gn.x, -gn.y);
+    S.g[j] = cscale(gj, cs);
+    const double res = sqrt(cabs2(gn));
+    S.res = res;
+    S.iters = iters + 1;
+    S.ncols = j + 1;
+    S.inv_norm = hn > 0.0 ? -1.0 / hn : 0.0;
+    const bool conv = res <= target;
+    S.conv = conv;
+    S.jcur = j;
+    S.j = j + 1;  // slot j + 1 holds the unnormalised new vector; the next apply scales it
+    const bool breakdown = !(hn > 1e-300 * (beta > 0 ? beta : 1.0));
+    const bool stop = conv || (j + 1 >= m) || breakdown || !(res == res);
+    S.stop = stop;
+    run[b] = stop ? 0 : 1;
   }
   __syncthreads();
-  if (do_givens) givens_step(S, run + b);
+  if (tid <= j) S.H[tid][j] = col[tid];
 }
 
 template <class T>
