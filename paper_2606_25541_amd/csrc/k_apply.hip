@@ -443,7 +443,11 @@ PSFD_D T window_factor_fast(double2 beta, double2 beta2, double2 num, double kap
   const T n = from_d<T>(make_double2(num.x * scale, num.y * scale));
   const T d = from_d<T>(den);
   typedef typename real_of<T>::type R;
-  const R inv = (R)1 / (d.x * d.x + d.y * d.y);
+  // FP32: hardware reciprocal (1 ulp, far inside the single-precision error of the
+  // apply); |den|^2 stays normal outside the resonance window of the series above
+  R inv;
+  if constexpr (sizeof(R) == 4) inv = __builtin_amdgcn_rcpf(d.x * d.x + d.y * d.y);
+  else inv = (R)1 / (d.x * d.x + d.y * d.y);
   T r;
   r.x = (n.x * d.x + n.y * d.y) * inv;
   r.y = (n.y * d.x - n.x * d.y) * inv;
@@ -481,15 +485,29 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   // The data half (z < nz) is LDS elements [0, nz LS): i = z LS + c bx + kxl, at
   // most 4 per thread (3 pz bx <= 8 nthr). Loads are unconditional (clamped index)
   // and all issued before the LDS writes; the padded half (z >= nz) is not stored.
-  const int nload = 3 * pz * bx, nval = nz * LS;
+  const int nval = nz * LS;
+  // compile-time shapes: nthr is a multiple of LS, so element i = tid + k nthr
+  // of a thread keeps its component c0 and column ck and moves zstep planes per
+  // k; its global offset (32-bit: a field has fewer than 2^31 elements) then
+  // advances by a constant
+  constexpr bool CT = LPZ > 0;
+  static_assert(!CT || pencil_threads_ct(LPZ) % 48 == 0, "pencil thread split");
+  const int ck = tid & (bx - 1);
+  const int zstep = CT ? nthr / LS : 0;
+  const int c0 = CT ? (tid >> lbx) % 3 : 0, z0 = CT ? tid / LS : 0;
+  const int goff0 = ((c0 * nz + z0) * ny + ky) * nx + kx0 + ck, gstep = zstep * ny * nx;
   {
     T buf[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int i = min(tid + k * nthr, nval - 1);
-      const int kxl = i & (bx - 1), rest = i >> lbx;
-      const int c = rest % 3, z = rest / 3;
-      buf[k] = w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl];
+      if constexpr (CT) {
+        buf[k] = w[goff0 + min(k, (nval - 1 - tid) / nthr) * gstep];
+      } else {
+        const int i = min(tid + k * nthr, nval - 1);
+        const int kxl = i & (bx - 1), rest = i >> lbx;
+        const int c = rest % 3, z = rest / 3;
+        buf[k] = w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl];
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -497,7 +515,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
       if (i < nval) lds[i] = buf[k];
     }
   }
-  (void)nload;  // the padded half is never read: the first forward pass treats it as zero
+  // the padded half is never read: the first forward pass treats it as zero
   const double* tab = a.tab + (long long)b * a.tab_stride;
   TabLayout L{nx, ny};
   // LDS after the data: phases exp(i beta z_k) [nz][bx] (T), the stack response
@@ -505,6 +523,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   T* ph = lds + pz * LS;
   const size_t off_e = ((size_t)(pz * LS + nz * bx) * sizeof(T) + 15) / 16;  // in double2
   double2* eup = smem_d + off_e;
+  T* eupT = reinterpret_cast<T*>(eup);  // E_up [bx][3] in the working precision
   double2* part = eup + 3 * bx;
   double2* ptab = part + pencil_part_words(pz, bx, nthr, (int)sizeof(T));
   T* twl = reinterpret_cast<T*>(ptab + 7 * bx);  // twiddles of length pz (compile-time shapes)
@@ -581,7 +600,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
       const double2* M = reinterpret_cast<const double2*>(tab + L.off_mono()) + 9LL * (nq * nx + mq);
       double2 o = make_double2(0, 0);
       for (int c = 0; c < 3; ++c) o = cadd(o, cmul(a.transpose ? M[3 * c + r] : M[3 * r + c], part[c * bx + kxl]));
-      eup[kxl * 3 + r] = o;
+      eupT[kxl * 3 + r] = from_d<T>(o);
     }
   }
   __syncthreads();
@@ -602,28 +621,31 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   if constexpr (LPZ > 0) lds_fft_tab<T, false, true, 8, ZCT, true, false, 4>(lds, ZCT(), twl, tid);
   else lds_fft<T, false, true, 8, true, false>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
 
-  const double kap_u = tab[TS_KAPPA], kbg = tab[TS_KBG];
+  // the points of a thread all lie in its column ck (nthr is a multiple of bx):
+  // its order constants are read once, in the working precision
   const int npt = bx * pz;
+  const double2* pc = ptab + ck * 7;
+  const bool keep_c = pc[5].x != 0.0;
+  const R kxk = (R)pc[4].x, kyk = (R)pc[4].y;
+  const T tz0 = from_d<T>(pc[6]);  // e^{i beta L} scale / k_bg^2 (zz term at s = +1)
+  const R kzr = (R)(tab[TS_KAPPA] / tab[TS_KBG]);  // kappa_l / k_bg = l kzr
   for (int pt = tid; pt < npt; pt += nthr) {
-    const int kxl = pt & (bx - 1);
     const int l = pt >> lbx;
     int ls = (l < pz / 2) ? l : l - pz;
     const bool nyqz = (ls == -pz / 2);
     const int lq = a.transpose ? -ls : ls;
-    T* p0 = lds + l * LS + 0 * bx + kxl;
+    T* p0 = lds + l * LS + 0 * bx + ck;
     T* p1 = p0 + bx;
     T* p2 = p0 + 2 * bx;
-    const double2* pt7 = ptab + kxl * 7;
-    if (pt7[5].x == 0.0) {
+    if (!keep_c) {
       *p0 = cmake<T>(0, 0); *p1 = cmake<T>(0, 0); *p2 = cmake<T>(0, 0);
       continue;
     }
-    const double kap = kap_u * lq;
     const bool odd = (lq & 1) != 0;
-    const T F = ftab[(lq < 0 ? -lq : lq) * bx + kxl];
-    T tz = from_d<T>(pt7[6]);  // s e^{i beta L} scale / k_bg^2 with s = (-1)^l
+    const T F = ftab[(lq < 0 ? -lq : lq) * bx + ck];
+    T tz = tz0;  // s e^{i beta L} scale / k_bg^2 with s = (-1)^l
     if (odd) { tz.x = -tz.x; tz.y = -tz.y; }
-    const R kxk = (R)pt7[4].x, kyk = (R)pt7[4].y, kzk = (R)(kap / kbg);
+    const R kzk = (R)lq * kzr;
     T v0 = *p0, v1 = *p1, v2 = *p2;
     T dxy; dxy.x = kxk * v0.x + kyk * v1.x; dxy.y = kxk * v0.y + kyk * v1.y;
     T o0, o1, o2;
@@ -646,14 +668,27 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   if constexpr (LPZ > 0) lds_fft_tab<T, true, true, 8, ZCT, false, true, 4>(lds, ZCT(), twl, tid);
   else lds_fft<T, true, true, 8, false, true>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
   const int nst = 3 * nz * bx;
-  for (int i = tid; i < nst; i += nthr) {
-    const int kxl = i & (bx - 1);
-    const int rest = i >> lbx;
-    const int c = rest % 3;
-    const int z = rest / 3;
-    T v = lds[z * LS + c * bx + kxl];
-    if (a.reflect) v = cadd(v, cmul(from_d<T>(eup[kxl * 3 + c]), ph[z * bx + kxl]));
-    w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl] = v;
+  if constexpr (CT) {
+    const T e = eupT[ck * 3 + c0];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = tid + k * nthr, z = z0 + k * zstep;
+      if (i < nst) {
+        T v = lds[i];
+        if (a.reflect) v = cadd(v, cmul(e, ph[z * bx + ck]));
+        w[goff0 + k * gstep] = v;
+      }
+    }
+  } else {
+    for (int i = tid; i < nst; i += nthr) {
+      const int kxl = i & (bx - 1);
+      const int rest = i >> lbx;
+      const int c = rest % 3;
+      const int z = rest / 3;
+      T v = lds[z * LS + c * bx + kxl];
+      if (a.reflect) v = cadd(v, cmul(eupT[kxl * 3 + c], ph[z * bx + kxl]));
+      w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl] = v;
+    }
   }
 }
 
