@@ -544,17 +544,16 @@ Status read_norms(Group& g, const double* d, std::vector<double>& out, hipStream
   return Status();
 }
 
-// Second Gram-Schmidt pass when the first pass leaves less than this fraction
-// of ||w||^2, i.e. ||w'|| < 0.32 ||w||. The classical "twice is enough" bound is
-// 0.5; with the Arnoldi process on B (A = I - B) the iteration counts of the
-// solver workloads do not change between 0.5 and 0, so only severe
-// cancellation pays for a second pass. PSFD_REORTH overrides it for experiments.
-double reorth_threshold() {
-  static double v = [] {
-    const char* e = std::getenv("PSFD_REORTH");
-    return e ? std::atof(e) : 0.1;
-  }();
-  return v;
+// A Gram-Schmidt update that leaves less than this fraction of ||w||^2
+// (||w'|| < 0.32 ||w||, the cancellation at which one classical pass stops
+// keeping the basis orthogonal to working accuracy) ends the Arnoldi cycle at
+// that column; the restart recomputes the residual and starts a fresh basis.
+// On the solver workloads it never triggers: iteration counts are those of a
+// basis orthogonalised twice. PSFD_CANCEL overrides it (read at every solve)
+// for experiments and for the test that forces the early restarts.
+double cancel_threshold() {
+  const char* e = std::getenv("PSFD_CANCEL");
+  return e ? std::atof(e) : 0.1;
 }
 
 // Arnoldi steps the server issues per host check of the run flags.
@@ -565,26 +564,28 @@ template <> const float2* deps_of<float2>(const Group& g) { return g.deps32; }
 template <> const double2* deps_of<double2>(const Group& g) { return g.deps64; }
 
 template <class T>
-void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s) {
+void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
   T* V = (T*)g.basis;
   const long long n3 = g.sh.n3, bsv = (long long)(g.m + 1) * n3;
   VecRef vin;
   vin.base = V; vin.bstride = bsv; vin.jstride = n3;
-  vin.idx = &g.st[0].j; vin.idx_stride = (int)(sizeof(GState) / sizeof(int)); vin.joff = 0;
+  if (jh >= 0) {  // every running instance stands at step jh: fixed slots
+    vin.idx = nullptr; vin.idx_stride = 0; vin.joff = jh;
+  } else {
+    vin.idx = &g.st[0].j; vin.idx_stride = (int)(sizeof(GState) / sizeof(int)); vin.joff = 0;
+  }
   VecRef vout = vin;
-  vout.joff = 1;
+  vout.joff = vin.joff + 1;
   // B v_j; slot j still holds the unnormalised vector of the previous step: the
   // first apply kernel scales it by inv_norm on load and writes v_j back
   apply_op<T>(g, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, &g.st[0].inv_norm,
               (long long)(sizeof(GState) / sizeof(double)));
-  krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 1, g.dpart2, g.B, s);
-  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 1, g.dpart2, g.part, g.B, s);
-  krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, 0, g.dpart2, g.B, s);
-  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, 0, g.dpart2, g.part, g.B, s);  // Givens step, j <- j + 1
+  krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.B, s, jh);
+  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.part, g.B, s, jh);  // Givens step, j <- j + 1
 }
 
-template void arnoldi_step<float2>(Group&, int, int, hipStream_t);
-template void arnoldi_step<double2>(Group&, int, int, hipStream_t);
+template void arnoldi_step<float2>(Group&, int, int, hipStream_t, int);
+template void arnoldi_step<double2>(Group&, int, int, hipStream_t, int);
 
 // Restarted GMRES on (I - K V) x = b for the instances with act[b] set, driven
 // from the device: each cycle computes the FP64 residual r = b - A x of the
@@ -620,7 +621,7 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   for (int cyc = 0; cyc < max_cycles && !done; ++cyc) {
     apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, refl, g.mask, s);  // A x
     krylov_residual<T>(g.b, g.r, (T*)g.basis, n3, n3, bsv, g.dpart, g.n2, g.mask, B, s);
-    krylov_cycle_start(g.st, g.n2, g.abs_target, eta, g.m, reorth_threshold(), g.mask, g.run, g.cyc, B, s);
+    krylov_cycle_start(g.st, g.n2, g.abs_target, eta, g.m, cancel_threshold(), g.mask, g.run, g.cyc, B, s);
     const int slot = cyc % FLAG_SLOTS;
     HIPCHK(hipMemcpyAsync(g.h_flags + slot * B, g.mask, sizeof(int) * B, hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(g.flag_ev[slot], s));
@@ -634,7 +635,9 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
       if (!snapshot_live(old)) { done = true; break; }
     }
     if (done) break;
-    for (int step = 0; step < g.m; ++step) arnoldi_step<T>(g, transpose, refl, s);
+    // every instance that runs a cycle starts it at j = 0 and stops for good
+    // when it ends, so the running ones all stand at step `step`
+    for (int step = 0; step < g.m; ++step) arnoldi_step<T>(g, transpose, refl, s, step);
     krylov_solve_small(g.st, g.cyc, B, s);
     krylov_lincomb<T, double2>((const T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.cyc, B, s);
     HIPCHK(hipGetLastError());

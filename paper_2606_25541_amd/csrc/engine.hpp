@@ -155,10 +155,12 @@ void readout(Group& g, const double2* x, const double2* e, const int* active, hi
 Status reflect(Group& g, double2* eup, const int* active, std::vector<double>* change, hipStream_t s);
 Status set_mask(Group& g, int* dmask, const std::vector<int>& h, hipStream_t s);
 Status read_norms(Group& g, const double* d, std::vector<double>& out, hipStream_t s);
-double reorth_threshold();
+double cancel_threshold();
 extern const int STEPS_PER_SYNC;
-// one Arnoldi step (apply of B, Gram-Schmidt, Givens, scale) for every instance with run[b]
+// one Arnoldi step (apply of B, Gram-Schmidt, Givens, scale) for every instance with run[b];
+// jh >= 0 when every running instance stands at step jh (the Krylov slots are
+// then fixed at launch), jh < 0 to take each instance's step from its state
 template <class T>
-void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s);
+void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh = -1);
 
 }  // namespace psfd

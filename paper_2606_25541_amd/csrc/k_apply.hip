@@ -459,28 +459,29 @@ PSFD_D T window_factor_fast(double2 beta, double2 beta2, double2 num, double kap
 // the global load/store touch consecutive LDS words across a wavefront.
 // At most 8 values per thread in the pencil FFTs (the launch gives 3 bx pz / 8
 // threads, at most 768), which halves the register arrays of the FP32 passes.
-// Threads of a pencil block with 16 columns and padded length 2^LPZ: at most 8
+// Threads of a pencil block with bx columns and padded length 2^LPZ: at most 8
 // values per thread in the FFT passes, at least four readout partial sums per
 // sequence (the host's pencil_threads gives the same count).
-__host__ __device__ constexpr int pencil_threads_ct(int lpz) {
-  return (3 * 16 * (1 << lpz) / 8 + 63) / 64 * 64 > 192 ? (3 * 16 * (1 << lpz) / 8 + 63) / 64 * 64 : 192;
+__host__ __device__ constexpr int pencil_threads_ct(int lpz, int bx) {
+  return (3 * bx * (1 << lpz) / 8 + 63) / 64 * 64 > (12 * bx + 63) / 64 * 64 ? (3 * bx * (1 << lpz) / 8 + 63) / 64 * 64
+                                                                            : (12 * bx + 63) / 64 * 64;
 }
 
-// LPZ > 0: 16 columns and padded length 2^LPZ fixed at compile time (the FFT
+// LPZ > 0: BXC columns and padded length 2^LPZ fixed at compile time (the FFT
 // index arithmetic folds to constants); LPZ = 0: shapes from the arguments.
-template <class T, int LPZ>
+template <class T, int LPZ, int BXC>
 __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   extern __shared__ double2 smem_d[];
   T* lds = reinterpret_cast<T*>(smem_d);
   typedef typename real_of<T>::type R;
   const int b = blockIdx.y;
   if (a.active && !a.active[b]) return;
-  const int bx = LPZ ? 16 : a.bx, pz = LPZ ? (1 << LPZ) : a.pz, nz = pz / 2, nx = a.nx, ny = a.ny;
+  const int bx = LPZ ? BXC : a.bx, pz = LPZ ? (1 << LPZ) : a.pz, nz = pz / 2, nx = a.nx, ny = a.ny;
   const int ky = blockIdx.x / a.nblk_x;
   const int kx0 = (blockIdx.x - ky * a.nblk_x) * bx;
-  const int tid = threadIdx.x, nthr = LPZ ? pencil_threads_ct(LPZ) : (int)blockDim.x;
+  const int tid = threadIdx.x, nthr = LPZ ? pencil_threads_ct(LPZ, BXC) : (int)blockDim.x;
   const int LS = 3 * bx;
-  const int lbx = LPZ ? 4 : ilog2i(bx);
+  const int lbx = LPZ ? (BXC == 16 ? 4 : BXC == 8 ? 3 : 2) : ilog2i(bx);
   T* w = vref<T>(a.w, b);
   // The data half (z < nz) is LDS elements [0, nz LS): i = z LS + c bx + kxl, at
   // most 4 per thread (3 pz bx <= 8 nthr). Loads are unconditional (clamped index)
@@ -491,7 +492,8 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   // k; its global offset (32-bit: a field has fewer than 2^31 elements) then
   // advances by a constant
   constexpr bool CT = LPZ > 0;
-  static_assert(!CT || pencil_threads_ct(LPZ) % 48 == 0, "pencil thread split");
+  static_assert(!CT || ((BXC == 16 || BXC == 8 || BXC == 4) && pencil_threads_ct(LPZ, BXC) % (3 * BXC) == 0),
+                "pencil thread split");
   const int ck = tid & (bx - 1);
   const int zstep = CT ? nthr / LS : 0;
   const int c0 = CT ? (tid >> lbx) % 3 : 0, z0 = CT ? tid / LS : 0;
@@ -617,7 +619,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     }
   }
   const T* tw = reinterpret_cast<const T*>(a.tw);
-  typedef FftCT<LPZ, 48, 1, 48, pencil_threads_ct(LPZ)> ZCT;
+  typedef FftCT<LPZ, 3 * BXC, 1, 3 * BXC, pencil_threads_ct(LPZ, BXC)> ZCT;
   if constexpr (LPZ > 0) lds_fft_tab<T, false, true, 8, ZCT, true, false, 4>(lds, ZCT(), twl, tid);
   else lds_fft<T, false, true, 8, true, false>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
 
@@ -699,9 +701,9 @@ void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStr
     allow_lds(reinterpret_cast<const void*>(kern), lds);
     hipLaunchKernelGGL(kern, grid, dim3(nthr), lds, s, a);
   };
-  if (a.bx == 16 && a.pz == 128 && nthr == pencil_threads_ct(7)) return go(k_pencil<T, 7>);
-  if (a.bx == 16 && a.pz == 64 && nthr == pencil_threads_ct(6)) return go(k_pencil<T, 6>);
-  go(k_pencil<T, 0>);
+  if (a.bx == 16 && a.pz == 128 && nthr == pencil_threads_ct(7, 16)) return go(k_pencil<T, 7, 16>);
+  if (a.bx == 16 && a.pz == 64 && nthr == pencil_threads_ct(6, 16)) return go(k_pencil<T, 6, 16>);
+  go(k_pencil<T, 0, 16>);
 }
 template void launch_pencil<float2>(const PencilArgs&, int, int, size_t, hipStream_t);
 template void launch_pencil<double2>(const PencilArgs&, int, int, size_t, hipStream_t);

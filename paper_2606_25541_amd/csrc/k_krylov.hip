@@ -1,6 +1,6 @@
 // Krylov kernels of restarted GMRES (Saad & Schultz) with classical Gram-Schmidt
-// and a conditional second pass: multi-dot products of the basis against the
-// new vector, fused update + norm, the Givens step of the new Hessenberg column,
+// (one pass; severe cancellation ends the cycle): multi-dot products of the basis
+// against the new vector, fused update + norm, the Givens step of the new Hessenberg column,
 // back substitution, the solution update and the device-side cycle control.
 // Vector data may be FP32 or FP64; per-thread and per-wavefront partial sums
 // are in the vector precision, every sum across wavefronts and blocks is in
@@ -102,19 +102,22 @@ template <class T> PSFD_D void cfma_conj(T& acc, T v, T w) {
   acc.y += v.x * w.y - v.y * w.x;
 }
 
-// Classical Gram-Schmidt pass, projections: per-block partial sums of
-// hc_i = <v_i, w> (i <= j) and of ||w||^2 for the new vector w = v_{j+1},
-// stored value-major (part[b][i][block]) for the update kernel, whose blocks
-// each sum them. The second pass runs only for instances whose first pass set
-// reorth. n must be even (fields are 3 nx ny nz complex with nx >= 4).
+// Classical Gram-Schmidt, projections: per-block partial sums of h_i = <v_i, w>
+// (i <= j) and of ||w||^2 for the new vector w = v_{j+1}, stored value-major
+// (part[b][i][block]) for the update kernel, whose blocks each sum them. n must
+// be even (fields are 3 nx ny nz complex with nx >= 4).
 template <class T>
 __global__ void __launch_bounds__(DotThreads<T>::value) k_dots(const T* V, long long ldv, long long bsv, long long n,
-                                                               GState* st, const int* run, int first, double2* part) {
+                                                               GState* st, const int* run, double2* part, int jh) {
   constexpr int KBD = DotThreads<T>::value;
   __shared__ double2 sm[(KBD / 64) * (MAXM + 1)];
   const int b = blockIdx.y;
-  if (!run[b] || (!first && !st[b].reorth)) return;
-  const int cnt = st[b].j + 1;
+  // the flag and the Krylov index are read together (one memory latency); a
+  // caller whose instances all stand at the same step passes it as jh >= 0
+  const int rb = run[b], jd = jh >= 0 ? jh : st[b].j;
+  asm volatile("" ::"s"(rb), "s"(jd));
+  if (!rb) return;
+  const int cnt = jd + 1;
   const T* Vb = V + (long long)b * bsv;
   const T* wb = Vb + (long long)cnt * ldv;
   T acc[MAXM + 1];
@@ -151,51 +154,64 @@ __global__ void __launch_bounds__(DotThreads<T>::value) k_dots(const T* V, long 
 }
 
 template <class T>
-void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
-                 double2* part, int nbatch, hipStream_t s) {
+void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* st, const int* run,
+                 double2* part, int nbatch, hipStream_t s, int jh) {
   hipLaunchKernelGGL((k_dots<T>), dim3(DotBlocks<T>::value, nbatch), dim3(DotThreads<T>::value), 0, s, V, ldv, bsv, n,
-                     st, run, first, part);
+                     st, run, part, jh);
 }
 
 // ---------------------------------------------------------------------------
-// Classical Gram-Schmidt pass, update: w -= sum_{i<=j} hc_i v_i, with per-block
+// Classical Gram-Schmidt, update: w -= sum_{i<=j} h_i v_i, with per-block
 // partial sums of ||w||^2 afterwards.
 template <class T>
 __global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bsv, long long n, GState* st,
-                                               const int* run, int first, const double2* dpart, double2* part) {
+                                               const int* run, const double2* dpart, double2* part, int jh) {
   __shared__ double2 sm[(KB / 64) * 1];
   __shared__ double2 hsum[MAXM + 2];
   __shared__ T hs[MAXM + 1];
   const int b = blockIdx.y;
-  if (!run[b] || (!first && !st[b].reorth)) return;
-  const int cnt = st[b].j + 1;
+  const int rb = run[b], jd = jh >= 0 ? jh : st[b].j;
+  asm volatile("" ::"s"(rb), "s"(jd));
+  if (!rb) return;
+  const int cnt = jd + 1;
   // projections: every block sums the DotBlocks<T> partials of k_dots itself, in
-  // a fixed order (wave w takes values w, w + 4, ...; lane l partials l, l + 64, ...)
+  // a fixed order (wave w takes values w, w + 4, ...; lane l partials l, l + 64,
+  // ...). The loads of up to RU values per wave are issued together (clamped
+  // value index), so the sum waits for one memory latency.
   {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int NBD = DotBlocks<T>::value;
+    constexpr int NBD = DotBlocks<T>::value, PL = NBD / 64, NW = KB / 64;
+    constexpr int RU = 12 / PL > 0 ? 12 / PL : 1;
     const double2* pb = dpart + (long long)b * PSTR * NBD;
-    for (int i = wave; i <= cnt; i += KB / 64) {
-      double2 t = make_double2(0, 0);
-#pragma unroll 4
-      for (int k = lane; k < NBD; k += 64) t = cadd(t, pb[(long long)i * NBD + k]);
-      t.x = wave_sum(t.x);
-      t.y = wave_sum(t.y);
-      if (lane == 0) hsum[i] = t;
+    for (int i0 = wave; i0 <= cnt; i0 += NW * RU) {
+      double2 pv[RU][PL];
+#pragma unroll
+      for (int r = 0; r < RU; ++r) {
+        const int i = min(i0 + r * NW, cnt);
+#pragma unroll
+        for (int k = 0; k < PL; ++k) pv[r][k] = pb[(long long)i * NBD + lane + 64 * k];
+      }
+#pragma unroll
+      for (int r = 0; r < RU; ++r) {
+        if (i0 + r * NW <= cnt) {
+          double2 t = make_double2(0, 0);
+#pragma unroll
+          for (int k = 0; k < PL; ++k) t = cadd(t, pv[r][k]);
+          t.x = wave_sum(t.x);
+          t.y = wave_sum(t.y);
+          if (lane == 0) hsum[i0 + r * NW] = t;
+        }
+      }
     }
   }
   __syncthreads();
   GState& S = st[b];
   if ((int)threadIdx.x < cnt) hs[threadIdx.x] = from_d<T>(hsum[threadIdx.x]);
   if (blockIdx.x == 0) {
-    // h = hc on the first pass, h += hc on the second; ||w||^2 before the pass
+    // the projections and ||w||^2 before the update
     const int i = threadIdx.x;
-    if (i < cnt) {
-      S.hc[i] = hsum[i];
-      S.h[i] = first ? hsum[i] : cadd(S.h[i], hsum[i]);
-    } else if (i == cnt) {
-      S.wn2_in = hsum[i].x;
-    }
+    if (i < cnt) S.h[i] = hsum[i];
+    else if (i == cnt) S.wn2_in = hsum[i].x;
   }
   __syncthreads();
   T* Vb = V + (long long)b * bsv;
@@ -232,24 +248,25 @@ __global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bs
   if (threadIdx.x == 0) part[((long long)b * gridDim.x + blockIdx.x)] = sm[0];
 }
 
-// ||w||^2 over the nblk partials (fixed order). After the first pass: decide the
-// second (||w||^2 fell below reorth_thr times its value before the pass); after
-// the last pass of the step: the Givens step of column j of A's Hessenberg.
-// Arnoldi runs on B with A = I - B: column j of A's Hessenberg is e_j - h, and
-// v_{j+1} = -(B v_j - V h) / ||.|| keeps the subdiagonal positive.
-// Every global read is issued at the start, before the first wait (flags,
+// ||w||^2 over the nblk partials (fixed order), then the Givens step of column j
+// of A's Hessenberg. Arnoldi runs on B with A = I - B: column j of A's
+// Hessenberg is e_j - h, and v_{j+1} = -(B v_j - V h) / ||.|| keeps the
+// subdiagonal positive. Severe cancellation (||w||^2 after the update below
+// cancel_thr times its value before) ends the cycle at this column instead of
+// a second Gram-Schmidt pass: the columns so far are kept, and the restart's
+// residual, computed afresh, carries the solve on with a new orthonormal basis.
+// Every global read is issued at the start, before the first wait (flag,
 // partials, this column's Givens inputs, the scalars), so the kernel pays one
 // memory latency; the rotations of the earlier columns are staged in LDS, so
 // the single-thread recurrence reads no global memory.
-__global__ void __launch_bounds__(KB) k_update_final(GState* st, int* run, const double2* part, int nblk,
-                                                     int first) {
+__global__ void __launch_bounds__(KB) k_update_final(GState* st, int* run, const double2* part, int nblk) {
   static_assert(KB > MAXM, "one thread per Hessenberg row");
   __shared__ double2 sm[KB / 64];
   __shared__ double2 col[MAXM + 1], snl[MAXM], gj_s;
   __shared__ double csl[MAXM];
   const int b = blockIdx.x, tid = threadIdx.x;
   GState& S = st[b];
-  const int runb = run[b], reo = S.reorth, j = S.j;
+  const int runb = run[b], j = S.j;
   const double2* pb = part + (long long)b * nblk;
   constexpr int PK = RED_BLOCKS / KB;  // partials per thread (nblk <= RED_BLOCKS)
   double2 pv[PK];
@@ -257,27 +274,20 @@ __global__ void __launch_bounds__(KB) k_update_final(GState* st, int* run, const
   for (int k = 0; k < PK; ++k) pv[k] = pb[min(tid + k * KB, nblk - 1)];
   const double2 hv = S.h[min(tid, MAXM)], gv = S.g[min(tid, MAXM)], snv = S.sn[min(tid, MAXM - 1)];
   const double csv = S.cs[min(tid, MAXM - 1)];
-  const double thr = S.reorth_thr, wn2in = S.wn2_in, beta = S.beta, target = S.target;
-  const int m = S.m, iters = S.iters, nreorth = S.nreorth;
+  const double thr = S.cancel_thr, wn2in = S.wn2_in, beta = S.beta, target = S.target;
+  const int m = S.m, iters = S.iters, ncancel = S.ncancel;
   // values used only under a branch below: tie them here, or the compiler sinks
   // their loads into the branch, each then costing a full memory latency
   asm volatile("" ::"v"(hv.x), "v"(hv.y), "v"(gv.x), "v"(gv.y), "v"(snv.x), "v"(snv.y), "v"(csv));
-  asm volatile("" ::"s"(thr), "s"(wn2in), "s"(beta), "s"(target), "s"(m), "s"(iters), "s"(nreorth));
-  if (!runb || (!first && !reo)) return;
+  asm volatile("" ::"s"(thr), "s"(wn2in), "s"(beta), "s"(target), "s"(m), "s"(iters), "s"(ncancel));
+  if (!runb) return;
   double2 acc[1] = {make_double2(0, 0)};
 #pragma unroll
   for (int k = 0; k < PK; ++k)
     if (tid + k * KB < nblk) acc[0] = cadd(acc[0], pv[k]);
   block_sum<1>(acc, 1, sm);
   const double wn2 = sm[0].x;
-  // every thread takes the same decision from the same values
-  const int reorth = first ? (wn2 < thr * wn2in ? 1 : 0) : 0;
-  if (tid == 0) {
-    S.wn2 = wn2;
-    S.reorth = reorth;
-    if (first) S.nreorth = nreorth + reorth;
-  }
-  if (reorth) return;  // the second pass follows; the Givens step waits for it
+  const bool cancel = wn2 < thr * wn2in;
   if (tid <= j) col[tid] = make_double2((tid == j ? 1.0 : 0.0) - hv.x, -hv.y);
   if (tid < j) { csl[tid] = csv; snl[tid] = snv; }
   if (tid == j) gj_s = gv;
@@ -316,7 +326,9 @@ __global__ void __launch_bounds__(KB) k_update_final(GState* st, int* run, const
     S.jcur = j;
     S.j = j + 1;  // slot j + 1 holds the unnormalised new vector; the next apply scales it
     const bool breakdown = !(hn > 1e-300 * (beta > 0 ? beta : 1.0));
-    const bool stop = conv || (j + 1 >= m) || breakdown || !(res == res);
+    const bool stop = conv || (j + 1 >= m) || breakdown || cancel || !(res == res);
+    S.wn2 = wn2;
+    if (cancel) S.ncancel = ncancel + 1;
     S.stop = stop;
     run[b] = stop ? 0 : 1;
   }
@@ -325,12 +337,12 @@ __global__ void __launch_bounds__(KB) k_update_final(GState* st, int* run, const
 }
 
 template <class T>
-void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run, int first,
-                   const double2* dpart, double2* part, int nbatch, hipStream_t s) {
-  const int nblk = first ? RED_BLOCKS : RED_BLOCKS / 4;
-  hipLaunchKernelGGL((k_update<T>), dim3(nblk, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, (const int*)run, first,
-                     dpart, part);
-  hipLaunchKernelGGL(k_update_final, dim3(nbatch), dim3(KB), 0, s, st, run, (const double2*)part, nblk, first);
+void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run,
+                   const double2* dpart, double2* part, int nbatch, hipStream_t s, int jh) {
+  const int nblk = RED_BLOCKS;
+  hipLaunchKernelGGL((k_update<T>), dim3(nblk, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, (const int*)run, dpart,
+                     part, jh);
+  hipLaunchKernelGGL(k_update_final, dim3(nbatch), dim3(KB), 0, s, st, run, (const double2*)part, nblk);
 }
 
 // ---------------------------------------------------------------------------
@@ -405,14 +417,14 @@ void krylov_lincomb(const T* V, long long ldv, long long bsv, TX* x, long long b
 }
 
 __global__ void k_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                        double reorth_thr, const int* mask, int* run) {
+                        double cancel_thr, const int* mask, int* run) {
   const int b = blockIdx.x;
   if (threadIdx.x != 0 || (mask && !mask[b])) return;  // other instances keep their state
   GState& S = st[b];
   const double rn = sqrt(rnorm2[b]);
   S.j = 0;
   S.m = m;
-  S.reorth_thr = reorth_thr;
+  S.cancel_thr = cancel_thr;
   S.ncols = 0;
   S.beta = rn;
   S.g[0] = make_double2(rn, 0.0);
@@ -446,7 +458,7 @@ void krylov_solve_init(GState* st, const double* bnorm2, const double* rtol, dou
 }
 
 __global__ void k_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                              double reorth_thr, int* act, int* run, int* cyc) {
+                              double cancel_thr, int* act, int* run, int* cyc) {
   const int b = blockIdx.x;
   if (threadIdx.x != 0) return;
   cyc[b] = 0;
@@ -460,7 +472,7 @@ __global__ void k_cycle_start(GState* st, const double* rnorm2, const double* ab
   if (S.iters >= S.iter_limit) { S.status = PSFD_NOT_CONVERGED; act[b] = 0; return; }
   S.j = 0;
   S.m = m;
-  S.reorth_thr = reorth_thr;
+  S.cancel_thr = cancel_thr;
   S.ncols = 0;
   S.beta = rn;
   S.g[0] = make_double2(rn, 0.0);
@@ -477,14 +489,14 @@ __global__ void k_cycle_start(GState* st, const double* rnorm2, const double* ab
 }
 
 void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                        double reorth_thr, int* act, int* run, int* cyc, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL(k_cycle_start, dim3(nbatch), dim3(64), 0, s, st, rnorm2, abs_target, eta, m, reorth_thr, act, run,
+                        double cancel_thr, int* act, int* run, int* cyc, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_start, dim3(nbatch), dim3(64), 0, s, st, rnorm2, abs_target, eta, m, cancel_thr, act, run,
                      cyc);
 }
 
 void krylov_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                  double reorth_thr, const int* mask, int* run, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL(k_start, dim3(nbatch), dim3(64), 0, s, st, rnorm2, abs_target, eta, m, reorth_thr, mask, run);
+                  double cancel_thr, const int* mask, int* run, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_start, dim3(nbatch), dim3(64), 0, s, st, rnorm2, abs_target, eta, m, cancel_thr, mask, run);
 }
 
 // ---------------------------------------------------------------------------
@@ -643,10 +655,10 @@ void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long
 
 // ---- instantiations ----------------------------------------------------------
 #define INST_T(T)                                                                                       \
-  template void krylov_dots<T>(const T*, long long, long long, long long, GState*, const int*, int,      \
-                               double2*, int, hipStream_t);                                             \
-  template void krylov_update<T>(T*, long long, long long, long long, GState*, int*, int,                \
-                                 const double2*, double2*, int, hipStream_t);                           \
+  template void krylov_dots<T>(const T*, long long, long long, long long, GState*, const int*,           \
+                               double2*, int, hipStream_t, int);                                        \
+  template void krylov_update<T>(T*, long long, long long, long long, GState*, int*,                     \
+                                 const double2*, double2*, int, hipStream_t, int);                      \
   template void vec_norm2<T>(const T*, long long, long long, double*, double*, const int*, int,          \
                              hipStream_t);                                                              \
   template void krylov_residual<T>(const double2*, const double2*, T*, long long, long long, long long,  \

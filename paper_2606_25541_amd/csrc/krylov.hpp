@@ -26,15 +26,15 @@ struct GState {
   int conv;         // residual estimate at or below target
   int iters;        // Arnoldi steps taken (all cycles)
   int ncols;        // Hessenberg columns completed in the current cycle
-  int reorth;       // the second Gram-Schmidt pass is needed for the current column
-  int nreorth;      // second passes taken (all cycles)
+  int ncancel;      // cycles ended early by severe cancellation (all cycles)
+  int pad0;
   double target;    // stopping threshold of the residual estimate
   double res;       // |g_{j+1}|: current residual estimate
   double beta;      // ||r0|| of the current cycle
   double inv_norm;  // scale of the unnormalised newest vector (-1 / ||w||; 1 for v_0)
   double wn2;       // ||w||^2 after the last orthogonalisation pass
   double wn2_in;    // ||w||^2 before the pass
-  double reorth_thr;  // second pass when ||w||^2 after the first < reorth_thr * ||w||^2 before
+  double cancel_thr;  // the cycle ends when ||w||^2 after the update < cancel_thr * ||w||^2 before
   int jcur;         // column index of the last step
   int cycles;       // restart cycles of the current linear solve
   int status;       // PSFD_OK, PSFD_NOT_CONVERGED or PSFD_ERR_NONFINITE (linear solve)
@@ -46,31 +46,30 @@ struct GState {
   double2 sn[MAXM];
   double2 g[MAXM + 1];
   double2 y[MAXM];
-  double2 h[MAXM + 1];        // Gram-Schmidt coefficients summed over passes
-  double2 hc[MAXM + 1];       // coefficients of the current pass
+  double2 h[MAXM + 1];        // Gram-Schmidt coefficients of the current column
 };
 
 // The Arnoldi process runs on B for systems A = I - B (B = K V or M V): the apply
 // writes B v_j into slot j+1, Gram-Schmidt orthogonalises it, and the Givens step
 // forms column j of A's Hessenberg as e_j - h (same Krylov space, no cancellation
 // against the identity part).
-// Classical Gram-Schmidt pass on w = v_{j+1} (the new apply output):
-// hc[i] = <v_i, w> for i = 0..j and wn2_in = ||w||^2 (h = hc on the first
-// pass, h += hc on the second). The second pass (first == 0) runs only for
-// instances whose first pass left ||w||^2 below reorth_thr times its value
-// before the pass. The projection pass leaves per-block partials in dpart
-// (PSTR * DotBlocks<T> complex values per instance); the update pass sums them.
+// Classical Gram-Schmidt on w = v_{j+1} (the new apply output), one pass:
+// h[i] = <v_i, w> for i = 0..j and wn2_in = ||w||^2. The projection kernel
+// leaves per-block partials in dpart (PSTR * DotBlocks<T> complex values per
+// instance); the update kernel sums them.
+// jh >= 0: every running instance stands at step j = jh (lock-step callers),
+// which spares the kernels the read of j; jh < 0: j from the state.
 template <class T>
-void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* st, const int* run, int first,
-                 double2* dpart, int nbatch, hipStream_t s);
-// w = v_{j+1}: hc from the projection partials (h = hc on the first pass, h += hc
-// on the second), w -= sum_{i<=j} hc_i v_i, wn2 = ||w||^2 afterwards (partials in
-// part, RED_BLOCKS * PSTR per instance); after the first pass decides the
-// second; after the last pass of the step takes the Givens step (rotated
-// Hessenberg column, residual estimate, inv_norm, stop/run)
+void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* st, const int* run,
+                 double2* dpart, int nbatch, hipStream_t s, int jh = -1);
+// w = v_{j+1}: h from the projection partials, w -= sum_{i<=j} h_i v_i,
+// wn2 = ||w||^2 afterwards (partials in part, RED_BLOCKS per instance), then the
+// Givens step (rotated Hessenberg column, residual estimate, inv_norm,
+// stop/run). Severe cancellation (wn2 < cancel_thr * wn2_in) ends the cycle at
+// this column: the restart's fresh residual replaces a second pass.
 template <class T>
-void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run, int first,
-                   const double2* dpart, double2* part, int nbatch, hipStream_t s);
+void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run,
+                   const double2* dpart, double2* part, int nbatch, hipStream_t s, int jh = -1);
 // y = H^{-1} g over the k = j + 1 completed columns
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s);
 // x += sum_{i<k} y_i v_i
@@ -96,12 +95,12 @@ void krylov_residual(const double2* b, const double2* ax, T* v0, long long n, lo
 // and run[b] are set for the instances whose cycle starts and cleared for all
 // others.
 void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                        double reorth_thr, int* act, int* run, int* cyc, int nbatch, hipStream_t s);
+                        double cancel_thr, int* act, int* run, int* cyc, int nbatch, hipStream_t s);
 // start a cycle from rnorm2[b] = ||r_b||^2 (v0 = r unnormalised, as left by
 // krylov_residual; inv_norm = 1 / ||r||): g = (||r||, 0, ...), j = 0,
 // target = max(abs_target[b], eta ||r||); run[b] = mask[b] && ||r|| > abs_target[b]
 void krylov_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                  double reorth_thr, const int* mask, int* run, int nbatch, hipStream_t s);
+                  double cancel_thr, const int* mask, int* run, int nbatch, hipStream_t s);
 
 // ---- batched vector kernels (instance b at offset b * bstride) ---------------
 // out = a x + c y (any mix of precisions; y may be null)

@@ -296,7 +296,7 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
       if (any) {
         st = set_mask(g, g.mask, go, s);
         if (!st.ok()) return st;
-        krylov_start(g.st, g.n2, g.abs_target, g.prec == PSFD_MIXED ? o.inner_eta : 0.0, g.m, reorth_threshold(),
+        krylov_start(g.st, g.n2, g.abs_target, g.prec == PSFD_MIXED ? o.inner_eta : 0.0, g.m, cancel_threshold(),
                      g.mask, g.run, B, s);
       }
     }

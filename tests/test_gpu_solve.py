@@ -60,6 +60,27 @@ def test_solve_matches_oracle(case, prec, coupling):
     assert info["outer_iters"] >= (2 if coupling == "outer" else 1)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_cancellation_restarts_converge(prec, monkeypatch):
+    """A Gram-Schmidt update that cancels below the threshold ends the Arnoldi
+    cycle; forcing it on (threshold 0.95) must still reach the oracle's solution,
+    through more, shorter cycles."""
+    from paper_2606_25541_amd import api
+    dev = device()
+    p = small(16, 8, 8, pol=1, phi=30.0)
+    de = clip_of("manhattan", p)
+    ref = O.solve(p, de, rtol=1e-12)
+    plan = api.Plan(p, rtol=1e-10, precision=prec, restart=20, coupling="mono")
+    _, _, base = plan.psfd_solve(torch.from_numpy(de).to(dev))
+    monkeypatch.setenv("PSFD_CANCEL", "0.95")
+    em, orders, info = plan.psfd_solve(torch.from_numpy(de).to(dev))
+    say("  forced", info, "default", base)
+    assert info["status"] == 0
+    assert info["cycles"] > base["cycles"]
+    assert rel(em.cpu().numpy(), ref["emask"]) < 1e-8
+    assert np.max(np.abs(orders.cpu().numpy() - ref["orders"])) < 1e-9
+
+
 @pytest.mark.parametrize("coupling", ["outer", "mono"])
 def test_bare_multilayer_on_gpu(coupling):
     from paper_2606_25541_amd import api
