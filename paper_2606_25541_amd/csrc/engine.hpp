@@ -97,6 +97,8 @@ struct Group {
   int* mask = nullptr;
   int* mask2 = nullptr;
   int* cyc = nullptr;        // a restart cycle started for the instance (device-driven solve)
+  int* tres = nullptr;       // the next restart evaluates b - A x (device-driven solve)
+  int* rres = nullptr;       // the next restart takes the GMRES residual from the basis
   double* rtol = nullptr;    // relative tolerance per instance of the current linear solve
   double2* part = nullptr;
   double2* dpart2 = nullptr;  // projection partials of the Gram-Schmidt passes (value-major)
@@ -156,6 +158,7 @@ Status reflect(Group& g, double2* eup, const int* active, std::vector<double>* c
 Status set_mask(Group& g, int* dmask, const std::vector<int>& h, hipStream_t s);
 Status read_norms(Group& g, const double* d, std::vector<double>& out, hipStream_t s);
 double cancel_threshold();
+int true_residual_every();
 extern const int STEPS_PER_SYNC;
 // one Arnoldi step (apply of B, Gram-Schmidt, Givens, scale) for every instance with run[b];
 // jh >= 0 when every running instance stands at step jh (the Krylov slots are

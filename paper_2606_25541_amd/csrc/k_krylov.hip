@@ -351,7 +351,8 @@ void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, 
 // Hessenberg matrix; the block stages R and g in LDS so that the single-thread
 // recurrence reads no global memory
 __global__ void __launch_bounds__(KB) k_solve_small(GState* st, const int* mask) {
-  __shared__ double2 R[MAXM][MAXM], gl[MAXM], yl[MAXM];
+  __shared__ double2 R[MAXM][MAXM], gl[MAXM + 1], yl[MAXM], cl[MAXM + 1], snl[MAXM];
+  __shared__ double csl[MAXM];
   const int b = blockIdx.x;
   if (mask && !mask[b]) return;
   GState& S = st[b];
@@ -360,7 +361,8 @@ __global__ void __launch_bounds__(KB) k_solve_small(GState* st, const int* mask)
     const int i = e / k, c = e - i * k;
     if (c >= i) R[i][c] = S.H[i][c];
   }
-  if ((int)threadIdx.x < k) gl[threadIdx.x] = S.g[threadIdx.x];
+  if ((int)threadIdx.x <= k) gl[threadIdx.x] = S.g[threadIdx.x];
+  if ((int)threadIdx.x < k) { csl[threadIdx.x] = S.cs[threadIdx.x]; snl[threadIdx.x] = S.sn[threadIdx.x]; }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int i = k - 1; i >= 0; --i) {
@@ -369,8 +371,22 @@ __global__ void __launch_bounds__(KB) k_solve_small(GState* st, const int* mask)
       yl[i] = cdiv(t, R[i][i]);
     }
   }
+  if (threadIdx.x == 1) {
+    // r = V_{k+1} (beta e_1 - Hbar y) = V_{k+1} Q^H (g_k e_k): undo the rotations
+    // G_i = [[cs, sn], [-conj(sn), cs]], last first, on g_k e_k
+    for (int i = 0; i < k; ++i) cl[i] = make_double2(0, 0);
+    cl[k] = gl[k];
+    for (int i = k - 1; i >= 0; --i) {
+      const double2 a = cl[i], c = cl[i + 1], sn = snl[i];
+      const double cs = csl[i];
+      cl[i] = csub(cscale(a, cs), cmul(sn, c));
+      cl[i + 1] = cadd(cmul(make_double2(sn.x, -sn.y), a), cscale(c, cs));
+    }
+    cl[k] = cscale(cl[k], S.inv_norm);  // slot k holds the unnormalised vector
+  }
   __syncthreads();
   if ((int)threadIdx.x < k) S.y[threadIdx.x] = yl[threadIdx.x];
+  if ((int)threadIdx.x <= k) S.cres[threadIdx.x] = cl[threadIdx.x];
 }
 
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s) {
@@ -378,42 +394,56 @@ void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s) 
 }
 
 template <class T, class TX>
-__global__ void __launch_bounds__(KB) k_lincomb(const T* V, long long ldv, long long bsv, TX* x, long long bsx,
-                                                long long n, GState* st, const int* mask) {
-  __shared__ double2 ys[MAXM];
+__global__ void __launch_bounds__(KB) k_lincomb_res(T* V, long long ldv, long long bsv, TX* x, long long bsx,
+                                                    long long n, GState* st, const int* mask, const int* rec,
+                                                    double* part) {
+  __shared__ double2 ys[MAXM], cr[MAXM + 1], sm[KB / 64];
   const int b = blockIdx.y;
   if (mask && !mask[b]) return;
   const int k = st[b].ncols;
+  const bool dor = rec[b] != 0;
   if ((int)threadIdx.x < k) ys[threadIdx.x] = st[b].y[threadIdx.x];
+  if ((int)threadIdx.x <= k) cr[threadIdx.x] = st[b].cres[threadIdx.x];
   __syncthreads();
   if (k == 0) return;
-  const T* Vb = V + (long long)b * bsv;
+  T* Vb = V + (long long)b * bsv;
   TX* xb = x + (long long)b * bsx;
+  double2 acc[1] = {make_double2(0, 0)};
+  const int nv = dor ? k + 1 : k;  // slots read: the cycle's basis, and slot k for the residual
   for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
-    double2 s = make_double2(0, 0);
+    double2 sx = make_double2(0, 0), sr = make_double2(0, 0);
     const double2 xv = to_d(xb[e]);
     // basis vectors in groups of VG with unconditional (clamped) loads, all in flight together
 #pragma unroll
-    for (int i0 = 0; i0 < MAXM; i0 += VG) {
-      if (i0 < k) {
+    for (int i0 = 0; i0 < MAXM + 1; i0 += VG) {
+      if (i0 < nv) {
         T v[VG];
 #pragma unroll
-        for (int u = 0; u < VG; ++u) v[u] = Vb[(long long)min(i0 + u, k - 1) * ldv + e];
+        for (int u = 0; u < VG; ++u) v[u] = Vb[(long long)min(i0 + u, nv - 1) * ldv + e];
 #pragma unroll
-        for (int u = 0; u < VG; ++u)
-          if (i0 + u < k) s = cadd(s, cmul(ys[i0 + u], to_d(v[u])));
+        for (int u = 0; u < VG; ++u) {
+          const int i = i0 + u;
+          if (i < k) sx = cadd(sx, cmul(ys[i], to_d(v[u])));
+          if (dor && i < nv) sr = cadd(sr, cmul(cr[i], to_d(v[u])));
+        }
       }
     }
-    xb[e] = from_d<TX>(cadd(xv, s));
+    xb[e] = from_d<TX>(cadd(xv, sx));
+    if (dor) {
+      Vb[e] = from_d<T>(sr);
+      acc[0].x += sr.x * sr.x + sr.y * sr.y;
+    }
   }
+  if (!dor) return;
+  block_sum<1>(acc, 1, sm);
+  if (threadIdx.x == 0) part[(long long)b * gridDim.x + blockIdx.x] = sm[0].x;
 }
 
 template <class T, class TX>
-void krylov_lincomb(const T* V, long long ldv, long long bsv, TX* x, long long bsx, long long n,
-                    GState* st, const int* mask, int nbatch, hipStream_t s) {
-  int nb = (int)((n + KB - 1) / KB);
-  if (nb > 2048) nb = 2048;
-  hipLaunchKernelGGL((k_lincomb<T, TX>), dim3(nb, nbatch), dim3(KB), 0, s, V, ldv, bsv, x, bsx, n, st, mask);
+void krylov_lincomb_res(T* V, long long ldv, long long bsv, TX* x, long long bsx, long long n, GState* st,
+                        const int* mask, const int* rec, double* part, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL((k_lincomb_res<T, TX>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, V, ldv, bsv, x, bsx, n, st,
+                     mask, rec, part);
 }
 
 __global__ void k_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
@@ -458,18 +488,28 @@ void krylov_solve_init(GState* st, const double* bnorm2, const double* rtol, dou
 }
 
 __global__ void k_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                              double cancel_thr, int* act, int* run, int* cyc) {
+                              double cancel_thr, int every, int* act, int* tres, int* rres, int* run, int* cyc) {
   const int b = blockIdx.x;
   if (threadIdx.x != 0) return;
   cyc[b] = 0;
   run[b] = 0;
+  const bool was_true = tres[b] != 0;
+  tres[b] = 0;
+  rres[b] = 0;
   if (!act[b]) return;
   GState& S = st[b];
   const double rn = sqrt(rnorm2[b]);
-  S.rel_res = S.bnorm > 0 ? rn / S.bnorm : 0.0;
   if (!(rn == rn) || isinf(rn)) { S.status = PSFD_ERR_NONFINITE; act[b] = 0; return; }
-  if (rn <= abs_target[b] || S.bnorm == 0.0) { act[b] = 0; return; }
-  if (S.iters >= S.iter_limit) { S.status = PSFD_NOT_CONVERGED; act[b] = 0; return; }
+  const bool met = rn <= abs_target[b] || S.bnorm == 0.0;
+  const bool limit = S.iters >= S.iter_limit;
+  if (was_true) {
+    S.rel_res = S.bnorm > 0 ? rn / S.bnorm : 0.0;
+    if (met) { act[b] = 0; return; }
+    if (limit) { S.status = PSFD_NOT_CONVERGED; act[b] = 0; return; }
+  } else if (met || limit) {
+    tres[b] = 1;  // decide on b - A x at the next restart, without a cycle now
+    return;
+  }
   S.j = 0;
   S.m = m;
   S.cancel_thr = cancel_thr;
@@ -484,15 +524,21 @@ __global__ void k_cycle_start(GState* st, const double* rnorm2, const double* ab
   S.stop = 0;
   S.inv_norm = 1.0 / rn;  // v_0 holds r unnormalised; the first apply scales it
   S.cycles += 1;
+  S.since_true = was_true ? 0 : S.since_true + 1;
+  const bool next_true = S.since_true + 1 >= every || rn <= 2.0 * abs_target[b];
+  tres[b] = next_true ? 1 : 0;
+  rres[b] = next_true ? 0 : 1;
   cyc[b] = 1;
   run[b] = 1;
 }
 
 void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                        double cancel_thr, int* act, int* run, int* cyc, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL(k_cycle_start, dim3(nbatch), dim3(64), 0, s, st, rnorm2, abs_target, eta, m, cancel_thr, act, run,
-                     cyc);
+                        double cancel_thr, int every, int* act, int* tres, int* rres, int* run, int* cyc,
+                        int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_start, dim3(nbatch), dim3(64), 0, s, st, rnorm2, abs_target, eta, m, cancel_thr, every,
+                     act, tres, rres, run, cyc);
 }
+
 
 void krylov_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
                   double cancel_thr, const int* mask, int* run, int nbatch, hipStream_t s) {
@@ -548,6 +594,10 @@ __global__ void __launch_bounds__(KB) k_sum_part(const double* part, int nblk, d
   double2 acc[1] = {make_double2(t, 0.0)};
   block_sum<1>(acc, 1, sm);
   if (threadIdx.x == 0) out[b] = sm[0].x;
+}
+
+void krylov_sum_norm(const double* part, double* n2, const int* mask, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_part, dim3(nbatch), dim3(KB), 0, s, part, RED_BLOCKS, n2, mask);
 }
 
 template <class T>
@@ -666,10 +716,10 @@ void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long
   template void vec_diff2<T>(const T*, const T*, long long, long long, double*, double*, int, hipStream_t);
 INST_T(float2)
 INST_T(double2)
-template void krylov_lincomb<float2, double2>(const float2*, long long, long long, double2*, long long, long long,
-                                              GState*, const int*, int, hipStream_t);
-template void krylov_lincomb<double2, double2>(const double2*, long long, long long, double2*, long long,
-                                               long long, GState*, const int*, int, hipStream_t);
+template void krylov_lincomb_res<float2, double2>(float2*, long long, long long, double2*, long long, long long,
+                                                  GState*, const int*, const int*, double*, int, hipStream_t);
+template void krylov_lincomb_res<double2, double2>(double2*, long long, long long, double2*, long long, long long,
+                                                   GState*, const int*, const int*, double*, int, hipStream_t);
 template void vec_axpby<double2, double2, double2>(double2*, const double2*, const double2*, double, double,
                                                    long long, long long, const int*, int, hipStream_t);
 template void vec_axpby<float2, double2, double2>(float2*, const double2*, const double2*, double, double,

@@ -27,7 +27,7 @@ struct GState {
   int iters;        // Arnoldi steps taken (all cycles)
   int ncols;        // Hessenberg columns completed in the current cycle
   int ncancel;      // cycles ended early by severe cancellation (all cycles)
-  int pad0;
+  int since_true;   // restarts since the last one with b - A x evaluated (basis residuals in between)
   double target;    // stopping threshold of the residual estimate
   double res;       // |g_{j+1}|: current residual estimate
   double beta;      // ||r0|| of the current cycle
@@ -47,6 +47,7 @@ struct GState {
   double2 g[MAXM + 1];
   double2 y[MAXM];
   double2 h[MAXM + 1];        // Gram-Schmidt coefficients of the current column
+  double2 cres[MAXM + 1];     // GMRES residual of the cycle in the basis: r = sum_i cres_i slot_i
 };
 
 // The Arnoldi process runs on B for systems A = I - B (B = K V or M V): the apply
@@ -70,12 +71,20 @@ void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* 
 template <class T>
 void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run,
                    const double2* dpart, double2* part, int nbatch, hipStream_t s, int jh = -1);
-// y = H^{-1} g over the k = j + 1 completed columns
+// y = H^{-1} g over the k = j + 1 completed columns, and the coefficients of the
+// cycle's GMRES residual in the basis, cres = Q^H (g_k e_k) (Q: the Givens
+// rotations), the last one scaled by inv_norm for the unnormalised slot k
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s);
-// x += sum_{i<k} y_i v_i
+// x += sum_{i<k} y_i v_i for the instances with mask[b]; for those with rec[b]
+// also the restart residual from the basis, r = sum_{i<=k} cres_i slot_i, into
+// slot 0 (unnormalised) with ||r||^2 partials in part (RED_BLOCKS per instance),
+// read by krylov_sum_norm. Slot 0 is read before it is overwritten, element by
+// element, in the same thread.
 template <class T, class TX>
-void krylov_lincomb(const T* V, long long ldv, long long bsv, TX* x, long long bsx, long long n,
-                    GState* st, const int* mask, int nbatch, hipStream_t s);
+void krylov_lincomb_res(T* V, long long ldv, long long bsv, TX* x, long long bsx, long long n, GState* st,
+                        const int* mask, const int* rec, double* part, int nbatch, hipStream_t s);
+// n2[b] = sum of the RED_BLOCKS partials in part for the instances with mask[b]
+void krylov_sum_norm(const double* part, double* n2, const int* mask, int nbatch, hipStream_t s);
 // Device-driven restarted solve of the instances with act[b] set.
 // krylov_solve_init: bnorm = sqrt(bnorm2[b]), abs_target[b] = rtol[b] bnorm,
 // iter_limit = iters + max_iters, cycles = 0, status = PSFD_OK.
@@ -87,15 +96,24 @@ void krylov_solve_init(GState* st, const double* bnorm2, const double* rtol, dou
 template <class T>
 void krylov_residual(const double2* b, const double2* ax, T* v0, long long n, long long bs, long long bsv,
                      double* part, double* n2, const int* mask, int nbatch, hipStream_t s);
-// krylov_cycle_start, after krylov_residual for an active instance (rnorm2[b]):
-// records rel_res, then ends the instance's solve (act[b] = 0) when the residual
-// meets abs_target[b] (or b = 0), is not finite (status NONFINITE) or the
-// iteration limit is reached (status NOT_CONVERGED); otherwise starts a cycle
-// like krylov_start with inv_norm = 1 / ||r|| for the unnormalised v0. cyc[b]
-// and run[b] are set for the instances whose cycle starts and cleared for all
-// others.
+// krylov_cycle_start, at a restart of an active instance with ||r||^2 in
+// rnorm2[b]. The restart's residual is b - A x (FP64; tres[b] set) or the
+// previous cycle's GMRES residual in its basis (rres[b] set).
+// - A non-finite residual ends the solve with status NONFINITE.
+// - After b - A x: records rel_res, and ends the solve (act[b] = 0) when the
+//   residual meets abs_target[b] (or b = 0), or with status NOT_CONVERGED when
+//   the iteration limit is reached.
+// - After a basis residual that meets the target, or at the iteration limit:
+//   runs no cycle; the next restart evaluates b - A x to decide.
+// - Otherwise starts a cycle like krylov_start, with inv_norm = 1 / ||r|| for
+//   the unnormalised v0, and chooses the next restart's residual: b - A x when
+//   `every` restarts have passed since the last one, or when ||r|| is within
+//   twice the target; the basis residual otherwise.
+// cyc[b] and run[b] are set for the instances whose cycle starts and cleared
+// for all others; tres and rres are rewritten for the next restart.
 void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                        double cancel_thr, int* act, int* run, int* cyc, int nbatch, hipStream_t s);
+                        double cancel_thr, int every, int* act, int* tres, int* rres, int* run, int* cyc,
+                        int nbatch, hipStream_t s);
 // start a cycle from rnorm2[b] = ||r_b||^2 (v0 = r unnormalised, as left by
 // krylov_residual; inv_norm = 1 / ||r||): g = (||r||, 0, ...), j = 0,
 // target = max(abs_target[b], eta ||r||); run[b] = mask[b] && ||r|| > abs_target[b]

@@ -174,6 +174,10 @@ struct SlotGroup {
   std::vector<Req*> req;
   std::vector<int> phase;
   std::vector<int> cycles;
+  // residual of the slot's next restart (the policy of the device-driven solve):
+  // b - A x (tres) or the last cycle's GMRES residual from its basis (rres);
+  // since: restarts since the last b - A x
+  std::vector<int> tres, rres, since;
   std::vector<double> bn, tgt, res;
   int occupied() const {
     int n = 0;
@@ -239,6 +243,9 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
         if (e == hipSuccess) e = hipMemsetAsync(g.st + b, 0, sizeof(GState), s);
         if (e != hipSuccess) return hip_status(e, "server init");
         G.cycles[b] = 0;
+        G.tres[b] = 1;
+        G.rres[b] = 0;
+        G.since[b] = 0;
       }
       st = set_mask(g, g.mask2, mk.first, s);
       if (!st.ok()) return st;
@@ -260,15 +267,23 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
       if (e != hipSuccess) return hip_status(e, "server targets");
     }
   }
-  // START: FP64 residual, convergence test, cycle start
+  // START: the restart's residual (b - A x, or the last cycle's basis residual),
+  // convergence test, cycle start; the same decisions as the device-driven
+  // solve, so a served request computes exactly what a lone solve does
   {
     auto mk = mask_of(P_START);
     if (mk.second) {
-      st = set_mask(g, g.mask, mk.first, s);
+      std::vector<int> mt(B, 0), mr(B, 0);
+      for (int b = 0; b < B; ++b)
+        if (mk.first[b]) (G.tres[b] ? mt : mr)[b] = 1;
+      st = set_mask(g, g.mask, mt, s);
       if (!st.ok()) return st;
       apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, 0, 1, g.mask, s);  // A x
       // r = b - A x to the first basis vector (unnormalised) and ||r||^2
       krylov_residual<T>(g.b, g.r, (T*)g.basis, n3, n3, bsv, g.dpart, g.n2, g.mask, B, s);
+      st = set_mask(g, g.rres, mr, s);
+      if (!st.ok()) return st;
+      krylov_sum_norm(g.dpart, g.n2, g.rres, B, s);
       std::vector<double> rn2;
       st = read_norms(g, g.n2, rn2, s);
       if (!st.ok()) return st;
@@ -278,16 +293,30 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
       if (e != hipSuccess) return hip_status(e, "server state");
       std::vector<int> go(B, 0);
       bool any = false;
+      const int every = true_residual_every();
       for (int b = 0; b < B; ++b) {
         if (!mk.first[b]) continue;
         const double rn = std::sqrt(rn2[b]);
+        const bool was_true = G.tres[b] != 0;
         Req* r = G.req[b];
-        r->info.rel_residual = G.bn[b] > 0 ? rn / G.bn[b] : 0.0;
         r->info.iters = hs[b].iters;
         r->info.cycles = G.cycles[b];
         if (!std::isfinite(rn)) { r->status = PSFD_ERR_NONFINITE; G.phase[b] = P_FIN; continue; }
-        if (rn <= G.tgt[b] || G.bn[b] == 0.0) { G.phase[b] = P_FIN; continue; }
-        if (hs[b].iters >= o.max_iters) { r->status = PSFD_NOT_CONVERGED; G.phase[b] = P_FIN; continue; }
+        const bool met = rn <= G.tgt[b] || G.bn[b] == 0.0;
+        const bool limit = hs[b].iters >= o.max_iters;
+        if (was_true) {
+          r->info.rel_residual = G.bn[b] > 0 ? rn / G.bn[b] : 0.0;
+          if (met) { G.phase[b] = P_FIN; continue; }
+          if (limit) { r->status = PSFD_NOT_CONVERGED; G.phase[b] = P_FIN; continue; }
+        } else if (met || limit) {
+          G.tres[b] = 1;  // decide on b - A x at the next tick, without a cycle now
+          G.rres[b] = 0;
+          continue;
+        }
+        G.since[b] = was_true ? 0 : G.since[b] + 1;
+        const bool next_true = G.since[b] + 1 >= every || rn <= 2.0 * G.tgt[b];
+        G.tres[b] = next_true ? 1 : 0;
+        G.rres[b] = next_true ? 0 : 1;
         go[b] = 1;
         any = true;
         G.phase[b] = P_ARN;
@@ -353,8 +382,12 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
       if (anyend) {
         st = set_mask(g, g.mask, end, s);
         if (!st.ok()) return st;
+        std::vector<int> rec(B, 0);
+        for (int b = 0; b < B; ++b) rec[b] = end[b] && G.rres[b];
+        st = set_mask(g, g.rres, rec, s);
+        if (!st.ok()) return st;
         krylov_solve_small(g.st, g.mask, B, s);
-        krylov_lincomb<T, double2>((const T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.mask, B, s);
+        krylov_lincomb_res<T, double2>((T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.mask, g.rres, g.dpart, B, s);
         for (int b = 0; b < B; ++b) if (end[b]) G.phase[b] = P_START;
       }
     }
@@ -432,6 +465,9 @@ static SlotGroup* group_for(psfd_server* S, const Shape& sh, Status& st) {
   ng->req.assign(cap, nullptr);
   ng->phase.assign(cap, P_FREE);
   ng->cycles.assign(cap, 0);
+  ng->tres.assign(cap, 1);
+  ng->rres.assign(cap, 0);
+  ng->since.assign(cap, 0);
   ng->bn.assign(cap, 0.0);
   ng->tgt.assign(cap, 0.0);
   ng->res.assign(cap, 0.0);
