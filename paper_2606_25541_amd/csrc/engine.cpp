@@ -308,7 +308,7 @@ size_t group_bytes(const Shape& sh, int B, int m, int prec) {
   per += 6 * n3 * 16;
   per += (size_t)(m + 1) * n3 * esz;
   per += prec == PSFD_MIXED ? n3 * esz : 0;
-  per += sizeof(GState) + RED_BLOCKS * PSTR * 16 + DOT_BLOCKS_MAX * PSTR * 16 + RED_BLOCKS * 2 * 8 + 6 * sizeof(int);
+  per += sizeof(GState) + RED_BLOCKS * PSTR * 16 + DOT_BLOCKS_MAX * PSTR * 16 + RED_BLOCKS * 2 * 8 + LIN_BLOCKS * 8 + 6 * sizeof(int);
   per += 5 * (size_t)sh.nxny * 3 * 16 + (size_t)((sh.nxny + 255) / 256) * 2 * 8 + 64;
   per += (size_t)(LAYER_CAP + 2) * sizeof(double4);
   return per * (size_t)B;
@@ -367,6 +367,7 @@ Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec) {
   GALLOC(g.n2b, 8 * B);
   GALLOC(g.abs_target, 8 * B);
   GALLOC(g.dpart, (size_t)RED_BLOCKS * 2 * 8 * B);
+  GALLOC(g.lpart, (size_t)LIN_BLOCKS * 8 * B);
   GALLOC(g.adn, nq * 16 * B);
   GALLOC(g.aup, nq * 16 * B);
   GALLOC(g.eup, nq * 16 * B);
@@ -646,7 +647,7 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
     // cycle's basis residual (left in v0 and its norm partials) where rres is
     apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, refl, g.tres, s);  // A x
     krylov_residual<T>(g.b, g.r, (T*)g.basis, n3, n3, bsv, g.dpart, g.n2, g.tres, B, s);
-    krylov_sum_norm(g.dpart, g.n2, g.rres, B, s);
+    krylov_sum_norm(g.lpart, g.n2, g.rres, B, s);
     krylov_cycle_start(g.st, g.n2, g.abs_target, eta, g.m, cancel_threshold(), every, g.mask, g.tres, g.rres, g.run,
                        g.cyc, B, s);
     const int slot = cyc % FLAG_SLOTS;
@@ -666,7 +667,7 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
     // when it ends, so the running ones all stand at step `step`
     for (int step = 0; step < g.m; ++step) arnoldi_step<T>(g, transpose, refl, s, step);
     krylov_solve_small(g.st, g.cyc, B, s);
-    krylov_lincomb_res<T, double2>((T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.cyc, g.rres, g.dpart, B, s);
+    krylov_lincomb_res<T, double2>((T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.cyc, g.rres, g.lpart, B, s);
     HIPCHK(hipGetLastError());
   }
   std::vector<GState> hs(B);

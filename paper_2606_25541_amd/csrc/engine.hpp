@@ -106,6 +106,7 @@ struct Group {
   double* n2b = nullptr;
   double* abs_target = nullptr;
   double* dpart = nullptr;
+  double* lpart = nullptr;   // norm partials of the basis residual (LIN_BLOCKS per instance)
   double2 *adn = nullptr, *aup = nullptr, *eup = nullptr, *ord = nullptr, *eup2 = nullptr;
   double* rpart = nullptr;
   int rblk = 1;

@@ -410,22 +410,25 @@ __global__ void __launch_bounds__(KB) k_lincomb_res(T* V, long long ldv, long lo
   TX* xb = x + (long long)b * bsx;
   double2 acc[1] = {make_double2(0, 0)};
   const int nv = dor ? k + 1 : k;  // slots read: the cycle's basis, and slot k for the residual
+  // basis vectors in groups of LG with unconditional (clamped) loads, all in
+  // flight together with the x load (two groups for a restart length of 10).
+  // The group loop stays rolled: unrolled, the compiler keeps every coefficient
+  // of the LDS tables in registers across the element loop (hundreds of VGPRs,
+  // one wavefront per SIMD); rolled, each group reads its coefficients at use.
+  constexpr int LG = 8;
   for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
     double2 sx = make_double2(0, 0), sr = make_double2(0, 0);
     const double2 xv = to_d(xb[e]);
-    // basis vectors in groups of VG with unconditional (clamped) loads, all in flight together
+#pragma unroll 1
+    for (int i0 = 0; i0 < nv; i0 += LG) {
+      T v[LG];
 #pragma unroll
-    for (int i0 = 0; i0 < MAXM + 1; i0 += VG) {
-      if (i0 < nv) {
-        T v[VG];
+      for (int u = 0; u < LG; ++u) v[u] = Vb[(long long)min(i0 + u, nv - 1) * ldv + e];
 #pragma unroll
-        for (int u = 0; u < VG; ++u) v[u] = Vb[(long long)min(i0 + u, nv - 1) * ldv + e];
-#pragma unroll
-        for (int u = 0; u < VG; ++u) {
-          const int i = i0 + u;
-          if (i < k) sx = cadd(sx, cmul(ys[i], to_d(v[u])));
-          if (dor && i < nv) sr = cadd(sr, cmul(cr[i], to_d(v[u])));
-        }
+      for (int u = 0; u < LG; ++u) {
+        const int i = i0 + u;
+        if (i < k) sx = cadd(sx, cmul(ys[i], to_d(v[u])));
+        if (dor && i < nv) sr = cadd(sr, cmul(cr[i], to_d(v[u])));
       }
     }
     xb[e] = from_d<TX>(cadd(xv, sx));
@@ -442,7 +445,7 @@ __global__ void __launch_bounds__(KB) k_lincomb_res(T* V, long long ldv, long lo
 template <class T, class TX>
 void krylov_lincomb_res(T* V, long long ldv, long long bsv, TX* x, long long bsx, long long n, GState* st,
                         const int* mask, const int* rec, double* part, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL((k_lincomb_res<T, TX>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, V, ldv, bsv, x, bsx, n, st,
+  hipLaunchKernelGGL((k_lincomb_res<T, TX>), dim3(LIN_BLOCKS, nbatch), dim3(KB), 0, s, V, ldv, bsv, x, bsx, n, st,
                      mask, rec, part);
 }
 
@@ -597,7 +600,7 @@ __global__ void __launch_bounds__(KB) k_sum_part(const double* part, int nblk, d
 }
 
 void krylov_sum_norm(const double* part, double* n2, const int* mask, int nbatch, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_part, dim3(nbatch), dim3(KB), 0, s, part, RED_BLOCKS, n2, mask);
+  hipLaunchKernelGGL(k_sum_part, dim3(nbatch), dim3(KB), 0, s, part, LIN_BLOCKS, n2, mask);
 }
 
 template <class T>

@@ -12,6 +12,7 @@ namespace psfd {
 
 constexpr int MAXM = 32;          // largest supported restart length
 constexpr int RED_BLOCKS = 1024;  // blocks per instance of the first reduction stage
+constexpr int LIN_BLOCKS = 2048;  // blocks per instance of the solution update (its norm partials)
 // blocks per instance of the projection pass: 256 of 1024 threads (FP32 vectors)
 // or 512 of 512 threads (FP64)
 template <class T> struct DotBlocks { static constexpr int value = sizeof(T) == 8 ? 256 : 512; };
@@ -77,13 +78,13 @@ void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, 
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s);
 // x += sum_{i<k} y_i v_i for the instances with mask[b]; for those with rec[b]
 // also the restart residual from the basis, r = sum_{i<=k} cres_i slot_i, into
-// slot 0 (unnormalised) with ||r||^2 partials in part (RED_BLOCKS per instance),
+// slot 0 (unnormalised) with ||r||^2 partials in part (LIN_BLOCKS per instance),
 // read by krylov_sum_norm. Slot 0 is read before it is overwritten, element by
 // element, in the same thread.
 template <class T, class TX>
 void krylov_lincomb_res(T* V, long long ldv, long long bsv, TX* x, long long bsx, long long n, GState* st,
                         const int* mask, const int* rec, double* part, int nbatch, hipStream_t s);
-// n2[b] = sum of the RED_BLOCKS partials in part for the instances with mask[b]
+// n2[b] = sum of the LIN_BLOCKS partials of krylov_lincomb_res in part, for the instances with mask[b]
 void krylov_sum_norm(const double* part, double* n2, const int* mask, int nbatch, hipStream_t s);
 // Device-driven restarted solve of the instances with act[b] set.
 // krylov_solve_init: bnorm = sqrt(bnorm2[b]), abs_target[b] = rtol[b] bnorm,

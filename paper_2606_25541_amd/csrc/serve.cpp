@@ -283,7 +283,7 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
       krylov_residual<T>(g.b, g.r, (T*)g.basis, n3, n3, bsv, g.dpart, g.n2, g.mask, B, s);
       st = set_mask(g, g.rres, mr, s);
       if (!st.ok()) return st;
-      krylov_sum_norm(g.dpart, g.n2, g.rres, B, s);
+      krylov_sum_norm(g.lpart, g.n2, g.rres, B, s);
       std::vector<double> rn2;
       st = read_norms(g, g.n2, rn2, s);
       if (!st.ok()) return st;
@@ -387,7 +387,7 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
         st = set_mask(g, g.rres, rec, s);
         if (!st.ok()) return st;
         krylov_solve_small(g.st, g.mask, B, s);
-        krylov_lincomb_res<T, double2>((T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.mask, g.rres, g.dpart, B, s);
+        krylov_lincomb_res<T, double2>((T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.mask, g.rres, g.lpart, B, s);
         for (int b = 0; b < B; ++b) if (end[b]) G.phase[b] = P_START;
       }
     }
