@@ -385,7 +385,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--restart", type=int, default=10)
+    ap.add_argument("--restart", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="headline solve only")
     ap.add_argument("--only", choices=SECTIONS, default=None, help="run one section")
