@@ -594,8 +594,8 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
   }
   VecRef vout = vin;
   vout.joff = vin.joff + 1;
-  // B v_j; slot j still holds the unnormalised vector of the previous step: the
-  // first apply kernel scales it by inv_norm on load and writes v_j back
+  // B v_j; slots keep the unnormalised vectors (v_i = sc[i] slot_i): the first
+  // apply kernel scales slot j by inv_norm = sc[j] on load
   apply_op<T>(g, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, &g.st[0].inv_norm,
               (long long)(sizeof(GState) / sizeof(double)));
   krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.B, s, jh);

@@ -53,9 +53,9 @@ __global__ void __launch_bounds__(1024) k_tile(TileArgs a) {
   constexpr int KG = 8;
   // in-plane offset of element i (32-bit: a plane holds at most 2^16 elements)
   auto off_of = [&](int i) -> int { return (y0 + (i >> ltx)) * nxa + (x0 + (i & (tx - 1))); };
-  // normalisation on load of the newest Arnoldi vector, written back (skipped at scale 1)
-  const R sc = (LD == LD_VX && a.in_scale) ? (R)a.in_scale[(long long)b * a.scale_stride] : (R)1;
-  T* inw = vref<T>(a.in, b) + poff;
+  // scale of the input on load (the newest Arnoldi vector is kept unnormalised),
+  // folded into the contrast factor
+  const R ks = k0sq * ((LD == LD_VX && a.in_scale) ? (R)a.in_scale[(long long)b * a.scale_stride] : (R)1);
   if (LD == LD_PLAIN || LD == LD_VX) {
 #pragma unroll 1
     for (int g = 0; g < KT; g += KG) {
@@ -73,12 +73,8 @@ __global__ void __launch_bounds__(1024) k_tile(TileArgs a) {
       for (int k = 0; k < KG; ++k) {
         const int i = tid + (g + k) * nthr;
         if (i < ntile) {
-          T x = va[k];
-          if (LD == LD_VX && sc != (R)1) {
-            x.x *= sc; x.y *= sc;
-            inw[off_of(i)] = x;
-          }
-          const T v = LD == LD_VX ? cscale(cmul(vb[k], x), k0sq) : x;
+          const T x = va[k];
+          const T v = LD == LD_VX ? cscale(cmul(vb[k], x), ks) : x;
           lds[(i >> ltx) * pitch + (i & (tx - 1))] = v;
         }
       }
@@ -217,18 +213,14 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   }
   const double* tab = a.tab + (long long)b * a.tab_stride;
   const R k0sq = (R)tab[TS_K0SQ];
-  // normalisation on load of the newest Arnoldi vector, written back (skipped at scale 1)
-  const R sc = (LD == LD_VX && a.in_scale) ? (R)a.in_scale[(long long)b * a.scale_stride] : (R)1;
-  T* inw = vref<T>(a.in, b) + poff;
+  // scale of the input on load (the newest Arnoldi vector is kept unnormalised),
+  // folded into the contrast factor
+  const R ks = k0sq * ((LD == LD_VX && a.in_scale) ? (R)a.in_scale[(long long)b * a.scale_stride] : (R)1);
   if (tid < N) twl[tid] = tw0;
   auto put = [&](int k) {
     const int i = tid + k * NT;
-    T x = va[k];
-    if (LD == LD_VX && sc != (R)1) {
-      x.x *= sc; x.y *= sc;
-      inw[i] = x;
-    }
-    const T v = LD == LD_VX ? cscale(cmul(vb[LD == LD_VX ? k : 0], x), k0sq) : x;
+    const T x = va[k];
+    const T v = LD == LD_VX ? cscale(cmul(vb[LD == LD_VX ? k : 0], x), ks) : x;
     lds[(i >> LN) * P + (i & (N - 1))] = v;
   };
   typedef FftCT<LN, N, P, 1, NT> Rows;
@@ -305,20 +297,16 @@ __global__ void __launch_bounds__(512) k_strip(TileArgs a) {
   }
   const double* tab = a.tab + (long long)b * a.tab_stride;
   const R k0sq = (R)tab[TS_K0SQ];
-  // normalisation on load of the newest Arnoldi vector, written back (skipped at scale 1)
-  const R sc = (LD == LD_VX && a.in_scale) ? (R)a.in_scale[(long long)b * a.scale_stride] : (R)1;
-  T* inw = vref<T>(a.in, b) + poff;
+  // scale of the input on load (the newest Arnoldi vector is kept unnormalised),
+  // folded into the contrast factor
+  const R ks = k0sq * ((LD == LD_VX && a.in_scale) ? (R)a.in_scale[(long long)b * a.scale_stride] : (R)1);
   static_assert(NT >= N, "one twiddle per thread");
   if (tid < N) twl[tid] = tw0;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     const int i = tid + k * NT;
-    T x = va[k];
-    if (LD == LD_VX && sc != (R)1) {
-      x.x *= sc; x.y *= sc;
-      inw[off_of(i)] = x;
-    }
-    const T v = LD == LD_VX ? cscale(cmul(vb[LD == LD_VX ? k : 0], x), k0sq) : x;
+    const T x = va[k];
+    const T v = LD == LD_VX ? cscale(cmul(vb[LD == LD_VX ? k : 0], x), ks) : x;
     lds[(i >> LTX) * P + (i & (TX - 1))] = v;
   }
   __syncthreads();

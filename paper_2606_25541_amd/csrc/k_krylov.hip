@@ -174,6 +174,8 @@ __global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bs
   asm volatile("" ::"s"(rb), "s"(jd));
   if (!rb) return;
   const int cnt = jd + 1;
+  // slot scale of this thread's projection (v_i = sc_i slot_i, sc real)
+  const double scv = st[b].sc[min((int)threadIdx.x, MAXM)];
   // projections: every block sums the DotBlocks<T> partials of k_dots itself, in
   // a fixed order (wave w takes values w, w + 4, ...; lane l partials l, l + 64,
   // ...). The loads of up to RU values per wave are issued together (clamped
@@ -206,11 +208,12 @@ __global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bs
   }
   __syncthreads();
   GState& S = st[b];
-  if ((int)threadIdx.x < cnt) hs[threadIdx.x] = from_d<T>(hsum[threadIdx.x]);
+  // h_i = <v_i, w> = sc_i <slot_i, w>; w -= sum_i h_i v_i = sum_i (h_i sc_i) slot_i
+  if ((int)threadIdx.x < cnt) hs[threadIdx.x] = from_d<T>(cscale(hsum[threadIdx.x], scv * scv));
   if (blockIdx.x == 0) {
     // the projections and ||w||^2 before the update
     const int i = threadIdx.x;
-    if (i < cnt) S.h[i] = hsum[i];
+    if (i < cnt) S.h[i] = cscale(hsum[i], scv);
     else if (i == cnt) S.wn2_in = hsum[i].x;
   }
   __syncthreads();
@@ -321,6 +324,7 @@ __global__ void __launch_bounds__(KB) k_update_final(GState* st, int* run, const
     S.iters = iters + 1;
     S.ncols = j + 1;
     S.inv_norm = hn > 0.0 ? -1.0 / hn : 0.0;
+    S.sc[j + 1] = S.inv_norm;
     const bool conv = res <= target;
     S.conv = conv;
     S.jcur = j;
@@ -382,11 +386,11 @@ __global__ void __launch_bounds__(KB) k_solve_small(GState* st, const int* mask)
       cl[i] = csub(cscale(a, cs), cmul(sn, c));
       cl[i + 1] = cadd(cmul(make_double2(sn.x, -sn.y), a), cscale(c, cs));
     }
-    cl[k] = cscale(cl[k], S.inv_norm);  // slot k holds the unnormalised vector
   }
   __syncthreads();
-  if ((int)threadIdx.x < k) S.y[threadIdx.x] = yl[threadIdx.x];
-  if ((int)threadIdx.x <= k) S.cres[threadIdx.x] = cl[threadIdx.x];
+  // as coefficients of the slots, which hold v_i / sc_i
+  if ((int)threadIdx.x < k) S.y[threadIdx.x] = cscale(yl[threadIdx.x], S.sc[threadIdx.x]);
+  if ((int)threadIdx.x <= k) S.cres[threadIdx.x] = cscale(cl[threadIdx.x], S.sc[threadIdx.x]);
 }
 
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s) {
@@ -467,6 +471,7 @@ __global__ void k_start(GState* st, const double* rnorm2, const double* abs_targ
   S.res = rn;
   S.conv = 0;
   S.inv_norm = rn > 0.0 ? 1.0 / rn : 0.0;  // v_0 holds r unnormalised; the first apply scales it
+  S.sc[0] = S.inv_norm;
   const bool go = rn > abs_target[b] && rn > 0.0 && rn == rn;
   S.stop = go ? 0 : 1;
   run[b] = go ? 1 : 0;
@@ -526,6 +531,7 @@ __global__ void k_cycle_start(GState* st, const double* rnorm2, const double* ab
   S.conv = 0;
   S.stop = 0;
   S.inv_norm = 1.0 / rn;  // v_0 holds r unnormalised; the first apply scales it
+  S.sc[0] = S.inv_norm;
   S.cycles += 1;
   S.since_true = was_true ? 0 : S.since_true + 1;
   const bool next_true = S.since_true + 1 >= every || rn <= 2.0 * abs_target[b];
@@ -682,30 +688,6 @@ void krylov_residual(const double2* bv, const double2* ax, T* v0, long long n, l
   hipLaunchKernelGGL(k_sum_part, dim3(nbatch), dim3(KB), 0, s, (const double*)part, RED_BLOCKS, n2, mask);
 }
 
-template <class TO, class TX>
-__global__ void __launch_bounds__(KB) k_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n,
-                                                      long long bs_out, long long bs_x, const int* mask) {
-  const int b = blockIdx.y;
-  if (mask && !mask[b]) return;
-  const double v = n2[b];
-  const double sc = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
-  TO* ob = out + (long long)b * bs_out;
-  const TX* xb = x + (long long)b * bs_x;
-  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
-    double2 xv = to_d(xb[e]);
-    ob[e] = from_d<TO>(make_double2(xv.x * sc, xv.y * sc));
-  }
-}
-
-template <class TO, class TX>
-void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long long bs_out, long long bs_x,
-                       const int* mask, int nbatch, hipStream_t s) {
-  int nb = (int)((n + KB - 1) / KB);
-  if (nb > 2048) nb = 2048;
-  hipLaunchKernelGGL((k_scale_invsqrt<TO, TX>), dim3(nb, nbatch), dim3(KB), 0, s, out, x, n2, n, bs_out, bs_x,
-                     mask);
-}
-
 // ---- instantiations ----------------------------------------------------------
 #define INST_T(T)                                                                                       \
   template void krylov_dots<T>(const T*, long long, long long, long long, GState*, const int*,           \
@@ -731,9 +713,5 @@ template void vec_axpby<double2, float2, float2>(double2*, const float2*, const 
                                                  long long, long long, const int*, int, hipStream_t);
 template void vec_axpby<float2, float2, float2>(float2*, const float2*, const float2*, double, double,
                                                 long long, long long, const int*, int, hipStream_t);
-template void vec_scale_invsqrt<double2, double2>(double2*, const double2*, const double*, long long, long long,
-                                                  long long, const int*, int, hipStream_t);
-template void vec_scale_invsqrt<float2, double2>(float2*, const double2*, const double*, long long, long long,
-                                                 long long, const int*, int, hipStream_t);
 
 }  // namespace psfd

@@ -24,7 +24,7 @@ struct TileArgs {
   const void* tw;        // twiddle table in the working precision
   double alpha, gamma;   // ST_AXPBY: out = alpha * aux + gamma * result
   const int* active;     // optional per-instance flags (0 = skip)
-  const double* in_scale;  // LD_VX, optional: in *= in_scale[b * scale_stride] on load, written back to in
+  const double* in_scale;  // LD_VX, optional: in scaled by in_scale[b * scale_stride] on load (in is not modified)
   long long scale_stride;
 };
 

@@ -32,7 +32,7 @@ struct GState {
   double target;    // stopping threshold of the residual estimate
   double res;       // |g_{j+1}|: current residual estimate
   double beta;      // ||r0|| of the current cycle
-  double inv_norm;  // scale of the unnormalised newest vector (-1 / ||w||; 1 for v_0)
+  double inv_norm;  // scale of the newest slot, sc[j] (-1 / ||w||; 1 / ||r|| for v_0)
   double wn2;       // ||w||^2 after the last orthogonalisation pass
   double wn2_in;    // ||w||^2 before the pass
   double cancel_thr;  // the cycle ends when ||w||^2 after the update < cancel_thr * ||w||^2 before
@@ -49,6 +49,7 @@ struct GState {
   double2 y[MAXM];
   double2 h[MAXM + 1];        // Gram-Schmidt coefficients of the current column
   double2 cres[MAXM + 1];     // GMRES residual of the cycle in the basis: r = sum_i cres_i slot_i
+  double sc[MAXM + 1];        // slot scales: v_i = sc[i] slot_i (slots keep the unnormalised vectors)
 };
 
 // The Arnoldi process runs on B for systems A = I - B (B = K V or M V): the apply
@@ -74,7 +75,8 @@ void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, 
                    const double2* dpart, double2* part, int nbatch, hipStream_t s, int jh = -1);
 // y = H^{-1} g over the k = j + 1 completed columns, and the coefficients of the
 // cycle's GMRES residual in the basis, cres = Q^H (g_k e_k) (Q: the Givens
-// rotations), the last one scaled by inv_norm for the unnormalised slot k
+// rotations); both are stored times the slot scales sc[i], as coefficients of
+// the slots themselves
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s);
 // x += sum_{i<k} y_i v_i for the instances with mask[b]; for those with rec[b]
 // also the restart residual from the basis, r = sum_{i<=k} cres_i slot_i, into
@@ -130,10 +132,6 @@ void vec_axpby(TO* out, const TX* x, const TY* y, double a, double c, long long 
 template <class T>
 void vec_norm2(const T* x, long long n, long long bstride, double* part, double* out, const int* mask,
                int nbatch, hipStream_t s);
-// out = x / sqrt(n2[b]) (0 when n2[b] == 0); out and x have their own instance strides
-template <class TO, class TX>
-void vec_scale_invsqrt(TO* out, const TX* x, const double* n2, long long n, long long bs_out, long long bs_x,
-                       const int* mask, int nbatch, hipStream_t s);
 // out[b] = ||x_b - y_b||^2 and ||x_b||^2 (for relative changes); out has 2 doubles per instance
 template <class T>
 void vec_diff2(const T* x, const T* y, long long n, long long bstride, double* part, double* out,
