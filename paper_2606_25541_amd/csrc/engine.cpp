@@ -410,7 +410,8 @@ static TileArgs tile_base(const Group& g, const void* tw, const TileShape& t) {
 
 template <class T>
 void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose,
-                 int refl, const int* active, hipStream_t s, const double* in_scale, long long scale_stride) {
+                 int refl, const int* active, hipStream_t s, const double* in_scale, long long scale_stride,
+                 const GivensTask* gt) {
   const Shape& sh = g.sh;
   const XYCfg c = xy_config(sh, sizeof(T));
   const int np = 3 * sh.nz;
@@ -422,8 +423,15 @@ void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* w
       TileArgs a = tile_base(g, tw, c.full);
       a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
       a.in_scale = in_scale; a.scale_stride = scale_stride;
+      if (gt) {
+        // the pending Givens step rides along with the square-plane kernel;
+        // other kernels take it as a launch of its own first
+        if (tile_is_plane(a, sizeof(T))) a.gv = *gt;
+        else krylov_givens(gt->st, gt->run, gt->part, g.B, s);
+      }
       launch_tile<T, false, LD_VX, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
     } else {
+      if (gt) krylov_givens(gt->st, gt->run, gt->part, g.B, s);
       TileArgs a = tile_base(g, tw, c.rows);
       a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
       a.in_scale = in_scale; a.scale_stride = scale_stride;
@@ -461,20 +469,22 @@ void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* w
   }
 }
 template void apply_stage<float2>(Group&, int, const float2*, VecRef, VecRef, float2*, int, int, int, const int*,
-                                  hipStream_t, const double*, long long);
+                                  hipStream_t, const double*, long long, const GivensTask*);
 template void apply_stage<double2>(Group&, int, const double2*, VecRef, VecRef, double2*, int, int, int,
-                                   const int*, hipStream_t, const double*, long long);
+                                   const int*, hipStream_t, const double*, long long, const GivensTask*);
 
 template <class T>
 void apply_op(Group& g, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose, int refl,
-              const int* active, hipStream_t s, const double* in_scale, long long scale_stride) {
+              const int* active, hipStream_t s, const double* in_scale, long long scale_stride,
+              const GivensTask* gt) {
   for (int stage = 0; stage < 3; ++stage)
-    apply_stage<T>(g, stage, deps, in, out, ws, kmode, transpose, refl, active, s, in_scale, scale_stride);
+    apply_stage<T>(g, stage, deps, in, out, ws, kmode, transpose, refl, active, s, in_scale, scale_stride,
+                   stage == 0 ? gt : nullptr);
 }
 template void apply_op<float2>(Group&, const float2*, VecRef, VecRef, float2*, int, int, int, const int*,
-                               hipStream_t, const double*, long long);
+                               hipStream_t, const double*, long long, const GivensTask*);
 template void apply_op<double2>(Group&, const double2*, VecRef, VecRef, double2*, int, int, int, const int*,
-                                hipStream_t, const double*, long long);
+                                hipStream_t, const double*, long long, const GivensTask*);
 
 // e = E_inc + IFFT_xy(E_up exp(i beta z)) per plane (FP64)
 void inject(Group& g, const double2* eup, double2* out, const int* active, hipStream_t s) {
@@ -595,11 +605,15 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
   VecRef vout = vin;
   vout.joff = vin.joff + 1;
   // B v_j; slots keep the unnormalised vectors (v_i = sc[i] slot_i): the first
-  // apply kernel scales slot j by inv_norm = sc[j] on load
+  // apply kernel scales slot j by inv_norm = sc[j] on load. In lock-step solves
+  // the Givens step of step j - 1 rides along with this apply (gt), and the
+  // last step of the cycle takes it at once.
+  const bool lock = jh >= 0;
+  const GivensTask gt{g.st, g.run, g.part};
   apply_op<T>(g, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, &g.st[0].inv_norm,
-              (long long)(sizeof(GState) / sizeof(double)));
+              (long long)(sizeof(GState) / sizeof(double)), lock && jh > 0 ? &gt : nullptr);
   krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.B, s, jh);
-  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.part, g.B, s, jh);  // Givens step, j <- j + 1
+  krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.part, g.B, s, jh, !lock || jh == g.m - 1);
 }
 
 template void arnoldi_step<float2>(Group&, int, int, hipStream_t, int);

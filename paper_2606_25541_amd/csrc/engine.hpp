@@ -127,14 +127,16 @@ Status group_set_tables(Group& g, int b, const Problem& pr, const std::vector<do
 // in_scale (optional): per-instance factor at in_scale[b * scale_stride] applied to
 // x on load, and the scaled x written back to in (normalisation of the newest
 // Arnoldi vector inside the apply).
+// gt (optional): a pending Givens step to take along with the first kernel.
 template <class T>
 void apply_op(Group& g, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose, int refl,
-              const int* active, hipStream_t s, const double* in_scale = nullptr, long long scale_stride = 0);
+              const int* active, hipStream_t s, const double* in_scale = nullptr, long long scale_stride = 0,
+              const GivensTask* gt = nullptr);
 // one of the three launches of apply_op: 0 transverse forward, 1 z-pencil, 2 transverse inverse
 template <class T>
 void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose,
                  int refl, const int* active, hipStream_t s, const double* in_scale = nullptr,
-                 long long scale_stride = 0);
+                 long long scale_stride = 0, const GivensTask* gt = nullptr);
 
 struct SolveStats {
   int iters = 0, outer = 0, cycles = 0, status = PSFD_OK;

@@ -7,6 +7,7 @@
 // plane-wave readouts of the mask field, reflection by T_R, order amplitudes.
 #include "kernels.hpp"
 #include "fft_lds.hpp"
+#include "givens.hpp"
 
 namespace psfd {
 
@@ -186,6 +187,11 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   T* lds = reinterpret_cast<T*>(smem_d);
   T* twl = lds + N * P;
   const int b = blockIdx.y;
+  // a GivensTask takes the extra last block of the grid
+  if (LD == LD_VX && a.gv.st && blockIdx.x == gridDim.x - 1) {
+    givens_task(a.gv.st, a.gv.run, a.gv.part, RED_BLOCKS, b);
+    return;
+  }
   if (a.active && !a.active[b]) return;
   const int plane = blockIdx.x;
   const int z = plane % a.nz;
@@ -214,8 +220,12 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   const double* tab = a.tab + (long long)b * a.tab_stride;
   const R k0sq = (R)tab[TS_K0SQ];
   // scale of the input on load (the newest Arnoldi vector is kept unnormalised),
-  // folded into the contrast factor
-  const R ks = k0sq * ((LD == LD_VX && a.in_scale) ? (R)a.in_scale[(long long)b * a.scale_stride] : (R)1);
+  // folded into the contrast factor: from in_scale, or with a GivensTask from
+  // the norm partials the task itself sums (bitwise the same value)
+  R scl = (R)1;
+  if (LD == LD_VX && a.gv.st) scl = (R)inv_norm_of(norm_from_partials(a.gv.part + (long long)b * RED_BLOCKS, RED_BLOCKS));
+  else if (LD == LD_VX && a.in_scale) scl = (R)a.in_scale[(long long)b * a.scale_stride];
+  const R ks = k0sq * scl;
   if (tid < N) twl[tid] = tw0;
   auto put = [&](int k) {
     const int i = tid + k * NT;
@@ -331,20 +341,31 @@ __global__ void __launch_bounds__(512) k_strip(TileArgs a) {
 // fused square planes of 64 x 64 (and 128 x 128 in FP32) with plain or
 // contrast-multiply loads take the square-plane kernel; the row and column
 // passes of square 128 x 128 and 256 x 256 planes take the strip kernel
+// log2 of the plane side when launch_tile runs the square-plane kernel (fused
+// transverse FFT of full N x N planes in LDS: 64^2, and 128^2 in FP32), else 0
+static int plane_ln(const TileArgs& a, size_t esz) {
+  const bool sq = a.do_x && a.do_y && a.tx == a.nx && a.ty == a.ny && a.nx == a.ny;
+  if (sq && a.nx == 64) return 6;
+  if (sq && a.nx == 128 && esz == 8) return 7;
+  return 0;
+}
+bool tile_is_plane(const TileArgs& a, size_t esz) { return plane_ln(a, esz) != 0; }
+
 template <class T, bool INV, int LD, int ST>
 void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t lds, hipStream_t s) {
   dim3 grid(nplanes * a.tiles_x * a.tiles_y, nbatch);
-  const bool sq = (LD == LD_PLAIN || LD == LD_VX) && a.do_x && a.do_y && a.tx == a.nx && a.ty == a.ny &&
-                  a.nx == a.ny;
   auto plane = [&](auto kern, int ln) {
     const size_t l = plane_lds(ln, sizeof(T));
     allow_lds(reinterpret_cast<const void*>(kern), l);
-    hipLaunchKernelGGL(kern, grid, dim3(plane_threads(ln)), l, s, a);
+    dim3 g2 = grid;
+    if (LD == LD_VX && a.gv.st) g2.x += 1;  // the GivensTask block
+    hipLaunchKernelGGL(kern, g2, dim3(plane_threads(ln)), l, s, a);
   };
   if constexpr (LD == LD_PLAIN || LD == LD_VX) {
-    if (sq && a.nx == 64) return plane(k_plane<T, INV, LD, ST, 6>, 6);
+    const int ln = plane_ln(a, sizeof(T));
+    if (ln == 6) return plane(k_plane<T, INV, LD, ST, 6>, 6);
     if constexpr (sizeof(T) == 8)
-      if (sq && a.nx == 128) return plane(k_plane<T, INV, LD, ST, 7>, 7);
+      if (ln == 7) return plane(k_plane<T, INV, LD, ST, 7>, 7);
     // strips of square planes: rows (TY = 4096 / N full rows) or 16-column strips
     auto strip = [&](auto kern, int nt, size_t l) {
       allow_lds(reinterpret_cast<const void*>(kern), l);

@@ -6,11 +6,13 @@
 // are in the vector precision, every sum across wavefronts and blocks is in
 // FP64 and in a fixed order (bitwise reproducible, independent of the batch).
 #include "krylov.hpp"
+#include "givens.hpp"
 #include "../../include/psfd.h"
 
 namespace psfd {
 
 static constexpr int KB = 256;  // threads per block of the vector kernels
+static_assert(KB == GIVENS_THREADS, "the update-final block is the Givens task's block");
 static constexpr int VG = 4;    // basis vectors loaded together in the Gram-Schmidt passes
 // threads per block of the projection pass: its accumulators fill 66 registers
 // in FP32 (1024 threads fit) and 132 in FP64 (512 threads); DotBlocks<T> blocks
@@ -251,102 +253,21 @@ __global__ void __launch_bounds__(KB) k_update(T* V, long long ldv, long long bs
   if (threadIdx.x == 0) part[((long long)b * gridDim.x + blockIdx.x)] = sm[0];
 }
 
-// ||w||^2 over the nblk partials (fixed order), then the Givens step of column j
-// of A's Hessenberg. Arnoldi runs on B with A = I - B: column j of A's
-// Hessenberg is e_j - h, and v_{j+1} = -(B v_j - V h) / ||.|| keeps the
-// subdiagonal positive. Severe cancellation (||w||^2 after the update below
-// cancel_thr times its value before) ends the cycle at this column instead of
-// a second Gram-Schmidt pass: the columns so far are kept, and the restart's
-// residual, computed afresh, carries the solve on with a new orthonormal basis.
-// Every global read is issued at the start, before the first wait (flag,
-// partials, this column's Givens inputs, the scalars), so the kernel pays one
-// memory latency; the rotations of the earlier columns are staged in LDS, so
-// the single-thread recurrence reads no global memory.
+// the Givens step of the newest column (see givens_task), one block per instance
 __global__ void __launch_bounds__(KB) k_update_final(GState* st, int* run, const double2* part, int nblk) {
-  static_assert(KB > MAXM, "one thread per Hessenberg row");
-  __shared__ double2 sm[KB / 64];
-  __shared__ double2 col[MAXM + 1], snl[MAXM], gj_s;
-  __shared__ double csl[MAXM];
-  const int b = blockIdx.x, tid = threadIdx.x;
-  GState& S = st[b];
-  const int runb = run[b], j = S.j;
-  const double2* pb = part + (long long)b * nblk;
-  constexpr int PK = RED_BLOCKS / KB;  // partials per thread (nblk <= RED_BLOCKS)
-  double2 pv[PK];
-#pragma unroll
-  for (int k = 0; k < PK; ++k) pv[k] = pb[min(tid + k * KB, nblk - 1)];
-  const double2 hv = S.h[min(tid, MAXM)], gv = S.g[min(tid, MAXM)], snv = S.sn[min(tid, MAXM - 1)];
-  const double csv = S.cs[min(tid, MAXM - 1)];
-  const double thr = S.cancel_thr, wn2in = S.wn2_in, beta = S.beta, target = S.target;
-  const int m = S.m, iters = S.iters, ncancel = S.ncancel;
-  // values used only under a branch below: tie them here, or the compiler sinks
-  // their loads into the branch, each then costing a full memory latency
-  asm volatile("" ::"v"(hv.x), "v"(hv.y), "v"(gv.x), "v"(gv.y), "v"(snv.x), "v"(snv.y), "v"(csv));
-  asm volatile("" ::"s"(thr), "s"(wn2in), "s"(beta), "s"(target), "s"(m), "s"(iters), "s"(ncancel));
-  if (!runb) return;
-  double2 acc[1] = {make_double2(0, 0)};
-#pragma unroll
-  for (int k = 0; k < PK; ++k)
-    if (tid + k * KB < nblk) acc[0] = cadd(acc[0], pv[k]);
-  block_sum<1>(acc, 1, sm);
-  const double wn2 = sm[0].x;
-  const bool cancel = wn2 < thr * wn2in;
-  if (tid <= j) col[tid] = make_double2((tid == j ? 1.0 : 0.0) - hv.x, -hv.y);
-  if (tid < j) { csl[tid] = csv; snl[tid] = snv; }
-  if (tid == j) gj_s = gv;
-  __syncthreads();
-  if (tid == 0) {
-    const double hn = sqrt(wn2);
-    for (int i = 0; i < j; ++i) {
-      const double2 a = col[i], c = col[i + 1];
-      const double2 sn = snl[i];
-      const double cs = csl[i];
-      col[i] = cadd(cscale(a, cs), cmul(sn, c));
-      col[i + 1] = csub(cscale(c, cs), cmulc(a, sn) /* a * conj(sn) */);
-    }
-    const double2 a = col[j];
-    const double aa = sqrt(cabs2(a));
-    const double den = hypot(aa, hn);
-    double cs;
-    double2 sn;
-    if (aa == 0.0) { cs = 0.0; sn = make_double2(1.0, 0.0); }
-    else { cs = aa / den; sn = make_double2(a.x / aa * hn / den, a.y / aa * hn / den); }
-    col[j] = cadd(cscale(a, cs), cscale(sn, hn));
-    S.cs[j] = cs;
-    S.sn[j] = sn;
-    const double2 gj = gj_s;
-    // g_{j+1} = -conj(sn) g_j ; g_j = cs g_j
-    const double2 gn = cmul(make_double2(sn.x, -sn.y), gj);
-    S.g[j + 1] = make_double2(-gn.x, -gn.y);
-    S.g[j] = cscale(gj, cs);
-    const double res = sqrt(cabs2(gn));
-    S.res = res;
-    S.iters = iters + 1;
-    S.ncols = j + 1;
-    S.inv_norm = hn > 0.0 ? -1.0 / hn : 0.0;
-    S.sc[j + 1] = S.inv_norm;
-    const bool conv = res <= target;
-    S.conv = conv;
-    S.jcur = j;
-    S.j = j + 1;  // slot j + 1 holds the unnormalised new vector; the next apply scales it
-    const bool breakdown = !(hn > 1e-300 * (beta > 0 ? beta : 1.0));
-    const bool stop = conv || (j + 1 >= m) || breakdown || cancel || !(res == res);
-    S.wn2 = wn2;
-    if (cancel) S.ncancel = ncancel + 1;
-    S.stop = stop;
-    run[b] = stop ? 0 : 1;
-  }
-  __syncthreads();
-  if (tid <= j) S.H[tid][j] = col[tid];
+  givens_task(st, run, part, nblk, blockIdx.x);
+}
+
+void krylov_givens(GState* st, int* run, const double2* part, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_final, dim3(nbatch), dim3(KB), 0, s, st, run, part, RED_BLOCKS);
 }
 
 template <class T>
 void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run,
-                   const double2* dpart, double2* part, int nbatch, hipStream_t s, int jh) {
-  const int nblk = RED_BLOCKS;
-  hipLaunchKernelGGL((k_update<T>), dim3(nblk, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, (const int*)run, dpart,
-                     part, jh);
-  hipLaunchKernelGGL(k_update_final, dim3(nbatch), dim3(KB), 0, s, st, run, (const double2*)part, nblk);
+                   const double2* dpart, double2* part, int nbatch, hipStream_t s, int jh, bool givens) {
+  hipLaunchKernelGGL((k_update<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, V, ldv, bsv, n, st, (const int*)run,
+                     dpart, part, jh);
+  if (givens) krylov_givens(st, run, part, nbatch, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -693,7 +614,7 @@ void krylov_residual(const double2* bv, const double2* ax, T* v0, long long n, l
   template void krylov_dots<T>(const T*, long long, long long, long long, GState*, const int*,           \
                                double2*, int, hipStream_t, int);                                        \
   template void krylov_update<T>(T*, long long, long long, long long, GState*, int*,                     \
-                                 const double2*, double2*, int, hipStream_t, int);                      \
+                                 const double2*, double2*, int, hipStream_t, int, bool);                \
   template void vec_norm2<T>(const T*, long long, long long, double*, double*, const int*, int,          \
                              hipStream_t);                                                              \
   template void krylov_residual<T>(const double2*, const double2*, T*, long long, long long, long long,  \

@@ -5,6 +5,17 @@
 namespace psfd {
 
 enum LoadOp { LD_PLAIN = 0, LD_VX = 1, LD_INJECT = 2, LD_VXE = 3, LD_INJECT_T = 4 };
+
+struct GState;
+// The Givens step of the previous Arnoldi step, left to the first apply kernel
+// of this one: an extra block of the kernel runs it (see givens_task), and the
+// other blocks take the scale of their input vector from the same norm
+// partials (RED_BLOCKS per instance in part) instead of in_scale.
+struct GivensTask {
+  GState* st;
+  int* run;
+  const double2* part;
+}; 
 enum StoreOp { ST_PLAIN = 0, ST_AXPBY = 1 };
 
 // One launch of the transverse (x/y) FFT kernel over tiles of every plane of
@@ -26,6 +37,7 @@ struct TileArgs {
   const int* active;     // optional per-instance flags (0 = skip)
   const double* in_scale;  // LD_VX, optional: in scaled by in_scale[b * scale_stride] on load (in is not modified)
   long long scale_stride;
+  GivensTask gv;           // LD_VX square planes, optional (gv.st null: none)
 };
 
 // One launch of the z-pencil kernel: forward z-FFT over the zero-padded
@@ -57,6 +69,9 @@ __host__ __device__ inline int pencil_part_words(int pz, int bx, int nthr, int e
 
 template <class T, bool INV, int LD, int ST>
 void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t lds, hipStream_t s);
+// whether launch_tile runs the square-plane kernel for these arguments (the
+// kernel that can carry a GivensTask)
+bool tile_is_plane(const TileArgs& a, size_t esz);
 template <class T>
 void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStream_t s);
 

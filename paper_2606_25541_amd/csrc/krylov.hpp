@@ -70,9 +70,15 @@ void krylov_dots(const T* V, long long ldv, long long bsv, long long n, GState* 
 // Givens step (rotated Hessenberg column, residual estimate, inv_norm,
 // stop/run). Severe cancellation (wn2 < cancel_thr * wn2_in) ends the cycle at
 // this column: the restart's fresh residual replaces a second pass.
+// givens == false leaves the Givens step to a later launch (krylov_givens, or
+// the first apply kernel of the next step, which reads the same norm partials).
 template <class T>
 void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run,
-                   const double2* dpart, double2* part, int nbatch, hipStream_t s, int jh = -1);
+                   const double2* dpart, double2* part, int nbatch, hipStream_t s, int jh = -1,
+                   bool givens = true);
+// the Givens step of the newest column from the norm partials of krylov_update
+// (RED_BLOCKS per instance in part): one block per instance
+void krylov_givens(GState* st, int* run, const double2* part, int nbatch, hipStream_t s);
 // y = H^{-1} g over the k = j + 1 completed columns, and the coefficients of the
 // cycle's GMRES residual in the basis, cres = Q^H (g_k e_k) (Q: the Givens
 // rotations); both are stored times the slot scales sc[i], as coefficients of
