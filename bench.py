@@ -41,8 +41,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 SECTIONS = ("solve", "fp64", "apply", "batched", "serving", "adjoint", "cpu")
-# sources that decide the code of the apply kernels (hashed into the counter summary)
-KERNEL_SOURCES = ("common.hpp", "layout.hpp", "kernels.hpp", "fft_lds.hpp", "k_apply.hip")
+# sources that decide the code of the measured kernels (hashed into the counter summary)
+KERNEL_SOURCES = ("common.hpp", "layout.hpp", "kernels.hpp", "fft_lds.hpp", "k_apply.hip", "krylov.hpp",
+                  "givens.hpp", "k_krylov.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "apply_G3_fp32_hbm_traffic.md")
 
 
@@ -58,8 +59,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(stage: int):
-    """HBM bytes per launch of an apply stage from the committed counter summary.
+def stored_traffic(key: str):
+    """HBM bytes per launch of a kernel (key: "stage 0|1|2", "projections", "update") from the
+    committed counter summary.
 
     None when the summary is missing or was taken on other kernel sources.
     """
@@ -70,7 +72,7 @@ def stored_traffic(stage: int):
     m = re.search(r"kernel source hash: `([0-9a-f]+)`", txt)
     if not m or m.group(1) != kernel_source_hash():
         return None
-    m = re.search(r"traffic stage %d: (\d+) bytes" % stage, txt)
+    m = re.search(r"traffic %s: (\d+) bytes" % re.escape(key), txt)
     return int(m.group(1)) if m else None
 
 
@@ -183,14 +185,44 @@ def sec_apply(ctx, args, out):
                      "apply_gbs": b_apply / t_apply / 1e9, "apply_frac_hbm": b_apply / t_apply / 1e9 / HBM_PEAK_GBS,
                      "stages": stages}
     out["apply"] = res
+    # Gram-Schmidt passes of one restart cycle (columns j = 0 .. m-1) on FP32 basis vectors:
+    # the projections read v_0..v_j and w, (j + 2) 3N complex64; the update also writes w, (j + 3) 3N
+    m = args.restart
+    x32 = x.to(torch.complex64)
+    gs = {}
+    for pname, pas, nvec in (("projections", 0, 2), ("update", 1, 3)):
+        us, byt = [], []
+        for j in range(m):
+            ms = C.c_float()
+            _lib.check(L.psfd_bench_gram_schmidt(plan._h, pas, j, C.c_void_p(x32.data_ptr()), _lib.PSFD_C64,
+                                                 max(5, reps // 4), C.byref(ms), C.c_void_p(stream.cuda_stream)),
+                       "psfd_bench_gram_schmidt")
+            us.append(1e3 * ms.value)
+            byt.append((j + nvec) * 3 * N * 8)
+        gs[pname] = {"us_per_column": us, "us_mean": sum(us) / m, "bytes_mean": sum(byt) / m,
+                     "gbs": sum(byt) / (sum(us) * 1e-6) / 1e9}
+    out["gram_schmidt_fp32"] = gs
+    # the dominant kernel of an Arnoldi step (largest time per step): the three apply stages and the
+    # two Gram-Schmidt passes (cycle averages)
     st32 = res["fp32"]["stages"]
-    dom = max(st32, key=lambda k: st32[k]["us"])
-    names = {0: "k_tile<float2,fwd,V*x> (transverse FFT forward)", 1: "k_pencil<float2> (z FFT, dyadic kernel)",
-             2: "k_tile<float2,inv,axpby> (transverse FFT inverse)"}
-    out["roofline"] = {"bound": "hbm", "kernel": names[dom], "achieved": st32[dom]["gbs"], "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": st32[dom]["gbs"] / HBM_PEAK_GBS, "traffic": stored_traffic(dom),
-                       "bytes_per_launch": st32[dom]["bytes"], "us_per_launch": st32[dom]["us"],
-                       "kernel_source_hash": kernel_source_hash()}
+    cand = {
+        "stage 0": ("k_plane<float2,fwd,V*x> (transverse FFT forward, 128x128 planes)", st32[0]["us"],
+                    st32[0]["bytes"]),
+        "stage 1": ("k_pencil<float2,7,16> (z FFT, dyadic kernel, stack response)", st32[1]["us"], st32[1]["bytes"]),
+        "stage 2": ("k_plane<float2,inv,axpby> (transverse FFT inverse)", st32[2]["us"], st32[2]["bytes"]),
+        "projections": ("k_dots<float2> (Gram-Schmidt projections, mean over j = 0..m-1)",
+                        gs["projections"]["us_mean"], gs["projections"]["bytes_mean"]),
+        "update": ("k_update<float2> (Gram-Schmidt update, mean over j = 0..m-1)", gs["update"]["us_mean"],
+                   gs["update"]["bytes_mean"]),
+    }
+    dom = max(cand, key=lambda k: cand[k][1])
+    name, us_d, bytes_d = cand[dom]
+    gbs = bytes_d / (us_d * 1e-6) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": name, "achieved": gbs, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": stored_traffic(dom),
+                       "bytes_per_launch": bytes_d, "us_per_launch": us_d,
+                       "kernel_source_hash": kernel_source_hash(),
+                       "per_step_us": {k: round(v[1], 2) for k, v in cand.items()}}
     if args.only == "apply":
         # plain copy of known size: the scale of the FETCH_SIZE / WRITE_SIZE counters
         a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)

@@ -176,6 +176,17 @@ int psfd_server_destroy(psfd_server* srv);
 int psfd_bench_stage(psfd_plan* plan, int stage, const void* d_deps, const void* d_x, void* d_y, int dtype,
                      int reps, float* ms, void* stream);
 
+/* Diagnostics: time one classical Gram-Schmidt pass of the Arnoldi step at
+ * column j (0 <= j < 32), on the plan's grid: pass 0 the projections <v_i, w>
+ * (i <= j) and ||w||^2 of GMRES (Saad & Schultz; Sec. 3), pass 1 the update
+ * w -= sum_i h_i v_i with the ||w||^2 partials. A basis of j + 2 vectors of
+ * `dtype`, each a copy of d_x (complex64 or complex128 [3][nz][ny][nx], device),
+ * is allocated for the call and freed after it; the pass runs `reps` times back
+ * to back between two HIP events on `stream`, and *ms receives the mean time per
+ * launch. Blocks until done. For throughput measurements only. */
+int psfd_bench_gram_schmidt(psfd_plan* plan, int pass, int j, const void* d_x, int dtype, int reps, float* ms,
+                            void* stream);
+
 const char* psfd_status_string(int status);
 const char* psfd_last_error(void);
 const char* psfd_version(void);

@@ -74,6 +74,8 @@ EXPORTS = {
     "psfd_server_destroy": (C.c_int, [C.c_void_p]),
     "psfd_bench_stage": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
                                    C.POINTER(C.c_float), C.c_void_p]),
+    "psfd_bench_gram_schmidt": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int,
+                                          C.POINTER(C.c_float), C.c_void_p]),
     "psfd_status_string": (C.c_char_p, [C.c_int]),
     "psfd_last_error": (C.c_char_p, []),
     "psfd_version": (C.c_char_p, []),

@@ -166,6 +166,24 @@ int psfd_bench_stage(psfd_plan* plan, int stage, const void* d_deps, const void*
   return PSFD_OK;
 }
 
+int psfd_bench_gram_schmidt(psfd_plan* plan, int pass, int j, const void* d_x, int dtype, int reps, float* ms,
+                            void* stream) {
+  if (!plan || !d_x || !ms || reps < 1 || pass < 0 || pass > 1 || j < 0 || j >= MAXM)
+    return fail(PSFD_ERR_INVALID_ARG, "bad arguments");
+  if (dtype != PSFD_C64 && dtype != PSFD_C128) return fail(PSFD_ERR_INVALID_ARG, "bad dtype");
+  hipStream_t s = (hipStream_t)stream;
+  const int prec = dtype == PSFD_C64 ? PSFD_MIXED : PSFD_FP64;
+  Group g;
+  Status st = group_alloc(g, plan->sh, 1, j + 1, prec);
+  if (st.ok()) st = bench_gram_schmidt(g, pass, j, d_x, reps, ms, s);
+  if (st.ok()) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_status(e, "Gram-Schmidt timing");
+  }
+  if (!st.ok()) return fail(st);
+  return PSFD_OK;
+}
+
 static void fill_info(psfd_info* info, const SolveStats& s) {
   if (!info) return;
   info->iters = s.iters;

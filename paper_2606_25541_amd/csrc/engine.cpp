@@ -584,6 +584,46 @@ int true_residual_every() {
   return v < 1 ? 1 : v;
 }
 
+template <class T>
+static Status bench_gs_t(Group& g, int pass, int j, const T* x, int reps, float* ms, hipStream_t s) {
+  T* V = (T*)g.basis;
+  const long long n3 = g.sh.n3, bsv = (long long)(g.m + 1) * n3;
+  for (int i = 0; i <= j + 1; ++i)
+    HIPCHK(hipMemcpyAsync(V + (size_t)i * n3, x, sizeof(T) * n3, hipMemcpyDeviceToDevice, s));
+  GState hs;
+  std::memset(&hs, 0, sizeof(hs));
+  hs.j = j;
+  hs.m = g.m;
+  for (int i = 0; i <= MAXM; ++i) hs.sc[i] = 1.0;
+  const int one = 1;
+  HIPCHK(hipMemcpyAsync(g.st, &hs, sizeof(GState), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(g.run, &one, sizeof(int), hipMemcpyHostToDevice, s));
+  // the projections the update pass consumes
+  krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, 1, s, j);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) {
+    if (pass == 0) krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, 1, s, j);
+    else krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.part, 1, s, j, false);
+  }
+  HIPCHK(hipEventRecord(e1, s));
+  hipError_t e = hipEventSynchronize(e1);
+  float t = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_status(e, "Gram-Schmidt timing");
+  *ms = t / reps;
+  return Status();
+}
+
+Status bench_gram_schmidt(Group& g, int pass, int j, const void* x, int reps, float* ms, hipStream_t s) {
+  if (g.prec == PSFD_MIXED) return bench_gs_t<float2>(g, pass, j, (const float2*)x, reps, ms, s);
+  return bench_gs_t<double2>(g, pass, j, (const double2*)x, reps, ms, s);
+}
+
 // Arnoldi steps the server issues per host check of the run flags.
 const int STEPS_PER_SYNC = 4;
 

@@ -151,6 +151,12 @@ Status adjoint_group(Group& g, const Opts& o, const std::vector<std::pair<int, i
 
 Status hip_status(hipError_t e, const char* what);
 
+// Times one Gram-Schmidt pass of the Arnoldi step at column j on a group of one
+// instance (pass 0: projections, pass 1: update; reps launches between two
+// events on s): slots 0..j+1 of the basis are copied from x (n3 values of the
+// group's working precision), every slot scale is 1, the instance runs.
+Status bench_gram_schmidt(Group& g, int pass, int j, const void* x, int reps, float* ms, hipStream_t s);
+
 // ---- building blocks shared with the serving runtime (all masked per instance) ----
 // e = E_inc + IFFT_xy(E_up exp(i beta z)) on every plane (FP64)
 void inject(Group& g, const double2* eup, double2* out, const int* active, hipStream_t s);
