@@ -19,11 +19,14 @@ Printed JSON line: the solve rate, plus
                     Manhattan clips) in lock-step batched solves, against the
                     same instances solved one by one;
   serving           Poisson arrivals over {64x64x32, 128x128x64, 256x256x64}
-                    at 0.7 of the saturated rate: p50 / p99 latency, solves/s;
+                    at 0.7 of the saturated rate (--serve-qps: several
+                    rates): p50 / p99 latency, solves/s;
   adjoint           forward + adjoint gradient on a 256x256x64 smooth clip;
   cpu_baseline      the CPU oracle on a bounded sample of the headline solve.
 
---only SECTION runs one section (profiling); --quick runs the headline only.
+--only SECTION runs one section (profiling); --quick runs the headline only;
+--oracle-study times the CPU oracle on every workload (host only, no GPU) and
+prints its own JSON line.
 """
 from __future__ import annotations
 
@@ -142,6 +145,21 @@ def sec_fp64(ctx, args, out):
     ttm, (_, _, itm) = timed(lambda: plantm.psfd_solve(deps, em, orders), 1)
     out["tm_mixed"] = {"ms_per_solve": 1e3 * ttm, "iters": itm["iters"], "outer_iters": itm["outer_iters"],
                        "mono_residual": itm["mono_residual"]}
+    # workload 1: 64 nm line/space, 32x32x32, FP64 GMRES(30) to 1e-8
+    clips = ctx["clips"]
+    p1 = clips.config_problem("G1")
+    d1 = torch.from_numpy(clips.line_space(p1.nx, p1.ny, p1.nz, p1.lx_nm, p1.ly_nm, 16.0, 48.0)).to(ctx["dev"])
+    em1 = torch.empty((3, p1.nz, p1.ny, p1.nx), dtype=torch.complex128, device=ctx["dev"])
+    or1 = torch.empty((p1.ny, p1.nx, 3), dtype=torch.complex128, device=ctx["dev"])
+    plan1 = api.Plan(p1, rtol=1e-8, outer_rtol=1e-8, precision="fp64", restart=30, max_iters=20000)
+    plan1.psfd_solve(d1, em1, or1)
+    t1, (_, _, i1) = timed(lambda: plan1.psfd_solve(d1, em1, or1), 5)
+    x1 = torch.from_numpy(clips.random_complex((3, p1.nz, p1.ny, p1.nx), 1)).to(ctx["dev"])
+    y1 = torch.empty_like(x1)
+    plan1.psfd_apply(d1, x1, y1)
+    ta1, _ = timed(lambda: plan1.psfd_apply(d1, x1, y1), 200)
+    out["line_space_G1_fp64"] = {"ms_per_solve": 1e3 * t1, "iters": i1["iters"], "us_per_apply": 1e6 * ta1}
+    log("bench: line/space 32x32x32", out["line_space_G1_fp64"])
 
 
 def sec_apply(ctx, args, out):
@@ -185,12 +203,18 @@ def sec_apply(ctx, args, out):
                      "apply_gbs": b_apply / t_apply / 1e9, "apply_frac_hbm": b_apply / t_apply / 1e9 / HBM_PEAK_GBS,
                      "stages": stages}
     out["apply"] = res
-    # Gram-Schmidt passes of one restart cycle (columns j = 0 .. m-1) on FP32 basis vectors:
-    # the projections read v_0..v_j and w, (j + 2) 3N complex64; the update also writes w, (j + 3) 3N
+    # kernels of the Arnoldi steps of one restart cycle (columns j = 0 .. m-1) on FP32 basis vectors,
+    # through psfd_bench_gram_schmidt: the projections read v_0..v_j and w, (j + 2) 3N complex64; the
+    # update also writes w, (j + 3) 3N; the step's inverse transverse kernel reads the workspace and
+    # writes w, 2 3N, and where it also forms the projections (FP32 128 x 128 planes) reads v_0..v_j
+    # as well, (j + 3) 3N, and no separate projection pass runs
     m = args.restart
+    fused = (prob.nx == prob.ny == 128 and 3 * prob.nz <= 256
+             and os.environ.get("PSFD_FUSE_DOTS", "1") != "0")
     x32 = x.to(torch.complex64)
     gs = {}
-    for pname, pas, nvec in (("projections", 0, 2), ("update", 1, 3)):
+    for pname, pas, nvec in (("projections", 0, lambda j: j + 2), ("update", 1, lambda j: j + 3),
+                             ("stage 2 step", 2, lambda j: j + 3 if fused else 2)):
         us, byt = [], []
         for j in range(m):
             ms = C.c_float()
@@ -198,23 +222,30 @@ def sec_apply(ctx, args, out):
                                                  max(5, reps // 4), C.byref(ms), C.c_void_p(stream.cuda_stream)),
                        "psfd_bench_gram_schmidt")
             us.append(1e3 * ms.value)
-            byt.append((j + nvec) * 3 * N * 8)
+            byt.append(nvec(j) * 3 * N * 8)
         gs[pname] = {"us_per_column": us, "us_mean": sum(us) / m, "bytes_mean": sum(byt) / m,
                      "gbs": sum(byt) / (sum(us) * 1e-6) / 1e9}
+    gs["projections_in_stage_2"] = fused
     out["gram_schmidt_fp32"] = gs
-    # the dominant kernel of an Arnoldi step (largest time per step): the three apply stages and the
-    # two Gram-Schmidt passes (cycle averages)
+    # the dominant kernel of an Arnoldi step (largest time per step): the forward and pencil apply
+    # stages, the step's inverse stage and the Gram-Schmidt passes (cycle averages)
     st32 = res["fp32"]["stages"]
     cand = {
         "stage 0": ("k_plane<float2,fwd,V*x> (transverse FFT forward, 128x128 planes)", st32[0]["us"],
                     st32[0]["bytes"]),
         "stage 1": ("k_pencil<float2,7,16> (z FFT, dyadic kernel, stack response)", st32[1]["us"], st32[1]["bytes"]),
-        "stage 2": ("k_plane<float2,inv,axpby> (transverse FFT inverse)", st32[2]["us"], st32[2]["bytes"]),
-        "projections": ("k_dots<float2> (Gram-Schmidt projections, mean over j = 0..m-1)",
-                        gs["projections"]["us_mean"], gs["projections"]["bytes_mean"]),
         "update": ("k_update<float2> (Gram-Schmidt update, mean over j = 0..m-1)", gs["update"]["us_mean"],
                    gs["update"]["bytes_mean"]),
     }
+    if fused:
+        cand["stage 2 + projections"] = (
+            "k_plane<float2,inv,dots> (transverse FFT inverse + Gram-Schmidt projections, mean over j = 0..m-1)",
+            gs["stage 2 step"]["us_mean"], gs["stage 2 step"]["bytes_mean"])
+    else:
+        cand["stage 2"] = ("k_plane<float2,inv> (transverse FFT inverse)", gs["stage 2 step"]["us_mean"],
+                           gs["stage 2 step"]["bytes_mean"])
+        cand["projections"] = ("k_dots<float2> (Gram-Schmidt projections, mean over j = 0..m-1)",
+                               gs["projections"]["us_mean"], gs["projections"]["bytes_mean"])
     dom = max(cand, key=lambda k: cand[k][1])
     name, us_d, bytes_d = cand[dom]
     gbs = bytes_d / (us_d * 1e-6) / 1e9
@@ -284,17 +315,27 @@ def sec_batched(ctx, args, out):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     del plans
+    # the first four instances alone (the sample the CPU oracle is timed on)
+    sample_ms = []
+    for g, p, d in items[:4]:
+        pl = api.Plan(p, **opts)
+        dd = torch.from_numpy(d).to(dev)
+        pl.psfd_solve(dd)
+        t, r = timed(lambda: pl.psfd_solve(dd), 1)
+        sample_ms.append({"grid": g, "ms": 1e3 * t, "iters": r[2]["iters"]})
+        del pl
     out["batched"] = {"instances": len(items), "per_grid": {g: len(v) for g, v in groups.items()},
                       "solves_per_s": len(items) / t_batch, "sequential_solves_per_s": len(items) / t_seq,
                       "first_call_solves_per_s": len(items) / t_first,
                       "speedup_vs_sequential": t_seq / t_batch,
                       "iters_mean": {g: float(np.mean(v)) for g, v in iters.items()},
-                      "iters_max": {g: int(np.max(v)) for g, v in iters.items()}}
+                      "iters_max": {g: int(np.max(v)) for g, v in iters.items()},
+                      "first4_alone_ms": sample_ms}
     log("bench: batched", out["batched"])
 
 
 def sec_serving(ctx, args, out):
-    """Poisson arrivals over three grids at 0.7 of the saturated rate; p50/p99 latency."""
+    """Poisson arrivals over three grids at fractions of the saturated rate; p50/p99 latency."""
     import numpy as np
     api, torch, clips, dev = ctx["api"], ctx["torch"], ctx["clips"], ctx["dev"]
     grids = ("G2", "G3", "G4")
@@ -334,31 +375,69 @@ def sec_serving(ctx, args, out):
     t_sat = max(v[1] for v in lat.values()) - t0
     sat = len(ts) / t_sat
     log("bench: serving saturated %.2f solves/s" % sat)
-    # Poisson stream at 0.7 S
-    qps = 0.7 * sat
-    reqs = [pool[int(rng.integers(len(pool)))] for _ in range(args.serve_requests)]
-    gaps = rng.exponential(1.0 / qps, size=len(reqs))
-    bufs = [outputs(p) for _, p, _ in reqs]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    t_next = t0
-    tickets, kinds = [], []
-    for (g, p, d), b, gap in zip(reqs, bufs, gaps):
-        t_next += gap
-        while time.perf_counter() < t_next:
-            time.sleep(0.0002)
-        tickets.append(srv.submit(p, d, *b))
-        kinds.append(g)
-    lat = drain(tickets, time.perf_counter() + 600)
-    t_end = max(v[1] for v in lat.values())
+    def stream(frac, nreq, seed):
+        """Poisson arrivals at frac * S: latency percentiles and the completed rate.
+
+        Output buffers are recycled once their request has completed, so a
+        long stream holds only the outputs of the requests in flight.
+        """
+        r = np.random.default_rng(seed)
+        qps = frac * sat
+        reqs = [pool[int(r.integers(len(pool)))] for _ in range(nreq)]
+        gaps = r.exponential(1.0 / qps, size=len(reqs))
+        free = {g: [] for g in grids}
+        for g, p, _ in pool[:3]:
+            free[g] = [outputs(p) for _ in range(8)]
+        flight, lat = {}, {}
+
+        def collect():
+            for t in list(flight):
+                done, info, l = srv.poll(t)
+                if done:
+                    assert info["status"] == 0, info
+                    g, b = flight.pop(t)
+                    free[g].append(b)
+                    lat[t] = (l, time.perf_counter())
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_next = t0
+        tickets, kinds = [], []
+        for i, ((g, p, d), gap) in enumerate(zip(reqs, gaps)):
+            t_next += gap
+            while time.perf_counter() < t_next:
+                collect()
+                time.sleep(0.0002)
+            b = free[g].pop() if free[g] else outputs(p)
+            t = srv.submit(p, d, *b)
+            flight[t] = (g, b)
+            tickets.append(t)
+            kinds.append(g)
+            if (i + 1) % 200 == 0:
+                log("bench: serving %.1f S, %d submitted, %d in flight" % (frac, i + 1, len(flight)))
+        deadline = time.perf_counter() + 600
+        while flight and time.perf_counter() < deadline:
+            collect()
+            time.sleep(0.0005)
+        assert not flight, "requests still running after the drain limit"
+        t_end = max(v[1] for v in lat.values())
+        ls = np.array([lat[t][0] for t in tickets])
+        per = {g: np.array([lat[t][0] for t, k in zip(tickets, kinds) if k == g]) for g in grids}
+        res = {"qps_frac": frac, "qps": qps, "requests": len(tickets),
+               "solves_per_s": len(tickets) / (t_end - t0),
+               "p50_ms": 1e3 * float(np.percentile(ls, 50)), "p99_ms": 1e3 * float(np.percentile(ls, 99)),
+               "per_grid_p50_ms": {g: 1e3 * float(np.percentile(v, 50)) for g, v in per.items() if len(v)},
+               "per_grid_p99_ms": {g: 1e3 * float(np.percentile(v, 99)) for g, v in per.items() if len(v)}}
+        log("bench: serving stream", res)
+        return res
+
+    fracs = [float(f) for f in args.serve_qps.split(",")]
+    runs = [stream(f, args.serve_requests, 4100 + i) for i, f in enumerate(fracs)]
     srv.close()
-    ls = np.array([lat[t][0] for t in tickets])
-    per = {g: np.array([lat[t][0] for t, k in zip(tickets, kinds) if k == g]) for g in grids}
-    out["serving"] = {"requests": len(tickets), "saturated_solves_per_s": sat, "qps": qps,
-                      "solves_per_s": len(tickets) / (t_end - t0),
-                      "p50_ms": 1e3 * float(np.percentile(ls, 50)), "p99_ms": 1e3 * float(np.percentile(ls, 99)),
-                      "per_grid_p50_ms": {g: 1e3 * float(np.percentile(v, 50)) for g, v in per.items() if len(v)},
-                      "per_grid_p99_ms": {g: 1e3 * float(np.percentile(v, 99)) for g, v in per.items() if len(v)}}
+    main = min(runs, key=lambda x: abs(x["qps_frac"] - 0.7))
+    out["serving"] = {"saturated_solves_per_s": sat, **main}
+    if len(runs) > 1:
+        out["serving"]["sweep"] = runs
     # the plain FP64 GPU solve of one request per grid, for comparison
     fp64 = {}
     for g, p, d in pool[:3]:
@@ -368,6 +447,15 @@ def sec_serving(ctx, args, out):
         fp64[g] = 1e3 * t
         del pl
     out["serving"]["fp64_single_solve_ms"] = fp64
+    # the first four requests of the pool alone, mixed (the sample the CPU oracle is timed on)
+    alone = []
+    for g, p, d in pool[:4]:
+        pl = api.Plan(p, **opts)
+        pl.psfd_solve(d)
+        t, r = timed(lambda: pl.psfd_solve(d), 1)
+        alone.append({"grid": g, "ms": 1e3 * t, "iters": r[2]["iters"]})
+        del pl
+    out["serving"]["first4_alone_ms"] = alone
     log("bench: serving", out["serving"])
 
 
@@ -412,6 +500,81 @@ def sec_cpu(ctx, args, out):
                            "s_per_iteration": t_it}
 
 
+def oracle_study(args):
+    """The CPU oracle timed on the workloads' own inputs (host only; no GPU is touched).
+
+    Workload 1 (64 nm line/space, 32x32x32, FP64 GMRES(30) to 1e-8) and the
+    headline contact-hole clip (128x128x64, GMRES(m) to 1e-6): operator apply
+    and full solve with scipy.fft on all host threads and on one. Workloads 3
+    and 4: full solves of the first four instances of the batched set and of
+    the serving pool (the instances the GPU times alone). Workload 5: forward
+    + adjoint gradient of the 256x256x64 smooth clip once. The oracle is the
+    plain FP64 one, with its outer reflection loop, untuned.
+    """
+    import numpy as np
+    import oracle as O
+    from paper_2606_25541_amd import clips
+    ncores = os.cpu_count() or 1
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    res = {"kind": "oracle", "host_threads": ncores, "cpu_model": model, "items": []}
+
+    def solve(name, p, d, rtol, restart, workers):
+        O.set_workers(workers)
+        t0 = time.perf_counter()
+        r = O.solve(p, d, rtol=rtol, restart=restart, max_iters=20000)
+        t = time.perf_counter() - t0
+        it = {"item": name, "what": "solve", "workers": workers, "s": t, "iters": r["iters"],
+              "outer_iters": r["outer_iters"], "mono_residual": r["mono_residual"]}
+        res["items"].append(it)
+        log("oracle study:", it)
+
+    def apply(name, p, d, workers, reps):
+        O.set_workers(workers)
+        S = O.Setup(p)
+        x = clips.random_complex((3, p.nz, p.ny, p.nx), 1)
+        O.apply_A(S, d, x)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            O.apply_A(S, d, x)
+        it = {"item": name, "what": "apply", "workers": workers, "s": (time.perf_counter() - t0) / reps}
+        res["items"].append(it)
+        log("oracle study:", it)
+
+    p1 = clips.config_problem("G1")
+    d1 = clips.line_space(p1.nx, p1.ny, p1.nz, p1.lx_nm, p1.ly_nm, 16.0, 48.0)
+    p2 = clips.config_problem("G3", pol=clips.TE)
+    d2 = clips.contact_holes(128, 128, 64, 256.0, 256.0, 8, seed=2001)
+    for w in (ncores, 1):
+        apply("line/space 32x32x32", p1, d1, w, 20)
+        solve("line/space 32x32x32", p1, d1, 1e-8, 30, w)
+        apply("contact holes 128x128x64", p2, d2, w, 3)
+        solve("contact holes 128x128x64", p2, d2, 1e-6, args.restart, w)
+    rng = np.random.default_rng(3000)
+    batched = _manhattan_set(clips, ["G2", "G3"] * 32, 3000, clips.pupil_angles(), rng)
+    for i, (g, p, d) in enumerate(batched[:4]):
+        solve("batched instance %d (%s)" % (i, g), p, d, 1e-6, args.restart, ncores)
+    pool = _manhattan_set(clips, ["G2", "G3", "G4"] * 4, 4000, clips.pupil_angles(), None)
+    for i, (g, p, d) in enumerate(pool[:4]):
+        solve("serving request %d (%s)" % (i, g), p, d, 1e-6, args.restart, ncores)
+    p5 = clips.config_problem("G4")
+    d5, _ = clips.smooth_density_eps(p5.nx, p5.ny, p5.nz, p5.lx_nm, p5.ly_nm, p5.t_nm, seed=5001)
+    O.set_workers(ncores)
+    t0 = time.perf_counter()
+    r = O.adjoint_gradient(p5, d5, [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)], rtol=1e-6, restart=args.restart)
+    it = {"item": "smooth clip 256x256x64", "what": "forward + adjoint", "workers": ncores,
+          "s": time.perf_counter() - t0, "iters": r["fwd"]["iters"] + r["iters"]}
+    res["items"].append(it)
+    log("oracle study:", it)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -423,7 +586,14 @@ def main():
     ap.add_argument("--only", choices=SECTIONS, default=None, help="run one section")
     ap.add_argument("--serve-requests", type=int, default=90)
     ap.add_argument("--serve-burst", type=int, default=24)
+    ap.add_argument("--serve-qps", default="0.7",
+                    help="comma-separated arrival rates as fractions of the saturated rate")
+    ap.add_argument("--oracle-study", action="store_true",
+                    help="time the CPU oracle on the workloads (host only) and exit")
     args = ap.parse_args()
+    if args.oracle_study:
+        oracle_study(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (no multi-GPU path)"}))
         sys.exit(2)

@@ -179,7 +179,10 @@ int psfd_bench_stage(psfd_plan* plan, int stage, const void* d_deps, const void*
 /* Diagnostics: time one classical Gram-Schmidt pass of the Arnoldi step at
  * column j (0 <= j < 32), on the plan's grid: pass 0 the projections <v_i, w>
  * (i <= j) and ||w||^2 of GMRES (Saad & Schultz; Sec. 3), pass 1 the update
- * w -= sum_i h_i v_i with the ||w||^2 partials. A basis of j + 2 vectors of
+ * w -= sum_i h_i v_i with the ||w||^2 partials, pass 2 the step's inverse
+ * transverse FFT kernel that writes w (stage 2 of the operator apply, eq. (18)),
+ * which on FP32 128 x 128 planes also forms the projections of pass 0 (then
+ * no separate pass 0 runs in a step). A basis of j + 2 vectors of
  * `dtype`, each a copy of d_x (complex64 or complex128 [3][nz][ny][nx], device),
  * is allocated for the call and freed after it; the pass runs `reps` times back
  * to back between two HIP events on `stream`, and *ms receives the mean time per

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 namespace psfd {
 
@@ -584,6 +585,38 @@ int true_residual_every() {
   return v < 1 ? 1 : v;
 }
 
+// Whether the inverse transverse kernel of an Arnoldi step also forms the
+// Gram-Schmidt projections of the vector it writes (FP32 128 x 128 square planes;
+// PSFD_FUSE_DOTS=0 keeps the separate projection pass, read per call).
+static bool fuse_dots(const Group& g, size_t esz) {
+  const char* e = std::getenv("PSFD_FUSE_DOTS");
+  if (e && std::atoi(e) == 0) return false;
+  const XYCfg c = xy_config(g.sh, esz);
+  return c.fused && tile_takes_dots(tile_base(g, nullptr, c.full), esz);
+}
+
+// The inverse transverse stage of an Arnoldi step: the slot vout (j + 1) =
+// IFFT_xy of the workspace. Returns true when the kernel also stored the
+// projection partials of the new vector (fuse_dots), false when the separate
+// projection pass must follow.
+template <class T>
+static bool arnoldi_inverse(Group& g, VecRef vout, int jh, hipStream_t s) {
+  T* ws = (T*)g.wsP;
+  if constexpr (std::is_same<T, float2>::value) {
+    if (fuse_dots(g, sizeof(T))) {
+      const long long n3 = g.sh.n3, bsv = (long long)(g.m + 1) * n3;
+      const XYCfg c = xy_config(g.sh, sizeof(T));
+      TileArgs a = tile_base(g, twiddles<T>(g), c.full);
+      a.in = vr(ws, n3); a.out = vout; a.active = g.run;
+      a.dt = DotTask{g.basis, n3, bsv, g.st, g.dpart2, jh};
+      launch_tile<T, true, LD_PLAIN, ST_DOTS>(a, 3 * g.sh.nz, g.B, c.full.nthr, c.full.lds, s);
+      return true;
+    }
+  }
+  apply_stage<T>(g, 2, (const T*)nullptr, vout, vout, ws, 1, 0, 0, g.run, s);
+  return false;
+}
+
 template <class T>
 static Status bench_gs_t(Group& g, int pass, int j, const T* x, int reps, float* ms, hipStream_t s) {
   T* V = (T*)g.basis;
@@ -600,13 +633,19 @@ static Status bench_gs_t(Group& g, int pass, int j, const T* x, int reps, float*
   HIPCHK(hipMemcpyAsync(g.run, &one, sizeof(int), hipMemcpyHostToDevice, s));
   // the projections the update pass consumes
   krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, 1, s, j);
+  // pass 2: the inverse transverse stage of the step, from a workspace holding x
+  VecRef vout;
+  std::memset(&vout, 0, sizeof(vout));
+  vout.base = V; vout.bstride = bsv; vout.jstride = n3; vout.joff = j + 1;
+  if (pass == 2) HIPCHK(hipMemcpyAsync(g.wsP, x, sizeof(T) * n3, hipMemcpyDeviceToDevice, s));
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, s));
   for (int r = 0; r < reps; ++r) {
     if (pass == 0) krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, 1, s, j);
-    else krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.part, 1, s, j, false);
+    else if (pass == 1) krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.part, 1, s, j, false);
+    else arnoldi_inverse<T>(g, vout, j, s);
   }
   HIPCHK(hipEventRecord(e1, s));
   hipError_t e = hipEventSynchronize(e1);
@@ -647,12 +686,17 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
   // B v_j; slots keep the unnormalised vectors (v_i = sc[i] slot_i): the first
   // apply kernel scales slot j by inv_norm = sc[j] on load. In lock-step solves
   // the Givens step of step j - 1 rides along with this apply (gt), and the
-  // last step of the cycle takes it at once.
+  // last step of the cycle takes it at once. The last apply kernel also forms
+  // the projections of the new vector where the shape allows (arnoldi_inverse);
+  // elsewhere the projection pass follows it.
   const bool lock = jh >= 0;
   const GivensTask gt{g.st, g.run, g.part};
-  apply_op<T>(g, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, &g.st[0].inv_norm,
-              (long long)(sizeof(GState) / sizeof(double)), lock && jh > 0 ? &gt : nullptr);
-  krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.B, s, jh);
+  const double* isc = &g.st[0].inv_norm;
+  const long long iss = (long long)(sizeof(GState) / sizeof(double));
+  apply_stage<T>(g, 0, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, isc, iss,
+                 lock && jh > 0 ? &gt : nullptr);
+  apply_stage<T>(g, 1, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s);
+  if (!arnoldi_inverse<T>(g, vout, jh, s)) krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.B, s, jh);
   krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.part, g.B, s, jh, !lock || jh == g.m - 1);
 }
 

@@ -178,6 +178,71 @@ __host__ __device__ constexpr size_t plane_lds(int ln, size_t esz) {
   return ((size_t)(1 << ln) * ((1 << ln) + 1) + (1 << ln)) * esz;
 }
 
+// Gram-Schmidt projections of one plane of the new Arnoldi vector w (its KT
+// values per thread in wv, element tid + k NT of the plane at poff): partial
+// <slot_i, w> for i = 0..j and ||w||^2, summed in the vector precision within a
+// wavefront and in FP64 across the wavefronts in a fixed order, stored as this
+// plane's partial of the projection pass; partial indices no plane owns get zeros.
+template <class T, int KT, int NT>
+PSFD_D void plane_dots(const TileArgs& a, const T (&wv)[KT], int b, int plane, long long poff) {
+  constexpr int NW = NT / 64, NBD = DotBlocks<float2>::value;
+  extern __shared__ double2 smem_d[];
+  double2* red = smem_d;  // [PSTR][NW]; the plane's LDS is free after the barrier
+  const DotTask& d = a.dt;
+  const int cnt = (d.jh >= 0 ? d.jh : d.st[b].j) + 1;
+  const T* vb = reinterpret_cast<const T*>(d.V) + (long long)b * d.bsv + poff;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  auto wsum = [](T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      v.x += __shfl_xor(v.x, off, 64);
+      v.y += __shfl_xor(v.y, off, 64);
+    }
+    return v;
+  };
+  __syncthreads();
+  // two slots per pass, their loads issued together (the second index clamped)
+  for (int i0 = 0; i0 < cnt; i0 += 2) {
+    const int i1 = min(i0 + 1, cnt - 1);
+    const T* s0 = vb + (long long)i0 * d.ldv;
+    const T* s1 = vb + (long long)i1 * d.ldv;
+    T p0[KT], p1[KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      p0[k] = s0[tid + k * NT];
+      p1[k] = s1[tid + k * NT];
+    }
+    T a0 = cmake<T>(0, 0), a1 = cmake<T>(0, 0);
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      a0.x += p0[k].x * wv[k].x + p0[k].y * wv[k].y;
+      a0.y += p0[k].x * wv[k].y - p0[k].y * wv[k].x;
+      a1.x += p1[k].x * wv[k].x + p1[k].y * wv[k].y;
+      a1.y += p1[k].x * wv[k].y - p1[k].y * wv[k].x;
+    }
+    a0 = wsum(a0);
+    a1 = wsum(a1);
+    if (lane == 0) {
+      red[i0 * NW + wave] = to_d(a0);
+      if (i0 + 1 < cnt) red[(i0 + 1) * NW + wave] = to_d(a1);
+    }
+  }
+  T nn = cmake<T>(0, 0);
+#pragma unroll
+  for (int k = 0; k < KT; ++k) nn.x += wv[k].x * wv[k].x + wv[k].y * wv[k].y;
+  nn = wsum(nn);
+  if (lane == 0) red[cnt * NW + wave] = to_d(nn);
+  __syncthreads();
+  if (tid <= cnt) {
+    double2 t = red[tid * NW];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) t = cadd(t, red[tid * NW + w]);
+    double2* pp = d.part + ((long long)b * PSTR + tid) * NBD;
+    pp[plane] = t;
+    for (int q = plane + 3 * a.nz; q < NBD; q += 3 * a.nz) pp[q] = make_double2(0, 0);
+  }
+}
+
 template <class T, bool INV, int LD, int ST, int LN>
 __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   constexpr int N = 1 << LN, P = N + 1, NT = plane_threads(LN);
@@ -254,7 +319,9 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
       v.y = al * xv.y + ga * v.y;
     }
     out[tid + k * NT] = v;
+    if (ST == ST_DOTS) va[k] = v;
   }
+  if constexpr (ST == ST_DOTS) plane_dots<T, KT, NT>(a, va, b, plane, poff);
 }
 
 // -------------------------------------------------------------------------
@@ -350,6 +417,9 @@ static int plane_ln(const TileArgs& a, size_t esz) {
   return 0;
 }
 bool tile_is_plane(const TileArgs& a, size_t esz) { return plane_ln(a, esz) != 0; }
+bool tile_takes_dots(const TileArgs& a, size_t esz) {
+  return esz == 8 && plane_ln(a, esz) == 7 && 3 * a.nz <= DotBlocks<float2>::value;
+}
 
 template <class T, bool INV, int LD, int ST>
 void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t lds, hipStream_t s) {
@@ -361,7 +431,12 @@ void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t ld
     if (LD == LD_VX && a.gv.st) g2.x += 1;  // the GivensTask block
     hipLaunchKernelGGL(kern, g2, dim3(plane_threads(ln)), l, s, a);
   };
-  if constexpr (LD == LD_PLAIN || LD == LD_VX) {
+  if constexpr (ST == ST_DOTS) {
+    // only the FP32 128 x 128 square planes store with the projections
+    if constexpr (sizeof(T) == 8)
+      if (tile_takes_dots(a, sizeof(T))) return plane(k_plane<T, INV, LD, ST, 7>, 7);
+    return;
+  } else if constexpr (LD == LD_PLAIN || LD == LD_VX) {
     const int ln = plane_ln(a, sizeof(T));
     if (ln == 6) return plane(k_plane<T, INV, LD, ST, 6>, 6);
     if constexpr (sizeof(T) == 8)
@@ -391,6 +466,7 @@ template void launch_tile<float2, false, LD_VX, ST_PLAIN>(const TileArgs&, int, 
 template void launch_tile<float2, false, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<float2, true, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<float2, true, LD_PLAIN, ST_AXPBY>(const TileArgs&, int, int, int, size_t, hipStream_t);
+template void launch_tile<float2, true, LD_PLAIN, ST_DOTS>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<double2, false, LD_VX, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<double2, false, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<double2, true, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);

@@ -16,7 +16,19 @@ struct GivensTask {
   int* run;
   const double2* part;
 }; 
-enum StoreOp { ST_PLAIN = 0, ST_AXPBY = 1 };
+// The Gram-Schmidt projections of the new Arnoldi vector, left to the kernel
+// that writes it (ST_DOTS, inverse square planes): each plane block also forms
+// the partial dot products <slot_i, w> (i = 0..j) and ||w||^2 over its plane
+// and stores them where the projection pass would (PSTR values per instance,
+// DotBlocks<float2> partials each: the plane's own, zeros in the others).
+struct DotTask {
+  const void* V;        // basis of instance 0; slot i of instance b at V + b bsv + i ldv
+  long long ldv, bsv;
+  const GState* st;     // j of each instance when jh < 0
+  double2* part;
+  int jh;               // >= 0: every running instance stands at step jh
+};
+enum StoreOp { ST_PLAIN = 0, ST_AXPBY = 1, ST_DOTS = 2 };
 
 // One launch of the transverse (x/y) FFT kernel over tiles of every plane of
 // every instance. A tile is ty rows x tx columns of one (component, z) plane.
@@ -38,6 +50,7 @@ struct TileArgs {
   const double* in_scale;  // LD_VX, optional: in scaled by in_scale[b * scale_stride] on load (in is not modified)
   long long scale_stride;
   GivensTask gv;           // LD_VX square planes, optional (gv.st null: none)
+  DotTask dt;              // ST_DOTS
 };
 
 // One launch of the z-pencil kernel: forward z-FFT over the zero-padded
@@ -72,6 +85,9 @@ void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t ld
 // whether launch_tile runs the square-plane kernel for these arguments (the
 // kernel that can carry a GivensTask)
 bool tile_is_plane(const TileArgs& a, size_t esz);
+// whether launch_tile can store with ST_DOTS for these arguments (FP32 128 x 128
+// planes, at most DotBlocks<float2> planes per instance)
+bool tile_takes_dots(const TileArgs& a, size_t esz);
 template <class T>
 void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStream_t s);
 

@@ -5,6 +5,8 @@ of the discrete system times the tolerance: FP64 field error <= 1e-8, orders
 <= 1e-9 absolute; mixed precision (FP32 Arnoldi, FP64 residual) converges to
 the same FP64 solution.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -58,6 +60,66 @@ def test_solve_matches_oracle(case, prec, coupling):
     assert np.max(np.abs(orders - ref["orders"])) < 1e-9
     assert info["mono_residual"] < 1e-8
     assert info["outer_iters"] >= (2 if coupling == "outer" else 1)
+
+
+_REF128 = {}
+
+
+def _ref_128():
+    """128 x 128 x 2 (64 nm clip, TE, azimuth 20 deg) and its oracle solve, computed once:
+    the oracle's outer reflection loop is slow on 128-point planes, so 6 planes
+    and a 64 nm period keep it to seconds (mono residual ~5e-11)."""
+    if not _REF128:
+        layers, es = clips.mo_si_stack(40)
+        p = clips.Problem(nx=128, ny=128, nz=2, lx_nm=64.0, ly_nm=64.0, t_nm=30.0, theta_deg=6.0,
+                          phi_deg=20.0, pol=0, layers=layers, eps_sub=es)
+        de = clips.manhattan(p.nx, p.ny, p.nz, p.lx_nm, p.ly_nm, seed=900)
+        _REF128.update(p=p, de=de, ref=O.solve(p, de, rtol=1e-11, max_outer=40))
+    return _REF128["p"], _REF128["de"], _REF128["ref"]
+
+
+@pytest.mark.parametrize("jh", ["lockstep", "server"])
+def test_solve_128_planes_projections_in_plane_kernel(jh, monkeypatch):
+    """128 x 128 planes, mixed: the inverse square-plane kernel also forms the
+    Gram-Schmidt projections (6 planes, so most partial slots are zero-filled).
+    The solve must match the oracle, and so must the separate projection pass
+    (PSFD_FUSE_DOTS=0), within one restart cycle of the same step count;
+    "server" runs it through the serving path (Krylov index read per slot)."""
+    from paper_2606_25541_amd import api
+    dev = device()
+    say("solve 128x128x2 mixed", jh)
+    p, de, ref = _ref_128()
+    d = torch.from_numpy(de).to(dev)
+
+    def run():
+        if jh == "lockstep":
+            plan = api.Plan(p, rtol=1e-10, precision="mixed", restart=8, coupling="mono")
+            return plan.psfd_solve(d)
+        srv = api.Server(hbm_budget=8 << 30, max_slots=2, rtol=1e-10, precision="mixed", restart=8)
+        em = torch.empty((3, p.nz, p.ny, p.nx), dtype=torch.complex128, device=dev)
+        od = torch.empty((p.ny, p.nx, 3), dtype=torch.complex128, device=dev)
+        t = srv.submit(p, d, em, od)
+        deadline = time.perf_counter() + 60
+        done = False
+        while not done and time.perf_counter() < deadline:
+            done, info, _ = srv.poll(t)
+            time.sleep(0.002)
+        srv.close()
+        assert done, "served request not finished within 60 s"
+        return em, od, info
+
+    em, orders, info = run()
+    say("  fused", info)
+    assert info["status"] == 0
+    assert rel(em.cpu().numpy(), ref["emask"]) < 1e-8
+    assert np.max(np.abs(orders.cpu().numpy() - ref["orders"])) < 1e-9
+    monkeypatch.setenv("PSFD_FUSE_DOTS", "0")
+    em2, orders2, info2 = run()
+    say("  separate pass", info2)
+    assert info2["status"] == 0
+    # the two paths differ only in the FP32 rounding order of the projections
+    assert abs(info2["iters"] - info["iters"]) <= 8
+    assert rel(em2.cpu().numpy(), ref["emask"]) < 1e-8
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
