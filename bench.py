@@ -208,13 +208,18 @@ def sec_apply(ctx, args, out):
     # update also writes w, (j + 3) 3N; the step's inverse transverse kernel reads the workspace and
     # writes w, 2 3N, and where it also forms the projections (FP32 128 x 128 planes) reads v_0..v_j
     # as well, (j + 3) 3N, and no separate projection pass runs
+    # The forward stage of step j + 1 (pass 3) reads the slot, the contrast and writes the workspace,
+    # 7N; where it also does the update of column j (FP32 128 x 128 planes, lock-step solves) it reads
+    # v_0..v_j too and writes the slot back, (j + 3) 3N + 7N
     m = args.restart
-    fused = (prob.nx == prob.ny == 128 and 3 * prob.nz <= 256
-             and os.environ.get("PSFD_FUSE_DOTS", "1") != "0")
+    sq128 = prob.nx == prob.ny == 128
+    fused = sq128 and 3 * prob.nz <= 256 and os.environ.get("PSFD_FUSE_DOTS", "1") != "0"
+    fused_upd = sq128 and os.environ.get("PSFD_FUSE_UPDATE", "1") != "0"
     x32 = x.to(torch.complex64)
     gs = {}
     for pname, pas, nvec in (("projections", 0, lambda j: j + 2), ("update", 1, lambda j: j + 3),
-                             ("stage 2 step", 2, lambda j: j + 3 if fused else 2)):
+                             ("stage 2 step", 2, lambda j: j + 3 if fused else 2),
+                             ("stage 0 step", 3, lambda j: (j + 3 if fused_upd else 0) + 7 / 3)):
         us, byt = [], []
         for j in range(m):
             ms = C.c_float()
@@ -226,17 +231,30 @@ def sec_apply(ctx, args, out):
         gs[pname] = {"us_per_column": us, "us_mean": sum(us) / m, "bytes_mean": sum(byt) / m,
                      "gbs": sum(byt) / (sum(us) * 1e-6) / 1e9}
     gs["projections_in_stage_2"] = fused
+    gs["update_in_stage_0"] = fused_upd
     out["gram_schmidt_fp32"] = gs
-    # the dominant kernel of an Arnoldi step (largest time per step): the forward and pencil apply
-    # stages, the step's inverse stage and the Gram-Schmidt passes (cycle averages)
+    # the dominant kernel of an Arnoldi step (largest mean time per step over a cycle): the forward
+    # stage (plain at step 0; with the previous column's update at steps 1..m-1 where fused), the
+    # pencil, the inverse stage (with the projections where fused) and the separate passes
     st32 = res["fp32"]["stages"]
-    cand = {
-        "stage 0": ("k_plane<float2,fwd,V*x> (transverse FFT forward, 128x128 planes)", st32[0]["us"],
-                    st32[0]["bytes"]),
-        "stage 1": ("k_pencil<float2,7,16> (z FFT, dyadic kernel, stack response)", st32[1]["us"], st32[1]["bytes"]),
-        "update": ("k_update<float2> (Gram-Schmidt update, mean over j = 0..m-1)", gs["update"]["us_mean"],
-                   gs["update"]["bytes_mean"]),
-    }
+    cand = {"stage 1": ("k_pencil<float2,7,16> (z FFT, dyadic kernel, stack response)", st32[1]["us"],
+                        st32[1]["bytes"])}
+    if fused_upd:
+        g0 = gs["stage 0 step"]
+        us0 = [st32[0]["us"]] + g0["us_per_column"][:m - 1]
+        by0 = [st32[0]["bytes"]] + [(j + 3) * 3 * N * 8 + 7 * N * 8 for j in range(m - 1)]
+        cand["stage 0 + update"] = (
+            "k_plane<float2,fwd,update+V*x> (Gram-Schmidt update of the previous column + transverse FFT "
+            "forward; plain at step 0; mean over the steps of a cycle)", sum(us0) / m, sum(by0) / m)
+        # the separate update runs only at the last column
+        cand["update (last column)"] = (
+            "k_update<float2> (Gram-Schmidt update of the last column, per step of a cycle)",
+            gs["update"]["us_per_column"][m - 1] / m, (m + 2) * 3 * N * 8 / m)
+    else:
+        cand["stage 0"] = ("k_plane<float2,fwd,V*x> (transverse FFT forward, 128x128 planes)", st32[0]["us"],
+                           st32[0]["bytes"])
+        cand["update"] = ("k_update<float2> (Gram-Schmidt update, mean over j = 0..m-1)", gs["update"]["us_mean"],
+                          gs["update"]["bytes_mean"])
     if fused:
         cand["stage 2 + projections"] = (
             "k_plane<float2,inv,dots> (transverse FFT inverse + Gram-Schmidt projections, mean over j = 0..m-1)",
@@ -503,13 +521,16 @@ def sec_cpu(ctx, args, out):
 def oracle_study(args):
     """The CPU oracle timed on the workloads' own inputs (host only; no GPU is touched).
 
-    Workload 1 (64 nm line/space, 32x32x32, FP64 GMRES(30) to 1e-8) and the
-    headline contact-hole clip (128x128x64, GMRES(m) to 1e-6): operator apply
-    and full solve with scipy.fft on all host threads and on one. Workloads 3
-    and 4: full solves of the first four instances of the batched set and of
-    the serving pool (the instances the GPU times alone). Workload 5: forward
-    + adjoint gradient of the 256x256x64 smooth clip once. The oracle is the
-    plain FP64 one, with its outer reflection loop, untuned.
+    Per item: the oracle's table set-up, one operator apply, and the time per
+    FP64 GMRES(m) iteration over a bounded sample of iterations (--oracle-iters),
+    with scipy.fft on all host threads and, for the first two workloads, on
+    one. A solve's time is then set-up + iterations x time per iteration, at
+    the iteration count of the GPU solve of the same instance (the oracle's own
+    outer reflection loop needs more; the 64 nm line/space clip is also solved
+    in full, which takes seconds). Items: 64 nm line/space 32x32x32; the
+    128x128x64 contact-hole clip; the first four instances of the batched set
+    and of the serving pool; the 256x256x64 smooth clip, forward and transposed
+    (adjoint) iterations. The oracle is the plain FP64 one, untuned.
     """
     import numpy as np
     import oracle as O
@@ -523,27 +544,33 @@ def oracle_study(args):
                 break
     except OSError:
         pass
-    res = {"kind": "oracle", "host_threads": ncores, "cpu_model": model, "items": []}
+    res = {"kind": "oracle", "host_threads": ncores, "cpu_model": model, "gmres_restart": args.restart,
+           "items": []}
+    k = args.oracle_iters
 
-    def solve(name, p, d, rtol, restart, workers):
+    def sample(name, p, d, workers, transpose=False, full_rtol=None):
         O.set_workers(workers)
         t0 = time.perf_counter()
-        r = O.solve(p, d, rtol=rtol, restart=restart, max_iters=20000)
-        t = time.perf_counter() - t0
-        it = {"item": name, "what": "solve", "workers": workers, "s": t, "iters": r["iters"],
-              "outer_iters": r["outer_iters"], "mono_residual": r["mono_residual"]}
-        res["items"].append(it)
-        log("oracle study:", it)
-
-    def apply(name, p, d, workers, reps):
-        O.set_workers(workers)
         S = O.Setup(p)
+        _ = S.G
+        t_setup = time.perf_counter() - t0
         x = clips.random_complex((3, p.nz, p.ny, p.nx), 1)
-        O.apply_A(S, d, x)
+        O.apply_A(S, d, x, transpose=transpose)
         t0 = time.perf_counter()
-        for _ in range(reps):
-            O.apply_A(S, d, x)
-        it = {"item": name, "what": "apply", "workers": workers, "s": (time.perf_counter() - t0) / reps}
+        O.apply_A(S, d, x, transpose=transpose)
+        t_apply = time.perf_counter() - t0
+        V = O.potential(S, d)
+        rhs = O.conv_K(S, V[None] * O.background_field(S))
+        t0 = time.perf_counter()
+        O.gmres(lambda v: O.apply_A(S, d, v, transpose=transpose), rhs, None, 1e-30, args.restart, k)
+        t_it = (time.perf_counter() - t0) / k
+        it = {"item": name, "workers": workers, "transpose": transpose, "s_setup": t_setup, "s_apply": t_apply,
+              "s_per_iteration": t_it, "sample_iterations": k}
+        if full_rtol is not None:
+            t0 = time.perf_counter()
+            r = O.solve(p, d, rtol=full_rtol, restart=30, max_iters=20000)
+            it.update({"s_full_solve": time.perf_counter() - t0, "full_iters": r["iters"],
+                       "full_outer_iters": r["outer_iters"], "full_mono_residual": float(r["mono_residual"])})
         res["items"].append(it)
         log("oracle study:", it)
 
@@ -552,26 +579,19 @@ def oracle_study(args):
     p2 = clips.config_problem("G3", pol=clips.TE)
     d2 = clips.contact_holes(128, 128, 64, 256.0, 256.0, 8, seed=2001)
     for w in (ncores, 1):
-        apply("line/space 32x32x32", p1, d1, w, 20)
-        solve("line/space 32x32x32", p1, d1, 1e-8, 30, w)
-        apply("contact holes 128x128x64", p2, d2, w, 3)
-        solve("contact holes 128x128x64", p2, d2, 1e-6, args.restart, w)
+        sample("line/space 32x32x32", p1, d1, w, full_rtol=1e-8)
+        sample("contact holes 128x128x64", p2, d2, w)
     rng = np.random.default_rng(3000)
     batched = _manhattan_set(clips, ["G2", "G3"] * 32, 3000, clips.pupil_angles(), rng)
     for i, (g, p, d) in enumerate(batched[:4]):
-        solve("batched instance %d (%s)" % (i, g), p, d, 1e-6, args.restart, ncores)
+        sample("batched instance %d (%s)" % (i, g), p, d, ncores)
     pool = _manhattan_set(clips, ["G2", "G3", "G4"] * 4, 4000, clips.pupil_angles(), None)
     for i, (g, p, d) in enumerate(pool[:4]):
-        solve("serving request %d (%s)" % (i, g), p, d, 1e-6, args.restart, ncores)
+        sample("serving request %d (%s)" % (i, g), p, d, ncores)
     p5 = clips.config_problem("G4")
     d5, _ = clips.smooth_density_eps(p5.nx, p5.ny, p5.nz, p5.lx_nm, p5.ly_nm, p5.t_nm, seed=5001)
-    O.set_workers(ncores)
-    t0 = time.perf_counter()
-    r = O.adjoint_gradient(p5, d5, [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)], rtol=1e-6, restart=args.restart)
-    it = {"item": "smooth clip 256x256x64", "what": "forward + adjoint", "workers": ncores,
-          "s": time.perf_counter() - t0, "iters": r["fwd"]["iters"] + r["iters"]}
-    res["items"].append(it)
-    log("oracle study:", it)
+    sample("smooth clip 256x256x64", p5, d5, ncores)
+    sample("smooth clip 256x256x64", p5, d5, ncores, transpose=True)
     print(json.dumps(res), flush=True)
 
 
@@ -590,6 +610,7 @@ def main():
                     help="comma-separated arrival rates as fractions of the saturated rate")
     ap.add_argument("--oracle-study", action="store_true",
                     help="time the CPU oracle on the workloads (host only) and exit")
+    ap.add_argument("--oracle-iters", type=int, default=20, help="GMRES iterations per oracle timing sample")
     args = ap.parse_args()
     if args.oracle_study:
         oracle_study(args)

@@ -168,7 +168,7 @@ int psfd_bench_stage(psfd_plan* plan, int stage, const void* d_deps, const void*
 
 int psfd_bench_gram_schmidt(psfd_plan* plan, int pass, int j, const void* d_x, int dtype, int reps, float* ms,
                             void* stream) {
-  if (!plan || !d_x || !ms || reps < 1 || pass < 0 || pass > 2 || j < 0 || j >= MAXM)
+  if (!plan || !d_x || !ms || reps < 1 || pass < 0 || pass > 3 || j < 0 || j >= MAXM)
     return fail(PSFD_ERR_INVALID_ARG, "bad arguments");
   if (dtype != PSFD_C64 && dtype != PSFD_C128) return fail(PSFD_ERR_INVALID_ARG, "bad dtype");
   hipStream_t s = (hipStream_t)stream;

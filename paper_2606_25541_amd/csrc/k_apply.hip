@@ -178,6 +178,88 @@ __host__ __device__ constexpr size_t plane_lds(int ln, size_t esz) {
   return ((size_t)(1 << ln) * ((1 << ln) + 1) + (1 << ln)) * esz;
 }
 
+// The Gram-Schmidt update of column j - 1 over one plane of slot j, in place:
+// wv (the plane's KT values per thread of slot j, element tid + k NT at poff)
+// becomes w - sum_{i<j} h_i s_i slot_i and is stored back to slot j (vb then
+// receives the plane's contrast values from vol), and the
+// plane's ||slot_j||^2 goes to part[b * planes + plane]. h_i = s_i <slot_i, w>
+// from the projection partials, each summed as the update kernel sums it (lane
+// l takes partials l, l + 64, ... in order, then the wavefront sum), so every
+// block gets the same coefficients bit for bit; the block of plane 0 stores h
+// and ||w||^2 before the update for the Givens step.
+template <class T, int KT, int NT>
+PSFD_D void plane_update(const TileArgs& a, T (&wv)[KT], T (&vb)[KT], const T* vol, T* slot, int b, int plane,
+                         long long poff) {
+  constexpr int NW = NT / 64, NBD = DotBlocks<float2>::value, PL = NBD / 64;
+  typedef typename real_of<T>::type R;
+  __shared__ double2 hsum[MAXM + 1];
+  __shared__ T hc[MAXM];
+  __shared__ double nred[NW];
+  const UpdateTask& u = a.up;
+  const int cnt = u.j;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  GState& S = u.st[b];
+  const T* sb = reinterpret_cast<const T*>(u.V) + (long long)b * u.bsv + poff;
+  // the slot scales and the projection partials are requested together (w is
+  // already on its way); then one slot per pass
+  const double scv = S.sc[min(tid, MAXM)];
+  const double2* pb = u.dpart + (long long)b * PSTR * NBD;
+  for (int i = wave; i <= cnt; i += NW) {
+    double2 pv[PL];
+#pragma unroll
+    for (int k = 0; k < PL; ++k) pv[k] = pb[(long long)i * NBD + lane + 64 * k];
+    double2 t = make_double2(0, 0);
+#pragma unroll
+    for (int k = 0; k < PL; ++k) t = cadd(t, pv[k]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      t.x += __shfl_xor(t.x, off, 64);
+      t.y += __shfl_xor(t.y, off, 64);
+    }
+    if (lane == 0) hsum[i] = t;
+  }
+  __syncthreads();
+  if (tid < cnt) {
+    hc[tid] = from_d<T>(cscale(hsum[tid], scv * scv));
+    if (plane == 0) S.h[tid] = cscale(hsum[tid], scv);
+  } else if (tid == cnt && plane == 0) {
+    S.wn2_in = hsum[cnt].x;
+  }
+  __syncthreads();
+  for (int i = 0; i < cnt; ++i) {
+    const T* si = sb + (long long)i * u.ldv;
+    T p[KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) p[k] = si[tid + k * NT];
+    const T h = hc[i];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      wv[k].x -= h.x * p[k].x - h.y * p[k].y;
+      wv[k].y -= h.x * p[k].y + h.y * p[k].x;
+    }
+  }
+  // the contrast values, loaded only now (fewer live registers in the loop
+  // above); their latency overlaps the stores and the norm reduction
+#pragma unroll
+  for (int k = 0; k < KT; ++k) vb[k] = vol[tid + k * NT];
+  R nn = 0;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    slot[tid + k * NT] = wv[k];
+    nn += wv[k].x * wv[k].x + wv[k].y * wv[k].y;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) nn += __shfl_xor(nn, off, 64);
+  if (lane == 0) nred[wave] = (double)nn;
+  __syncthreads();
+  if (tid == 0) {
+    double t = nred[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) t += nred[w];
+    u.part[(long long)b * (3 * a.nz) + plane] = make_double2(t, 0.0);
+  }
+}
+
 // Gram-Schmidt projections of one plane of the new Arnoldi vector w (its KT
 // values per thread in wv, element tid + k NT of the plane at poff): partial
 // <slot_i, w> for i = 0..j and ||w||^2, summed in the vector precision within a
@@ -252,9 +334,10 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   T* lds = reinterpret_cast<T*>(smem_d);
   T* twl = lds + N * P;
   const int b = blockIdx.y;
+  constexpr bool VX = LD == LD_VX || LD == LD_UPD_VX;  // contrast multiply on load
   // a GivensTask takes the extra last block of the grid
   if (LD == LD_VX && a.gv.st && blockIdx.x == gridDim.x - 1) {
-    givens_task(a.gv.st, a.gv.run, a.gv.part, RED_BLOCKS, b);
+    givens_task(a.gv.st, a.gv.run, a.gv.part, a.gv.nblk, b);
     return;
   }
   if (a.active && !a.active[b]) return;
@@ -263,7 +346,7 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   const long long poff = (long long)plane * N * N;
   const int tid = threadIdx.x;
   const T* in = vref<T>(a.in, b) + poff;
-  const T* vol = LD == LD_VX ? vref<T>(a.vol, b) + (long long)z * N * N : nullptr;
+  const T* vol = VX ? vref<T>(a.vol, b) + (long long)z * N * N : nullptr;
   const T* aux = ST == ST_AXPBY ? vref<T>(a.aux, b) + poff : nullptr;
   typedef typename real_of<T>::type R;
   const T* twg = reinterpret_cast<const T*>(a.tw) + N;
@@ -272,7 +355,7 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   // keep the twiddle load ahead of the data loads: its LDS write below then waits
   // for it alone
   __builtin_amdgcn_sched_barrier(0);
-  T va[KT], vb[LD == LD_VX ? KT : 1], xa[ST == ST_AXPBY ? KT : 1];
+  T va[KT], vb[VX ? KT : 1], xa[ST == ST_AXPBY ? KT : 1];
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     va[k] = in[tid + k * NT];
@@ -282,20 +365,23 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
 #pragma unroll
     for (int k = 0; k < KT; ++k) xa[k] = aux[tid + k * NT];
   }
+  // the Gram-Schmidt update of the previous column on slot j before its transform
+  if constexpr (LD == LD_UPD_VX) plane_update<T, KT, NT>(a, va, vb, vol, const_cast<T*>(in), b, plane, poff);
   const double* tab = a.tab + (long long)b * a.tab_stride;
   const R k0sq = (R)tab[TS_K0SQ];
   // scale of the input on load (the newest Arnoldi vector is kept unnormalised),
   // folded into the contrast factor: from in_scale, or with a GivensTask from
-  // the norm partials the task itself sums (bitwise the same value)
+  // the norm partials the task itself sums (bitwise the same value); LD_UPD_VX
+  // leaves the vector unscaled (the pencil kernel scales it)
   R scl = (R)1;
-  if (LD == LD_VX && a.gv.st) scl = (R)inv_norm_of(norm_from_partials(a.gv.part + (long long)b * RED_BLOCKS, RED_BLOCKS));
+  if (LD == LD_VX && a.gv.st) scl = (R)inv_norm_of(norm_from_partials(a.gv.part + (long long)b * a.gv.nblk, a.gv.nblk));
   else if (LD == LD_VX && a.in_scale) scl = (R)a.in_scale[(long long)b * a.scale_stride];
   const R ks = k0sq * scl;
   if (tid < N) twl[tid] = tw0;
   auto put = [&](int k) {
     const int i = tid + k * NT;
     const T x = va[k];
-    const T v = LD == LD_VX ? cscale(cmul(vb[LD == LD_VX ? k : 0], x), ks) : x;
+    const T v = VX ? cscale(cmul(vb[VX ? k : 0], x), ks) : x;
     lds[(i >> LN) * P + (i & (N - 1))] = v;
   };
   typedef FftCT<LN, N, P, 1, NT> Rows;
@@ -417,6 +503,7 @@ static int plane_ln(const TileArgs& a, size_t esz) {
   return 0;
 }
 bool tile_is_plane(const TileArgs& a, size_t esz) { return plane_ln(a, esz) != 0; }
+bool tile_takes_update(const TileArgs& a, size_t esz) { return esz == 8 && plane_ln(a, esz) == 7; }
 bool tile_takes_dots(const TileArgs& a, size_t esz) {
   return esz == 8 && plane_ln(a, esz) == 7 && 3 * a.nz <= DotBlocks<float2>::value;
 }
@@ -435,6 +522,11 @@ void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t ld
     // only the FP32 128 x 128 square planes store with the projections
     if constexpr (sizeof(T) == 8)
       if (tile_takes_dots(a, sizeof(T))) return plane(k_plane<T, INV, LD, ST, 7>, 7);
+    return;
+  } else if constexpr (LD == LD_UPD_VX) {
+    // only the FP32 128 x 128 square planes load with the update
+    if constexpr (sizeof(T) == 8)
+      if (tile_takes_update(a, sizeof(T))) return plane(k_plane<T, INV, LD, ST, 7>, 7);
     return;
   } else if constexpr (LD == LD_PLAIN || LD == LD_VX) {
     const int ln = plane_ln(a, sizeof(T));
@@ -467,6 +559,7 @@ template void launch_tile<float2, false, LD_PLAIN, ST_PLAIN>(const TileArgs&, in
 template void launch_tile<float2, true, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<float2, true, LD_PLAIN, ST_AXPBY>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<float2, true, LD_PLAIN, ST_DOTS>(const TileArgs&, int, int, int, size_t, hipStream_t);
+template void launch_tile<float2, false, LD_UPD_VX, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<double2, false, LD_VX, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<double2, false, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<double2, true, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
@@ -560,6 +653,11 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   T* lds = reinterpret_cast<T*>(smem_d);
   typedef typename real_of<T>::type R;
   const int b = blockIdx.y;
+  // a GivensTask takes the extra last block of the grid
+  if (a.gv.st && blockIdx.x == gridDim.x - 1) {
+    givens_task(a.gv.st, a.gv.run, a.gv.part, a.gv.nblk, b);
+    return;
+  }
   if (a.active && !a.active[b]) return;
   const int bx = LPZ ? BXC : a.bx, pz = LPZ ? (1 << LPZ) : a.pz, nz = pz / 2, nx = a.nx, ny = a.ny;
   const int ky = blockIdx.x / a.nblk_x;
@@ -595,6 +693,13 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
         const int c = rest % 3, z = rest / 3;
         buf[k] = w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl];
       }
+    }
+    // with a GivensTask the input is the new Arnoldi vector unscaled: its scale
+    // from the norm partials the task sums (bitwise the same value)
+    if (a.gv.st) {
+      const R scl = (R)inv_norm_of(norm_from_partials(a.gv.part + (long long)b * a.gv.nblk, a.gv.nblk));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) buf[k] = cscale(buf[k], scl);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -781,7 +886,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
 
 template <class T>
 void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStream_t s) {
-  dim3 grid(a.nblk_x * a.ny, nbatch);
+  dim3 grid(a.nblk_x * a.ny + (a.gv.st ? 1 : 0), nbatch);  // + the GivensTask block
   auto go = [&](auto kern) {
     allow_lds(reinterpret_cast<const void*>(kern), lds);
     hipLaunchKernelGGL(kern, grid, dim3(nthr), lds, s, a);

@@ -4,18 +4,34 @@
 
 namespace psfd {
 
-enum LoadOp { LD_PLAIN = 0, LD_VX = 1, LD_INJECT = 2, LD_VXE = 3, LD_INJECT_T = 4 };
+enum LoadOp { LD_PLAIN = 0, LD_VX = 1, LD_INJECT = 2, LD_VXE = 3, LD_INJECT_T = 4, LD_UPD_VX = 5 };
 
 struct GState;
-// The Givens step of the previous Arnoldi step, left to the first apply kernel
-// of this one: an extra block of the kernel runs it (see givens_task), and the
-// other blocks take the scale of their input vector from the same norm
-// partials (RED_BLOCKS per instance in part) instead of in_scale.
+// The Givens step of the previous Arnoldi step, left to an apply kernel of
+// this one: an extra block of the kernel runs it (see givens_task), and the
+// other blocks take the scale of the step's input vector from the same norm
+// partials (nblk per instance in part, instance stride nblk) instead of in_scale.
 struct GivensTask {
   GState* st;
   int* run;
   const double2* part;
-}; 
+  int nblk;
+};
+// The Gram-Schmidt update of column j - 1, left to the forward square-plane
+// kernel of step j (LD_UPD_VX, lock-step solves): every plane block sums the
+// projection partials of the step before (dpart, DotBlocks<float2> per value,
+// PSTR values per instance), forms slot_j -= sum_{i<j} h_i s_i slot_i over its
+// plane, stores it, and leaves the plane's ||slot_j||^2 in part[b * planes + plane];
+// the block of plane 0 stores h and ||w||^2 before the update for the Givens step.
+// The vector enters the transform unscaled: the next kernel applies its scale.
+struct UpdateTask {
+  const void* V;        // basis of instance 0; slot i of instance b at V + b bsv + i ldv
+  long long ldv, bsv;
+  GState* st;
+  const double2* dpart;
+  double2* part;
+  int j;
+};
 // The Gram-Schmidt projections of the new Arnoldi vector, left to the kernel
 // that writes it (ST_DOTS, inverse square planes): each plane block also forms
 // the partial dot products <slot_i, w> (i = 0..j) and ||w||^2 over its plane
@@ -51,6 +67,7 @@ struct TileArgs {
   long long scale_stride;
   GivensTask gv;           // LD_VX square planes, optional (gv.st null: none)
   DotTask dt;              // ST_DOTS
+  UpdateTask up;           // LD_UPD_VX
 };
 
 // One launch of the z-pencil kernel: forward z-FFT over the zero-padded
@@ -64,6 +81,8 @@ struct PencilArgs {
   int transpose;         // use the kernel at the negated wavevector (bilinear transpose)
   int reflect;           // add the layered-stack response R_vol T_R K_top (monolithic coupling)
   const int* active;
+  GivensTask gv;         // optional (gv.st null: none): the pending Givens step in one extra
+                         // block; the other blocks scale the input by the new vector's scale
 };
 
 struct TileShape { int tx, ty, do_x, do_y, nthr; size_t lds; int pitch; };
@@ -88,6 +107,8 @@ bool tile_is_plane(const TileArgs& a, size_t esz);
 // whether launch_tile can store with ST_DOTS for these arguments (FP32 128 x 128
 // planes, at most DotBlocks<float2> planes per instance)
 bool tile_takes_dots(const TileArgs& a, size_t esz);
+// whether launch_tile can load with LD_UPD_VX for these arguments (FP32 128 x 128 planes)
+bool tile_takes_update(const TileArgs& a, size_t esz);
 template <class T>
 void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStream_t s);
 
