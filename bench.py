@@ -246,10 +246,7 @@ def sec_apply(ctx, args, out):
         cand["stage 0 + update"] = (
             "k_plane<float2,fwd,update+V*x> (Gram-Schmidt update of the previous column + transverse FFT "
             "forward; plain at step 0; mean over the steps of a cycle)", sum(us0) / m, sum(by0) / m)
-        # the separate update runs only at the last column
-        cand["update (last column)"] = (
-            "k_update<float2> (Gram-Schmidt update of the last column, per step of a cycle)",
-            gs["update"]["us_per_column"][m - 1] / m, (m + 2) * 3 * N * 8 / m)
+        # the last column takes no update pass: its Givens step works from the projections
     else:
         cand["stage 0"] = ("k_plane<float2,fwd,V*x> (transverse FFT forward, 128x128 planes)", st32[0]["us"],
                            st32[0]["bytes"])

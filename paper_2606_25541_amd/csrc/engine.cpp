@@ -755,9 +755,11 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
     apply_stage<T>(g, 1, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s);
   }
   if (!arnoldi_inverse<T>(g, vout, jh, s)) krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.B, s, jh);
-  // with the fused update, only the last column of a cycle takes the update pass
-  if (!upd || jh == g.m - 1)
-    krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.part, g.B, s, jh, !lock || jh == g.m - 1);
+  // with the fused update, the last column of a cycle takes no update pass: its
+  // Givens step uses the projections alone, and slot m keeps w (the restart's
+  // residual coefficients fold the update in)
+  if (upd && jh == g.m - 1) krylov_givens_proj(g.st, g.run, g.dpart2, g.B, s, jh);
+  else if (!upd) krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.part, g.B, s, jh, !lock || jh == g.m - 1);
 }
 
 template void arnoldi_step<float2>(Group&, int, int, hipStream_t, int);

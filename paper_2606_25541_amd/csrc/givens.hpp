@@ -64,23 +64,28 @@ PSFD_D double inv_norm_of(double wn2) {
 // memory latency; the rotations of the earlier columns are staged in LDS, so
 // the single-thread recurrence reads no global memory. Every thread of the
 // block must call it (blockDim >= GIVENS_THREADS).
-PSFD_D void givens_task(GState* st, int* run, const double2* part, int nblk, int b) {
+// PROJ: the caller passes this thread's projection hp (h_t of the column), ||w||^2
+// before the update (wn2in_p) and after it (wn2_p) instead of the state and the
+// norm partials, and the column's slot j + 1 keeps w (raw_last = j + 1).
+template <bool PROJ>
+PSFD_D void givens_impl(GState* st, int* run, const double2* part, int nblk, int b, double2 hp, double wn2in_p,
+                        double wn2_p) {
   static_assert(GIVENS_THREADS > MAXM, "one thread per Hessenberg row");
   __shared__ double2 col[MAXM + 1], snl[MAXM], gj_s;
   __shared__ double csl[MAXM];
   const int tid = threadIdx.x;
   GState& S = st[b];
   const int runb = run[b], j = S.j;
-  const double2 hv = S.h[min(tid, MAXM)], gv = S.g[min(tid, MAXM)], snv = S.sn[min(tid, MAXM - 1)];
+  const double2 hv = PROJ ? hp : S.h[min(tid, MAXM)], gv = S.g[min(tid, MAXM)], snv = S.sn[min(tid, MAXM - 1)];
   const double csv = S.cs[min(tid, MAXM - 1)];
-  const double thr = S.cancel_thr, wn2in = S.wn2_in, beta = S.beta, target = S.target;
+  const double thr = S.cancel_thr, wn2in = PROJ ? wn2in_p : S.wn2_in, beta = S.beta, target = S.target;
   const int m = S.m, iters = S.iters, ncancel = S.ncancel;
   // values used only under a branch below: tie them here, or the compiler sinks
   // their loads into the branch, each then costing a full memory latency
   asm volatile("" ::"v"(hv.x), "v"(hv.y), "v"(gv.x), "v"(gv.y), "v"(snv.x), "v"(snv.y), "v"(csv));
   asm volatile("" ::"s"(thr), "s"(wn2in), "s"(beta), "s"(target), "s"(m), "s"(iters), "s"(ncancel));
   if (!runb) return;
-  const double wn2 = norm_from_partials(part + (long long)b * nblk, nblk);
+  const double wn2 = PROJ ? wn2_p : norm_from_partials(part + (long long)b * nblk, nblk);
   const bool cancel = wn2 < thr * wn2in;
   if (tid <= j) col[tid] = make_double2((tid == j ? 1.0 : 0.0) - hv.x, -hv.y);
   if (tid < j) { csl[tid] = csv; snl[tid] = snv; }
@@ -123,12 +128,17 @@ PSFD_D void givens_task(GState* st, int* run, const double2* part, int nblk, int
     const bool breakdown = !(hn > 1e-300 * (beta > 0 ? beta : 1.0));
     const bool stop = conv || (j + 1 >= m) || breakdown || cancel || !(res == res);
     S.wn2 = wn2;
+    S.raw_last = PROJ ? j + 1 : 0;
     if (cancel) S.ncancel = ncancel + 1;
     S.stop = stop;
     run[b] = stop ? 0 : 1;
   }
   __syncthreads();
   if (tid <= j) S.H[tid][j] = col[tid];
+}
+
+PSFD_D void givens_task(GState* st, int* run, const double2* part, int nblk, int b) {
+  givens_impl<false>(st, run, part, nblk, b, make_double2(0, 0), 0.0, 0.0);
 }
 
 }  // namespace psfd

@@ -262,6 +262,56 @@ void krylov_givens(GState* st, int* run, const double2* part, int nbatch, hipStr
   hipLaunchKernelGGL(k_update_final, dim3(nbatch), dim3(KB), 0, s, st, run, part, RED_BLOCKS);
 }
 
+// the Givens step of the last column from its projections alone (see
+// krylov_givens_proj); the partials are summed as k_update sums them
+__global__ void __launch_bounds__(KB) k_givens_proj(GState* st, int* run, const double2* dpart, int jh) {
+  __shared__ double2 hsum[MAXM + 2];
+  __shared__ double wn2s;
+  const int b = blockIdx.x;
+  const int rb = run[b], jd = jh >= 0 ? jh : st[b].j;
+  asm volatile("" ::"s"(rb), "s"(jd));
+  if (!rb) return;
+  const int cnt = jd + 1;
+  const double scv = st[b].sc[min((int)threadIdx.x, MAXM)];
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NBD = DotBlocks<float2>::value, PL = NBD / 64, NW = KB / 64;
+    const double2* pb = dpart + (long long)b * PSTR * NBD;
+    for (int i = wave; i <= cnt; i += NW) {
+      double2 pv[PL];
+#pragma unroll
+      for (int k = 0; k < PL; ++k) pv[k] = pb[(long long)i * NBD + lane + 64 * k];
+      double2 t = make_double2(0, 0);
+#pragma unroll
+      for (int k = 0; k < PL; ++k) t = cadd(t, pv[k]);
+      t.x = wave_sum(t.x);
+      t.y = wave_sum(t.y);
+      if (lane == 0) hsum[i] = t;
+    }
+  }
+  __syncthreads();
+  // h_i = sc_i <slot_i, w>; ||w - V h||^2 = ||w||^2 - sum |h_i|^2 in a fixed order
+  const double2 hv = (int)threadIdx.x < cnt ? cscale(hsum[threadIdx.x], scv) : make_double2(0, 0);
+  GState& S = st[b];
+  if ((int)threadIdx.x < cnt) S.h[threadIdx.x] = hv;
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int i = 0; i < cnt; ++i) {
+      const double2 h = cscale(hsum[i], st[b].sc[i]);
+      a += h.x * h.x + h.y * h.y;
+    }
+    const double w2 = hsum[cnt].x;
+    S.wn2_in = w2;
+    wn2s = w2 - a > 0.0 ? w2 - a : 0.0;
+  }
+  __syncthreads();
+  givens_impl<true>(st, run, nullptr, 0, b, hv, hsum[cnt].x, wn2s);
+}
+
+void krylov_givens_proj(GState* st, int* run, const double2* dpart, int nbatch, hipStream_t s, int jh) {
+  hipLaunchKernelGGL(k_givens_proj, dim3(nbatch), dim3(KB), 0, s, st, run, dpart, jh);
+}
+
 template <class T>
 void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, int* run,
                    const double2* dpart, double2* part, int nbatch, hipStream_t s, int jh, bool givens) {
@@ -311,7 +361,15 @@ __global__ void __launch_bounds__(KB) k_solve_small(GState* st, const int* mask)
   __syncthreads();
   // as coefficients of the slots, which hold v_i / sc_i
   if ((int)threadIdx.x < k) S.y[threadIdx.x] = cscale(yl[threadIdx.x], S.sc[threadIdx.x]);
-  if ((int)threadIdx.x <= k) S.cres[threadIdx.x] = cscale(cl[threadIdx.x], S.sc[threadIdx.x]);
+  if ((int)threadIdx.x <= k) {
+    double2 c = cscale(cl[threadIdx.x], S.sc[threadIdx.x]);
+    // slot k still holds w = v_k / sc_k + sum_{i<k} h_i v_i: fold the update in
+    if (k > 0 && S.raw_last == k && (int)threadIdx.x < k) {
+      const double2 ck = cscale(cl[k], S.sc[k]);
+      c = csub(c, cscale(cmul(ck, S.h[threadIdx.x]), S.sc[threadIdx.x]));
+    }
+    S.cres[threadIdx.x] = c;
+  }
 }
 
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s) {

@@ -29,6 +29,8 @@ struct GState {
   int ncols;        // Hessenberg columns completed in the current cycle
   int ncancel;      // cycles ended early by severe cancellation (all cycles)
   int since_true;   // restarts since the last one with b - A x evaluated (basis residuals in between)
+  int raw_last;     // k > 0: slot k holds w before its Gram-Schmidt update (last column of the
+                    // cycle, Givens step from the projections); 0: every slot is updated
   double target;    // stopping threshold of the residual estimate
   double res;       // |g_{j+1}|: current residual estimate
   double beta;      // ||r0|| of the current cycle
@@ -79,10 +81,17 @@ void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, 
 // the Givens step of the newest column from the norm partials of krylov_update
 // (RED_BLOCKS per instance in part): one block per instance
 void krylov_givens(GState* st, int* run, const double2* part, int nbatch, hipStream_t s);
+// The last column of a cycle without its update pass: h and ||w||^2 from the
+// projection partials (DotBlocks<float2> per value in dpart, as the update pass
+// sums them), ||w - V h||^2 = ||w||^2 - sum |h_i|^2 (orthonormal basis), then the
+// Givens step. Slot j + 1 keeps w; the residual coefficients of the restart fold
+// the update in (krylov_solve_small). One block per instance; FP32 bases.
+void krylov_givens_proj(GState* st, int* run, const double2* dpart, int nbatch, hipStream_t s, int jh);
 // y = H^{-1} g over the k = j + 1 completed columns, and the coefficients of the
 // cycle's GMRES residual in the basis, cres = Q^H (g_k e_k) (Q: the Givens
 // rotations); both are stored times the slot scales sc[i], as coefficients of
-// the slots themselves
+// the slots themselves. When slot k holds w before its update (raw_last == k),
+// cres_i -= cres_k h_i sc_i for i < k, so that cres applies to the slots as they are
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s);
 // x += sum_{i<k} y_i v_i for the instances with mask[b]; for those with rec[b]
 // also the restart residual from the basis, r = sum_{i<=k} cres_i slot_i, into
