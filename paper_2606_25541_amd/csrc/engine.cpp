@@ -601,13 +601,16 @@ static bool fuse_dots(const Group& g, size_t esz) {
 }
 
 // Whether the forward transverse kernel of a lock-step Arnoldi step also does the
-// Gram-Schmidt update of the previous column (FP32 128 x 128 square planes;
-// PSFD_FUSE_UPDATE=0 keeps the separate update pass, read per call).
+// Gram-Schmidt update of the previous column (FP32 128 x 128 square planes, and
+// pencil blocks large enough to run the Givens task: at least GIVENS_THREADS
+// threads, i.e. padded z lengths of 64 and more; PSFD_FUSE_UPDATE=0 keeps the
+// separate update pass, read per call).
 static bool fuse_update(const Group& g, size_t esz) {
   const char* e = std::getenv("PSFD_FUSE_UPDATE");
   if (e && std::atoi(e) == 0) return false;
   const XYCfg c = xy_config(g.sh, esz);
-  return c.fused && tile_takes_update(tile_base(g, nullptr, c.full), esz);
+  return c.fused && tile_takes_update(tile_base(g, nullptr, c.full), esz) &&
+         z_config(g.sh, esz).nthr >= GIVENS_THREADS;
 }
 
 // The inverse transverse stage of an Arnoldi step: the slot vout (j + 1) =

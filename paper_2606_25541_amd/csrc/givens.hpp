@@ -8,7 +8,6 @@
 
 namespace psfd {
 
-constexpr int GIVENS_THREADS = 256;  // threads of a block that take part (the rest only meet the barriers)
 
 PSFD_D double gv_wave_sum(double v) {
 #pragma unroll
@@ -19,7 +18,8 @@ PSFD_D double gv_wave_sum(double v) {
 // ||w||^2 from the nblk (<= RED_BLOCKS) norm partials of one instance: the first
 // GIVENS_THREADS threads take partials tid, tid + 256, ... in order, then
 // wavefront sums, then the four wavefront totals in order. Every thread of the
-// block must call it; all of them get the total.
+// block must call it, and the block must have at least GIVENS_THREADS threads
+// (the rest only meet the barriers); all of them get the total.
 PSFD_D double norm_from_partials(const double2* pb, int nblk) {
   __shared__ double2 gsm[GIVENS_THREADS / 64];
   __shared__ double gtot;

@@ -11,6 +11,7 @@ struct GState;
 // this one: an extra block of the kernel runs it (see givens_task), and the
 // other blocks take the scale of the step's input vector from the same norm
 // partials (nblk per instance in part, instance stride nblk) instead of in_scale.
+// The kernel's blocks must have at least GIVENS_THREADS threads.
 struct GivensTask {
   GState* st;
   int* run;

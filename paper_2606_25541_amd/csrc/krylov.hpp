@@ -18,6 +18,9 @@ constexpr int LIN_BLOCKS = 2048;  // blocks per instance of the solution update 
 template <class T> struct DotBlocks { static constexpr int value = sizeof(T) == 8 ? 256 : 512; };
 constexpr int DOT_BLOCKS_MAX = 512;
 constexpr int PSTR = MAXM + 2;    // partial stride: up to MAXM + 1 dots and ||w||^2
+// threads of a block that take part in the Givens task and its norm sum; a
+// kernel that runs them needs at least this many threads per block
+constexpr int GIVENS_THREADS = 256;
 
 // Device-resident state of one GMRES(m) instance. All scalars are FP64.
 struct GState {

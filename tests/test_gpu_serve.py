@@ -64,6 +64,42 @@ def test_batch_equals_single():
         assert inf["iters"] == i1["iters"]
 
 
+def test_batch_equals_single_128_planes():
+    """FP32 128 x 128 planes, 32 of them per component (padded z length 64, pencil
+    blocks large enough for the Givens task): the lock-step batch runs the
+    Gram-Schmidt update in the forward plane kernel, the projections in the
+    inverse one and the last column's Givens step from the projections. Three
+    instances, one of which converges cycles before the others, must each equal
+    their lone solve bitwise."""
+    from paper_2606_25541_amd import api
+    dev = device()
+    angles = clips.pupil_angles()
+    cs = []
+    for i in range(3):
+        th, ph = angles[(11 * i + 3) % len(angles)]
+        p = prob(128, 32, th, ph, i % 2)
+        de = clips.manhattan(128, 128, 32, p.lx_nm, p.ly_nm, seed=300 + i)
+        if i == 2:
+            de = de * 0.25  # weaker contrast: converges in fewer cycles
+        cs.append((p, de))
+    opts = dict(rtol=1e-9, precision="mixed", restart=8)
+    say("batch of 3 at 128x128x32")
+    em, od, infos = api.psfd_solve_batch([c[0] for c in cs], [torch.from_numpy(c[1]).to(dev) for c in cs], **opts)
+    torch.cuda.synchronize()
+    iters = []
+    for (p, de), e, o, inf in zip(cs, em, od, infos):
+        plan = api.Plan(p, **opts)
+        e1, o1, i1 = plan.psfd_solve(torch.from_numpy(de).to(dev))
+        torch.cuda.synchronize()
+        say("  batched", inf, "alone", i1)
+        assert inf["status"] == 0
+        assert inf["iters"] == i1["iters"]
+        assert np.array_equal(e.cpu().numpy(), e1.cpu().numpy()), rel(e.cpu().numpy(), e1.cpu().numpy())
+        assert np.array_equal(o.cpu().numpy(), o1.cpu().numpy())
+        iters.append(inf["iters"])
+    assert min(iters) < max(iters)
+
+
 def test_batch_reuses_cached_workspace():
     # a second call of the same kind runs in the kept workspace: same results;
     # after the cache is released the call allocates afresh, same results again

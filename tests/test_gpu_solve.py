@@ -81,7 +81,9 @@ def _ref_128():
 @pytest.mark.parametrize("jh", ["lockstep", "server"])
 def test_solve_128_planes_projections_in_plane_kernel(jh, monkeypatch):
     """128 x 128 planes, mixed: the inverse square-plane kernel also forms the
-    Gram-Schmidt projections (6 planes, so most partial slots are zero-filled).
+    Gram-Schmidt projections (6 planes, so most partial slots are zero-filled;
+    the update stays a separate pass here: the pencil blocks of a padded z
+    length of 4 are too small for the Givens task).
     The solve must match the oracle, and so must the separate projection pass
     (PSFD_FUSE_DOTS=0), within one restart cycle of the same step count;
     "server" runs it through the serving path (Krylov index read per slot)."""
@@ -120,6 +122,32 @@ def test_solve_128_planes_projections_in_plane_kernel(jh, monkeypatch):
     # the two paths differ only in the FP32 rounding order of the projections
     assert abs(info2["iters"] - info["iters"]) <= 8
     assert rel(em2.cpu().numpy(), ref["emask"]) < 1e-8
+
+
+def test_update_in_forward_plane_kernel_matches_separate_pass(monkeypatch):
+    """128 x 128 x 32, mixed, lock-step: the Gram-Schmidt update in the forward
+    plane kernel (pencil with the Givens step, last column from the projections)
+    against the separate update pass (PSFD_FUSE_UPDATE=0, the path the oracle
+    parity cases run): the same solution to the solve tolerance, within one
+    restart cycle of the same step count, and deterministic."""
+    from paper_2606_25541_amd import api
+    dev = device()
+    layers, es = clips.mo_si_stack(40)
+    p = clips.Problem(nx=128, ny=128, nz=32, lx_nm=256.0, ly_nm=256.0, t_nm=60.0, theta_deg=6.0,
+                      phi_deg=15.0, pol=1, layers=layers, eps_sub=es)
+    d = torch.from_numpy(clips.contact_holes(128, 128, 32, 256.0, 256.0, 6, seed=77)).to(dev)
+    say("solve 128x128x32 mixed, update fused vs separate")
+    plan = api.Plan(p, rtol=1e-10, precision="mixed", restart=8)
+    e1, o1, i1 = plan.psfd_solve(d)
+    e1b, o1b, i1b = plan.psfd_solve(d)
+    monkeypatch.setenv("PSFD_FUSE_UPDATE", "0")
+    e2, o2, i2 = plan.psfd_solve(d)
+    say("  fused", i1, "separate", i2)
+    assert i1["status"] == 0 and i2["status"] == 0
+    assert torch.equal(e1, e1b) and i1 == i1b
+    assert abs(i1["iters"] - i2["iters"]) <= 8
+    assert rel(e1.cpu().numpy(), e2.cpu().numpy()) < 1e-8
+    assert np.max(np.abs(o1.cpu().numpy() - o2.cpu().numpy())) < 1e-9
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
