@@ -100,6 +100,36 @@ def test_batch_equals_single_128_planes():
     assert min(iters) < max(iters)
 
 
+def test_server_matches_alone_128_planes():
+    """128 x 128 x 32, mixed: the lone (lock-step) solve fuses the Gram-Schmidt
+    update into the forward plane kernel, the server's slots (each at its own
+    step) keep the separate update pass; both reach the same solution to the
+    solve tolerance."""
+    from paper_2606_25541_amd import api
+    dev = device()
+    p = prob(128, 32, 6.0, 0.0, 0)
+    de = clips.manhattan(128, 128, 32, p.lx_nm, p.ly_nm, seed=401)
+    d = torch.from_numpy(de).to(dev)
+    opts = dict(rtol=1e-10, precision="mixed", restart=8)
+    plan = api.Plan(p, **opts)
+    e1, o1, i1 = plan.psfd_solve(d)
+    srv = api.Server(hbm_budget=8 << 30, max_slots=2, **opts)
+    e2 = torch.empty_like(e1)
+    o2 = torch.empty_like(o1)
+    t = srv.submit(p, d, e2, o2)
+    deadline = time.perf_counter() + 60
+    done = False
+    while not done and time.perf_counter() < deadline:
+        done, i2, _ = srv.poll(t)
+        time.sleep(0.002)
+    srv.close()
+    assert done, "served request not finished within 60 s"
+    say("  alone", i1, "served", i2)
+    assert i1["status"] == 0 and i2["status"] == 0
+    assert rel(e2.cpu().numpy(), e1.cpu().numpy()) < 1e-8
+    assert np.max(np.abs(o2.cpu().numpy() - o1.cpu().numpy())) < 1e-9
+
+
 def test_batch_reuses_cached_workspace():
     # a second call of the same kind runs in the kept workspace: same results;
     # after the cache is released the call allocates afresh, same results again
