@@ -600,17 +600,18 @@ static bool fuse_dots(const Group& g, size_t esz) {
   return c.fused && tile_takes_dots(tile_base(g, nullptr, c.full), esz);
 }
 
-// Whether the forward transverse kernel of a lock-step Arnoldi step also does the
+// Whether the forward transverse kernel of an Arnoldi step also does the
 // Gram-Schmidt update of the previous column (FP32 128 x 128 square planes, and
 // pencil blocks large enough to run the Givens task: at least GIVENS_THREADS
-// threads, i.e. padded z lengths of 64 and more; PSFD_FUSE_UPDATE=0 keeps the
-// separate update pass, read per call).
+// threads, i.e. padded z lengths of 64 and more; with the projections in the
+// inverse kernel, which also marks the update pending; PSFD_FUSE_UPDATE=0 keeps
+// the separate update pass, read per call).
 static bool fuse_update(const Group& g, size_t esz) {
   const char* e = std::getenv("PSFD_FUSE_UPDATE");
   if (e && std::atoi(e) == 0) return false;
   const XYCfg c = xy_config(g.sh, esz);
   return c.fused && tile_takes_update(tile_base(g, nullptr, c.full), esz) &&
-         z_config(g.sh, esz).nthr >= GIVENS_THREADS;
+         z_config(g.sh, esz).nthr >= GIVENS_THREADS && fuse_dots(g, esz);
 }
 
 // The inverse transverse stage of an Arnoldi step: the slot vout (j + 1) =
@@ -737,9 +738,30 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
   const GivensTask gt{g.st, g.run, g.part, RED_BLOCKS};
   const double* isc = &g.st[0].inv_norm;
   const long long iss = (long long)(sizeof(GState) / sizeof(double));
-  bool upd = false;
-  if constexpr (std::is_same<T, float2>::value) upd = lock && fuse_update(g, sizeof(T));
-  if (upd && jh > 0) {
+  bool upd = false, upd_slots = false;
+  if constexpr (std::is_same<T, float2>::value) {
+    upd = lock && fuse_update(g, sizeof(T));
+    upd_slots = !lock && fuse_update(g, sizeof(T));
+  }
+  if (upd_slots) {
+    // instances at different steps (server slots): the same fused kernels, each
+    // instance taking the update, the scale and the Givens step only while an
+    // update is pending (GState::pend), and the last column's Givens step from
+    // the projections, so that a slot computes exactly what a lone solve does
+    const int np = 3 * g.sh.nz;
+    const XYCfg c = xy_config(g.sh, sizeof(T));
+    TileArgs a = tile_base(g, twiddles<T>(g), c.full);
+    a.in = vin; a.vol = vr(deps_of<T>(g), g.sh.N); a.out = vr((T*)g.wsP, n3); a.active = g.run;
+    a.up = UpdateTask{V, n3, bsv, g.st, g.dpart2, g.part, -1};
+    if constexpr (std::is_same<T, float2>::value)
+      launch_tile<T, false, LD_UPD_VX, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
+    const GivensTask gp{g.st, g.run, g.part, np, 1};
+    apply_stage<T>(g, 1, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, nullptr, 0, &gp);
+    if (!arnoldi_inverse<T>(g, vout, jh, s)) krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.B, s, jh);
+    krylov_givens_proj(g.st, g.run, g.dpart2, g.B, s, -1);
+    return;
+  }
+  if (upd) {
     // the update of column jh - 1 in the forward plane kernel, which transforms
     // slot jh unscaled; the pencil kernel scales it from the plane norm
     // partials and runs the Givens step of column jh - 1 in one extra block
@@ -750,8 +772,10 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
     a.up = UpdateTask{V, n3, bsv, g.st, g.dpart2, g.part, jh};
     if constexpr (std::is_same<T, float2>::value)
       launch_tile<T, false, LD_UPD_VX, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
+    // at step 0 the kernel loads slot 0 scaled (no update), and no Givens step is pending
     const GivensTask gp{g.st, g.run, g.part, np};
-    apply_stage<T>(g, 1, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, nullptr, 0, &gp);
+    apply_stage<T>(g, 1, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, nullptr, 0,
+                   jh > 0 ? &gp : nullptr);
   } else {
     apply_stage<T>(g, 0, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, isc, iss,
                    lock && jh > 0 ? &gt : nullptr);

@@ -188,15 +188,14 @@ __host__ __device__ constexpr size_t plane_lds(int ln, size_t esz) {
 // block gets the same coefficients bit for bit; the block of plane 0 stores h
 // and ||w||^2 before the update for the Givens step.
 template <class T, int KT, int NT>
-PSFD_D void plane_update(const TileArgs& a, T (&wv)[KT], T (&vb)[KT], const T* vol, T* slot, int b, int plane,
-                         long long poff) {
+PSFD_D void plane_update(const TileArgs& a, int cnt, T (&wv)[KT], T (&vb)[KT], const T* vol, T* slot, int b,
+                         int plane, long long poff) {
   constexpr int NW = NT / 64, NBD = DotBlocks<float2>::value, PL = NBD / 64;
   typedef typename real_of<T>::type R;
   __shared__ double2 hsum[MAXM + 1];
   __shared__ T hc[MAXM];
   __shared__ double nred[NW];
   const UpdateTask& u = a.up;
-  const int cnt = u.j;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   GState& S = u.st[b];
   const T* sb = reinterpret_cast<const T*>(u.V) + (long long)b * u.bsv + poff;
@@ -323,6 +322,8 @@ PSFD_D void plane_dots(const TileArgs& a, const T (&wv)[KT], int b, int plane, l
     pp[plane] = t;
     for (int q = plane + 3 * a.nz; q < NBD; q += 3 * a.nz) pp[q] = make_double2(0, 0);
   }
+  // the update of this column is now pending (read by the next step's kernels)
+  if (plane == 0 && tid == 0) d.st[b].pend = 1;
 }
 
 template <class T, bool INV, int LD, int ST, int LN>
@@ -346,6 +347,24 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   const long long poff = (long long)plane * N * N;
   const int tid = threadIdx.x;
   const T* in = vref<T>(a.in, b) + poff;
+  // LD_UPD_VX: the update of column cnt - 1 on slot cnt; per instance (up.j < 0)
+  // only with a pending update, and at up.j = 0 not at all: then the plain
+  // scaled load of the slot (by S.inv_norm, as LD_VX with in_scale)
+  int cnt = 0;
+  bool upd = LD == LD_UPD_VX;
+  if constexpr (LD == LD_UPD_VX) {
+    if (a.up.j >= 0) {
+      cnt = a.up.j;
+      upd = cnt > 0;  // step 0 of a cycle: the plain scaled load
+    } else {
+      const GState& S = a.up.st[b];
+      const int pend = S.pend, js = S.j;
+      upd = pend != 0;
+      cnt = js + 1;
+      in = reinterpret_cast<const T*>(a.up.V) + (long long)b * a.up.bsv + (long long)(upd ? js + 1 : js) * a.up.ldv +
+           poff;
+    }
+  }
   const T* vol = VX ? vref<T>(a.vol, b) + (long long)z * N * N : nullptr;
   const T* aux = ST == ST_AXPBY ? vref<T>(a.aux, b) + poff : nullptr;
   typedef typename real_of<T>::type R;
@@ -366,7 +385,14 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
     for (int k = 0; k < KT; ++k) xa[k] = aux[tid + k * NT];
   }
   // the Gram-Schmidt update of the previous column on slot j before its transform
-  if constexpr (LD == LD_UPD_VX) plane_update<T, KT, NT>(a, va, vb, vol, const_cast<T*>(in), b, plane, poff);
+  if constexpr (LD == LD_UPD_VX) {
+    if (upd) {
+      plane_update<T, KT, NT>(a, cnt, va, vb, vol, const_cast<T*>(in), b, plane, poff);
+    } else {
+#pragma unroll
+      for (int k = 0; k < KT; ++k) vb[k] = vol[tid + k * NT];
+    }
+  }
   const double* tab = a.tab + (long long)b * a.tab_stride;
   const R k0sq = (R)tab[TS_K0SQ];
   // scale of the input on load (the newest Arnoldi vector is kept unnormalised),
@@ -376,6 +402,7 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   R scl = (R)1;
   if (LD == LD_VX && a.gv.st) scl = (R)inv_norm_of(norm_from_partials(a.gv.part + (long long)b * a.gv.nblk, a.gv.nblk));
   else if (LD == LD_VX && a.in_scale) scl = (R)a.in_scale[(long long)b * a.scale_stride];
+  else if (LD == LD_UPD_VX && !upd) scl = (R)a.up.st[b].inv_norm;
   const R ks = k0sq * scl;
   if (tid < N) twl[tid] = tw0;
   auto put = [&](int k) {
@@ -653,9 +680,11 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   T* lds = reinterpret_cast<T*>(smem_d);
   typedef typename real_of<T>::type R;
   const int b = blockIdx.y;
-  // a GivensTask takes the extra last block of the grid
+  // a GivensTask takes the extra last block of the grid; by_pend: only for the
+  // instances with a pending update
+  const bool gvb = a.gv.st && (!a.gv.by_pend || a.gv.st[b].pend);
   if (a.gv.st && blockIdx.x == gridDim.x - 1) {
-    givens_task(a.gv.st, a.gv.run, a.gv.part, a.gv.nblk, b);
+    if (gvb) givens_task(a.gv.st, a.gv.run, a.gv.part, a.gv.nblk, b);
     return;
   }
   if (a.active && !a.active[b]) return;
@@ -696,7 +725,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     }
     // with a GivensTask the input is the new Arnoldi vector unscaled: its scale
     // from the norm partials the task sums (bitwise the same value)
-    if (a.gv.st) {
+    if (gvb) {
       const R scl = (R)inv_norm_of(norm_from_partials(a.gv.part + (long long)b * a.gv.nblk, a.gv.nblk));
 #pragma unroll
       for (int k = 0; k < 4; ++k) buf[k] = cscale(buf[k], scl);

@@ -268,9 +268,10 @@ __global__ void __launch_bounds__(KB) k_givens_proj(GState* st, int* run, const 
   __shared__ double2 hsum[MAXM + 2];
   __shared__ double wn2s;
   const int b = blockIdx.x;
-  const int rb = run[b], jd = jh >= 0 ? jh : st[b].j;
-  asm volatile("" ::"s"(rb), "s"(jd));
-  if (!rb) return;
+  const int rb = run[b], jd = jh >= 0 ? jh : st[b].j, mb = st[b].m;
+  asm volatile("" ::"s"(rb), "s"(jd), "s"(mb));
+  // jh < 0 (instances at different steps): only those at the last column
+  if (!rb || (jh < 0 && jd != mb - 1)) return;
   const int cnt = jd + 1;
   const double scv = st[b].sc[min((int)threadIdx.x, MAXM)];
   {
@@ -439,6 +440,7 @@ __global__ void k_start(GState* st, const double* rnorm2, const double* abs_targ
   GState& S = st[b];
   const double rn = sqrt(rnorm2[b]);
   S.j = 0;
+  S.pend = 0;
   S.m = m;
   S.cancel_thr = cancel_thr;
   S.ncols = 0;
@@ -498,6 +500,7 @@ __global__ void k_cycle_start(GState* st, const double* rnorm2, const double* ab
     return;
   }
   S.j = 0;
+  S.pend = 0;
   S.m = m;
   S.cancel_thr = cancel_thr;
   S.ncols = 0;

@@ -17,6 +17,8 @@ struct GivensTask {
   int* run;
   const double2* part;
   int nblk;
+  int by_pend;  // 1: only the instances with a pending update (GState::pend) take the task
+                // and the scale; the others' input was scaled on load
 };
 // The Gram-Schmidt update of column j - 1, left to the forward square-plane
 // kernel of step j (LD_UPD_VX, lock-step solves): every plane block sums the
@@ -25,6 +27,10 @@ struct GivensTask {
 // plane, stores it, and leaves the plane's ||slot_j||^2 in part[b * planes + plane];
 // the block of plane 0 stores h and ||w||^2 before the update for the Givens step.
 // The vector enters the transform unscaled: the next kernel applies its scale.
+// j = 0 (the first step of a cycle): no update, slot 0 scaled on load by
+// S.inv_norm, as LD_VX does. j < 0 (instances at different steps): per instance
+// from its state; with a pending update (pend) the update of column S.j on slot
+// S.j + 1, else slot S.j scaled on load.
 struct UpdateTask {
   const void* V;        // basis of instance 0; slot i of instance b at V + b bsv + i ldv
   long long ldv, bsv;
@@ -41,7 +47,8 @@ struct UpdateTask {
 struct DotTask {
   const void* V;        // basis of instance 0; slot i of instance b at V + b bsv + i ldv
   long long ldv, bsv;
-  const GState* st;     // j of each instance when jh < 0
+  GState* st;           // j of each instance when jh < 0; pend is set (the update of the
+                        // column is pending)
   double2* part;
   int jh;               // >= 0: every running instance stands at step jh
 };

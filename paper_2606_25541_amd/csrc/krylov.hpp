@@ -34,6 +34,9 @@ struct GState {
   int since_true;   // restarts since the last one with b - A x evaluated (basis residuals in between)
   int raw_last;     // k > 0: slot k holds w before its Gram-Schmidt update (last column of the
                     // cycle, Givens step from the projections); 0: every slot is updated
+  int pend;         // 1: slot j + 1 holds B v_j with its projections stored, and the update of
+                    // column j is left to the next forward plane kernel (set by the inverse
+                    // kernel that forms the projections, cleared at a cycle start)
   double target;    // stopping threshold of the residual estimate
   double res;       // |g_{j+1}|: current residual estimate
   double beta;      // ||r0|| of the current cycle

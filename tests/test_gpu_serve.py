@@ -101,33 +101,50 @@ def test_batch_equals_single_128_planes():
 
 
 def test_server_matches_alone_128_planes():
-    """128 x 128 x 32, mixed: the lone (lock-step) solve fuses the Gram-Schmidt
-    update into the forward plane kernel, the server's slots (each at its own
-    step) keep the separate update pass; both reach the same solution to the
-    solve tolerance."""
+    """128 x 128 x 32, mixed: the lone (lock-step) solve and the server's slots
+    (each at its own step, with a per-slot pending-update flag) run the same
+    fused kernels: the Gram-Schmidt update in the forward plane kernel, the
+    projections in the inverse one, the Givens step in the pencil and the last
+    column's from the projections. Two requests submitted apart, so that their
+    slots stand at different steps, each equal their lone solve bit for bit."""
     from paper_2606_25541_amd import api
     dev = device()
-    p = prob(128, 32, 6.0, 0.0, 0)
-    de = clips.manhattan(128, 128, 32, p.lx_nm, p.ly_nm, seed=401)
-    d = torch.from_numpy(de).to(dev)
     opts = dict(rtol=1e-10, precision="mixed", restart=8)
-    plan = api.Plan(p, **opts)
-    e1, o1, i1 = plan.psfd_solve(d)
+    reqs = []
+    for i, (th, ph, pol) in enumerate(((6.0, 0.0, 0), (7.5, 40.0, 1))):
+        p = prob(128, 32, th, ph, pol)
+        de = clips.manhattan(128, 128, 32, p.lx_nm, p.ly_nm, seed=401 + i)
+        reqs.append((p, torch.from_numpy(de).to(dev)))
     srv = api.Server(hbm_budget=8 << 30, max_slots=2, **opts)
-    e2 = torch.empty_like(e1)
-    o2 = torch.empty_like(o1)
-    t = srv.submit(p, d, e2, o2)
+    outs, tickets = [], []
+    for k, (p, d) in enumerate(reqs):
+        e = torch.empty((3, p.nz, p.ny, p.nx), dtype=torch.complex128, device=dev)
+        o = torch.empty((p.ny, p.nx, 3), dtype=torch.complex128, device=dev)
+        tickets.append(srv.submit(p, d, e, o))
+        outs.append((e, o))
+        if k == 0:
+            time.sleep(0.003)  # the second request joins while the first runs
+    infos = {}
     deadline = time.perf_counter() + 60
-    done = False
-    while not done and time.perf_counter() < deadline:
-        done, i2, _ = srv.poll(t)
+    while len(infos) < len(tickets) and time.perf_counter() < deadline:
+        for t in tickets:
+            if t not in infos:
+                done, info, _ = srv.poll(t)
+                if done:
+                    infos[t] = info
         time.sleep(0.002)
     srv.close()
-    assert done, "served request not finished within 60 s"
-    say("  alone", i1, "served", i2)
-    assert i1["status"] == 0 and i2["status"] == 0
-    assert rel(e2.cpu().numpy(), e1.cpu().numpy()) < 1e-8
-    assert np.max(np.abs(o2.cpu().numpy() - o1.cpu().numpy())) < 1e-9
+    assert len(infos) == len(tickets), "served requests not finished within 60 s"
+    for (p, d), (e2, o2), t in zip(reqs, outs, tickets):
+        plan = api.Plan(p, **opts)
+        e1, o1, i1 = plan.psfd_solve(d)
+        torch.cuda.synchronize()
+        i2 = infos[t]
+        say("  alone", i1, "served", i2)
+        assert i1["status"] == 0 and i2["status"] == 0
+        assert i1["iters"] == i2["iters"]
+        assert torch.equal(e1, e2), rel(e2.cpu().numpy(), e1.cpu().numpy())
+        assert torch.equal(o1, o2)
 
 
 def test_batch_reuses_cached_workspace():
