@@ -754,7 +754,7 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
     a.in = vin; a.vol = vr(deps_of<T>(g), g.sh.N); a.out = vr((T*)g.wsP, n3); a.active = g.run;
     a.up = UpdateTask{V, n3, bsv, g.st, g.dpart2, g.part, -1};
     if constexpr (std::is_same<T, float2>::value)
-      launch_tile<T, false, LD_UPD_VX, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
+      launch_tile<T, false, LD_UPD_SLOT, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
     const GivensTask gp{g.st, g.run, g.part, np, 1};
     apply_stage<T>(g, 1, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, nullptr, 0, &gp);
     if (!arnoldi_inverse<T>(g, vout, jh, s)) krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.B, s, jh);
@@ -770,9 +770,12 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
     TileArgs a = tile_base(g, twiddles<T>(g), c.full);
     a.in = vin; a.vol = vr(deps_of<T>(g), g.sh.N); a.out = vr((T*)g.wsP, n3); a.active = g.run;
     a.up = UpdateTask{V, n3, bsv, g.st, g.dpart2, g.part, jh};
-    if constexpr (std::is_same<T, float2>::value)
-      launch_tile<T, false, LD_UPD_VX, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
-    // at step 0 the kernel loads slot 0 scaled (no update), and no Givens step is pending
+    // at step 0 the per-slot kernel loads slot 0 scaled (no update, as the
+    // server's first step does), and no Givens step is pending
+    if constexpr (std::is_same<T, float2>::value) {
+      if (jh > 0) launch_tile<T, false, LD_UPD_VX, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
+      else launch_tile<T, false, LD_UPD_SLOT, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
+    }
     const GivensTask gp{g.st, g.run, g.part, np};
     apply_stage<T>(g, 1, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, nullptr, 0,
                    jh > 0 ? &gp : nullptr);

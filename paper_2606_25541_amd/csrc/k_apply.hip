@@ -335,7 +335,8 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   T* lds = reinterpret_cast<T*>(smem_d);
   T* twl = lds + N * P;
   const int b = blockIdx.y;
-  constexpr bool VX = LD == LD_VX || LD == LD_UPD_VX;  // contrast multiply on load
+  constexpr bool UPD = LD == LD_UPD_VX || LD == LD_UPD_SLOT;  // Gram-Schmidt update on load
+  constexpr bool VX = LD == LD_VX || UPD;                     // contrast multiply on load
   // a GivensTask takes the extra last block of the grid
   if (LD == LD_VX && a.gv.st && blockIdx.x == gridDim.x - 1) {
     givens_task(a.gv.st, a.gv.run, a.gv.part, a.gv.nblk, b);
@@ -350,9 +351,9 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   // LD_UPD_VX: the update of column cnt - 1 on slot cnt; per instance (up.j < 0)
   // only with a pending update, and at up.j = 0 not at all: then the plain
   // scaled load of the slot (by S.inv_norm, as LD_VX with in_scale)
-  int cnt = 0;
+  int cnt = LD == LD_UPD_VX ? a.up.j : 0;
   bool upd = LD == LD_UPD_VX;
-  if constexpr (LD == LD_UPD_VX) {
+  if constexpr (LD == LD_UPD_SLOT) {
     if (a.up.j >= 0) {
       cnt = a.up.j;
       upd = cnt > 0;  // step 0 of a cycle: the plain scaled load
@@ -385,8 +386,8 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
     for (int k = 0; k < KT; ++k) xa[k] = aux[tid + k * NT];
   }
   // the Gram-Schmidt update of the previous column on slot j before its transform
-  if constexpr (LD == LD_UPD_VX) {
-    if (upd) {
+  if constexpr (UPD) {
+    if (LD == LD_UPD_VX || upd) {
       plane_update<T, KT, NT>(a, cnt, va, vb, vol, const_cast<T*>(in), b, plane, poff);
     } else {
 #pragma unroll
@@ -402,7 +403,7 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   R scl = (R)1;
   if (LD == LD_VX && a.gv.st) scl = (R)inv_norm_of(norm_from_partials(a.gv.part + (long long)b * a.gv.nblk, a.gv.nblk));
   else if (LD == LD_VX && a.in_scale) scl = (R)a.in_scale[(long long)b * a.scale_stride];
-  else if (LD == LD_UPD_VX && !upd) scl = (R)a.up.st[b].inv_norm;
+  else if (LD == LD_UPD_SLOT && !upd) scl = (R)a.up.st[b].inv_norm;
   const R ks = k0sq * scl;
   if (tid < N) twl[tid] = tw0;
   auto put = [&](int k) {
@@ -550,7 +551,7 @@ void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t ld
     if constexpr (sizeof(T) == 8)
       if (tile_takes_dots(a, sizeof(T))) return plane(k_plane<T, INV, LD, ST, 7>, 7);
     return;
-  } else if constexpr (LD == LD_UPD_VX) {
+  } else if constexpr (LD == LD_UPD_VX || LD == LD_UPD_SLOT) {
     // only the FP32 128 x 128 square planes load with the update
     if constexpr (sizeof(T) == 8)
       if (tile_takes_update(a, sizeof(T))) return plane(k_plane<T, INV, LD, ST, 7>, 7);
@@ -587,6 +588,7 @@ template void launch_tile<float2, true, LD_PLAIN, ST_PLAIN>(const TileArgs&, int
 template void launch_tile<float2, true, LD_PLAIN, ST_AXPBY>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<float2, true, LD_PLAIN, ST_DOTS>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<float2, false, LD_UPD_VX, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
+template void launch_tile<float2, false, LD_UPD_SLOT, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<double2, false, LD_VX, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<double2, false, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);
 template void launch_tile<double2, true, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, int, size_t, hipStream_t);

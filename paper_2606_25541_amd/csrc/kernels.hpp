@@ -4,7 +4,7 @@
 
 namespace psfd {
 
-enum LoadOp { LD_PLAIN = 0, LD_VX = 1, LD_INJECT = 2, LD_VXE = 3, LD_INJECT_T = 4, LD_UPD_VX = 5 };
+enum LoadOp { LD_PLAIN = 0, LD_VX = 1, LD_INJECT = 2, LD_VXE = 3, LD_INJECT_T = 4, LD_UPD_VX = 5, LD_UPD_SLOT = 6 };
 
 struct GState;
 // The Givens step of the previous Arnoldi step, left to an apply kernel of
@@ -27,10 +27,11 @@ struct GivensTask {
 // plane, stores it, and leaves the plane's ||slot_j||^2 in part[b * planes + plane];
 // the block of plane 0 stores h and ||w||^2 before the update for the Givens step.
 // The vector enters the transform unscaled: the next kernel applies its scale.
-// j = 0 (the first step of a cycle): no update, slot 0 scaled on load by
-// S.inv_norm, as LD_VX does. j < 0 (instances at different steps): per instance
-// from its state; with a pending update (pend) the update of column S.j on slot
-// S.j + 1, else slot S.j scaled on load.
+// LD_UPD_VX: j >= 1, every instance at step j. LD_UPD_SLOT: per instance, j = 0
+// (the first step of a cycle: no update, slot 0 scaled on load by S.inv_norm, as
+// LD_VX does) or j < 0 (instances at different steps: from its state; with a
+// pending update (pend) the update of column S.j on slot S.j + 1, else slot S.j
+// scaled on load). Both run the same arithmetic for the same case.
 struct UpdateTask {
   const void* V;        // basis of instance 0; slot i of instance b at V + b bsv + i ldv
   long long ldv, bsv;
@@ -115,7 +116,7 @@ bool tile_is_plane(const TileArgs& a, size_t esz);
 // whether launch_tile can store with ST_DOTS for these arguments (FP32 128 x 128
 // planes, at most DotBlocks<float2> planes per instance)
 bool tile_takes_dots(const TileArgs& a, size_t esz);
-// whether launch_tile can load with LD_UPD_VX for these arguments (FP32 128 x 128 planes)
+// whether launch_tile can load with LD_UPD_VX / LD_UPD_SLOT for these arguments (FP32 128 x 128 planes)
 bool tile_takes_update(const TileArgs& a, size_t esz);
 template <class T>
 void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStream_t s);
