@@ -613,7 +613,7 @@ def main():
         oracle_study(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (no multi-GPU path)"}))
+        print(json.dumps({"error": "single-GPU implementation: --gpus must be 1 (there is no multi-GPU path)"}))
         sys.exit(2)
 
     import torch
