@@ -181,10 +181,10 @@ int psfd_bench_stage(psfd_plan* plan, int stage, const void* d_deps, const void*
  * (i <= j) and ||w||^2 of GMRES (Saad & Schultz; Sec. 3), pass 1 the update
  * w -= sum_i h_i v_i with the ||w||^2 partials, pass 2 the step's inverse
  * transverse FFT kernel that writes w (stage 2 of the operator apply, eq. (18)),
- * which on FP32 128 x 128 planes also forms the projections of pass 0 (then
+ * which on FP32 64 x 64 and 128 x 128 planes also forms the projections of pass 0 (then
  * no separate pass 0 runs in a step), pass 3 the forward transverse FFT kernel
  * of step j + 1 (stage 0, contrast from the first nz*ny*nx values of d_x),
- * which on FP32 128 x 128 planes in lock-step solves also does the update of
+ * which on FP32 64 x 64 and 128 x 128 planes in lock-step solves also does the update of
  * pass 1 for column j (then pass 1 runs only at the last column of a cycle).
  * A basis of j + 2 vectors of
  * `dtype`, each a copy of d_x (complex64 or complex128 [3][nz][ny][nx], device),

@@ -591,7 +591,7 @@ template <> float2* deps_of_mut<float2>(Group& g) { return g.deps32; }
 template <> double2* deps_of_mut<double2>(Group& g) { return g.deps64; }
 
 // Whether the inverse transverse kernel of an Arnoldi step also forms the
-// Gram-Schmidt projections of the vector it writes (FP32 128 x 128 square planes;
+// Gram-Schmidt projections of the vector it writes (FP32 64 x 64 and 128 x 128 square planes;
 // PSFD_FUSE_DOTS=0 keeps the separate projection pass, read per call).
 static bool fuse_dots(const Group& g, size_t esz) {
   const char* e = std::getenv("PSFD_FUSE_DOTS");
@@ -601,7 +601,7 @@ static bool fuse_dots(const Group& g, size_t esz) {
 }
 
 // Whether the forward transverse kernel of an Arnoldi step also does the
-// Gram-Schmidt update of the previous column (FP32 128 x 128 square planes, and
+// Gram-Schmidt update of the previous column (FP32 64 x 64 and 128 x 128 square planes, and
 // pencil blocks large enough to run the Givens task: at least GIVENS_THREADS
 // threads, i.e. padded z lengths of 64 and more; with the projections in the
 // inverse kernel, which also marks the update pending; PSFD_FUSE_UPDATE=0 keeps

@@ -531,9 +531,9 @@ static int plane_ln(const TileArgs& a, size_t esz) {
   return 0;
 }
 bool tile_is_plane(const TileArgs& a, size_t esz) { return plane_ln(a, esz) != 0; }
-bool tile_takes_update(const TileArgs& a, size_t esz) { return esz == 8 && plane_ln(a, esz) == 7; }
+bool tile_takes_update(const TileArgs& a, size_t esz) { return esz == 8 && plane_ln(a, esz) != 0; }
 bool tile_takes_dots(const TileArgs& a, size_t esz) {
-  return esz == 8 && plane_ln(a, esz) == 7 && 3 * a.nz <= DotBlocks<float2>::value;
+  return esz == 8 && plane_ln(a, esz) != 0 && 3 * a.nz <= DotBlocks<float2>::value;
 }
 
 template <class T, bool INV, int LD, int ST>
@@ -547,14 +547,22 @@ void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t ld
     hipLaunchKernelGGL(kern, g2, dim3(plane_threads(ln)), l, s, a);
   };
   if constexpr (ST == ST_DOTS) {
-    // only the FP32 128 x 128 square planes store with the projections
-    if constexpr (sizeof(T) == 8)
-      if (tile_takes_dots(a, sizeof(T))) return plane(k_plane<T, INV, LD, ST, 7>, 7);
+    // only the FP32 square planes (64 x 64, 128 x 128) store with the projections
+    if constexpr (sizeof(T) == 8) {
+      if (tile_takes_dots(a, sizeof(T))) {
+        if (plane_ln(a, sizeof(T)) == 6) return plane(k_plane<T, INV, LD, ST, 6>, 6);
+        return plane(k_plane<T, INV, LD, ST, 7>, 7);
+      }
+    }
     return;
   } else if constexpr (LD == LD_UPD_VX || LD == LD_UPD_SLOT) {
-    // only the FP32 128 x 128 square planes load with the update
-    if constexpr (sizeof(T) == 8)
-      if (tile_takes_update(a, sizeof(T))) return plane(k_plane<T, INV, LD, ST, 7>, 7);
+    // only the FP32 square planes (64 x 64, 128 x 128) load with the update
+    if constexpr (sizeof(T) == 8) {
+      if (tile_takes_update(a, sizeof(T))) {
+        if (plane_ln(a, sizeof(T)) == 6) return plane(k_plane<T, INV, LD, ST, 6>, 6);
+        return plane(k_plane<T, INV, LD, ST, 7>, 7);
+      }
+    }
     return;
   } else if constexpr (LD == LD_PLAIN || LD == LD_VX) {
     const int ln = plane_ln(a, sizeof(T));

@@ -113,10 +113,11 @@ void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t ld
 // whether launch_tile runs the square-plane kernel for these arguments (the
 // kernel that can carry a GivensTask)
 bool tile_is_plane(const TileArgs& a, size_t esz);
-// whether launch_tile can store with ST_DOTS for these arguments (FP32 128 x 128
-// planes, at most DotBlocks<float2> planes per instance)
+// whether launch_tile can store with ST_DOTS for these arguments (FP32 64 x 64 and
+// 128 x 128 planes, at most DotBlocks<float2> planes per instance)
 bool tile_takes_dots(const TileArgs& a, size_t esz);
-// whether launch_tile can load with LD_UPD_VX / LD_UPD_SLOT for these arguments (FP32 128 x 128 planes)
+// whether launch_tile can load with LD_UPD_VX / LD_UPD_SLOT for these arguments (FP32 64 x 64 and
+// 128 x 128 planes)
 bool tile_takes_update(const TileArgs& a, size_t esz);
 template <class T>
 void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStream_t s);

@@ -64,8 +64,9 @@ def test_batch_equals_single():
         assert inf["iters"] == i1["iters"]
 
 
-def test_batch_equals_single_128_planes():
-    """FP32 128 x 128 planes, 32 of them per component (padded z length 64, pencil
+@pytest.mark.parametrize("n", [64, 128])
+def test_batch_equals_single_128_planes(n):
+    """FP32 square planes (64 x 64 and 128 x 128), 32 per component (padded z length 64, pencil
     blocks large enough for the Givens task): the lock-step batch runs the
     Gram-Schmidt update in the forward plane kernel, the projections in the
     inverse one and the last column's Givens step from the projections. Three
@@ -77,13 +78,13 @@ def test_batch_equals_single_128_planes():
     cs = []
     for i in range(3):
         th, ph = angles[(11 * i + 3) % len(angles)]
-        p = prob(128, 32, th, ph, i % 2)
-        de = clips.manhattan(128, 128, 32, p.lx_nm, p.ly_nm, seed=300 + i)
+        p = prob(n, 32, th, ph, i % 2)
+        de = clips.manhattan(n, n, 32, p.lx_nm, p.ly_nm, seed=300 + i)
         if i == 2:
             de = de * 0.25  # weaker contrast: converges in fewer cycles
         cs.append((p, de))
     opts = dict(rtol=1e-9, precision="mixed", restart=8)
-    say("batch of 3 at 128x128x32")
+    say("batch of 3 at %dx%dx32" % (n, n))
     em, od, infos = api.psfd_solve_batch([c[0] for c in cs], [torch.from_numpy(c[1]).to(dev) for c in cs], **opts)
     torch.cuda.synchronize()
     iters = []
@@ -100,8 +101,9 @@ def test_batch_equals_single_128_planes():
     assert min(iters) < max(iters)
 
 
-def test_server_matches_alone_128_planes():
-    """128 x 128 x 32, mixed: the lone (lock-step) solve and the server's slots
+@pytest.mark.parametrize("n", [64, 128])
+def test_server_matches_alone_128_planes(n):
+    """n x n x 32 (n = 64, 128), mixed: the lone (lock-step) solve and the server's slots
     (each at its own step, with a per-slot pending-update flag) run the same
     fused kernels: the Gram-Schmidt update in the forward plane kernel, the
     projections in the inverse one, the Givens step in the pencil and the last
@@ -112,8 +114,8 @@ def test_server_matches_alone_128_planes():
     opts = dict(rtol=1e-10, precision="mixed", restart=8)
     reqs = []
     for i, (th, ph, pol) in enumerate(((6.0, 0.0, 0), (7.5, 40.0, 1))):
-        p = prob(128, 32, th, ph, pol)
-        de = clips.manhattan(128, 128, 32, p.lx_nm, p.ly_nm, seed=401 + i)
+        p = prob(n, 32, th, ph, pol)
+        de = clips.manhattan(n, n, 32, p.lx_nm, p.ly_nm, seed=401 + i)
         reqs.append((p, torch.from_numpy(de).to(dev)))
     srv = api.Server(hbm_budget=8 << 30, max_slots=2, **opts)
     outs, tickets = [], []

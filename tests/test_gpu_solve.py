@@ -124,8 +124,9 @@ def test_solve_128_planes_projections_in_plane_kernel(jh, monkeypatch):
     assert rel(em2.cpu().numpy(), ref["emask"]) < 1e-8
 
 
-def test_update_in_forward_plane_kernel_matches_separate_pass(monkeypatch):
-    """128 x 128 x 32, mixed, lock-step: the Gram-Schmidt update in the forward
+@pytest.mark.parametrize("n", [64, 128])
+def test_update_in_forward_plane_kernel_matches_separate_pass(n, monkeypatch):
+    """n x n x 32 (n = 64, 128), mixed, lock-step: the Gram-Schmidt update in the forward
     plane kernel (pencil with the Givens step, last column from the projections)
     against the separate update pass (PSFD_FUSE_UPDATE=0, the path the oracle
     parity cases run): the same solution to the solve tolerance, within one
@@ -133,10 +134,11 @@ def test_update_in_forward_plane_kernel_matches_separate_pass(monkeypatch):
     from paper_2606_25541_amd import api
     dev = device()
     layers, es = clips.mo_si_stack(40)
-    p = clips.Problem(nx=128, ny=128, nz=32, lx_nm=256.0, ly_nm=256.0, t_nm=60.0, theta_deg=6.0,
+    L = 2.0 * n
+    p = clips.Problem(nx=n, ny=n, nz=32, lx_nm=L, ly_nm=L, t_nm=60.0, theta_deg=6.0,
                       phi_deg=15.0, pol=1, layers=layers, eps_sub=es)
-    d = torch.from_numpy(clips.contact_holes(128, 128, 32, 256.0, 256.0, 6, seed=77)).to(dev)
-    say("solve 128x128x32 mixed, update fused vs separate")
+    d = torch.from_numpy(clips.contact_holes(n, n, 32, L, L, 6, seed=77)).to(dev)
+    say("solve %dx%dx32 mixed, update fused vs separate" % (n, n))
     plan = api.Plan(p, rtol=1e-10, precision="mixed", restart=8)
     e1, o1, i1 = plan.psfd_solve(d)
     e1b, o1b, i1b = plan.psfd_solve(d)
