@@ -12,6 +12,10 @@ outer fixed point eqs. (8)-(9), Lippmann-Schwinger eqs. (11)-(12), windowed
 dyadic Green's function eqs. (13)-(17), discrete system eq. (18)) plus the
 readings listed in the design notes for the points where the paper is silent.
 
+``oracle.isolated`` holds the spherically windowed dyadic kernel of the
+isolated-domain mode (eqs. (15)-(17) with the corrected h and A(0)), pinned by a
+radial quadrature of the windowed kernel; it is not on the periodic hot path.
+
 Parity status: every function is pinned by the ``-m "not gpu"`` tests
 (quadrature of the kernel, independent transfer-matrix code, dense direct
 solves, reciprocity, uniform-film convergence to the layered reflection, Born

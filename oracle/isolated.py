@@ -1,0 +1,83 @@
+"""Spherically windowed dyadic Green's function of the isolated-domain mode
+(test infrastructure only, see the package doc).
+
+The isolated-domain form of the method convolves with the free-space dyadic
+Green's function truncated to a ball of radius R, whose transform is analytic
+(the windowed kernel section, eqs. (13)-(17)):
+
+    F[G_R](k) = A(k) I + B(k) k^ k^,
+    A(k) = F[g_R](k) + h(k; R),   B(k) = -F[g_R](k) - 3 h(k; R) - 1 / k_bg^2   (k > 0),
+    A(0) = F[g_R](0) + h(0; R),   B(0) = 0,
+
+with g(r) = exp(i k_bg r) / (4 pi r), the windowed scalar transform F[g_R] of
+eq. (17), and h(k; R) = 4 pi R^2 g'(R) j1(kR) / (k_bg^2 kR). The printed h has
+R where R^2 belongs, and the printed A(0) lacks the factor 4 pi; both readings
+are pinned by a radial quadrature of the windowed kernel (tests). With the
+corrections, A(0) is the k -> 0 limit of A(k), and B(k) -> 0 there.
+
+Only the kernel is here: the isolated-domain apply (padding by 2 on all
+three axes, the 4x-oversampled kernel precompute) is not part of the hot path.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _j1_over_x(x):
+    """j1(x) / x, with its series below |x| = 1e-3 (the limit at 0 is 1/3)."""
+    x = np.asarray(x, dtype=float)
+    small = np.abs(x) < 1e-3
+    xs = np.where(small, 1.0, x)
+    val = (np.sin(xs) / xs - np.cos(xs)) / (xs * xs)
+    ser = 1.0 / 3.0 - x * x / 30.0 + x ** 4 / 840.0
+    return np.where(small, ser, val)
+
+
+def g_prime_times_4pi_r2(kbg: complex, R: float) -> complex:
+    """4 pi R^2 g'(R) = exp(i k_bg R) (i k_bg R - 1) for g = exp(i k_bg r) / (4 pi r)."""
+    return np.exp(1j * kbg * R) * (1j * kbg * R - 1.0)
+
+
+def window_sphere_scalar(k, kbg: complex, R: float):
+    """F[g_R](k) = 4 pi int_0^R g(r) j0(kr) r^2 dr in closed form (eq. (17)).
+
+    k = 0 and the removable point k^2 = k_bg^2 take their limits (the latter
+    only arises for a lossless background)."""
+    k = np.asarray(k, dtype=float)
+    e = np.exp(1j * kbg * R)
+    kk = np.where(k == 0.0, 1.0, k)
+    den = kbg * kbg - kk * kk
+    near = np.abs(den) < 1e-10 * np.abs(kbg * kbg)
+    den = np.where(near, 1.0, den)
+    gen = (e * (np.cos(kk * R) - 1j * kbg / kk * np.sin(kk * R)) - 1.0) / den
+    at0 = (e * (1.0 - 1j * R * kbg) - 1.0) / (kbg * kbg)
+    atkb = 1j * R / (2.0 * kbg) - 1j / (2.0 * kbg * kbg) * e * np.sin(kbg * R)
+    return np.where(k == 0.0, at0, np.where(near, atkb, gen))
+
+
+def window_sphere_h(k, kbg: complex, R: float):
+    """h(k; R) = 4 pi R^2 g'(R) j1(kR) / (k_bg^2 kR) (the corrected reading of the
+    auxiliary function of the windowed kernel)."""
+    k = np.asarray(k, dtype=float)
+    return g_prime_times_4pi_r2(kbg, R) * _j1_over_x(k * R) / (kbg * kbg)
+
+
+def window_sphere_AB(k, kbg: complex, R: float):
+    """A(k), B(k) of F[G_R](k) = A I + B k^ k^ (k >= 0)."""
+    k = np.asarray(k, dtype=float)
+    F = window_sphere_scalar(k, kbg, R)
+    h = window_sphere_h(k, kbg, R)
+    A = F + h
+    B = np.where(k == 0.0, 0.0 + 0.0j, -F - 3.0 * h - 1.0 / (kbg * kbg))
+    return A, B
+
+
+def gtilde_isolated(kx, ky, kz, kbg: complex, R: float) -> np.ndarray:
+    """F[G_R] at wavevectors (kx, ky, kz): array [..., 3, 3] (symmetric, even in k)."""
+    kx, ky, kz = np.broadcast_arrays(np.asarray(kx, float), np.asarray(ky, float), np.asarray(kz, float))
+    k = np.sqrt(kx * kx + ky * ky + kz * kz)
+    A, B = window_sphere_AB(k, kbg, R)
+    ks = np.where(k == 0.0, 1.0, k)
+    kh = np.stack([kx / ks, ky / ks, kz / ks], axis=-1)
+    out = A[..., None, None] * np.eye(3) + B[..., None, None] * kh[..., :, None] * kh[..., None, :]
+    return out

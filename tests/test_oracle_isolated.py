@@ -1,0 +1,126 @@
+"""Pins of the spherically windowed dyadic kernel (isolated-domain mode, eqs. (15)-(17)).
+
+The closed forms are checked against an independent derivation by radial
+quadrature. With g = exp(i k r) / (4 pi r), the truncated dyadic kernel is, as
+a distribution on the ball,
+
+    G_R = (2/3) g I - delta(r) I / (3 k^2) + (g'' - g'/r) (r^ r^ - I/3) / k^2,
+
+whose transform, from the angular integrals of 1 and of r^ r^ - I/3 (the j0 and
+j2 terms of the plane-wave expansion), is A I + B k^ k^ with
+
+    S0 = 4 pi int_0^R g j0(kr) r^2 dr,   T2 = (4 pi / k^2) int_0^R (g'' - g'/r) j2(kr) r^2 dr,
+    A = (2/3) S0 - 1 / (3 k^2) + T2 / 3,   B = -T2.
+
+The printed h(k; R) (R in place of R^2) and the printed A(0) (no 4 pi) fail the
+same check, which is what the readings of the windowed kernel rest on.
+"""
+import warnings
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+from oracle import isolated as I
+
+K0 = 2 * np.pi / 13.5
+
+
+def cquad(f, a, b):
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", integrate.IntegrationWarning)
+        re = integrate.quad(lambda r: f(r).real, a, b, limit=400, epsabs=1e-14, epsrel=1e-12)[0]
+        im = integrate.quad(lambda r: f(r).imag, a, b, limit=400, epsabs=1e-14, epsrel=1e-12)[0]
+    return re + 1j * im
+
+
+def by_quadrature(k, kbg, R):
+    """(A, B, S0) from the radial integrals of the distributional decomposition."""
+    S0 = cquad(lambda r: np.exp(1j * kbg * r) * r * special.spherical_jn(0, k * r), 0.0, R)
+    # (g'' - g'/r) r^2 4 pi = exp(i k r) (3 - 3 i k r - k^2 r^2) / r
+    T2 = cquad(lambda r: np.exp(1j * kbg * r) * (3 - 3j * kbg * r - kbg ** 2 * r ** 2)
+               * special.spherical_jn(2, k * r) / r, 0.0, R) / kbg ** 2
+    return 2.0 / 3.0 * S0 - 1.0 / (3.0 * kbg ** 2) + T2 / 3.0, -T2, S0
+
+
+CASES = [(K0 * (1 + 0.02j), 40.0), (K0 * (1 + 0.05j), 25.0), (0.9 * K0 * (1 + 0.01j), 60.0)]
+KS = [0.02, 0.1, 0.3, K0, 0.9, 2.0, 5.0]
+
+
+@pytest.mark.parametrize("kbg,R", CASES)
+def test_scalar_window_matches_quadrature(kbg, R):
+    for k in KS:
+        F = I.window_sphere_scalar(k, kbg, R)
+        _, _, S0 = by_quadrature(k, kbg, R)
+        assert abs(F - S0) <= 1e-9 * abs(S0), (k, F, S0)
+    # k = 0: 4 pi int_0^R g r^2 dr
+    S00 = cquad(lambda r: np.exp(1j * kbg * r) * r, 0.0, R)
+    assert abs(I.window_sphere_scalar(0.0, kbg, R) - S00) <= 1e-9 * abs(S00)
+
+
+@pytest.mark.parametrize("kbg,R", CASES)
+def test_dyadic_window_matches_quadrature(kbg, R):
+    for k in KS:
+        A, B = I.window_sphere_AB(k, kbg, R)
+        Aq, Bq, _ = by_quadrature(k, kbg, R)
+        assert abs(A - Aq) <= 1e-9 * abs(Aq), (k, A, Aq)
+        assert abs(B - Bq) <= 1e-9 * abs(Bq), (k, B, Bq)
+
+
+@pytest.mark.parametrize("kbg,R", CASES)
+def test_limits_at_k0(kbg, R):
+    """A is continuous at k = 0 (with the 4 pi of the corrected A(0)) and B -> 0 as k^2."""
+    A0, B0 = I.window_sphere_AB(0.0, kbg, R)
+    assert B0 == 0
+    for k in (1e-4 / R, 1e-3 / R, 1e-2 / R):
+        A, B = I.window_sphere_AB(k, kbg, R)
+        assert abs(A - A0) <= 1e-4 * abs(A0)
+        assert abs(B) <= 0.2 * (k * R) ** 2 * abs(A0)
+    # the quadrature at k = 0 (j2 vanishes: B = 0, A = (2/3) S0 - 1/(3 k^2))
+    S00 = cquad(lambda r: np.exp(1j * kbg * r) * r, 0.0, R)
+    assert abs(A0 - (2.0 / 3.0 * S00 - 1.0 / (3.0 * kbg ** 2))) <= 1e-9 * abs(A0)
+
+
+def test_lossless_resonance_limit():
+    """For a real k_bg the scalar transform has a removable point at k = k_bg."""
+    kbg, R = K0, 30.0
+    F0 = I.window_sphere_scalar(kbg, kbg, R)
+    for d in (1e-5, -1e-5, 1e-4):
+        assert abs(I.window_sphere_scalar(kbg * (1 + d), kbg, R) - F0) <= 5e-3 * abs(F0) * abs(d) / 1e-5
+    _, _, S0 = by_quadrature(kbg, kbg, R)
+    assert abs(F0 - S0) <= 1e-9 * abs(S0)
+
+
+def test_printed_forms_fail_quadrature():
+    """The printed h (R instead of R^2) and the printed A(0) (no 4 pi) disagree with the kernel."""
+    kbg, R, k = K0 * (1 + 0.02j), 40.0, 0.3
+    Aq, Bq, _ = by_quadrature(k, kbg, R)
+    F = I.window_sphere_scalar(k, kbg, R)
+    h_printed = I.window_sphere_h(k, kbg, R) / R  # 4 pi R g'(R) j1(kR) / (k^2 kR)
+    assert abs((F + h_printed) - Aq) > 1e-2 * abs(Aq)
+    assert abs((-F - 3 * h_printed - 1 / kbg ** 2) - Bq) > 1e-2 * abs(Bq)
+    A0, _ = I.window_sphere_AB(0.0, kbg, R)
+    A0_printed = I.window_sphere_scalar(0.0, kbg, R) + R ** 2 * (
+        I.g_prime_times_4pi_r2(kbg, R) / (4 * np.pi * R ** 2)) / (3 * kbg ** 2)
+    assert abs(A0_printed - A0) > 1e-2 * abs(A0)
+
+
+def test_dyadic_structure():
+    """F[G_R] is symmetric and even in k, k^ is an eigenvector (A + B), the transverse plane A."""
+    kbg, R = K0 * (1 + 0.02j), 40.0
+    rng = np.random.default_rng(9)
+    kv = rng.normal(size=(20, 3)) * 0.4
+    G = I.gtilde_isolated(kv[:, 0], kv[:, 1], kv[:, 2], kbg, R)
+    Gm = I.gtilde_isolated(-kv[:, 0], -kv[:, 1], -kv[:, 2], kbg, R)
+    assert np.allclose(G, np.swapaxes(G, -1, -2), rtol=0, atol=1e-14)
+    assert np.allclose(G, Gm, rtol=0, atol=1e-14)
+    k = np.linalg.norm(kv, axis=1)
+    A, B = I.window_sphere_AB(k, kbg, R)
+    kh = kv / k[:, None]
+    assert np.allclose(np.einsum("nij,nj->ni", G, kh), (A + B)[:, None] * kh, atol=1e-12)
+    t = np.cross(kh, np.array([0.3, -0.2, 0.9]))
+    t /= np.linalg.norm(t, axis=1)[:, None]
+    assert np.allclose(np.einsum("nij,nj->ni", G, t), A[:, None] * t, atol=1e-12)
+    # k = 0: A(0) I
+    G0 = I.gtilde_isolated(0.0, 0.0, 0.0, kbg, R)
+    assert np.allclose(G0, I.window_sphere_AB(0.0, kbg, R)[0] * np.eye(3), atol=1e-14)
