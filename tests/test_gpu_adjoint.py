@@ -74,3 +74,29 @@ def test_adjoint_finite_differences_and_autograd():
             an = g[k, j, i].real if part == 1.0 else g[k, j, i].imag
             say("  fd", fd, "adjoint", an)
             assert abs(fd - an) <= 1e-4 * abs(fd) + 1e-10
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_adjoint_fused_krylov_kernels_match_separate_passes(n, monkeypatch):
+    """n x n x 32 (n = 64, 128), mixed: the forward and the transposed solve of
+    the adjoint run the Gram-Schmidt projections and update inside the transform
+    kernels (the pencil carrying the Givens step of the transposed operator
+    too); the gradient and J agree with the separate passes
+    (PSFD_FUSE_DOTS=0, PSFD_FUSE_UPDATE=0) to the solve tolerance."""
+    from paper_2606_25541_amd import api
+    dev = device()
+    nz = 32
+    p = problem(n, n, nz, phi=20.0)
+    de, _ = clips.smooth_density_eps(n, n, nz, p.lx_nm, p.ly_nm, p.t_nm, seed=11, sigma_xy_nm=4.0, sigma_z_nm=3.0)
+    d = torch.from_numpy(de).to(dev)
+    plan = api.Plan(p, rtol=1e-10, precision="mixed", restart=8)
+    say("adjoint %dx%dx%d fused vs separate" % (n, n, nz))
+    g1, J1, f1, a1 = plan.psfd_solve_adjoint(d, ORDERS)
+    monkeypatch.setenv("PSFD_FUSE_DOTS", "0")
+    monkeypatch.setenv("PSFD_FUSE_UPDATE", "0")
+    g2, J2, f2, a2 = plan.psfd_solve_adjoint(d, ORDERS)
+    say("  fused", f1, a1, "separate", f2, a2)
+    assert f1["status"] == 0 and a1["status"] == 0
+    assert abs(f1["iters"] - f2["iters"]) <= 8 and abs(a1["iters"] - a2["iters"]) <= 8
+    assert abs(J1 - J2) <= 1e-8 * abs(J2)
+    assert rel(g1.cpu().numpy(), g2.cpu().numpy()) < 1e-7
