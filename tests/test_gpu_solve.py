@@ -152,6 +152,35 @@ def test_update_in_forward_plane_kernel_matches_separate_pass(n, monkeypatch):
     assert np.max(np.abs(o1.cpu().numpy() - o2.cpu().numpy())) < 1e-9
 
 
+def test_fused_krylov_64_planes_matches_oracle_monolithic():
+    """64 x 64 x 32, mixed, lock-step with the projections and the update inside
+    the transform kernels, against the oracle: the oracle's GMRES on its
+    monolithic operator (I - M V) u = e_bg (the system the GPU solves), the mask
+    field x = K V u and the reflected orders from u. Both sides stop at a
+    residual of 1e-10 or below, so the fields agree to the conditioning times
+    that: <= 1e-7 relative, orders <= 1e-8."""
+    from paper_2606_25541_amd import api
+    dev = device()
+    layers, es = clips.mo_si_stack(40)
+    n = 64
+    p = clips.Problem(nx=n, ny=n, nz=32, lx_nm=2.0 * n, ly_nm=2.0 * n, t_nm=60.0, theta_deg=6.0,
+                      phi_deg=15.0, pol=1, layers=layers, eps_sub=es)
+    de = clips.contact_holes(n, n, 32, 2.0 * n, 2.0 * n, 6, seed=77)
+    plan = api.Plan(p, rtol=1e-10, precision="mixed", restart=8)
+    em, orders, info = plan.psfd_solve(torch.from_numpy(de).to(dev))
+    say("  gpu", info, "; oracle monolithic GMRES next")
+    assert info["status"] == 0
+    S = O.Setup(p)
+    u, oi = O.gmres(lambda v: O.apply_monolithic(S, de, v), O.background_field(S), None, 1e-10, 30, 4000)
+    say("  oracle", oi["iters"], oi["rel_residual"])
+    V = O.potential(S, de)
+    x = O.conv_K(S, V[None] * u)
+    a_up = O.reflect(S, O.incident_down(S) + O.read_down(S, V[None] * u))
+    ords = O.reflected_orders(S, de, u, a_up)
+    assert rel(em.cpu().numpy(), x) < 1e-7
+    assert np.max(np.abs(orders.cpu().numpy() - ords)) < 1e-8
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_cancellation_restarts_converge(prec, monkeypatch):
     """A Gram-Schmidt update that cancels below the threshold ends the Arnoldi
