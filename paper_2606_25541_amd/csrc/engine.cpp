@@ -836,10 +836,10 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
     // the restart's residual: b - A x (FP64) where tres is set, the previous
     // cycle's basis residual (left in v0 and its norm partials) where rres is
     apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, refl, g.tres, s);  // A x
-    krylov_residual<T>(g.b, g.r, (T*)g.basis, n3, n3, bsv, g.dpart, g.n2, g.tres, B, s);
-    krylov_sum_norm(g.lpart, g.n2, g.rres, B, s);
-    krylov_cycle_start(g.st, g.n2, g.abs_target, eta, g.m, cancel_threshold(), every, g.mask, g.tres, g.rres, g.run,
-                       g.cyc, B, s);
+    krylov_residual_parts<T>(g.b, g.r, (T*)g.basis, n3, n3, bsv, g.dpart, g.tres, B, s);
+    // ||r||^2 from the partials of b - A x or of the basis residual, summed in the cycle start
+    krylov_cycle_start_sum(g.st, g.n2, g.dpart, g.lpart, g.abs_target, eta, g.m, cancel_threshold(), every, g.mask,
+                           g.tres, g.rres, g.run, g.cyc, B, s);
     const int slot = cyc % FLAG_SLOTS;
     HIPCHK(hipMemcpyAsync(g.h_flags + slot * B, g.mask, sizeof(int) * B, hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(g.flag_ev[slot], s));

@@ -476,10 +476,20 @@ void krylov_solve_init(GState* st, const double* bnorm2, const double* rtol, dou
   hipLaunchKernelGGL(k_solve_init, dim3(nbatch), dim3(64), 0, s, st, bnorm2, rtol, abs_target, max_iters, act);
 }
 
-__global__ void k_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                              double cancel_thr, int every, int* act, int* tres, int* rres, int* run, int* cyc) {
-  const int b = blockIdx.x;
-  if (threadIdx.x != 0) return;
+// sum of the nblk partials of instance b, fixed order (thread t adds partials
+// t, t + KB, ..., then a fixed block tree); every thread of a KB-thread block
+// calls it and gets the total
+PSFD_D double sum_partials(const double* part, int nblk, int b) {
+  __shared__ double2 sm[KB / 64];
+  double t = 0;
+  for (int k = threadIdx.x; k < nblk; k += KB) t += part[(long long)b * nblk + k];
+  double2 acc[1] = {make_double2(t, 0.0)};
+  block_sum<1>(acc, 1, sm);
+  return sm[0].x;
+}
+
+PSFD_D void cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
+                        double cancel_thr, int every, int* act, int* tres, int* rres, int* run, int* cyc, int b) {
   cyc[b] = 0;
   run[b] = 0;
   const bool was_true = tres[b] != 0;
@@ -523,12 +533,43 @@ __global__ void k_cycle_start(GState* st, const double* rnorm2, const double* ab
   run[b] = 1;
 }
 
+__global__ void k_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
+                              double cancel_thr, int every, int* act, int* tres, int* rres, int* run, int* cyc) {
+  if (threadIdx.x == 0) cycle_start(st, rnorm2, abs_target, eta, m, cancel_thr, every, act, tres, rres, run, cyc,
+                                    blockIdx.x);
+}
+
+// the same, with ||r||^2 summed here from the partials of b - A x (tpart,
+// RED_BLOCKS per instance) or of the basis residual (lpart, LIN_BLOCKS), in the
+// order of k_sum_part, and stored to rnorm2
+__global__ void __launch_bounds__(KB) k_cycle_start_sum(GState* st, double* rnorm2, const double* tpart,
+                                                        const double* lpart, const double* abs_target, double eta,
+                                                        int m, double cancel_thr, int every, int* act, int* tres,
+                                                        int* rres, int* run, int* cyc) {
+  const int b = blockIdx.x;
+  const int t = tres[b], r = rres[b];
+  if (t || r) {
+    const double n2 = t ? sum_partials(tpart, RED_BLOCKS, b) : sum_partials(lpart, LIN_BLOCKS, b);
+    if (threadIdx.x == 0) rnorm2[b] = n2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) cycle_start(st, rnorm2, abs_target, eta, m, cancel_thr, every, act, tres, rres, run, cyc, b);
+}
+
 void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
                         double cancel_thr, int every, int* act, int* tres, int* rres, int* run, int* cyc,
                         int nbatch, hipStream_t s) {
   hipLaunchKernelGGL(k_cycle_start, dim3(nbatch), dim3(64), 0, s, st, rnorm2, abs_target, eta, m, cancel_thr, every,
                      act, tres, rres, run, cyc);
 }
+
+void krylov_cycle_start_sum(GState* st, double* rnorm2, const double* tpart, const double* lpart,
+                            const double* abs_target, double eta, int m, double cancel_thr, int every, int* act,
+                            int* tres, int* rres, int* run, int* cyc, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_start_sum, dim3(nbatch), dim3(KB), 0, s, st, rnorm2, tpart, lpart, abs_target, eta, m,
+                     cancel_thr, every, act, tres, rres, run, cyc);
+}
+
 
 
 void krylov_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
@@ -574,17 +615,11 @@ __global__ void __launch_bounds__(KB) k_norm2(const T* x, long long n, long long
   if (threadIdx.x == 0) part[(long long)b * gridDim.x + blockIdx.x] = sm[0].x;
 }
 
-// sum of the nblk partials of instance b, fixed order (thread t adds partials
-// t, t + KB, ..., then a fixed block tree)
 __global__ void __launch_bounds__(KB) k_sum_part(const double* part, int nblk, double* out, const int* mask) {
-  __shared__ double2 sm[KB / 64];
   const int b = blockIdx.x;
   if (mask && !mask[b]) return;
-  double t = 0;
-  for (int k = threadIdx.x; k < nblk; k += KB) t += part[(long long)b * nblk + k];
-  double2 acc[1] = {make_double2(t, 0.0)};
-  block_sum<1>(acc, 1, sm);
-  if (threadIdx.x == 0) out[b] = sm[0].x;
+  const double t = sum_partials(part, nblk, b);
+  if (threadIdx.x == 0) out[b] = t;
 }
 
 void krylov_sum_norm(const double* part, double* n2, const int* mask, int nbatch, hipStream_t s) {
@@ -670,6 +705,12 @@ void krylov_residual(const double2* bv, const double2* ax, T* v0, long long n, l
   hipLaunchKernelGGL(k_sum_part, dim3(nbatch), dim3(KB), 0, s, (const double*)part, RED_BLOCKS, n2, mask);
 }
 
+template <class T>
+void krylov_residual_parts(const double2* bv, const double2* ax, T* v0, long long n, long long bs, long long bsv,
+                           double* part, const int* mask, int nbatch, hipStream_t s) {
+  hipLaunchKernelGGL((k_resid<T>), dim3(RED_BLOCKS, nbatch), dim3(KB), 0, s, bv, ax, v0, n, bs, bsv, part, mask);
+}
+
 // ---- instantiations ----------------------------------------------------------
 #define INST_T(T)                                                                                       \
   template void krylov_dots<T>(const T*, long long, long long, long long, GState*, const int*,           \
@@ -680,6 +721,8 @@ void krylov_residual(const double2* bv, const double2* ax, T* v0, long long n, l
                              hipStream_t);                                                              \
   template void krylov_residual<T>(const double2*, const double2*, T*, long long, long long, long long,  \
                                    double*, double*, const int*, int, hipStream_t);                     \
+  template void krylov_residual_parts<T>(const double2*, const double2*, T*, long long, long long,      \
+                                         long long, double*, const int*, int, hipStream_t);             \
   template void vec_diff2<T>(const T*, const T*, long long, long long, double*, double*, int, hipStream_t);
 INST_T(float2)
 INST_T(double2)

@@ -120,6 +120,10 @@ void krylov_solve_init(GState* st, const double* bnorm2, const double* rtol, dou
 template <class T>
 void krylov_residual(const double2* b, const double2* ax, T* v0, long long n, long long bs, long long bsv,
                      double* part, double* n2, const int* mask, int nbatch, hipStream_t s);
+// the same without the sum of the partials (krylov_cycle_start_sum sums them)
+template <class T>
+void krylov_residual_parts(const double2* b, const double2* ax, T* v0, long long n, long long bs, long long bsv,
+                           double* part, const int* mask, int nbatch, hipStream_t s);
 // krylov_cycle_start, at a restart of an active instance with ||r||^2 in
 // rnorm2[b]. The restart's residual is b - A x (FP64; tres[b] set) or the
 // previous cycle's GMRES residual in its basis (rres[b] set).
@@ -138,6 +142,13 @@ void krylov_residual(const double2* b, const double2* ax, T* v0, long long n, lo
 void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
                         double cancel_thr, int every, int* act, int* tres, int* rres, int* run, int* cyc,
                         int nbatch, hipStream_t s);
+// krylov_cycle_start with ||r||^2 summed in the same launch, in the order of
+// krylov_residual / krylov_sum_norm: from the b - A x partials in tpart
+// (RED_BLOCKS per instance) where tres is set, from the basis-residual partials
+// in lpart (LIN_BLOCKS) where rres is; the sum is also stored to rnorm2
+void krylov_cycle_start_sum(GState* st, double* rnorm2, const double* tpart, const double* lpart,
+                            const double* abs_target, double eta, int m, double cancel_thr, int every, int* act,
+                            int* tres, int* rres, int* run, int* cyc, int nbatch, hipStream_t s);
 // start a cycle from rnorm2[b] = ||r_b||^2 (v0 = r unnormalised, as left by
 // krylov_residual; inv_norm = 1 / ||r||): g = (||r||, 0, ...), j = 0,
 // target = max(abs_target[b], eta ||r||); run[b] = mask[b] && ||r|| > abs_target[b]
