@@ -14,7 +14,8 @@ readings listed in the design notes for the points where the paper is silent.
 
 ``oracle.isolated`` holds the spherically windowed dyadic kernel of the
 isolated-domain mode (eqs. (15)-(17) with the corrected h and A(0)), pinned by a
-radial quadrature of the windowed kernel; it is not on the periodic hot path.
+radial quadrature of the windowed kernel, and the isolated apply with the
+4x-oversampled kernel precompute; it is not on the periodic hot path.
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests
 (quadrature of the kernel, independent transfer-matrix code, dense direct

@@ -15,8 +15,9 @@ R where R^2 belongs, and the printed A(0) lacks the factor 4 pi; both readings
 are pinned by a radial quadrature of the windowed kernel (tests). With the
 corrections, A(0) is the k -> 0 limit of A(k), and B(k) -> 0 there.
 
-Only the kernel is here: the isolated-domain apply (padding by 2 on all
-three axes, the 4x-oversampled kernel precompute) is not part of the hot path.
+Below the kernel: its real-space samples by the 4x-oversampled precompute and
+the isolated-domain apply with padding by 2 on all three axes. None of this is
+on the periodic hot path.
 """
 from __future__ import annotations
 
@@ -81,3 +82,57 @@ def gtilde_isolated(kx, ky, kz, kbg: complex, R: float) -> np.ndarray:
     kh = np.stack([kx / ks, ky / ks, kz / ks], axis=-1)
     out = A[..., None, None] * np.eye(3) + B[..., None, None] * kh[..., :, None] * kh[..., None, :]
     return out
+
+
+def kernel_samples(shape, spacing, kbg: complex, R: float, over: int = 4) -> np.ndarray:
+    """Real-space samples of the windowed dyadic kernel on the lattice offsets of
+    a grid of `shape` (nz, ny, nx) with `spacing` (dz, dy, dx): K[j] for every
+    offset j in [-n, n) per axis, in FFT order on the 2n grid, shape
+    (2nz, 2ny, 2nx, 3, 3).
+
+    The transform F[G_R] is sampled on the grid oversampled `over` times (period
+    over * n * h per axis; its Nyquist planes zeroed), brought to real space by the inverse DFT (divided by
+    the cell volume, so that a Riemann sum of K against a density is the
+    convolution), and restricted to the offsets a 2n-padded convolution meets
+    (the precompute of the truncated-kernel method the windowed kernel section
+    cites)."""
+    nz, ny, nx = shape
+    dz, dy, dx = spacing
+    M = (over * nz, over * ny, over * nx)
+    kz = 2 * np.pi * np.fft.fftfreq(M[0], d=dz)
+    ky = 2 * np.pi * np.fft.fftfreq(M[1], d=dy)
+    kx = 2 * np.pi * np.fft.fftfreq(M[2], d=dx)
+    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    G = gtilde_isolated(KX, KY, KZ, kbg, R)                      # (Mz, My, Mx, 3, 3)
+    # the Nyquist planes have no partner of opposite sign, and the off-diagonal
+    # entries are odd in each component of k: zeroed, as on the periodic path,
+    # so that the samples are exactly even in the offset
+    G[M[0] // 2] = 0
+    G[:, M[1] // 2] = 0
+    G[:, :, M[2] // 2] = 0
+    g = np.fft.ifftn(G, axes=(0, 1, 2)) / (dx * dy * dz)          # samples at offsets, FFT order
+    iz = np.r_[0:nz, M[0] - nz:M[0]]
+    iy = np.r_[0:ny, M[1] - ny:M[1]]
+    ix = np.r_[0:nx, M[2] - nx:M[2]]
+    return g[np.ix_(iz, iy, ix)]                                   # offsets [-n, n) in FFT order on 2n
+
+
+def isolated_table(shape, spacing, kbg: complex, R: float, over: int = 4) -> np.ndarray:
+    """The kernel of the isolated-domain apply on the 2n grid: the DFT of the
+    kernel samples (times the cell volume), shape (2nz, 2ny, 2nx, 3, 3)."""
+    dz, dy, dx = spacing
+    K = kernel_samples(shape, spacing, kbg, R, over)
+    return np.fft.fftn(K, axes=(0, 1, 2)) * (dx * dy * dz)
+
+
+def apply_isolated(table: np.ndarray, vol: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """y = x - P IFFT(table . FFT(Z (vol x))) with Z the zero padding of every axis
+    to twice its length and P the restriction back (eq. (18) for an isolated
+    scatterer). vol is the potential V per voxel (nz, ny, nx); x is (3, nz, ny, nx)."""
+    _, nz, ny, nx = x.shape
+    f = np.zeros((3, 2 * nz, 2 * ny, 2 * nx), dtype=complex)
+    f[:, :nz, :ny, :nx] = vol[None] * x
+    fh = np.fft.fftn(f, axes=(1, 2, 3))
+    wh = np.einsum("zyxij,jzyx->izyx", table, fh)
+    w = np.fft.ifftn(wh, axes=(1, 2, 3))[:, :nz, :ny, :nx]
+    return x - w

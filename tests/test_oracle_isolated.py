@@ -124,3 +124,58 @@ def test_dyadic_structure():
     # k = 0: A(0) I
     G0 = I.gtilde_isolated(0.0, 0.0, 0.0, kbg, R)
     assert np.allclose(G0, I.window_sphere_AB(0.0, kbg, R)[0] * np.eye(3), atol=1e-14)
+
+
+def test_isolated_apply_is_the_discrete_linear_convolution():
+    """The 2x-padded FFT apply equals the direct sum over voxel pairs with the
+    kernel samples of the 4x-oversampled precompute (a tiny grid, so that the
+    O(N^2) sum is cheap): y_i = x_i - sum_j K[i - j] V_j x_j dV."""
+    shape, spacing = (3, 4, 5), (2.0, 1.5, 1.0)
+    kbg = K0 * (1 + 0.02j)
+    nz, ny, nx = shape
+    R = 1.2 * np.sqrt((nz * spacing[0]) ** 2 + (ny * spacing[1]) ** 2 + (nx * spacing[2]) ** 2)
+    rng = np.random.default_rng(3)
+    vol = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    x = rng.normal(size=(3,) + shape) + 1j * rng.normal(size=(3,) + shape)
+    K = I.kernel_samples(shape, spacing, kbg, R)
+    y = I.apply_isolated(I.isolated_table(shape, spacing, kbg, R), vol, x)
+    dV = spacing[0] * spacing[1] * spacing[2]
+    ref = x.copy()
+    for iz in range(nz):
+        for iy in range(ny):
+            for ix in range(nx):
+                acc = np.zeros(3, dtype=complex)
+                for jz in range(nz):
+                    for jy in range(ny):
+                        for jx in range(nx):
+                            k = K[(iz - jz) % (2 * nz), (iy - jy) % (2 * ny), (ix - jx) % (2 * nx)]
+                            acc += k @ (vol[jz, jy, jx] * x[:, jz, jy, jx])
+                ref[:, iz, iy, ix] -= acc * dV
+    assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_isolated_kernel_samples_even_and_symmetric():
+    """The kernel samples are symmetric 3x3 and even in the offset, so the
+    discrete isolated operator is complex-symmetric (reciprocal)."""
+    shape, spacing = (4, 4, 6), (1.0, 1.0, 1.0)
+    kbg = K0 * (1 + 0.03j)
+    R = 1.1 * np.sqrt(4 ** 2 + 4 ** 2 + 6 ** 2)
+    K = I.kernel_samples(shape, spacing, kbg, R)
+    assert np.allclose(K, np.swapaxes(K, -1, -2), rtol=0, atol=1e-12 * np.abs(K).max())
+    # K at offset -j (FFT order on 2n); the offset -n of each axis has no stored
+    # partner +n, so those planes are left out
+    Kneg = np.roll(np.flip(K, axis=(0, 1, 2)), shift=(1, 1, 1), axis=(0, 1, 2))
+    inner = np.ones(K.shape[:3], dtype=bool)
+    inner[shape[0]] = False
+    inner[:, shape[1]] = False
+    inner[:, :, shape[2]] = False
+    assert np.allclose(K[inner], Kneg[inner], rtol=0, atol=1e-12 * np.abs(K).max())
+    # reciprocity of the apply: <a, (I - A) b> = <b, (I - A) a> (bilinear) for V = 1
+    rng = np.random.default_rng(5)
+    T = I.isolated_table(shape, spacing, kbg, R)
+    a = rng.normal(size=(3,) + shape) + 1j * rng.normal(size=(3,) + shape)
+    b = rng.normal(size=(3,) + shape) + 1j * rng.normal(size=(3,) + shape)
+    one = np.ones(shape)
+    lhs = np.sum(a * (b - I.apply_isolated(T, one, b)))
+    rhs = np.sum(b * (a - I.apply_isolated(T, one, a)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
