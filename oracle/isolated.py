@@ -84,21 +84,40 @@ def gtilde_isolated(kx, ky, kz, kbg: complex, R: float) -> np.ndarray:
     return out
 
 
-def kernel_samples(shape, spacing, kbg: complex, R: float, over: int = 4) -> np.ndarray:
+def oversampling(shape, spacing, R: float) -> tuple:
+    """Per-axis oversampling factor of the kernel precompute: the smallest power
+    of two that is at least 4 (the factor the windowed kernel section uses) and
+    at least 1 + R / L_a, L_a = n_a h_a. The inverse DFT of samples of F[G_R] at
+    spacing 2 pi / P_a has the images of the ball of radius R at multiples of
+    the period P_a; the offsets |j| <= L_a that the padded convolution meets
+    stay clear of them when P_a >= L_a + R (for a cube with R at the diagonal
+    the factor 4 suffices; a flat absorber needs more along its thin axis)."""
+    out = []
+    for n, h in zip(shape, spacing):
+        f = 4
+        while f < 1.0 + R / (n * h):
+            f *= 2
+        out.append(f)
+    return tuple(out)
+
+
+def kernel_samples(shape, spacing, kbg: complex, R: float, over=4) -> np.ndarray:
     """Real-space samples of the windowed dyadic kernel on the lattice offsets of
     a grid of `shape` (nz, ny, nx) with `spacing` (dz, dy, dx): K[j] for every
     offset j in [-n, n) per axis, in FFT order on the 2n grid, shape
     (2nz, 2ny, 2nx, 3, 3).
 
-    The transform F[G_R] is sampled on the grid oversampled `over` times (period
-    over * n * h per axis; its Nyquist planes zeroed), brought to real space by the inverse DFT (divided by
+    The transform F[G_R] is sampled on the grid oversampled `over` times (an int,
+    or one factor per axis (z, y, x); period over * n * h per axis; its Nyquist
+    planes zeroed), brought to real space by the inverse DFT (divided by
     the cell volume, so that a Riemann sum of K against a density is the
     convolution), and restricted to the offsets a 2n-padded convolution meets
     (the precompute of the truncated-kernel method the windowed kernel section
     cites)."""
     nz, ny, nx = shape
     dz, dy, dx = spacing
-    M = (over * nz, over * ny, over * nx)
+    oz, oy, ox = (over, over, over) if np.isscalar(over) else over
+    M = (oz * nz, oy * ny, ox * nx)
     kz = 2 * np.pi * np.fft.fftfreq(M[0], d=dz)
     ky = 2 * np.pi * np.fft.fftfreq(M[1], d=dy)
     kx = 2 * np.pi * np.fft.fftfreq(M[2], d=dx)
@@ -117,7 +136,7 @@ def kernel_samples(shape, spacing, kbg: complex, R: float, over: int = 4) -> np.
     return g[np.ix_(iz, iy, ix)]                                   # offsets [-n, n) in FFT order on 2n
 
 
-def isolated_table(shape, spacing, kbg: complex, R: float, over: int = 4) -> np.ndarray:
+def isolated_table(shape, spacing, kbg: complex, R: float, over=4) -> np.ndarray:
     """The kernel of the isolated-domain apply on the 2n grid: the DFT of the
     kernel samples (times the cell volume), shape (2nz, 2ny, 2nx, 3, 3)."""
     dz, dy, dx = spacing
