@@ -195,6 +195,64 @@ int psfd_bench_stage(psfd_plan* plan, int stage, const void* d_deps, const void*
 int psfd_bench_gram_schmidt(psfd_plan* plan, int pass, int j, const void* d_x, int dtype, int reps, float* ms,
                             void* stream);
 
+/* ------------------------------------------------------------------------
+ * Isolated-domain mode: a scatterer in free space (no periodicity, no
+ * multilayer), with the dyadic Green's function truncated to a ball of radius R
+ * (the windowed kernel of eqs. (13) and (15)-(17), with h(k; R) carrying R^2
+ * and A(0) the factor 4 pi) and the convolution of eq. (18) zero-padded to twice
+ * the grid on all three axes. The kernel table is precomputed once per plan in
+ * FP64 from the closed form F[G_R] = A(k) I + B(k) k^ k^: sampled on a grid
+ * oversampled per axis (factor o_a, the smallest power of two >= max(4, 1 + R /
+ * L_a), L_a = n_a h_a; Nyquist planes zeroed), inverse DFT, restricted to the
+ * offsets [-n, n) per axis, forward DFT on the 2n grid.
+ *
+ * Grid: nx, ny, nz powers of two in [2, 128] with o_a n_a <= 1024; voxel sizes
+ * dx, dy, dz in nm; sample (k, j, i) at (i dx, j dy, k dz). Fields are
+ * [3][nz][ny][nx] (component x, y, z), the contrast delta_eps = eps - eps_bg is
+ * [nz][ny][nx], V = k0^2 delta_eps, k0 = 2 pi / wavelength, k_bg = k0 sqrt(eps_bg).
+ */
+typedef struct psfd_iso_plan psfd_iso_plan;
+
+typedef struct {
+  int32_t nx, ny, nz;
+  double dx_nm, dy_nm, dz_nm;   /* voxel size */
+  double wavelength_nm;
+  double eps_bg_re, eps_bg_im;  /* background permittivity: Re > 0, Im >= 0 */
+  double radius_nm;             /* window radius R; <= 0: the box diagonal sqrt(sum L_a^2) */
+} psfd_iso_problem;
+
+/* Validate the problem and precompute the kernel table on the current device
+ * (blocks until done; the precompute holds 96 prod(o_a n_a) bytes of device
+ * memory while it runs). *out receives the plan, owned by the caller and
+ * released with psfd_iso_plan_destroy. Errors: INVALID_ARG, UNSUPPORTED_SIZE
+ * (a size, or a radius that needs o_a n_a > 1024), OOM / HIP. */
+int psfd_iso_plan_create(const psfd_iso_problem* prob, psfd_iso_plan** out);
+void psfd_iso_plan_destroy(psfd_iso_plan* plan);
+
+/* y = x - P IFFT(table . FFT(Z V x)) (eq. (18) for the isolated scatterer; Z
+ * pads every axis to twice its length, P restricts back). d_deps, d_x, d_y:
+ * device arrays of `dtype` (PSFD_C64: complex64, FP32 arithmetic on the FP32
+ * rounding of the table; PSFD_C128: complex128, FP64); d_y must not alias d_x.
+ * A workspace of 96 nx ny nz (C64) or 192 nx ny nz (C128) bytes is allocated at
+ * the first call of each dtype and kept with the plan. Asynchronous on
+ * `stream`; calls on one plan must not overlap. */
+int psfd_iso_apply(psfd_iso_plan* plan, const void* d_deps, const void* d_x, void* d_y, int dtype, void* stream);
+
+/* The precomputed table (may be NULL): complex128 [6][2nz][2ny][2nx], the
+ * entries xx, yy, zz, xy, xz, yz of the symmetric 3 x 3 kernel per wavevector
+ * of the padded grid in FFT order, copied to the device array d_table on
+ * `stream`. over (may be NULL): the 3 oversampling factors (z, y, x) of the
+ * precompute; radius_nm (may be NULL): R. */
+int psfd_iso_table(psfd_iso_plan* plan, void* d_table, int32_t* over, double* radius_nm, void* stream);
+
+/* Diagnostics: run pass `stage` of psfd_iso_apply (-1: all of it; 0: x rows
+ * times V, FFT; 1: y columns FFT; 2: z FFT, table product, inverse z FFT; 3:
+ * inverse y columns; 4: inverse x rows with y = x - w) `reps` times back to back
+ * between two HIP events on `stream`; *ms receives the mean time per launch.
+ * Same buffers as psfd_iso_apply. Blocks until done. */
+int psfd_iso_bench_stage(psfd_iso_plan* plan, int stage, const void* d_deps, const void* d_x, void* d_y, int dtype,
+                         int reps, float* ms, void* stream);
+
 const char* psfd_status_string(int status);
 const char* psfd_last_error(void);
 const char* psfd_version(void);

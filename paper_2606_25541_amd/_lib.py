@@ -53,6 +53,13 @@ class psfd_info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class psfd_iso_problem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx_nm", C.c_double), ("dy_nm", C.c_double), ("dz_nm", C.c_double),
+                ("wavelength_nm", C.c_double), ("eps_bg_re", C.c_double), ("eps_bg_im", C.c_double),
+                ("radius_nm", C.c_double)]
+
+
 EXPORTS = {
     "psfd_plan_create": (C.c_int, [C.POINTER(psfd_problem), C.POINTER(psfd_opts), C.POINTER(C.c_void_p)]),
     "psfd_plan_destroy": (None, [C.c_void_p]),
@@ -76,6 +83,13 @@ EXPORTS = {
                                    C.POINTER(C.c_float), C.c_void_p]),
     "psfd_bench_gram_schmidt": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int,
                                           C.POINTER(C.c_float), C.c_void_p]),
+    "psfd_iso_plan_create": (C.c_int, [C.POINTER(psfd_iso_problem), C.POINTER(C.c_void_p)]),
+    "psfd_iso_plan_destroy": (None, [C.c_void_p]),
+    "psfd_iso_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "psfd_iso_table": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                 C.c_void_p]),
+    "psfd_iso_bench_stage": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                       C.c_int, C.POINTER(C.c_float), C.c_void_p]),
     "psfd_status_string": (C.c_char_p, [C.c_int]),
     "psfd_last_error": (C.c_char_p, []),
     "psfd_version": (C.c_char_p, []),

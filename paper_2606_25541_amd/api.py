@@ -224,3 +224,73 @@ class OrderIntensity(torch.autograd.Function):
     def backward(ctx, gout):
         (grad,) = ctx.saved_tensors
         return gout.to(grad.real.dtype) * grad, None, None
+
+
+class IsoPlan:
+    """Isolated-domain mode: a scatterer in free space with the spherically
+    windowed dyadic kernel and padding by 2 on all axes (psfd_iso_* entry
+    points). The kernel table is precomputed on the current device at
+    construction."""
+
+    def __init__(self, nx: int, ny: int, nz: int, spacing_nm: Tuple[float, float, float],
+                 wavelength_nm: float = 13.5, eps_bg: complex = 1.0, radius_nm: float = 0.0):
+        dz, dy, dx = (float(v) for v in spacing_nm)
+        e = complex(eps_bg)
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self._cp = L.psfd_iso_problem(self.nx, self.ny, self.nz, dx, dy, dz, float(wavelength_nm), e.real, e.imag,
+                                      float(radius_nm))
+        h = C.c_void_p()
+        L.check(L.lib().psfd_iso_plan_create(C.byref(self._cp), C.byref(h)), "psfd_iso_plan_create")
+        self._h = h
+        self._destroy = L.lib().psfd_iso_plan_destroy
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    @property
+    def field_shape(self):
+        return (3, self.nz, self.ny, self.nx)
+
+    def _check(self, deps, x, out):
+        dt = x.dtype
+        code = {torch.complex64: L.PSFD_C64, torch.complex128: L.PSFD_C128}[dt]
+        _dev(deps, dt, "deps")
+        _dev(x, dt, "x")
+        if tuple(x.shape) != self.field_shape or tuple(deps.shape) != self.field_shape[1:]:
+            raise ValueError("shape mismatch")
+        if out is None:
+            out = torch.empty_like(x)
+        _dev(out, dt, "out")
+        return code, out
+
+    def psfd_iso_apply(self, deps: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """y = x - P IFFT(table . FFT(Z V x)), V = k0^2 deps."""
+        code, out = self._check(deps, x, out)
+        L.check(L.lib().psfd_iso_apply(self._h, C.c_void_p(deps.data_ptr()), C.c_void_p(x.data_ptr()),
+                                       C.c_void_p(out.data_ptr()), code, _stream()), "psfd_iso_apply")
+        return out
+
+    apply = psfd_iso_apply
+
+    def psfd_iso_table(self):
+        """(table complex128 [6][2nz][2ny][2nx] on the device, (o_z, o_y, o_x), R)."""
+        t = torch.empty((6, 2 * self.nz, 2 * self.ny, 2 * self.nx), dtype=torch.complex128, device="cuda")
+        over = (C.c_int32 * 3)()
+        r = C.c_double()
+        L.check(L.lib().psfd_iso_table(self._h, C.c_void_p(t.data_ptr()), over, C.byref(r), _stream()),
+                "psfd_iso_table")
+        return t, tuple(int(v) for v in over), float(r.value)
+
+    table = psfd_iso_table
+
+    def bench_stage(self, stage: int, deps: torch.Tensor, x: torch.Tensor, out: torch.Tensor, reps: int) -> float:
+        code, out = self._check(deps, x, out)
+        ms = C.c_float()
+        L.check(L.lib().psfd_iso_bench_stage(self._h, int(stage), C.c_void_p(deps.data_ptr()),
+                                             C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), code, int(reps),
+                                             C.byref(ms), _stream()), "psfd_iso_bench_stage")
+        return float(ms.value)

@@ -4,6 +4,7 @@
 #include <string>
 
 #include "engine.hpp"
+#include "iso.hpp"
 #include "serve.hpp"
 
 using namespace psfd;
@@ -299,6 +300,52 @@ int psfd_server_destroy(psfd_server* srv) {
   if (!srv) return fail(PSFD_ERR_INVALID_ARG, "NULL server");
   Status st = server_destroy(srv);
   return st.ok() ? PSFD_OK : fail(st);
+}
+
+int psfd_iso_plan_create(const psfd_iso_problem* prob, psfd_iso_plan** out) {
+  if (!prob || !out) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  Status st = iso_create(*prob, *out);
+  return st.ok() ? PSFD_OK : fail(st);
+}
+
+void psfd_iso_plan_destroy(psfd_iso_plan* plan) { iso_destroy(plan); }
+
+int psfd_iso_apply(psfd_iso_plan* plan, const void* d_deps, const void* d_x, void* d_y, int dtype, void* stream) {
+  if (!plan || !d_deps || !d_x || !d_y) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  if (d_x == d_y) return fail(PSFD_ERR_INVALID_ARG, "d_y must not alias d_x");
+  Status st = iso_apply(plan, d_deps, d_x, d_y, dtype, -1, (hipStream_t)stream);
+  return st.ok() ? PSFD_OK : fail(st);
+}
+
+int psfd_iso_table(psfd_iso_plan* plan, void* d_table, int32_t* over, double* radius_nm, void* stream) {
+  if (!plan) return fail(PSFD_ERR_INVALID_ARG, "NULL plan");
+  Status st = iso_table(plan, d_table, over, radius_nm, (hipStream_t)stream);
+  return st.ok() ? PSFD_OK : fail(st);
+}
+
+int psfd_iso_bench_stage(psfd_iso_plan* plan, int stage, const void* d_deps, const void* d_x, void* d_y, int dtype,
+                         int reps, float* ms, void* stream) {
+  if (!plan || !d_deps || !d_x || !d_y || !ms || reps < 1) return fail(PSFD_ERR_INVALID_ARG, "bad arguments");
+  if (d_x == d_y) return fail(PSFD_ERR_INVALID_ARG, "d_y must not alias d_x");
+  hipStream_t s = (hipStream_t)stream;
+  Status st = iso_apply(plan, d_deps, d_x, d_y, dtype, stage, s);  // untimed first launch
+  if (!st.ok()) return fail(st);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(PSFD_ERR_HIP, "hipEventCreate");
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < reps && st.ok(); ++r) st = iso_apply(plan, d_deps, d_x, d_y, dtype, stage, s);
+  (void)hipEventRecord(e1, s);
+  hipError_t e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!st.ok()) return fail(st);
+  if (e != hipSuccess) return fail(PSFD_ERR_HIP, hipGetErrorString(e));
+  *ms = t / reps;
+  return PSFD_OK;
 }
 
 }  // extern "C"

@@ -102,3 +102,29 @@ def test_plan_create_and_footprint_on_host(lib):
 def test_release_cached_workspaces_without_cache(lib):
     # only the host-side cache is touched: returns OK with nothing kept
     assert lib.psfd_release_cached_workspaces() == 0
+
+
+def test_isolated_plan_validation_errors(lib):
+    """psfd_iso_plan_create rejects bad grids, sizes, media and radii before any
+    device call."""
+    from paper_2606_25541_amd import _lib as L
+    h = C.c_void_p()
+
+    def P(nx=8, ny=8, nz=4, d=(2.0, 2.0, 1.0), lam=13.5, e=(1.0, 0.0), R=0.0):
+        return L.psfd_iso_problem(nx, ny, nz, d[0], d[1], d[2], lam, e[0], e[1], R)
+
+    cases = [
+        (P(nx=12), L.PSFD_ERR_UNSUPPORTED_SIZE),
+        (P(nz=256), L.PSFD_ERR_UNSUPPORTED_SIZE),
+        (P(ny=1), L.PSFD_ERR_UNSUPPORTED_SIZE),
+        (P(d=(2.0, 0.0, 1.0)), L.PSFD_ERR_INVALID_ARG),
+        (P(lam=-1.0), L.PSFD_ERR_INVALID_ARG),
+        (P(e=(1.0, -0.1)), L.PSFD_ERR_INVALID_ARG),
+        # a radius far beyond the box needs an oversampled grid longer than 1024
+        (P(nx=128, R=1e6), L.PSFD_ERR_UNSUPPORTED_SIZE),
+    ]
+    for p, code in cases:
+        assert lib.psfd_iso_plan_create(C.byref(p), C.byref(h)) == code, (p.nx, p.ny, p.nz)
+        assert lib.psfd_last_error().decode()
+    assert lib.psfd_iso_plan_create(None, C.byref(h)) == L.PSFD_ERR_INVALID_ARG
+    assert lib.psfd_iso_apply(None, None, None, None, 0, None) == L.PSFD_ERR_INVALID_ARG

@@ -1,0 +1,158 @@
+"""Parity of the isolated-domain mode (spherical window, padding by 2 on all
+axes) with the oracle: the precomputed kernel table and the operator apply.
+
+Tolerances: the FP64 table 1e-10 of its largest entry (closed-form samples
+rounded differently by the device and host libraries, then O(log N) FFT
+passes), the FP64 apply 1e-10 of the largest output and of the largest
+scattered part x - y, the FP32 apply 2e-5 of each (single-precision FFTs of
+length <= 256 per axis on the FP32 rounding of the table). At 128 x 128 x 64, where the oracle's precompute is out
+of reach, properties that hold at any size: reciprocity of the operator, its
+linearity in the contrast, the identity for a zero contrast, determinism, and
+the FP32 / FP64 agreement.
+"""
+import numpy as np
+import pytest
+
+from oracle import isolated as I
+from paper_2606_25541_amd import clips
+
+from gpu_util import device, say, torch
+
+pytestmark = pytest.mark.gpu
+
+LAM = 13.5
+# (nz, ny, nx), (dz, dy, dx), eps_bg: cubic and flat boxes (the flat ones need
+# more oversampling along z), a lossy and a lossless background
+CASES = [
+    ((2, 2, 2), (1.0, 1.0, 1.0), 1.0 + 0.02j),
+    ((4, 8, 8), (1.0, 3.0, 3.0), 1.0 + 0.05j),
+    ((8, 4, 16), (2.0, 2.0, 1.0), 1.0 + 0.0j),
+    ((16, 16, 8), (0.9375, 2.0, 2.0), 1.0 + 0.0j),
+]
+
+
+def iso_plan(shape, spacing, eps_bg, R=0.0):
+    from paper_2606_25541_amd import api
+    nz, ny, nx = shape
+    return api.IsoPlan(nx, ny, nz, spacing, LAM, eps_bg, R)
+
+
+def oracle_table(shape, spacing, eps_bg, R):
+    kbg = 2 * np.pi / LAM * np.sqrt(complex(eps_bg))
+    over = I.oversampling(shape, spacing, R)
+    return I.isolated_table(shape, spacing, kbg, R, over), over
+
+
+def full_table(t6):
+    xx, yy, zz, xy, xz, yz = t6
+    return np.stack([np.stack([xx, xy, xz], -1), np.stack([xy, yy, yz], -1), np.stack([xz, yz, zz], -1)], -2)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_isolated_table_matches_oracle(case):
+    dev = device()
+    shape, spacing, eps = CASES[case]
+    say("isolated table", shape, spacing, eps)
+    plan = iso_plan(shape, spacing, eps)
+    t, over, R = plan.table()
+    torch.cuda.synchronize()
+    Rd = float(np.sqrt(sum((n * h) ** 2 for n, h in zip(shape, spacing))))
+    assert abs(R - Rd) <= 1e-12 * Rd
+    ref, over_o = oracle_table(shape, spacing, eps, R)
+    assert over == over_o
+    g = full_table(t.cpu().numpy())
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    say("  over", over, "rel err", err)
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_isolated_apply_matches_oracle(case, dtype):
+    dev = device()
+    shape, spacing, eps = CASES[case]
+    say("isolated apply", shape, dtype)
+    R = float(np.sqrt(sum((n * h) ** 2 for n, h in zip(shape, spacing))))
+    ref_t, _ = oracle_table(shape, spacing, eps, R)
+    plan = iso_plan(shape, spacing, eps)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    x = clips.random_complex((3,) + shape, seed=11 + case)
+    de = clips.random_complex(shape, seed=31 + case) * 0.2
+    if dtype == "c64":  # the oracle sees the same FP32-rounded inputs
+        x = x.astype(np.complex64).astype(np.complex128)
+        de = de.astype(np.complex64).astype(np.complex128)
+    y = plan.apply(torch.from_numpy(de).to(dev, tdt), torch.from_numpy(x).to(dev, tdt))
+    torch.cuda.synchronize()
+    k0 = 2 * np.pi / LAM
+    ref = I.apply_isolated(ref_t, k0 * k0 * de, x)
+    yg = y.cpu().numpy().astype(np.complex128)
+    err = np.abs(yg - ref).max() / np.abs(ref).max()
+    # the scattered part w = x - y on its own scale
+    errw = np.abs((x - yg) - (x - ref)).max() / np.abs(x - ref).max()
+    say("  rel err", err, "of w", errw)
+    assert err <= (1e-10 if dtype == "c128" else 2e-5)
+    assert errw <= (1e-10 if dtype == "c128" else 2e-5)
+
+
+def test_isolated_apply_medium_matches_oracle():
+    """32 x 32 x 16 over the absorber geometry of the 128 x 128 x 64 clip (256 x 256 x
+    60 nm, coarser voxels): x rows of 64, z pencils of 32, several blocks per pass."""
+    dev = device()
+    shape, spacing = (16, 32, 32), (60.0 / 16, 8.0, 8.0)
+    R = float(np.sqrt(sum((n * h) ** 2 for n, h in zip(shape, spacing))))
+    ref_t, over = oracle_table(shape, spacing, 1.0, R)
+    say("isolated apply medium", shape, over)
+    plan = iso_plan(shape, spacing, 1.0)
+    x = clips.random_complex((3,) + shape, seed=5)
+    de = clips.contact_holes(32, 32, 16, 256.0, 256.0, 4, seed=7).astype(np.complex128)
+    y = plan.apply(torch.from_numpy(de).to(dev), torch.from_numpy(x).to(dev))
+    torch.cuda.synchronize()
+    k0 = 2 * np.pi / LAM
+    ref = I.apply_isolated(ref_t, k0 * k0 * de, x)
+    err = np.abs(y.cpu().numpy() - ref).max() / np.abs(ref).max()
+    say("  rel err", err)
+    assert err <= 1e-10
+
+
+def test_isolated_apply_full_size_properties():
+    """128 x 128 x 64, 256 x 256 x 60 nm in vacuum (oversampling 8 along z): the
+    padded convolution only meets offsets |j| < n, where the kernel samples are
+    symmetric and even, so with a constant contrast the operator is
+    complex-symmetric: <a, A b> = <b, A a> (bilinear)."""
+    dev = device()
+    shape, spacing = (64, 128, 128), (60.0 / 64, 2.0, 2.0)
+    say("isolated full size", shape)
+    plan = iso_plan(shape, spacing, 1.0)
+    _, over, _ = plan.table()
+    assert over == (8, 4, 4)
+    for dt, tol in ((torch.complex128, 1e-11), (torch.complex64, 2e-5)):
+        one = torch.full(shape, 0.3 + 0.1j, dtype=dt, device=dev)
+        a = torch.from_numpy(clips.random_complex((3,) + shape, seed=1)).to(dev, dt)
+        b = torch.from_numpy(clips.random_complex((3,) + shape, seed=2)).to(dev, dt)
+        Ab = a.new_empty(a.shape)
+        Aa = a.new_empty(a.shape)
+        plan.apply(one, b, Ab)
+        plan.apply(one, a, Aa)
+        lhs = torch.sum((a * (b - Ab)).to(torch.complex128)).item()
+        rhs = torch.sum((b * (a - Aa)).to(torch.complex128)).item()
+        say("  reciprocity", dt, abs(lhs - rhs) / abs(lhs))
+        assert abs(lhs - rhs) <= tol * abs(lhs)
+        # linearity in the contrast, identity at zero contrast, determinism
+        de = torch.from_numpy(clips.contact_holes(128, 128, 64, 256.0, 256.0, 8, seed=2001)).to(dev, dt)
+        y1 = plan.apply(de, a)
+        y2 = plan.apply(2.0 * de, a)
+        y1b = plan.apply(de, a)
+        assert torch.equal(y1, y1b)
+        d1 = (y1 - a).to(torch.complex128)
+        d2 = (y2 - a).to(torch.complex128)
+        lin = ((d2 - 2.0 * d1).abs().max() / d2.abs().max()).item()
+        say("  linearity", lin)
+        assert lin <= (1e-12 if dt == torch.complex128 else 2e-5)
+        y0 = plan.apply(torch.zeros_like(de), a)
+        assert torch.equal(y0, a)
+        if dt == torch.complex128:
+            y64 = y1
+    y32 = plan.apply(de.to(torch.complex64), a.to(torch.complex64)).to(torch.complex128)
+    d = ((y32 - y64).abs().max() / (y64 - a.to(torch.complex128)).abs().max()).item()
+    say("  fp32 vs fp64", d)
+    assert d <= 2e-5
