@@ -21,6 +21,11 @@ Printed JSON line: the solve rate, plus
   serving           Poisson arrivals over {64x64x32, 128x128x64, 256x256x64}
                     at 0.7 of the saturated rate (--serve-qps: several
                     rates): p50 / p99 latency, solves/s;
+  isolated          the isolated-domain operator (spherical window, padding by
+                    2 on all axes) on the same 128x128x64 contact holes taken
+                    as a free-standing 256x256x60 nm scatterer in vacuum:
+                    table precompute time, applies/s FP32 / FP64, per-pass
+                    bandwidth and the roofline of its dominant kernel;
   adjoint           forward + adjoint gradient on a 256x256x64 smooth clip;
   cpu_baseline      the CPU oracle on a bounded sample of the headline solve.
 
@@ -43,37 +48,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SECTIONS = ("solve", "fp64", "apply", "batched", "serving", "adjoint", "cpu")
+SECTIONS = ("solve", "fp64", "apply", "isolated", "batched", "serving", "adjoint", "cpu")
 # sources that decide the code of the measured kernels (hashed into the counter summary)
 KERNEL_SOURCES = ("common.hpp", "layout.hpp", "kernels.hpp", "fft_lds.hpp", "k_apply.hip", "krylov.hpp",
                   "givens.hpp", "k_krylov.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "apply_G3_fp32_hbm_traffic.md")
+ISO_SOURCES = ("common.hpp", "fft_lds.hpp", "k_iso.hip")
+ISO_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "isolated_apply_G3_hbm_traffic.md")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2606_25541_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(key: str):
+def stored_traffic(key: str, summary: str = TRAFFIC_SUMMARY, sources=KERNEL_SOURCES):
     """HBM bytes per launch of a kernel (key: "stage 0|1|2", "projections", "update") from the
     committed counter summary.
 
     None when the summary is missing or was taken on other kernel sources.
     """
     try:
-        txt = open(TRAFFIC_SUMMARY).read()
+        txt = open(summary).read()
     except OSError:
         return None
     m = re.search(r"kernel source hash: `([0-9a-f]+)`", txt)
-    if not m or m.group(1) != kernel_source_hash():
+    if not m or m.group(1) != kernel_source_hash(sources):
         return None
     m = re.search(r"traffic %s: (\d+) bytes" % re.escape(key), txt)
     return int(m.group(1)) if m else None
@@ -275,6 +282,64 @@ def sec_apply(ctx, args, out):
         b = torch.empty_like(a)
         for _ in range(5):
             b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_bytes"] = a.numel() * 4
+
+
+def sec_isolated(ctx, args, out):
+    """Isolated-domain apply: the headline contact holes as a free-standing absorber block
+    (256 x 256 x 60 nm, vacuum, R = box diagonal); passes timed with HIP events on the launch stream."""
+    api, torch, clips = ctx["api"], ctx["torch"], ctx["clips"]
+    prob, dev = ctx["prob"], ctx["dev"]
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    spacing = (prob.t_nm / nz, prob.ly_nm / ny, prob.lx_nm / nx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = api.IsoPlan(nx, ny, nz, spacing, prob.wavelength_nm, 1.0)
+    t_pre = time.perf_counter() - t0
+    _, over, R = plan.table()
+    N = nx * ny * nz
+    x = torch.from_numpy(clips.random_complex((3, nz, ny, nx), 7)).to(dev)
+    reps = 20 if args.only == "isolated" else 100
+    # algorithmic bytes per voxel in complex values (esz bytes each): x rows read x (3) and
+    # delta_eps (1), write half the padded rows (6); y columns read 6, write 12; the z pencils read
+    # and write 12 and read the 6-entry table of the padded grid (48); inverse y columns read 12,
+    # write 6; inverse x rows read 6 and x (3), write y (3)
+    per_vox = {0: 10, 1: 18, 2: 72, 3: 18, 4: 12}
+    names = {0: "k_iso_lines<fwd, x rows * V>", 1: "k_iso_lines<fwd, y columns>",
+             2: "k_iso_zmul (z FFT, 3x3 table product, inverse z FFT)", 3: "k_iso_lines<inv, y columns>",
+             4: "k_iso_lines<inv, x rows, y = x - w>"}
+    res = {"grid": [nx, ny, nz], "spacing_nm": list(spacing), "radius_nm": R, "oversampling_zyx": list(over),
+           "precompute_ms": 1e3 * t_pre}
+    for name, dt_, esz in (("fp32", torch.complex64, 8), ("fp64", torch.complex128, 16)):
+        xx, dd = x.to(dt_), ctx["deps"].to(dt_)
+        y = torch.empty_like(xx)
+        ms = plan.bench_stage(-1, dd, xx, y, reps)
+        stages = {}
+        for st in range(5):
+            t = plan.bench_stage(st, dd, xx, y, reps) * 1e-3
+            stages[st] = {"kernel": names[st], "us": 1e6 * t, "bytes": per_vox[st] * esz * N,
+                          "gbs": per_vox[st] * esz * N / t / 1e9}
+        b = sum(per_vox.values()) * esz * N
+        res[name] = {"applies_per_s": 1e3 / ms, "us_per_apply": 1e3 * ms, "apply_bytes": b,
+                     "apply_gbs": b / (ms * 1e-3) / 1e9, "stages": stages}
+    st32 = res["fp32"]["stages"]
+    dom = max(st32, key=lambda k: st32[k]["us"])
+    gbs = st32[dom]["gbs"]
+    res["roofline"] = {"bound": "hbm", "kernel": names[dom] + " FP32", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                       "traffic": stored_traffic("z pencil fp32", ISO_TRAFFIC_SUMMARY, ISO_SOURCES) if dom == 2 else None,
+                       "bytes_per_launch": st32[dom]["bytes"], "us_per_launch": st32[dom]["us"],
+                       "kernel_source_hash": kernel_source_hash(ISO_SOURCES)}
+    res["vs_periodic_apply_fp32"] = (res["fp32"]["us_per_apply"] / out["apply"]["fp32"]["us_per_apply"]
+                                     if "apply" in out else None)
+    out["isolated"] = res
+    log("bench: isolated", res)
+    if args.only == "isolated":
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        b2 = torch.empty_like(a)
+        for _ in range(5):
+            b2.copy_(a)
         torch.cuda.synchronize()
         out["copy_bytes"] = a.numel() * 4
 
@@ -640,7 +705,7 @@ def main():
         todo = ["solve"]
     else:
         todo = [s for s in SECTIONS if s != "cpu" or not args.no_cpu]
-    fns = {"solve": sec_solve, "fp64": sec_fp64, "apply": sec_apply, "batched": sec_batched,
+    fns = {"solve": sec_solve, "fp64": sec_fp64, "apply": sec_apply, "isolated": sec_isolated, "batched": sec_batched,
            "serving": sec_serving, "adjoint": sec_adjoint, "cpu": sec_cpu}
     for s in todo:
         log("bench: section", s)

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -59,6 +60,10 @@ struct IsoLines {
 
 enum { LN_PLAIN = 0, LN_VLOAD = 1, LN_AXPY = 2 };
 
+// values per thread in the FFT passes of a line block (8 complex values: no
+// spills in either precision; the block has (lines x length) / 8 threads)
+constexpr int LFE = 8;
+
 PSFD_D long long line_base(long long l, int lcin, long long s_in, long long s_out) {
   return (l & ((1LL << lcin) - 1)) * s_in + (l >> lcin) * s_out;
 }
@@ -89,8 +94,8 @@ __global__ void k_iso_lines(IsoLines a) {
     lds[SFL ? (e << a.llb) + li : (li << a.ln) + e] = v;
   }
   __syncthreads();
-  if (SFL) lds_fft<T, INV, true, FftBudget<T>::E, ZIN, ZOUT>(lds, a.ln, a.lb, 1, a.lb, (const T*)a.tw, tid, nthr);
-  else lds_fft<T, INV, false, FftBudget<T>::E, ZIN, ZOUT>(lds, a.ln, a.lb, n, 1, (const T*)a.tw, tid, nthr);
+  if (SFL) lds_fft<T, INV, true, LFE, ZIN, ZOUT>(lds, a.ln, a.lb, 1, a.lb, (const T*)a.tw, tid, nthr);
+  else lds_fft<T, INV, false, LFE, ZIN, ZOUT>(lds, a.ln, a.lb, n, 1, (const T*)a.tw, tid, nthr);
   T* dst = (T*)a.dst;
   const T* xin = (const T*)a.xin;
   typedef typename real_of<T>::type R;
@@ -111,7 +116,7 @@ __global__ void k_iso_lines(IsoLines a) {
 // components: 3 lb sequences of length 2nz interleaved in LDS.
 struct IsoZ {
   void* w;
-  const void* table;   // [6][2nz][2ny][2nx]: xx, yy, zz, xy, xz, yz
+  const void* table;   // pencil-major: block (ky, kx / lb), then [2nz][6][lb]; entries xx, yy, zz, xy, xz, yz
   int lnz, lnx2;       // log2 nz, log2 2nx
   int lb, llb;
   long long plane;     // 2ny 2nx
@@ -119,13 +124,45 @@ struct IsoZ {
   const void* tw;
 };
 
+// Each thread owns the table products of points tid + i nthr (i < ZPT) and
+// loads their six table entries before the forward z FFT, so that the loads
+// are in flight while the FFT runs; points beyond ZPT nthr (not met by the
+// launch shapes used) load theirs after it.
+// (ZPT: 2 points per thread in FP32; none in FP64, where the prefetched
+// entries and the FFT registers do not fit together without spills)
+template <class T> struct Zpt { static constexpr int v = sizeof(T) == 8 ? 2 : 0; };
+// values per thread in the z FFT passes (the block has at least els / ZFE threads)
+constexpr int ZFE = 8;
+
+template <class T>
+PSFD_D void zmul_point(T* f, int lb, const T t[6]) {
+  const T f0 = f[0], f1 = f[lb], f2 = f[2 * lb];
+  f[0] = cadd(cadd(cmul(t[0], f0), cmul(t[3], f1)), cmul(t[4], f2));
+  f[lb] = cadd(cadd(cmul(t[3], f0), cmul(t[1], f1)), cmul(t[5], f2));
+  f[2 * lb] = cadd(cadd(cmul(t[4], f0), cmul(t[5], f1)), cmul(t[2], f2));
+}
+
 template <class T>
 __global__ void k_iso_zmul(IsoZ a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int nz = 1 << a.lnz, lb = a.lb, nsq = 3 * lb;
+  const int nz = 1 << a.lnz, lb = a.lb, nsq = 3 * lb, npts = 2 * nz * lb;
   const long long col = ((long long)blockIdx.y << a.lnx2) + ((long long)blockIdx.x << a.llb);
+  // this block's table entries: one contiguous run of 2nz * 6 * lb values,
+  // point (kz, li) entry k at (kz * 6 + k) * lb + li
+  const T* tb = (const T*)a.table + (((long long)blockIdx.y * gridDim.x + blockIdx.x) * npts * 6);
+  constexpr int ZPT = Zpt<T>::v;
+  T tt[ZPT > 0 ? ZPT : 1][6];
+#pragma unroll
+  for (int i = 0; i < ZPT; ++i) {
+    const int p = tid + i * nthr;
+    if (p < npts) {
+      const T* q = tb + (p >> a.llb) * 6 * lb + (p & (lb - 1));
+#pragma unroll
+      for (int k = 0; k < 6; ++k) tt[i][k] = q[k * lb];
+    }
+  }
   T* w = (T*)a.w;
   for (int idx = tid; idx < nz * nsq; idx += nthr) {
     const int li = idx & (lb - 1), r = idx >> a.llb;
@@ -133,21 +170,21 @@ __global__ void k_iso_zmul(IsoZ a) {
     lds[iz * nsq + c * lb + li] = w[(long long)(c * nz + iz) * a.plane + col + li];
   }
   __syncthreads();
-  lds_fft<T, false, true, FftBudget<T>::E, true, false>(lds, a.lnz + 1, nsq, 1, nsq, (const T*)a.tw, tid, nthr);
-  const T* tb = (const T*)a.table;
-  for (int p = tid; p < 2 * nz * lb; p += nthr) {
-    const int li = p & (lb - 1), kz = p >> a.llb;
-    const long long o = (long long)kz * a.plane + col + li;
-    const T txx = tb[o], tyy = tb[a.n8 + o], tzz = tb[2 * a.n8 + o];
-    const T txy = tb[3 * a.n8 + o], txz = tb[4 * a.n8 + o], tyz = tb[5 * a.n8 + o];
-    T* f = lds + kz * nsq + li;
-    const T f0 = f[0], f1 = f[lb], f2 = f[2 * lb];
-    f[0] = cadd(cadd(cmul(txx, f0), cmul(txy, f1)), cmul(txz, f2));
-    f[lb] = cadd(cadd(cmul(txy, f0), cmul(tyy, f1)), cmul(tyz, f2));
-    f[2 * lb] = cadd(cadd(cmul(txz, f0), cmul(tyz, f1)), cmul(tzz, f2));
+  lds_fft<T, false, true, ZFE, true, false>(lds, a.lnz + 1, nsq, 1, nsq, (const T*)a.tw, tid, nthr);
+#pragma unroll
+  for (int i = 0; i < ZPT; ++i) {
+    const int p = tid + i * nthr;
+    if (p < npts) zmul_point(lds + (p >> a.llb) * nsq + (p & (lb - 1)), lb, tt[i]);
+  }
+  for (int p = tid + ZPT * nthr; p < npts; p += nthr) {
+    const T* q = tb + (p >> a.llb) * 6 * lb + (p & (lb - 1));
+    T t[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) t[k] = q[k * lb];
+    zmul_point(lds + (p >> a.llb) * nsq + (p & (lb - 1)), lb, t);
   }
   __syncthreads();
-  lds_fft<T, true, true, FftBudget<T>::E, false, true>(lds, a.lnz + 1, nsq, 1, nsq, (const T*)a.tw, tid, nthr);
+  lds_fft<T, true, true, ZFE, false, true>(lds, a.lnz + 1, nsq, 1, nsq, (const T*)a.tw, tid, nthr);
   for (int idx = tid; idx < nz * nsq; idx += nthr) {
     const int li = idx & (lb - 1), r = idx >> a.llb;
     const int iz = r / 3, c = r - 3 * iz;
@@ -240,9 +277,25 @@ __global__ void k_iso_restrict(const double2* __restrict__ g, double2* __restric
   t[idx] = cscale(g[src], scale);
 }
 
-__global__ void k_iso_to32(const double2* __restrict__ a, float2* __restrict__ b, long long n) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = to_f(a[i]);
+// the table in the z-pencil order of the apply: for block (ky, kb) of lb
+// adjacent kx, [2nz][6][lb]; from the natural [6][2nz][2ny][2nx]
+template <class T>
+__global__ void k_iso_pencil_table(const double2* __restrict__ nat, T* __restrict__ out, int lz, int ly, int lx,
+                                   int llb) {
+  const long long n8 = 8LL << (lz + ly + lx);
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 6 * n8) return;
+  const int lb = 1 << llb;
+  const int li = (int)(idx & (lb - 1));
+  const long long r = idx >> llb;
+  const int k = (int)(r % 6);
+  const long long r2 = r / 6;
+  const int kz = (int)(r2 & ((2 << lz) - 1));
+  const long long blk = r2 >> (lz + 1);          // ky * (2nx / lb) + kb
+  const int nkb = (2 << lx) >> llb;
+  const long long ky = blk / nkb, kb = blk - ky * nkb;
+  const long long src = k * n8 + (((long long)kz << (ly + 1)) + ky) * (2LL << lx) + (kb << llb) + li;
+  out[idx] = from_d<T>(nat[src]);
 }
 
 int ilog2_exact(long long v) {
@@ -262,12 +315,13 @@ struct psfd_iso_plan {
   double R = 0.0, k0 = 0.0;
   int device = 0;
   double2* tab64 = nullptr;  // [6][2nz][2ny][2nx]
-  float2* tab32 = nullptr;
+  double2* ptab64 = nullptr; // tab64 in the z-pencil order of the FP64 apply
+  float2* ptab32 = nullptr;  // FP32 rounding, in the z-pencil order of the FP32 apply
   double2* tw64 = nullptr;   // tw[m + i] = exp(-2 pi i i / m), m = 2 .. ISO_TW_MAX
   float2* tw32 = nullptr;
   void* work[2] = {nullptr, nullptr};  // W [3][nz][2ny][2nx] per dtype (C64, C128)
   ~psfd_iso_plan() {
-    for (void* q : {(void*)tab64, (void*)tab32, (void*)tw64, (void*)tw32, work[0], work[1]})
+    for (void* q : {(void*)tab64, (void*)ptab64, (void*)ptab32, (void*)tw64, (void*)tw32, work[0], work[1]})
       if (q) (void)hipFree(q);
   }
 };
@@ -284,8 +338,6 @@ namespace {
 
 Status bad(int code, const char* m) { Status s; s.code = code; s.msg = m; return s; }
 
-template <class T> int fft_e() { return FftBudget<T>::E; }
-
 // lines per block and threads of a line pass of FFT length 2^ln over nlines lines
 void line_shape(int ln, long long nlines, int e, int& lb, int& nthr) {
   lb = std::max(1, std::min(16, 4096 >> ln));
@@ -297,7 +349,7 @@ void line_shape(int ln, long long nlines, int e, int& lb, int& nthr) {
 template <class T, bool INV, int MODE, bool SFL, bool ZIN, bool ZOUT>
 Status run_lines(IsoLines a, hipStream_t s) {
   int lb, nthr;
-  line_shape(a.ln, a.nlines, fft_e<T>(), lb, nthr);
+  line_shape(a.ln, a.nlines, LFE, lb, nthr);
   a.lb = lb;
   a.llb = ilog2_exact(lb);
   const size_t bytes = ((size_t)lb << a.ln) * sizeof(T);
@@ -333,8 +385,26 @@ template <class T> T* tw_of(psfd_iso_plan* p);
 template <> double2* tw_of<double2>(psfd_iso_plan* p) { return p->tw64; }
 template <> float2* tw_of<float2>(psfd_iso_plan* p) { return p->tw32; }
 template <class T> const T* tab_of(psfd_iso_plan* p);
-template <> const double2* tab_of<double2>(psfd_iso_plan* p) { return p->tab64; }
-template <> const float2* tab_of<float2>(psfd_iso_plan* p) { return p->tab32; }
+template <> const double2* tab_of<double2>(psfd_iso_plan* p) { return p->ptab64; }
+template <> const float2* tab_of<float2>(psfd_iso_plan* p) { return p->ptab32; }
+
+// adjacent kx per z-pencil block: at most the cap below, the three padded z
+// sequences of all of them within 64 KB of LDS and at most ZFE values per
+// thread of 1024
+template <class T> int z_lb(int nz, int nx) {
+  // measured at 128 x 128 x 64 (widths 16, 8, 4): 8 in FP32, 4 in FP64 (more
+  // blocks per CU to cover the FFT barriers); PSFD_ISO_ZLB overrides (sweeps)
+  static const int cap = [] {
+    const char* e = std::getenv("PSFD_ISO_ZLB");
+    const int dflt = sizeof(T) == 8 ? 8 : 4;
+    const int v = e ? std::atoi(e) : dflt;
+    return v >= 1 && v <= 16 && (v & (v - 1)) == 0 ? v : dflt;
+  }();
+  int lb = std::min(cap, 2 * nx);
+  while (lb > 1 && ((long long)2 * nz * 3 * lb * (long long)sizeof(T) > 65536 || 2 * nz * 3 * lb > ZFE * 1024))
+    lb >>= 1;
+  return lb;
+}
 
 // stage -1: the whole apply; 0 .. 4: X_FWD, Y_FWD, Z_MUL, Y_INV, X_INV
 template <class T>
@@ -368,14 +438,14 @@ Status apply_t(psfd_iso_plan* p, const T* deps, const T* x, T* y, T* W, int stag
   if (stage < 0 || stage == 2) {
     IsoZ z{};
     z.w = W; z.table = tab_of<T>(p); z.lnz = lz; z.lnx2 = lx + 1;
-    // adjacent kx per block: at most 16, the three padded z sequences of all of
-    // them within 64 KB of LDS (so at most 8 values per thread in FP64)
-    z.lb = (int)std::min<long long>(16, 2 * nx);
-    while (z.lb > 1 && 2 * nz * 3 * z.lb * (long long)sizeof(T) > 65536) z.lb >>= 1;
+    z.lb = z_lb<T>((int)nz, (int)nx);
     z.llb = ilog2_exact(z.lb);
     z.plane = plane; z.n8 = 8 * nx * ny * nz; z.tw = tw;
     const int els = (int)(2 * nz) * 3 * z.lb;
-    const int nthr = std::min(1024, std::max(64, (els / fft_e<T>() + 63) / 64 * 64));
+    const int npts = (int)(2 * nz) * z.lb;
+    const int pre = Zpt<T>::v ? (npts / std::max(1, Zpt<T>::v) + 63) / 64 * 64 : 64;
+    const int nthr = std::min(1024, std::max({64, (els / ZFE + 63) / 64 * 64, pre}));
+    if (els > ZFE * nthr) return bad(PSFD_ERR_UNSUPPORTED_SIZE, "z pencil tile exceeds the FFT budget");
     const size_t bytes = (size_t)els * sizeof(T);
     auto fn = k_iso_zmul<T>;
     if (bytes > 65536) ISOCHK(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
@@ -468,7 +538,8 @@ Status iso_create(const psfd_iso_problem& pr, psfd_iso_plan*& out) {
   ISOCHK(hipMalloc((void**)&g, 6 * Mtot * sizeof(double2)));
   struct Free { double2* q; ~Free() { if (q) (void)hipFree(q); } } fg{g};
   ISOCHK(hipMalloc((void**)&p->tab64, 6 * n8 * sizeof(double2)));
-  ISOCHK(hipMalloc((void**)&p->tab32, 6 * n8 * sizeof(float2)));
+  ISOCHK(hipMalloc((void**)&p->ptab64, 6 * n8 * sizeof(double2)));
+  ISOCHK(hipMalloc((void**)&p->ptab32, 6 * n8 * sizeof(float2)));
   IsoSample smp{};
   smp.g = g; smp.l0 = lo[0]; smp.l1 = lo[1]; smp.l2 = lo[2];
   smp.dk0 = 2.0 * M_PI / ((double)(1 << lo[0]) * hh[0]);
@@ -486,7 +557,10 @@ Status iso_create(const psfd_iso_problem& pr, psfd_iso_plan*& out) {
   ISOCHK(hipGetLastError());
   st = fft3_c<false>(p->tab64, 6, p->ln[0] + 1, p->ln[1] + 1, p->ln[2] + 1, p->tw64, s);
   if (!st.ok()) return st;
-  hipLaunchKernelGGL(k_iso_to32, dim3((unsigned)((6 * n8 + 255) / 256)), dim3(256), 0, s, p->tab64, p->tab32, 6 * n8);
+  hipLaunchKernelGGL(k_iso_pencil_table<double2>, dim3((unsigned)((6 * n8 + 255) / 256)), dim3(256), 0, s, p->tab64,
+                     p->ptab64, p->ln[0], p->ln[1], p->ln[2], ilog2_exact(z_lb<double2>(nn[0], nn[2])));
+  hipLaunchKernelGGL(k_iso_pencil_table<float2>, dim3((unsigned)((6 * n8 + 255) / 256)), dim3(256), 0, s, p->tab64,
+                     p->ptab32, p->ln[0], p->ln[1], p->ln[2], ilog2_exact(z_lb<float2>(nn[0], nn[2])));
   ISOCHK(hipGetLastError());
   ISOCHK(hipStreamSynchronize(s));
   out = p.release();
