@@ -15,8 +15,9 @@ R where R^2 belongs, and the printed A(0) lacks the factor 4 pi; both readings
 are pinned by a radial quadrature of the windowed kernel (tests). With the
 corrections, A(0) is the k -> 0 limit of A(k), and B(k) -> 0 there.
 
-Below the kernel: its real-space samples by the 4x-oversampled precompute and
-the isolated-domain apply with padding by 2 on all three axes. None of this is
+Below the kernel: its real-space samples by the oversampled precompute (4x, or
+more along an axis where the ball of radius R needs a longer period) and the
+isolated-domain apply with padding by 2 on all three axes. None of this is
 on the periodic hot path.
 """
 from __future__ import annotations
