@@ -156,3 +156,19 @@ def apply_isolated(table: np.ndarray, vol: np.ndarray, x: np.ndarray) -> np.ndar
     wh = np.einsum("zyxij,jzyx->izyx", table, fh)
     w = np.fft.ifftn(wh, axes=(1, 2, 3))[:, :nz, :ny, :nx]
     return x - w
+
+
+def solve_isolated_dense(table: np.ndarray, vol: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """u with u - P IFFT(table . FFT(Z (vol u))) = b (eq. (18) for the isolated
+    scatterer with right-hand side b): the operator is assembled column by
+    column by applying it to unit vectors, then solved by LU. Small grids only
+    (3 N unknowns, a dense 3N x 3N matrix)."""
+    shape = b.shape
+    n = b.size
+    A = np.empty((n, n), dtype=complex)
+    e = np.zeros(n, dtype=complex)
+    for j in range(n):
+        e[j] = 1.0
+        A[:, j] = apply_isolated(table, vol, e.reshape(shape)).ravel()
+        e[j] = 0.0
+    return np.linalg.solve(A, b.ravel()).reshape(shape)
