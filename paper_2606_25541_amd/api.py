@@ -276,6 +276,20 @@ class IsoPlan:
 
     apply = psfd_iso_apply
 
+    def psfd_iso_solve(self, deps: torch.Tensor, b: torch.Tensor, rtol: float = 1e-8, restart: int = 30,
+                       max_iters: int = 2000, out: Optional[torch.Tensor] = None):
+        """u with u - K(V u) = b (FP64 GMRES); returns (u, info dict)."""
+        if b.dtype != torch.complex128:
+            raise ValueError("b must be complex128")
+        _, out = self._check(deps, b, out)
+        info = L.psfd_info()
+        L.check(L.lib().psfd_iso_solve(self._h, C.c_void_p(deps.data_ptr()), C.c_void_p(b.data_ptr()),
+                                       C.c_void_p(out.data_ptr()), float(rtol), int(restart), int(max_iters),
+                                       C.byref(info), _stream()), "psfd_iso_solve")
+        return out, info.as_dict()
+
+    solve = psfd_iso_solve
+
     def psfd_iso_table(self):
         """(table complex128 [6][2nz][2ny][2nx] on the device, (o_z, o_y, o_x), R)."""
         t = torch.empty((6, 2 * self.nz, 2 * self.ny, 2 * self.nx), dtype=torch.complex128, device="cuda")

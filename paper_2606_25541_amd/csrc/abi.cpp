@@ -318,6 +318,21 @@ int psfd_iso_apply(psfd_iso_plan* plan, const void* d_deps, const void* d_x, voi
   return st.ok() ? PSFD_OK : fail(st);
 }
 
+int psfd_iso_solve(psfd_iso_plan* plan, const void* d_deps, const void* d_b, void* d_u, double rtol, int32_t restart,
+                   int32_t max_iters, psfd_info* info, void* stream) {
+  if (!plan || !d_deps || !d_b || !d_u) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  if (d_b == d_u) return fail(PSFD_ERR_INVALID_ARG, "d_u must not alias d_b");
+  psfd_info inf{};
+  Status st = iso_solve(plan, d_deps, d_b, d_u, rtol, restart, max_iters, &inf, (hipStream_t)stream);
+  if (info) *info = inf;
+  if (!st.ok()) return fail(st);
+  if (inf.status == PSFD_NOT_CONVERGED) {
+    g_last_error = "iteration limit reached";
+    return PSFD_NOT_CONVERGED;
+  }
+  return PSFD_OK;
+}
+
 int psfd_iso_table(psfd_iso_plan* plan, void* d_table, int32_t* over, double* radius_nm, void* stream) {
   if (!plan) return fail(PSFD_ERR_INVALID_ARG, "NULL plan");
   Status st = iso_table(plan, d_table, over, radius_nm, (hipStream_t)stream);

@@ -298,6 +298,76 @@ __global__ void k_iso_pencil_table(const double2* __restrict__ nat, T* __restric
   out[idx] = from_d<T>(nat[src]);
 }
 
+// ---------------------------------------------------------------------------
+// Krylov kernels of the isolated-domain GMRES (FP64). Reductions run in a
+// fixed order (block partials, then one block per sum), so a solve is
+// deterministic.
+
+constexpr int KB = 256;      // threads per block
+constexpr int KNB = 1024;    // blocks of a reduction pass
+
+// part[i * KNB + blk] = sum over the block's chunk of conj(V_i) w, i < nv
+__global__ void k_iso_dots(const double2* __restrict__ V, long long stride, const double2* __restrict__ w,
+                           long long n, double2* __restrict__ part) {
+  __shared__ double2 red[KB];
+  const int i = blockIdx.y;
+  const double2* v = V + i * stride;
+  double2 acc = make_double2(0.0, 0.0);
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)KNB * KB) {
+    const double2 a = v[e], b = w[e];
+    acc.x += a.x * b.x + a.y * b.y;
+    acc.y += a.x * b.y - a.y * b.x;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = KB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long long)i * KNB + blockIdx.x] = red[0];
+}
+
+// out[i] = sum of the KNB partials of i (one block per i, fixed order)
+__global__ void k_iso_sum(const double2* __restrict__ part, double2* __restrict__ out) {
+  __shared__ double2 red[KB];
+  const int i = blockIdx.x;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int b = threadIdx.x; b < KNB; b += KB) acc = cadd(acc, part[(long long)i * KNB + b]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = KB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
+}
+
+// w += sgn sum_{i < nv} coef[i] V_i
+__global__ void k_iso_axpys(double2* __restrict__ w, const double2* __restrict__ V, long long stride,
+                            const double2* __restrict__ coef, int nv, long long n, double sgn) {
+  const long long e = (long long)blockIdx.x * KB + threadIdx.x;
+  if (e >= n) return;
+  double2 acc = w[e];
+  for (int i = 0; i < nv; ++i) {
+    const double2 c = coef[i], v = V[i * stride + e];
+    acc.x += sgn * (c.x * v.x - c.y * v.y);
+    acc.y += sgn * (c.x * v.y + c.y * v.x);
+  }
+  w[e] = acc;
+}
+
+// out = a + s b (s real)
+__global__ void k_iso_comb(const double2* __restrict__ a, const double2* __restrict__ b, double s,
+                           double2* __restrict__ out, long long n) {
+  const long long e = (long long)blockIdx.x * KB + threadIdx.x;
+  if (e < n) out[e] = make_double2(a[e].x + s * b[e].x, a[e].y + s * b[e].y);
+}
+
+__global__ void k_iso_scale(const double2* a, double s, double2* out, long long n) {  // a may equal out
+  const long long e = (long long)blockIdx.x * KB + threadIdx.x;
+  if (e < n) out[e] = cscale(a[e], s);
+}
+
 int ilog2_exact(long long v) {
   int r = 0;
   while ((1LL << r) < v) ++r;
@@ -600,6 +670,135 @@ Status iso_table(psfd_iso_plan* p, void* d_table, int32_t* over, double* radius,
   if (over)
     for (int a = 0; a < 3; ++a) over[a] = p->over[a];
   if (radius) *radius = p->R;
+  return Status();
+}
+
+
+// GMRES(m) on y = x - K(V x) (Saad & Schultz), FP64, x0 = 0: classical
+// Gram-Schmidt with a second pass, Givens rotations and the small
+// Hessenberg system on the host (one apply per step costs far more than the
+// few host round trips), every restart from the FP64 residual b - A x.
+Status iso_solve(psfd_iso_plan* p, const void* deps, const void* b, void* u, double rtol, int m, int max_iters,
+                 psfd_info* info, hipStream_t s) {
+  typedef std::complex<double> cd;
+  if (!(rtol > 0.0) || m < 1 || m > 64 || max_iters < 1)
+    return bad(PSFD_ERR_INVALID_ARG, "need rtol > 0, 1 <= restart <= 64, max_iters >= 1");
+  int dev = 0;
+  ISOCHK(hipGetDevice(&dev));
+  if (dev != p->device) return bad(PSFD_ERR_INVALID_ARG, "plan belongs to another device");
+  const long long n = 3LL * p->n[0] * p->n[1] * p->n[2];
+  double2 *V = nullptr, *w = nullptr, *part = nullptr, *hd = nullptr;
+  struct Free {
+    double2** q[4];
+    ~Free() { for (auto* a : q) if (*a) (void)hipFree(*a); }
+  } fr{{&V, &w, &part, &hd}};
+  ISOCHK(hipMalloc((void**)&V, (size_t)(m + 1) * n * sizeof(double2)));
+  ISOCHK(hipMalloc((void**)&w, (size_t)n * sizeof(double2)));
+  ISOCHK(hipMalloc((void**)&part, (size_t)KNB * (m + 1) * sizeof(double2)));
+  ISOCHK(hipMalloc((void**)&hd, (size_t)(m + 1) * sizeof(double2)));
+  const unsigned g1 = (unsigned)((n + KB - 1) / KB);
+  const double2* B = (const double2*)b;
+  double2* X = (double2*)u;
+  std::vector<cd> hv(m + 1);
+  // hv[0..nv) = V_i^H x
+  auto dots = [&](const double2* Vb, int nv, const double2* x) -> Status {
+    hipLaunchKernelGGL(k_iso_dots, dim3(KNB, nv), dim3(KB), 0, s, Vb, n, x, n, part);
+    hipLaunchKernelGGL(k_iso_sum, dim3(nv), dim3(KB), 0, s, part, hd);
+    ISOCHK(hipGetLastError());
+    ISOCHK(hipMemcpyAsync(hv.data(), hd, nv * sizeof(double2), hipMemcpyDeviceToHost, s));
+    ISOCHK(hipStreamSynchronize(s));
+    return Status();
+  };
+  // x += sgn sum_i c[i] V_i
+  auto axpys = [&](double2* x, const double2* Vb, const std::vector<cd>& c, int nv, double sgn) -> Status {
+    ISOCHK(hipMemcpyAsync(hd, c.data(), nv * sizeof(double2), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_iso_axpys, dim3(g1), dim3(KB), 0, s, x, Vb, n, (const double2*)hd, nv, n, sgn);
+    ISOCHK(hipGetLastError());
+    ISOCHK(hipStreamSynchronize(s));  // c may change before the next call
+    return Status();
+  };
+  auto norm = [&](const double2* x, double& out) -> Status {
+    Status st = dots(x, 1, x);
+    out = std::sqrt(std::max(hv[0].real(), 0.0));
+    return st;
+  };
+  Status st;
+  ISOCHK(hipMemsetAsync(X, 0, n * sizeof(double2), s));
+  double bnorm = 0.0;
+  if (!(st = norm(B, bnorm)).ok()) return st;
+  psfd_info inf{};
+  inf.outer_iters = 1;
+  inf.status = PSFD_NOT_CONVERGED;
+  if (!std::isfinite(bnorm)) return bad(PSFD_ERR_NONFINITE, "right-hand side is not finite");
+  if (bnorm == 0.0) {
+    inf.status = PSFD_OK;
+    if (info) *info = inf;
+    ISOCHK(hipStreamSynchronize(s));
+    return Status();
+  }
+  double beta = bnorm, rel = 1.0;
+  hipLaunchKernelGGL(k_iso_scale, dim3(g1), dim3(KB), 0, s, B, 1.0 / beta, V, n);
+  std::vector<cd> H((size_t)(m + 1) * m), g(m + 1), sn(m), h1(m + 1), y(m);
+  std::vector<double> cs(m);
+  auto Hij = [&](int i, int j) -> cd& { return H[(size_t)i * m + j]; };
+  while (inf.iters < max_iters) {
+    ++inf.cycles;
+    std::fill(H.begin(), H.end(), cd(0.0));
+    std::fill(g.begin(), g.end(), cd(0.0));
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m && inf.iters < max_iters; ++j) {
+      if (!(st = iso_apply(p, deps, V + j * n, w, PSFD_C128, -1, s)).ok()) return st;
+      // two classical Gram-Schmidt passes
+      for (int pass = 0; pass < 2; ++pass) {
+        if (!(st = dots(V, j + 1, w)).ok()) return st;
+        for (int i = 0; i <= j; ++i) { h1[i] = hv[i]; Hij(i, j) += hv[i]; }
+        if (!(st = axpys(w, V, h1, j + 1, -1.0)).ok()) return st;
+      }
+      double hn = 0.0;
+      if (!(st = norm(w, hn)).ok()) return st;
+      if (!std::isfinite(hn)) return bad(PSFD_ERR_NONFINITE, "non-finite Krylov vector");
+      Hij(j + 1, j) = hn;
+      ++inf.iters;
+      k = j + 1;
+      for (int i = 0; i < j; ++i) {  // previous rotations
+        const cd a = Hij(i, j), c2 = Hij(i + 1, j);
+        Hij(i, j) = cs[i] * a + sn[i] * c2;
+        Hij(i + 1, j) = -std::conj(sn[i]) * a + cs[i] * c2;
+      }
+      const cd a = Hij(j, j);
+      const double bb = hn, r = std::sqrt(std::norm(a) + bb * bb);
+      if (r == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
+      else if (std::abs(a) == 0.0) { cs[j] = 0.0; sn[j] = 1.0; }
+      else { cs[j] = std::abs(a) / r; sn[j] = (a / std::abs(a)) * bb / r; }
+      Hij(j, j) = cs[j] * a + sn[j] * bb;
+      Hij(j + 1, j) = 0.0;
+      g[j + 1] = -std::conj(sn[j]) * g[j];
+      g[j] = cs[j] * g[j];
+      if (hn > 0.0) hipLaunchKernelGGL(k_iso_scale, dim3(g1), dim3(KB), 0, s, w, 1.0 / hn, V + (j + 1) * n, n);
+      if (std::abs(g[j + 1]) <= rtol * bnorm || hn == 0.0) break;
+    }
+    for (int i = k - 1; i >= 0; --i) {  // back substitution
+      cd acc = g[i];
+      for (int l = i + 1; l < k; ++l) acc -= Hij(i, l) * y[l];
+      y[i] = acc / Hij(i, i);
+    }
+    std::vector<cd> yk(y.begin(), y.begin() + k);
+    if (!(st = axpys(X, V, yk, k, 1.0)).ok()) return st;
+    // FP64 residual r = b - A x into slot 0
+    if (!(st = iso_apply(p, deps, X, w, PSFD_C128, -1, s)).ok()) return st;
+    hipLaunchKernelGGL(k_iso_comb, dim3(g1), dim3(KB), 0, s, B, w, -1.0, V, n);
+    if (!(st = norm(V, beta)).ok()) return st;
+    rel = beta / bnorm;
+    if (!std::isfinite(rel)) return bad(PSFD_ERR_NONFINITE, "non-finite residual");
+    if (rel <= rtol) { inf.status = PSFD_OK; break; }
+    hipLaunchKernelGGL(k_iso_scale, dim3(g1), dim3(KB), 0, s, V, 1.0 / beta, V, n);
+  }
+  inf.rel_residual = rel;
+  inf.mono_residual = rel;
+  ISOCHK(hipGetLastError());
+  ISOCHK(hipStreamSynchronize(s));
+  if (info) *info = inf;
   return Status();
 }
 

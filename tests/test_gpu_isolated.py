@@ -156,3 +156,77 @@ def test_isolated_apply_full_size_properties():
     d = ((y32 - y64).abs().max() / (y64 - a.to(torch.complex128)).abs().max()).item()
     say("  fp32 vs fp64", d)
     assert d <= 2e-5
+
+
+def test_isolated_solve_matches_dense_oracle():
+    """FP64 GMRES on the isolated system vs the oracle's dense LU solve (3 x 2 x 4 x 8
+    unknowns, lossy background, strong random contrast), with restarts."""
+    dev = device()
+    shape, spacing, eps = (2, 4, 8), (1.0, 2.0, 1.5), 1.0 + 0.02j
+    R = float(np.sqrt(sum((n * h) ** 2 for n, h in zip(shape, spacing))))
+    ref_t, _ = oracle_table(shape, spacing, eps, R)
+    plan = iso_plan(shape, spacing, eps)
+    rng = np.random.default_rng(21)
+    de = -0.3 + 0.2 * rng.normal(size=shape) + 0.06j
+    b = clips.random_complex((3,) + shape, seed=22)
+    say("isolated solve", shape)
+    u, info = plan.solve(torch.from_numpy(de).to(dev), torch.from_numpy(b).to(dev), rtol=1e-13, restart=6,
+                         max_iters=400)
+    torch.cuda.synchronize()
+    say("  info", info)
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-13 and info["cycles"] > 1
+    k0 = 2 * np.pi / LAM
+    ref = I.solve_isolated_dense(ref_t, k0 * k0 * de, b)
+    err = np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref)
+    say("  rel err", err)
+    assert err <= 1e-10
+
+
+def test_isolated_solve_medium_residual_by_oracle():
+    """32 x 32 x 16 contact holes over the 256 x 256 x 60 nm block, b a normally
+    incident plane wave polarised along y: the oracle's apply confirms the GPU
+    solution's residual."""
+    dev = device()
+    shape, spacing = (16, 32, 32), (60.0 / 16, 8.0, 8.0)
+    R = float(np.sqrt(sum((n * h) ** 2 for n, h in zip(shape, spacing))))
+    ref_t, _ = oracle_table(shape, spacing, 1.0, R)
+    plan = iso_plan(shape, spacing, 1.0)
+    de = clips.contact_holes(32, 32, 16, 256.0, 256.0, 4, seed=7).astype(np.complex128)
+    k0 = 2 * np.pi / LAM
+    z = (np.arange(16) * spacing[0])[:, None, None] * np.ones((1, 32, 32))
+    b = np.zeros((3,) + shape, dtype=complex)
+    b[1] = np.exp(1j * k0 * z)
+    say("isolated solve medium", shape)
+    u, info = plan.solve(torch.from_numpy(de).to(dev), torch.from_numpy(b).to(dev), rtol=1e-10, restart=20)
+    torch.cuda.synchronize()
+    say("  info", info)
+    assert info["status"] == 0
+    un = u.cpu().numpy()
+    r = b - I.apply_isolated(ref_t, k0 * k0 * de, un)
+    rel = np.linalg.norm(r) / np.linalg.norm(b)
+    say("  oracle residual", rel)
+    assert rel <= 1e-9
+
+
+def test_isolated_solve_edge_cases():
+    """b = 0 gives u = 0 without a step; zero contrast gives u = b in one step; an
+    iteration limit returns NOT_CONVERGED with the iterate written."""
+    from paper_2606_25541_amd import _lib as L
+    import ctypes as C
+    dev = device()
+    shape, spacing = (4, 8, 8), (1.0, 2.0, 2.0)
+    plan = iso_plan(shape, spacing, 1.0 + 0.01j)
+    b = torch.from_numpy(clips.random_complex((3,) + shape, seed=3)).to(dev)
+    de = torch.from_numpy(clips.random_complex(shape, seed=4) * 0.3).to(dev)
+    u, info = plan.solve(de, torch.zeros_like(b), rtol=1e-10)
+    assert info["status"] == 0 and info["iters"] == 0 and torch.count_nonzero(u).item() == 0
+    u, info = plan.solve(torch.zeros_like(de), b, rtol=1e-12)
+    assert info["status"] == 0 and info["iters"] == 1
+    assert ((u - b).abs().max() / b.abs().max()).item() <= 1e-14
+    u = torch.empty_like(b)
+    inf = L.psfd_info()
+    code = L.lib().psfd_iso_solve(plan._h, C.c_void_p(de.data_ptr()), C.c_void_p(b.data_ptr()),
+                                  C.c_void_p(u.data_ptr()), 1e-14, 4, 3, C.byref(inf), None)
+    torch.cuda.synchronize()
+    assert code == L.PSFD_NOT_CONVERGED and inf.iters == 3 and inf.status == L.PSFD_NOT_CONVERGED
+    assert 0 < inf.rel_residual < 1 and torch.isfinite(u.abs()).all()
