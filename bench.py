@@ -333,17 +333,19 @@ def sec_isolated(ctx, args, out):
                        "kernel_source_hash": kernel_source_hash(ISO_SOURCES)}
     res["vs_periodic_apply_fp32"] = (res["fp32"]["us_per_apply"] / out["apply"]["fp32"]["us_per_apply"]
                                      if "apply" in out else None)
-    # FP64 GMRES(20) to 1e-6 with b the normally incident plane wave polarised along y
+    # GMRES(20) to 1e-6 (FP64, and mixed: FP32 cycles with FP64 restarts) with b the normally
+    # incident plane wave polarised along y
     k0 = 2 * math.pi / prob.wavelength_nm
     zz = torch.arange(nz, dtype=torch.float64, device=dev) * spacing[0]
     b = torch.zeros((3, nz, ny, nx), dtype=torch.complex128, device=dev)
     b[1] = torch.exp(1j * k0 * zz)[:, None, None].expand(nz, ny, nx)
     u = torch.empty_like(b)
-    plan.solve(ctx["deps"], b, rtol=1e-6, restart=20, out=u)
-    ts, (_, inf) = timed(lambda: plan.solve(ctx["deps"], b, rtol=1e-6, restart=20, out=u), 2)
-    res["solve_fp64"] = {"ms_per_solve": 1e3 * ts, "iters": inf["iters"], "cycles": inf["cycles"],
-                         "rel_residual": inf["rel_residual"], "rhs": "plane wave along z, E along y",
-                         "restart": 20, "rtol": 1e-6}
+    for prec in ("fp64", "mixed"):
+        plan.solve(ctx["deps"], b, rtol=1e-6, restart=20, out=u, precision=prec)
+        ts, (_, inf) = timed(lambda: plan.solve(ctx["deps"], b, rtol=1e-6, restart=20, out=u, precision=prec), 2)
+        res["solve_" + prec] = {"ms_per_solve": 1e3 * ts, "iters": inf["iters"], "cycles": inf["cycles"],
+                                "rel_residual": inf["rel_residual"], "rhs": "plane wave along z, E along y",
+                                "restart": 20, "rtol": 1e-6}
     out["isolated"] = res
     log("bench: isolated", res)
     if args.only == "isolated":

@@ -87,7 +87,7 @@ EXPORTS = {
     "psfd_iso_plan_destroy": (None, [C.c_void_p]),
     "psfd_iso_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "psfd_iso_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
-                                 C.POINTER(psfd_info), C.c_void_p]),
+                                 C.c_int32, C.POINTER(psfd_info), C.c_void_p]),
     "psfd_iso_table": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                  C.c_void_p]),
     "psfd_iso_bench_stage": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,

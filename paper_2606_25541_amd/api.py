@@ -277,15 +277,16 @@ class IsoPlan:
     apply = psfd_iso_apply
 
     def psfd_iso_solve(self, deps: torch.Tensor, b: torch.Tensor, rtol: float = 1e-8, restart: int = 30,
-                       max_iters: int = 2000, out: Optional[torch.Tensor] = None):
-        """u with u - K(V u) = b (FP64 GMRES); returns (u, info dict)."""
+                       max_iters: int = 2000, out: Optional[torch.Tensor] = None, precision: str = "fp64"):
+        """u with u - K(V u) = b by GMRES (precision "fp64" or "mixed"); returns (u, info dict)."""
         if b.dtype != torch.complex128:
             raise ValueError("b must be complex128")
         _, out = self._check(deps, b, out)
         info = L.psfd_info()
         L.check(L.lib().psfd_iso_solve(self._h, C.c_void_p(deps.data_ptr()), C.c_void_p(b.data_ptr()),
                                        C.c_void_p(out.data_ptr()), float(rtol), int(restart), int(max_iters),
-                                       C.byref(info), _stream()), "psfd_iso_solve")
+                                       {"fp64": L.PSFD_FP64, "mixed": L.PSFD_MIXED}[precision], C.byref(info),
+                                       _stream()), "psfd_iso_solve")
         return out, info.as_dict()
 
     solve = psfd_iso_solve

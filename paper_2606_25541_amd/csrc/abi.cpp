@@ -319,11 +319,11 @@ int psfd_iso_apply(psfd_iso_plan* plan, const void* d_deps, const void* d_x, voi
 }
 
 int psfd_iso_solve(psfd_iso_plan* plan, const void* d_deps, const void* d_b, void* d_u, double rtol, int32_t restart,
-                   int32_t max_iters, psfd_info* info, void* stream) {
+                   int32_t max_iters, int32_t precision, psfd_info* info, void* stream) {
   if (!plan || !d_deps || !d_b || !d_u) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
   if (d_b == d_u) return fail(PSFD_ERR_INVALID_ARG, "d_u must not alias d_b");
   psfd_info inf{};
-  Status st = iso_solve(plan, d_deps, d_b, d_u, rtol, restart, max_iters, &inf, (hipStream_t)stream);
+  Status st = iso_solve(plan, d_deps, d_b, d_u, rtol, restart, max_iters, precision, &inf, (hipStream_t)stream);
   if (info) *info = inf;
   if (!st.ok()) return fail(st);
   if (inf.status == PSFD_NOT_CONVERGED) {

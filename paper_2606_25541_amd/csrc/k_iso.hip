@@ -26,6 +26,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <type_traits>
 #include <vector>
 
 #include "engine.hpp"
@@ -307,14 +308,16 @@ constexpr int KB = 256;      // threads per block
 constexpr int KNB = 1024;    // blocks of a reduction pass
 
 // part[i * KNB + blk] = sum over the block's chunk of conj(V_i) w, i < nv
-__global__ void k_iso_dots(const double2* __restrict__ V, long long stride, const double2* __restrict__ w,
-                           long long n, double2* __restrict__ part) {
+// (accumulated in FP64 whatever the storage type)
+template <class TV, class TW>
+__global__ void k_iso_dots(const TV* __restrict__ V, long long stride, const TW* __restrict__ w, long long n,
+                           double2* __restrict__ part) {
   __shared__ double2 red[KB];
   const int i = blockIdx.y;
-  const double2* v = V + i * stride;
+  const TV* v = V + i * stride;
   double2 acc = make_double2(0.0, 0.0);
   for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)KNB * KB) {
-    const double2 a = v[e], b = w[e];
+    const double2 a = to_d(v[e]), b = to_d(w[e]);
     acc.x += a.x * b.x + a.y * b.y;
     acc.y += a.x * b.y - a.y * b.x;
   }
@@ -342,18 +345,19 @@ __global__ void k_iso_sum(const double2* __restrict__ part, double2* __restrict_
   if (threadIdx.x == 0) out[i] = red[0];
 }
 
-// w += sgn sum_{i < nv} coef[i] V_i
-__global__ void k_iso_axpys(double2* __restrict__ w, const double2* __restrict__ V, long long stride,
+// w += sgn sum_{i < nv} coef[i] V_i (in FP64, stored in w's type)
+template <class TW, class TV>
+__global__ void k_iso_axpys(TW* __restrict__ w, const TV* __restrict__ V, long long stride,
                             const double2* __restrict__ coef, int nv, long long n, double sgn) {
   const long long e = (long long)blockIdx.x * KB + threadIdx.x;
   if (e >= n) return;
-  double2 acc = w[e];
+  double2 acc = to_d(w[e]);
   for (int i = 0; i < nv; ++i) {
-    const double2 c = coef[i], v = V[i * stride + e];
+    const double2 c = coef[i], v = to_d(V[i * stride + e]);
     acc.x += sgn * (c.x * v.x - c.y * v.y);
     acc.y += sgn * (c.x * v.y + c.y * v.x);
   }
-  w[e] = acc;
+  w[e] = from_d<TW>(acc);
 }
 
 // out = a + s b (s real)
@@ -363,9 +367,11 @@ __global__ void k_iso_comb(const double2* __restrict__ a, const double2* __restr
   if (e < n) out[e] = make_double2(a[e].x + s * b[e].x, a[e].y + s * b[e].y);
 }
 
-__global__ void k_iso_scale(const double2* a, double s, double2* out, long long n) {  // a may equal out
+// out = s a, converted to out's type (a may equal out)
+template <class TA, class TO>
+__global__ void k_iso_scale(const TA* a, double s, TO* out, long long n) {
   const long long e = (long long)blockIdx.x * KB + threadIdx.x;
-  if (e < n) out[e] = cscale(a[e], s);
+  if (e < n) out[e] = from_d<TO>(cscale(to_d(a[e]), s));
 }
 
 int ilog2_exact(long long v) {
@@ -674,35 +680,56 @@ Status iso_table(psfd_iso_plan* p, void* d_table, int32_t* over, double* radius,
 }
 
 
-// GMRES(m) on y = x - K(V x) (Saad & Schultz), FP64, x0 = 0: classical
-// Gram-Schmidt with a second pass, Givens rotations and the small
-// Hessenberg system on the host (one apply per step costs far more than the
-// few host round trips), every restart from the FP64 residual b - A x.
-Status iso_solve(psfd_iso_plan* p, const void* deps, const void* b, void* u, double rtol, int m, int max_iters,
-                 psfd_info* info, hipStream_t s) {
+// GMRES(m) on y = x - K(V x) (Saad & Schultz) from x0 = 0, the basis and the
+// operator applies in T: classical Gram-Schmidt with a second pass, Givens
+// rotations and the small Hessenberg system on the host (one apply per step
+// costs far more than the few host round trips). Every restart starts from the
+// FP64 residual b - A x, and x accumulates in FP64. With an FP32 basis (mixed
+// precision) a cycle also ends once it has reduced the residual estimate by
+// ETA_MIXED, since FP32 Arnoldi cannot go much further.
+namespace {
+
+constexpr double ETA_MIXED = 1e-4;
+
+template <class T>
+Status iso_solve_t(psfd_iso_plan* p, const double2* deps, const double2* B, double2* X, double rtol, int m,
+                   int max_iters, psfd_info& inf, hipStream_t s) {
   typedef std::complex<double> cd;
-  if (!(rtol > 0.0) || m < 1 || m > 64 || max_iters < 1)
-    return bad(PSFD_ERR_INVALID_ARG, "need rtol > 0, 1 <= restart <= 64, max_iters >= 1");
-  int dev = 0;
-  ISOCHK(hipGetDevice(&dev));
-  if (dev != p->device) return bad(PSFD_ERR_INVALID_ARG, "plan belongs to another device");
-  const long long n = 3LL * p->n[0] * p->n[1] * p->n[2];
-  double2 *V = nullptr, *w = nullptr, *part = nullptr, *hd = nullptr;
+  const bool f32 = sizeof(T) == 8;
+  const long long N = (long long)p->n[0] * p->n[1] * p->n[2], n = 3 * N;
+  T *V = nullptr, *w = nullptr, *depsT = nullptr;
+  double2 *w64 = nullptr, *r64 = nullptr, *part = nullptr, *hd = nullptr;
   struct Free {
-    double2** q[4];
-    ~Free() { for (auto* a : q) if (*a) (void)hipFree(*a); }
-  } fr{{&V, &w, &part, &hd}};
-  ISOCHK(hipMalloc((void**)&V, (size_t)(m + 1) * n * sizeof(double2)));
-  ISOCHK(hipMalloc((void**)&w, (size_t)n * sizeof(double2)));
+    void* q[7];
+    ~Free() { for (void* a : q) if (a) (void)hipFree(a); }
+  };
+  ISOCHK(hipMalloc((void**)&V, (size_t)(m + 1) * n * sizeof(T)));
+  Free fr{{V}};
+  ISOCHK(hipMalloc((void**)&w, (size_t)n * sizeof(T)));
+  fr.q[1] = w;
+  ISOCHK(hipMalloc((void**)&w64, (size_t)n * sizeof(double2)));
+  fr.q[2] = w64;
+  ISOCHK(hipMalloc((void**)&r64, (size_t)n * sizeof(double2)));
+  fr.q[3] = r64;
   ISOCHK(hipMalloc((void**)&part, (size_t)KNB * (m + 1) * sizeof(double2)));
+  fr.q[4] = part;
   ISOCHK(hipMalloc((void**)&hd, (size_t)(m + 1) * sizeof(double2)));
+  fr.q[5] = hd;
   const unsigned g1 = (unsigned)((n + KB - 1) / KB);
-  const double2* B = (const double2*)b;
-  double2* X = (double2*)u;
+  const int dt = f32 ? PSFD_C64 : PSFD_C128;
+  if (f32) {
+    ISOCHK(hipMalloc((void**)&depsT, (size_t)N * sizeof(T)));
+    fr.q[6] = depsT;
+    hipLaunchKernelGGL((k_iso_scale<double2, T>), dim3((unsigned)((N + KB - 1) / KB)), dim3(KB), 0, s, deps, 1.0,
+                       depsT, N);
+  }
+  const void* dA = f32 ? (const void*)depsT : (const void*)deps;
   std::vector<cd> hv(m + 1);
   // hv[0..nv) = V_i^H x
-  auto dots = [&](const double2* Vb, int nv, const double2* x) -> Status {
-    hipLaunchKernelGGL(k_iso_dots, dim3(KNB, nv), dim3(KB), 0, s, Vb, n, x, n, part);
+  auto dots = [&](auto Vb, int nv, auto x) -> Status {
+    typedef std::remove_cv_t<std::remove_pointer_t<decltype(Vb)>> TV;
+    typedef std::remove_cv_t<std::remove_pointer_t<decltype(x)>> TX;
+    hipLaunchKernelGGL((k_iso_dots<TV, TX>), dim3(KNB, nv), dim3(KB), 0, s, Vb, n, x, n, part);
     hipLaunchKernelGGL(k_iso_sum, dim3(nv), dim3(KB), 0, s, part, hd);
     ISOCHK(hipGetLastError());
     ISOCHK(hipMemcpyAsync(hv.data(), hd, nv * sizeof(double2), hipMemcpyDeviceToHost, s));
@@ -710,14 +737,15 @@ Status iso_solve(psfd_iso_plan* p, const void* deps, const void* b, void* u, dou
     return Status();
   };
   // x += sgn sum_i c[i] V_i
-  auto axpys = [&](double2* x, const double2* Vb, const std::vector<cd>& c, int nv, double sgn) -> Status {
+  auto axpys = [&](auto x, const T* Vb, const std::vector<cd>& c, int nv, double sgn) -> Status {
+    typedef std::remove_pointer_t<decltype(x)> TX;
     ISOCHK(hipMemcpyAsync(hd, c.data(), nv * sizeof(double2), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_iso_axpys, dim3(g1), dim3(KB), 0, s, x, Vb, n, (const double2*)hd, nv, n, sgn);
+    hipLaunchKernelGGL((k_iso_axpys<TX, T>), dim3(g1), dim3(KB), 0, s, x, Vb, n, (const double2*)hd, nv, n, sgn);
     ISOCHK(hipGetLastError());
     ISOCHK(hipStreamSynchronize(s));  // c may change before the next call
     return Status();
   };
-  auto norm = [&](const double2* x, double& out) -> Status {
+  auto norm = [&](auto x, double& out) -> Status {
     Status st = dots(x, 1, x);
     out = std::sqrt(std::max(hv[0].real(), 0.0));
     return st;
@@ -726,18 +754,14 @@ Status iso_solve(psfd_iso_plan* p, const void* deps, const void* b, void* u, dou
   ISOCHK(hipMemsetAsync(X, 0, n * sizeof(double2), s));
   double bnorm = 0.0;
   if (!(st = norm(B, bnorm)).ok()) return st;
-  psfd_info inf{};
-  inf.outer_iters = 1;
-  inf.status = PSFD_NOT_CONVERGED;
   if (!std::isfinite(bnorm)) return bad(PSFD_ERR_NONFINITE, "right-hand side is not finite");
   if (bnorm == 0.0) {
     inf.status = PSFD_OK;
-    if (info) *info = inf;
     ISOCHK(hipStreamSynchronize(s));
     return Status();
   }
   double beta = bnorm, rel = 1.0;
-  hipLaunchKernelGGL(k_iso_scale, dim3(g1), dim3(KB), 0, s, B, 1.0 / beta, V, n);
+  hipLaunchKernelGGL((k_iso_scale<double2, T>), dim3(g1), dim3(KB), 0, s, B, 1.0 / beta, V, n);
   std::vector<cd> H((size_t)(m + 1) * m), g(m + 1), sn(m), h1(m + 1), y(m);
   std::vector<double> cs(m);
   auto Hij = [&](int i, int j) -> cd& { return H[(size_t)i * m + j]; };
@@ -746,17 +770,18 @@ Status iso_solve(psfd_iso_plan* p, const void* deps, const void* b, void* u, dou
     std::fill(H.begin(), H.end(), cd(0.0));
     std::fill(g.begin(), g.end(), cd(0.0));
     g[0] = beta;
+    const double stop = std::max(rtol * bnorm, f32 ? ETA_MIXED * beta : 0.0);
     int k = 0;
     for (int j = 0; j < m && inf.iters < max_iters; ++j) {
-      if (!(st = iso_apply(p, deps, V + j * n, w, PSFD_C128, -1, s)).ok()) return st;
+      if (!(st = iso_apply(p, dA, V + j * n, w, dt, -1, s)).ok()) return st;
       // two classical Gram-Schmidt passes
       for (int pass = 0; pass < 2; ++pass) {
-        if (!(st = dots(V, j + 1, w)).ok()) return st;
+        if (!(st = dots((const T*)V, j + 1, (const T*)w)).ok()) return st;
         for (int i = 0; i <= j; ++i) { h1[i] = hv[i]; Hij(i, j) += hv[i]; }
         if (!(st = axpys(w, V, h1, j + 1, -1.0)).ok()) return st;
       }
       double hn = 0.0;
-      if (!(st = norm(w, hn)).ok()) return st;
+      if (!(st = norm((const T*)w, hn)).ok()) return st;
       if (!std::isfinite(hn)) return bad(PSFD_ERR_NONFINITE, "non-finite Krylov vector");
       Hij(j + 1, j) = hn;
       ++inf.iters;
@@ -775,8 +800,9 @@ Status iso_solve(psfd_iso_plan* p, const void* deps, const void* b, void* u, dou
       Hij(j + 1, j) = 0.0;
       g[j + 1] = -std::conj(sn[j]) * g[j];
       g[j] = cs[j] * g[j];
-      if (hn > 0.0) hipLaunchKernelGGL(k_iso_scale, dim3(g1), dim3(KB), 0, s, w, 1.0 / hn, V + (j + 1) * n, n);
-      if (std::abs(g[j + 1]) <= rtol * bnorm || hn == 0.0) break;
+      if (hn > 0.0)
+        hipLaunchKernelGGL((k_iso_scale<T, T>), dim3(g1), dim3(KB), 0, s, w, 1.0 / hn, V + (j + 1) * n, n);
+      if (std::abs(g[j + 1]) <= stop || hn == 0.0) break;
     }
     for (int i = k - 1; i >= 0; --i) {  // back substitution
       cd acc = g[i];
@@ -785,21 +811,43 @@ Status iso_solve(psfd_iso_plan* p, const void* deps, const void* b, void* u, dou
     }
     std::vector<cd> yk(y.begin(), y.begin() + k);
     if (!(st = axpys(X, V, yk, k, 1.0)).ok()) return st;
-    // FP64 residual r = b - A x into slot 0
-    if (!(st = iso_apply(p, deps, X, w, PSFD_C128, -1, s)).ok()) return st;
-    hipLaunchKernelGGL(k_iso_comb, dim3(g1), dim3(KB), 0, s, B, w, -1.0, V, n);
-    if (!(st = norm(V, beta)).ok()) return st;
+    // FP64 residual r = b - A x
+    if (!(st = iso_apply(p, deps, X, w64, PSFD_C128, -1, s)).ok()) return st;
+    hipLaunchKernelGGL(k_iso_comb, dim3(g1), dim3(KB), 0, s, B, w64, -1.0, r64, n);
+    if (!(st = norm((const double2*)r64, beta)).ok()) return st;
     rel = beta / bnorm;
     if (!std::isfinite(rel)) return bad(PSFD_ERR_NONFINITE, "non-finite residual");
     if (rel <= rtol) { inf.status = PSFD_OK; break; }
-    hipLaunchKernelGGL(k_iso_scale, dim3(g1), dim3(KB), 0, s, V, 1.0 / beta, V, n);
+    hipLaunchKernelGGL((k_iso_scale<double2, T>), dim3(g1), dim3(KB), 0, s, r64, 1.0 / beta, V, n);
   }
   inf.rel_residual = rel;
   inf.mono_residual = rel;
   ISOCHK(hipGetLastError());
   ISOCHK(hipStreamSynchronize(s));
-  if (info) *info = inf;
   return Status();
+}
+
+}  // namespace
+
+Status iso_solve(psfd_iso_plan* p, const void* deps, const void* b, void* u, double rtol, int m, int max_iters,
+                 int precision, psfd_info* info, hipStream_t s) {
+  if (!(rtol > 0.0) || m < 1 || m > 64 || max_iters < 1)
+    return bad(PSFD_ERR_INVALID_ARG, "need rtol > 0, 1 <= restart <= 64, max_iters >= 1");
+  if (precision != PSFD_FP64 && precision != PSFD_MIXED)
+    return bad(PSFD_ERR_INVALID_ARG, "precision must be PSFD_FP64 or PSFD_MIXED");
+  int dev = 0;
+  ISOCHK(hipGetDevice(&dev));
+  if (dev != p->device) return bad(PSFD_ERR_INVALID_ARG, "plan belongs to another device");
+  psfd_info inf{};
+  inf.outer_iters = 1;
+  inf.status = PSFD_NOT_CONVERGED;
+  Status st = precision == PSFD_MIXED
+                  ? iso_solve_t<float2>(p, (const double2*)deps, (const double2*)b, (double2*)u, rtol, m, max_iters,
+                                        inf, s)
+                  : iso_solve_t<double2>(p, (const double2*)deps, (const double2*)b, (double2*)u, rtol, m,
+                                         max_iters, inf, s);
+  if (info) *info = inf;
+  return st;
 }
 
 }  // namespace psfd

@@ -158,9 +158,11 @@ def test_isolated_apply_full_size_properties():
     assert d <= 2e-5
 
 
-def test_isolated_solve_matches_dense_oracle():
-    """FP64 GMRES on the isolated system vs the oracle's dense LU solve (3 x 2 x 4 x 8
-    unknowns, lossy background, strong random contrast), with restarts."""
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_isolated_solve_matches_dense_oracle(precision):
+    """GMRES on the isolated system vs the oracle's dense LU solve (3 x 2 x 4 x 8
+    unknowns, lossy background, strong random contrast), with restarts; mixed:
+    FP32 cycles, FP64 residual at every restart."""
     dev = device()
     shape, spacing, eps = (2, 4, 8), (1.0, 2.0, 1.5), 1.0 + 0.02j
     R = float(np.sqrt(sum((n * h) ** 2 for n, h in zip(shape, spacing))))
@@ -169,20 +171,22 @@ def test_isolated_solve_matches_dense_oracle():
     rng = np.random.default_rng(21)
     de = -0.3 + 0.2 * rng.normal(size=shape) + 0.06j
     b = clips.random_complex((3,) + shape, seed=22)
-    say("isolated solve", shape)
-    u, info = plan.solve(torch.from_numpy(de).to(dev), torch.from_numpy(b).to(dev), rtol=1e-13, restart=6,
-                         max_iters=400)
+    say("isolated solve", shape, precision)
+    rtol = 1e-13 if precision == "fp64" else 1e-11
+    u, info = plan.solve(torch.from_numpy(de).to(dev), torch.from_numpy(b).to(dev), rtol=rtol, restart=6,
+                         max_iters=400, precision=precision)
     torch.cuda.synchronize()
     say("  info", info)
-    assert info["status"] == 0 and info["rel_residual"] <= 1e-13 and info["cycles"] > 1
+    assert info["status"] == 0 and info["rel_residual"] <= rtol and info["cycles"] > 1
     k0 = 2 * np.pi / LAM
     ref = I.solve_isolated_dense(ref_t, k0 * k0 * de, b)
     err = np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref)
     say("  rel err", err)
-    assert err <= 1e-10
+    assert err <= (1e-10 if precision == "fp64" else 1e-9)
 
 
-def test_isolated_solve_medium_residual_by_oracle():
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_isolated_solve_medium_residual_by_oracle(precision):
     """32 x 32 x 16 contact holes over the 256 x 256 x 60 nm block, b a normally
     incident plane wave polarised along y: the oracle's apply confirms the GPU
     solution's residual."""
@@ -196,8 +200,9 @@ def test_isolated_solve_medium_residual_by_oracle():
     z = (np.arange(16) * spacing[0])[:, None, None] * np.ones((1, 32, 32))
     b = np.zeros((3,) + shape, dtype=complex)
     b[1] = np.exp(1j * k0 * z)
-    say("isolated solve medium", shape)
-    u, info = plan.solve(torch.from_numpy(de).to(dev), torch.from_numpy(b).to(dev), rtol=1e-10, restart=20)
+    say("isolated solve medium", shape, precision)
+    u, info = plan.solve(torch.from_numpy(de).to(dev), torch.from_numpy(b).to(dev), rtol=1e-10, restart=20,
+                         precision=precision)
     torch.cuda.synchronize()
     say("  info", info)
     assert info["status"] == 0
@@ -226,7 +231,28 @@ def test_isolated_solve_edge_cases():
     u = torch.empty_like(b)
     inf = L.psfd_info()
     code = L.lib().psfd_iso_solve(plan._h, C.c_void_p(de.data_ptr()), C.c_void_p(b.data_ptr()),
-                                  C.c_void_p(u.data_ptr()), 1e-14, 4, 3, C.byref(inf), None)
+                                  C.c_void_p(u.data_ptr()), 1e-14, 4, 3, L.PSFD_FP64, C.byref(inf), None)
     torch.cuda.synchronize()
     assert code == L.PSFD_NOT_CONVERGED and inf.iters == 3 and inf.status == L.PSFD_NOT_CONVERGED
     assert 0 < inf.rel_residual < 1 and torch.isfinite(u.abs()).all()
+
+
+def test_isolated_apply_max_size():
+    """128 x 128 x 128 (the largest grid; 256-long padded lines on every axis,
+    the narrowest z-pencil tiles): zero-contrast identity, determinism and
+    reciprocity with a constant contrast in both precisions."""
+    dev = device()
+    shape, spacing = (128, 128, 128), (1.0, 1.0, 1.0)
+    say("isolated max size", shape)
+    plan = iso_plan(shape, spacing, 1.0 + 0.01j)
+    for dt, tol in ((torch.complex128, 1e-11), (torch.complex64, 2e-5)):
+        a = torch.from_numpy(clips.random_complex((3,) + shape, seed=8)).to(dev, dt)
+        b = torch.from_numpy(clips.random_complex((3,) + shape, seed=9)).to(dev, dt)
+        one = torch.full(shape, 0.2 - 0.1j, dtype=dt, device=dev)
+        Ab, Aa = plan.apply(one, b), plan.apply(one, a)
+        assert torch.equal(Ab, plan.apply(one, b))
+        lhs = torch.sum((a * (b - Ab)).to(torch.complex128)).item()
+        rhs = torch.sum((b * (a - Aa)).to(torch.complex128)).item()
+        say("  reciprocity", dt, abs(lhs - rhs) / abs(lhs))
+        assert abs(lhs - rhs) <= tol * abs(lhs)
+        assert torch.equal(plan.apply(torch.zeros_like(one), a), a)
