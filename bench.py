@@ -303,9 +303,10 @@ def sec_isolated(ctx, args, out):
     reps = 20 if args.only == "isolated" else 100
     # algorithmic bytes per voxel in complex values (esz bytes each): x rows read x (3) and
     # delta_eps (1), write half the padded rows (6); y columns read 6, write 12; the z pencils read
-    # and write 12 and read the 6-entry table of the padded grid (48); inverse y columns read 12,
-    # write 6; inverse x rows read 6 and x (3), write y (3)
-    per_vox = {0: 10, 1: 18, 2: 72, 3: 18, 4: 12}
+    # and write 12 and read the 6-entry table of the padded grid for kz = 0 .. nz (the table is even
+    # or odd in kz: 24 (nz + 1) / nz); inverse y columns read 12, write 6; inverse x rows read 6 and
+    # x (3), write y (3)
+    per_vox = {0: 10, 1: 18, 2: 24 + 24 * (nz + 1) / nz, 3: 18, 4: 12}
     names = {0: "k_iso_lines<fwd, x rows * V>", 1: "k_iso_lines<fwd, y columns>",
              2: "k_iso_zmul (z FFT, 3x3 table product, inverse z FFT)", 3: "k_iso_lines<inv, y columns>",
              4: "k_iso_lines<inv, x rows, y = x - w>"}
@@ -318,9 +319,9 @@ def sec_isolated(ctx, args, out):
         stages = {}
         for st in range(5):
             t = plan.bench_stage(st, dd, xx, y, reps) * 1e-3
-            stages[st] = {"kernel": names[st], "us": 1e6 * t, "bytes": per_vox[st] * esz * N,
+            stages[st] = {"kernel": names[st], "us": 1e6 * t, "bytes": int(per_vox[st] * esz * N),
                           "gbs": per_vox[st] * esz * N / t / 1e9}
-        b = sum(per_vox.values()) * esz * N
+        b = int(sum(per_vox.values()) * esz * N)
         res[name] = {"applies_per_s": 1e3 / ms, "us_per_apply": 1e3 * ms, "apply_bytes": b,
                      "apply_gbs": b / (ms * 1e-3) / 1e9, "stages": stages}
     st32 = res["fp32"]["stages"]

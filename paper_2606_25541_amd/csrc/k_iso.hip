@@ -117,7 +117,7 @@ __global__ void k_iso_lines(IsoLines a) {
 // components: 3 lb sequences of length 2nz interleaved in LDS.
 struct IsoZ {
   void* w;
-  const void* table;   // pencil-major: block (ky, kx / lb), then [2nz][6][lb]; entries xx, yy, zz, xy, xz, yz
+  const void* table;   // pencil-major: block (ky, kx / lb), then [nz + 1][6][lb] (kz <= nz); entries xx, yy, zz, xy, xz, yz
   int lnz, lnx2;       // log2 nz, log2 2nx
   int lb, llb;
   long long plane;     // 2ny 2nx
@@ -144,25 +144,35 @@ PSFD_D void zmul_point(T* f, int lb, const T t[6]) {
 }
 
 template <class T>
+PSFD_D void zmul_entries(const T* tb, int kz, int li, int nz, int lb, T t[6]) {
+  const bool up = kz > nz;
+  const T* q = tb + (up ? 2 * nz - kz : kz) * 6 * lb + li;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) t[k] = q[k * lb];
+  if (up) {
+    t[4].x = -t[4].x; t[4].y = -t[4].y;
+    t[5].x = -t[5].x; t[5].y = -t[5].y;
+  }
+}
+
+template <class T>
 __global__ void k_iso_zmul(IsoZ a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int nz = 1 << a.lnz, lb = a.lb, nsq = 3 * lb, npts = 2 * nz * lb;
   const long long col = ((long long)blockIdx.y << a.lnx2) + ((long long)blockIdx.x << a.llb);
-  // this block's table entries: one contiguous run of 2nz * 6 * lb values,
-  // point (kz, li) entry k at (kz * 6 + k) * lb + li
-  const T* tb = (const T*)a.table + (((long long)blockIdx.y * gridDim.x + blockIdx.x) * npts * 6);
+  // this block's table entries: one contiguous run of (nz + 1) 6 lb values,
+  // point (kz, li) entry k at (kz * 6 + k) * lb + li for kz <= nz; a point
+  // kz > nz takes kz' = 2nz - kz, with xz and yz negated (the table is even in
+  // kz, those two entries odd)
+  const T* tb = (const T*)a.table + (((long long)blockIdx.y * gridDim.x + blockIdx.x) * (nz + 1) * 6 * lb);
   constexpr int ZPT = Zpt<T>::v;
   T tt[ZPT > 0 ? ZPT : 1][6];
 #pragma unroll
   for (int i = 0; i < ZPT; ++i) {
     const int p = tid + i * nthr;
-    if (p < npts) {
-      const T* q = tb + (p >> a.llb) * 6 * lb + (p & (lb - 1));
-#pragma unroll
-      for (int k = 0; k < 6; ++k) tt[i][k] = q[k * lb];
-    }
+    if (p < npts) zmul_entries(tb, p >> a.llb, p & (lb - 1), nz, lb, tt[i]);
   }
   T* w = (T*)a.w;
   for (int idx = tid; idx < nz * nsq; idx += nthr) {
@@ -178,10 +188,8 @@ __global__ void k_iso_zmul(IsoZ a) {
     if (p < npts) zmul_point(lds + (p >> a.llb) * nsq + (p & (lb - 1)), lb, tt[i]);
   }
   for (int p = tid + ZPT * nthr; p < npts; p += nthr) {
-    const T* q = tb + (p >> a.llb) * 6 * lb + (p & (lb - 1));
     T t[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) t[k] = q[k * lb];
+    zmul_entries(tb, p >> a.llb, p & (lb - 1), nz, lb, t);
     zmul_point(lds + (p >> a.llb) * nsq + (p & (lb - 1)), lb, t);
   }
   __syncthreads();
@@ -279,24 +287,37 @@ __global__ void k_iso_restrict(const double2* __restrict__ g, double2* __restric
 }
 
 // the table in the z-pencil order of the apply: for block (ky, kb) of lb
-// adjacent kx, [2nz][6][lb]; from the natural [6][2nz][2ny][2nx]
+// adjacent kx, [nz + 1][6][lb] (kz = 0 .. nz), from the natural [6][2nz][2ny][2nx]
 template <class T>
 __global__ void k_iso_pencil_table(const double2* __restrict__ nat, T* __restrict__ out, int lz, int ly, int lx,
                                    int llb) {
   const long long n8 = 8LL << (lz + ly + lx);
+  const int nz1 = (1 << lz) + 1;
+  const long long tot = 6LL * nz1 * (4LL << (ly + lx));
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 6 * n8) return;
+  if (idx >= tot) return;
   const int lb = 1 << llb;
   const int li = (int)(idx & (lb - 1));
   const long long r = idx >> llb;
   const int k = (int)(r % 6);
   const long long r2 = r / 6;
-  const int kz = (int)(r2 & ((2 << lz) - 1));
-  const long long blk = r2 >> (lz + 1);          // ky * (2nx / lb) + kb
+  const int kz = (int)(r2 % nz1);
+  const long long blk = r2 / nz1;                 // ky * (2nx / lb) + kb
   const int nkb = (2 << lx) >> llb;
   const long long ky = blk / nkb, kb = blk - ky * nkb;
   const long long src = k * n8 + (((long long)kz << (ly + 1)) + ky) * (2LL << lx) + (kb << llb) + li;
   out[idx] = from_d<T>(nat[src]);
+}
+
+// zero the offset plane jz = -nz (index nz on the 2n grid) of the samples
+// [6][2nz][2ny][2nx]: it couples no two voxels of the box, and without it the
+// samples are even (xx, yy, zz, xy) or odd (xz, yz) in jz
+__global__ void k_iso_zero_zplane(double2* __restrict__ k, int lz, int ly, int lx) {
+  const long long pl = 4LL << (ly + lx);
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 6 * pl) return;
+  const long long c = idx / pl, e = idx - c * pl;
+  k[c * (8LL << (lz + ly + lx)) + ((long long)1 << lz) * pl + e] = make_double2(0.0, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -614,8 +635,12 @@ Status iso_create(const psfd_iso_problem& pr, psfd_iso_plan*& out) {
   ISOCHK(hipMalloc((void**)&g, 6 * Mtot * sizeof(double2)));
   struct Free { double2* q; ~Free() { if (q) (void)hipFree(q); } } fg{g};
   ISOCHK(hipMalloc((void**)&p->tab64, 6 * n8 * sizeof(double2)));
-  ISOCHK(hipMalloc((void**)&p->ptab64, 6 * n8 * sizeof(double2)));
-  ISOCHK(hipMalloc((void**)&p->ptab32, 6 * n8 * sizeof(float2)));
+  const long long nhalf = 6LL * (nn[0] + 1) * 4 * nn[1] * nn[2];  // pencil tables: kz = 0 .. nz
+  ISOCHK(hipMalloc((void**)&p->ptab64, nhalf * sizeof(double2)));
+  ISOCHK(hipMalloc((void**)&p->ptab32, nhalf * sizeof(float2)));
+  double2* kev = nullptr;
+  ISOCHK(hipMalloc((void**)&kev, 6 * n8 * sizeof(double2)));
+  struct Free2 { double2* q; ~Free2() { if (q) (void)hipFree(q); } } fk{kev};
   IsoSample smp{};
   smp.g = g; smp.l0 = lo[0]; smp.l1 = lo[1]; smp.l2 = lo[2];
   smp.dk0 = 2.0 * M_PI / ((double)(1 << lo[0]) * hh[0]);
@@ -631,11 +656,19 @@ Status iso_create(const psfd_iso_problem& pr, psfd_iso_plan*& out) {
   hipLaunchKernelGGL(k_iso_restrict, dim3((unsigned)((6 * n8 + 255) / 256)), dim3(256), 0, s, g, p->tab64,
                      p->ln[0], p->ln[1], p->ln[2], lo[0], lo[1], lo[2], 1.0 / (double)Mtot);
   ISOCHK(hipGetLastError());
+  // the samples with the offset plane jz = -nz zeroed: the same operator, a
+  // table even / odd in kz (the apply reads kz <= nz only)
+  ISOCHK(hipMemcpyAsync(kev, p->tab64, 6 * n8 * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_iso_zero_zplane, dim3((unsigned)((6 * n8 / (2 * nn[0]) + 255) / 256)), dim3(256), 0, s, kev,
+                     p->ln[0], p->ln[1], p->ln[2]);
+  ISOCHK(hipGetLastError());
+  st = fft3_c<false>(kev, 6, p->ln[0] + 1, p->ln[1] + 1, p->ln[2] + 1, p->tw64, s);
+  if (!st.ok()) return st;
   st = fft3_c<false>(p->tab64, 6, p->ln[0] + 1, p->ln[1] + 1, p->ln[2] + 1, p->tw64, s);
   if (!st.ok()) return st;
-  hipLaunchKernelGGL(k_iso_pencil_table<double2>, dim3((unsigned)((6 * n8 + 255) / 256)), dim3(256), 0, s, p->tab64,
+  hipLaunchKernelGGL(k_iso_pencil_table<double2>, dim3((unsigned)((nhalf + 255) / 256)), dim3(256), 0, s, kev,
                      p->ptab64, p->ln[0], p->ln[1], p->ln[2], ilog2_exact(z_lb<double2>(nn[0], nn[2])));
-  hipLaunchKernelGGL(k_iso_pencil_table<float2>, dim3((unsigned)((6 * n8 + 255) / 256)), dim3(256), 0, s, p->tab64,
+  hipLaunchKernelGGL(k_iso_pencil_table<float2>, dim3((unsigned)((nhalf + 255) / 256)), dim3(256), 0, s, kev,
                      p->ptab32, p->ln[0], p->ln[1], p->ln[2], ilog2_exact(z_lb<float2>(nn[0], nn[2])));
   ISOCHK(hipGetLastError());
   ISOCHK(hipStreamSynchronize(s));
