@@ -201,3 +201,36 @@ def test_isolated_dense_solve():
     ug, info = gmres(op, b.ravel(), rtol=1e-13, atol=0.0, restart=b.size, maxiter=10)
     assert info == 0
     assert np.linalg.norm(ug - u.ravel()) <= 1e-10 * np.linalg.norm(u)
+
+
+@pytest.mark.parametrize("shape,spacing", [((4, 8, 8), (1.0, 3.0, 3.0)), ((8, 4, 16), (2.0, 2.0, 1.0))])
+def test_isolated_offset_minus_n_plane_is_inert(shape, spacing):
+    """The padded convolution meets offsets in (-n, n) only, so zeroing the kernel
+    samples at the offset plane jz = -nz leaves the operator unchanged. Without
+    that plane the samples are even along z in xx, yy, zz, xy and odd in xz, yz,
+    so the table is even / odd in kz and kz = 0 .. nz determines it (what the
+    z-pencil order of the apply stores)."""
+    kbg = K0 * (1 + 0.02j)
+    nz = shape[0]
+    R = float(np.sqrt(sum((n * h) ** 2 for n, h in zip(shape, spacing))))
+    K = I.kernel_samples(shape, spacing, kbg, R, I.oversampling(shape, spacing, R))
+    dV = np.prod(spacing)
+    T = np.fft.fftn(K, axes=(0, 1, 2)) * dV
+    Ke = K.copy()
+    Ke[nz] = 0
+    Te = np.fft.fftn(Ke, axes=(0, 1, 2)) * dV
+    sgn = np.array([[1, 1, -1], [1, 1, -1], [-1, -1, 1]])
+    kz = np.arange(1, 2 * nz)
+    assert np.abs(Te[kz] - sgn * Te[2 * nz - kz]).max() <= 1e-14 * np.abs(Te).max()
+    rng = np.random.default_rng(1)
+    vol = rng.normal(size=shape) + 0.3j
+    x = rng.normal(size=(3,) + shape) + 1j * rng.normal(size=(3,) + shape)
+    y0 = I.apply_isolated(T, vol, x)
+    Th = Te.copy()
+    Th[nz + 1:] = sgn * Te[2 * nz - np.arange(nz + 1, 2 * nz)]
+    assert np.abs(I.apply_isolated(Th, vol, x) - y0).max() <= 1e-14 * np.abs(y0).max()
+    # the plane itself is not negligible: dropping another plane does change the operator
+    Kb = K.copy()
+    Kb[1] = 0
+    Tb = np.fft.fftn(Kb, axes=(0, 1, 2)) * dV
+    assert np.abs(I.apply_isolated(Tb, vol, x) - y0).max() > 1e-6 * np.abs(y0).max()
