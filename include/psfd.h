@@ -224,7 +224,7 @@ typedef struct {
 /* Validate the problem and precompute the kernel table on the current device
  * (blocks until done; the precompute holds 96 prod(o_a n_a) bytes of device
  * memory while it runs; the plan keeps the natural FP64 table, 768 nx ny nz
- * bytes, and the tables in the order of the z pass, 288 (nz + 1) nx ny bytes
+ * bytes, and the tables in the order of the z pass, 576 (nz + 1) nx ny bytes
  * for FP64 and FP32 together). *out receives the plan, owned by the caller and
  * released with psfd_iso_plan_destroy. Errors: INVALID_ARG, UNSUPPORTED_SIZE
  * (a size, or a radius that needs o_a n_a > 1024), OOM / HIP. */
