@@ -242,14 +242,15 @@ int psfd_iso_apply(psfd_iso_plan* plan, const void* d_deps, const void* d_x, voi
 
 /* Solve u - P IFFT(table . FFT(Z V u)) = b (eq. (18) for the isolated scatterer,
  * b e.g. the incident field sampled on the grid) by GMRES(restart) (Saad &
- * Schultz) from u = 0: classical Gram-Schmidt with a second pass, every restart
+ * Schultz) from u = 0: classical Gram-Schmidt (a second pass where it cancels
+ * severely), every restart
  * from the FP64 residual b - A u, u accumulated in FP64. precision: PSFD_FP64,
  * or PSFD_MIXED (FP32 basis and applies; a cycle also ends after reducing the
  * residual 1e4-fold). d_deps, d_b, d_u: complex128 device
  * arrays ([nz][ny][nx], [3][nz][ny][nx] twice); d_u must not alias d_b. Stops
  * when ||b - A u|| <= rtol ||b|| (info->rel_residual) or after max_iters
  * Arnoldi steps (then PSFD_NOT_CONVERGED, u written). 1 <= restart <= 64. The
- * basis ((restart + 1) 48 nx ny nz bytes in FP64, half in mixed) and three
+ * basis ((restart + 1) 48 nx ny nz bytes in FP64, half in mixed) and two FP64
  * vectors are allocated for the call. Blocks
  * until done; calls on one plan must not overlap. */
 int psfd_iso_solve(psfd_iso_plan* plan, const void* d_deps, const void* d_b, void* d_u, double rtol, int32_t restart,

@@ -714,7 +714,8 @@ Status iso_table(psfd_iso_plan* p, void* d_table, int32_t* over, double* radius,
 
 
 // GMRES(m) on y = x - K(V x) (Saad & Schultz) from x0 = 0, the basis and the
-// operator applies in T: classical Gram-Schmidt with a second pass, Givens
+// operator applies in T: classical Gram-Schmidt (a second pass where it
+// cancels severely), Givens
 // rotations and the small Hessenberg system on the host (one apply per step
 // costs far more than the few host round trips). Every restart starts from the
 // FP64 residual b - A x, and x accumulates in FP64. With an FP32 basis (mixed
@@ -723,6 +724,8 @@ Status iso_table(psfd_iso_plan* p, void* d_table, int32_t* over, double* radius,
 namespace {
 
 constexpr double ETA_MIXED = 1e-4;
+// second Gram-Schmidt pass when ||w - V h|| < CANCEL ||w||
+constexpr double CANCEL = 0.1;
 
 template <class T>
 Status iso_solve_t(psfd_iso_plan* p, const double2* deps, const double2* B, double2* X, double rtol, int m,
@@ -730,7 +733,7 @@ Status iso_solve_t(psfd_iso_plan* p, const double2* deps, const double2* B, doub
   typedef std::complex<double> cd;
   const bool f32 = sizeof(T) == 8;
   const long long N = (long long)p->n[0] * p->n[1] * p->n[2], n = 3 * N;
-  T *V = nullptr, *w = nullptr, *depsT = nullptr;
+  T *V = nullptr, *depsT = nullptr;
   double2 *w64 = nullptr, *r64 = nullptr, *part = nullptr, *hd = nullptr;
   struct Free {
     void* q[7];
@@ -738,8 +741,6 @@ Status iso_solve_t(psfd_iso_plan* p, const double2* deps, const double2* B, doub
   };
   ISOCHK(hipMalloc((void**)&V, (size_t)(m + 1) * n * sizeof(T)));
   Free fr{{V}};
-  ISOCHK(hipMalloc((void**)&w, (size_t)n * sizeof(T)));
-  fr.q[1] = w;
   ISOCHK(hipMalloc((void**)&w64, (size_t)n * sizeof(double2)));
   fr.q[2] = w64;
   ISOCHK(hipMalloc((void**)&r64, (size_t)n * sizeof(double2)));
@@ -806,16 +807,25 @@ Status iso_solve_t(psfd_iso_plan* p, const double2* deps, const double2* B, doub
     const double stop = std::max(rtol * bnorm, f32 ? ETA_MIXED * beta : 0.0);
     int k = 0;
     for (int j = 0; j < m && inf.iters < max_iters; ++j) {
-      if (!(st = iso_apply(p, dA, V + j * n, w, dt, -1, s)).ok()) return st;
-      // two classical Gram-Schmidt passes
-      for (int pass = 0; pass < 2; ++pass) {
-        if (!(st = dots((const T*)V, j + 1, (const T*)w)).ok()) return st;
+      // w = A v_j straight into slot j + 1; one launch gives V_{0..j}^H w and
+      // ||w||^2; the norm after the update follows from Pythagoras, and only a
+      // severe cancellation (norm ratio below CANCEL) takes a second pass with
+      // a computed norm
+      T* wj = V + (j + 1) * n;
+      if (!(st = iso_apply(p, dA, V + j * n, wj, dt, -1, s)).ok()) return st;
+      if (!(st = dots((const T*)V, j + 2, (const T*)wj)).ok()) return st;
+      const double w2 = hv[j + 1].real();
+      double p2 = 0.0;
+      for (int i = 0; i <= j; ++i) { h1[i] = hv[i]; Hij(i, j) = hv[i]; p2 += std::norm(hv[i]); }
+      if (!(st = axpys(wj, V, h1, j + 1, -1.0)).ok()) return st;
+      double hn = std::sqrt(std::max(w2 - p2, 0.0));
+      if (!(hn >= CANCEL * std::sqrt(std::max(w2, 0.0)))) {
+        if (!(st = dots((const T*)V, j + 1, (const T*)wj)).ok()) return st;
         for (int i = 0; i <= j; ++i) { h1[i] = hv[i]; Hij(i, j) += hv[i]; }
-        if (!(st = axpys(w, V, h1, j + 1, -1.0)).ok()) return st;
+        if (!(st = axpys(wj, V, h1, j + 1, -1.0)).ok()) return st;
+        if (!(st = norm((const T*)wj, hn)).ok()) return st;
       }
-      double hn = 0.0;
-      if (!(st = norm((const T*)w, hn)).ok()) return st;
-      if (!std::isfinite(hn)) return bad(PSFD_ERR_NONFINITE, "non-finite Krylov vector");
+      if (!std::isfinite(hn) || !std::isfinite(w2)) return bad(PSFD_ERR_NONFINITE, "non-finite Krylov vector");
       Hij(j + 1, j) = hn;
       ++inf.iters;
       k = j + 1;
@@ -833,8 +843,7 @@ Status iso_solve_t(psfd_iso_plan* p, const double2* deps, const double2* B, doub
       Hij(j + 1, j) = 0.0;
       g[j + 1] = -std::conj(sn[j]) * g[j];
       g[j] = cs[j] * g[j];
-      if (hn > 0.0)
-        hipLaunchKernelGGL((k_iso_scale<T, T>), dim3(g1), dim3(KB), 0, s, w, 1.0 / hn, V + (j + 1) * n, n);
+      if (hn > 0.0) hipLaunchKernelGGL((k_iso_scale<T, T>), dim3(g1), dim3(KB), 0, s, wj, 1.0 / hn, wj, n);
       if (std::abs(g[j + 1]) <= stop || hn == 0.0) break;
     }
     for (int i = k - 1; i >= 0; --i) {  // back substitution
