@@ -624,3 +624,51 @@ def adjoint_gradient(prob, deps: np.ndarray, orders: Sequence[Tuple[int, int]],
     g = S.vscale * np.sum(lam * u, axis=0)
     return {"grad": 2.0 * np.conj(g), "lam": lam, "J": objective(S, a, orders), "iters": its,
             "outer_iters": outer, "fwd": fwd}
+
+
+def order_vjp(prob, deps: np.ndarray, grad_orders: np.ndarray, u: Optional[np.ndarray] = None,
+              rtol: float = 1e-10, restart: int = 30, max_iters: int = 20000) -> Dict:
+    """Vector-Jacobian product of the reflected orders a(delta_eps) for any real loss L(a).
+
+    grad_orders = dL/dRe a + i dL/dIm a, shape (ny, nx, 3) (PyTorch's convention for
+    complex tensors). The orders a = c0 + W V u are holomorphic in delta_eps, with u
+    the total field of the monolithic system (I - M V) u = e_bg (eqs. (3), (8)-(9),
+    (18)); so dL = Re sum_q conj(G_q) . da_q and, by the push-through identity,
+    da = W (I - V M)^{-1} dV u. With lambda = (I - M^T V)^{-1} W^T conj(G),
+    dL = Re sum_r k0^2 d(delta_eps)(r) sum_c lambda_c u_c, and the gradient in the
+    same convention is conj(k0^2 sum_c lambda_c u_c). u (the forward total field)
+    is solved for when not given. Returns grad, lambda, u and the GMRES counters.
+    """
+    S = Setup(prob)
+    deps = np.asarray(deps, dtype=np.complex128)
+    V = potential(S, deps)
+    its_fwd = 0
+    if u is None:
+        u, fi = gmres(lambda v: apply_monolithic(S, deps, v), background_field(S), None, rtol, restart, max_iters)
+        its_fwd = fi["iters"]
+    s = readout_T(S, np.conj(np.asarray(grad_orders, dtype=np.complex128)))
+    lam, info = gmres(lambda v: v - apply_M_T(S, V[None] * v), s, None, rtol, restart, max_iters)
+    g = S.vscale * np.sum(lam * u, axis=0)
+    return {"grad": np.conj(g), "lam": lam, "u": u, "iters_fwd": its_fwd, "iters_adj": info["iters"],
+            "rel_residual_adj": info["rel_residual"], "setup": S}
+
+
+def orders_of_total_field(S: Setup, deps: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Reflected orders at z = T of a total field u in the slab: the layered-stack
+    reflection of the downgoing field at z = 0 propagated to T, plus the upgoing
+    mask field (eq. (9) and its readouts)."""
+    V = potential(S, deps)
+    a_up = reflect(S, incident_down(S) + read_down(S, V[None] * u))
+    return reflected_orders(S, deps, u, a_up)
+
+
+def solve_monolithic(prob, deps: np.ndarray, rtol: float = 1e-10, restart: int = 30,
+                     max_iters: int = 20000) -> Dict:
+    """GMRES(m) on the monolithic system (I - M V) u = e_bg (the fixed point of the
+    outer loop of eqs. (8)-(9)): total field u, E_mask = K V u and the orders."""
+    S = Setup(prob)
+    deps = np.asarray(deps, dtype=np.complex128)
+    u, info = gmres(lambda v: apply_monolithic(S, deps, v), background_field(S), None, rtol, restart, max_iters)
+    V = potential(S, deps)
+    return {"u": u, "emask": conv_K(S, V[None] * u), "orders": orders_of_total_field(S, deps, u),
+            "iters": info["iters"], "rel_residual": info["rel_residual"], "setup": S}

@@ -197,3 +197,35 @@ def random_complex(shape, seed: int, dtype=np.complex128) -> np.ndarray:
     """Seeded standard complex Gaussian array (test vectors)."""
     rng = np.random.default_rng(seed)
     return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(dtype)
+
+
+def manhattan_set(grids: Sequence[str], seed0: int, angles: Sequence[Tuple[float, float]],
+                  rng: Optional[np.random.Generator] = None):
+    """``(grid, problem, delta_eps)`` per grid name: a pupil angle each and a Manhattan clip.
+
+    The angle of item i is drawn from ``rng`` when given, else it is
+    ``angles[(7 i) mod len(angles)]``; the clip of item i has seed ``seed0 + i``.
+    """
+    items = []
+    for i, g in enumerate(grids):
+        th, ph = angles[int(rng.integers(len(angles))) if rng is not None else (7 * i) % len(angles)]
+        p = config_problem(g, theta_deg=th, phi_deg=ph)
+        items.append((g, p, manhattan(p.nx, p.ny, p.nz, p.lx_nm, p.ly_nm, seed=seed0 + i)))
+    return items
+
+
+def batched_set():
+    """The 64 batched instances: 64x64x32 and 128x128x64 Manhattan clips alternating,
+    pupil angles drawn with seed 3000, clip seeds 3000 + i."""
+    return manhattan_set(["G2", "G3"] * 32, 3000, pupil_angles(), np.random.default_rng(3000))
+
+
+def serving_pool():
+    """The 12 requests of the serving pool: 64x64x32, 128x128x64 and 256x256x64 in turn,
+    pupil angle (7 i) mod 48, clip seeds 4000 + i."""
+    return manhattan_set(["G2", "G3", "G4"] * 4, 4000, pupil_angles(), None)
+
+
+def headline_clip() -> np.ndarray:
+    """The 128x128x64 contact-hole clip of the headline solve (8 holes, seed 2001)."""
+    return contact_holes(128, 128, 64, 256.0, 256.0, 8, seed=2001)

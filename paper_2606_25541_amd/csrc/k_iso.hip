@@ -724,8 +724,14 @@ Status iso_table(psfd_iso_plan* p, void* d_table, int32_t* over, double* radius,
 namespace {
 
 constexpr double ETA_MIXED = 1e-4;
-// second Gram-Schmidt pass when ||w - V h|| < CANCEL ||w||
-constexpr double CANCEL = 0.1;
+// Second Gram-Schmidt pass when ||w - V h|| < cancel ||w||: 1/sqrt(2), the
+// classical criterion after which one more pass restores orthogonality to
+// working accuracy ("twice is enough"). PSFD_ISO_CANCEL overrides it (read per
+// solve), so that a test can force the second pass on every step.
+static double iso_cancel() {
+  const char* e = std::getenv("PSFD_ISO_CANCEL");
+  return e ? std::atof(e) : 0.70710678118654752;
+}
 
 template <class T>
 Status iso_solve_t(psfd_iso_plan* p, const double2* deps, const double2* B, double2* X, double rtol, int m,
@@ -758,6 +764,7 @@ Status iso_solve_t(psfd_iso_plan* p, const double2* deps, const double2* B, doub
                        depsT, N);
   }
   const void* dA = f32 ? (const void*)depsT : (const void*)deps;
+  const double CANCEL = iso_cancel();
   std::vector<cd> hv(m + 1);
   // hv[0..nv) = V_i^H x
   auto dots = [&](auto Vb, int nv, auto x) -> Status {
@@ -809,7 +816,7 @@ Status iso_solve_t(psfd_iso_plan* p, const double2* deps, const double2* B, doub
     for (int j = 0; j < m && inf.iters < max_iters; ++j) {
       // w = A v_j straight into slot j + 1; one launch gives V_{0..j}^H w and
       // ||w||^2; the norm after the update follows from Pythagoras, and only a
-      // severe cancellation (norm ratio below CANCEL) takes a second pass with
+      // cancellation (norm ratio below CANCEL) takes a second pass with
       // a computed norm
       T* wj = V + (j + 1) * n;
       if (!(st = iso_apply(p, dA, V + j * n, wj, dt, -1, s)).ok()) return st;

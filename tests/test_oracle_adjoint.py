@@ -75,3 +75,61 @@ def test_gradient_matches_finite_differences():
             g = adj["grad"][k, j, i]
             an = g.real if part == 1.0 else g.imag
             assert abs(fd - an) <= 1e-6 * abs(fd) + 1e-12
+
+
+def _vjp_problem():
+    layers, es = C.mo_si_stack(10)
+    p = C.Problem(nx=8, ny=8, nz=4, lx_nm=24.0, ly_nm=24.0, t_nm=20.0, theta_deg=6.0, phi_deg=10.0,
+                  pol=1, layers=layers, eps_sub=es)
+    de, _ = C.smooth_density_eps(8, 8, 4, 24.0, 24.0, 20.0, seed=6, sigma_xy_nm=3.0, sigma_z_nm=3.0)
+    return p, de
+
+
+W_PLUS1 = np.array([0.7 - 0.2j, -0.4 + 0.9j, 0.3 + 0.1j])
+
+
+def non_intensity_loss(a):
+    """L(a) = Re(w . a_(+1,0)) - ||a_(-1,0)||^2 and its gradient dL/dRe a + i dL/dIm a."""
+    L = float(np.real(W_PLUS1 @ a[0, 1]) - np.sum(np.abs(a[0, -1]) ** 2))
+    G = np.zeros_like(a)
+    G[0, 1] = np.conj(W_PLUS1)
+    G[0, -1] = -2.0 * a[0, -1]
+    return L, G
+
+
+def test_order_vjp_matches_finite_differences_for_a_general_loss():
+    """The vector-Jacobian product of the orders (any cotangent) against central
+    differences of full FP64 monolithic solves, for a loss that is not an intensity."""
+    p, de = _vjp_problem()
+    fwd = O.solve_monolithic(p, de, rtol=1e-13)
+    _, G = non_intensity_loss(fwd["orders"])
+    v = O.order_vjp(p, de, G, u=fwd["u"], rtol=1e-13)
+    rng = np.random.default_rng(21)
+    for _ in range(4):
+        k, j, i = int(rng.integers(0, 4)), int(rng.integers(0, 8)), int(rng.integers(0, 8))
+        for part in (1.0, 1j):
+            h = 1e-5
+            lp = non_intensity_loss(O.solve_monolithic(p, de + _bump(de, k, j, i, h * part), rtol=1e-13)["orders"])[0]
+            lm = non_intensity_loss(O.solve_monolithic(p, de - _bump(de, k, j, i, h * part), rtol=1e-13)["orders"])[0]
+            fd = (lp - lm) / (2 * h)
+            g = v["grad"][k, j, i]
+            an = g.real if part == 1.0 else g.imag
+            assert abs(fd - an) <= 1e-6 * abs(fd) + 1e-12, (k, j, i, part, fd, an)
+
+
+def _bump(de, k, j, i, h):
+    d = np.zeros_like(de)
+    d[k, j, i] = h
+    return d
+
+
+def test_order_vjp_of_the_intensity_is_the_intensity_gradient():
+    """With the cotangent 2 a on the selected orders (the gradient of sum ||a_q||^2),
+    the monolithic vector-Jacobian product equals the outer-splitting adjoint."""
+    p, de = _vjp_problem()
+    orders = [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)]
+    adj = O.adjoint_gradient(p, de, orders, rtol=1e-13)
+    S = adj["fwd"]["setup"]
+    G = np.where(O.order_mask(S, orders)[..., None], 2.0 * adj["fwd"]["orders"], 0.0)
+    v = O.order_vjp(p, de, G, rtol=1e-13)
+    assert np.max(np.abs(v["grad"] - adj["grad"])) <= 1e-8 * np.max(np.abs(adj["grad"]))
