@@ -122,20 +122,35 @@ int psfd_plan_footprint(const psfd_plan* plan, size_t* device_bytes);
 int psfd_apply(psfd_plan* plan, const void* d_deps, const void* d_x, void* d_y, int dtype, int flags,
                void* stream);
 
-/* Full solve: outer reflection loop around GMRES on eq. (18). d_deps complex128
- * [nz][ny][nx]; outputs (complex128, device): d_emask [3][nz][ny][nx] = E_mask
- * envelope, d_orders [ny][nx][3] = reflected order amplitudes at z = t (may be
- * NULL). Blocks until done. Returns NOT_CONVERGED when an iteration limit stops it. */
-int psfd_solve(psfd_plan* plan, const void* d_deps, void* d_emask, void* d_orders, psfd_info* info,
+/* Full solve (Sec. 2, eqs. (8)-(9); Sec. 3, eq. (18)): the background source,
+ * GMRES on eq. (18) with the monolithic or outer coupling of the multilayer
+ * response, and the readouts. d_deps complex128 [nz][ny][nx] (device); outputs
+ * (complex128, device): d_emask [3][nz][ny][nx] = E_mask envelope, d_orders
+ * [ny][nx][3] = reflected order amplitudes a_q at z = t (may be NULL), d_u
+ * [3][nz][ny][nx] = the total field u = E_inc + E_layer + E_mask in the slab
+ * (may be NULL; what psfd_solve_adjoint takes: E_mask alone does not determine
+ * the layered part, which follows from the downgoing readout of V u). Blocks
+ * until done. Returns NOT_CONVERGED when an iteration limit stops it. */
+int psfd_solve(psfd_plan* plan, const void* d_deps, void* d_emask, void* d_orders, void* d_u, psfd_info* info,
                void* stream);
 
-/* Gradient of J = sum_{q in orders} ||a_q||^2 with respect to delta_eps
- * (a_q: reflected order amplitudes). d_orders_sel: host array of n_sel (m, n)
- * integer pairs. d_grad (complex128 [nz][ny][nx], device) receives
- * dJ/dRe + i dJ/dIm. Runs the forward solve, then the transposed solve. *J_out
- * (may be NULL) receives J. */
-int psfd_solve_adjoint(psfd_plan* plan, const void* d_deps, const int32_t* orders_sel, int32_t n_sel,
-                       void* d_grad, double* J_out, psfd_info* info_fwd, psfd_info* info_adj, void* stream);
+/* Adjoint solve: the vector-Jacobian product of the reflected orders with
+ * respect to the contrast, for any real loss L of the orders. The orders
+ * a = c0 + W V u are holomorphic in delta_eps, u being the total field of
+ * (I - M V) u = e_bg (M = K + R_vol T_R K_top, eqs. (3), (8)-(9), (18)); with
+ * lambda = (I - M^T V)^-1 W^T conj(G) (the transposed coupled system, kernel
+ * at the negated wavevector), dL = Re sum_r k0^2 d(delta_eps) sum_c lambda_c u_c.
+ * Inputs (device, complex128): d_deps [nz][ny][nx]; d_u [3][nz][ny][nx], the
+ * forward total field (psfd_solve's d_u with the same plan and contrast);
+ * d_grad_orders [ny][nx][3], G = dL/dRe a + i dL/dIm a (PyTorch's convention
+ * for complex tensors, twice dL/d conj(a)). Output d_grad [nz][ny][nx]
+ * (device, complex128, must not alias an input) = dL/dRe delta_eps + i dL/dIm
+ * delta_eps. The transposed GMRES runs with the plan's options (tolerance,
+ * restart, precision); info (may be NULL) receives its counters. Blocks until
+ * done. Errors: INVALID_ARG, NONFINITE, OOM, HIP; NOT_CONVERGED with d_grad
+ * written when the iteration limit stops the solve. */
+int psfd_solve_adjoint(psfd_plan* plan, const void* d_deps, const void* d_u, const void* d_grad_orders,
+                       void* d_grad, psfd_info* info, void* stream);
 
 /* Batched solves of instances of one grid shape (same nx, ny, nz, lx, ly, t,
  * wavelength and stack; angles, polarisation and contrast per instance) in
@@ -151,17 +166,28 @@ int psfd_solve_batch(int32_t n, const psfd_problem* probs, const psfd_opts* opts
 int psfd_release_cached_workspaces(void);
 
 /* Serving: continuous batching of solve requests admitted by device-memory
- * footprint. Requests of one grid shape share a slot group of up to max_slots
- * instances, created on the first request of that shape while it fits the
- * remaining hbm_budget (bytes of device workspace the server may allocate);
- * a request whose shape cannot get a group completes at once with
- * PSFD_ERR_OOM. Every group has its own worker thread and HIP stream, so the
- * groups run concurrently. submit copies the problem; the caller's buffers
+ * footprint. Requests of one kind (grid shape, restart length, precision,
+ * inner_eta) share a slot group; tolerance and iteration limit are per
+ * request. A group of min(max_slots, free budget / slot bytes) slots is
+ * created when a request of its kind arrives and one slot fits what is left
+ * of hbm_budget (bytes of device workspace the server may allocate; a slot is
+ * psfd_plan_footprint's bytes). Otherwise the request waits, first come first
+ * served: idle groups are released and the oldest busy groups drained (they
+ * finish their slots, then free their memory) until it fits. A group idle for
+ * 5 s frees its memory. Only a request that does not fit even an empty budget
+ * completes at once with PSFD_ERR_OOM. Every group has its own worker thread
+ * and HIP stream, so groups run concurrently; each group replays its Arnoldi
+ * steps as a captured HIP graph. Served solves use the monolithic coupling;
+ * a served result equals the lone psfd_solve of the same problem and options
+ * (same kernels, reductions in a fixed order per instance).
+ * create: opts (may be NULL: library defaults) are the defaults of requests
+ * submitted without options. submit copies the problem and options (opts may
+ * be NULL: the server's; the coupling field is ignored); the caller's buffers
  * must stay valid until poll reports done. destroy finishes every submitted
- * request, then frees the workspaces. */
+ * request, then frees the workspaces. submit / poll are thread-safe. */
 int psfd_server_create(size_t hbm_budget, int32_t max_slots, const psfd_opts* opts, psfd_server** out);
-int psfd_server_submit(psfd_server* srv, const psfd_problem* prob, const void* d_deps, void* d_emask,
-                       void* d_orders, uint64_t* ticket);
+int psfd_server_submit(psfd_server* srv, const psfd_problem* prob, const psfd_opts* opts, const void* d_deps,
+                       void* d_emask, void* d_orders, uint64_t* ticket);
 /* done = 1 once finished; info filled then. latency_s (may be NULL): submit to
  * completion wall time. */
 int psfd_server_poll(psfd_server* srv, uint64_t ticket, int32_t* done, psfd_info* info, double* latency_s);
@@ -242,16 +268,17 @@ int psfd_iso_apply(psfd_iso_plan* plan, const void* d_deps, const void* d_x, voi
 
 /* Solve u - P IFFT(table . FFT(Z V u)) = b (eq. (18) for the isolated scatterer,
  * b e.g. the incident field sampled on the grid) by GMRES(restart) (Saad &
- * Schultz) from u = 0: classical Gram-Schmidt (a second pass where it cancels
- * severely), every restart
+ * Schultz) from u = 0: classical Gram-Schmidt (a second pass where the update
+ * leaves less than 1/sqrt(2) of the norm), every restart
  * from the FP64 residual b - A u, u accumulated in FP64. precision: PSFD_FP64,
  * or PSFD_MIXED (FP32 basis and applies; a cycle also ends after reducing the
  * residual 1e4-fold). d_deps, d_b, d_u: complex128 device
  * arrays ([nz][ny][nx], [3][nz][ny][nx] twice); d_u must not alias d_b. Stops
  * when ||b - A u|| <= rtol ||b|| (info->rel_residual) or after max_iters
  * Arnoldi steps (then PSFD_NOT_CONVERGED, u written). 1 <= restart <= 64. The
- * basis ((restart + 1) 48 nx ny nz bytes in FP64, half in mixed) and two FP64
- * vectors are allocated for the call. Blocks
+ * basis ((restart + 1) 48 nx ny nz bytes in FP64, half in mixed), two FP64
+ * vectors and, in mixed precision, an FP32 copy of the contrast (8 nx ny nz
+ * bytes) are allocated for the call. Blocks
  * until done; calls on one plan must not overlap. */
 int psfd_iso_solve(psfd_iso_plan* plan, const void* d_deps, const void* d_b, void* d_u, double rtol, int32_t restart,
                    int32_t max_iters, int32_t precision, psfd_info* info, void* stream);

@@ -65,17 +65,17 @@ EXPORTS = {
     "psfd_plan_destroy": (None, [C.c_void_p]),
     "psfd_plan_footprint": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "psfd_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
-    "psfd_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(psfd_info), C.c_void_p]),
-    "psfd_solve_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_void_p,
-                                     C.POINTER(C.c_double), C.POINTER(psfd_info), C.POINTER(psfd_info),
-                                     C.c_void_p]),
+    "psfd_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(psfd_info),
+                             C.c_void_p]),
+    "psfd_solve_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.POINTER(psfd_info), C.c_void_p]),
     "psfd_solve_batch": (C.c_int, [C.c_int32, C.POINTER(psfd_problem), C.POINTER(psfd_opts),
                                    C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                    C.POINTER(psfd_info), C.c_void_p]),
     "psfd_release_cached_workspaces": (C.c_int, []),
     "psfd_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.POINTER(psfd_opts), C.POINTER(C.c_void_p)]),
-    "psfd_server_submit": (C.c_int, [C.c_void_p, C.POINTER(psfd_problem), C.c_void_p, C.c_void_p, C.c_void_p,
-                                     C.POINTER(C.c_uint64)]),
+    "psfd_server_submit": (C.c_int, [C.c_void_p, C.POINTER(psfd_problem), C.POINTER(psfd_opts), C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)]),
     "psfd_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(psfd_info),
                                    C.POINTER(C.c_double)]),
     "psfd_server_destroy": (C.c_int, [C.c_void_p]),

@@ -99,7 +99,9 @@ class Plan:
     apply = psfd_apply
 
     def psfd_solve(self, deps: torch.Tensor, emask: Optional[torch.Tensor] = None,
-                   orders: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, torch.Tensor, Dict]:
+                   orders: Optional[torch.Tensor] = None,
+                   u: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, torch.Tensor, Dict]:
+        """(E_mask, orders, info); u (optional, complex128 [3][nz][ny][nx]) receives the total field."""
         _dev(deps, torch.complex128, "deps")
         if tuple(deps.shape) != self.field_shape[1:]:
             raise ValueError("deps shape mismatch")
@@ -107,28 +109,41 @@ class Plan:
             emask = torch.empty(self.field_shape, dtype=torch.complex128, device=deps.device)
         if orders is None:
             orders = torch.empty((self.ny, self.nx, 3), dtype=torch.complex128, device=deps.device)
+        _dev(emask, torch.complex128, "emask")
+        _dev(orders, torch.complex128, "orders")
+        if tuple(emask.shape) != self.field_shape or tuple(orders.shape) != (self.ny, self.nx, 3):
+            raise ValueError("output shape mismatch")
+        up = None
+        if u is not None:
+            _dev(u, torch.complex128, "u")
+            if tuple(u.shape) != self.field_shape:
+                raise ValueError("u shape mismatch")
+            up = C.c_void_p(u.data_ptr())
         info = L.psfd_info()
         L.check(L.lib().psfd_solve(self._h, C.c_void_p(deps.data_ptr()), C.c_void_p(emask.data_ptr()),
-                                   C.c_void_p(orders.data_ptr()), C.byref(info), _stream()), "psfd_solve")
+                                   C.c_void_p(orders.data_ptr()), up, C.byref(info), _stream()), "psfd_solve")
         return emask, orders, info.as_dict()
 
     solve = psfd_solve
 
-    def psfd_solve_adjoint(self, deps: torch.Tensor, orders_sel: Sequence[Tuple[int, int]],
-                           grad: Optional[torch.Tensor] = None):
-        """Gradient dJ/dRe + i dJ/dIm of J = sum_q ||a_q||^2 over orders_sel."""
+    def psfd_solve_adjoint(self, deps: torch.Tensor, u: torch.Tensor, grad_orders: torch.Tensor,
+                           grad: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, Dict]:
+        """dL/dRe + i dL/dIm of delta_eps from the forward total field u and the cotangent
+        grad_orders = dL/dRe a + i dL/dIm a of the orders (complex128 [ny][nx][3])."""
         _dev(deps, torch.complex128, "deps")
+        _dev(u, torch.complex128, "u")
+        _dev(grad_orders, torch.complex128, "grad_orders")
+        if tuple(deps.shape) != self.field_shape[1:] or tuple(u.shape) != self.field_shape or \
+                tuple(grad_orders.shape) != (self.ny, self.nx, 3):
+            raise ValueError("shape mismatch")
         if grad is None:
             grad = torch.empty_like(deps)
-        sel = (C.c_int32 * (2 * max(1, len(orders_sel))))()
-        for i, (m, n) in enumerate(orders_sel):
-            sel[2 * i], sel[2 * i + 1] = int(m), int(n)
-        J = C.c_double()
-        fi, ai = L.psfd_info(), L.psfd_info()
-        L.check(L.lib().psfd_solve_adjoint(self._h, C.c_void_p(deps.data_ptr()), sel, len(orders_sel),
-                                           C.c_void_p(grad.data_ptr()), C.byref(J), C.byref(fi), C.byref(ai),
-                                           _stream()), "psfd_solve_adjoint")
-        return grad, float(J.value), fi.as_dict(), ai.as_dict()
+        _dev(grad, torch.complex128, "grad")
+        info = L.psfd_info()
+        L.check(L.lib().psfd_solve_adjoint(self._h, C.c_void_p(deps.data_ptr()), C.c_void_p(u.data_ptr()),
+                                           C.c_void_p(grad_orders.data_ptr()), C.c_void_p(grad.data_ptr()),
+                                           C.byref(info), _stream()), "psfd_solve_adjoint")
+        return grad, info.as_dict()
 
     adjoint = psfd_solve_adjoint
 
@@ -163,20 +178,30 @@ def psfd_release_cached_workspaces() -> None:
 
 
 class Server:
-    """Continuous-batching solve server (own worker thread and stream)."""
+    """Continuous-batching solve server (a worker thread and stream per group of requests)."""
 
     def __init__(self, hbm_budget: int, max_slots: int, **opts):
         self._opts = _c_opts(**opts)
+        self._defaults = dict(opts)
         h = C.c_void_p()
         L.check(L.lib().psfd_server_create(int(hbm_budget), int(max_slots), C.byref(self._opts), C.byref(h)),
                 "psfd_server_create")
         self._h = h
         self._keep = {}
 
-    def psfd_server_submit(self, prob, deps: torch.Tensor, emask: torch.Tensor, orders: torch.Tensor) -> int:
+    def psfd_server_submit(self, prob, deps: torch.Tensor, emask: torch.Tensor, orders: torch.Tensor,
+                           **opts) -> int:
+        """Submit one solve; opts (rtol, restart, precision, ...) override the server's defaults."""
         cp, k = _c_problem(prob)
+        for name, t, shape in (("deps", deps, (prob.nz, prob.ny, prob.nx)),
+                               ("emask", emask, (3, prob.nz, prob.ny, prob.nx)),
+                               ("orders", orders, (prob.ny, prob.nx, 3))):
+            _dev(t, torch.complex128, name)
+            if tuple(t.shape) != shape:
+                raise ValueError(f"{name} shape mismatch")
+        o = C.byref(_c_opts(**{**self._defaults, **opts})) if opts else None
         t = C.c_uint64()
-        L.check(L.lib().psfd_server_submit(self._h, C.byref(cp), C.c_void_p(deps.data_ptr()),
+        L.check(L.lib().psfd_server_submit(self._h, C.byref(cp), o, C.c_void_p(deps.data_ptr()),
                                            C.c_void_p(emask.data_ptr()), C.c_void_p(orders.data_ptr()),
                                            C.byref(t)), "psfd_server_submit")
         self._keep[int(t.value)] = (deps, emask, orders)
@@ -205,25 +230,40 @@ class Server:
     __del__ = close
 
 
-class OrderIntensity(torch.autograd.Function):
-    """J(delta_eps) = sum over the selected reflected orders of ||a_q||^2.
+class Orders(torch.autograd.Function):
+    """a(delta_eps): the reflected order amplitudes [ny][nx][3] of the plan's problem.
 
-    Forward runs the solve; backward the hand-written adjoint solve. The
-    gradient follows torch's convention for real losses of complex inputs
-    (dJ/dRe + i dJ/dIm).
+    Forward runs psfd_solve and keeps the total field; backward runs the
+    hand-written adjoint solve (psfd_solve_adjoint) on the incoming cotangent,
+    so any real loss of the orders can be differentiated. Gradients follow
+    torch's convention for complex tensors (dL/dRe + i dL/dIm).
     """
 
     @staticmethod
-    def forward(ctx, deps: torch.Tensor, plan: Plan, orders_sel: Tuple[Tuple[int, int], ...]):
-        grad, J, fi, ai = plan.psfd_solve_adjoint(deps.detach().contiguous(), orders_sel)
-        ctx.save_for_backward(grad)
-        ctx.info = (fi, ai)
-        return torch.tensor(J, dtype=torch.float64, device=deps.device)
+    def forward(ctx, deps: torch.Tensor, plan: Plan):
+        d = deps.detach().contiguous()
+        u = torch.empty(plan.field_shape, dtype=torch.complex128, device=deps.device)
+        _, orders, info = plan.psfd_solve(d, u=u)
+        ctx.save_for_backward(d, u)
+        ctx.plan = plan
+        ctx.info = info
+        return orders
 
     @staticmethod
     def backward(ctx, gout):
-        (grad,) = ctx.saved_tensors
-        return gout.to(grad.real.dtype) * grad, None, None
+        d, u = ctx.saved_tensors
+        grad, info = ctx.plan.psfd_solve_adjoint(d, u, gout.to(torch.complex128).contiguous())
+        ctx.adjoint_info = info
+        return grad, None
+
+
+def order_intensity(deps: torch.Tensor, plan: Plan, orders_sel: Sequence[Tuple[int, int]]) -> torch.Tensor:
+    """J = sum over the selected orders (m, n) of ||a_q||^2, differentiable in deps through Orders."""
+    a = Orders.apply(deps, plan)
+    ny, nx = a.shape[0], a.shape[1]
+    idx = torch.tensor([(n % ny) * nx + (m % nx) for (m, n) in orders_sel], device=a.device)
+    sel = a.reshape(ny * nx, 3).index_select(0, idx)
+    return (sel.real ** 2 + sel.imag ** 2).sum()
 
 
 class IsoPlan:

@@ -207,7 +207,8 @@ static Status ensure_solve(psfd_plan* p, hipStream_t s) {
   return Status();
 }
 
-int psfd_solve(psfd_plan* plan, const void* d_deps, void* d_emask, void* d_orders, psfd_info* info, void* stream) {
+int psfd_solve(psfd_plan* plan, const void* d_deps, void* d_emask, void* d_orders, void* d_u, psfd_info* info,
+               void* stream) {
   if (!plan || !d_deps || !d_emask) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
   Status st = ensure_solve(plan, s);
@@ -221,6 +222,11 @@ int psfd_solve(psfd_plan* plan, const void* d_deps, void* d_emask, void* d_order
   if (!st.ok()) return fail(st);
   e = hipMemcpyAsync(d_emask, g.x, sh.n3 * 16, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess && d_orders) e = hipMemcpyAsync(d_orders, g.ord, sh.nxny * 3 * 16, hipMemcpyDeviceToDevice, s);
+  // total field u = E_mask + E_inc + E_layer (g.x + g.e after either coupling)
+  if (e == hipSuccess && d_u) {
+    vec_axpby<double2, double2, double2>((double2*)d_u, g.x, g.e, 1.0, 1.0, sh.n3, sh.n3, nullptr, 1, s);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(hip_status(e, "copy results"));
   fill_info(info, stats[0]);
@@ -232,10 +238,11 @@ int psfd_solve(psfd_plan* plan, const void* d_deps, void* d_emask, void* d_order
   return PSFD_OK;
 }
 
-int psfd_solve_adjoint(psfd_plan* plan, const void* d_deps, const int32_t* orders_sel, int32_t n_sel, void* d_grad,
-                       double* J_out, psfd_info* info_fwd, psfd_info* info_adj, void* stream) {
-  if (!plan || !d_deps || !d_grad || (n_sel > 0 && !orders_sel) || n_sel < 0)
-    return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+int psfd_solve_adjoint(psfd_plan* plan, const void* d_deps, const void* d_u, const void* d_grad_orders, void* d_grad,
+                       psfd_info* info, void* stream) {
+  if (!plan || !d_deps || !d_u || !d_grad_orders || !d_grad) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  if (d_grad == d_u || d_grad == d_grad_orders || d_grad == d_deps)
+    return fail(PSFD_ERR_INVALID_ARG, "d_grad must not alias an input");
   hipStream_t s = (hipStream_t)stream;
   Status st = ensure_solve(plan, s);
   if (!st.ok()) return fail(st);
@@ -243,22 +250,17 @@ int psfd_solve_adjoint(psfd_plan* plan, const void* d_deps, const int32_t* order
   const Shape& sh = plan->sh;
   hipError_t e = hipMemcpyAsync(g.deps64, d_deps, sh.N * 16, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return fail(hip_status(e, "copy contrast"));
-  std::vector<SolveStats> fst, ast;
-  st = solve_group(g, plan->o, fst, s);
-  if (!st.ok()) return fail(st);
-  fill_info(info_fwd, fst[0]);
-  std::vector<std::pair<int, int>> sel;
-  for (int i = 0; i < n_sel; ++i) sel.emplace_back(orders_sel[2 * i], orders_sel[2 * i + 1]);
-  std::vector<double> J;
-  st = adjoint_group(g, plan->o, sel, (double2*)d_grad, J, ast, s);
+  std::vector<SolveStats> ast;
+  st = adjoint_group(g, plan->o, (const double2*)d_u, (const double2*)d_grad_orders, (double2*)d_grad, ast, s);
   if (!st.ok()) return fail(st);
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(hip_status(e, "adjoint"));
-  if (J_out) *J_out = J[0];
-  fill_info(info_adj, ast[0]);
-  int worst = std::min(fst[0].status, ast[0].status);
-  if (worst < 0) return fail(worst, "non-finite residual");
-  if (fst[0].status == PSFD_NOT_CONVERGED || ast[0].status == PSFD_NOT_CONVERGED) return PSFD_NOT_CONVERGED;
+  fill_info(info, ast[0]);
+  if (ast[0].status < 0) return fail(ast[0].status, "non-finite residual");
+  if (ast[0].status == PSFD_NOT_CONVERGED) {
+    g_last_error = "iteration limit reached";
+    return PSFD_NOT_CONVERGED;
+  }
   return PSFD_OK;
 }
 
@@ -283,10 +285,10 @@ int psfd_server_create(size_t hbm_budget, int32_t max_slots, const psfd_opts* op
   return st.ok() ? PSFD_OK : fail(st);
 }
 
-int psfd_server_submit(psfd_server* srv, const psfd_problem* prob, const void* d_deps, void* d_emask, void* d_orders,
-                       uint64_t* ticket) {
+int psfd_server_submit(psfd_server* srv, const psfd_problem* prob, const psfd_opts* opts, const void* d_deps,
+                       void* d_emask, void* d_orders, uint64_t* ticket) {
   if (!srv || !prob || !d_deps || !d_emask || !ticket) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
-  Status st = server_submit(srv, prob, d_deps, d_emask, d_orders, ticket);
+  Status st = server_submit(srv, prob, opts, d_deps, d_emask, d_orders, ticket);
   return st.ok() ? PSFD_OK : fail(st);
 }
 

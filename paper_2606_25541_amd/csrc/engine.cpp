@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -292,6 +293,11 @@ Status device_consts(DeviceConsts*& out) {
 
 // ---------------------------------------------------------------------------
 Group::~Group() {
+  for (auto& a : cycle_graph)
+    for (auto& c : a)
+      if (c.exec) (void)hipGraphExecDestroy(c.exec);
+  if (steps_graph.exec) (void)hipGraphExecDestroy(steps_graph.exec);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
   for (void* p : owned) (void)hipFree(p);
   for (hipEvent_t e : flag_ev)
     if (e) (void)hipEventDestroy(e);
@@ -586,6 +592,45 @@ int true_residual_every() {
   return v < 1 ? 1 : v;
 }
 
+bool use_graphs() {
+  const char* e = std::getenv("PSFD_GRAPH");
+  return !(e && std::atoi(e) == 0);
+}
+
+Status replay(Group& g, Group::Captured& c, const std::string& key, hipStream_t s,
+              const std::function<void(hipStream_t)>& issue) {
+  if (!c.exec || c.key != key) {
+    if (c.exec) {
+      HIPCHK(hipGraphExecDestroy(c.exec));
+      c.exec = nullptr;
+    }
+    if (!g.cap_stream) HIPCHK(hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal));
+    issue(g.cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(g.cap_stream, &graph);
+    if (e != hipSuccess) return hip_status(e, "graph capture");
+    e = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      c.exec = nullptr;
+      return hip_status(e, "graph instantiate");
+    }
+    c.key = key;
+  }
+  HIPCHK(hipGraphLaunch(c.exec, s));
+  return Status();
+}
+
+std::string launch_key(double eta, int every) {
+  char buf[160];
+  const char* d = std::getenv("PSFD_FUSE_DOTS");
+  const char* u = std::getenv("PSFD_FUSE_UPDATE");
+  std::snprintf(buf, sizeof(buf), "%.17g|%.17g|%d|%s|%s", cancel_threshold(), eta, every, d ? d : "-",
+                u ? u : "-");
+  return buf;
+}
+
 template <class T> static T* deps_of_mut(Group& g);
 template <> float2* deps_of_mut<float2>(Group& g) { return g.deps32; }
 template <> double2* deps_of_mut<double2>(Group& g) { return g.deps64; }
@@ -832,14 +877,39 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
       if (g.h_flags[slot * B + b]) return true;
     return false;
   };
+  const double cancel = cancel_threshold();
+  // the restart's residual: b - A x (FP64) where tres is set, the previous
+  // cycle's basis residual (left in v0 and its norm partials) where rres is;
+  // ||r||^2 from the partials of b - A x or of the basis residual, summed in the
+  // cycle start
+  auto cycle_start = [&](hipStream_t q) {
+    apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, refl, g.tres, q);  // A x
+    krylov_residual_parts<T>(g.b, g.r, (T*)g.basis, n3, n3, bsv, g.dpart, g.tres, B, q);
+    krylov_cycle_start_sum(g.st, g.n2, g.dpart, g.lpart, g.abs_target, eta, g.m, cancel, every, g.mask, g.tres,
+                           g.rres, g.run, g.cyc, B, q);
+  };
+  // every instance that runs a cycle starts it at j = 0 and stops for good
+  // when it ends, so the running ones all stand at step `step`; the cycle's
+  // solution update and the next restart's residual follow
+  auto cycle_body = [&](hipStream_t q) {
+    for (int step = 0; step < g.m; ++step) arnoldi_step<T>(g, transpose, refl, q, step);
+    krylov_solve_small(g.st, g.cyc, B, q);
+    krylov_lincomb_res<T, double2>((T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.cyc, g.rres, g.lpart, B, q);
+    cycle_start(q);
+  };
+  const bool graphs = use_graphs();
+  const std::string key = launch_key(eta, every);
+  cycle_start(s);
   for (int cyc = 0; cyc < max_cycles && !done; ++cyc) {
-    // the restart's residual: b - A x (FP64) where tres is set, the previous
-    // cycle's basis residual (left in v0 and its norm partials) where rres is
-    apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, refl, g.tres, s);  // A x
-    krylov_residual_parts<T>(g.b, g.r, (T*)g.basis, n3, n3, bsv, g.dpart, g.tres, B, s);
-    // ||r||^2 from the partials of b - A x or of the basis residual, summed in the cycle start
-    krylov_cycle_start_sum(g.st, g.n2, g.dpart, g.lpart, g.abs_target, eta, g.m, cancel_threshold(), every, g.mask,
-                           g.tres, g.rres, g.run, g.cyc, B, s);
+    if (cyc > 0) {
+      if (graphs) {
+        Status gs = replay(g, g.cycle_graph[transpose ? 1 : 0][refl ? 1 : 0], key, s, cycle_body);
+        if (!gs.ok()) return gs;
+      } else {
+        cycle_body(s);
+      }
+      HIPCHK(hipGetLastError());
+    }
     const int slot = cyc % FLAG_SLOTS;
     HIPCHK(hipMemcpyAsync(g.h_flags + slot * B, g.mask, sizeof(int) * B, hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(g.flag_ev[slot], s));
@@ -853,12 +923,6 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
       if (!snapshot_live(old)) { done = true; break; }
     }
     if (done) break;
-    // every instance that runs a cycle starts it at j = 0 and stops for good
-    // when it ends, so the running ones all stand at step `step`
-    for (int step = 0; step < g.m; ++step) arnoldi_step<T>(g, transpose, refl, s, step);
-    krylov_solve_small(g.st, g.cyc, B, s);
-    krylov_lincomb_res<T, double2>((T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.cyc, g.rres, g.lpart, B, s);
-    HIPCHK(hipGetLastError());
   }
   std::vector<GState> hs(B);
   HIPCHK(hipMemcpyAsync(hs.data(), g.st, sizeof(GState) * B, hipMemcpyDeviceToHost, s));
@@ -1006,37 +1070,22 @@ Status solve_group(Group& g, const Opts& o, std::vector<SolveStats>& stats, hipS
   return solve_group_t<double2>(g, o, stats, s);
 }
 
-// Adjoint of J = sum_{q in Q} ||a_q||^2 with a = c0 + W V u and (I - M V) u = e_bg:
-// dJ = 2 Re sum_r k0^2 d(delta_eps) sum_c lam_c u_c with
-// (I - M^T V) lam = W^T conj(a|_Q),  W = diag(e^{i beta T}) T_R K_top + K_up.
-// Runs after solve_group (fields of the forward solve in g.x, g.e, g.ord).
+// Vector-Jacobian product of the reflected orders a = c0 + W V u, with u the total
+// field of (I - M V) u = e_bg, for a cotangent G = dL/dRe a + i dL/dIm a of a real
+// loss L: dL = Re sum_r k0^2 d(delta_eps) sum_c lam_c u_c with
+// (I - M^T V) lam = W^T conj(G),  W = diag(e^{i beta T}) T_R K_top + K_up,
+// so dL/dRe + i dL/dIm of delta_eps is conj(k0^2 sum_c lam_c u_c).
+// u and G are device arrays [B][n3] and [B][nx ny 3]; the contrast is in g.deps64.
 template <class T>
-static Status adjoint_group_t(Group& g, const Opts& o, const std::vector<std::pair<int, int>>& sel, double2* grad,
-                              long long gstride, std::vector<double>& J, std::vector<SolveStats>& stats,
-                              hipStream_t s) {
+static Status adjoint_group_t(Group& g, const Opts& o, const double2* u, const double2* gord, double2* grad,
+                              long long gstride, std::vector<SolveStats>& stats, hipStream_t s) {
   const int B = g.B;
   const Shape& sh = g.sh;
   const long long n3 = sh.n3, nq = sh.nxny * 3;
   stats.assign(B, SolveStats());
-  // u = E_inc + E_layer + E_mask of the forward solve
-  vec_axpby<double2, double2, double2>(g.u, g.x, g.e, 1.0, 1.0, n3, n3, nullptr, B, s);
-  // c = conj(a) on the selected orders
-  std::vector<double2> a((size_t)nq * B), c((size_t)nq * B);
-  HIPCHK(hipMemcpyAsync(a.data(), g.ord, sizeof(double2) * nq * B, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  J.assign(B, 0.0);
-  std::memset(c.data(), 0, sizeof(double2) * c.size());
-  for (int b = 0; b < B; ++b)
-    for (auto& mn : sel) {
-      const int i = ((mn.first % sh.nx) + sh.nx) % sh.nx, j = ((mn.second % sh.ny) + sh.ny) % sh.ny;
-      const long long q = (long long)b * nq + 3LL * ((long long)j * sh.nx + i);
-      for (int k = 0; k < 3; ++k) {
-        J[b] += a[q + k].x * a[q + k].x + a[q + k].y * a[q + k].y;
-        c[q + k] = make_double2(a[q + k].x, -a[q + k].y);
-      }
-    }
-  HIPCHK(hipMemcpyAsync(g.eup2, c.data(), sizeof(double2) * nq * B, hipMemcpyHostToDevice, s));
-  launch_adjoint_source(sh.nx, sh.ny, g.tab, g.tab_stride, g.eup2, g.adn, g.aup, nq, B, s);
+  if (g.prec == PSFD_MIXED)
+    vec_axpby<float2, double2, double2>(g.deps32, g.deps64, nullptr, 1.0, 0.0, sh.N, sh.N, nullptr, B, s);
+  launch_adjoint_source(sh.nx, sh.ny, g.tab, g.tab_stride, gord, g.adn, g.aup, nq, B, s);
   // s = W^T c: transposed plane-wave injection into b
   std::vector<int> all(B, 1);
   Status st = set_mask(g, g.mask2, all, s);
@@ -1064,16 +1113,16 @@ static Status adjoint_group_t(Group& g, const Opts& o, const std::vector<std::pa
   std::vector<double> tol(B, o.rtol);
   st = linear_solve<T>(g, o, all, tol, stats, 1, 1, s);
   if (!st.ok()) return st;
-  launch_gradient(sh.N, g.tab, g.tab_stride, g.x, g.u, n3, grad, gstride, B, s);
+  launch_gradient(sh.N, g.tab, g.tab_stride, g.x, u, n3, grad, gstride, B, s);
   for (int b = 0; b < B; ++b) { stats[b].outer = 1; stats[b].mono = stats[b].rel_res; }
   HIPCHK(hipGetLastError());
   return Status();
 }
 
-Status adjoint_group(Group& g, const Opts& o, const std::vector<std::pair<int, int>>& orders_sel, double2* grad,
-                     std::vector<double>& J, std::vector<SolveStats>& stats, hipStream_t s) {
-  if (g.prec == PSFD_MIXED) return adjoint_group_t<float2>(g, o, orders_sel, grad, g.sh.N, J, stats, s);
-  return adjoint_group_t<double2>(g, o, orders_sel, grad, g.sh.N, J, stats, s);
+Status adjoint_group(Group& g, const Opts& o, const double2* u, const double2* grad_orders, double2* grad,
+                     std::vector<SolveStats>& stats, hipStream_t s) {
+  if (g.prec == PSFD_MIXED) return adjoint_group_t<float2>(g, o, u, grad_orders, grad, g.sh.N, stats, s);
+  return adjoint_group_t<double2>(g, o, u, grad_orders, grad, g.sh.N, stats, s);
 }
 
 }  // namespace psfd

@@ -1,6 +1,7 @@
 // Host engine: problem tables, device workspaces of a group of same-shape
 // instances, operator apply orchestration and the solve drivers.
 #pragma once
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -114,9 +115,30 @@ struct Group {
   hipEvent_t flag_ev[FLAG_SLOTS] = {};
   int* h_run = nullptr;      // pinned host mirrors
   double* h_dbl = nullptr;
+  // Captured launch sequences (HIP graphs), replayed on the caller's stream:
+  // one restart cycle of the device-driven solve, or the server's block of
+  // Arnoldi steps. A graph is re-captured when its key (the launch choices
+  // baked into it) changes.
+  struct Captured {
+    hipGraphExec_t exec = nullptr;
+    std::string key;
+  };
+  Captured cycle_graph[2][2];   // [transpose][refl]
+  Captured steps_graph;
+  hipStream_t cap_stream = nullptr;  // capture only (launches are not executed there)
   std::vector<void*> owned;
   ~Group();
 };
+
+// Whether restart cycles and the server's Arnoldi blocks run as captured HIP
+// graphs (PSFD_GRAPH=0 issues the same launches one by one; read per call).
+bool use_graphs();
+// Replays the captured sequence `c` on stream s, capturing `issue(cs)` first when
+// the key differs (cs is the group's capture stream).
+Status replay(Group& g, Group::Captured& c, const std::string& key, hipStream_t s,
+              const std::function<void(hipStream_t)>& issue);
+// The launch choices read from the environment that a captured sequence bakes in.
+std::string launch_key(double eta, int every);
 
 size_t group_bytes(const Shape& sh, int B, int m, int prec);
 Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec);
@@ -145,9 +167,12 @@ struct SolveStats {
 
 // Forward solve of every instance (deps64 filled). Results stay in g.x / g.ord.
 Status solve_group(Group& g, const Opts& o, std::vector<SolveStats>& stats, hipStream_t s);
-// Adjoint of J = sum over orders_sel of ||a_q||^2 after solve_group; grad (complex128 [N]) per instance.
-Status adjoint_group(Group& g, const Opts& o, const std::vector<std::pair<int, int>>& orders_sel,
-                     double2* grad, std::vector<double>& J, std::vector<SolveStats>& stats, hipStream_t s);
+// Vector-Jacobian product of the reflected orders (adjoint solve, transposed
+// coupled system): u [B][n3] the forward total field, grad_orders [B][nx ny 3]
+// the cotangent dL/dRe a + i dL/dIm a; grad [B][N] receives dL/dRe + i dL/dIm of
+// delta_eps. The contrast must be in g.deps64 and the tables set.
+Status adjoint_group(Group& g, const Opts& o, const double2* u, const double2* grad_orders, double2* grad,
+                     std::vector<SolveStats>& stats, hipStream_t s);
 
 Status hip_status(hipError_t e, const char* what);
 

@@ -5,6 +5,9 @@
 //                          F[G_L](k) evaluated on the fly, inverse z-FFT),
 // plus the per-order background-field kernels of the outer loop (eqs. (8)-(9)):
 // plane-wave readouts of the mask field, reflection by T_R, order amplitudes.
+#include <cstdio>
+#include <cstdlib>
+
 #include "kernels.hpp"
 #include "fft_lds.hpp"
 #include "givens.hpp"
@@ -536,6 +539,17 @@ bool tile_takes_dots(const TileArgs& a, size_t esz) {
   return esz == 8 && plane_ln(a, esz) != 0 && 3 * a.nz <= DotBlocks<float2>::value;
 }
 
+// The Givens task and norm_from_partials need blocks of at least GIVENS_THREADS
+// threads (their partial sums are spread over that many lanes). Every launch that
+// passes a GivensTask (or the update task, whose blocks sum the same partials) is
+// gated on that by its caller; a launch that breaks the rule would sum unwritten
+// LDS words, so it stops the process instead of computing a wrong result.
+[[noreturn]] static void givens_block_too_small(const char* kern, int nthr) {
+  std::fprintf(stderr, "psfd: internal error: %s launched with a Givens task in blocks of %d threads (< %d)\n",
+               kern, nthr, GIVENS_THREADS);
+  std::abort();
+}
+
 template <class T, bool INV, int LD, int ST>
 void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t lds, hipStream_t s) {
   dim3 grid(nplanes * a.tiles_x * a.tiles_y, nbatch);
@@ -544,6 +558,8 @@ void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t ld
     allow_lds(reinterpret_cast<const void*>(kern), l);
     dim3 g2 = grid;
     if (LD == LD_VX && a.gv.st) g2.x += 1;  // the GivensTask block
+    if ((a.gv.st || LD == LD_UPD_VX || LD == LD_UPD_SLOT) && plane_threads(ln) < GIVENS_THREADS)
+      givens_block_too_small("k_plane", plane_threads(ln));
     hipLaunchKernelGGL(kern, g2, dim3(plane_threads(ln)), l, s, a);
   };
   if constexpr (ST == ST_DOTS) {
@@ -926,6 +942,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
 template <class T>
 void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStream_t s) {
   dim3 grid(a.nblk_x * a.ny + (a.gv.st ? 1 : 0), nbatch);  // + the GivensTask block
+  if (a.gv.st && nthr < GIVENS_THREADS) givens_block_too_small("k_pencil", nthr);
   auto go = [&](auto kern) {
     allow_lds(reinterpret_cast<const void*>(kern), lds);
     hipLaunchKernelGGL(kern, grid, dim3(nthr), lds, s, a);
@@ -1036,7 +1053,7 @@ void launch_reflect(int nx, int ny, const double* tab, long long tab_stride, con
   hipLaunchKernelGGL(k_reflect, grid, dim3(256), 0, s, nx, ny, tab, tab_stride, adn, eup, ostride, part, active);
 }
 
-__global__ void k_adjoint_source(int nx, int ny, const double* tab_all, long long tab_stride, const double2* c_all,
+__global__ void k_adjoint_source(int nx, int ny, const double* tab_all, long long tab_stride, const double2* g_all,
                                  double2* bdn_all, double2* bup_all, long long ostride) {
   const int b = blockIdx.y;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1055,8 +1072,9 @@ __global__ void k_adjoint_source(int nx, int ny, const double* tab_all, long lon
   const double2 fac = cscale(cdiv(make_double2(0.0, dz), make_double2(2.0 * beta.x, 2.0 * beta.y)), tab[TS_INVNXNY]);
   const double2 ph = cexp_i(make_double2(beta.x * T, beta.y * T));
   const double2* tr = reinterpret_cast<const double2*>(tab + L.off_tr()) + 9LL * q;
-  const double2* c = c_all + o;
-  double2 v[3], t[3];
+  // c = conj(G): the cotangent in the convention dL/dRe a + i dL/dIm a
+  double2 c[3], v[3], t[3];
+  for (int i = 0; i < 3; ++i) c[i] = make_double2(g_all[o + i].x, -g_all[o + i].y);
   for (int i = 0; i < 3; ++i) v[i] = cmul(ph, c[i]);
   for (int r = 0; r < 3; ++r) t[r] = cadd(cadd(cmul(tr[r], v[0]), cmul(tr[3 + r], v[1])), cmul(tr[6 + r], v[2]));
   const double ik2 = 1.0 / (kbg * kbg);
@@ -1087,7 +1105,7 @@ __global__ void k_gradient(long long N, const double* tab_all, long long tab_str
   for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (long long)gridDim.x * blockDim.x) {
     double2 t = make_double2(0, 0);
     for (int c = 0; c < 3; ++c) t = cadd(t, cmul(lam[c * N + r], u[c * N + r]));
-    g[r] = make_double2(2.0 * k0sq * t.x, -2.0 * k0sq * t.y);
+    g[r] = make_double2(k0sq * t.x, -k0sq * t.y);
   }
 }
 

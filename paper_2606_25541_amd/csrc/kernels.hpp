@@ -130,11 +130,13 @@ void launch_readout(int nx, int ny, int nz, VecRef spec, const double* tab, long
 void launch_reflect(int nx, int ny, const double* tab, long long tab_stride, const double2* adn,
                     double2* eup, long long ostride, double* part, int nblk, const int* active, int nbatch,
                     hipStream_t s);
-// Adjoint source per order from c = dJ/da (conj of the selected amplitudes):
+// Adjoint source per order from the cotangent G = dL/dRe a + i dL/dIm a of the
+// orders, with c = conj(G):
 // b_dn = (i dz / 2 beta)(1/NxNy) P- T_R^T (exp(i beta T) c), b_up = (i dz / 2 beta)(1/NxNy) P+ c
-void launch_adjoint_source(int nx, int ny, const double* tab, long long tab_stride, const double2* c,
+void launch_adjoint_source(int nx, int ny, const double* tab, long long tab_stride, const double2* g,
                            double2* bdn, double2* bup, long long ostride, int nbatch, hipStream_t s);
-// grad = 2 conj(k0^2 sum_c lam_c u_c) per voxel (complex128 [nz][ny][nx]); out[b] at outs[b]
+// grad = conj(k0^2 sum_c lam_c u_c) per voxel (complex128 [nz][ny][nx]), the
+// gradient dL/dRe + i dL/dIm of the loss whose cotangent made the adjoint source
 void launch_gradient(long long N, const double* tab, long long tab_stride, const double2* lam, const double2* u,
                      long long n3stride, double2* grad, long long gstride, int nbatch, hipStream_t s);
 // per-order part of an instance table (beta, exp(i beta L), keep, T_R) from kx, ky,

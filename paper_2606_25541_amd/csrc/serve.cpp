@@ -127,14 +127,14 @@ Status solve_batch(int n, const psfd_problem* probs, const psfd_opts* opts, cons
 // ---------------------------------------------------------------------------
 // Continuous-batching solve server.
 //
-// Requests are grouped by grid shape. Each shape owns a slot group (a Group of
-// `cap` instances) allocated the first time the shape appears, sized so that
-// the groups' device footprint stays within the budget. Every slot group has
-// its own worker thread and HIP stream, so the groups of different shapes run
-// concurrently on the device and small requests never wait behind the launches
-// of large ones. A worker runs ticks; every tick advances every occupied slot
-// of its group by one phase of its own coupled solve (monolithic coupling,
-// GMRES(m) with FP64 residuals):
+// Requests are grouped by kind: grid shape, restart length, precision and the
+// FP32 cycle reduction (what fixes a group's buffers and launches); tolerance
+// and iteration limit are per request. Each kind runs in a slot group (a Group
+// of `cap` instances) with its own worker thread and HIP stream, so groups of
+// different kinds run concurrently on the device and small requests never wait
+// behind the launches of large ones. A worker runs ticks; every tick advances
+// every occupied slot of its group by one phase of its own coupled solve
+// (monolithic coupling, GMRES(m) with FP64 residuals):
 //   INIT  tables, contrast, e_bg, x0 = e_bg, ||b||
 //   START FP64 residual r = b - A x: done, or start an Arnoldi cycle
 //   ARN   Arnoldi steps (all running slots share each launch)
@@ -144,15 +144,40 @@ Status solve_batch(int n, const psfd_problem* probs, const psfd_opts* opts, cons
 // next tick and share the launches from then on. Every kernel works per
 // instance with a fixed reduction layout, so a result does not depend on which
 // other requests share the group.
+//
+// Admission by device-memory footprint. A request whose kind has a running
+// group joins that group's queue. Otherwise it waits in the server's pending
+// list (first come, first served) until its kind can get a group: a group of
+// min(max_slots, free budget / slot bytes) slots is created as soon as one
+// slot fits what is left of the budget. When it does not fit, idle groups are
+// released at once and, if that is not enough, the oldest busy groups are
+// drained: they take no new requests, finish the ones already queued to them,
+// then free their memory. A group idle for IDLE_RELEASE_S also frees its
+// memory. Only a request that cannot fit even an empty budget completes with
+// PSFD_ERR_OOM.
 // ---------------------------------------------------------------------------
 using clk = std::chrono::steady_clock;
 
+static const double IDLE_RELEASE_S = 5.0;
+
 enum Phase { P_FREE = 0, P_INIT, P_START, P_ARN, P_END, P_FIN };
+
+// what fixes a slot group's buffers and launches
+struct Kind {
+  Shape sh;
+  int m = 30, prec = PSFD_MIXED;
+  double eta = 1e-4;
+  bool operator==(const Kind& k) const {
+    return sh.nx == k.sh.nx && sh.ny == k.sh.ny && sh.nz == k.sh.nz && m == k.m && prec == k.prec && eta == k.eta;
+  }
+};
 
 struct Req {
   uint64_t ticket = 0;
   Problem pr;
-  Shape sh;
+  Opts o;
+  Kind kind;
+  size_t slot_bytes = 0;
   std::vector<double> tab;
   const void* d_deps = nullptr;
   void* d_emask = nullptr;
@@ -164,13 +189,16 @@ struct Req {
 };
 
 struct SlotGroup {
-  Shape sh;
+  Kind kind;
+  size_t bytes = 0;
   std::unique_ptr<Group> g;
   int cap = 0;
   hipStream_t s = nullptr;
   std::thread worker;
   std::condition_variable cv;
   std::deque<Req*> queue;  // waiting for a free slot of this group (guarded by the server mutex)
+  bool draining = false;   // takes no new requests; released once its queue and slots are empty
+  bool dead = false;       // released (memory freed, worker exiting)
   std::vector<Req*> req;
   std::vector<int> phase;
   std::vector<int> cycles;
@@ -193,18 +221,17 @@ struct psfd_server {
   int max_slots = 1;
   psfd::Opts o;
   int device = 0;
-  std::mutex mu;  // guards reqs, groups, every group queue, next, stop, allocated, err
+  std::mutex mu;  // guards everything below and every group's queue, req slots' ownership, flags
   std::unordered_map<uint64_t, std::unique_ptr<psfd::Req>> reqs;
+  std::deque<psfd::Req*> pending;  // waiting for a group of their kind, in ticket order
   uint64_t next = 1;
   bool stop = false;
   size_t allocated = 0;
-  std::vector<std::unique_ptr<psfd::SlotGroup>> groups;
+  std::vector<std::unique_ptr<psfd::SlotGroup>> groups;  // live and released (joined at destroy)
   psfd::Status err;
 };
 
 namespace psfd {
-
-static bool shape_eq(const Shape& a, const Shape& b) { return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz; }
 
 static void finish_req(psfd_server* S, Req* r, int status) {
   std::lock_guard<std::mutex> lk(S->mu);
@@ -218,9 +245,8 @@ template <class T>
 static Status tick_group(psfd_server* S, SlotGroup& G) {
   Group& g = *G.g;
   hipStream_t s = G.s;
-  const Opts& o = S->o;
   const int B = G.cap;
-  const Shape& sh = G.sh;
+  const Shape& sh = G.kind.sh;
   const long long n3 = sh.n3, nq = sh.nxny * 3, N = sh.N, bsv = (long long)(g.m + 1) * n3;
   auto mask_of = [&](int ph) {
     std::vector<int> m(B, 0);
@@ -260,7 +286,11 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
       st = read_norms(g, g.n2b, bn2, s);
       if (!st.ok()) return st;
       for (int b = 0; b < B; ++b)
-        if (mk.first[b]) { G.bn[b] = std::sqrt(bn2[b]); G.tgt[b] = o.rtol * G.bn[b]; G.phase[b] = P_START; }
+        if (mk.first[b]) {
+          G.bn[b] = std::sqrt(bn2[b]);
+          G.tgt[b] = G.req[b]->o.rtol * G.bn[b];
+          G.phase[b] = P_START;
+        }
       std::memcpy(g.h_dbl, G.tgt.data(), sizeof(double) * B);
       hipError_t e = hipMemcpyAsync(g.abs_target, g.h_dbl, sizeof(double) * B, hipMemcpyHostToDevice, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -303,7 +333,7 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
         r->info.cycles = G.cycles[b];
         if (!std::isfinite(rn)) { r->status = PSFD_ERR_NONFINITE; G.phase[b] = P_FIN; continue; }
         const bool met = rn <= G.tgt[b] || G.bn[b] == 0.0;
-        const bool limit = hs[b].iters >= o.max_iters;
+        const bool limit = hs[b].iters >= r->o.max_iters;
         if (was_true) {
           r->info.rel_residual = G.bn[b] > 0 ? rn / G.bn[b] : 0.0;
           if (met) { G.phase[b] = P_FIN; continue; }
@@ -325,7 +355,7 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
       if (any) {
         st = set_mask(g, g.mask, go, s);
         if (!st.ok()) return st;
-        krylov_start(g.st, g.n2, g.abs_target, g.prec == PSFD_MIXED ? o.inner_eta : 0.0, g.m, cancel_threshold(),
+        krylov_start(g.st, g.n2, g.abs_target, g.prec == PSFD_MIXED ? G.kind.eta : 0.0, g.m, cancel_threshold(),
                      g.mask, g.run, B, s);
       }
     }
@@ -369,7 +399,15 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
     bool any = false;
     for (int b = 0; b < B; ++b) any |= G.phase[b] == P_ARN;
     if (any) {
-      for (int k = 0; k < STEPS_PER_SYNC; ++k) arnoldi_step<T>(g, 0, 1, s);
+      auto steps = [&](hipStream_t q) {
+        for (int k = 0; k < STEPS_PER_SYNC; ++k) arnoldi_step<T>(g, 0, 1, q);
+      };
+      if (use_graphs()) {
+        st = replay(g, g.steps_graph, launch_key(0.0, 0), s, steps);
+        if (!st.ok()) return st;
+      } else {
+        steps(s);
+      }
       hipError_t e = hipGetLastError();
       if (e == hipSuccess) e = hipMemcpyAsync(g.h_run, g.run, sizeof(int) * B, hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -395,18 +433,135 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
   return Status();
 }
 
+static void group_worker(psfd_server* S, SlotGroup* G);
+
+// Merge requests (in ticket order) into the pending list, keeping it in ticket order.
+static void to_pending(psfd_server* S, std::deque<Req*>& q) {
+  for (Req* r : q) {
+    auto it = S->pending.begin();
+    while (it != S->pending.end() && (*it)->ticket < r->ticket) ++it;
+    S->pending.insert(it, r);
+  }
+  q.clear();
+}
+
+static SlotGroup* live_group(psfd_server* S, const Kind& k) {
+  for (auto& gp : S->groups)
+    if (!gp->dead && !gp->draining && gp->kind == k) return gp.get();
+  return nullptr;
+}
+
+// A new slot group of kind k with cap slots: workspace, stream and worker.
+static Status make_group(psfd_server* S, const Kind& k, size_t per, int cap, SlotGroup*& out) {
+  auto ng = std::make_unique<SlotGroup>();
+  ng->kind = k;
+  ng->g = std::make_unique<Group>();
+  Status st = group_alloc(*ng->g, k.sh, cap, k.m, k.prec);
+  if (!st.ok()) return st;
+  hipError_t e = hipStreamCreateWithFlags(&ng->s, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_status(e, "server stream");
+  ng->cap = cap;
+  ng->bytes = per * (size_t)cap;
+  ng->req.assign(cap, nullptr);
+  ng->phase.assign(cap, P_FREE);
+  ng->cycles.assign(cap, 0);
+  ng->tres.assign(cap, 1);
+  ng->rres.assign(cap, 0);
+  ng->since.assign(cap, 0);
+  ng->bn.assign(cap, 0.0);
+  ng->tgt.assign(cap, 0.0);
+  ng->res.assign(cap, 0.0);
+  S->allocated += ng->bytes;
+  out = ng.get();
+  S->groups.push_back(std::move(ng));
+  out->worker = std::thread(group_worker, S, out);
+  return Status();
+}
+
+// Admission of the pending list, first come, first served (server mutex held).
+static void admit_pending(psfd_server* S) {
+  while (!S->pending.empty()) {
+    Req* r = S->pending.front();
+    if (SlotGroup* G = live_group(S, r->kind)) {
+      S->pending.pop_front();
+      G->queue.push_back(r);
+      G->cv.notify_one();
+      continue;
+    }
+    const size_t per = r->slot_bytes;
+    const size_t avail = S->budget > S->allocated ? S->budget - S->allocated : 0;
+    if (avail >= per) {
+      const int cap = (int)std::min<size_t>((size_t)S->max_slots, avail / per);
+      SlotGroup* G = nullptr;
+      Status st = make_group(S, r->kind, per, cap, G);
+      if (!st.ok()) {
+        // the device refused the memory: the request ends with that status
+        S->pending.pop_front();
+        S->err = st;
+        r->status = st.code;
+        r->info.status = st.code;
+        r->t_done = clk::now();
+        r->done = true;
+        continue;
+      }
+      S->pending.pop_front();
+      G->queue.push_back(r);
+      G->cv.notify_one();
+      continue;
+    }
+    // not enough memory left: release idle groups, then drain the oldest busy ones
+    size_t freeing = 0;
+    for (auto& gp : S->groups)
+      if (!gp->dead && gp->draining) freeing += gp->bytes;
+    for (int pass = 0; pass < 2 && avail + freeing < per; ++pass)
+      for (auto& gp : S->groups) {
+        if (gp->dead || gp->draining || avail + freeing >= per) continue;
+        const bool idle = gp->occupied() == 0 && gp->queue.empty();
+        if (pass == 0 && !idle) continue;
+        gp->draining = true;
+        freeing += gp->bytes;
+        gp->cv.notify_one();
+      }
+    break;  // the head waits for the memory; later requests keep their place behind it
+  }
+}
+
+// Release of a group by its own worker (server mutex held, queue empty): memory
+// freed, then admission of the pending list.
+static void release_group(psfd_server* S, SlotGroup* G) {
+  G->dead = true;
+  to_pending(S, G->queue);
+  if (G->s) {
+    (void)hipStreamSynchronize(G->s);
+    (void)hipStreamDestroy(G->s);
+    G->s = nullptr;
+  }
+  G->g.reset();
+  S->allocated -= G->bytes;
+  G->bytes = 0;
+  admit_pending(S);
+}
+
 // Worker of one slot group: admits its queued requests into free slots and
-// ticks while any slot is occupied; sleeps otherwise. On shutdown it finishes
-// every request already submitted, then exits.
+// ticks while any slot is occupied. With no slot occupied it waits for work;
+// it releases the group when asked to drain, after IDLE_RELEASE_S without work,
+// or at shutdown once nothing is left for it.
 static void group_worker(psfd_server* S, SlotGroup* G) {
   (void)hipSetDevice(S->device);
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
       if (G->occupied() == 0) {
-        G->cv.wait(lk, [&] { return S->stop || !G->queue.empty(); });
-        if (S->stop && G->queue.empty()) return;
+        const bool work = G->cv.wait_for(lk, std::chrono::duration<double>(IDLE_RELEASE_S), [&] {
+          return S->stop || G->draining || !G->queue.empty();
+        });
+        if (G->queue.empty() && (G->draining || S->stop || !work)) {
+          release_group(S, G);
+          return;
+        }
       }
+      // requests already in the queue were admitted to this group: a draining
+      // group still runs them, it only takes no new ones
       for (int b = 0; b < G->cap && !G->queue.empty(); ++b) {
         if (G->req[b]) continue;
         G->req[b] = G->queue.front();
@@ -414,7 +569,7 @@ static void group_worker(psfd_server* S, SlotGroup* G) {
         G->queue.pop_front();
       }
     }
-    Status st = S->o.precision == PSFD_MIXED ? tick_group<float2>(S, *G) : tick_group<double2>(S, *G);
+    Status st = G->kind.prec == PSFD_MIXED ? tick_group<float2>(S, *G) : tick_group<double2>(S, *G);
     if (!st.ok()) {
       // a runtime failure ends every request of the group
       {
@@ -441,51 +596,25 @@ Status server_create(size_t hbm_budget, int max_slots, const psfd_opts* opts, ps
   return st;
 }
 
-// The slot group of a shape, created (workspace, stream, worker) on first use
-// within the remaining budget; nullptr with status OOM when not even one slot fits.
-static SlotGroup* group_for(psfd_server* S, const Shape& sh, Status& st) {
-  for (auto& gp : S->groups)
-    if (shape_eq(gp->sh, sh)) return gp.get();
-  const size_t per = group_bytes(sh, 1, S->o.restart, S->o.precision);
-  const size_t avail = S->budget > S->allocated ? S->budget - S->allocated : 0;
-  const int cap = (int)std::min<size_t>((size_t)S->max_slots, avail / per);
-  if (cap < 1) {
-    st.code = PSFD_ERR_OOM;
-    st.msg = "the request does not fit the server's device-memory budget";
-    return nullptr;
-  }
-  auto ng = std::make_unique<SlotGroup>();
-  ng->sh = sh;
-  ng->g = std::make_unique<Group>();
-  st = group_alloc(*ng->g, sh, cap, S->o.restart, S->o.precision);
-  if (!st.ok()) return nullptr;
-  hipError_t e = hipStreamCreateWithFlags(&ng->s, hipStreamNonBlocking);
-  if (e != hipSuccess) { st = hip_status(e, "server stream"); return nullptr; }
-  ng->cap = cap;
-  ng->req.assign(cap, nullptr);
-  ng->phase.assign(cap, P_FREE);
-  ng->cycles.assign(cap, 0);
-  ng->tres.assign(cap, 1);
-  ng->rres.assign(cap, 0);
-  ng->since.assign(cap, 0);
-  ng->bn.assign(cap, 0.0);
-  ng->tgt.assign(cap, 0.0);
-  ng->res.assign(cap, 0.0);
-  S->allocated += per * (size_t)cap;
-  SlotGroup* G = ng.get();
-  S->groups.push_back(std::move(ng));
-  G->worker = std::thread(group_worker, S, G);
-  return G;
-}
-
-Status server_submit(psfd_server* S, const psfd_problem* prob, const void* d_deps, void* d_emask, void* d_orders,
-                     uint64_t* ticket) {
+Status server_submit(psfd_server* S, const psfd_problem* prob, const psfd_opts* opts, const void* d_deps,
+                     void* d_emask, void* d_orders, uint64_t* ticket) {
   auto r = std::make_unique<Req>();
   Status st = validate_problem(prob, r->pr);
   if (!st.ok()) return st;
+  if (opts) {
+    st = make_opts(opts, r->o);
+    if (!st.ok()) return st;
+  } else {
+    r->o = S->o;
+  }
+  r->o.coupling = PSFD_COUPLING_MONO;
   st = build_table(r->pr, r->tab);
   if (!st.ok()) return st;
-  r->sh = shape_of(r->pr.p);
+  r->kind.sh = shape_of(r->pr.p);
+  r->kind.m = r->o.restart;
+  r->kind.prec = r->o.precision;
+  r->kind.eta = r->o.precision == PSFD_MIXED ? r->o.inner_eta : 0.0;
+  r->slot_bytes = group_bytes(r->kind.sh, 1, r->kind.m, r->kind.prec);
   r->d_deps = d_deps;
   r->d_emask = d_emask;
   r->d_orders = d_orders;
@@ -496,18 +625,21 @@ Status server_submit(psfd_server* S, const psfd_problem* prob, const void* d_dep
   *ticket = r->ticket;
   Req* raw = r.get();
   S->reqs.emplace(r->ticket, std::move(r));
-  Status gst;
-  SlotGroup* G = group_for(S, raw->sh, gst);
-  if (!G) {
-    // refused by admission: the ticket completes at once with the status
-    raw->status = gst.code;
-    raw->info.status = gst.code;
+  if (raw->slot_bytes > S->budget) {
+    // cannot fit even an empty budget: the ticket completes at once
+    raw->status = PSFD_ERR_OOM;
+    raw->info.status = PSFD_ERR_OOM;
     raw->t_done = clk::now();
     raw->done = true;
     return Status();
   }
-  G->queue.push_back(raw);
-  G->cv.notify_one();
+  if (SlotGroup* G = S->pending.empty() ? live_group(S, raw->kind) : nullptr) {
+    G->queue.push_back(raw);
+    G->cv.notify_one();
+    return Status();
+  }
+  S->pending.push_back(raw);
+  admit_pending(S);
   return Status();
 }
 
@@ -531,11 +663,18 @@ Status server_destroy(psfd_server* S) {
     S->stop = true;
     for (auto& G : S->groups) G->cv.notify_all();
   }
-  for (auto& G : S->groups)
-    if (G->worker.joinable()) G->worker.join();
-  for (auto& G : S->groups)
-    if (G->s) (void)hipStreamDestroy(G->s);
-  S->groups.clear();
+  // Workers finish every submitted request; a group released at shutdown may
+  // admit pending requests into new groups, so join until no worker is left.
+  for (;;) {
+    std::vector<std::thread*> th;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (auto& G : S->groups)
+        if (G->worker.joinable()) th.push_back(&G->worker);
+    }
+    if (th.empty()) break;
+    for (auto* t : th) t->join();
+  }
   Status st = S->err;
   delete S;
   return st;

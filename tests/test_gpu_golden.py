@@ -1,0 +1,98 @@
+"""Oracle parity of the measured workloads at their full sizes.
+
+The reference solutions in tests/golden/ were written by tests/golden/make_golden.py,
+which calls only the oracle: FP64 GMRES(30) on the monolithic system
+(I - M V) u = e_bg (eqs. (3), (8)-(9), (18)) to a relative residual of 1e-10,
+stored as E_mask on a lattice of 8 planes x 16 x 16 points and the orders with
+|m|, |n| <= 8. Each test runs the exact path the benchmark times (GMRES(8),
+fused Krylov kernels on 64 x 64 and 128 x 128 planes, captured restart cycles)
+and compares element by element:
+
+* mixed precision at rtol 3e-7 (the headline tolerance): field error <= 1e-6
+  relative (the accuracy bar), orders <= 1e-6 of the largest order;
+* mixed precision at rtol 1e-6: field error <= 1e-5;
+* FP64 at rtol 1e-10: field error <= 1e-8.
+
+Field error = ||E_gpu - E_oracle|| / ||E_oracle|| over the stored samples. The
+oracle's own operator also checks the GPU total field: its monolithic relative
+residual is at most twice the tolerance the GPU solve reports.
+"""
+import glob
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_25541_amd import clips
+
+from gpu_util import device, say, torch
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+O.set_workers(os.cpu_count() or 1)
+GOLDEN = sorted(glob.glob(os.path.join(HERE, "golden", "*.npz")))
+
+
+def load(path):
+    z = np.load(path, allow_pickle=False)
+    return {k: z[k] for k in z.files}, json.loads(str(z["meta"]))
+
+
+def inputs(meta):
+    """The case's problem and contrast from the input generators (the recipe in its name)."""
+    name = meta["case"]
+    if name.startswith("contact_holes_128x128x64_"):
+        pol = clips.TE if name.endswith("te") else clips.TM
+        return clips.config_problem("G3", pol=pol), clips.headline_clip()
+    idx = int(name.split("_")[-2])
+    items = clips.serving_pool() if name.startswith("serving_pool") else clips.batched_set()
+    _, p, d = items[idx]
+    return p, d
+
+
+def sample(em, g):
+    return em[:, g["zi"]][:, :, g["yi"]][:, :, :, g["xi"]]
+
+
+def orders_sel(od, p):
+    mi = np.arange(-8, 9)
+    return od[np.ix_(mi % p.ny, mi % p.nx)]
+
+
+@pytest.mark.parametrize("path", GOLDEN, ids=[os.path.basename(p)[:-4] for p in GOLDEN])
+def test_measured_workload_matches_oracle(path):
+    from paper_2606_25541_amd import api
+    dev = device()
+    g, meta = load(path)
+    p, de = inputs(meta)
+    assert [p.nx, p.ny, p.nz] == meta["grid"] and abs(p.theta_deg - meta["theta_deg"]) < 1e-12
+    say("golden", meta["case"], "oracle iters", meta["iters"], "residual", meta["rel_residual"])
+    d = torch.from_numpy(de).to(dev)
+    ref_e, ref_o = g["emask_sample"], g["orders"]
+    nref = np.linalg.norm(ref_e)
+    oscale = np.abs(ref_o).max()
+    results = {}
+    for prec, rtol, fbar, obar in (("mixed", 3e-7, 1e-6, 1e-6), ("mixed", 1e-6, 1e-5, 1e-5),
+                                   ("fp64", 1e-10, 1e-8, 1e-8)):
+        plan = api.Plan(p, rtol=rtol, precision=prec, restart=8, max_iters=20000)
+        u = torch.empty((3, p.nz, p.ny, p.nx), dtype=torch.complex128, device=dev)
+        em, od, info = plan.psfd_solve(d, u=u)
+        torch.cuda.synchronize()
+        ferr = float(np.linalg.norm(sample(em.cpu().numpy(), g) - ref_e) / nref)
+        oerr = float(np.abs(orders_sel(od.cpu().numpy(), p) - ref_o).max() / oscale)
+        say("  %s rtol %g: iters %d residual %.2e field err %.2e order err %.2e" % (
+            prec, rtol, info["iters"], info["rel_residual"], ferr, oerr))
+        assert info["status"] == 0
+        assert ferr <= fbar and oerr <= obar, (prec, rtol, ferr, oerr)
+        results[(prec, rtol)] = (u, info)
+    # the oracle's operator on the GPU's total field (headline tolerance)
+    u, info = results[("mixed", 3e-7)]
+    S = O.Setup(p)
+    ebg = O.background_field(S)
+    r = O.apply_monolithic(S, de, u.cpu().numpy()) - ebg
+    res = float(np.linalg.norm(r) / np.linalg.norm(ebg))
+    say("  oracle residual of the GPU field %.2e (GPU reports %.2e)" % (res, info["rel_residual"]))
+    assert res <= 2 * 3e-7

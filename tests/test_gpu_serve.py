@@ -246,3 +246,104 @@ def test_server_budget_admission():
     assert lats[0] < lats[1] < lats[2]
     for bb in bufs[1:]:
         assert torch.equal(bb[0], bufs[0][0])
+
+
+def _drain(srv, tickets, limit_s=120.0):
+    infos = {}
+    deadline = time.perf_counter() + limit_s
+    while len(infos) < len(tickets) and time.perf_counter() < deadline:
+        for t in tickets:
+            if t not in infos:
+                done, info, lat = srv.poll(t)
+                if done:
+                    infos[t] = (info, lat)
+        time.sleep(0.002)
+    return infos
+
+
+def test_server_binding_budget_queues_mixed_shapes():
+    """A budget that holds one slot of either shape but not one of each: requests
+    of the second shape wait (no OOM) until the first shape's group is drained
+    and released, and every result still equals its lone solve bitwise."""
+    from paper_2606_25541_amd import api
+    dev = device()
+    cs = cases()  # 16x16x8 and 32x32x8 alternating
+    per = {c[0].nx: api.Plan(c[0], **OPTS).footprint() for c in cs[:2]}
+    budget = int(max(per.values()) * 1.2)
+    assert budget < sum(per.values())
+    say("budget", budget, "per slot", per)
+    srv = api.Server(hbm_budget=budget, max_slots=4, **OPTS)
+    outs, tickets = [], []
+    for p, de in cs:
+        d = torch.from_numpy(de).to(dev)
+        e = torch.empty((3, p.nz, p.ny, p.nx), dtype=torch.complex128, device=dev)
+        o = torch.empty((p.ny, p.nx, 3), dtype=torch.complex128, device=dev)
+        torch.cuda.synchronize()
+        tickets.append(srv.submit(p, d, e, o))
+        outs.append((e, o))
+    infos = _drain(srv, tickets)
+    srv.close()
+    assert len(infos) == len(tickets), "served requests not finished"
+    for (p, de), t, (e, o) in zip(cs, tickets, outs):
+        info, lat = infos[t]
+        say("  served", p.nx, info["status"], info["iters"], "latency %.3f" % lat)
+        assert info["status"] == 0
+        e1, o1, i1 = alone(p, de, dev)
+        assert info["iters"] == i1["iters"]
+        assert np.array_equal(e.cpu().numpy(), e1)
+        assert np.array_equal(o.cpu().numpy(), o1)
+
+
+def test_server_per_request_options():
+    """Options per request: a tighter tolerance and an FP64 request (another
+    kind, its own group) next to the server's defaults; each equals the lone
+    solve with the same options."""
+    from paper_2606_25541_amd import api
+    dev = device()
+    cs = [c for c in cases() if c[0].nx == 16]
+    variants = [dict(), dict(rtol=1e-11), dict(precision="fp64", restart=12)]
+    srv = api.Server(hbm_budget=8 << 30, max_slots=2, **OPTS)
+    outs, tickets = [], []
+    for (p, de), v in zip(cs, variants):
+        d = torch.from_numpy(de).to(dev)
+        e = torch.empty((3, p.nz, p.ny, p.nx), dtype=torch.complex128, device=dev)
+        o = torch.empty((p.ny, p.nx, 3), dtype=torch.complex128, device=dev)
+        torch.cuda.synchronize()
+        tickets.append(srv.submit(p, d, e, o, **v))
+        outs.append((d, e, o))
+    infos = _drain(srv, tickets)
+    srv.close()
+    assert len(infos) == len(tickets)
+    for (p, de), v, t, (d, e, o) in zip(cs, variants, tickets, outs):
+        info, _ = infos[t]
+        plan = api.Plan(p, **{**OPTS, **v})
+        e1, o1, i1 = plan.psfd_solve(d)
+        torch.cuda.synchronize()
+        say("  opts", v, "served", info["iters"], info["rel_residual"], "alone", i1["iters"])
+        assert info["status"] == 0 and info["iters"] == i1["iters"]
+        assert info["rel_residual"] <= {**OPTS, **v}["rtol"]
+        assert torch.equal(e, e1) and torch.equal(o, o1)
+
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_graph_replay_equals_eager_launches(n, monkeypatch):
+    """Restart cycles replayed as a captured HIP graph against the same launches
+    issued one by one (PSFD_GRAPH=0): bitwise equal fields, orders and counts,
+    over several solves in a row (each replays the graph many times, with
+    eager launches and host synchronisation between the replays)."""
+    from paper_2606_25541_amd import api
+    dev = device()
+    p = prob(n, 32 if n == 64 else 8, 6.0, 20.0, 1)
+    de = clips.manhattan(n, n, p.nz, p.lx_nm, p.ly_nm, seed=500 + n)
+    d = torch.from_numpy(de).to(dev)
+    opts = dict(rtol=1e-9, precision="mixed", restart=8)
+    plan = api.Plan(p, **opts)
+    runs = [plan.psfd_solve(d) for _ in range(3)]
+    monkeypatch.setenv("PSFD_GRAPH", "0")
+    e0, o0, i0 = plan.psfd_solve(d)
+    torch.cuda.synchronize()
+    say("  graph", runs[0][2], "eager", i0)
+    assert i0["status"] == 0
+    for e, o, i in runs:
+        assert i == i0
+        assert torch.equal(e, e0) and torch.equal(o, o0)
