@@ -105,7 +105,7 @@ typedef struct psfd_server psfd_server;
 
 /* Build the FP64 tables of a problem (orders, reflection matrices T_R from the
  * recursive generalized reflection of the stack, kernel scalars, FFT twiddles)
- * on the current HIP device. opts may be NULL (defaults: rtol 1e-6, restart 30,
+ * on the current HIP device (the plan's device; blocks until they are there). opts may be NULL (defaults: rtol 1e-6, restart 30,
  * max_iters 5000, max_outer 100, PSFD_MIXED). Errors: INVALID_ARG,
  * UNSUPPORTED_SIZE, SINGULAR, OOM, HIP. */
 int psfd_plan_create(const psfd_problem* prob, const psfd_opts* opts, psfd_plan** out);
@@ -121,6 +121,20 @@ int psfd_plan_footprint(const psfd_plan* plan, size_t* device_bytes);
  * Uses a plan-owned scratch field (allocated on first use). */
 int psfd_apply(psfd_plan* plan, const void* d_deps, const void* d_x, void* d_y, int dtype, int flags,
                void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): psfd_apply with the same
+ * arguments, kernels and results, that allocates nothing. Its workspace (3 nx ny nz
+ * values of `dtype`) lives in a static device array of PSFD_NOALLOC_SCRATCH_BYTES
+ * per device, held until the process ends; the plan's device tables come from
+ * psfd_plan_create. The plan's device must be current. A grid whose workspace
+ * exceeds the array (e.g. 256 x 256 x 64 in complex128) is refused with
+ * UNSUPPORTED_SIZE. Every call on a device shares that device's array: calls
+ * that overlap on one device (on different streams or threads) race; calls
+ * ordered on one stream do not. Asynchronous on `stream`. */
+#define PSFD_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int psfd_apply_noalloc(psfd_plan* plan, const void* d_deps, const void* d_x, void* d_y, int dtype, int flags,
+                       void* stream);
 
 /* Full solve (Sec. 2, eqs. (8)-(9); Sec. 3, eq. (18)): the background source,
  * GMRES on eq. (18) with the monolithic or outer coupling of the multilayer

@@ -65,6 +65,8 @@ EXPORTS = {
     "psfd_plan_destroy": (None, [C.c_void_p]),
     "psfd_plan_footprint": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "psfd_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
+    "psfd_apply_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                     C.c_void_p]),
     "psfd_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(psfd_info),
                              C.c_void_p]),
     "psfd_solve_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

@@ -5,6 +5,7 @@
 
 #include "engine.hpp"
 #include "iso.hpp"
+#include "noalloc.hpp"
 #include "serve.hpp"
 
 using namespace psfd;
@@ -35,6 +36,8 @@ struct psfd_plan {
     if (scratch64) (void)hipFree(scratch64);
   }
 };
+
+static Status ensure_lite(psfd_plan* p, hipStream_t s);
 
 extern "C" {
 
@@ -68,6 +71,17 @@ int psfd_plan_create(const psfd_problem* prob, const psfd_opts* opts, psfd_plan*
   st = build_table(plan->pr, plan->tab);
   if (!st.ok()) return fail(st);
   if (hipGetDevice(&plan->device) != hipSuccess) return fail(PSFD_ERR_HIP, "hipGetDevice failed");
+  // device tables now, so that the applies allocate no table memory later; the
+  // device's scratch array of the allocation-free apply is looked up here too
+  st = ensure_lite(plan.get(), nullptr);
+  if (st.ok()) {
+    hipError_t e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) st = hip_status(e, "plan tables");
+  }
+  if (!st.ok()) return fail(st);
+  void* sp = nullptr;
+  st = noalloc_scratch(plan->device, &sp);
+  if (!st.ok()) return fail(st);
   *out = plan.release();
   return PSFD_OK;
 }
@@ -127,6 +141,19 @@ int psfd_apply(psfd_plan* plan, const void* d_deps, const void* d_x, void* d_y, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(hip_status(e, "apply launch"));
   return PSFD_OK;
+}
+
+int psfd_apply_noalloc(psfd_plan* plan, const void* d_deps, const void* d_x, void* d_y, int dtype, int flags,
+                       void* stream) {
+  if (!plan || !d_deps || !d_x || !d_y) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  if (d_x == d_y) return fail(PSFD_ERR_INVALID_ARG, "d_y must not alias d_x");
+  if (dtype != PSFD_C64 && dtype != PSFD_C128) return fail(PSFD_ERR_INVALID_ARG, "dtype must be PSFD_C64 or PSFD_C128");
+  if (!plan->lite) return fail(PSFD_ERR_INVALID_ARG, "the plan has no device tables");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(PSFD_ERR_HIP, "hipGetDevice failed");
+  if (cur != plan->device) return fail(PSFD_ERR_INVALID_ARG, "the plan's device is not the current device");
+  Status st = apply_noalloc(*plan->lite, cur, d_deps, d_x, d_y, dtype, flags, (hipStream_t)stream);
+  return st.ok() ? PSFD_OK : fail(st);
 }
 
 int psfd_bench_stage(psfd_plan* plan, int stage, const void* d_deps, const void* d_x, void* d_y, int dtype,
