@@ -312,6 +312,71 @@ int psfd_iso_table(psfd_iso_plan* plan, void* d_table, int32_t* over, double* ra
 int psfd_iso_bench_stage(psfd_iso_plan* plan, int stage, const void* d_deps, const void* d_x, void* d_y, int dtype,
                          int reps, float* ms, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Differential PSFD operator with a z-PML: the comparison solver of the
+ * preconditioner study (Sec. 3). The curl-curl equation of the mask field on
+ * the homogeneous background (eq. (8)),
+ *     A E = curl curl E - k_bg^2 E - V E = V e_src,   V = k0^2 delta_eps,
+ * discretised pseudo-spectrally (every derivative a Fourier derivative along
+ * its axis, eq. (6)); the clip is periodic in x and y (Floquet envelopes, as on
+ * the main path) and z covers an extended grid of nz_ext planes of spacing
+ * t_nm / nz, with perfectly matched layers at both ends where the z derivative
+ * is stretched by 1 / (1 + i s(z)) (eq. (7)); s(z) = s_max (d / L)^p at the depth
+ * d of the plane centre into a layer of L = pml_cells planes, s_max =
+ * (p + 1) ln(1 / R0) / (2 k_bg L) for a target round-trip reflection R0. The
+ * z derivative zeroes the z-Nyquist wavenumber. Preconditioning on the left:
+ * PSFD_PRECOND_NONE (A x = b) or PSFD_PRECOND_DAMPING (D A x = D b with the
+ * spectral damping D(k) = min(1, k_bg^2 / |k|^2) of the full wavevector).
+ * Forms: PSFD_DIFF_BACKGROUND, the background-field method: the contrast planes
+ * are the absorber, e_src = E_inc + E_layer with E_layer from the multilayer
+ * reflection T_R of the downgoing field at z = 0, read on the plane below the
+ * absorber, in an outer fixed point (eqs. (8)-(9)); PSFD_DIFF_FULL_DOMAIN, the
+ * full-domain method: the multilayer is on the grid as contrast (the caller
+ * builds it into the contrast planes below the absorber), e_src = E_inc, and
+ * the background medium continues below the stack (no reflection operator).
+ * Planes z_k = (k - z0 + 1/2) dz with z0 the absorber's first plane; the
+ * absorber is the top nz of the ncz contrast planes starting at zc0. Fields
+ * [3][nz_ext][ny][nx], contrast [ncz][ny][nx]. */
+typedef struct psfd_diff_plan psfd_diff_plan;
+enum { PSFD_DIFF_BACKGROUND = 0, PSFD_DIFF_FULL_DOMAIN = 1 };
+enum { PSFD_PRECOND_NONE = 0, PSFD_PRECOND_DAMPING = 1 };
+
+typedef struct {
+  psfd_problem base;       /* clip, incidence, multilayer, absorber grid (nz planes over t_nm) */
+  int32_t nz_ext;          /* planes of the extended z grid: a power of two in [16, 1024] */
+  int32_t zc0, ncz;        /* contrast planes [zc0, zc0 + ncz); background form: ncz = base.nz */
+  int32_t pml_cells;       /* PML planes at each end (0: none, the z axis stays periodic) */
+  int32_t pml_order;       /* grading p (<= 0: 3) */
+  double pml_reflection;   /* R0 (outside (0, 1): 1e-8) */
+  int32_t form;            /* PSFD_DIFF_BACKGROUND or PSFD_DIFF_FULL_DOMAIN */
+} psfd_diff_problem;
+
+/* Validates (pml_cells + 1 <= zc0, zc0 + ncz + 1 <= nz_ext - pml_cells: a readout
+ * plane on each side of the contrast planes outside the PML) and builds the
+ * tables on the current device (blocks). Errors: INVALID_ARG, UNSUPPORTED_SIZE,
+ * SINGULAR, OOM, HIP. */
+int psfd_diff_plan_create(const psfd_diff_problem* prob, psfd_diff_plan** out);
+void psfd_diff_plan_destroy(psfd_diff_plan* plan);
+/* y = A x or D A x (precond); d_deps [ncz][ny][nx], d_x, d_y [3][nz_ext][ny][nx],
+ * all of dtype (PSFD_C64: FP32 arithmetic, PSFD_C128: FP64), device; d_y must not
+ * alias d_x. A workspace of one field of dtype is allocated at the first call of
+ * each dtype and kept with the plan. Asynchronous on stream. */
+int psfd_diff_apply(psfd_diff_plan* plan, const void* d_deps, const void* d_x, void* d_y, int dtype, int precond,
+                    void* stream);
+/* Solve of the form: GMRES(restart) (host-driven, restarts from the FP64
+ * residual; opts->precision PSFD_MIXED: FP32 basis and applies) on the
+ * (preconditioned) system to opts->rtol, inside the outer fixed point of the
+ * background form until the reflected spectrum changes by at most outer_rtol
+ * (<= 0: rtol) or max_outer steps. d_deps complex128 [ncz][ny][nx]; d_e
+ * (complex128 [3][nz_ext][ny][nx]) receives the mask field (background form) or
+ * the scattered field (full domain) on the extended grid; d_orders (may be
+ * NULL; complex128 [ny][nx][3]) the reflected order amplitudes at z = t (the
+ * top of the absorber), the same quantity psfd_solve returns. opts may be NULL
+ * (defaults of psfd_plan_create; restart <= 64). Blocks; NOT_CONVERGED when a
+ * limit stops it. */
+int psfd_diff_solve(psfd_diff_plan* plan, const void* d_deps, void* d_e, void* d_orders, const psfd_opts* opts,
+                    int precond, psfd_info* info, void* stream);
+
 const char* psfd_status_string(int status);
 const char* psfd_last_error(void);
 const char* psfd_version(void);

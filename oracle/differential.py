@@ -130,10 +130,22 @@ def rhs(D: DiffSetup, deps_c: np.ndarray, e_src_c: np.ndarray) -> np.ndarray:
     return b
 
 
-def solve_linear(D: DiffSetup, deps_c, b, precond="none", x0=None, rtol=1e-10, restart=30, max_iters=20000):
-    """GMRES(m) on A x = b ("none") or D A x = D b ("damping")."""
+def solve_linear(D: DiffSetup, deps_c, b, precond="none", x0=None, rtol=1e-10, restart=30, max_iters=20000,
+                 dense=None):
+    """GMRES(m) on A x = b ("none") or D A x = D b ("damping"); with `dense` (the
+    assembled matrix of A, tiny grids) a direct solve of A x = b instead."""
+    if dense is not None:
+        x = np.linalg.solve(dense, np.asarray(b).ravel()).reshape(b.shape)
+        return x, {"iters": 0, "rel_residual": float(np.linalg.norm(dense @ x.ravel() - b.ravel())
+                                                     / max(np.linalg.norm(b), 1e-300))}
     bb = damping(D, b) if precond == "damping" else b
     return P.gmres(lambda v: apply_diff(D, deps_c, v, precond), bb, x0, rtol, restart, max_iters)
+
+
+def dense_operator(D: DiffSetup, deps_c) -> np.ndarray:
+    """A assembled column by column (3 nz_ext ny nx unknowns: tiny grids only)."""
+    shape = (3, D.pe, D.ny, D.nx)
+    return P.dense_matrix(lambda v: apply_diff(D, deps_c, v), int(np.prod(shape)), shape)
 
 
 def read_plane(D: DiffSetup, E: np.ndarray, k: int, dist: float) -> np.ndarray:
@@ -147,7 +159,7 @@ def read_plane(D: DiffSetup, E: np.ndarray, k: int, dist: float) -> np.ndarray:
 
 def solve_background(D: DiffSetup, deps: np.ndarray, precond: str = "none", rtol: float = 1e-10,
                      outer_rtol: Optional[float] = None, restart: int = 30, max_iters: int = 20000,
-                     max_outer: int = 200) -> Dict:
+                     max_outer: int = 200, dense: bool = False) -> Dict:
     """The background-field method with the differential operator (eqs. (8)-(9)):
     outer fixed point over the multilayer reflection around GMRES on the
     curl-curl equation of the mask field; returns E_mask on the extended grid,
@@ -159,10 +171,11 @@ def solve_background(D: DiffSetup, deps: np.ndarray, precond: str = "none", rtol
     a_up = P.reflect(S, a_inc)
     e_inc = P.incident_field(S)
     E = np.zeros((3, D.pe, D.ny, D.nx), dtype=complex)
+    Ad = dense_operator(D, deps) if dense else None
     its, change = 0, float("inf")
     for outer in range(1, max_outer + 1):
         e = e_inc + P.inject_up(S, a_up)
-        E, info = solve_linear(D, deps, rhs(D, deps, e), precond, E, rtol, restart, max_iters)
+        E, info = solve_linear(D, deps, rhs(D, deps, e), precond, E, rtol, restart, max_iters, Ad)
         its += info["iters"]
         a_dn = read_plane(D, E, D.z0 - 1, 0.5 * D.dz)
         a_new = P.reflect(S, a_inc + a_dn)
@@ -178,7 +191,7 @@ def solve_background(D: DiffSetup, deps: np.ndarray, precond: str = "none", rtol
 
 
 def solve_full_domain(D: DiffSetup, deps_c: np.ndarray, precond: str = "none", rtol: float = 1e-10,
-                      restart: int = 30, max_iters: int = 20000) -> Dict:
+                      restart: int = 30, max_iters: int = 20000, dense: bool = False) -> Dict:
     """Full-domain PSFD: the multilayer is part of the contrast (planes [zc0, zc0 + ncz)),
     the source is V E_inc, and the reflected orders at z = T are read above the absorber."""
     S = D.S
@@ -190,7 +203,8 @@ def solve_full_domain(D: DiffSetup, deps_c: np.ndarray, precond: str = "none", r
     for c in range(3):
         spec[c, :, jj, ii] = S.e_inc[c] * np.exp(-1j * b0 * zc)
     e_inc = P.field_from_spectrum(S, spec)
-    E, info = solve_linear(D, deps_c, rhs(D, deps_c, e_inc), precond, None, rtol, restart, max_iters)
+    E, info = solve_linear(D, deps_c, rhs(D, deps_c, e_inc), precond, None, rtol, restart, max_iters,
+                           dense_operator(D, deps_c) if dense else None)
     orders = read_plane(D, E, D.z0 + D.nz, 0.5 * D.dz)
     return {"E": E, "orders": orders, "iters": info["iters"], "rel_residual": info["rel_residual"]}
 

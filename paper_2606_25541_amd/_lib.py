@@ -60,6 +60,15 @@ class psfd_iso_problem(C.Structure):
                 ("radius_nm", C.c_double)]
 
 
+class psfd_diff_problem(C.Structure):
+    _fields_ = [("base", psfd_problem), ("nz_ext", C.c_int32), ("zc0", C.c_int32), ("ncz", C.c_int32),
+                ("pml_cells", C.c_int32), ("pml_order", C.c_int32), ("pml_reflection", C.c_double),
+                ("form", C.c_int32)]
+
+
+PSFD_DIFF_BACKGROUND, PSFD_DIFF_FULL_DOMAIN = 0, 1
+PSFD_PRECOND_NONE, PSFD_PRECOND_DAMPING = 0, 1
+
 EXPORTS = {
     "psfd_plan_create": (C.c_int, [C.POINTER(psfd_problem), C.POINTER(psfd_opts), C.POINTER(C.c_void_p)]),
     "psfd_plan_destroy": (None, [C.c_void_p]),
@@ -94,6 +103,11 @@ EXPORTS = {
                                  C.c_void_p]),
     "psfd_iso_bench_stage": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                                        C.c_int, C.POINTER(C.c_float), C.c_void_p]),
+    "psfd_diff_plan_create": (C.c_int, [C.POINTER(psfd_diff_problem), C.POINTER(C.c_void_p)]),
+    "psfd_diff_plan_destroy": (None, [C.c_void_p]),
+    "psfd_diff_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
+    "psfd_diff_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(psfd_opts), C.c_int,
+                                  C.POINTER(psfd_info), C.c_void_p]),
     "psfd_status_string": (C.c_char_p, [C.c_int]),
     "psfd_last_error": (C.c_char_p, []),
     "psfd_version": (C.c_char_p, []),

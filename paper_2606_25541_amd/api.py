@@ -349,3 +349,78 @@ class IsoPlan:
                                              C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), code, int(reps),
                                              C.byref(ms), _stream()), "psfd_iso_bench_stage")
         return float(ms.value)
+
+
+class DiffPlan:
+    """Differential PSFD operator with a z-PML on an extended z grid (psfd_diff_* entry
+    points): the comparison solver of the preconditioner study, in the background-field
+    form (outer reflection loop) or the full-domain form (multilayer on the grid)."""
+
+    def __init__(self, prob, nz_ext: int, zc0: int, ncz: int, pml_cells: int, pml_order: int = 3,
+                 pml_reflection: float = 1e-8, form: str = "background"):
+        self.prob = prob
+        self.nx, self.ny, self.nz = int(prob.nx), int(prob.ny), int(prob.nz)
+        self.nz_ext, self.zc0, self.ncz = int(nz_ext), int(zc0), int(ncz)
+        cp, self._keep = _c_problem(prob)
+        self._cp = L.psfd_diff_problem(cp, self.nz_ext, self.zc0, self.ncz, int(pml_cells), int(pml_order),
+                                       float(pml_reflection),
+                                       {"background": L.PSFD_DIFF_BACKGROUND, "full": L.PSFD_DIFF_FULL_DOMAIN}[form])
+        h = C.c_void_p()
+        L.check(L.lib().psfd_diff_plan_create(C.byref(self._cp), C.byref(h)), "psfd_diff_plan_create")
+        self._h = h
+        self._destroy = L.lib().psfd_diff_plan_destroy
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    @property
+    def field_shape(self):
+        return (3, self.nz_ext, self.ny, self.nx)
+
+    @staticmethod
+    def _pc(precond):
+        return {"none": L.PSFD_PRECOND_NONE, "damping": L.PSFD_PRECOND_DAMPING}[precond]
+
+    def psfd_diff_apply(self, deps: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None,
+                        precond: str = "none") -> torch.Tensor:
+        """y = A x (or D A x): curl curl x - k_bg^2 x - V x on the extended grid."""
+        dt = x.dtype
+        code = {torch.complex64: L.PSFD_C64, torch.complex128: L.PSFD_C128}[dt]
+        _dev(deps, dt, "deps")
+        _dev(x, dt, "x")
+        if tuple(x.shape) != self.field_shape or tuple(deps.shape) != (self.ncz, self.ny, self.nx):
+            raise ValueError("shape mismatch")
+        if out is None:
+            out = torch.empty_like(x)
+        _dev(out, dt, "out")
+        L.check(L.lib().psfd_diff_apply(self._h, C.c_void_p(deps.data_ptr()), C.c_void_p(x.data_ptr()),
+                                        C.c_void_p(out.data_ptr()), code, self._pc(precond), _stream()),
+                "psfd_diff_apply")
+        return out
+
+    apply = psfd_diff_apply
+
+    def psfd_diff_solve(self, deps: torch.Tensor, precond: str = "none", e: Optional[torch.Tensor] = None,
+                        orders: Optional[torch.Tensor] = None, **opts):
+        """(field on the extended grid, orders, info) of the background-field or full-domain solve."""
+        _dev(deps, torch.complex128, "deps")
+        if tuple(deps.shape) != (self.ncz, self.ny, self.nx):
+            raise ValueError("deps shape mismatch")
+        if e is None:
+            e = torch.empty(self.field_shape, dtype=torch.complex128, device=deps.device)
+        if orders is None:
+            orders = torch.empty((self.ny, self.nx, 3), dtype=torch.complex128, device=deps.device)
+        _dev(e, torch.complex128, "e")
+        _dev(orders, torch.complex128, "orders")
+        o = _c_opts(**opts)
+        info = L.psfd_info()
+        L.check(L.lib().psfd_diff_solve(self._h, C.c_void_p(deps.data_ptr()), C.c_void_p(e.data_ptr()),
+                                        C.c_void_p(orders.data_ptr()), C.byref(o), self._pc(precond),
+                                        C.byref(info), _stream()), "psfd_diff_solve")
+        return e, orders, info.as_dict()
+
+    solve = psfd_diff_solve

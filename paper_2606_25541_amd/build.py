@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpsfd.so")
-SOURCES = ["k_apply.hip", "k_krylov.hip", "k_table.hip", "k_iso.hip", "noalloc.hip", "engine.cpp", "serve.cpp",
+SOURCES = ["k_apply.hip", "k_krylov.hip", "k_table.hip", "k_iso.hip", "noalloc.hip", "gmres_host.hip", "k_diff.hip", "engine.cpp", "serve.cpp",
            "abi.cpp"]
 ARCH = os.environ.get("PSFD_OFFLOAD_ARCH", "gfx950")
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -4,6 +4,7 @@
 #include <string>
 
 #include "engine.hpp"
+#include "diff.hpp"
 #include "iso.hpp"
 #include "noalloc.hpp"
 #include "serve.hpp"
@@ -329,6 +330,38 @@ int psfd_server_destroy(psfd_server* srv) {
   if (!srv) return fail(PSFD_ERR_INVALID_ARG, "NULL server");
   Status st = server_destroy(srv);
   return st.ok() ? PSFD_OK : fail(st);
+}
+
+int psfd_diff_plan_create(const psfd_diff_problem* prob, psfd_diff_plan** out) {
+  if (!prob || !out) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  Status st = diff_create(*prob, *out);
+  return st.ok() ? PSFD_OK : fail(st);
+}
+
+void psfd_diff_plan_destroy(psfd_diff_plan* plan) { diff_destroy(plan); }
+
+int psfd_diff_apply(psfd_diff_plan* plan, const void* d_deps, const void* d_x, void* d_y, int dtype, int precond,
+                    void* stream) {
+  if (!plan || !d_deps || !d_x || !d_y) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  if (d_x == d_y) return fail(PSFD_ERR_INVALID_ARG, "d_y must not alias d_x");
+  if (dtype != PSFD_C64 && dtype != PSFD_C128) return fail(PSFD_ERR_INVALID_ARG, "dtype must be PSFD_C64 or PSFD_C128");
+  Status st = diff_apply(plan, d_deps, d_x, d_y, dtype, precond, (hipStream_t)stream);
+  return st.ok() ? PSFD_OK : fail(st);
+}
+
+int psfd_diff_solve(psfd_diff_plan* plan, const void* d_deps, void* d_e, void* d_orders, const psfd_opts* opts,
+                    int precond, psfd_info* info, void* stream) {
+  if (!plan || !d_deps || !d_e) return fail(PSFD_ERR_INVALID_ARG, "NULL argument");
+  psfd_info inf{};
+  Status st = diff_solve(plan, d_deps, d_e, d_orders, opts, precond, &inf, (hipStream_t)stream);
+  if (info) *info = inf;
+  if (!st.ok()) return fail(st);
+  if (inf.status == PSFD_NOT_CONVERGED) {
+    g_last_error = "iteration limit reached";
+    return PSFD_NOT_CONVERGED;
+  }
+  return PSFD_OK;
 }
 
 int psfd_iso_plan_create(const psfd_iso_problem* prob, psfd_iso_plan** out) {

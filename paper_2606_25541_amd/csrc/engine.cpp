@@ -187,8 +187,8 @@ Status upload_table(double* d_tab, double4* d_lay, const Problem& pr, const std:
 }
 
 void build_twiddles(std::vector<double>& tw) {
-  tw.assign(2 * 512, 0.0);
-  for (int n = 2; n <= 256; n <<= 1)
+  tw.assign(2 * 2 * TW_MAX_N, 0.0);
+  for (int n = 2; n <= TW_MAX_N; n <<= 1)
     for (int i = 0; i < n; ++i) {
       // exp(-2 pi i i / n); the angle is reduced to the first octant by symmetry
       const double a = 2.0 * PI * i / n;

@@ -47,7 +47,8 @@ Status upload_table(double* d_tab, double4* d_lay, const Problem& pr, const std:
                     hipStream_t s);
 // largest layer count of a stack
 const int LAYER_CAP = 2048;
-// twiddle tables of all power-of-two lengths up to 256 (tw[n + i] = exp(-2 pi i i / n))
+// twiddle tables of all power-of-two lengths up to TW_MAX_N (tw[n + i] = exp(-2 pi i i / n))
+constexpr int TW_MAX_N = 1024;
 void build_twiddles(std::vector<double>& tw64);
 
 // Launch configurations of the transverse FFT and z-pencil kernels.

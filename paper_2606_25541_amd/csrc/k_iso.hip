@@ -31,6 +31,7 @@
 
 #include "engine.hpp"
 #include "fft_lds.hpp"
+#include "gmres_host.hpp"
 #include "iso.hpp"
 
 using namespace psfd;
@@ -320,73 +321,7 @@ __global__ void k_iso_zero_zplane(double2* __restrict__ k, int lz, int ly, int l
   k[c * (8LL << (lz + ly + lx)) + ((long long)1 << lz) * pl + e] = make_double2(0.0, 0.0);
 }
 
-// ---------------------------------------------------------------------------
-// Krylov kernels of the isolated-domain GMRES (FP64). Reductions run in a
-// fixed order (block partials, then one block per sum), so a solve is
-// deterministic.
-
-constexpr int KB = 256;      // threads per block
-constexpr int KNB = 1024;    // blocks of a reduction pass
-
-// part[i * KNB + blk] = sum over the block's chunk of conj(V_i) w, i < nv
-// (accumulated in FP64 whatever the storage type)
-template <class TV, class TW>
-__global__ void k_iso_dots(const TV* __restrict__ V, long long stride, const TW* __restrict__ w, long long n,
-                           double2* __restrict__ part) {
-  __shared__ double2 red[KB];
-  const int i = blockIdx.y;
-  const TV* v = V + i * stride;
-  double2 acc = make_double2(0.0, 0.0);
-  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)KNB * KB) {
-    const double2 a = to_d(v[e]), b = to_d(w[e]);
-    acc.x += a.x * b.x + a.y * b.y;
-    acc.y += a.x * b.y - a.y * b.x;
-  }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int h = KB / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + h]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[(long long)i * KNB + blockIdx.x] = red[0];
-}
-
-// out[i] = sum of the KNB partials of i (one block per i, fixed order)
-__global__ void k_iso_sum(const double2* __restrict__ part, double2* __restrict__ out) {
-  __shared__ double2 red[KB];
-  const int i = blockIdx.x;
-  double2 acc = make_double2(0.0, 0.0);
-  for (int b = threadIdx.x; b < KNB; b += KB) acc = cadd(acc, part[(long long)i * KNB + b]);
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int h = KB / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + h]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[i] = red[0];
-}
-
-// w += sgn sum_{i < nv} coef[i] V_i (in FP64, stored in w's type)
-template <class TW, class TV>
-__global__ void k_iso_axpys(TW* __restrict__ w, const TV* __restrict__ V, long long stride,
-                            const double2* __restrict__ coef, int nv, long long n, double sgn) {
-  const long long e = (long long)blockIdx.x * KB + threadIdx.x;
-  if (e >= n) return;
-  double2 acc = to_d(w[e]);
-  for (int i = 0; i < nv; ++i) {
-    const double2 c = coef[i], v = to_d(V[i * stride + e]);
-    acc.x += sgn * (c.x * v.x - c.y * v.y);
-    acc.y += sgn * (c.x * v.y + c.y * v.x);
-  }
-  w[e] = from_d<TW>(acc);
-}
-
-// out = a + s b (s real)
-__global__ void k_iso_comb(const double2* __restrict__ a, const double2* __restrict__ b, double s,
-                           double2* __restrict__ out, long long n) {
-  const long long e = (long long)blockIdx.x * KB + threadIdx.x;
-  if (e < n) out[e] = make_double2(a[e].x + s * b[e].x, a[e].y + s * b[e].y);
-}
+constexpr int KB = 256;      // threads per block of the elementwise kernels
 
 // out = s a, converted to out's type (a may equal out)
 template <class TA, class TO>
@@ -713,171 +648,11 @@ Status iso_table(psfd_iso_plan* p, void* d_table, int32_t* over, double* radius,
 }
 
 
-// GMRES(m) on y = x - K(V x) (Saad & Schultz) from x0 = 0, the basis and the
-// operator applies in T: classical Gram-Schmidt (a second pass where it
-// cancels severely), Givens
-// rotations and the small Hessenberg system on the host (one apply per step
-// costs far more than the few host round trips). Every restart starts from the
-// FP64 residual b - A x, and x accumulates in FP64. With an FP32 basis (mixed
-// precision) a cycle also ends once it has reduced the residual estimate by
-// ETA_MIXED, since FP32 Arnoldi cannot go much further.
-namespace {
-
-constexpr double ETA_MIXED = 1e-4;
-// Second Gram-Schmidt pass when ||w - V h|| < cancel ||w||: 1/sqrt(2), the
-// classical criterion after which one more pass restores orthogonality to
-// working accuracy ("twice is enough"). PSFD_ISO_CANCEL overrides it (read per
-// solve), so that a test can force the second pass on every step.
-static double iso_cancel() {
-  const char* e = std::getenv("PSFD_ISO_CANCEL");
-  return e ? std::atof(e) : 0.70710678118654752;
-}
-
-template <class T>
-Status iso_solve_t(psfd_iso_plan* p, const double2* deps, const double2* B, double2* X, double rtol, int m,
-                   int max_iters, psfd_info& inf, hipStream_t s) {
-  typedef std::complex<double> cd;
-  const bool f32 = sizeof(T) == 8;
-  const long long N = (long long)p->n[0] * p->n[1] * p->n[2], n = 3 * N;
-  T *V = nullptr, *depsT = nullptr;
-  double2 *w64 = nullptr, *r64 = nullptr, *part = nullptr, *hd = nullptr;
-  struct Free {
-    void* q[7];
-    ~Free() { for (void* a : q) if (a) (void)hipFree(a); }
-  };
-  ISOCHK(hipMalloc((void**)&V, (size_t)(m + 1) * n * sizeof(T)));
-  Free fr{{V}};
-  ISOCHK(hipMalloc((void**)&w64, (size_t)n * sizeof(double2)));
-  fr.q[2] = w64;
-  ISOCHK(hipMalloc((void**)&r64, (size_t)n * sizeof(double2)));
-  fr.q[3] = r64;
-  ISOCHK(hipMalloc((void**)&part, (size_t)KNB * (m + 1) * sizeof(double2)));
-  fr.q[4] = part;
-  ISOCHK(hipMalloc((void**)&hd, (size_t)(m + 1) * sizeof(double2)));
-  fr.q[5] = hd;
-  const unsigned g1 = (unsigned)((n + KB - 1) / KB);
-  const int dt = f32 ? PSFD_C64 : PSFD_C128;
-  if (f32) {
-    ISOCHK(hipMalloc((void**)&depsT, (size_t)N * sizeof(T)));
-    fr.q[6] = depsT;
-    hipLaunchKernelGGL((k_iso_scale<double2, T>), dim3((unsigned)((N + KB - 1) / KB)), dim3(KB), 0, s, deps, 1.0,
-                       depsT, N);
-  }
-  const void* dA = f32 ? (const void*)depsT : (const void*)deps;
-  const double CANCEL = iso_cancel();
-  std::vector<cd> hv(m + 1);
-  // hv[0..nv) = V_i^H x
-  auto dots = [&](auto Vb, int nv, auto x) -> Status {
-    typedef std::remove_cv_t<std::remove_pointer_t<decltype(Vb)>> TV;
-    typedef std::remove_cv_t<std::remove_pointer_t<decltype(x)>> TX;
-    hipLaunchKernelGGL((k_iso_dots<TV, TX>), dim3(KNB, nv), dim3(KB), 0, s, Vb, n, x, n, part);
-    hipLaunchKernelGGL(k_iso_sum, dim3(nv), dim3(KB), 0, s, part, hd);
-    ISOCHK(hipGetLastError());
-    ISOCHK(hipMemcpyAsync(hv.data(), hd, nv * sizeof(double2), hipMemcpyDeviceToHost, s));
-    ISOCHK(hipStreamSynchronize(s));
-    return Status();
-  };
-  // x += sgn sum_i c[i] V_i
-  auto axpys = [&](auto x, const T* Vb, const std::vector<cd>& c, int nv, double sgn) -> Status {
-    typedef std::remove_pointer_t<decltype(x)> TX;
-    ISOCHK(hipMemcpyAsync(hd, c.data(), nv * sizeof(double2), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL((k_iso_axpys<TX, T>), dim3(g1), dim3(KB), 0, s, x, Vb, n, (const double2*)hd, nv, n, sgn);
-    ISOCHK(hipGetLastError());
-    ISOCHK(hipStreamSynchronize(s));  // c may change before the next call
-    return Status();
-  };
-  auto norm = [&](auto x, double& out) -> Status {
-    Status st = dots(x, 1, x);
-    out = std::sqrt(std::max(hv[0].real(), 0.0));
-    return st;
-  };
-  Status st;
-  ISOCHK(hipMemsetAsync(X, 0, n * sizeof(double2), s));
-  double bnorm = 0.0;
-  if (!(st = norm(B, bnorm)).ok()) return st;
-  if (!std::isfinite(bnorm)) return bad(PSFD_ERR_NONFINITE, "right-hand side is not finite");
-  if (bnorm == 0.0) {
-    inf.status = PSFD_OK;
-    ISOCHK(hipStreamSynchronize(s));
-    return Status();
-  }
-  double beta = bnorm, rel = 1.0;
-  hipLaunchKernelGGL((k_iso_scale<double2, T>), dim3(g1), dim3(KB), 0, s, B, 1.0 / beta, V, n);
-  std::vector<cd> H((size_t)(m + 1) * m), g(m + 1), sn(m), h1(m + 1), y(m);
-  std::vector<double> cs(m);
-  auto Hij = [&](int i, int j) -> cd& { return H[(size_t)i * m + j]; };
-  while (inf.iters < max_iters) {
-    ++inf.cycles;
-    std::fill(H.begin(), H.end(), cd(0.0));
-    std::fill(g.begin(), g.end(), cd(0.0));
-    g[0] = beta;
-    const double stop = std::max(rtol * bnorm, f32 ? ETA_MIXED * beta : 0.0);
-    int k = 0;
-    for (int j = 0; j < m && inf.iters < max_iters; ++j) {
-      // w = A v_j straight into slot j + 1; one launch gives V_{0..j}^H w and
-      // ||w||^2; the norm after the update follows from Pythagoras, and only a
-      // cancellation (norm ratio below CANCEL) takes a second pass with
-      // a computed norm
-      T* wj = V + (j + 1) * n;
-      if (!(st = iso_apply(p, dA, V + j * n, wj, dt, -1, s)).ok()) return st;
-      if (!(st = dots((const T*)V, j + 2, (const T*)wj)).ok()) return st;
-      const double w2 = hv[j + 1].real();
-      double p2 = 0.0;
-      for (int i = 0; i <= j; ++i) { h1[i] = hv[i]; Hij(i, j) = hv[i]; p2 += std::norm(hv[i]); }
-      if (!(st = axpys(wj, V, h1, j + 1, -1.0)).ok()) return st;
-      double hn = std::sqrt(std::max(w2 - p2, 0.0));
-      if (!(hn >= CANCEL * std::sqrt(std::max(w2, 0.0)))) {
-        if (!(st = dots((const T*)V, j + 1, (const T*)wj)).ok()) return st;
-        for (int i = 0; i <= j; ++i) { h1[i] = hv[i]; Hij(i, j) += hv[i]; }
-        if (!(st = axpys(wj, V, h1, j + 1, -1.0)).ok()) return st;
-        if (!(st = norm((const T*)wj, hn)).ok()) return st;
-      }
-      if (!std::isfinite(hn) || !std::isfinite(w2)) return bad(PSFD_ERR_NONFINITE, "non-finite Krylov vector");
-      Hij(j + 1, j) = hn;
-      ++inf.iters;
-      k = j + 1;
-      for (int i = 0; i < j; ++i) {  // previous rotations
-        const cd a = Hij(i, j), c2 = Hij(i + 1, j);
-        Hij(i, j) = cs[i] * a + sn[i] * c2;
-        Hij(i + 1, j) = -std::conj(sn[i]) * a + cs[i] * c2;
-      }
-      const cd a = Hij(j, j);
-      const double bb = hn, r = std::sqrt(std::norm(a) + bb * bb);
-      if (r == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
-      else if (std::abs(a) == 0.0) { cs[j] = 0.0; sn[j] = 1.0; }
-      else { cs[j] = std::abs(a) / r; sn[j] = (a / std::abs(a)) * bb / r; }
-      Hij(j, j) = cs[j] * a + sn[j] * bb;
-      Hij(j + 1, j) = 0.0;
-      g[j + 1] = -std::conj(sn[j]) * g[j];
-      g[j] = cs[j] * g[j];
-      if (hn > 0.0) hipLaunchKernelGGL((k_iso_scale<T, T>), dim3(g1), dim3(KB), 0, s, wj, 1.0 / hn, wj, n);
-      if (std::abs(g[j + 1]) <= stop || hn == 0.0) break;
-    }
-    for (int i = k - 1; i >= 0; --i) {  // back substitution
-      cd acc = g[i];
-      for (int l = i + 1; l < k; ++l) acc -= Hij(i, l) * y[l];
-      y[i] = acc / Hij(i, i);
-    }
-    std::vector<cd> yk(y.begin(), y.begin() + k);
-    if (!(st = axpys(X, V, yk, k, 1.0)).ok()) return st;
-    // FP64 residual r = b - A x
-    if (!(st = iso_apply(p, deps, X, w64, PSFD_C128, -1, s)).ok()) return st;
-    hipLaunchKernelGGL(k_iso_comb, dim3(g1), dim3(KB), 0, s, B, w64, -1.0, r64, n);
-    if (!(st = norm((const double2*)r64, beta)).ok()) return st;
-    rel = beta / bnorm;
-    if (!std::isfinite(rel)) return bad(PSFD_ERR_NONFINITE, "non-finite residual");
-    if (rel <= rtol) { inf.status = PSFD_OK; break; }
-    hipLaunchKernelGGL((k_iso_scale<double2, T>), dim3(g1), dim3(KB), 0, s, r64, 1.0 / beta, V, n);
-  }
-  inf.rel_residual = rel;
-  inf.mono_residual = rel;
-  ISOCHK(hipGetLastError());
-  ISOCHK(hipStreamSynchronize(s));
-  return Status();
-}
-
-}  // namespace
-
+// GMRES(m) on y = x - K(V x) from x0 = 0 (the host-driven solver of
+// gmres_host.hip): in mixed precision the basis and the applies are FP32 (an
+// FP32 copy of the contrast is made for the call) and every restart starts
+// from the FP64 residual. PSFD_ISO_CANCEL overrides the norm ratio below which
+// Gram-Schmidt takes a second pass (1/sqrt(2)), so that a test can force it.
 Status iso_solve(psfd_iso_plan* p, const void* deps, const void* b, void* u, double rtol, int m, int max_iters,
                  int precision, psfd_info* info, hipStream_t s) {
   if (!(rtol > 0.0) || m < 1 || m > 64 || max_iters < 1)
@@ -887,14 +662,31 @@ Status iso_solve(psfd_iso_plan* p, const void* deps, const void* b, void* u, dou
   int dev = 0;
   ISOCHK(hipGetDevice(&dev));
   if (dev != p->device) return bad(PSFD_ERR_INVALID_ARG, "plan belongs to another device");
+  const long long N = (long long)p->n[0] * p->n[1] * p->n[2];
+  float2* depsT = nullptr;
+  struct Free {
+    void* q;
+    ~Free() { if (q) (void)hipFree(q); }
+  } fr{nullptr};
+  if (precision == PSFD_MIXED) {
+    ISOCHK(hipMalloc((void**)&depsT, (size_t)N * sizeof(float2)));
+    fr.q = depsT;
+    hipLaunchKernelGGL((k_iso_scale<double2, float2>), dim3((unsigned)((N + KB - 1) / KB)), dim3(KB), 0, s,
+                       (const double2*)deps, 1.0, depsT, N);
+    ISOCHK(hipGetLastError());
+  }
+  ApplyFn A = [&](const void* x, void* y, int dt, hipStream_t q) {
+    return iso_apply(p, dt == PSFD_C64 ? (const void*)depsT : deps, x, y, dt, -1, q);
+  };
+  HostGmres o;
+  o.rtol = rtol;
+  o.m = m;
+  o.max_iters = max_iters;
+  o.precision = precision;
+  if (const char* e = std::getenv("PSFD_ISO_CANCEL")) o.cancel = std::atof(e);
   psfd_info inf{};
   inf.outer_iters = 1;
-  inf.status = PSFD_NOT_CONVERGED;
-  Status st = precision == PSFD_MIXED
-                  ? iso_solve_t<float2>(p, (const double2*)deps, (const double2*)b, (double2*)u, rtol, m, max_iters,
-                                        inf, s)
-                  : iso_solve_t<double2>(p, (const double2*)deps, (const double2*)b, (double2*)u, rtol, m,
-                                         max_iters, inf, s);
+  Status st = gmres_host(3 * N, A, (const double2*)b, (double2*)u, o, inf, s);
   if (info) *info = inf;
   return st;
 }
