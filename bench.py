@@ -48,7 +48,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SECTIONS = ("solve", "fp64", "apply", "isolated", "batched", "serving", "adjoint", "cpu")
+SECTIONS = ("solve", "fp64", "apply", "isolated", "batched", "serving", "adjoint", "precond", "layers", "cpu")
 # sources that decide the code of the measured kernels (hashed into the counter summary)
 KERNEL_SOURCES = ("common.hpp", "layout.hpp", "kernels.hpp", "fft_lds.hpp", "k_apply.hip", "krylov.hpp",
                   "givens.hpp", "k_krylov.hip")
@@ -639,6 +639,125 @@ def sec_adjoint(ctx, args, out):
     log("bench: adjoint", out["adjoint"])
 
 
+def _diff_layout(nz, pe, npml):
+    """zc0 of an absorber of nz planes centred in an extended grid of pe planes."""
+    return (pe - nz) // 2
+
+
+def sec_precond(ctx, args, out):
+    """The preconditioner study (the Table of Sec. 3) on synthetic clips: GMRES steps and
+    wall time of the differential PSFD solve with no preconditioner and with spectral
+    damping D(k) = min(1, k_bg^2 / |k|^2), against the Green's-function (Lippmann-Schwinger)
+    solve of the same background-field problem (outer coupling, as in the paper, and
+    monolithic), all to rtol 1e-4, GMRES(30), mixed precision. Clips: 32x32x16 Manhattan
+    (64 nm, 30 nm absorber, 40 Mo/Si pairs, TE 6 deg), extended z grid of 64 planes with
+    a 30 nm PML (16 planes) at each end; differential solves capped at
+    --precond-max-iters steps (a capped solve counts as not converged)."""
+    import numpy as np
+    api, torch, clips, dev = ctx["api"], ctx["torch"], ctx["clips"], ctx["dev"]
+    nclips = args.precond_clips
+    rows = {"none": [], "damping": [], "ls_outer": [], "ls_mono": []}
+    times = {k: [] for k in rows}
+    layers, es = clips.mo_si_stack(40)
+    rtol = 1e-4
+    for i in range(nclips):
+        p = clips.Problem(nx=32, ny=32, nz=16, lx_nm=64.0, ly_nm=64.0, t_nm=30.0, theta_deg=6.0, phi_deg=0.0,
+                          pol=clips.TE, layers=layers, eps_sub=es)
+        d = torch.from_numpy(clips.manhattan(p.nx, p.ny, p.nz, p.lx_nm, p.ly_nm, seed=6000 + i)).to(dev)
+        pe, npml = 64, 16
+        plan = api.DiffPlan(p, pe, _diff_layout(p.nz, pe, npml), p.nz, npml)
+        for pc in ("none", "damping"):
+            t0 = time.perf_counter()
+            _, _, info = plan.solve(d, pc, rtol=rtol, restart=30, max_iters=args.precond_max_iters, max_outer=200,
+                                    precision="mixed")
+            torch.cuda.synchronize()
+            times[pc].append(time.perf_counter() - t0)
+            rows[pc].append(info["iters"] if info["status"] == 0 else None)
+            log("bench: precond clip %d %s: %d steps, %d outer, status %d, %.1f s" % (
+                i, pc, info["iters"], info["outer_iters"], info["status"], times[pc][-1]))
+        for cp, key in (("outer", "ls_outer"), ("mono", "ls_mono")):
+            ls = api.Plan(p, rtol=rtol, precision="mixed", restart=30, coupling=cp, max_outer=200, max_iters=20000)
+            ls.solve(d)
+            t, (_, _, li) = timed(lambda: ls.solve(d), 1)
+            times[key].append(t)
+            rows[key].append(li["iters"])
+        log("bench: precond clip %d LS: outer %d steps, mono %d steps" % (i, rows["ls_outer"][-1], rows["ls_mono"][-1]))
+        del plan
+    res = {"clips": nclips, "grid": [32, 32, 16], "extended_z": 64, "rtol": rtol, "restart": 30,
+           "precision": "mixed", "max_iters": args.precond_max_iters}
+    for k in rows:
+        its = [v for v in rows[k] if v is not None]
+        res[k] = {"iters_avg_min_max": [float(np.mean(its)), int(min(its)), int(max(its))] if its else None,
+                  "not_converged": sum(v is None for v in rows[k]),
+                  "seconds_avg": float(np.mean(times[k])),
+                  "rel_time_vs_none": float(np.mean(np.array(times[k]) / np.array(times["none"])))}
+    res["paper_table_context"] = {"none": [2166, 2012, 2374], "damping": [876, 811, 930], "green": [38, 32, 46],
+                                  "rel_time": {"none": 1.0, "damping": 0.43, "green": 0.11}}
+    out["precond_study"] = res
+    log("bench: precond", res)
+
+
+def sec_layers(ctx, args, out):
+    """Cost against the number of multilayer pairs (Figs. 7-8): a 30 x 30 nm absorber
+    block, 44.8 nm thick (64 planes of 0.7 nm), on a 64 nm clip (32 x 32) over Mo/Si
+    pairs of 7 nm (Si 4.2 nm, Mo 2.8 nm: 6 and 4 planes), the substrate being the
+    background medium, TE 6 deg, rtol 1e-4, mixed precision, no preconditioner.
+    Full-domain PSFD (pairs on the grid, the extended z grid grown to hold them)
+    against the background-field method with the same differential operator (absorber
+    only, the pairs in T_R) and the Lippmann-Schwinger solve (monolithic coupling)."""
+    import numpy as np
+    api, torch, clips, dev = ctx["api"], ctx["torch"], ctx["clips"], ctx["dev"]
+    dz, nz, n, L, npml, gap = 0.7, 64, 32, 64.0, 43, 8
+    dabs = clips.cuboid(n, n, nz, L, L, 30.0, 30.0)
+    d_abs = torch.from_numpy(dabs).to(dev)
+    rows = []
+    for pairs in [int(v) for v in args.layer_pairs.split(",")]:
+        layers, _ = clips.mo_si_stack(pairs, period_nm=7.0)
+        p = clips.Problem(nx=n, ny=n, nz=nz, lx_nm=L, ly_nm=L, t_nm=nz * dz, theta_deg=6.0, phi_deg=0.0,
+                          pol=clips.TE, layers=layers, eps_sub=1.0)
+        row = {"pairs": pairs}
+        # full domain: the pairs below the absorber on the grid
+        nl = 10 * pairs
+        need = 2 * npml + 2 * gap + nl + nz
+        pe = 1 << (need - 1).bit_length()
+        zc0 = npml + gap + (pe - need) // 2
+        pf = clips.Problem(**{**p.__dict__, "layers": []})
+        dc = torch.from_numpy(clips.layered_contrast(nz + nl, nz, dz, layers, dabs)).to(dev)
+        plan = api.DiffPlan(pf, pe, zc0, nz + nl, npml, form="full")
+        t0 = time.perf_counter()
+        _, of, fi = plan.solve(dc, "none", rtol=1e-4, restart=30, max_iters=args.precond_max_iters,
+                               precision="mixed")
+        torch.cuda.synchronize()
+        row["full_domain"] = {"z_planes": pe, "iters": fi["iters"], "status": fi["status"],
+                              "seconds": time.perf_counter() - t0}
+        del plan
+        # background field, differential operator: absorber only
+        peb = 1 << (2 * npml + 2 * gap + nz - 1).bit_length()
+        plan = api.DiffPlan(p, peb, (peb - nz) // 2, nz, npml)
+        t0 = time.perf_counter()
+        log("bench: layers %d pairs full domain: %d steps, status %d, %.1f s" % (
+            pairs, fi["iters"], fi["status"], row["full_domain"]["seconds"]))
+        _, ob, bi = plan.solve(d_abs, "none", rtol=1e-4, restart=30, max_iters=args.precond_max_iters,
+                               max_outer=200, precision="mixed")
+        torch.cuda.synchronize()
+        row["background_diff"] = {"z_planes": peb, "iters": bi["iters"], "outer_iters": bi["outer_iters"],
+                                  "status": bi["status"], "seconds": time.perf_counter() - t0}
+        del plan
+        # Lippmann-Schwinger (Green's function), monolithic coupling
+        ls = api.Plan(p, rtol=1e-4, precision="mixed", restart=8, max_iters=20000)
+        ls.solve(d_abs)
+        t, (_, ol, li) = timed(lambda: ls.solve(d_abs), 1)
+        row["ls_mono"] = {"iters": li["iters"], "seconds": t}
+        a = [o.cpu().numpy()[0, 0] for o in (of, ob, ol)]
+        row["specular_order"] = {"full_domain": [complex(v).__repr__() for v in a[0]],
+                                 "diff_vs_full": float(np.abs(a[1] - a[0]).max() / np.abs(a[0]).max()),
+                                 "ls_vs_full": float(np.abs(a[2] - a[0]).max() / np.abs(a[0]).max())}
+        rows.append(row)
+        log("bench: layers", row)
+    out["layer_study"] = {"rows": rows, "grid": [n, n, nz], "dz_nm": dz, "pml_planes": npml,
+                          "precond": "none", "rtol": 1e-4, "max_iters": args.precond_max_iters}
+
+
 def sec_cpu(ctx, args, out):
     import oracle as O
     clips, prob, deps_np = ctx["clips"], ctx["prob"], ctx["deps_np"]
@@ -752,6 +871,10 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline solve only")
     ap.add_argument("--only", choices=SECTIONS, default=None, help="run one section")
     ap.add_argument("--adjoint-fd", type=int, default=16, help="voxels of the adjoint's finite-difference check")
+    ap.add_argument("--precond-clips", type=int, default=4, help="clips of the preconditioner study")
+    ap.add_argument("--precond-max-iters", type=int, default=20000,
+                    help="GMRES step limit of the differential solves")
+    ap.add_argument("--layer-pairs", default="5,10,20,40", help="multilayer pairs of the layer-count study")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-budget-gib", type=float, default=12.0,
                     help="device-memory budget of the server (binding: the three grids at 8 slots need ~24 GiB)")
@@ -795,7 +918,8 @@ def main():
     else:
         todo = [s for s in SECTIONS if s != "cpu" or not args.no_cpu]
     fns = {"solve": sec_solve, "fp64": sec_fp64, "apply": sec_apply, "isolated": sec_isolated, "batched": sec_batched,
-           "serving": sec_serving, "adjoint": sec_adjoint, "cpu": sec_cpu}
+           "serving": sec_serving, "adjoint": sec_adjoint, "precond": sec_precond, "layers": sec_layers,
+           "cpu": sec_cpu}
     for s in todo:
         log("bench: section", s)
         fns[s](ctx, args, out)

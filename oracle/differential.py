@@ -30,7 +30,8 @@ layers at both ends. Readings, recorded in the design notes:
   plane above (z = T + dz/2) the same way; E_up = T_R (a_inc + a_dn); the orders
   at z = T are E_up exp(i beta T) + a_up;
 * full-domain form (the paper's baseline without the background decomposition):
-  the multilayer is on the grid as permittivity, the source is V E_inc with the
+  the multilayer is on the grid as permittivity (the contrast planes below the
+  absorber, built by the input generators), the source is V E_inc with the
   incident wave alone, and the substrate is the background medium.
 """
 from __future__ import annotations
@@ -207,19 +208,3 @@ def solve_full_domain(D: DiffSetup, deps_c: np.ndarray, precond: str = "none", r
                            dense_operator(D, deps_c) if dense else None)
     orders = read_plane(D, E, D.z0 + D.nz, 0.5 * D.dz)
     return {"E": E, "orders": orders, "iters": info["iters"], "rel_residual": info["rel_residual"]}
-
-
-def layered_contrast(D: DiffSetup, deps_abs: np.ndarray, layers, eps_bg: float = 1.0) -> np.ndarray:
-    """Contrast planes (ncz, ny, nx) of the full-domain form: the multilayer below the
-    absorber (each plane takes the layer that contains its centre; layers from the
-    top down), the absorber's own contrast on its nz planes."""
-    out = np.zeros((D.ncz, D.ny, D.nx), dtype=complex)
-    nl = D.ncz - D.nz
-    bounds = np.cumsum([0.0] + [float(d) for _, d in layers])      # depth below z = 0
-    for k in range(nl):
-        depth = (nl - k - 0.5) * D.dz
-        i = int(np.searchsorted(bounds, depth, side="right")) - 1
-        if 0 <= i < len(layers):
-            out[k] = complex(layers[i][0]) - eps_bg
-    out[nl:] = deps_abs
-    return out

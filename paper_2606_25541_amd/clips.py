@@ -229,3 +229,27 @@ def serving_pool():
 def headline_clip() -> np.ndarray:
     """The 128x128x64 contact-hole clip of the headline solve (8 holes, seed 2001)."""
     return contact_holes(128, 128, 64, 256.0, 256.0, 8, seed=2001)
+
+
+def layered_contrast(ncz: int, nz: int, dz: float, layers: Sequence[Tuple[complex, float]], deps_abs: np.ndarray,
+                     eps_bg: float = 1.0) -> np.ndarray:
+    """Contrast planes (ncz, ny, nx) of a full-domain grid: the multilayer below the
+    absorber (each plane takes the layer containing its centre, layers listed from
+    the top down, plane spacing dz) under the absorber's own nz planes on top."""
+    ny, nx = deps_abs.shape[1:]
+    out = np.zeros((ncz, ny, nx), dtype=np.complex128)
+    nl = ncz - nz
+    bounds = np.cumsum([0.0] + [float(d) for _, d in layers])      # depth below the absorber
+    for k in range(nl):
+        depth = (nl - k - 0.5) * dz
+        i = int(np.searchsorted(bounds, depth, side="right")) - 1
+        if 0 <= i < len(layers):
+            out[k] = complex(layers[i][0]) - eps_bg
+    out[nl:] = deps_abs
+    return out
+
+
+def cuboid(nx: int, ny: int, nz: int, lx: float, ly: float, wx: float, wy: float,
+           n_abs: complex = N_ABSORBER) -> np.ndarray:
+    """A single absorber block wx x wy nm centred on the clip, through the absorber."""
+    return extrude(_box_mask(nx, ny, lx, ly, [((lx - wx) / 2, (ly - wy) / 2, wx, wy)]), nz, n_abs)

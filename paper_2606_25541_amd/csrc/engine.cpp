@@ -62,14 +62,15 @@ Status validate_problem(const psfd_problem* p, Problem& out) {
   return st;
 }
 
-Status make_opts(const psfd_opts* o, Opts& out) {
+Status make_opts(const psfd_opts* o, Opts& out, int max_restart) {
   Status st;
   out = Opts();
   if (!o) return st;
-  if (!(o->rtol > 0) || o->restart < 1 || o->restart > MAXM || o->max_iters < 1 || o->max_outer < 1 ||
+  if (!(o->rtol > 0) || o->restart < 1 || o->restart > max_restart || o->max_iters < 1 || o->max_outer < 1 ||
       (o->precision != PSFD_FP64 && o->precision != PSFD_MIXED)) {
     st.code = PSFD_ERR_INVALID_ARG;
-    st.msg = "bad options (rtol > 0, 1 <= restart <= 32, max_iters, max_outer >= 1, precision)";
+    st.msg = "bad options (rtol > 0, 1 <= restart <= " + std::to_string(max_restart) +
+             ", max_iters, max_outer >= 1, precision)";
     return st;
   }
   out.rtol = o->rtol;

@@ -35,7 +35,8 @@ struct Opts {
 };
 
 Status validate_problem(const psfd_problem* p, Problem& out);
-Status make_opts(const psfd_opts* o, Opts& out);
+// restart limited to max_restart (the device-driven solves: MAXM)
+Status make_opts(const psfd_opts* o, Opts& out, int max_restart = MAXM);
 Shape shape_of(const psfd_problem& p);
 // per-instance FP64 tables (TabLayout) of a problem; SINGULAR on a grazing order
 // Host part of an instance table (scalars, kx, ky, incident order); fails with

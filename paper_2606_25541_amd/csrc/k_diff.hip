@@ -476,11 +476,10 @@ Status diff_apply(psfd_diff_plan* P, const void* deps, const void* x, void* y, i
 Status diff_solve(psfd_diff_plan* P, const void* deps_v, void* e_v, void* orders, const psfd_opts* opts, int precond,
                   psfd_info* info, hipStream_t s) {
   Opts o;
-  Status st = make_opts(opts, o);
+  Status st = make_opts(opts, o, 64);
   if (!st.ok()) return st;
   if (precond != PSFD_PRECOND_NONE && precond != PSFD_PRECOND_DAMPING)
     return bad(PSFD_ERR_INVALID_ARG, "precond must be PSFD_PRECOND_NONE or PSFD_PRECOND_DAMPING");
-  if (o.restart > 64) return bad(PSFD_ERR_INVALID_ARG, "restart must be at most 64");
   if ((st = ensure_ws(P, PSFD_C128)).ok() && o.precision == PSFD_MIXED) st = ensure_ws(P, PSFD_C64);
   if (!st.ok()) return st;
   const Shape& se = P->se;

@@ -97,7 +97,7 @@ def test_diff_full_domain_solve_matches_oracle(precond):
     zc0 = npml + 6
     D = Df.DiffSetup(p, pe, zc0, nz + nl, npml)
     dabs = clips.manhattan(nx, ny, nz, 8.0, 8.0, seed=9)
-    dc = Df.layered_contrast(D, dabs, layers)
+    dc = clips.layered_contrast(nz + nl, nz, 0.69, layers, dabs)
     ref = Df.solve_full_domain(D, dc, precond, dense=True)
     plan = api.DiffPlan(p, pe, zc0, nz + nl, npml, form="full")
     e, orders, info = plan.solve(torch.from_numpy(dc).to(dev), precond, rtol=1e-11, restart=64, max_iters=200000)
