@@ -70,6 +70,15 @@ PSFD_D long long line_base(long long l, int lcin, long long s_in, long long s_ou
   return (l & ((1LL << lcin) - 1)) * s_in + (l >> lcin) * s_out;
 }
 
+// XCD-aware block order. The dispatcher hands workgroup hw to XCD hw mod 8, so
+// the blocks one XCD receives (hw = x, x + 8, x + 16, ...) are given one
+// contiguous run of logical ids: neighbouring logical blocks then share an L2
+// and run at about the same time. A bijection of [0, nb) when 8 divides nb,
+// the identity otherwise.
+PSFD_D unsigned xcd_order(unsigned hw, unsigned nb) {
+  return (nb & 7u) ? hw : (hw & 7u) * (nb >> 3) + (hw >> 3);
+}
+
 // One block: lb lines. SFL (strided lines, es != 1): consecutive threads take
 // consecutive lines at one element (adjacent in memory), and the lines are
 // interleaved in LDS; otherwise consecutive threads take consecutive elements
@@ -79,7 +88,15 @@ __global__ void k_iso_lines(IsoLines a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const long long l0 = (long long)blockIdx.x << a.llb;
+  long long blk = blockIdx.x;
+  if (MODE == LN_VLOAD) {
+    // the three component blocks of one row group read the same delta_eps
+    // rows: consecutive ids of an XCD's run take components 0, 1, 2 of one
+    // group (the pass has 3 nz ny lines, so 3 divides the block count)
+    const unsigned nb = gridDim.x, q = xcd_order(blockIdx.x, nb);
+    blk = (long long)(q % 3u) * (nb / 3u) + q / 3u;
+  }
+  const long long l0 = blk << a.llb;
   const int n = 1 << a.ln;
   const T* src = (const T*)a.src;
   const int nld = (1 << a.lload) << a.llb;
@@ -114,7 +131,7 @@ __global__ void k_iso_lines(IsoLines a) {
   }
 }
 
-// Z_MUL: a block takes lb adjacent kx of one ky (blockIdx.y), all three
+// Z_MUL: a block takes lb adjacent kx of one ky, all three
 // components: 3 lb sequences of length 2nz interleaved in LDS.
 struct IsoZ {
   void* w;
@@ -162,12 +179,17 @@ __global__ void k_iso_zmul(IsoZ a) {
   T* lds = reinterpret_cast<T*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int nz = 1 << a.lnz, lb = a.lb, nsq = 3 * lb, npts = 2 * nz * lb;
-  const long long col = ((long long)blockIdx.y << a.lnx2) + ((long long)blockIdx.x << a.llb);
+  // logical block (ky, kx / lb) in XCD order: the blocks of adjacent kx runs
+  // fill the two halves of the same 128-byte lines of W, so they are kept on
+  // one L2 (else each XCD fetches the whole line for its half)
+  const unsigned nbx = gridDim.x;
+  const unsigned lid = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y);
+  const long long col = ((long long)(lid / nbx) << a.lnx2) + ((long long)(lid % nbx) << a.llb);
   // this block's table entries: one contiguous run of (nz + 1) 6 lb values,
   // point (kz, li) entry k at (kz * 6 + k) * lb + li for kz <= nz; a point
   // kz > nz takes kz' = 2nz - kz, with xz and yz negated (the table is even in
   // kz, those two entries odd)
-  const T* tb = (const T*)a.table + (((long long)blockIdx.y * gridDim.x + blockIdx.x) * (nz + 1) * 6 * lb);
+  const T* tb = (const T*)a.table + ((long long)lid * (nz + 1) * 6 * lb);
   constexpr int ZPT = Zpt<T>::v;
   T tt[ZPT > 0 ? ZPT : 1][6];
 #pragma unroll
@@ -384,6 +406,7 @@ Status run_lines(IsoLines a, hipStream_t s) {
   line_shape(a.ln, a.nlines, LFE, lb, nthr);
   a.lb = lb;
   a.llb = ilog2_exact(lb);
+  if (MODE == LN_VLOAD && (a.nlines / lb) % 3) return bad(PSFD_ERR_UNSUPPORTED_SIZE, "row pass needs three component blocks per group");
   const size_t bytes = ((size_t)lb << a.ln) * sizeof(T);
   auto fn = k_iso_lines<T, INV, MODE, SFL, ZIN, ZOUT>;
   if (bytes > 65536) ISOCHK(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
