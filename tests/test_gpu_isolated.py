@@ -159,10 +159,15 @@ def test_isolated_apply_full_size_properties():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_isolated_solve_matches_dense_oracle(precision):
+@pytest.mark.parametrize("second_pass", ["on_cancellation", "always"])
+def test_isolated_solve_matches_dense_oracle(precision, second_pass, monkeypatch):
     """GMRES on the isolated system vs the oracle's dense LU solve (3 x 2 x 4 x 8
     unknowns, lossy background, strong random contrast), with restarts; mixed:
-    FP32 cycles, FP64 residual at every restart."""
+    FP32 cycles, FP64 residual at every restart. "always" sets the cancellation
+    threshold of the Gram-Schmidt step to 1, so every Arnoldi step takes the
+    second projection pass and its computed norm."""
+    if second_pass == "always":
+        monkeypatch.setenv("PSFD_ISO_CANCEL", "1.0")
     dev = device()
     shape, spacing, eps = (2, 4, 8), (1.0, 2.0, 1.5), 1.0 + 0.02j
     R = float(np.sqrt(sum((n * h) ** 2 for n, h in zip(shape, spacing))))
