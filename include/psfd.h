@@ -190,8 +190,9 @@ int psfd_release_cached_workspaces(void);
  * finish their slots, then free their memory) until it fits. A group idle for
  * 5 s frees its memory. Only a request that does not fit even an empty budget
  * completes at once with PSFD_ERR_OOM. Every group has its own worker thread
- * and HIP stream, so groups run concurrently; each group replays its Arnoldi
- * steps as a captured HIP graph. Served solves use the monolithic coupling;
+ * and HIP stream, so groups run concurrently; a group issues its Arnoldi steps
+ * as plain launches (no stream capture, which other threads' work could
+ * invalidate). Served solves use the monolithic coupling;
  * a served result equals the lone psfd_solve of the same problem and options
  * (same kernels, reductions in a fixed order per instance).
  * create: opts (may be NULL: library defaults) are the defaults of requests

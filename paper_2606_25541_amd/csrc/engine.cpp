@@ -297,7 +297,6 @@ Group::~Group() {
   for (auto& a : cycle_graph)
     for (auto& c : a)
       if (c.exec) (void)hipGraphExecDestroy(c.exec);
-  if (steps_graph.exec) (void)hipGraphExecDestroy(steps_graph.exec);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   for (void* p : owned) (void)hipFree(p);
   for (hipEvent_t e : flag_ev)
@@ -600,26 +599,37 @@ bool use_graphs() {
 
 Status replay(Group& g, Group::Captured& c, const std::string& key, hipStream_t s,
               const std::function<void(hipStream_t)>& issue) {
-  if (!c.exec || c.key != key) {
-    if (c.exec) {
-      HIPCHK(hipGraphExecDestroy(c.exec));
-      c.exec = nullptr;
-    }
-    if (!g.cap_stream) HIPCHK(hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking));
-    HIPCHK(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal));
-    issue(g.cap_stream);
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(g.cap_stream, &graph);
-    if (e != hipSuccess) return hip_status(e, "graph capture");
-    e = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) {
-      c.exec = nullptr;
-      return hip_status(e, "graph instantiate");
-    }
+  if (c.key != key) {
+    if (c.exec) HIPCHK(hipGraphExecDestroy(c.exec));
+    c.exec = nullptr;
+    c.failed = false;
     c.key = key;
   }
-  HIPCHK(hipGraphLaunch(c.exec, s));
+  if (!c.exec && !c.failed) {
+    // relaxed mode: the capture puts no restriction on what other threads of
+    // the process do meanwhile. If HIP still refuses it (a capture invalidated
+    // by work elsewhere), the error is cleared and this key runs eagerly.
+    if (!g.cap_stream) HIPCHK(hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      issue(g.cap_stream);
+      e = hipStreamEndCapture(g.cap_stream, &graph);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      c.exec = nullptr;
+      c.failed = true;
+      (void)hipGetLastError();
+    }
+  }
+  if (c.exec) {
+    HIPCHK(hipGraphLaunch(c.exec, s));
+  } else {
+    issue(s);
+  }
   return Status();
 }
 

@@ -118,15 +118,15 @@ struct Group {
   int* h_run = nullptr;      // pinned host mirrors
   double* h_dbl = nullptr;
   // Captured launch sequences (HIP graphs), replayed on the caller's stream:
-  // one restart cycle of the device-driven solve, or the server's block of
-  // Arnoldi steps. A graph is re-captured when its key (the launch choices
-  // baked into it) changes.
+  // one restart cycle of the device-driven solve. A graph is re-captured when
+  // its key (the launch choices baked into it) changes; a capture that HIP
+  // refuses leaves `failed` set for that key, and the cycles run eagerly.
   struct Captured {
     hipGraphExec_t exec = nullptr;
     std::string key;
+    bool failed = false;
   };
   Captured cycle_graph[2][2];   // [transpose][refl]
-  Captured steps_graph;
   hipStream_t cap_stream = nullptr;  // capture only (launches are not executed there)
   std::vector<void*> owned;
   ~Group();

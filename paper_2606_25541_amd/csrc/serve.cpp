@@ -399,15 +399,10 @@ static Status tick_group(psfd_server* S, SlotGroup& G) {
     bool any = false;
     for (int b = 0; b < B; ++b) any |= G.phase[b] == P_ARN;
     if (any) {
-      auto steps = [&](hipStream_t q) {
-        for (int k = 0; k < STEPS_PER_SYNC; ++k) arnoldi_step<T>(g, 0, 1, q);
-      };
-      if (use_graphs()) {
-        st = replay(g, g.steps_graph, launch_key(0.0, 0), s, steps);
-        if (!st.ok()) return st;
-      } else {
-        steps(s);
-      }
+      // issued eagerly: the groups' worker threads, the submitting thread and
+      // the caller's own threads all issue work while a group runs, and HIP
+      // has failed such work in another thread during a stream capture
+      for (int k = 0; k < STEPS_PER_SYNC; ++k) arnoldi_step<T>(g, 0, 1, s);
       hipError_t e = hipGetLastError();
       if (e == hipSuccess) e = hipMemcpyAsync(g.h_run, g.run, sizeof(int) * B, hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
