@@ -295,6 +295,69 @@ __device__ __forceinline__ void lds_fft_tab(T* lds, const D& d, const T* __restr
   }
 }
 
+// Last pass of lds_fft_tab with the kept half of its outputs left in
+// registers instead of LDS (a ZOUT pass that stores nothing): out[i R/2 + j] is
+// output t + j p of butterfly b = tid + i nt (sequence s, index t < p = n / R,
+// p the stride of the last pass), for j < R/2. It only reads LDS, so it has
+// no barrier; the caller consumes out directly.
+template <class T, int R, bool INV, bool SF, int E, class D>
+__device__ __forceinline__ void stockham_pass_regout(const T* lds, const D& d, int log2p, const T* __restrict__ tw,
+                                                     int tid, T* out) {
+  constexpr int NB = E >= R ? E / R : 1;
+  constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+  const int log2nr = d.ln() - LR;
+  const int nr = 1 << log2nr;
+  const int nbt = d.ns() << log2nr;
+  const int nthr = d.nt();
+  const float inv_nseq = 1.0f / (float)d.ns();
+  const int p = 1 << log2p;
+  const int tsh = d.ln() - log2p - LR;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = tid + i * nthr;
+    if (b < nbt) {
+      int s, t;
+      bfly_index<SF>(b, log2nr, d.ns(), inv_nseq, s, t);
+      const T* base = lds + s * d.ss() + t * d.es();
+      T u[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) u[j] = base[j * nr * d.es()];
+      const int k = t & (p - 1);
+      if (k != 0) twiddle_apply<T, R, INV>(u, tw, k << tsh);
+      dft_r<T, R, INV>(u);
+#pragma unroll
+      for (int j = 0; j < R / 2; ++j) out[i * (R / 2) + j] = u[j];
+    }
+  }
+}
+
+// lds_fft_tab (compile-time shapes) whose last pass returns the first half of
+// every result in registers (stockham_pass_regout) instead of storing it.
+template <class T, bool INV, bool SF, int E, class D, int LRM = FftBudget<T>::LRMAX>
+__device__ __forceinline__ void lds_fft_tab_regout(T* lds, const D& d, const T* __restrict__ tw, int tid, T* out) {
+#pragma unroll
+  for (int log2p = 0; log2p < d.ln();) {
+    const int rem = d.ln() - log2p;
+    const int lr = rem >= LRM ? LRM : rem;
+    const bool first = log2p == 0;
+    if (lr == rem) {
+      if (LRM >= 4 && lr == 4) stockham_pass_regout<T, 16, INV, SF, E, D>(lds, d, log2p, tw, tid, out);
+      else if (lr == 3) stockham_pass_regout<T, 8, INV, SF, E, D>(lds, d, log2p, tw, tid, out);
+      else if (lr == 2) stockham_pass_regout<T, 4, INV, SF, E, D>(lds, d, log2p, tw, tid, out);
+      else stockham_pass_regout<T, 2, INV, SF, E, D>(lds, d, log2p, tw, tid, out);
+    } else if (LRM >= 4 && lr == 4) {
+      pass_r<T, INV, SF, E, D, false, false, 16>(lds, d, log2p, tw, tid, first, false);
+    } else if (lr == 3) {
+      pass_r<T, INV, SF, E, D, false, false, 8>(lds, d, log2p, tw, tid, first, false);
+    } else if (lr == 2) {
+      pass_r<T, INV, SF, E, D, false, false, 4>(lds, d, log2p, tw, tid, first, false);
+    } else {
+      pass_r<T, INV, SF, E, D, false, false, 2>(lds, d, log2p, tw, tid, first, false);
+    }
+    log2p += lr;
+  }
+}
+
 // tw_all: the table of every length (tw_all[n + i] = exp(-2 pi i i / n))
 template <class T, bool INV, bool SF, int E, class D, bool ZIN = false, bool ZOUT = false,
           int LRM = FftBudget<T>::LRMAX>

@@ -912,21 +912,31 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     *p2 = csub(cmul(F, o2), cmul(tz, v2));
   }
   __syncthreads();
-  if constexpr (LPZ > 0) lds_fft_tab<T, true, true, 8, ZCT, false, true, 4>(lds, ZCT(), twl, tid);
-  else lds_fft<T, true, true, 8, false, true>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
   const int nst = 3 * nz * bx;
   if constexpr (CT) {
-    const T e = eupT[ck * 3 + c0];
+    // the inverse transform's last pass leaves the kept half in registers, and
+    // the thread that forms output t + 16 j of sequence s stores it: last pass
+    // of radix R (8 for pz = 128, 4 for pz = 64) has stride pz / R = 16 and
+    // 8 / R butterflies b = tid + i nthr per thread, b = t LS + s
+    T out[4];
+    lds_fft_tab_regout<T, true, true, 8, ZCT, 4>(lds, ZCT(), twl, tid, out);
+    constexpr int RL = LPZ == 7 ? 8 : 4, NBL = 8 / RL, PL = (1 << LPZ) / RL;
+    static_assert(LPZ == 6 || LPZ == 7, "pencil lengths with a register last pass");
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int i = tid + k * nthr, z = z0 + k * zstep;
-      if (i < nst) {
-        T v = lds[i];
-        if (a.reflect) v = cadd(v, cmul(e, ph[z * bx + ck]));
-        w[goff0 + k * gstep] = v;
+    for (int i = 0; i < NBL; ++i) {
+      const int bfl = tid + i * nthr, t = bfl / LS, sq = bfl - t * LS;
+      const int c = sq >> lbx, kxl = sq & (bx - 1);
+      const T e = eupT[kxl * 3 + c];
+#pragma unroll
+      for (int j = 0; j < RL / 2; ++j) {
+        const int z = t + PL * j;
+        T v = out[i * (RL / 2) + j];
+        if (a.reflect) v = cadd(v, cmul(e, ph[z * bx + kxl]));
+        w[((c * nz + z) * ny + ky) * nx + kx0 + kxl] = v;
       }
     }
   } else {
+    lds_fft<T, true, true, 8, false, true>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
     for (int i = tid; i < nst; i += nthr) {
       const int kxl = i & (bx - 1);
       const int rest = i >> lbx;
