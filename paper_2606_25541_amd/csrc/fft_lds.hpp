@@ -295,14 +295,15 @@ __device__ __forceinline__ void lds_fft_tab(T* lds, const D& d, const T* __restr
   }
 }
 
-// Last pass of lds_fft_tab with the kept half of its outputs left in
-// registers instead of LDS (a ZOUT pass that stores nothing): out[i R/2 + j] is
-// output t + j p of butterfly b = tid + i nt (sequence s, index t < p = n / R,
-// p the stride of the last pass), for j < R/2. It only reads LDS, so it has
-// no barrier; the caller consumes out directly.
-template <class T, int R, bool INV, bool SF, int E, class D>
+// Last pass of lds_fft_tab with its outputs left in registers instead of LDS:
+// out[i NO + j] is output t + j p of butterfly b = tid + i nt (sequence s,
+// index t < p = n / R, p the stride of the last pass), for j < NO, NO = R / 2
+// with HALF (only the first half of every sequence is kept, as ZOUT), else R.
+// It only reads LDS, so it has no barrier; the caller consumes out directly.
+template <class T, int R, bool INV, bool SF, int E, class D, bool HALF>
 __device__ __forceinline__ void stockham_pass_regout(const T* lds, const D& d, int log2p, const T* __restrict__ tw,
                                                      int tid, T* out) {
+  constexpr int NO = HALF ? R / 2 : R;
   constexpr int NB = E >= R ? E / R : 1;
   constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
   const int log2nr = d.ln() - LR;
@@ -326,14 +327,15 @@ __device__ __forceinline__ void stockham_pass_regout(const T* lds, const D& d, i
       if (k != 0) twiddle_apply<T, R, INV>(u, tw, k << tsh);
       dft_r<T, R, INV>(u);
 #pragma unroll
-      for (int j = 0; j < R / 2; ++j) out[i * (R / 2) + j] = u[j];
+      for (int j = 0; j < NO; ++j) out[i * NO + j] = u[j];
     }
   }
 }
 
-// lds_fft_tab (compile-time shapes) whose last pass returns the first half of
-// every result in registers (stockham_pass_regout) instead of storing it.
-template <class T, bool INV, bool SF, int E, class D, int LRM = FftBudget<T>::LRMAX>
+// lds_fft_tab (compile-time shapes) whose last pass returns its results (the
+// first half of every sequence with HALF) in registers (stockham_pass_regout)
+// instead of storing them.
+template <class T, bool INV, bool SF, int E, class D, bool HALF, int LRM = FftBudget<T>::LRMAX>
 __device__ __forceinline__ void lds_fft_tab_regout(T* lds, const D& d, const T* __restrict__ tw, int tid, T* out) {
 #pragma unroll
   for (int log2p = 0; log2p < d.ln();) {
@@ -341,10 +343,10 @@ __device__ __forceinline__ void lds_fft_tab_regout(T* lds, const D& d, const T* 
     const int lr = rem >= LRM ? LRM : rem;
     const bool first = log2p == 0;
     if (lr == rem) {
-      if (LRM >= 4 && lr == 4) stockham_pass_regout<T, 16, INV, SF, E, D>(lds, d, log2p, tw, tid, out);
-      else if (lr == 3) stockham_pass_regout<T, 8, INV, SF, E, D>(lds, d, log2p, tw, tid, out);
-      else if (lr == 2) stockham_pass_regout<T, 4, INV, SF, E, D>(lds, d, log2p, tw, tid, out);
-      else stockham_pass_regout<T, 2, INV, SF, E, D>(lds, d, log2p, tw, tid, out);
+      if (LRM >= 4 && lr == 4) stockham_pass_regout<T, 16, INV, SF, E, D, HALF>(lds, d, log2p, tw, tid, out);
+      else if (lr == 3) stockham_pass_regout<T, 8, INV, SF, E, D, HALF>(lds, d, log2p, tw, tid, out);
+      else if (lr == 2) stockham_pass_regout<T, 4, INV, SF, E, D, HALF>(lds, d, log2p, tw, tid, out);
+      else stockham_pass_regout<T, 2, INV, SF, E, D, HALF>(lds, d, log2p, tw, tid, out);
     } else if (LRM >= 4 && lr == 4) {
       pass_r<T, INV, SF, E, D, false, false, 16>(lds, d, log2p, tw, tid, first, false);
     } else if (lr == 3) {

@@ -423,13 +423,20 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
   // sequence-fastest butterflies: consecutive lanes take consecutive rows (or
   // columns), so with the odd pitch every LDS access of a pass is conflict-free
   lds_fft_tab<T, INV, true, KT, Rows, false, false, 4>(lds, Rows(), twl, tid);
-  lds_fft_tab<T, INV, true, KT, Cols, false, false, 4>(lds, Cols(), twl, tid);
+  // the column transform's last pass leaves its results in registers: its
+  // butterfly b = tid + i NT (column b mod N, index t = b / N) forms rows
+  // t + PL j of that column, i.e. plane elements tid + (i + KJ j) NT, which are
+  // this thread's own store elements k = i + KJ j
+  T res[KT];
+  lds_fft_tab_regout<T, INV, true, KT, Cols, false, 4>(lds, Cols(), twl, tid, res);
+  constexpr int LRL = (LN - 1) % 4 + 1, RL = 1 << LRL, NBL = KT / RL, PL = N / RL, KJ = PL * N / NT;
+  static_assert(LN >= 4 && NBL * RL == KT && KJ * NT == PL * N && KJ == NBL, "plane last pass");
   T* out = vref<T>(a.out, b) + poff;
   const R al = (R)a.alpha, ga = (R)a.gamma;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
-    const int i = tid + k * NT;
-    T v = lds[(i >> LN) * P + (i & (N - 1))];
+    const int kj = k / KJ, ki = k - kj * KJ;  // k = ki + KJ kj: butterfly ki, output kj
+    T v = res[ki * RL + kj];
     if (ST == ST_AXPBY) {
       const T xv = xa[ST == ST_AXPBY ? k : 0];
       v.x = al * xv.x + ga * v.x;
@@ -919,7 +926,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     // of radix R (8 for pz = 128, 4 for pz = 64) has stride pz / R = 16 and
     // 8 / R butterflies b = tid + i nthr per thread, b = t LS + s
     T out[4];
-    lds_fft_tab_regout<T, true, true, 8, ZCT, 4>(lds, ZCT(), twl, tid, out);
+    lds_fft_tab_regout<T, true, true, 8, ZCT, true, 4>(lds, ZCT(), twl, tid, out);
     constexpr int RL = LPZ == 7 ? 8 : 4, NBL = 8 / RL, PL = (1 << LPZ) / RL;
     static_assert(LPZ == 6 || LPZ == 7, "pencil lengths with a register last pass");
 #pragma unroll
