@@ -343,9 +343,12 @@ __device__ __forceinline__ void lds_fft_tab_regout(T* lds, const D& d, const T* 
     const int lr = rem >= LRM ? LRM : rem;
     const bool first = log2p == 0;
     if (lr == rem) {
-      if (LRM >= 4 && lr == 4) stockham_pass_regout<T, 16, INV, SF, E, D, HALF>(lds, d, log2p, tw, tid, out);
-      else if (lr == 3) stockham_pass_regout<T, 8, INV, SF, E, D, HALF>(lds, d, log2p, tw, tid, out);
-      else if (lr == 2) stockham_pass_regout<T, 4, INV, SF, E, D, HALF>(lds, d, log2p, tw, tid, out);
+      // (radix 16 only where LRM allows it: out holds E / 2 values with HALF, E without)
+      if (lr == 4) {
+        if constexpr (LRM >= 4) stockham_pass_regout<T, 16, INV, SF, E, D, HALF>(lds, d, log2p, tw, tid, out);
+      } else if (lr == 3) {
+        stockham_pass_regout<T, 8, INV, SF, E, D, HALF>(lds, d, log2p, tw, tid, out);
+      } else if (lr == 2) stockham_pass_regout<T, 4, INV, SF, E, D, HALF>(lds, d, log2p, tw, tid, out);
       else stockham_pass_regout<T, 2, INV, SF, E, D, HALF>(lds, d, log2p, tw, tid, out);
     } else if (LRM >= 4 && lr == 4) {
       pass_r<T, INV, SF, E, D, false, false, 16>(lds, d, log2p, tw, tid, first, false);
