@@ -295,6 +295,38 @@ __device__ __forceinline__ void lds_fft_tab(T* lds, const D& d, const T* __restr
   }
 }
 
+// First pass (p = 1, no twiddles) of a transform whose inputs are already in
+// registers: in[i NI + j] is element t + j nr of the sequence of butterfly
+// b = tid + i nt (sequence s, index t < nr = n / R), for j < NI, NI = R / 2
+// with ZIN (the second half of every sequence is zero), else R. The outputs
+// go to LDS in Stockham order; the caller synchronises before the next pass.
+template <class T, int R, bool INV, bool SF, int E, class D, bool ZIN>
+__device__ __forceinline__ void stockham_pass_regin(T* lds, const D& d, int tid, const T* in) {
+  constexpr int NB = E >= R ? E / R : 1;
+  constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+  constexpr int NI = ZIN ? R / 2 : R;
+  const int log2nr = d.ln() - LR;
+  const int nbt = d.ns() << log2nr;
+  const int nthr = d.nt();
+  const float inv_nseq = 1.0f / (float)d.ns();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = tid + i * nthr;
+    if (b < nbt) {
+      int s, t;
+      bfly_index<SF>(b, log2nr, d.ns(), inv_nseq, s, t);
+      T u[R];
+#pragma unroll
+      for (int j = 0; j < NI; ++j) u[j] = in[i * NI + j];
+      if (ZIN) dft_r_half<T, R, INV>(u);
+      else dft_r<T, R, INV>(u);
+      T* base = lds + s * d.ss() + t * R * d.es();
+#pragma unroll
+      for (int j = 0; j < R; ++j) base[j * d.es()] = u[j];
+    }
+  }
+}
+
 // Last pass of lds_fft_tab with its outputs left in registers instead of LDS:
 // out[i NO + j] is output t + j p of butterfly b = tid + i nt (sequence s,
 // index t < p = n / R, p the stride of the last pass), for j < NO, NO = R / 2

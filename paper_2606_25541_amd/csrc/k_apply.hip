@@ -743,8 +743,11 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   const int zstep = CT ? nthr / LS : 0;
   const int c0 = CT ? (tid >> lbx) % 3 : 0, z0 = CT ? tid / LS : 0;
   const int goff0 = ((c0 * nz + z0) * ny + ky) * nx + kx0 + ck, gstep = zstep * ny * nx;
+  // compile-time shapes: the data stays in registers, where the forward
+  // transform's first pass and the readout partial sums take it (elements
+  // z0 + k zstep of sequence (c0, ck) are exactly that pass's inputs)
+  T buf[4];
   {
-    T buf[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if constexpr (CT) {
@@ -763,10 +766,12 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) buf[k] = cscale(buf[k], scl);
     }
+    if constexpr (!CT) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int i = tid + k * nthr;
-      if (i < nval) lds[i] = buf[k];
+      for (int k = 0; k < 4; ++k) {
+        const int i = tid + k * nthr;
+        if (i < nval) lds[i] = buf[k];
+      }
     }
   }
   // the padded half is never read: the first forward pass treats it as zero
@@ -836,7 +841,13 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
       const int sq = tid % LS, ch = tid / LS;
       const int kxl = sq & (bx - 1);
       T acc = cmake<T>(0, 0);
-      for (int z = ch; z < nz; z += nch) acc = cadd(acc, cmul(ph[z * bx + kxl], lds[z * LS + sq]));
+      if constexpr (CT) {
+        // (ch, sq) = (z0, tid mod LS): this thread's own data, planes z0 + k zstep
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc = cadd(acc, cmul(ph[(ch + k * nch) * bx + kxl], buf[k]));
+      } else {
+        for (int z = ch; z < nz; z += nch) acc = cadd(acc, cmul(ph[z * bx + kxl], lds[z * LS + sq]));
+      }
       part[tid] = to_d(acc);
     }
     __syncthreads();
@@ -872,8 +883,17 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   }
   const T* tw = reinterpret_cast<const T*>(a.tw);
   typedef FftCT<LPZ, 3 * BXC, 1, 3 * BXC, pencil_threads_ct(LPZ, BXC)> ZCT;
-  if constexpr (LPZ > 0) lds_fft_tab<T, false, true, 8, ZCT, true, false, 4>(lds, ZCT(), twl, tid);
-  else lds_fft<T, false, true, 8, true, false>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
+  if constexpr (LPZ > 0) {
+    // radix 8 first, from the registers (its inputs t + pz/8 j, j < 4, of
+    // sequence tid mod LS, t = tid / LS, are buf[j]), then the last pass
+    static_assert(LPZ == 6 || LPZ == 7, "pencil lengths with a register first pass");
+    stockham_pass_regin<T, 8, false, true, 8, ZCT, true>(lds, ZCT(), tid, buf);
+    __syncthreads();
+    if constexpr (LPZ == 7) pass_r<T, false, true, 8, ZCT, false, false, 16>(lds, ZCT(), 3, twl, tid, false, true);
+    else pass_r<T, false, true, 8, ZCT, false, false, 8>(lds, ZCT(), 3, twl, tid, false, true);
+  } else {
+    lds_fft<T, false, true, 8, true, false>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
+  }
 
   // the points of a thread all lie in its column ck (nthr is a multiple of bx):
   // its order constants are read once, in the working precision
