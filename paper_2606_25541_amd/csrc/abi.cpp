@@ -176,10 +176,12 @@ int psfd_bench_stage(psfd_plan* plan, int stage, const void* d_deps, const void*
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(PSFD_ERR_HIP, "hipEventCreate");
   Group& g = *plan->lite;
+  const bool qp = quarter_planes(g, esz);  // the stage as psfd_apply runs it
   (void)hipEventRecord(e0, s);
   for (int r = 0; r < reps; ++r) {
     if (dtype == PSFD_C64)
-      apply_stage<float2>(g, stage, (const float2*)d_deps, vr(d_x), vr(d_y), (float2*)scratch, 0, 0, 1, nullptr, s);
+      apply_stage<float2>(g, stage, (const float2*)d_deps, vr(d_x), vr(d_y), (float2*)scratch, 0, 0, 1, nullptr, s,
+                          nullptr, 0, nullptr, qp);
     else
       apply_stage<double2>(g, stage, (const double2*)d_deps, vr(d_x), vr(d_y), (double2*)scratch, 0, 0, 1,
                            nullptr, s);

@@ -47,3 +47,12 @@ template <> PSFD_HD float2 from_d<float2>(double2 a) { return to_f(a); }
 template <> PSFD_HD double2 from_d<double2>(double2 a) { return a; }
 
 PSFD_HD int ilog2i(int v) { int r = 0; while ((1 << r) < v) ++r; return r; }
+
+// XCD-aware block order. The dispatcher hands workgroup hw to XCD hw mod 8, so
+// the blocks one XCD receives (hw = x, x + 8, x + 16, ...) are given one
+// contiguous run of logical ids: neighbouring logical blocks then share an L2
+// and run at about the same time. A bijection of [0, nb) when 8 divides nb,
+// the identity otherwise.
+PSFD_D unsigned xcd_order(unsigned hw, unsigned nb) {
+  return (nb & 7u) ? hw : (hw & 7u) * (nb >> 3) + (hw >> 3);
+}

@@ -200,7 +200,7 @@ void build_twiddles(std::vector<double>& tw) {
 
 // ---------------------------------------------------------------------------
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-// launch-shape overrides for tuning sweeps (read once)
+// launch-shape overrides for tuning sweeps (read at every call)
 static int env_int(const char* name, int dflt) {
   const char* e = std::getenv(name);
   return e ? std::atoi(e) : dflt;
@@ -415,18 +415,36 @@ static TileArgs tile_base(const Group& g, const void* tw, const TileShape& t) {
   return a;
 }
 
+bool quarter_planes(const Group& g, size_t esz) {
+  const Shape& sh = g.sh;
+  if (esz != 8 || !xy_config(sh, esz).fused || env_int("PSFD_QUARTER_PLANES", 1) == 0) return false;
+  const ZCfg z = z_config(sh, esz);
+  return qplane_shape(sh.nx, sh.ny, sh.nz, sh.pz, z.bx, z.nthr);
+}
+
 template <class T>
 void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose,
                  int refl, const int* active, hipStream_t s, const double* in_scale, long long scale_stride,
-                 const GivensTask* gt) {
+                 const GivensTask* gt, bool qp) {
   const Shape& sh = g.sh;
   const XYCfg c = xy_config(sh, sizeof(T));
   const int np = 3 * sh.nz;
   const T* tw = twiddles<T>(g);
   VecRef wsr = vr(ws, sh.n3);
+  if (qp && (gt || !quarter_planes(g, sizeof(T)))) {
+    std::fprintf(stderr, "psfd: internal error: quarter-plane apply stage on an unsupported shape\n");
+    std::abort();
+  }
   if (stage == 0) {
     // forward: w = FFT_xy(k0^2 delta_eps x)
-    if (c.fused) {
+    if (qp) {
+      if constexpr (sizeof(T) == 8) {
+        TileArgs a = tile_base(g, tw, c.full);
+        a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
+        a.in_scale = in_scale; a.scale_stride = scale_stride;
+        launch_qplane<T, false, LD_VX, ST_PLAIN>(a, np, g.B, s);
+      }
+    } else if (c.fused) {
       TileArgs a = tile_base(g, tw, c.full);
       a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
       a.in_scale = in_scale; a.scale_stride = scale_stride;
@@ -453,14 +471,21 @@ void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* w
     PencilArgs p;
     std::memset(&p, 0, sizeof(p));
     p.nx = sh.nx; p.ny = sh.ny; p.nz = sh.nz; p.pz = sh.pz; p.log2pz = ilog2i(sh.pz);
-    p.bx = z.bx; p.pitch = sh.pz + 1; p.nblk_x = sh.nx / z.bx;
+    p.bx = z.bx; p.pitch = sh.pz + 1; p.nblk_x = qp ? sh.nx / 4 : sh.nx / z.bx; p.yq = qp;
     p.w = wsr; p.tab = g.tab; p.tab_stride = g.tab_stride; p.tw = tw; p.transpose = transpose; p.reflect = refl;
     p.active = active;
     if (gt) p.gv = *gt;  // the pending Givens step, and the scale of the input from its partials
     launch_pencil<T>(p, g.B, z.nthr, z.lds, s);
   } else {
     // inverse: out = in - IFFT_xy(w) (kmode 0) or out = IFFT_xy(w) (kmode 1, no read of in)
-    if (c.fused) {
+    if (qp) {
+      if constexpr (sizeof(T) == 8) {
+        TileArgs a = tile_base(g, tw, c.full);
+        a.in = wsr; a.aux = in; a.out = out; a.alpha = 1.0; a.gamma = -1.0; a.active = active;
+        if (kmode == 0) launch_qplane<T, true, LD_PLAIN, ST_AXPBY>(a, np, g.B, s);
+        else launch_qplane<T, true, LD_PLAIN, ST_PLAIN>(a, np, g.B, s);
+      }
+    } else if (c.fused) {
       TileArgs a = tile_base(g, tw, c.full);
       a.in = wsr; a.aux = in; a.out = out; a.alpha = 1.0; a.gamma = -1.0; a.active = active;
       if (kmode == 0) launch_tile<T, true, LD_PLAIN, ST_AXPBY>(a, np, g.B, c.full.nthr, c.full.lds, s);
@@ -477,17 +502,19 @@ void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* w
   }
 }
 template void apply_stage<float2>(Group&, int, const float2*, VecRef, VecRef, float2*, int, int, int, const int*,
-                                  hipStream_t, const double*, long long, const GivensTask*);
+                                  hipStream_t, const double*, long long, const GivensTask*, bool);
 template void apply_stage<double2>(Group&, int, const double2*, VecRef, VecRef, double2*, int, int, int,
-                                   const int*, hipStream_t, const double*, long long, const GivensTask*);
+                                   const int*, hipStream_t, const double*, long long, const GivensTask*, bool);
 
 template <class T>
 void apply_op(Group& g, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose, int refl,
               const int* active, hipStream_t s, const double* in_scale, long long scale_stride,
               const GivensTask* gt) {
+  // the quarter-plane kernels where the shape takes them (no Givens step to carry)
+  const bool qp = !gt && quarter_planes(g, sizeof(T));
   for (int stage = 0; stage < 3; ++stage)
     apply_stage<T>(g, stage, deps, in, out, ws, kmode, transpose, refl, active, s, in_scale, scale_stride,
-                   stage == 0 ? gt : nullptr);
+                   stage == 0 ? gt : nullptr, qp);
 }
 template void apply_op<float2>(Group&, const float2*, VecRef, VecRef, float2*, int, int, int, const int*,
                                hipStream_t, const double*, long long, const GivensTask*);

@@ -156,11 +156,17 @@ template <class T>
 void apply_op(Group& g, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose, int refl,
               const int* active, hipStream_t s, const double* in_scale = nullptr, long long scale_stride = 0,
               const GivensTask* gt = nullptr);
-// one of the three launches of apply_op: 0 transverse forward, 1 z-pencil, 2 transverse inverse
+// one of the three launches of apply_op: 0 transverse forward, 1 z-pencil, 2 transverse inverse.
+// qp: the quarter-plane kernels and layout (all three stages of one apply alike;
+// only where quarter_planes holds and with no gt)
 template <class T>
 void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose,
                  int refl, const int* active, hipStream_t s, const double* in_scale = nullptr,
-                 long long scale_stride = 0, const GivensTask* gt = nullptr);
+                 long long scale_stride = 0, const GivensTask* gt = nullptr, bool qp = false);
+// whether the operator apply of this group's shape takes the quarter-plane
+// kernels (FP32 128 x 128 planes with the compile-time pencil; PSFD_QUARTER_PLANES=0
+// turns them off)
+bool quarter_planes(const Group& g, size_t esz);
 
 struct SolveStats {
   int iters = 0, outer = 0, cycles = 0, status = PSFD_OK;

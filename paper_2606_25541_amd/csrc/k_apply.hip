@@ -449,6 +449,153 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
 }
 
 // -------------------------------------------------------------------------
+// Quarter-plane kernels (FP32 128 x 128 planes, operator apply). The
+// transverse transform of a plane is split four ways over y: block q of a
+// plane takes the rows y = 4 r + q (r < 32), transforms them along x (128
+// points) and along r (32 points), and stores the quarter spectrum times its
+// twiddle, Y'_q(ky', kx) = W128^(q ky') Y_q(ky', kx), ky' < 32. The full
+// spectrum is the radix-4 decimation-in-time combine
+//   X(ky' + 32 m, kx) = sum_q W4^(q m) Y'_q(ky', kx),
+// a twiddle-free 4-point DFT that the z-pencil kernel takes on load. Back the
+// same way: the pencil stores Z'_q = sum_m W4^(-q m) X(ky' + 32 m), and block q
+// multiplies by W128^(-q ky') and transforms along r and x back to the rows
+// y = 4 r + q. Four blocks per plane (768 at 192 planes) keep every CU busy
+// with three resident blocks whose loads and FFT passes overlap; one block per
+// plane leaves 64 of 256 CUs idle and runs each CU's load, transform and store
+// one after the other.
+// Layout between the kernels, per plane: the four quarter spectra interleaved
+// in 32-byte pieces, (q, ky', kx) at qp_index(ky', kx, q), so that the 16 values
+// a pencil block takes at one (component, z) form one 128-byte line.
+// -------------------------------------------------------------------------
+constexpr int QP_N = 128, QP_ROWS = 32, QP_THREADS = 256;
+__host__ __device__ constexpr size_t qplane_lds(size_t esz) {
+  return ((size_t)QP_ROWS * (QP_N + 1) + QP_N + QP_ROWS) * esz;
+}
+PSFD_D int qp_index(int kyq, int kx, int q) { return kyq * (4 * QP_N) + (kx >> 2) * 16 + 4 * q + (kx & 3); }
+
+template <class T, bool INV, int LD, int ST>
+__global__ void __launch_bounds__(QP_THREADS) k_qplane(TileArgs a) {
+  constexpr int N = QP_N, P = N + 1, NT = QP_THREADS, KT = QP_ROWS * N / NT;
+  static_assert(sizeof(T) == 8 && KT == 16, "FP32, 16 values per thread");
+  static_assert(!INV || LD == LD_PLAIN, "inverse: plain load");
+  static_assert(INV || (LD == LD_VX && ST == ST_PLAIN), "forward: contrast multiply, plain store");
+  extern __shared__ double2 smem_d[];
+  T* lds = reinterpret_cast<T*>(smem_d);
+  T* twl = lds + QP_ROWS * P;  // W128^k, k < 128
+  T* twl32 = twl + N;          // W32^k = W128^(4 k), k < 32
+  const int b = blockIdx.y;
+  if (a.active && !a.active[b]) return;
+  // block order: with 8 | nz, XCD x (= hw mod 8) takes the planes z = x mod 8 of
+  // all three components and their four quarters, so the three blocks that read
+  // one contrast plane share an L2, and so do the four that write (or read) one
+  // 128-byte line of the layout
+  int plane, q;
+  {
+    const int hw = blockIdx.x;
+    if ((a.nz & 7) == 0) {
+      const int xc = hw & 7, i = hw >> 3, t = i >> 2, c = t % 3, zz = t / 3;
+      q = i & 3;
+      plane = c * a.nz + xc + 8 * zz;
+    } else {
+      plane = hw >> 2;
+      q = hw & 3;
+    }
+  }
+  const int z = plane % a.nz;
+  const long long poff = (long long)plane * N * N;
+  const int tid = threadIdx.x;
+  typedef typename real_of<T>::type R;
+  const T* twg = reinterpret_cast<const T*>(a.tw) + N;
+  const T tw0 = twg[tid & (N - 1)];
+  const T tw1 = twg[(tid & (QP_ROWS - 1)) * 4];
+  // the twiddle loads ahead of the data loads: their LDS writes wait for them alone
+  __builtin_amdgcn_sched_barrier(0);
+  const T* in = vref<T>(a.in, b) + poff;
+  const T* vol = INV ? nullptr : vref<T>(a.vol, b) + (long long)z * N * N;
+  const T* aux = ST == ST_AXPBY ? vref<T>(a.aux, b) + poff : nullptr;
+  // the column transform's last pass (radix 4, stride 8) leaves its results in
+  // registers: butterfly i of the thread (column s = tid mod 128, index
+  // t = tid / 128 + 2 i) forms rows r = t + 8 j of that column
+  constexpr int RL = 4, PL = 8, NBL = KT / RL;
+  T va[KT], vb[INV ? 1 : KT], xa[ST == ST_AXPBY ? KT : 1];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int i = tid + k * NT, r = i >> 7, x = i & (N - 1);
+    if constexpr (!INV) {
+      va[k] = in[(4 * r + q) * N + x];
+      vb[k] = vol[(4 * r + q) * N + x];
+    } else {
+      va[k] = in[qp_index(r, x, q)];
+    }
+  }
+  if constexpr (ST == ST_AXPBY) {
+#pragma unroll
+    for (int i = 0; i < NBL; ++i)
+#pragma unroll
+      for (int j = 0; j < RL; ++j) {
+        const int r = (tid >> 7) + 2 * i + PL * j, x = tid & (N - 1);
+        xa[i * RL + j] = aux[(4 * r + q) * N + x];
+      }
+  }
+  const double* tab = a.tab + (long long)b * a.tab_stride;
+  R ks = (R)1;
+  if constexpr (!INV) ks = (R)tab[TS_K0SQ] * (a.in_scale ? (R)a.in_scale[(long long)b * a.scale_stride] : (R)1);
+  if (tid < N) twl[tid] = tw0;
+  if (tid < QP_ROWS) twl32[tid] = tw1;
+  // the inverse multiplies by W128^(-q ky') on the way into LDS
+  if constexpr (INV) __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int i = tid + k * NT, r = i >> 7;
+    T v;
+    if constexpr (INV) v = cmulc(va[k], twl[q * r]);
+    else v = cscale(cmul(vb[k], va[k]), ks);
+    lds[r * P + (i & (N - 1))] = v;
+  }
+  __syncthreads();
+  typedef FftCT<7, QP_ROWS, P, 1, NT> Rows;  // 32 rows of 128 points
+  typedef FftCT<5, N, 1, P, NT> Cols;        // 128 columns of 32 points
+  lds_fft_tab<T, INV, true, KT, Rows, false, false, 4>(lds, Rows(), twl, tid);
+  T res[KT];
+  lds_fft_tab_regout<T, INV, true, KT, Cols, false, 3>(lds, Cols(), twl32, tid, res);
+  T* out = vref<T>(a.out, b) + poff;
+  const R al = (R)a.alpha, ga = (R)a.gamma;
+#pragma unroll
+  for (int i = 0; i < NBL; ++i)
+#pragma unroll
+    for (int j = 0; j < RL; ++j) {
+      const int r = (tid >> 7) + 2 * i + PL * j, x = tid & (N - 1);
+      T v = res[i * RL + j];
+      if constexpr (!INV) {
+        out[qp_index(r, x, q)] = cmul(v, twl[q * r]);
+      } else {
+        if constexpr (ST == ST_AXPBY) {
+          const T xv = xa[ST == ST_AXPBY ? i * RL + j : 0];
+          v.x = al * xv.x + ga * v.x;
+          v.y = al * xv.y + ga * v.y;
+        }
+        out[(4 * r + q) * N + x] = v;
+      }
+    }
+}
+
+
+template <class T, bool INV, int LD, int ST>
+void launch_qplane(const TileArgs& a, int nplanes, int nbatch, hipStream_t s) {
+  if constexpr (sizeof(T) == 8) {
+    if (a.nx != QP_N || a.ny != QP_N || a.gv.st || nplanes != 3 * a.nz) {
+      std::fprintf(stderr, "psfd: internal error: quarter-plane launch on an unsupported shape\n");
+      std::abort();
+    }
+    hipLaunchKernelGGL((k_qplane<T, INV, LD, ST>), dim3(4 * nplanes, nbatch), dim3(QP_THREADS),
+                       qplane_lds(sizeof(T)), s, a);
+  }
+}
+template void launch_qplane<float2, false, LD_VX, ST_PLAIN>(const TileArgs&, int, int, hipStream_t);
+template void launch_qplane<float2, true, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, hipStream_t);
+template void launch_qplane<float2, true, LD_PLAIN, ST_AXPBY>(const TileArgs&, int, int, hipStream_t);
+
+// -------------------------------------------------------------------------
 // Strip kernel: for square N x N planes too large for LDS, the x-FFT of
 // TY = 4096 / N full rows (ROWS) or the y-FFT of 16 full columns of one plane,
 // with the shapes fixed at compile time; 8 elements per thread, twiddles in
@@ -705,9 +852,51 @@ __host__ __device__ constexpr int pencil_threads_ct(int lpz, int bx) {
                                                                             : (12 * bx + 63) / 64 * 64;
 }
 
+// Quarter-spectrum combine of the pencil (quarter-plane layout): a 4-point DFT
+// across the four lanes of a quad, lane q holding input q. Its radix-2 stages
+// pair lanes q, q ^ 2 and then q, q ^ 1 through DPP quad permutations
+// (partner + sign * own). Forward: lane q receives X_brev(q) =
+// sum_p W4^(p brev(q)) Y_p (brev: the 2-bit reversal); inverse: lane q holds
+// X_brev(q) and receives Z_q = sum_m W4^(-q m) X_m.
+template <int CTRL> PSFD_D float quad_perm_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> PSFD_D float2 quad_bfly(float2 v, float sg) {
+  float2 r;
+  r.x = quad_perm_f<CTRL>(v.x) + sg * v.x;
+  r.y = quad_perm_f<CTRL>(v.y) + sg * v.y;
+  return r;
+}
+constexpr int DPP_QUAD_SWAP2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+constexpr int DPP_QUAD_SWAP1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+PSFD_D float2 quad_dft4_fwd(float2 v, int q) {
+  v = quad_bfly<DPP_QUAD_SWAP2>(v, q < 2 ? 1.f : -1.f);
+  if (q == 3) v = make_float2(v.y, -v.x);  // times -i
+  return quad_bfly<DPP_QUAD_SWAP1>(v, (q & 1) ? -1.f : 1.f);
+}
+PSFD_D float2 quad_dft4_inv(float2 v, int q) {
+  v = quad_bfly<DPP_QUAD_SWAP1>(v, (q & 1) ? -1.f : 1.f);
+  if (q == 3) v = make_float2(-v.y, v.x);  // times +i
+  return quad_bfly<DPP_QUAD_SWAP2>(v, q < 2 ? 1.f : -1.f);
+}
+template <class T> PSFD_D T quad_dft4(T v, int q, bool inv);
+template <> PSFD_D float2 quad_dft4<float2>(float2 v, int q, bool inv) {
+  return inv ? quad_dft4_inv(v, q) : quad_dft4_fwd(v, q);
+}
+template <> PSFD_D double2 quad_dft4<double2>(double2 v, int, bool) { return v; }  // not instantiated with YQ
+// pencil column c of a quarter-layout block: kx = kx0 + c / 4 and quarter
+// q = c mod 4 on load (position 4 q + c / 4 of the block's 16-value piece), row
+// ky' + (ny / 4) brev(q) after the combine
+PSFD_D int qp_pos(int c) { return ((c & 3) << 2) | (c >> 2); }
+PSFD_D int brev2(int q) { return ((q & 1) << 1) | (q >> 1); }
+
 // LPZ > 0: BXC columns and padded length 2^LPZ fixed at compile time (the FFT
 // index arithmetic folds to constants); LPZ = 0: shapes from the arguments.
-template <class T, int LPZ, int BXC>
+// YQ: the workspace holds the quarter-plane layout (see k_qplane): a block
+// takes 4 kx of the quarter-spectrum row ky' in its 4 quarters, which the
+// combine on load turns into the 16 columns kx0 + kx, ky' + (ny / 4) m, and
+// the inverse combine on store back into quarters.
+template <class T, int LPZ, int BXC, bool YQ>
 __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   extern __shared__ double2 smem_d[];
   T* lds = reinterpret_cast<T*>(smem_d);
@@ -722,8 +911,9 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   }
   if (a.active && !a.active[b]) return;
   const int bx = LPZ ? BXC : a.bx, pz = LPZ ? (1 << LPZ) : a.pz, nz = pz / 2, nx = a.nx, ny = a.ny;
-  const int ky = blockIdx.x / a.nblk_x;
-  const int kx0 = (blockIdx.x - ky * a.nblk_x) * bx;
+  static_assert(!YQ || (LPZ > 0 && BXC == 16 && sizeof(T) == 8), "quarter layout: FP32 compile-time pencils");
+  const int ky = blockIdx.x / a.nblk_x;  // YQ: the quarter-spectrum row ky'
+  const int kx0 = (blockIdx.x - ky * a.nblk_x) * (YQ ? 4 : bx);
   const int tid = threadIdx.x, nthr = LPZ ? pencil_threads_ct(LPZ, BXC) : (int)blockDim.x;
   const int LS = 3 * bx;
   const int lbx = LPZ ? (BXC == 16 ? 4 : BXC == 8 ? 3 : 2) : ilog2i(bx);
@@ -742,7 +932,9 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   const int ck = tid & (bx - 1);
   const int zstep = CT ? nthr / LS : 0;
   const int c0 = CT ? (tid >> lbx) % 3 : 0, z0 = CT ? tid / LS : 0;
-  const int goff0 = ((c0 * nz + z0) * ny + ky) * nx + kx0 + ck, gstep = zstep * ny * nx;
+  const int goff0 = YQ ? (c0 * nz + z0) * ny * nx + ky * 4 * nx + kx0 * 4 + qp_pos(ck)
+                      : ((c0 * nz + z0) * ny + ky) * nx + kx0 + ck,
+            gstep = zstep * ny * nx;
   // compile-time shapes: the data stays in registers, where the forward
   // transform's first pass and the readout partial sums take it (elements
   // z0 + k zstep of sequence (c0, ck) are exactly that pass's inputs)
@@ -765,6 +957,12 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
       const R scl = (R)inv_norm_of(norm_from_partials(a.gv.part + (long long)b * a.gv.nblk, a.gv.nblk));
 #pragma unroll
       for (int k = 0; k < 4; ++k) buf[k] = cscale(buf[k], scl);
+    }
+    // the quarter spectra of the thread's quad become its 4 columns' spectra
+    // (the 16 lanes of a quad group share their component and planes)
+    if constexpr (YQ) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) buf[k] = quad_dft4<T>(buf[k], tid & 3, false);
     }
     if constexpr (!CT) {
 #pragma unroll
@@ -792,7 +990,11 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   T* ftab = reinterpret_cast<T*>(part);
   // order of column kxl (the transposed operator reads the kernel at the negated order)
   auto order_of = [&](int kxl, int& mq, int& nq) {
-    mq = kx0 + kxl; nq = ky;
+    if constexpr (YQ) {
+      mq = kx0 + (kxl >> 2); nq = ky + (ny >> 2) * brev2(kxl & 3);
+    } else {
+      mq = kx0 + kxl; nq = ky;
+    }
     if (a.transpose) { mq = (nx - mq) & (nx - 1); nq = (ny - nq) & (ny - 1); }
   };
   if (LPZ > 0 && tid < pz) twl[tid] = reinterpret_cast<const T*>(a.tw)[pz + tid];
@@ -959,7 +1161,13 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
         const int z = t + PL * j;
         T v = out[i * (RL / 2) + j];
         if (a.reflect) v = cadd(v, cmul(e, ph[z * bx + kxl]));
-        w[((c * nz + z) * ny + ky) * nx + kx0 + kxl] = v;
+        if constexpr (YQ) {
+          // back to quarter spectra across the quad (kxl = tid mod 16)
+          v = quad_dft4<T>(v, kxl & 3, true);
+          w[(c * nz + z) * ny * nx + ky * 4 * nx + kx0 * 4 + qp_pos(kxl)] = v;
+        } else {
+          w[((c * nz + z) * ny + ky) * nx + kx0 + kxl] = v;
+        }
       }
     }
   } else {
@@ -978,18 +1186,34 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
 
 template <class T>
 void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStream_t s) {
-  dim3 grid(a.nblk_x * a.ny + (a.gv.st ? 1 : 0), nbatch);  // + the GivensTask block
+  // + the GivensTask block; the quarter layout has ny / 4 block rows
+  dim3 grid(a.nblk_x * (a.yq ? a.ny / 4 : a.ny) + (a.gv.st ? 1 : 0), nbatch);
   if (a.gv.st && nthr < GIVENS_THREADS) givens_block_too_small("k_pencil", nthr);
   auto go = [&](auto kern) {
     allow_lds(reinterpret_cast<const void*>(kern), lds);
     hipLaunchKernelGGL(kern, grid, dim3(nthr), lds, s, a);
   };
-  if (a.bx == 16 && a.pz == 128 && nthr == pencil_threads_ct(7, 16)) return go(k_pencil<T, 7, 16>);
-  if (a.bx == 16 && a.pz == 64 && nthr == pencil_threads_ct(6, 16)) return go(k_pencil<T, 6, 16>);
-  go(k_pencil<T, 0, 16>);
+  if (a.yq) {
+    if constexpr (sizeof(T) == 8) {
+      if (a.bx == 16 && a.pz == 128 && nthr == pencil_threads_ct(7, 16)) return go(k_pencil<T, 7, 16, true>);
+      if (a.bx == 16 && a.pz == 64 && nthr == pencil_threads_ct(6, 16)) return go(k_pencil<T, 6, 16, true>);
+    }
+    std::fprintf(stderr, "psfd: internal error: quarter-plane pencil on an unsupported shape\n");
+    std::abort();
+  }
+  if (a.bx == 16 && a.pz == 128 && nthr == pencil_threads_ct(7, 16)) return go(k_pencil<T, 7, 16, false>);
+  if (a.bx == 16 && a.pz == 64 && nthr == pencil_threads_ct(6, 16)) return go(k_pencil<T, 6, 16, false>);
+  go(k_pencil<T, 0, 16, false>);
 }
 template void launch_pencil<float2>(const PencilArgs&, int, int, size_t, hipStream_t);
 template void launch_pencil<double2>(const PencilArgs&, int, int, size_t, hipStream_t);
+
+// the operator apply's shapes that take the quarter-plane kernels and the
+// quarter-layout pencil (FP32 128 x 128 planes, compile-time pencil)
+bool qplane_shape(int nx, int ny, int nz, int pz, int bx, int nthr) {
+  return nx == QP_N && ny == QP_N && nz > 0 && bx == 16 &&
+         ((pz == 128 && nthr == pencil_threads_ct(7, 16)) || (pz == 64 && nthr == pencil_threads_ct(6, 16)));
+}
 
 // -------------------------------------------------------------------------
 // Per-order kernels of the background-field outer loop (FP64)

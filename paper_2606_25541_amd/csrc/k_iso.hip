@@ -70,15 +70,6 @@ PSFD_D long long line_base(long long l, int lcin, long long s_in, long long s_ou
   return (l & ((1LL << lcin) - 1)) * s_in + (l >> lcin) * s_out;
 }
 
-// XCD-aware block order. The dispatcher hands workgroup hw to XCD hw mod 8, so
-// the blocks one XCD receives (hw = x, x + 8, x + 16, ...) are given one
-// contiguous run of logical ids: neighbouring logical blocks then share an L2
-// and run at about the same time. A bijection of [0, nb) when 8 divides nb,
-// the identity otherwise.
-PSFD_D unsigned xcd_order(unsigned hw, unsigned nb) {
-  return (nb & 7u) ? hw : (hw & 7u) * (nb >> 3) + (hw >> 3);
-}
-
 // One block: lb lines. SFL (strided lines, es != 1): consecutive threads take
 // consecutive lines at one element (adjacent in memory), and the lines are
 // interleaved in LDS; otherwise consecutive threads take consecutive elements

@@ -92,6 +92,7 @@ struct PencilArgs {
   const int* active;
   GivensTask gv;         // optional (gv.st null: none): the pending Givens step in one extra
                          // block; the other blocks scale the input by the new vector's scale
+  int yq;                // w in the quarter-plane layout of launch_qplane (nblk_x = nx / 4)
 };
 
 struct TileShape { int tx, ty, do_x, do_y, nthr; size_t lds; int pitch; };
@@ -121,6 +122,14 @@ bool tile_takes_dots(const TileArgs& a, size_t esz);
 bool tile_takes_update(const TileArgs& a, size_t esz);
 template <class T>
 void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStream_t s);
+// Quarter-plane transverse kernels of the FP32 operator apply on 128 x 128
+// planes: forward (LD_VX, ST_PLAIN) into the quarter-plane layout, inverse
+// (LD_PLAIN, ST_PLAIN or ST_AXPBY) from it; nplanes = 3 nz, no GivensTask.
+// The pencil between them runs with PencilArgs::yq.
+template <class T, bool INV, int LD, int ST>
+void launch_qplane(const TileArgs& a, int nplanes, int nbatch, hipStream_t s);
+// whether a shape (and its pencil's columns bx and threads) takes them
+bool qplane_shape(int nx, int ny, int nz, int pz, int bx, int nthr);
 
 // per-order readouts of the source density spectra (FP64):
 // adn = (i dz / 2 beta) P- sum_k exp(i beta z_k) f_q(z_k) / (NxNy), aup likewise at z = T.
