@@ -210,18 +210,31 @@ def sec_apply(ctx, args, out):
         # algorithmic bytes per voxel (esz = bytes per complex value): stage 0 reads x (3 esz) and
         # delta_eps (esz), writes w (3 esz); stage 1 reads and writes w; stage 2 reads w and x, writes y
         per_vox = {0: 7 * esz, 1: 6 * esz, 2: 9 * esz}
-        stages = {}
-        for st in (0, 1, 2):
-            ms = C.c_float()
-            _lib.check(L.psfd_bench_stage(plan._h, st, C.c_void_p(dd.data_ptr()), C.c_void_p(xx.data_ptr()),
-                                          C.c_void_p(y.data_ptr()), code, reps, C.byref(ms),
-                                          C.c_void_p(stream.cuda_stream)), "psfd_bench_stage")
-            t = ms.value * 1e-3
-            stages[st] = {"us": 1e3 * ms.value, "bytes": per_vox[st] * N, "gbs": per_vox[st] * N / t / 1e9}
+
+        def time_stages():
+            st_ = {}
+            for st in (0, 1, 2):
+                ms = C.c_float()
+                _lib.check(L.psfd_bench_stage(plan._h, st, C.c_void_p(dd.data_ptr()), C.c_void_p(xx.data_ptr()),
+                                              C.c_void_p(y.data_ptr()), code, reps, C.byref(ms),
+                                              C.c_void_p(stream.cuda_stream)), "psfd_bench_stage")
+                t = ms.value * 1e-3
+                st_[st] = {"us": 1e3 * ms.value, "bytes": per_vox[st] * N, "gbs": per_vox[st] * N / t / 1e9}
+            return st_
+        stages = time_stages()
         b_apply = 22 * esz * N
         res[name] = {"applies_per_s": 1.0 / t_apply, "us_per_apply": 1e6 * t_apply, "apply_bytes": b_apply,
                      "apply_gbs": b_apply / t_apply / 1e9, "apply_frac_hbm": b_apply / t_apply / 1e9 / HBM_PEAK_GBS,
                      "stages": stages}
+        if name == "fp32" and prob.nx == prob.ny == 128:
+            # the operator apply runs the quarter-plane kernels (four blocks per 128 x 128 plane, the
+            # pencil on the quarter layout); the Arnoldi steps of a solve run the one-block-per-plane
+            # kernels with their fused Gram-Schmidt work, whose plain forms are timed here
+            os.environ["PSFD_QUARTER_PLANES"] = "0"
+            try:
+                res[name]["stages_full_planes"] = time_stages()
+            finally:
+                os.environ.pop("PSFD_QUARTER_PLANES", None)
     out["apply"] = res
     # kernels of the Arnoldi steps of one restart cycle (columns j = 0 .. m-1) on FP32 basis vectors,
     # through psfd_bench_gram_schmidt: the projections read v_0..v_j and w, (j + 2) 3N complex64; the
@@ -256,7 +269,7 @@ def sec_apply(ctx, args, out):
     # the dominant kernel of an Arnoldi step (largest mean time per step over a cycle): the forward
     # stage (plain at step 0; with the previous column's update at steps 1..m-1 where fused), the
     # pencil, the inverse stage (with the projections where fused) and the separate passes
-    st32 = res["fp32"]["stages"]
+    st32 = res["fp32"].get("stages_full_planes", res["fp32"]["stages"])
     cand = {"stage 1": ("k_pencil<float2,7,16> (z FFT, dyadic kernel, stack response)", st32[1]["us"],
                         st32[1]["bytes"])}
     if fused_upd:

@@ -858,8 +858,9 @@ __host__ __device__ constexpr int pencil_threads_ct(int lpz, int bx) {
 // (partner + sign * own). Forward: lane q receives X_brev(q) =
 // sum_p W4^(p brev(q)) Y_p (brev: the 2-bit reversal); inverse: lane q holds
 // X_brev(q) and receives Z_q = sum_m W4^(-q m) X_m.
+// (every source lane of a quad permutation is valid, so no old value is needed)
 template <int CTRL> PSFD_D float quad_perm_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL> PSFD_D float2 quad_bfly(float2 v, float sg) {
   float2 r;
