@@ -184,7 +184,7 @@ int psfd_bench_stage(psfd_plan* plan, int stage, const void* d_deps, const void*
                           nullptr, 0, nullptr, qp);
     else
       apply_stage<double2>(g, stage, (const double2*)d_deps, vr(d_x), vr(d_y), (double2*)scratch, 0, 0, 1,
-                           nullptr, s);
+                           nullptr, s, nullptr, 0, nullptr, qp);
   }
   (void)hipEventRecord(e1, s);
   hipError_t e = hipEventSynchronize(e1);

@@ -417,7 +417,7 @@ static TileArgs tile_base(const Group& g, const void* tw, const TileShape& t) {
 
 bool quarter_planes(const Group& g, size_t esz) {
   const Shape& sh = g.sh;
-  if (esz != 8 || !xy_config(sh, esz).fused || env_int("PSFD_QUARTER_PLANES", 1) == 0) return false;
+  if ((esz != 8 && esz != 16) || env_int("PSFD_QUARTER_PLANES", 1) == 0) return false;
   const ZCfg z = z_config(sh, esz);
   return qplane_shape(sh.nx, sh.ny, sh.nz, sh.pz, z.bx, z.nthr);
 }
@@ -431,19 +431,19 @@ void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* w
   const int np = 3 * sh.nz;
   const T* tw = twiddles<T>(g);
   VecRef wsr = vr(ws, sh.n3);
-  if (qp && (gt || !quarter_planes(g, sizeof(T)))) {
+  if (qp && !quarter_planes(g, sizeof(T))) {
     std::fprintf(stderr, "psfd: internal error: quarter-plane apply stage on an unsupported shape\n");
     std::abort();
   }
   if (stage == 0) {
     // forward: w = FFT_xy(k0^2 delta_eps x)
     if (qp) {
-      if constexpr (sizeof(T) == 8) {
-        TileArgs a = tile_base(g, tw, c.full);
-        a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
-        a.in_scale = in_scale; a.scale_stride = scale_stride;
-        launch_qplane<T, false, LD_VX, ST_PLAIN>(a, np, g.B, s);
-      }
+      // a pending Givens step takes a launch of its own first
+      if (gt) krylov_givens(gt->st, gt->run, gt->part, g.B, s);
+      TileArgs a = tile_base(g, tw, c.full);
+      a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
+      a.in_scale = in_scale; a.scale_stride = scale_stride;
+      launch_qplane<T, false, LD_VX, ST_PLAIN>(a, np, g.B, s);
     } else if (c.fused) {
       TileArgs a = tile_base(g, tw, c.full);
       a.in = in; a.vol = vr(deps, sh.N); a.out = wsr; a.active = active;
@@ -479,12 +479,10 @@ void apply_stage(Group& g, int stage, const T* deps, VecRef in, VecRef out, T* w
   } else {
     // inverse: out = in - IFFT_xy(w) (kmode 0) or out = IFFT_xy(w) (kmode 1, no read of in)
     if (qp) {
-      if constexpr (sizeof(T) == 8) {
-        TileArgs a = tile_base(g, tw, c.full);
-        a.in = wsr; a.aux = in; a.out = out; a.alpha = 1.0; a.gamma = -1.0; a.active = active;
-        if (kmode == 0) launch_qplane<T, true, LD_PLAIN, ST_AXPBY>(a, np, g.B, s);
-        else launch_qplane<T, true, LD_PLAIN, ST_PLAIN>(a, np, g.B, s);
-      }
+      TileArgs a = tile_base(g, tw, c.full);
+      a.in = wsr; a.aux = in; a.out = out; a.alpha = 1.0; a.gamma = -1.0; a.active = active;
+      if (kmode == 0) launch_qplane<T, true, LD_PLAIN, ST_AXPBY>(a, np, g.B, s);
+      else launch_qplane<T, true, LD_PLAIN, ST_PLAIN>(a, np, g.B, s);
     } else if (c.fused) {
       TileArgs a = tile_base(g, tw, c.full);
       a.in = wsr; a.aux = in; a.out = out; a.alpha = 1.0; a.gamma = -1.0; a.active = active;
@@ -510,8 +508,8 @@ template <class T>
 void apply_op(Group& g, const T* deps, VecRef in, VecRef out, T* ws, int kmode, int transpose, int refl,
               const int* active, hipStream_t s, const double* in_scale, long long scale_stride,
               const GivensTask* gt) {
-  // the quarter-plane kernels where the shape takes them (no Givens step to carry)
-  const bool qp = !gt && quarter_planes(g, sizeof(T));
+  // the quarter-plane kernels where the shape takes them
+  const bool qp = quarter_planes(g, sizeof(T));
   for (int stage = 0; stage < 3; ++stage)
     apply_stage<T>(g, stage, deps, in, out, ws, kmode, transpose, refl, active, s, in_scale, scale_stride,
                    stage == 0 ? gt : nullptr, qp);
@@ -702,7 +700,7 @@ static bool fuse_update(const Group& g, size_t esz) {
 // projection partials of the new vector (fuse_dots), false when the separate
 // projection pass must follow.
 template <class T>
-static bool arnoldi_inverse(Group& g, VecRef vout, int jh, hipStream_t s) {
+static bool arnoldi_inverse(Group& g, VecRef vout, int jh, hipStream_t s, bool qp = false) {
   T* ws = (T*)g.wsP;
   if constexpr (std::is_same<T, float2>::value) {
     if (fuse_dots(g, sizeof(T))) {
@@ -715,7 +713,7 @@ static bool arnoldi_inverse(Group& g, VecRef vout, int jh, hipStream_t s) {
       return true;
     }
   }
-  apply_stage<T>(g, 2, (const T*)nullptr, vout, vout, ws, 1, 0, 0, g.run, s);
+  apply_stage<T>(g, 2, (const T*)nullptr, vout, vout, ws, 1, 0, 0, g.run, s, nullptr, 0, nullptr, qp);
   return false;
 }
 
@@ -862,12 +860,16 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
     const GivensTask gp{g.st, g.run, g.part, np};
     apply_stage<T>(g, 1, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, nullptr, 0,
                    jh > 0 ? &gp : nullptr);
-  } else {
-    apply_stage<T>(g, 0, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, isc, iss,
-                   lock && jh > 0 ? &gt : nullptr);
-    apply_stage<T>(g, 1, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s);
   }
-  if (!arnoldi_inverse<T>(g, vout, jh, s)) krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.B, s, jh);
+  // FP64 steps on 128 x 128 planes take the quarter-plane kernels (the FP32
+  // steps keep one block per plane, whose kernels carry the Gram-Schmidt work)
+  const bool qp = !upd && std::is_same<T, double2>::value && quarter_planes(g, sizeof(T));
+  if (!upd) {
+    apply_stage<T>(g, 0, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, isc, iss,
+                   lock && jh > 0 ? &gt : nullptr, qp);
+    apply_stage<T>(g, 1, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, nullptr, 0, nullptr, qp);
+  }
+  if (!arnoldi_inverse<T>(g, vout, jh, s, qp)) krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.B, s, jh);
   // with the fused update, the last column of a cycle takes no update pass: its
   // Givens step uses the projections alone, and slot m keeps w (the restart's
   // residual coefficients fold the update in)

@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
 }
 
 // -------------------------------------------------------------------------
-// Quarter-plane kernels (FP32 128 x 128 planes, operator apply). The
+// Quarter-plane kernels (128 x 128 planes, operator apply). The
 // transverse transform of a plane is split four ways over y: block q of a
 // plane takes the rows y = 4 r + q (r < 32), transforms them along x (128
 // points) and along r (32 points), and stores the quarter spectrum times its
@@ -467,16 +467,21 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
 // in 32-byte pieces, (q, ky', kx) at qp_index(ky', kx, q), so that the 16 values
 // a pencil block takes at one (component, z) form one 128-byte line.
 // -------------------------------------------------------------------------
-constexpr int QP_N = 128, QP_ROWS = 32, QP_THREADS = 256;
+constexpr int QP_N = 128, QP_ROWS = 32;
+// threads of a quarter-plane block: 16 values each in FP32 (row passes of radix
+// 16 and 8), 8 in FP64 (radix 8, 8 and 2); the column passes take radix 8 and 4
+template <class T> struct QpShape {
+  static constexpr int NT = sizeof(T) == 8 ? 256 : 512, KT = QP_ROWS * QP_N / NT, LRM_ROWS = sizeof(T) == 8 ? 4 : 3;
+};
 __host__ __device__ constexpr size_t qplane_lds(size_t esz) {
   return ((size_t)QP_ROWS * (QP_N + 1) + QP_N + QP_ROWS) * esz;
 }
 PSFD_D int qp_index(int kyq, int kx, int q) { return kyq * (4 * QP_N) + (kx >> 2) * 16 + 4 * q + (kx & 3); }
 
 template <class T, bool INV, int LD, int ST>
-__global__ void __launch_bounds__(QP_THREADS) k_qplane(TileArgs a) {
-  constexpr int N = QP_N, P = N + 1, NT = QP_THREADS, KT = QP_ROWS * N / NT;
-  static_assert(sizeof(T) == 8 && KT == 16, "FP32, 16 values per thread");
+__global__ void __launch_bounds__(QpShape<T>::NT) k_qplane(TileArgs a) {
+  constexpr int N = QP_N, P = N + 1, NT = QpShape<T>::NT, KT = QpShape<T>::KT, TS = NT / N;
+  static_assert(KT * NT == QP_ROWS * N && NT % N == 0, "quarter-plane thread split");
   static_assert(!INV || LD == LD_PLAIN, "inverse: plain load");
   static_assert(INV || (LD == LD_VX && ST == ST_PLAIN), "forward: contrast multiply, plain store");
   extern __shared__ double2 smem_d[];
@@ -515,7 +520,7 @@ __global__ void __launch_bounds__(QP_THREADS) k_qplane(TileArgs a) {
   const T* aux = ST == ST_AXPBY ? vref<T>(a.aux, b) + poff : nullptr;
   // the column transform's last pass (radix 4, stride 8) leaves its results in
   // registers: butterfly i of the thread (column s = tid mod 128, index
-  // t = tid / 128 + 2 i) forms rows r = t + 8 j of that column
+  // t = tid / 128 + (NT / 128) i) forms rows r = t + 8 j of that column
   constexpr int RL = 4, PL = 8, NBL = KT / RL;
   T va[KT], vb[INV ? 1 : KT], xa[ST == ST_AXPBY ? KT : 1];
 #pragma unroll
@@ -533,7 +538,7 @@ __global__ void __launch_bounds__(QP_THREADS) k_qplane(TileArgs a) {
     for (int i = 0; i < NBL; ++i)
 #pragma unroll
       for (int j = 0; j < RL; ++j) {
-        const int r = (tid >> 7) + 2 * i + PL * j, x = tid & (N - 1);
+        const int r = (tid >> 7) + TS * i + PL * j, x = tid & (N - 1);
         xa[i * RL + j] = aux[(4 * r + q) * N + x];
       }
   }
@@ -555,7 +560,7 @@ __global__ void __launch_bounds__(QP_THREADS) k_qplane(TileArgs a) {
   __syncthreads();
   typedef FftCT<7, QP_ROWS, P, 1, NT> Rows;  // 32 rows of 128 points
   typedef FftCT<5, N, 1, P, NT> Cols;        // 128 columns of 32 points
-  lds_fft_tab<T, INV, true, KT, Rows, false, false, 4>(lds, Rows(), twl, tid);
+  lds_fft_tab<T, INV, true, KT, Rows, false, false, QpShape<T>::LRM_ROWS>(lds, Rows(), twl, tid);
   T res[KT];
   lds_fft_tab_regout<T, INV, true, KT, Cols, false, 3>(lds, Cols(), twl32, tid, res);
   T* out = vref<T>(a.out, b) + poff;
@@ -564,7 +569,7 @@ __global__ void __launch_bounds__(QP_THREADS) k_qplane(TileArgs a) {
   for (int i = 0; i < NBL; ++i)
 #pragma unroll
     for (int j = 0; j < RL; ++j) {
-      const int r = (tid >> 7) + 2 * i + PL * j, x = tid & (N - 1);
+      const int r = (tid >> 7) + TS * i + PL * j, x = tid & (N - 1);
       T v = res[i * RL + j];
       if constexpr (!INV) {
         out[qp_index(r, x, q)] = cmul(v, twl[q * r]);
@@ -582,18 +587,20 @@ __global__ void __launch_bounds__(QP_THREADS) k_qplane(TileArgs a) {
 
 template <class T, bool INV, int LD, int ST>
 void launch_qplane(const TileArgs& a, int nplanes, int nbatch, hipStream_t s) {
-  if constexpr (sizeof(T) == 8) {
-    if (a.nx != QP_N || a.ny != QP_N || a.gv.st || nplanes != 3 * a.nz) {
-      std::fprintf(stderr, "psfd: internal error: quarter-plane launch on an unsupported shape\n");
-      std::abort();
-    }
-    hipLaunchKernelGGL((k_qplane<T, INV, LD, ST>), dim3(4 * nplanes, nbatch), dim3(QP_THREADS),
-                       qplane_lds(sizeof(T)), s, a);
+  if (a.nx != QP_N || a.ny != QP_N || a.gv.st || nplanes != 3 * a.nz) {
+    std::fprintf(stderr, "psfd: internal error: quarter-plane launch on an unsupported shape\n");
+    std::abort();
   }
+  const size_t l = qplane_lds(sizeof(T));
+  allow_lds(reinterpret_cast<const void*>(&k_qplane<T, INV, LD, ST>), l);
+  hipLaunchKernelGGL((k_qplane<T, INV, LD, ST>), dim3(4 * nplanes, nbatch), dim3(QpShape<T>::NT), l, s, a);
 }
 template void launch_qplane<float2, false, LD_VX, ST_PLAIN>(const TileArgs&, int, int, hipStream_t);
 template void launch_qplane<float2, true, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, hipStream_t);
 template void launch_qplane<float2, true, LD_PLAIN, ST_AXPBY>(const TileArgs&, int, int, hipStream_t);
+template void launch_qplane<double2, false, LD_VX, ST_PLAIN>(const TileArgs&, int, int, hipStream_t);
+template void launch_qplane<double2, true, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, hipStream_t);
+template void launch_qplane<double2, true, LD_PLAIN, ST_AXPBY>(const TileArgs&, int, int, hipStream_t);
 
 // -------------------------------------------------------------------------
 // Strip kernel: for square N x N planes too large for LDS, the x-FFT of
@@ -862,29 +869,34 @@ __host__ __device__ constexpr int pencil_threads_ct(int lpz, int bx) {
 template <int CTRL> PSFD_D float quad_perm_f(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
-template <int CTRL> PSFD_D float2 quad_bfly(float2 v, float sg) {
-  float2 r;
+// a double moves as its two 32-bit halves
+template <int CTRL> PSFD_D double quad_perm_f(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int CTRL, class T> PSFD_D T quad_bfly(T v, typename real_of<T>::type sg) {
+  T r;
   r.x = quad_perm_f<CTRL>(v.x) + sg * v.x;
   r.y = quad_perm_f<CTRL>(v.y) + sg * v.y;
   return r;
 }
 constexpr int DPP_QUAD_SWAP2 = 0x4E;  // quad_perm [2, 3, 0, 1]
 constexpr int DPP_QUAD_SWAP1 = 0xB1;  // quad_perm [1, 0, 3, 2]
-PSFD_D float2 quad_dft4_fwd(float2 v, int q) {
-  v = quad_bfly<DPP_QUAD_SWAP2>(v, q < 2 ? 1.f : -1.f);
-  if (q == 3) v = make_float2(v.y, -v.x);  // times -i
-  return quad_bfly<DPP_QUAD_SWAP1>(v, (q & 1) ? -1.f : 1.f);
+template <class T> PSFD_D T quad_dft4(T v, int q, bool inv) {
+  typedef typename real_of<T>::type R;
+  const R s2 = q < 2 ? (R)1 : (R)-1, s1 = (q & 1) ? (R)-1 : (R)1;
+  T r;
+  if (!inv) {
+    v = quad_bfly<DPP_QUAD_SWAP2>(v, s2);
+    if (q == 3) { r.x = v.y; r.y = -v.x; v = r; }  // times -i
+    return quad_bfly<DPP_QUAD_SWAP1>(v, s1);
+  }
+  v = quad_bfly<DPP_QUAD_SWAP1>(v, s1);
+  if (q == 3) { r.x = -v.y; r.y = v.x; v = r; }  // times +i
+  return quad_bfly<DPP_QUAD_SWAP2>(v, s2);
 }
-PSFD_D float2 quad_dft4_inv(float2 v, int q) {
-  v = quad_bfly<DPP_QUAD_SWAP1>(v, (q & 1) ? -1.f : 1.f);
-  if (q == 3) v = make_float2(-v.y, v.x);  // times +i
-  return quad_bfly<DPP_QUAD_SWAP2>(v, q < 2 ? 1.f : -1.f);
-}
-template <class T> PSFD_D T quad_dft4(T v, int q, bool inv);
-template <> PSFD_D float2 quad_dft4<float2>(float2 v, int q, bool inv) {
-  return inv ? quad_dft4_inv(v, q) : quad_dft4_fwd(v, q);
-}
-template <> PSFD_D double2 quad_dft4<double2>(double2 v, int, bool) { return v; }  // not instantiated with YQ
 // pencil column c of a quarter-layout block: kx = kx0 + c / 4 and quarter
 // q = c mod 4 on load (position 4 q + c / 4 of the block's 16-value piece), row
 // ky' + (ny / 4) brev(q) after the combine
@@ -912,7 +924,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   }
   if (a.active && !a.active[b]) return;
   const int bx = LPZ ? BXC : a.bx, pz = LPZ ? (1 << LPZ) : a.pz, nz = pz / 2, nx = a.nx, ny = a.ny;
-  static_assert(!YQ || (LPZ > 0 && BXC == 16 && sizeof(T) == 8), "quarter layout: FP32 compile-time pencils");
+  static_assert(!YQ || (LPZ > 0 && BXC == 16), "quarter layout: compile-time pencils");
   const int ky = blockIdx.x / a.nblk_x;  // YQ: the quarter-spectrum row ky'
   const int kx0 = (blockIdx.x - ky * a.nblk_x) * (YQ ? 4 : bx);
   const int tid = threadIdx.x, nthr = LPZ ? pencil_threads_ct(LPZ, BXC) : (int)blockDim.x;
@@ -1195,10 +1207,8 @@ void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStr
     hipLaunchKernelGGL(kern, grid, dim3(nthr), lds, s, a);
   };
   if (a.yq) {
-    if constexpr (sizeof(T) == 8) {
-      if (a.bx == 16 && a.pz == 128 && nthr == pencil_threads_ct(7, 16)) return go(k_pencil<T, 7, 16, true>);
-      if (a.bx == 16 && a.pz == 64 && nthr == pencil_threads_ct(6, 16)) return go(k_pencil<T, 6, 16, true>);
-    }
+    if (a.bx == 16 && a.pz == 128 && nthr == pencil_threads_ct(7, 16)) return go(k_pencil<T, 7, 16, true>);
+    if (a.bx == 16 && a.pz == 64 && nthr == pencil_threads_ct(6, 16)) return go(k_pencil<T, 6, 16, true>);
     std::fprintf(stderr, "psfd: internal error: quarter-plane pencil on an unsupported shape\n");
     std::abort();
   }

@@ -19,8 +19,8 @@ pytestmark = pytest.mark.gpu
 # (128, 128, 4): square-plane kernel in FP32, row/column strips in FP64;
 # (256, 256, 2): strips in both precisions; (16, 16, 32) and (16, 8, 64): the
 # z-pencil with compile-time padded lengths 64 and 128; (128, 128, 32) and
-# (128, 128, 64): in FP32 the quarter-plane kernels with the quarter-layout
-# pencil at both compile-time lengths
+# (128, 128, 64): the quarter-plane kernels with the quarter-layout pencil at
+# both compile-time lengths, in both precisions
 SHAPES = [
     (4, 4, 2), (8, 8, 4), (16, 8, 8), (32, 32, 16), (64, 32, 8), (128, 128, 4), (256, 64, 2), (64, 256, 2),
     (256, 256, 2), (16, 16, 32), (16, 8, 64), (128, 128, 32), (128, 128, 64),
@@ -89,27 +89,31 @@ def test_coupled_apply_matches_oracle(shape, dtype):
     assert rel(yt, reft) < tol, rel(yt, reft)
 
 
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("nz", [32, 64])
-def test_quarter_planes_match_full_planes(nz, monkeypatch):
-    """FP32 128 x 128 planes: the quarter-plane kernels (four blocks per plane,
-    the radix-4 y combine in the pencil) against the one-block-per-plane
-    kernels, in every apply variant (plain, K only, transposed, coupled)."""
+def test_quarter_planes_match_full_planes(nz, dtype, monkeypatch):
+    """128 x 128 planes: the quarter-plane kernels (four blocks per plane, the
+    radix-4 y combine in the pencil) against the one-block-per-plane kernels
+    (FP32) or the row and column strips (FP64), in every apply variant (plain,
+    K only, transposed, coupled)."""
     from paper_2606_25541_amd import api
     dev = device()
-    say("quarter vs full planes", nz)
+    say("quarter vs full planes", nz, dtype)
     p = make(128, 128, nz, phi=10.0)
     de = clips.manhattan(128, 128, nz, p.lx_nm, p.ly_nm, seed=nz + 5)
     x = clips.random_complex((3, nz, 128, 128), seed=29)
     plan = api.Plan(p)
-    dd = torch.from_numpy(de).to(dev, torch.complex64)
-    xx = torch.from_numpy(x).to(dev, torch.complex64)
+    td = torch.complex64 if dtype == "c64" else torch.complex128
+    dd = torch.from_numpy(de).to(dev, td)
+    xx = torch.from_numpy(x).to(dev, td)
     variants = [{}, {"k_only": True}, {"transpose": True}, {"reflect": True}, {"reflect": True, "transpose": True}]
     ys = {}
     for q in ("1", "0"):
         monkeypatch.setenv("PSFD_QUARTER_PLANES", q)
         ys[q] = [plan.psfd_apply(dd, xx, **v).cpu().numpy() for v in variants]
+    tol = 1e-6 if dtype == "c64" else 1e-13
     for v, a, b in zip(variants, ys["1"], ys["0"]):
-        assert rel(a, b) < 1e-6, (v, rel(a, b))
+        assert rel(a, b) < tol, (v, rel(a, b))
 
 
 def test_apply_is_deterministic():
