@@ -659,11 +659,12 @@ Status replay(Group& g, Group::Captured& c, const std::string& key, hipStream_t 
 }
 
 std::string launch_key(double eta, int every) {
-  char buf[160];
+  char buf[192];
   const char* d = std::getenv("PSFD_FUSE_DOTS");
   const char* u = std::getenv("PSFD_FUSE_UPDATE");
-  std::snprintf(buf, sizeof(buf), "%.17g|%.17g|%d|%s|%s", cancel_threshold(), eta, every, d ? d : "-",
-                u ? u : "-");
+  const char* q = std::getenv("PSFD_QUARTER_PLANES");
+  std::snprintf(buf, sizeof(buf), "%.17g|%.17g|%d|%s|%s|%s", cancel_threshold(), eta, every, d ? d : "-",
+                u ? u : "-", q ? q : "-");
   return buf;
 }
 
