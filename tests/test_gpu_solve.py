@@ -152,6 +152,34 @@ def test_update_in_forward_plane_kernel_matches_separate_pass(n, monkeypatch):
     assert np.max(np.abs(o1.cpu().numpy() - o2.cpu().numpy())) < 1e-9
 
 
+def test_fp64_solve_quarter_planes_match_strips(monkeypatch):
+    """128 x 128 x 32, FP64, lock-step: the Arnoldi steps and b - A x on quarter
+    planes (four blocks per plane, the radix-4 y combine in the pencil) against
+    the row and column strips (PSFD_QUARTER_PLANES=0), in one process: the
+    switch is part of the captured restart cycle's key, so the second solve
+    captures the strip kernels instead of replaying the quarter-plane ones. Both
+    reach the tolerance and the same field to the conditioning times it."""
+    from paper_2606_25541_amd import api
+    dev = device()
+    layers, es = clips.mo_si_stack(40)
+    p = clips.Problem(nx=128, ny=128, nz=32, lx_nm=256.0, ly_nm=256.0, t_nm=60.0, theta_deg=6.0,
+                      phi_deg=15.0, pol=0, layers=layers, eps_sub=es)
+    d = torch.from_numpy(clips.contact_holes(128, 128, 32, 256.0, 256.0, 6, seed=91)).to(dev)
+    say("solve 128x128x32 fp64, quarter planes vs strips")
+    plan = api.Plan(p, rtol=1e-10, precision="fp64", restart=8)
+    e1, o1, i1 = plan.psfd_solve(d)
+    e1b, o1b, i1b = plan.psfd_solve(d)
+    monkeypatch.setenv("PSFD_QUARTER_PLANES", "0")
+    e2, o2, i2 = plan.psfd_solve(d)
+    say("  quarter", i1, "strips", i2)
+    assert i1["status"] == 0 and i2["status"] == 0
+    assert torch.equal(e1, e1b) and i1 == i1b
+    assert not torch.equal(e1, e2)  # the strip kernels ran: other rounding
+    assert abs(i1["iters"] - i2["iters"]) <= 2
+    assert rel(e1.cpu().numpy(), e2.cpu().numpy()) < 1e-8
+    assert np.max(np.abs(o1.cpu().numpy() - o2.cpu().numpy())) < 1e-9
+
+
 def test_fused_krylov_64_planes_matches_oracle_monolithic():
     """64 x 64 x 32, mixed, lock-step with the projections and the update inside
     the transform kernels, against the oracle: the oracle's GMRES on its
