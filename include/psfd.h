@@ -118,7 +118,11 @@ int psfd_plan_footprint(const psfd_plan* plan, size_t* device_bytes);
  * the negated wavevector); with PSFD_APPLY_REFLECT, K is replaced by the coupled
  * M = K + R_vol T_R K_top (free space plus the multilayer response of eq. (9)). d_deps [nz][ny][nx], d_x and d_y [3][nz][ny][nx], all of
  * `dtype` (complex64 or complex128), device memory; d_y must not alias d_x.
- * Uses a plan-owned scratch field (allocated on first use). */
+ * Uses a plan-owned scratch field (allocated on first use). On 128 x 128 planes
+ * with nz 32 or 64 the transverse transforms run split four ways over y (rows
+ * y = 4 r + q) and the z pencil combines the quarter spectra; the environment
+ * variable PSFD_QUARTER_PLANES=0 selects the one-kernel-per-plane (FP32) or
+ * strip (FP64) transforms instead (same results to rounding). */
 int psfd_apply(psfd_plan* plan, const void* d_deps, const void* d_x, void* d_y, int dtype, int flags,
                void* stream);
 
@@ -212,8 +216,9 @@ int psfd_server_destroy(psfd_server* srv);
  * the contrast multiply, 1: z-pencil FFT / dyadic kernel / inverse, 2: transverse
  * inverse FFT with the axpy) `reps` times back to back between two HIP events on
  * `stream` and store the mean time per launch in *ms. Same buffers as psfd_apply
- * (d_y receives stage 2's output; the plan scratch holds stages 0-1). For
- * throughput measurements; results of a lone stage are not an operator apply. */
+ * (d_y receives stage 2's output; the plan scratch holds stages 0-1), with the
+ * kernels psfd_apply takes for the shape. For throughput measurements; results of
+ * a lone stage are not an operator apply. */
 int psfd_bench_stage(psfd_plan* plan, int stage, const void* d_deps, const void* d_x, void* d_y, int dtype,
                      int reps, float* ms, void* stream);
 
