@@ -121,7 +121,7 @@ int psfd_plan_footprint(const psfd_plan* plan, size_t* device_bytes);
  * Uses a plan-owned scratch field (allocated on first use). On 128 x 128 planes
  * with nz 32 or 64 the transverse transforms run split four ways over y (rows
  * y = 4 r + q) and the z pencil combines the quarter spectra; the environment
- * variable PSFD_QUARTER_PLANES=0 selects the one-kernel-per-plane (FP32) or
+ * variable PSFD_QUARTER_PLANES=0 selects the one-block-per-plane (FP32) or
  * strip (FP64) transforms instead (same results to rounding). */
 int psfd_apply(psfd_plan* plan, const void* d_deps, const void* d_x, void* d_y, int dtype, int flags,
                void* stream);
