@@ -64,14 +64,15 @@ def test_batch_equals_single():
         assert inf["iters"] == i1["iters"]
 
 
-@pytest.mark.parametrize("n", [64, 128])
-def test_batch_equals_single_128_planes(n):
+@pytest.mark.parametrize("n,prec", [(64, "mixed"), (128, "mixed"), (128, "fp64")])
+def test_batch_equals_single_128_planes(n, prec):
     """FP32 square planes (64 x 64 and 128 x 128), 32 per component (padded z length 64, pencil
     blocks large enough for the Givens task): the lock-step batch runs the
     Gram-Schmidt update in the forward plane kernel, the projections in the
-    inverse one and the last column's Givens step from the projections. Three
-    instances, one of which converges cycles before the others, must each equal
-    their lone solve bitwise."""
+    inverse one and the last column's Givens step from the projections. FP64 at
+    128 x 128: the Arnoldi steps on quarter planes with a separate Givens launch.
+    Three instances, one of which converges cycles before the others, must each
+    equal their lone solve bitwise."""
     from paper_2606_25541_amd import api
     dev = device()
     angles = clips.pupil_angles()
@@ -83,8 +84,8 @@ def test_batch_equals_single_128_planes(n):
         if i == 2:
             de = de * 0.25  # weaker contrast: converges in fewer cycles
         cs.append((p, de))
-    opts = dict(rtol=1e-9, precision="mixed", restart=8)
-    say("batch of 3 at %dx%dx32" % (n, n))
+    opts = dict(rtol=1e-9, precision=prec, restart=8)
+    say("batch of 3 at %dx%dx32 %s" % (n, n, prec))
     em, od, infos = api.psfd_solve_batch([c[0] for c in cs], [torch.from_numpy(c[1]).to(dev) for c in cs], **opts)
     torch.cuda.synchronize()
     iters = []
@@ -101,17 +102,19 @@ def test_batch_equals_single_128_planes(n):
     assert min(iters) < max(iters)
 
 
-@pytest.mark.parametrize("n", [64, 128])
-def test_server_matches_alone_128_planes(n):
+@pytest.mark.parametrize("n,prec", [(64, "mixed"), (128, "mixed"), (128, "fp64")])
+def test_server_matches_alone_128_planes(n, prec):
     """n x n x 32 (n = 64, 128), mixed: the lone (lock-step) solve and the server's slots
     (each at its own step, with a per-slot pending-update flag) run the same
     fused kernels: the Gram-Schmidt update in the forward plane kernel, the
     projections in the inverse one, the Givens step in the pencil and the last
-    column's from the projections. Two requests submitted apart, so that their
-    slots stand at different steps, each equal their lone solve bit for bit."""
+    column's from the projections. FP64 at 128 x 128: the quarter-plane steps,
+    the Givens step in its own launch (lone) or in the update pass (slots).
+    Two requests submitted apart, so that their slots stand at different steps,
+    each equal their lone solve bit for bit."""
     from paper_2606_25541_amd import api
     dev = device()
-    opts = dict(rtol=1e-10, precision="mixed", restart=8)
+    opts = dict(rtol=1e-10, precision=prec, restart=8)
     reqs = []
     for i, (th, ph, pol) in enumerate(((6.0, 0.0, 0), (7.5, 40.0, 1))):
         p = prob(n, 32, th, ph, pol)
