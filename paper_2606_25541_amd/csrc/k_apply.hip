@@ -1011,6 +1011,18 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     if (a.transpose) { mq = (nx - mq) & (nx - 1); nq = (ny - nq) & (ny - 1); }
   };
   if (LPZ > 0 && tid < pz) twl[tid] = reinterpret_cast<const T*>(a.tw)[pz + tid];
+  // the stack response's row r of M (or of M^T) for column kxl, thread tid =
+  // r bx + kxl < 3 bx: requested now, so that its latency overlaps the data
+  // loads instead of following the readout's barriers
+  double2 mrow[3];
+  if (a.reflect && tid < 3 * bx) {
+    const int kxl = tid % bx, r = tid / bx;
+    int mq, nq;
+    order_of(kxl, mq, nq);
+    const double2* M = reinterpret_cast<const double2*>(tab + L.off_mono()) + 9LL * (nq * nx + mq);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mrow[c] = a.transpose ? M[3 * c + r] : M[3 * r + c];
+  }
   if (tid < bx) {
     int mq, nq;
     order_of(tid, mq, nq);
@@ -1075,11 +1087,9 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     if (tid < 3 * bx) {
       // row r of M (or of M^T) times the summed readouts of column kxl
       const int kxl = tid % bx, r = tid / bx;
-      int mq, nq;
-      order_of(kxl, mq, nq);
-      const double2* M = reinterpret_cast<const double2*>(tab + L.off_mono()) + 9LL * (nq * nx + mq);
       double2 o = make_double2(0, 0);
-      for (int c = 0; c < 3; ++c) o = cadd(o, cmul(a.transpose ? M[3 * c + r] : M[3 * r + c], part[c * bx + kxl]));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) o = cadd(o, cmul(mrow[c], part[c * bx + kxl]));
       eupT[kxl * 3 + r] = from_d<T>(o);
     }
   }
