@@ -419,7 +419,7 @@ bool quarter_planes(const Group& g, size_t esz) {
   const Shape& sh = g.sh;
   if ((esz != 8 && esz != 16) || env_int("PSFD_QUARTER_PLANES", 1) == 0) return false;
   const ZCfg z = z_config(sh, esz);
-  return qplane_shape(sh.nx, sh.ny, sh.nz, sh.pz, z.bx, z.nthr);
+  return qplane_shape(sh.nx, sh.ny, sh.nz, sh.pz, z.bx, z.nthr, esz);
 }
 
 template <class T>
@@ -862,9 +862,12 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
     apply_stage<T>(g, 1, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, nullptr, 0,
                    jh > 0 ? &gp : nullptr);
   }
-  // FP64 steps on 128 x 128 planes take the quarter-plane kernels (the FP32
-  // steps keep one block per plane, whose kernels carry the Gram-Schmidt work)
-  const bool qp = !upd && std::is_same<T, double2>::value && quarter_planes(g, sizeof(T));
+  // steps on planes the quarter split takes run the quarter-plane kernels,
+  // except where the one-block-per-plane kernels carry the Gram-Schmidt work
+  // (FP32 128 x 128: the update in the forward kernel, the projections in the
+  // inverse one)
+  const bool qp = !upd && quarter_planes(g, sizeof(T)) &&
+                  (std::is_same<T, double2>::value || !fuse_dots(g, sizeof(T)));
   if (!upd) {
     apply_stage<T>(g, 0, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, isc, iss,
                    lock && jh > 0 ? &gt : nullptr, qp);

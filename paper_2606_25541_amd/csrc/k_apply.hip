@@ -449,45 +449,51 @@ __global__ void __launch_bounds__(plane_threads(LN)) k_plane(TileArgs a) {
 }
 
 // -------------------------------------------------------------------------
-// Quarter-plane kernels (128 x 128 planes, operator apply). The
-// transverse transform of a plane is split four ways over y: block q of a
-// plane takes the rows y = 4 r + q (r < 32), transforms them along x (128
-// points) and along r (32 points), and stores the quarter spectrum times its
-// twiddle, Y'_q(ky', kx) = W128^(q ky') Y_q(ky', kx), ky' < 32. The full
+// Quarter-plane kernels (N x N planes, N = 128, and 256 in FP32; operator
+// apply). The transverse transform of a plane is split four ways over y: block
+// q of a plane takes the rows y = 4 r + q (r < N / 4), transforms them along x
+// (N points) and along r (N / 4 points), and stores the quarter spectrum times
+// its twiddle, Y'_q(ky', kx) = W_N^(q ky') Y_q(ky', kx), ky' < N / 4. The full
 // spectrum is the radix-4 decimation-in-time combine
-//   X(ky' + 32 m, kx) = sum_q W4^(q m) Y'_q(ky', kx),
+//   X(ky' + (N / 4) m, kx) = sum_q W4^(q m) Y'_q(ky', kx),
 // a twiddle-free 4-point DFT that the z-pencil kernel takes on load. Back the
-// same way: the pencil stores Z'_q = sum_m W4^(-q m) X(ky' + 32 m), and block q
-// multiplies by W128^(-q ky') and transforms along r and x back to the rows
-// y = 4 r + q. Four blocks per plane (768 at 192 planes) keep every CU busy
-// with three resident blocks whose loads and FFT passes overlap; one block per
-// plane leaves 64 of 256 CUs idle and runs each CU's load, transform and store
-// one after the other.
+// same way: the pencil stores Z'_q = sum_m W4^(-q m) X(ky' + (N / 4) m), and
+// block q multiplies by W_N^(-q ky') and transforms along r and x back to the
+// rows y = 4 r + q. At N = 128, four blocks per plane (768 at 192 planes) keep
+// every CU busy with three resident blocks whose loads and FFT passes overlap;
+// one block per plane leaves 64 of 256 CUs idle and runs each CU's load,
+// transform and store one after the other. At N = 256 (FP32) a quarter plane
+// is one block per CU, and the transform is one pass through HBM where the
+// row and column strips take two.
 // Layout between the kernels, per plane: the four quarter spectra interleaved
-// in 32-byte pieces, (q, ky', kx) at qp_index(ky', kx, q), so that the 16 values
-// a pencil block takes at one (component, z) form one 128-byte line.
+// in 32-byte pieces, (q, ky', kx) at qp_index<N>(ky', kx, q), so that the 16
+// values a pencil block takes at one (component, z) form one 128-byte line.
 // -------------------------------------------------------------------------
-constexpr int QP_N = 128, QP_ROWS = 32;
-// threads of a quarter-plane block: 16 values each in FP32 (row passes of radix
-// 16 and 8), 8 in FP64 (radix 8, 8 and 2); the column passes take radix 8 and 4
-template <class T> struct QpShape {
-  static constexpr int NT = sizeof(T) == 8 ? 256 : 512, KT = QP_ROWS * QP_N / NT, LRM_ROWS = sizeof(T) == 8 ? 4 : 3;
+// threads of a quarter-plane block: 16 values each in FP32 (rows of 128 by radix
+// 16 and 8, of 256 by 16 and 16), 8 in FP64 (radix 8, 8 and 2); the column
+// passes take radix 8, then 4 (N / 4 = 32) or 8 (N / 4 = 64)
+template <class T, int LN> struct QpShape {
+  static constexpr int N = 1 << LN, ROWS = N / 4;
+  static constexpr int NT = sizeof(T) == 16 ? 512 : (LN == 7 ? 256 : 1024), KT = ROWS * N / NT;
+  static constexpr int LRM_ROWS = sizeof(T) == 8 ? 4 : 3;
+  static constexpr int LRL = (LN - 3) % 3 + 1, RL = 1 << LRL;  // last column pass: radix RL
 };
-__host__ __device__ constexpr size_t qplane_lds(size_t esz) {
-  return ((size_t)QP_ROWS * (QP_N + 1) + QP_N + QP_ROWS) * esz;
+__host__ __device__ constexpr size_t qplane_lds(int ln, size_t esz) {
+  return ((size_t)((1 << ln) / 4) * ((1 << ln) + 1) + (1 << ln) + (1 << ln) / 4) * esz;
 }
-PSFD_D int qp_index(int kyq, int kx, int q) { return kyq * (4 * QP_N) + (kx >> 2) * 16 + 4 * q + (kx & 3); }
+template <int N> PSFD_D int qp_index(int kyq, int kx, int q) { return kyq * (4 * N) + (kx >> 2) * 16 + 4 * q + (kx & 3); }
 
-template <class T, bool INV, int LD, int ST>
-__global__ void __launch_bounds__(QpShape<T>::NT) k_qplane(TileArgs a) {
-  constexpr int N = QP_N, P = N + 1, NT = QpShape<T>::NT, KT = QpShape<T>::KT, TS = NT / N;
+template <class T, bool INV, int LD, int ST, int LN>
+__global__ void __launch_bounds__((QpShape<T, LN>::NT)) k_qplane(TileArgs a) {
+  typedef QpShape<T, LN> S;
+  constexpr int N = S::N, QP_ROWS = S::ROWS, P = N + 1, NT = S::NT, KT = S::KT, TS = NT / N;
   static_assert(KT * NT == QP_ROWS * N && NT % N == 0, "quarter-plane thread split");
   static_assert(!INV || LD == LD_PLAIN, "inverse: plain load");
   static_assert(INV || (LD == LD_VX && ST == ST_PLAIN), "forward: contrast multiply, plain store");
   extern __shared__ double2 smem_d[];
   T* lds = reinterpret_cast<T*>(smem_d);
-  T* twl = lds + QP_ROWS * P;  // W128^k, k < 128
-  T* twl32 = twl + N;          // W32^k = W128^(4 k), k < 32
+  T* twl = lds + QP_ROWS * P;  // W_N^k, k < N
+  T* twl32 = twl + N;          // W_(N/4)^k = W_N^(4 k), k < N / 4
   const int b = blockIdx.y;
   if (a.active && !a.active[b]) return;
   // block order: with 8 | nz, XCD x (= hw mod 8) takes the planes z = x mod 8 of
@@ -518,19 +524,21 @@ __global__ void __launch_bounds__(QpShape<T>::NT) k_qplane(TileArgs a) {
   const T* in = vref<T>(a.in, b) + poff;
   const T* vol = INV ? nullptr : vref<T>(a.vol, b) + (long long)z * N * N;
   const T* aux = ST == ST_AXPBY ? vref<T>(a.aux, b) + poff : nullptr;
-  // the column transform's last pass (radix 4, stride 8) leaves its results in
-  // registers: butterfly i of the thread (column s = tid mod 128, index
-  // t = tid / 128 + (NT / 128) i) forms rows r = t + 8 j of that column
-  constexpr int RL = 4, PL = 8, NBL = KT / RL;
+  // the column transform's last pass (radix RL, stride PL = N / 4 / RL = 8)
+  // leaves its results in registers: butterfly i of the thread (column
+  // s = tid mod N, index t = tid / N + (NT / N) i) forms rows r = t + PL j of
+  // that column
+  constexpr int RL = S::RL, PL = QP_ROWS / RL, NBL = KT / RL;
+  static_assert(PL == 8 && NBL * RL == KT, "quarter-plane last column pass");
   T va[KT], vb[INV ? 1 : KT], xa[ST == ST_AXPBY ? KT : 1];
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
-    const int i = tid + k * NT, r = i >> 7, x = i & (N - 1);
+    const int i = tid + k * NT, r = i >> LN, x = i & (N - 1);
     if constexpr (!INV) {
       va[k] = in[(4 * r + q) * N + x];
       vb[k] = vol[(4 * r + q) * N + x];
     } else {
-      va[k] = in[qp_index(r, x, q)];
+      va[k] = in[qp_index<N>(r, x, q)];
     }
   }
   if constexpr (ST == ST_AXPBY) {
@@ -538,7 +546,7 @@ __global__ void __launch_bounds__(QpShape<T>::NT) k_qplane(TileArgs a) {
     for (int i = 0; i < NBL; ++i)
 #pragma unroll
       for (int j = 0; j < RL; ++j) {
-        const int r = (tid >> 7) + TS * i + PL * j, x = tid & (N - 1);
+        const int r = (tid >> LN) + TS * i + PL * j, x = tid & (N - 1);
         xa[i * RL + j] = aux[(4 * r + q) * N + x];
       }
   }
@@ -551,16 +559,16 @@ __global__ void __launch_bounds__(QpShape<T>::NT) k_qplane(TileArgs a) {
   if constexpr (INV) __syncthreads();
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
-    const int i = tid + k * NT, r = i >> 7;
+    const int i = tid + k * NT, r = i >> LN;
     T v;
     if constexpr (INV) v = cmulc(va[k], twl[q * r]);
     else v = cscale(cmul(vb[k], va[k]), ks);
     lds[r * P + (i & (N - 1))] = v;
   }
   __syncthreads();
-  typedef FftCT<7, QP_ROWS, P, 1, NT> Rows;  // 32 rows of 128 points
-  typedef FftCT<5, N, 1, P, NT> Cols;        // 128 columns of 32 points
-  lds_fft_tab<T, INV, true, KT, Rows, false, false, QpShape<T>::LRM_ROWS>(lds, Rows(), twl, tid);
+  typedef FftCT<LN, QP_ROWS, P, 1, NT> Rows;  // N / 4 rows of N points
+  typedef FftCT<LN - 2, N, 1, P, NT> Cols;     // N columns of N / 4 points
+  lds_fft_tab<T, INV, true, KT, Rows, false, false, S::LRM_ROWS>(lds, Rows(), twl, tid);
   T res[KT];
   lds_fft_tab_regout<T, INV, true, KT, Cols, false, 3>(lds, Cols(), twl32, tid, res);
   T* out = vref<T>(a.out, b) + poff;
@@ -569,10 +577,10 @@ __global__ void __launch_bounds__(QpShape<T>::NT) k_qplane(TileArgs a) {
   for (int i = 0; i < NBL; ++i)
 #pragma unroll
     for (int j = 0; j < RL; ++j) {
-      const int r = (tid >> 7) + TS * i + PL * j, x = tid & (N - 1);
+      const int r = (tid >> LN) + TS * i + PL * j, x = tid & (N - 1);
       T v = res[i * RL + j];
       if constexpr (!INV) {
-        out[qp_index(r, x, q)] = cmul(v, twl[q * r]);
+        out[qp_index<N>(r, x, q)] = cmul(v, twl[q * r]);
       } else {
         if constexpr (ST == ST_AXPBY) {
           const T xv = xa[ST == ST_AXPBY ? i * RL + j : 0];
@@ -587,13 +595,20 @@ __global__ void __launch_bounds__(QpShape<T>::NT) k_qplane(TileArgs a) {
 
 template <class T, bool INV, int LD, int ST>
 void launch_qplane(const TileArgs& a, int nplanes, int nbatch, hipStream_t s) {
-  if (a.nx != QP_N || a.ny != QP_N || a.gv.st || nplanes != 3 * a.nz) {
+  const bool ok = a.nx == a.ny && (a.nx == 128 || (a.nx == 256 && sizeof(T) == 8));
+  if (!ok || a.gv.st || nplanes != 3 * a.nz) {
     std::fprintf(stderr, "psfd: internal error: quarter-plane launch on an unsupported shape\n");
     std::abort();
   }
-  const size_t l = qplane_lds(sizeof(T));
-  allow_lds(reinterpret_cast<const void*>(&k_qplane<T, INV, LD, ST>), l);
-  hipLaunchKernelGGL((k_qplane<T, INV, LD, ST>), dim3(4 * nplanes, nbatch), dim3(QpShape<T>::NT), l, s, a);
+  auto go = [&](auto kern, int ln, int nt) {
+    const size_t l = qplane_lds(ln, sizeof(T));
+    allow_lds(reinterpret_cast<const void*>(kern), l);
+    hipLaunchKernelGGL(kern, dim3(4 * nplanes, nbatch), dim3(nt), l, s, a);
+  };
+  if constexpr (sizeof(T) == 8) {
+    if (a.nx == 256) return go(k_qplane<T, INV, LD, ST, 8>, 8, QpShape<T, 8>::NT);
+  }
+  go(k_qplane<T, INV, LD, ST, 7>, 7, QpShape<T, 7>::NT);
 }
 template void launch_qplane<float2, false, LD_VX, ST_PLAIN>(const TileArgs&, int, int, hipStream_t);
 template void launch_qplane<float2, true, LD_PLAIN, ST_PLAIN>(const TileArgs&, int, int, hipStream_t);
@@ -1231,8 +1246,8 @@ template void launch_pencil<double2>(const PencilArgs&, int, int, size_t, hipStr
 
 // the operator apply's shapes that take the quarter-plane kernels and the
 // quarter-layout pencil (FP32 128 x 128 planes, compile-time pencil)
-bool qplane_shape(int nx, int ny, int nz, int pz, int bx, int nthr) {
-  return nx == QP_N && ny == QP_N && nz > 0 && bx == 16 &&
+bool qplane_shape(int nx, int ny, int nz, int pz, int bx, int nthr, size_t esz) {
+  return nx == ny && (nx == 128 || (nx == 256 && esz == 8)) && nz > 0 && bx == 16 &&
          ((pz == 128 && nthr == pencil_threads_ct(7, 16)) || (pz == 64 && nthr == pencil_threads_ct(6, 16)));
 }
 

@@ -122,14 +122,15 @@ bool tile_takes_dots(const TileArgs& a, size_t esz);
 bool tile_takes_update(const TileArgs& a, size_t esz);
 template <class T>
 void launch_pencil(const PencilArgs& a, int nbatch, int nthr, size_t lds, hipStream_t s);
-// Quarter-plane transverse kernels of the FP32 operator apply on 128 x 128
-// planes: forward (LD_VX, ST_PLAIN) into the quarter-plane layout, inverse
+// Quarter-plane transverse kernels of the operator apply on 128 x 128 planes
+// (and 256 x 256 in FP32): forward (LD_VX, ST_PLAIN) into the quarter-plane layout, inverse
 // (LD_PLAIN, ST_PLAIN or ST_AXPBY) from it; nplanes = 3 nz, no GivensTask.
 // The pencil between them runs with PencilArgs::yq.
 template <class T, bool INV, int LD, int ST>
 void launch_qplane(const TileArgs& a, int nplanes, int nbatch, hipStream_t s);
-// whether a shape (and its pencil's columns bx and threads) takes them
-bool qplane_shape(int nx, int ny, int nz, int pz, int bx, int nthr);
+// whether a shape (and its pencil's columns bx and threads) takes them: 128 x 128
+// planes, and 256 x 256 in FP32 (esz 8)
+bool qplane_shape(int nx, int ny, int nz, int pz, int bx, int nthr, size_t esz);
 
 // per-order readouts of the source density spectra (FP64):
 // adn = (i dz / 2 beta) P- sum_k exp(i beta z_k) f_q(z_k) / (NxNy), aup likewise at z = T.

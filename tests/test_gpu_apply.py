@@ -20,10 +20,11 @@ pytestmark = pytest.mark.gpu
 # (256, 256, 2): strips in both precisions; (16, 16, 32) and (16, 8, 64): the
 # z-pencil with compile-time padded lengths 64 and 128; (128, 128, 32) and
 # (128, 128, 64): the quarter-plane kernels with the quarter-layout pencil at
-# both compile-time lengths, in both precisions
+# both compile-time lengths, in both precisions; (256, 256, 32): quarter planes
+# in FP32, strips in FP64
 SHAPES = [
     (4, 4, 2), (8, 8, 4), (16, 8, 8), (32, 32, 16), (64, 32, 8), (128, 128, 4), (256, 64, 2), (64, 256, 2),
-    (256, 256, 2), (16, 16, 32), (16, 8, 64), (128, 128, 32), (128, 128, 64),
+    (256, 256, 2), (16, 16, 32), (16, 8, 64), (128, 128, 32), (128, 128, 64), (256, 256, 32),
 ]
 
 
@@ -63,7 +64,7 @@ def test_apply_matches_oracle(shape, dtype):
 
 
 @pytest.mark.parametrize("shape", [(8, 8, 4), (16, 8, 8), (32, 32, 16), (128, 128, 4), (64, 256, 2), (128, 128, 32),
-                                   (128, 128, 64)])
+                                   (128, 128, 64), (256, 256, 32)])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_coupled_apply_matches_oracle(shape, dtype):
     """y = u - M V u with M = K + R_vol T_R K_top (and its bilinear transpose)."""
@@ -89,19 +90,19 @@ def test_coupled_apply_matches_oracle(shape, dtype):
     assert rel(yt, reft) < tol, rel(yt, reft)
 
 
-@pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("nz", [32, 64])
-def test_quarter_planes_match_full_planes(nz, dtype, monkeypatch):
-    """128 x 128 planes: the quarter-plane kernels (four blocks per plane, the
+@pytest.mark.parametrize("n,nz,dtype", [(128, 32, "c64"), (128, 64, "c64"), (128, 32, "c128"), (128, 64, "c128"),
+                                        (256, 64, "c64")])
+def test_quarter_planes_match_full_planes(n, nz, dtype, monkeypatch):
+    """n x n planes: the quarter-plane kernels (four blocks per plane, the
     radix-4 y combine in the pencil) against the one-block-per-plane kernels
-    (FP32) or the row and column strips (FP64), in every apply variant (plain,
-    K only, transposed, coupled)."""
+    (FP32, 128 x 128) or the row and column strips (FP64; FP32 at 256 x 256), in
+    every apply variant (plain, K only, transposed, coupled)."""
     from paper_2606_25541_amd import api
     dev = device()
-    say("quarter vs full planes", nz, dtype)
-    p = make(128, 128, nz, phi=10.0)
-    de = clips.manhattan(128, 128, nz, p.lx_nm, p.ly_nm, seed=nz + 5)
-    x = clips.random_complex((3, nz, 128, 128), seed=29)
+    say("quarter vs full planes", n, nz, dtype)
+    p = make(n, n, nz, phi=10.0)
+    de = clips.manhattan(n, n, nz, p.lx_nm, p.ly_nm, seed=nz + 5)
+    x = clips.random_complex((3, nz, n, n), seed=29)
     plan = api.Plan(p)
     td = torch.complex64 if dtype == "c64" else torch.complex128
     dd = torch.from_numpy(de).to(dev, td)
