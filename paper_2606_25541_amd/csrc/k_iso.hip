@@ -215,6 +215,78 @@ __global__ void k_iso_zmul(IsoZ a) {
   }
 }
 
+// The same pass with the shape fixed at compile time (FFT length 2^LZ2, LB
+// columns, NT threads): every global load of a thread is issued before its
+// first LDS write, the twiddles are staged in LDS so that no FFT pass waits on
+// the vector-memory counter of the table entries in flight, and the FFT index
+// arithmetic folds to constants.
+template <class T, int LZ2, int LB, int NT>
+__global__ void __launch_bounds__(NT) k_iso_zmul_ct(IsoZ a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  constexpr int NZ = 1 << (LZ2 - 1), NSQ = 3 * LB, NPTS = 2 * NZ * LB, LLB = LB == 8 ? 3 : LB == 4 ? 2 : 1;
+  constexpr int NV = NZ * NSQ / NT;  // data values per thread
+  static_assert(NV * NT == NZ * NSQ && (1 << LLB) == LB, "z pass split");
+  T* twl = lds + (2 * NZ) * NSQ;
+  const int tid = threadIdx.x;
+  const unsigned nbx = gridDim.x;
+  const unsigned lid = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y);
+  const long long col = ((long long)(lid / nbx) << a.lnx2) + ((long long)(lid % nbx) << LLB);
+  const T* tb = (const T*)a.table + ((long long)lid * (NZ + 1) * 6 * LB);
+  const T* twg = (const T*)a.tw + 2 * NZ;
+  const T tw0 = twg[tid & (2 * NZ - 1)];
+  __builtin_amdgcn_sched_barrier(0);
+  const T* w = (const T*)a.w;
+  T v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int idx = tid + k * NT, li = idx & (LB - 1), r = idx >> LLB;
+    const int iz = r / 3, c = r - 3 * iz;
+    v[k] = w[(long long)(c * NZ + iz) * a.plane + col + li];
+  }
+  constexpr int ZPT = Zpt<T>::v;
+  T tt[ZPT > 0 ? ZPT : 1][6];
+#pragma unroll
+  for (int i = 0; i < ZPT; ++i) {
+    const int pt = tid + i * NT;
+    if (pt < NPTS) zmul_entries(tb, pt >> LLB, pt & (LB - 1), NZ, LB, tt[i]);
+  }
+  if (tid < 2 * NZ) twl[tid] = tw0;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int idx = tid + k * NT, li = idx & (LB - 1), r = idx >> LLB;
+    const int iz = r / 3, c = r - 3 * iz;
+    lds[iz * NSQ + c * LB + li] = v[k];
+  }
+  __syncthreads();
+  typedef FftCT<LZ2, NSQ, 1, NSQ, NT> D;
+  lds_fft_tab<T, false, true, ZFE, D, true, false>(lds, D(), twl, tid);
+#pragma unroll
+  for (int i = 0; i < ZPT; ++i) {
+    const int pt = tid + i * NT;
+    if (pt < NPTS) zmul_point(lds + (pt >> LLB) * NSQ + (pt & (LB - 1)), LB, tt[i]);
+  }
+  for (int pt = tid + ZPT * NT; pt < NPTS; pt += NT) {
+    T t[6];
+    zmul_entries(tb, pt >> LLB, pt & (LB - 1), NZ, LB, t);
+    zmul_point(lds + (pt >> LLB) * NSQ + (pt & (LB - 1)), LB, t);
+  }
+  __syncthreads();
+  lds_fft_tab<T, true, true, ZFE, D, false, true>(lds, D(), twl, tid);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int idx = tid + k * NT, li = idx & (LB - 1), r = idx >> LLB;
+    const int iz = r / 3, c = r - 3 * iz;
+    v[k] = lds[iz * NSQ + c * LB + li];
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int idx = tid + k * NT, li = idx & (LB - 1), r = idx >> LLB;
+    const int iz = r / 3, c = r - 3 * iz;
+    ((T*)a.w)[(long long)(c * NZ + iz) * a.plane + col + li] = v[k];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Precompute kernels (FP64).
 
@@ -437,6 +509,11 @@ template <> const float2* tab_of<float2>(psfd_iso_plan* p) { return p->ptab32; }
 // adjacent kx per z-pencil block: at most the cap below, the three padded z
 // sequences of all of them within 64 KB of LDS and at most ZFE values per
 // thread of 1024
+static int env_int_iso(const char* name, int dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::atoi(e) : dflt;
+}
+
 template <class T> int z_lb(int nz, int nx) {
   // measured at 128 x 128 x 64 (widths 16, 8, 4): 8 in FP32, 4 in FP64 (more
   // blocks per CU to cover the FFT barriers); PSFD_ISO_ZLB overrides (sweeps)
@@ -493,9 +570,19 @@ Status apply_t(psfd_iso_plan* p, const T* deps, const T* x, T* y, T* W, int stag
     const int nthr = std::min(1024, std::max({64, (els / ZFE + 63) / 64 * 64, pre}));
     if (els > ZFE * nthr) return bad(PSFD_ERR_UNSUPPORTED_SIZE, "z pencil tile exceeds the FFT budget");
     const size_t bytes = (size_t)els * sizeof(T);
-    auto fn = k_iso_zmul<T>;
-    if (bytes > 65536) ISOCHK(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-    hipLaunchKernelGGL(fn, dim3((unsigned)(2 * nx / z.lb), (unsigned)(2 * ny)), dim3(nthr), bytes, s, z);
+    const dim3 grid((unsigned)(2 * nx / z.lb), (unsigned)(2 * ny));
+    // compile-time shapes for the 64-plane grids at the measured block widths
+    constexpr int LBC = sizeof(T) == 8 ? 8 : 4, NTC = sizeof(T) == 8 ? 512 : 192;
+    if (lz == 6 && z.lb == LBC && nthr == NTC && env_int_iso("PSFD_ISO_ZCT", 1)) {
+      auto fc = k_iso_zmul_ct<T, 7, LBC, NTC>;
+      const size_t bc = bytes + (size_t)128 * sizeof(T);
+      if (bc > 65536) ISOCHK(hipFuncSetAttribute((const void*)fc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bc));
+      hipLaunchKernelGGL(fc, grid, dim3(NTC), bc, s, z);
+    } else {
+      auto fn = k_iso_zmul<T>;
+      if (bytes > 65536) ISOCHK(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+      hipLaunchKernelGGL(fn, grid, dim3(nthr), bytes, s, z);
+    }
   }
   if (stage < 0 || stage == 3) {  // columns 2ny -> first ny
     IsoLines b = a;

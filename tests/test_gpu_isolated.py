@@ -28,6 +28,8 @@ CASES = [
     ((4, 8, 8), (1.0, 3.0, 3.0), 1.0 + 0.05j),
     ((8, 4, 16), (2.0, 2.0, 1.0), 1.0 + 0.0j),
     ((16, 16, 8), (0.9375, 2.0, 2.0), 1.0 + 0.0j),
+    # 64 planes: the z pass with compile-time shapes (the 128 x 128 x 64 grid's)
+    ((64, 8, 8), (0.9375, 2.0, 2.0), 1.0 + 0.0j),
 ]
 
 
@@ -156,6 +158,25 @@ def test_isolated_apply_full_size_properties():
     d = ((y32 - y64).abs().max() / (y64 - a.to(torch.complex128)).abs().max()).item()
     say("  fp32 vs fp64", d)
     assert d <= 2e-5
+
+
+@pytest.mark.parametrize("dt,tol", [(torch.complex128, 1e-13), (torch.complex64, 1e-6)])
+def test_isolated_z_pass_compile_time_matches_run_time(dt, tol, monkeypatch):
+    """128 x 128 x 64: the z pass with compile-time shapes against the same pass
+    with run-time shapes (PSFD_ISO_ZCT=0): the same FFT passes and table
+    products, so the applies agree to the rounding of the FFT index order."""
+    dev = device()
+    shape, spacing = (64, 128, 128), (60.0 / 64, 2.0, 2.0)
+    plan = iso_plan(shape, spacing, 1.0)
+    de = torch.from_numpy(clips.contact_holes(128, 128, 64, 256.0, 256.0, 8, seed=2001)).to(dev, dt)
+    a = torch.from_numpy(clips.random_complex((3,) + shape, seed=1)).to(dev, dt)
+    y1 = plan.apply(de, a)
+    monkeypatch.setenv("PSFD_ISO_ZCT", "0")
+    y2 = plan.apply(de, a)
+    w1, w2 = (a - y1).to(torch.complex128), (a - y2).to(torch.complex128)
+    d = ((w1 - w2).abs().max() / w2.abs().max()).item()
+    say("  z pass compile-time vs run-time", dt, d)
+    assert d <= tol
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
