@@ -245,13 +245,9 @@ static int pencil_threads(const Shape& sh, int bx) {
   return nthr;
 }
 
-// data [pz][3 bx], phases [nz][bx], E_up [bx][3], shared region (partial sums,
-// phase factors, window factors), order constants [bx][7], twiddles [pz]
+// LDS bytes of a pencil block (the regions of PencilLds)
 static size_t pencil_lds(const Shape& sh, int bx, int nthr, size_t esz) {
-  size_t d = (size_t)sh.pz * 3 * bx * esz + (size_t)sh.nz * bx * esz;
-  d = (d + 15) / 16 * 16;
-  return d + (size_t)3 * bx * 16 + (size_t)pencil_part_words(sh.pz, bx, nthr, (int)esz) * 16 +
-         (size_t)7 * bx * 16 + (size_t)sh.pz * esz;
+  return (size_t)PencilLds(sh.pz, bx, nthr, (int)esz).total;
 }
 
 ZCfg z_config(const Shape& sh, size_t esz) {

@@ -70,15 +70,9 @@ template <class T, bool INV, int K> PSFD_D T w16(T a) {
 }
 
 // 16-point DFT as 4 x 4: DFT4 over n1 of x[4 n1 + n2], twiddle W16^(n2 k1),
-// DFT4 over n2; output k1 + 4 k2 in natural order
-template <class T, bool INV> PSFD_D void dft16(T* x) {
-  T y[16];
-#pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2) {
-    T a = x[n2], b = x[4 + n2], c = x[8 + n2], d = x[12 + n2];
-    dft4<T, INV>(a, b, c, d);
-    y[4 * n2 + 0] = a; y[4 * n2 + 1] = b; y[4 * n2 + 2] = c; y[4 * n2 + 3] = d;
-  }
+// DFT4 over n2; output k1 + 4 k2 in natural order. dft16_tail: the twiddles
+// and the second DFT4s, from the first stage's y[4 n2 + k1].
+template <class T, bool INV> PSFD_D void dft16_tail(T* y, T* x) {
   // W16^(n2 k1): n2 = 1: k1 = 1, 2, 3 -> W^1, W^2, W^3; n2 = 2: W^2, W^4, W^6; n2 = 3: W^3, W^6, W^9
   y[5] = w16<T, INV, 1>(y[5]);
   y[6] = w8<T, INV, 1>(y[6]);
@@ -100,6 +94,16 @@ template <class T, bool INV> PSFD_D void dft16(T* x) {
     x[k1] = a; x[k1 + 4] = b; x[k1 + 8] = c; x[k1 + 12] = d;
   }
 }
+template <class T, bool INV> PSFD_D void dft16(T* x) {
+  T y[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    T a = x[n2], b = x[4 + n2], c = x[8 + n2], d = x[12 + n2];
+    dft4<T, INV>(a, b, c, d);
+    y[4 * n2 + 0] = a; y[4 * n2 + 1] = b; y[4 * n2 + 2] = c; y[4 * n2 + 3] = d;
+  }
+  dft16_tail<T, INV>(y, x);
+}
 
 template <class T, int R, bool INV> PSFD_D void dft_r(T* u) {
   if (R == 2) dft2<T, INV>(u[0], u[1]);
@@ -118,9 +122,15 @@ template <class T, int R, bool INV> PSFD_D void dft_r_half(T* u) {
     const T c = cmul_mi<T, INV>(b);
     u[0] = cadd(a, b); u[2] = csub(a, b); u[1] = cadd(a, c); u[3] = csub(a, c);
   } else if (R == 16) {
+    // dft16 with x[8..15] = 0: each first-stage DFT4 takes (x[n2], x[4 + n2], 0, 0)
+    T y[16];
 #pragma unroll
-    for (int j = 8; j < 16; ++j) u[j] = cmake<T>(0, 0);
-    dft16<T, INV>(u);
+    for (int n2 = 0; n2 < 4; ++n2) {
+      const T a = u[n2], b = u[4 + n2], c = cmul_mi<T, INV>(b);
+      y[4 * n2 + 0] = cadd(a, b); y[4 * n2 + 2] = csub(a, b);
+      y[4 * n2 + 1] = cadd(a, c); y[4 * n2 + 3] = csub(a, c);
+    }
+    dft16_tail<T, INV>(y, u);
   } else {
     // even part (x0, x2, 0, 0) and odd part (x1, x3, 0, 0) as 4-point DFTs
     const T x0 = u[0], x1 = u[1], x2 = u[2], x3 = u[3];

@@ -15,33 +15,40 @@ PSFD_D double gv_wave_sum(double v) {
   return v;
 }
 
-// ||w||^2 from the nblk (<= RED_BLOCKS) norm partials of one instance: the first
-// GIVENS_THREADS threads take partials tid, tid + 256, ... in order, then
-// wavefront sums, then the four wavefront totals in order. Every thread of the
-// block must call it, and the block must have at least GIVENS_THREADS threads
-// (the rest only meet the barriers); all of them get the total.
-PSFD_D double norm_from_partials(const double2* pb, int nblk) {
-  __shared__ double2 gsm[GIVENS_THREADS / 64];
-  __shared__ double gtot;
+// ||w||^2 from the nblk (<= RED_BLOCKS) norm partials of one instance, in two
+// halves for callers with barriers of their own between them. norm_wave_sums:
+// the first GIVENS_THREADS threads take partials tid, tid + 256, ... in order
+// and leave their four wavefront sums in gs (LDS; the other threads do
+// nothing). norm_total, after a barrier: the four sums in order.
+PSFD_D void norm_wave_sums(const double2* pb, int nblk, double2* gs) {
   constexpr int PK = RED_BLOCKS / GIVENS_THREADS;
   const int tid = threadIdx.x;
-  double2 acc = make_double2(0, 0);
   if (tid < GIVENS_THREADS) {
     double2 pv[PK];
+    double2 acc = make_double2(0, 0);
 #pragma unroll
     for (int k = 0; k < PK; ++k) pv[k] = pb[min(tid + k * GIVENS_THREADS, nblk - 1)];
 #pragma unroll
     for (int k = 0; k < PK; ++k)
       if (tid + k * GIVENS_THREADS < nblk) acc = cadd(acc, pv[k]);
     const double re = gv_wave_sum(acc.x), im = gv_wave_sum(acc.y);
-    if ((tid & 63) == 0) gsm[tid >> 6] = make_double2(re, im);
+    if ((tid & 63) == 0) gs[tid >> 6] = make_double2(re, im);
   }
+}
+PSFD_D double norm_total(const double2* gs) {
+  double2 t = gs[0];
+  for (int wv = 1; wv < GIVENS_THREADS / 64; ++wv) t = cadd(t, gs[wv]);
+  return t.x;
+}
+
+// Both halves with their barriers: every thread of the block must call it, and
+// the block must have at least GIVENS_THREADS threads; all of them get the total.
+PSFD_D double norm_from_partials(const double2* pb, int nblk) {
+  __shared__ double2 gsm[GIVENS_THREADS / 64];
+  __shared__ double gtot;
+  norm_wave_sums(pb, nblk, gsm);
   __syncthreads();
-  if (tid == 0) {
-    double2 t = gsm[0];
-    for (int wv = 1; wv < GIVENS_THREADS / 64; ++wv) t = cadd(t, gsm[wv]);
-    gtot = t.x;
-  }
+  if (threadIdx.x == 0) gtot = norm_total(gsm);
   __syncthreads();
   return gtot;
 }

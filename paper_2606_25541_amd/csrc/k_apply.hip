@@ -979,13 +979,6 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
         buf[k] = w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl];
       }
     }
-    // with a GivensTask the input is the new Arnoldi vector unscaled: its scale
-    // from the norm partials the task sums (bitwise the same value)
-    if (gvb) {
-      const R scl = (R)inv_norm_of(norm_from_partials(a.gv.part + (long long)b * a.gv.nblk, a.gv.nblk));
-#pragma unroll
-      for (int k = 0; k < 4; ++k) buf[k] = cscale(buf[k], scl);
-    }
     // the quarter spectra of the thread's quad become its 4 columns' spectra
     // (the 16 lanes of a quad group share their component and planes)
     if constexpr (YQ) {
@@ -1003,19 +996,20 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   // the padded half is never read: the first forward pass treats it as zero
   const double* tab = a.tab + (long long)b * a.tab_stride;
   TabLayout L{nx, ny};
-  // LDS after the data: phases exp(i beta z_k) [nz][bx] (T), the stack response
-  // E_up [bx][3], readout partial sums [nthr], per-column order constants [bx][6]
-  T* ph = lds + pz * LS;
-  const size_t off_e = ((size_t)(pz * LS + nz * bx) * sizeof(T) + 15) / 16;  // in double2
-  double2* eup = smem_d + off_e;
-  T* eupT = reinterpret_cast<T*>(eup);  // E_up [bx][3] in the working precision
-  double2* part = eup + 3 * bx;
-  double2* ptab = part + pencil_part_words(pz, bx, nthr, (int)sizeof(T));
-  T* twl = reinterpret_cast<T*>(ptab + 7 * bx);  // twiddles of length pz (compile-time shapes)
-  // the partial-sum region also holds the phase factors and, after the stack
-  // response, the window factors F(|l|) of the kernel multiply
-  T* ab = reinterpret_cast<T*>(part);
-  T* ftab = reinterpret_cast<T*>(part);
+  // LDS after the data: the phase factors of the stack response, the window
+  // factors F(|l|) of the kernel multiply, E_up [bx][3] in the working
+  // precision, the readout partial sums, the order constants [bx][7] and the
+  // twiddles of length pz (compile-time shapes)
+  const PencilLds lo(pz, bx, nthr, (int)sizeof(T));
+  char* lb = reinterpret_cast<char*>(smem_d);
+  T* ab = reinterpret_cast<T*>(lb + lo.fac);
+  T* ftab = reinterpret_cast<T*>(lb + lo.win);
+  T* eupT = reinterpret_cast<T*>(lb + lo.eup);
+  double2* part = reinterpret_cast<double2*>(lb + lo.part);
+  double2* ptab = reinterpret_cast<double2*>(lb + lo.ptab);
+  T* twl = reinterpret_cast<T*>(lb + lo.twl);
+  // the norm partials' wavefront sums (the scale of a GivensTask's input)
+  __shared__ double2 gsw[GIVENS_THREADS / 64];
   // order of column kxl (the transposed operator reads the kernel at the negated order)
   auto order_of = [&](int kxl, int& mq, int& nq) {
     if constexpr (YQ) {
@@ -1054,16 +1048,18 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     ptab[tid * 7 + 5] = make_double2(tab[L.off_keep() + q], 0.0);
     ptab[tid * 7 + 6] = make_double2(e.x * sik, e.y * sik);  // e^{i beta L} scale / k_bg^2 (zz term at s = +1)
   }
+  // Layered-stack response of this block's orders (monolithic coupling):
+  // E_up,q = M_q sum_k exp(i beta_q z_k) f_q(z_k), M_q = T_R (i dz / 2 beta) P- / (Nx Ny)
+  // from the table, added back as E_up,q exp(i beta_q z_k) on every plane. The
+  // transposed operator uses the negated order and M_q^T. The phases
+  // exp(i beta z_k), z_k = (k + 1/2) dz, are products of two factors, k = Q a + c:
+  // exp(i beta (c + 1/2) dz) exp(i beta Q a dz); the NF = Q + nz / Q factors of a
+  // column are tabulated, and every use forms the same product.
+  const int Q = nz < 8 ? nz : 8, NF = Q + nz / Q;
+  auto phase_at = [&](int z, int kxl) { return cmul(ab[(z % Q) * bx + kxl], ab[(Q + z / Q) * bx + kxl]); };
   if (a.reflect) {
-    // Layered-stack response of this block's orders (monolithic coupling):
-    // E_up,q = M_q sum_k exp(i beta_q z_k) f_q(z_k), M_q = T_R (i dz / 2 beta) P- / (Nx Ny)
-    // from the table, added back as E_up,q exp(i beta_q z_k) on every plane. The
-    // transposed operator uses the negated order and M_q^T.
     const double2* tb = reinterpret_cast<const double2*>(tab + L.off_beta());
     const double dz = tab[TS_DZ];
-    // phases exp(i beta z_k), z_k = (k + 1/2) dz, as products of two factors:
-    // k = Q a + c: exp(i beta (c + 1/2) dz) exp(i beta Q a dz)
-    const int Q = nz < 8 ? nz : 8, NA = nz / Q, NF = Q + NA;
     for (int i = tid; i < NF * bx; i += nthr) {
       const int kxl = i % bx, f = i / bx;
       int mq, nq;
@@ -1071,44 +1067,29 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
       const double2 bq = tb[nq * nx + mq];
       ab[f * bx + kxl] = phase_exp<T>(bq, f < Q ? (f + 0.5) * dz : (double)(Q * (f - Q)) * dz);
     }
-    __syncthreads();
-    for (int i = tid; i < nz * bx; i += nthr) {
-      const int kxl = i & (bx - 1), z = i >> lbx;
-      ph[i] = cmul(ab[(z % Q) * bx + kxl], ab[(Q + z / Q) * bx + kxl]);
-    }
-    __syncthreads();
-    // partial sums over z: thread (ch, sq) takes planes ch, ch + nch, ...
-    const int nch = nthr / LS;
-    if (tid < nch * LS) {
-      const int sq = tid % LS, ch = tid / LS;
-      const int kxl = sq & (bx - 1);
-      T acc = cmake<T>(0, 0);
-      if constexpr (CT) {
-        // (ch, sq) = (z0, tid mod LS): this thread's own data, planes z0 + k zstep
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc = cadd(acc, cmul(ph[(ch + k * nch) * bx + kxl], buf[k]));
-      } else {
-        for (int z = ch; z < nz; z += nch) acc = cadd(acc, cmul(ph[z * bx + kxl], lds[z * LS + sq]));
-      }
-      part[tid] = to_d(acc);
-    }
-    __syncthreads();
-    if (tid < LS) {
-      double2 v = make_double2(0, 0);
-      for (int ch = 0; ch < nch; ++ch) v = cadd(v, part[ch * LS + tid]);
-      part[tid] = v;  // slot 0 of this thread's own sequence, which no other thread reads
-    }
-    __syncthreads();
-    if (tid < 3 * bx) {
-      // row r of M (or of M^T) times the summed readouts of column kxl
-      const int kxl = tid % bx, r = tid / bx;
-      double2 o = make_double2(0, 0);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) o = cadd(o, cmul(mrow[c], part[c * bx + kxl]));
-      eupT[kxl * 3 + r] = from_d<T>(o);
-    }
   }
+  // with a GivensTask the input is the new Arnoldi vector unscaled: its scale,
+  // from the norm partials the task sums (bitwise the same value), multiplies
+  // the output (every step of the kernel is linear in its input)
+  if (gvb) norm_wave_sums(a.gv.part + (long long)b * a.gv.nblk, a.gv.nblk, gsw);
   __syncthreads();
+  const R scl = gvb ? (R)inv_norm_of(norm_total(gsw)) : (R)1;
+  // readout partial sums over z: thread (ch, sq) takes planes ch, ch + nch, ...
+  // (read before the forward transform's first barrier, summed after its last)
+  const int nch = nthr / LS;
+  if (a.reflect && tid < nch * LS) {
+    const int sq = tid % LS, ch = tid / LS;
+    const int kxl = sq & (bx - 1);
+    T acc = cmake<T>(0, 0);
+    if constexpr (CT) {
+      // (ch, sq) = (z0, tid mod LS): this thread's own data, planes z0 + k zstep
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc = cadd(acc, cmul(phase_at(ch + k * nch, kxl), buf[k]));
+    } else {
+      for (int z = ch; z < nz; z += nch) acc = cadd(acc, cmul(phase_at(z, kxl), lds[z * LS + sq]));
+    }
+    part[tid] = to_d(acc);
+  }
   // window factors F(|l|) of every column (F is even in l): the FP64 work of the
   // kernel multiply once per |l| instead of once per point
   {
@@ -1133,6 +1114,13 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     else pass_r<T, false, true, 8, ZCT, false, false, 8>(lds, ZCT(), 3, twl, tid, false, true);
   } else {
     lds_fft<T, false, true, 8, true, false>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
+  }
+  // the readout of sequence tid: its partial sums in order (slot 0 is its own,
+  // which no other thread reads)
+  if (a.reflect && tid < LS) {
+    double2 v = make_double2(0, 0);
+    for (int ch = 0; ch < nch; ++ch) v = cadd(v, part[ch * LS + tid]);
+    part[tid] = v;
   }
 
   // the points of a thread all lie in its column ck (nthr is a multiple of bx):
@@ -1179,6 +1167,15 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     *p2 = csub(cmul(F, o2), cmul(tz, v2));
   }
   __syncthreads();
+  if (a.reflect && tid < 3 * bx) {
+    // row r of M (or of M^T) times the summed readouts of column kxl (read at
+    // the store, after the inverse transform's barriers)
+    const int kxl = tid % bx, r = tid / bx;
+    double2 o = make_double2(0, 0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o = cadd(o, cmul(mrow[c], part[c * bx + kxl]));
+    eupT[kxl * 3 + r] = from_d<T>(o);
+  }
   const int nst = 3 * nz * bx;
   if constexpr (CT) {
     // the inverse transform's last pass leaves the kept half in registers, and
@@ -1198,7 +1195,8 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
       for (int j = 0; j < RL / 2; ++j) {
         const int z = t + PL * j;
         T v = out[i * (RL / 2) + j];
-        if (a.reflect) v = cadd(v, cmul(e, ph[z * bx + kxl]));
+        if (a.reflect) v = cadd(v, cmul(e, phase_at(z, kxl)));
+        if (gvb) v = cscale(v, scl);
         if constexpr (YQ) {
           // back to quarter spectra across the quad (kxl = tid mod 16)
           v = quad_dft4<T>(v, kxl & 3, true);
@@ -1216,7 +1214,8 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
       const int c = rest % 3;
       const int z = rest / 3;
       T v = lds[z * LS + c * bx + kxl];
-      if (a.reflect) v = cadd(v, cmul(eupT[kxl * 3 + c], ph[z * bx + kxl]));
+      if (a.reflect) v = cadd(v, cmul(eupT[kxl * 3 + c], phase_at(z, kxl)));
+      if (gvb) v = cscale(v, scl);
       w[((long long)(c * nz + z) * ny + ky) * nx + kx0 + kxl] = v;
     }
   }

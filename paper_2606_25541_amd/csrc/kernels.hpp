@@ -97,17 +97,24 @@ struct PencilArgs {
 
 struct TileShape { int tx, ty, do_x, do_y, nthr; size_t lds; int pitch; };
 
-// LDS words (16 bytes) of the pencil's shared region: readout partial sums
-// (nthr), the phase factors (bx (Q + nz / Q), Q = min(8, nz)) and the window
-// factors (bx (pz / 2 + 1)), in elements of esz bytes
-__host__ __device__ inline int pencil_part_words(int pz, int bx, int nthr, int esz) {
-  const int nz = pz / 2, q = nz < 8 ? nz : 8;
-  const int fac = bx * (q + nz / q) * esz, win = bx * (pz / 2 + 1) * esz;
-  int words = nthr;
-  if ((fac + 15) / 16 > words) words = (fac + 15) / 16;
-  if ((win + 15) / 16 > words) words = (win + 15) / 16;
-  return words;
-}
+// Byte offsets of a pencil block's LDS regions: the data [pz][3 bx], the phase
+// factors [Q + nz / Q][bx] of the stack response (Q = min(8, nz)) and the window
+// factors [pz / 2 + 1][bx], in elements of esz bytes; then, 16-byte aligned,
+// E_up [bx][3], the readout partial sums [nthr] and the order constants [bx][7]
+// (16-byte words), and the twiddles [pz] (esz).
+struct PencilLds {
+  int fac, win, eup, part, ptab, twl, total;
+  __host__ __device__ PencilLds(int pz, int bx, int nthr, int esz) {
+    const int nz = pz / 2, q = nz < 8 ? nz : 8;
+    fac = pz * 3 * bx * esz;
+    win = fac + bx * (q + nz / q) * esz;
+    eup = (win + bx * (pz / 2 + 1) * esz + 15) / 16 * 16;
+    part = eup + 3 * bx * 16;
+    ptab = part + nthr * 16;
+    twl = ptab + 7 * bx * 16;
+    total = twl + pz * esz;
+  }
+};
 
 template <class T, bool INV, int LD, int ST>
 void launch_tile(const TileArgs& a, int nplanes, int nbatch, int nthr, size_t lds, hipStream_t s);
