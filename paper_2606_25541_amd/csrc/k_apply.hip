@@ -1045,7 +1045,9 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     ptab[tid * 7 + 2] = make_double2(e.x - 1.0, e.y);    // s e^{i beta L} - 1 at s = +1
     ptab[tid * 7 + 3] = make_double2(-e.x - 1.0, -e.y);  // and at s = -1
     ptab[tid * 7 + 4] = make_double2(tab[L.off_kx() + mq] * ikb, tab[L.off_ky() + nq] * ikb);
-    ptab[tid * 7 + 5] = make_double2(tab[L.off_keep() + q], 0.0);
+    // the keep flag, and kappa / k_bg (the same for every column: one FP64
+    // division here instead of one per wavefront)
+    ptab[tid * 7 + 5] = make_double2(tab[L.off_keep() + q], tab[TS_KAPPA] / tab[TS_KBG]);
     ptab[tid * 7 + 6] = make_double2(e.x * sik, e.y * sik);  // e^{i beta L} scale / k_bg^2 (zz term at s = +1)
   }
   // Layered-stack response of this block's orders (monolithic coupling):
@@ -1073,10 +1075,17 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   // the output (every step of the kernel is linear in its input)
   if (gvb) norm_wave_sums(a.gv.part + (long long)b * a.gv.nblk, a.gv.nblk, gsw);
   __syncthreads();
-  const R scl = gvb ? (R)inv_norm_of(norm_total(gsw)) : (R)1;
+  // the first wavefront forms the scale (FP64 square root and division) for
+  // the block; the others read it at the store, many barriers later
+  __shared__ R sclw;
+  if (gvb && tid < 64) {
+    const R sc = (R)inv_norm_of(norm_total(gsw));
+    if (tid == 0) sclw = sc;
+  }
   // readout partial sums over z: thread (ch, sq) takes planes ch, ch + nch, ...
   // (read before the forward transform's first barrier, summed after its last)
   const int nch = nthr / LS;
+  T ph4[4];  // compile-time shapes: the phases of the thread's planes z0 + k zstep, kept for the store
   if (a.reflect && tid < nch * LS) {
     const int sq = tid % LS, ch = tid / LS;
     const int kxl = sq & (bx - 1);
@@ -1084,7 +1093,10 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     if constexpr (CT) {
       // (ch, sq) = (z0, tid mod LS): this thread's own data, planes z0 + k zstep
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc = cadd(acc, cmul(phase_at(ch + k * nch, kxl), buf[k]));
+      for (int k = 0; k < 4; ++k) {
+        ph4[k] = phase_at(ch + k * nch, kxl);
+        acc = cadd(acc, cmul(ph4[k], buf[k]));
+      }
     } else {
       for (int z = ch; z < nz; z += nch) acc = cadd(acc, cmul(phase_at(z, kxl), lds[z * LS + sq]));
     }
@@ -1130,7 +1142,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
   const bool keep_c = pc[5].x != 0.0;
   const R kxk = (R)pc[4].x, kyk = (R)pc[4].y;
   const T tz0 = from_d<T>(pc[6]);  // e^{i beta L} scale / k_bg^2 (zz term at s = +1)
-  const R kzr = (R)(tab[TS_KAPPA] / tab[TS_KBG]);  // kappa_l / k_bg = l kzr
+  const R kzr = (R)pc[5].y;  // kappa_l / k_bg = l kzr
   for (int pt = tid; pt < npt; pt += nthr) {
     const int l = pt >> lbx;
     int ls = (l < pz / 2) ? l : l - pz;
@@ -1184,8 +1196,13 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     // 8 / R butterflies b = tid + i nthr per thread, b = t LS + s
     T out[4];
     lds_fft_tab_regout<T, true, true, 8, ZCT, true, 4>(lds, ZCT(), twl, tid, out);
+    const R scl = gvb ? sclw : (R)1;
     constexpr int RL = LPZ == 7 ? 8 : 4, NBL = 8 / RL, PL = (1 << LPZ) / RL;
     static_assert(LPZ == 6 || LPZ == 7, "pencil lengths with a register last pass");
+    // output plane t + PL j of butterfly i is the thread's loaded plane z0 + k zstep,
+    // k = i + j PL / zstep (t = z0 + i zstep): its phase is ph4[k]
+    constexpr int ZST = pencil_threads_ct(LPZ, BXC) / (3 * BXC);
+    static_assert(PL % ZST == 0 && (NBL - 1) + (RL / 2 - 1) * (PL / ZST) < 4, "store planes are the loaded planes");
 #pragma unroll
     for (int i = 0; i < NBL; ++i) {
       const int bfl = tid + i * nthr, t = bfl / LS, sq = bfl - t * LS;
@@ -1195,7 +1212,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
       for (int j = 0; j < RL / 2; ++j) {
         const int z = t + PL * j;
         T v = out[i * (RL / 2) + j];
-        if (a.reflect) v = cadd(v, cmul(e, phase_at(z, kxl)));
+        if (a.reflect) v = cadd(v, cmul(e, ph4[i + j * (PL / ZST)]));
         if (gvb) v = cscale(v, scl);
         if constexpr (YQ) {
           // back to quarter spectra across the quad (kxl = tid mod 16)
@@ -1208,6 +1225,7 @@ __global__ void __launch_bounds__(768) k_pencil(PencilArgs a) {
     }
   } else {
     lds_fft<T, true, true, 8, false, true>(lds, a.log2pz, LS, 1, LS, tw, tid, nthr);
+    const R scl = gvb ? sclw : (R)1;
     for (int i = tid; i < nst; i += nthr) {
       const int kxl = i & (bx - 1);
       const int rest = i >> lbx;
