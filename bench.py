@@ -302,6 +302,23 @@ def sec_apply(ctx, args, out):
                        "bytes_per_launch": bytes_d, "us_per_launch": us_d,
                        "kernel_source_hash": kernel_source_hash(),
                        "per_step_us": {k: round(v[1], 2) for k, v in cand.items()}}
+    # the device's own copy of 256 MiB (read + write, best of five): the practical streaming
+    # ceiling, against which the fraction is also given
+    ca = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(5):
+        e0.record()
+        cb.copy_(ca)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    copy_gbs = 2 * ca.numel() * 4 / (best * 1e-3) / 1e9
+    out["roofline"]["copy_gbs"] = copy_gbs
+    out["roofline"]["frac_of_copy"] = gbs / copy_gbs
+    del ca, cb
     if args.only == "apply":
         # plain copy of known size: the scale of the FETCH_SIZE / WRITE_SIZE counters
         a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
@@ -806,7 +823,20 @@ def sec_cpu(ctx, args, out):
                            "sample": f"table set-up plus {k} FP64 GMRES(30) iterations of the oracle's monolithic "
                                      f"operator on the same clip (scipy.fft workers={ncores}), {t_it:.2f} s per "
                                      f"iteration, scaled to {its} iterations ({src})",
-                           "s_per_iteration": t_it, "s_setup": t_setup, "iterations_scaled_to": its}
+                           "s_per_iteration": t_it, "s_setup": t_setup, "iterations_scaled_to": its,
+                           "cpu_model": cpu_model()}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (first processor in /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def oracle_study(args):
