@@ -379,7 +379,10 @@ Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec) {
   g.rblk = (int)((sh.nxny + 255) / 256);
   GALLOC(g.rpart, (size_t)g.rblk * 2 * 8 * B);
   HIPCHK(hipHostMalloc((void**)&g.h_run, sizeof(int) * B * 4, hipHostMallocDefault));
-  HIPCHK(hipHostMalloc((void**)&g.h_flags, sizeof(int) * B * FLAG_SLOTS, hipHostMallocDefault));
+  // the solve flags, written by the cycle-start kernel itself (coherent, mapped)
+  HIPCHK(hipHostMalloc((void**)&g.h_flags, sizeof(int) * B, hipHostMallocCoherent | hipHostMallocMapped));
+  HIPCHK(hipHostGetDevicePointer((void**)&g.d_flags, g.h_flags, 0));
+  for (int b = 0; b < B; ++b) g.h_flags[b] = 0;
   for (int i = 0; i < FLAG_SLOTS; ++i) HIPCHK(hipEventCreateWithFlags(&g.flag_ev[i], hipEventDisableTiming));
   HIPCHK(hipHostMalloc((void**)&g.h_dbl, sizeof(double) * (size_t)B * 2 * std::max(8, g.rblk), hipHostMallocDefault));
   HIPCHK(hipMemset(g.st, 0, sizeof(GState) * B));
@@ -905,16 +908,18 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   vec_norm2<double2>(g.b, n3, n3, g.dpart, g.n2b, g.mask, B, s);
   krylov_solve_init(g.st, g.n2b, g.rtol, g.abs_target, o.max_iters, g.mask, B, s);
   const double eta = g.prec == PSFD_MIXED ? o.inner_eta : 0.0;
-  // After each cycle start the active flags travel to pinned host memory behind
-  // an event; the host polls the events without blocking and stops launching
-  // once a snapshot shows no active instance. It blocks only when more than
-  // FLAG_LAG snapshots are outstanding, so the GPU queue stays full.
+  // Each cycle start writes the active flags to mapped host memory, and an event
+  // follows it; the host polls the events without blocking and stops launching
+  // once the flags read after one show no active instance. An instance's flag
+  // only ever goes from 1 to 0, so flags written by a later cycle start than
+  // the event's are as good. The host blocks only when more than FLAG_LAG
+  // events are outstanding, so the GPU queue stays full.
   const int max_cycles = o.max_iters + 2;  // every cycle that starts takes at least one step
   std::deque<int> pending;                 // snapshot slots in flight, oldest first
   bool done = false;
-  auto snapshot_live = [&](int slot) {
+  auto snapshot_live = [&]() {
     for (int b = 0; b < B; ++b)
-      if (g.h_flags[slot * B + b]) return true;
+      if (reinterpret_cast<volatile int*>(g.h_flags)[b]) return true;
     return false;
   };
   const double cancel = cancel_threshold();
@@ -926,7 +931,7 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
     apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, refl, g.tres, q);  // A x
     krylov_residual_parts<T>(g.b, g.r, (T*)g.basis, n3, n3, bsv, g.dpart, g.tres, B, q);
     krylov_cycle_start_sum(g.st, g.n2, g.dpart, g.lpart, g.abs_target, eta, g.m, cancel, every, g.mask, g.tres,
-                           g.rres, g.run, g.cyc, B, q);
+                           g.rres, g.run, g.cyc, B, q, g.d_flags);
   };
   // every instance that runs a cycle starts it at j = 0 and stops for good
   // when it ends, so the running ones all stand at step `step`; the cycle's
@@ -951,7 +956,6 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
       HIPCHK(hipGetLastError());
     }
     const int slot = cyc % FLAG_SLOTS;
-    HIPCHK(hipMemcpyAsync(g.h_flags + slot * B, g.mask, sizeof(int) * B, hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(g.flag_ev[slot], s));
     pending.push_back(slot);
     while (!pending.empty()) {
@@ -960,7 +964,7 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
       if (q == hipErrorNotReady) break;
       if (q != hipSuccess) return hip_status(q, "solve flags");
       pending.pop_front();
-      if (!snapshot_live(old)) { done = true; break; }
+      if (!snapshot_live()) { done = true; break; }
     }
     if (done) break;
   }

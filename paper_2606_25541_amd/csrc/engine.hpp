@@ -113,7 +113,8 @@ struct Group {
   double2 *adn = nullptr, *aup = nullptr, *eup = nullptr, *ord = nullptr, *eup2 = nullptr;
   double* rpart = nullptr;
   int rblk = 1;
-  int* h_flags = nullptr;    // pinned snapshots of the solve flags (FLAG_SLOTS x B)
+  int* h_flags = nullptr;    // the solve flags in mapped, coherent host memory (B), and
+  int* d_flags = nullptr;    // the device's address of it, written by each cycle start
   hipEvent_t flag_ev[FLAG_SLOTS] = {};
   int* h_run = nullptr;      // pinned host mirrors
   double* h_dbl = nullptr;

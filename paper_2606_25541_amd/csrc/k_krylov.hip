@@ -541,11 +541,12 @@ __global__ void k_cycle_start(GState* st, const double* rnorm2, const double* ab
 
 // the same, with ||r||^2 summed here from the partials of b - A x (tpart,
 // RED_BLOCKS per instance) or of the basis residual (lpart, LIN_BLOCKS), in the
-// order of k_sum_part, and stored to rnorm2
+// order of k_sum_part, and stored to rnorm2; act[b] is also written to
+// host_act[b] (host memory mapped for the device, or null)
 __global__ void __launch_bounds__(KB) k_cycle_start_sum(GState* st, double* rnorm2, const double* tpart,
                                                         const double* lpart, const double* abs_target, double eta,
                                                         int m, double cancel_thr, int every, int* act, int* tres,
-                                                        int* rres, int* run, int* cyc) {
+                                                        int* rres, int* run, int* cyc, int* host_act) {
   const int b = blockIdx.x;
   const int t = tres[b], r = rres[b];
   if (t || r) {
@@ -553,7 +554,10 @@ __global__ void __launch_bounds__(KB) k_cycle_start_sum(GState* st, double* rnor
     if (threadIdx.x == 0) rnorm2[b] = n2;
   }
   __syncthreads();
-  if (threadIdx.x == 0) cycle_start(st, rnorm2, abs_target, eta, m, cancel_thr, every, act, tres, rres, run, cyc, b);
+  if (threadIdx.x == 0) {
+    cycle_start(st, rnorm2, abs_target, eta, m, cancel_thr, every, act, tres, rres, run, cyc, b);
+    if (host_act) host_act[b] = act[b];
+  }
 }
 
 void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
@@ -565,9 +569,9 @@ void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_targ
 
 void krylov_cycle_start_sum(GState* st, double* rnorm2, const double* tpart, const double* lpart,
                             const double* abs_target, double eta, int m, double cancel_thr, int every, int* act,
-                            int* tres, int* rres, int* run, int* cyc, int nbatch, hipStream_t s) {
+                            int* tres, int* rres, int* run, int* cyc, int nbatch, hipStream_t s, int* host_act) {
   hipLaunchKernelGGL(k_cycle_start_sum, dim3(nbatch), dim3(KB), 0, s, st, rnorm2, tpart, lpart, abs_target, eta, m,
-                     cancel_thr, every, act, tres, rres, run, cyc);
+                     cancel_thr, every, act, tres, rres, run, cyc, host_act);
 }
 
 

@@ -145,10 +145,12 @@ void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_targ
 // krylov_cycle_start with ||r||^2 summed in the same launch, in the order of
 // krylov_residual / krylov_sum_norm: from the b - A x partials in tpart
 // (RED_BLOCKS per instance) where tres is set, from the basis-residual partials
-// in lpart (LIN_BLOCKS) where rres is; the sum is also stored to rnorm2
+// in lpart (LIN_BLOCKS) where rres is; the sum is also stored to rnorm2. With
+// host_act (host memory the device can write), act[b] is also written there.
 void krylov_cycle_start_sum(GState* st, double* rnorm2, const double* tpart, const double* lpart,
                             const double* abs_target, double eta, int m, double cancel_thr, int every, int* act,
-                            int* tres, int* rres, int* run, int* cyc, int nbatch, hipStream_t s);
+                            int* tres, int* rres, int* run, int* cyc, int nbatch, hipStream_t s,
+                            int* host_act = nullptr);
 // start a cycle from rnorm2[b] = ||r_b||^2 (v0 = r unnormalised, as left by
 // krylov_residual; inv_norm = 1 / ||r||): g = (||r||, 0, ...), j = 0,
 // target = max(abs_target[b], eta ||r||); run[b] = mask[b] && ||r|| > abs_target[b]
