@@ -797,7 +797,7 @@ template <> const float2* deps_of<float2>(const Group& g) { return g.deps32; }
 template <> const double2* deps_of<double2>(const Group& g) { return g.deps64; }
 
 template <class T>
-void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
+bool arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh, const int* solve_mask) {
   T* V = (T*)g.basis;
   const long long n3 = g.sh.n3, bsv = (long long)(g.m + 1) * n3;
   VecRef vin;
@@ -840,7 +840,7 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
     apply_stage<T>(g, 1, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, nullptr, 0, &gp);
     if (!arnoldi_inverse<T>(g, vout, jh, s)) krylov_dots<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.B, s, jh);
     krylov_givens_proj(g.st, g.run, g.dpart2, g.B, s, -1);
-    return;
+    return false;
   }
   if (upd) {
     // the update of column jh - 1 in the forward plane kernel, which transforms
@@ -876,12 +876,21 @@ void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh) {
   // with the fused update, the last column of a cycle takes no update pass: its
   // Givens step uses the projections alone, and slot m keeps w (the restart's
   // residual coefficients fold the update in)
-  if (upd && jh == g.m - 1) krylov_givens_proj(g.st, g.run, g.dpart2, g.B, s, jh);
-  else if (!upd) krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.part, g.B, s, jh, !lock || jh == g.m - 1);
+  // (with solve_mask the back substitution of the cycle follows in the same launch)
+  if (upd && jh == g.m - 1) {
+    if (solve_mask) {
+      krylov_givens_proj_solve(g.st, g.run, g.dpart2, solve_mask, g.B, s, jh);
+      return true;
+    }
+    krylov_givens_proj(g.st, g.run, g.dpart2, g.B, s, jh);
+  } else if (!upd) {
+    krylov_update<T>(V, n3, bsv, n3, g.st, g.run, g.dpart2, g.part, g.B, s, jh, !lock || jh == g.m - 1);
+  }
+  return false;
 }
 
-template void arnoldi_step<float2>(Group&, int, int, hipStream_t, int);
-template void arnoldi_step<double2>(Group&, int, int, hipStream_t, int);
+template bool arnoldi_step<float2>(Group&, int, int, hipStream_t, int, const int*);
+template bool arnoldi_step<double2>(Group&, int, int, hipStream_t, int, const int*);
 
 // Restarted GMRES on (I - K V) x = b for the instances with act[b] set, driven
 // from the device. Each restart takes the residual of the active instances,
@@ -937,8 +946,10 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   // when it ends, so the running ones all stand at step `step`; the cycle's
   // solution update and the next restart's residual follow
   auto cycle_body = [&](hipStream_t q) {
-    for (int step = 0; step < g.m; ++step) arnoldi_step<T>(g, transpose, refl, q, step);
-    krylov_solve_small(g.st, g.cyc, B, q);
+    bool solved = false;
+    for (int step = 0; step < g.m; ++step)
+      solved = arnoldi_step<T>(g, transpose, refl, q, step, step == g.m - 1 ? g.cyc : nullptr);
+    if (!solved) krylov_solve_small(g.st, g.cyc, B, q);
     krylov_lincomb_res<T, double2>((T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.cyc, g.rres, g.lpart, B, q);
     cycle_start(q);
   };

@@ -205,8 +205,11 @@ int true_residual_every();
 extern const int STEPS_PER_SYNC;
 // one Arnoldi step (apply of B, Gram-Schmidt, Givens, scale) for every instance with run[b];
 // jh >= 0 when every running instance stands at step jh (the Krylov slots are
-// then fixed at launch), jh < 0 to take each instance's step from its state
+// then fixed at launch), jh < 0 to take each instance's step from its state.
+// solve_mask: at the last step of a lock-step cycle with the fused update, the
+// back substitution (krylov_solve_small over solve_mask) runs in the launch of
+// the last column's Givens step, and the call returns true; false otherwise.
 template <class T>
-void arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh = -1);
+bool arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh = -1, const int* solve_mask = nullptr);
 
 }  // namespace psfd

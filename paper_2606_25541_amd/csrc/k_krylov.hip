@@ -263,8 +263,9 @@ void krylov_givens(GState* st, int* run, const double2* part, int nbatch, hipStr
 }
 
 // the Givens step of the last column from its projections alone (see
-// krylov_givens_proj); the partials are summed as k_update sums them
-__global__ void __launch_bounds__(KB) k_givens_proj(GState* st, int* run, const double2* dpart, int jh) {
+// krylov_givens_proj); the partials are summed as k_update sums them. Every
+// thread of the block calls it (the condition is uniform over the block).
+PSFD_D void givens_proj_block(GState* st, int* run, const double2* dpart, int jh) {
   __shared__ double2 hsum[MAXM + 2];
   __shared__ double wn2s;
   const int b = blockIdx.x;
@@ -309,6 +310,10 @@ __global__ void __launch_bounds__(KB) k_givens_proj(GState* st, int* run, const 
   givens_impl<true>(st, run, nullptr, 0, b, hv, hsum[cnt].x, wn2s);
 }
 
+__global__ void __launch_bounds__(KB) k_givens_proj(GState* st, int* run, const double2* dpart, int jh) {
+  givens_proj_block(st, run, dpart, jh);
+}
+
 void krylov_givens_proj(GState* st, int* run, const double2* dpart, int nbatch, hipStream_t s, int jh) {
   hipLaunchKernelGGL(k_givens_proj, dim3(nbatch), dim3(KB), 0, s, st, run, dpart, jh);
 }
@@ -326,7 +331,7 @@ void krylov_update(T* V, long long ldv, long long bsv, long long n, GState* st, 
 // back substitution y = R^{-1} g on the upper triangle of the rotated
 // Hessenberg matrix; the block stages R and g in LDS so that the single-thread
 // recurrence reads no global memory
-__global__ void __launch_bounds__(KB) k_solve_small(GState* st, const int* mask) {
+PSFD_D void solve_small_block(GState* st, const int* mask) {
   __shared__ double2 R[MAXM][MAXM], gl[MAXM + 1], yl[MAXM], cl[MAXM + 1], snl[MAXM];
   __shared__ double csl[MAXM];
   const int b = blockIdx.x;
@@ -373,8 +378,25 @@ __global__ void __launch_bounds__(KB) k_solve_small(GState* st, const int* mask)
   }
 }
 
+__global__ void __launch_bounds__(KB) k_solve_small(GState* st, const int* mask) { solve_small_block(st, mask); }
+
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s) {
   hipLaunchKernelGGL(k_solve_small, dim3(nbatch), dim3(KB), 0, s, st, mask);
+}
+
+// the last column's Givens step from its projections, then the back
+// substitution, in one launch (the block's barrier orders the state it writes
+// before the reads of the second part)
+__global__ void __launch_bounds__(KB) k_givens_proj_solve(GState* st, int* run, const double2* dpart, int jh,
+                                                          const int* mask) {
+  givens_proj_block(st, run, dpart, jh);
+  __syncthreads();
+  solve_small_block(st, mask);
+}
+
+void krylov_givens_proj_solve(GState* st, int* run, const double2* dpart, const int* mask, int nbatch, hipStream_t s,
+                              int jh) {
+  hipLaunchKernelGGL(k_givens_proj_solve, dim3(nbatch), dim3(KB), 0, s, st, run, dpart, jh, mask);
 }
 
 template <class T, class TX>

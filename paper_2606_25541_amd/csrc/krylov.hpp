@@ -99,6 +99,9 @@ void krylov_givens_proj(GState* st, int* run, const double2* dpart, int nbatch, 
 // the slots themselves. When slot k holds w before its update (raw_last == k),
 // cres_i -= cres_k h_i sc_i for i < k, so that cres applies to the slots as they are
 void krylov_solve_small(GState* st, const int* mask, int nbatch, hipStream_t s);
+// krylov_givens_proj (column jh) followed by krylov_solve_small (mask) in one launch
+void krylov_givens_proj_solve(GState* st, int* run, const double2* dpart, const int* mask, int nbatch, hipStream_t s,
+                              int jh);
 // x += sum_{i<k} y_i v_i for the instances with mask[b]; for those with rec[b]
 // also the restart residual from the basis, r = sum_{i<=k} cres_i slot_i, into
 // slot 0 (unnormalised) with ||r||^2 partials in part (LIN_BLOCKS per instance),
