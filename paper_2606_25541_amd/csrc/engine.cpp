@@ -205,6 +205,10 @@ static int env_int(const char* name, int dflt) {
   const char* e = std::getenv(name);
   return e ? std::atoi(e) : dflt;
 }
+static double env_double(const char* name, double dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::atof(e) : dflt;
+}
 // complex values per thread of an LDS FFT pass (see FftBudget)
 static int fft_elems(size_t esz) { return esz == 8 ? 16 : 8; }
 
@@ -291,8 +295,9 @@ Status device_consts(DeviceConsts*& out) {
 // ---------------------------------------------------------------------------
 Group::~Group() {
   for (auto& a : cycle_graph)
-    for (auto& c : a)
-      if (c.exec) (void)hipGraphExecDestroy(c.exec);
+    for (auto& b2 : a)
+      for (auto& c : b2)
+        if (c.exec) (void)hipGraphExecDestroy(c.exec);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   for (void* p : owned) (void)hipFree(p);
   for (hipEvent_t e : flag_ev)
@@ -380,9 +385,9 @@ Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec) {
   GALLOC(g.rpart, (size_t)g.rblk * 2 * 8 * B);
   HIPCHK(hipHostMalloc((void**)&g.h_run, sizeof(int) * B * 4, hipHostMallocDefault));
   // the solve flags, written by the cycle-start kernel itself (coherent, mapped)
-  HIPCHK(hipHostMalloc((void**)&g.h_flags, sizeof(int) * B, hipHostMallocCoherent | hipHostMallocMapped));
+  HIPCHK(hipHostMalloc((void**)&g.h_flags, sizeof(HostFlags) * B, hipHostMallocCoherent | hipHostMallocMapped));
   HIPCHK(hipHostGetDevicePointer((void**)&g.d_flags, g.h_flags, 0));
-  for (int b = 0; b < B; ++b) g.h_flags[b] = 0;
+  for (int b = 0; b < B; ++b) g.h_flags[b] = HostFlags{0, 0, 0.0};
   for (int i = 0; i < FLAG_SLOTS; ++i) HIPCHK(hipEventCreateWithFlags(&g.flag_ev[i], hipEventDisableTiming));
   HIPCHK(hipHostMalloc((void**)&g.h_dbl, sizeof(double) * (size_t)B * 2 * std::max(8, g.rblk), hipHostMallocDefault));
   HIPCHK(hipMemset(g.st, 0, sizeof(GState) * B));
@@ -618,6 +623,11 @@ int true_residual_every() {
 
 bool use_graphs() {
   const char* e = std::getenv("PSFD_GRAPH");
+  return !(e && std::atoi(e) == 0);
+}
+
+bool lite_restarts() {
+  const char* e = std::getenv("PSFD_LITE_RESTARTS");
   return !(e && std::atoi(e) == 0);
 }
 
@@ -923,12 +933,44 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   // only ever goes from 1 to 0, so flags written by a later cycle start than
   // the event's are as good. The host blocks only when more than FLAG_LAG
   // events are outstanding, so the GPU queue stays full.
-  const int max_cycles = o.max_iters + 2;  // every cycle that starts takes at least one step
+  // every cycle that starts takes at least one step; restarts without b - A x
+  // can make an instance wait (below) for at most FLAG_LAG + 2 cycles, near
+  // convergence and at the iteration limit
+  const int max_cycles = o.max_iters + 2 + 2 * (FLAG_LAG + 2);
   std::deque<int> pending;                 // snapshot slots in flight, oldest first
   bool done = false;
+  volatile HostFlags* hf = g.h_flags;
   auto snapshot_live = [&]() {
     for (int b = 0; b < B; ++b)
-      if (reinterpret_cast<volatile int*>(g.h_flags)[b]) return true;
+      if (hf[b].act) return true;
+    return false;
+  };
+  // Restarts with and without b - A x. Most restarts take the basis residual,
+  // and the launches of an unused b - A x (the FP64 apply and the residual
+  // kernel, ~18 us of launches that return at once) are left out of them. A
+  // restart includes b - A x at every `every`-th cycle (the device's cadence
+  // from the first restart), once any instance's residual is within NEAR_RATIO
+  // of its target (from then on: the device asks for b - A x near convergence
+  // and before it declares convergence), and whenever the flags show a pending
+  // request. An instance whose request meets a restart without b - A x keeps
+  // it and waits (cycle_start), so the choice affects speed, never results.
+  // PSFD_LITE_RESTARTS=0 includes b - A x in every restart; PSFD_NEAR_RATIO
+  // overrides NEAR_RATIO (0: requests are only seen in the flags, so that a
+  // test can make instances wait).
+  const double NEAR_RATIO = env_double("PSFD_NEAR_RATIO", 64.0);
+  const bool lite_ok = lite_restarts();
+  bool near = false;
+  auto want_full = [&](int cyc) {
+    if (!lite_ok || near || cyc % every == 0) return true;
+    for (int b = 0; b < B; ++b) {
+      if (!hf[b].act) continue;
+      if (hf[b].want) return true;
+      const double r = hf[b].ratio;
+      if (r > 0.0 && r <= NEAR_RATIO) {
+        near = true;
+        return true;
+      }
+    }
     return false;
   };
   const double cancel = cancel_threshold();
@@ -936,33 +978,41 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   // cycle's basis residual (left in v0 and its norm partials) where rres is;
   // ||r||^2 from the partials of b - A x or of the basis residual, summed in the
   // cycle start
-  auto cycle_start = [&](hipStream_t q) {
-    apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, refl, g.tres, q);  // A x
-    krylov_residual_parts<T>(g.b, g.r, (T*)g.basis, n3, n3, bsv, g.dpart, g.tres, B, q);
+  auto cycle_start = [&](hipStream_t q, bool full) {
+    if (full) {
+      apply_op<double2>(g, g.deps64, vr(g.x, n3), vr(g.r, n3), g.ws64, 0, transpose, refl, g.tres, q);  // A x
+      krylov_residual_parts<T>(g.b, g.r, (T*)g.basis, n3, n3, bsv, g.dpart, g.tres, B, q);
+    }
     krylov_cycle_start_sum(g.st, g.n2, g.dpart, g.lpart, g.abs_target, eta, g.m, cancel, every, g.mask, g.tres,
-                           g.rres, g.run, g.cyc, B, q, g.d_flags);
+                           g.rres, g.run, g.cyc, B, q, g.d_flags, full);
   };
   // every instance that runs a cycle starts it at j = 0 and stops for good
   // when it ends, so the running ones all stand at step `step`; the cycle's
   // solution update and the next restart's residual follow
-  auto cycle_body = [&](hipStream_t q) {
+  auto cycle_body = [&](hipStream_t q, bool full) {
     bool solved = false;
     for (int step = 0; step < g.m; ++step)
       solved = arnoldi_step<T>(g, transpose, refl, q, step, step == g.m - 1 ? g.cyc : nullptr);
     if (!solved) krylov_solve_small(g.st, g.cyc, B, q);
     krylov_lincomb_res<T, double2>((T*)g.basis, n3, bsv, g.x, n3, n3, g.st, g.cyc, g.rres, g.lpart, B, q);
-    cycle_start(q);
+    cycle_start(q, full);
   };
   const bool graphs = use_graphs();
   const std::string key = launch_key(eta, every);
-  cycle_start(s);
+  for (int b = 0; b < B; ++b) {
+    hf[b].want = 0;
+    hf[b].ratio = 0.0;
+  }
+  cycle_start(s, true);  // the first restart evaluates b - A x
   for (int cyc = 0; cyc < max_cycles && !done; ++cyc) {
     if (cyc > 0) {
+      const bool full = want_full(cyc);
       if (graphs) {
-        Status gs = replay(g, g.cycle_graph[transpose ? 1 : 0][refl ? 1 : 0], key, s, cycle_body);
+        Status gs = replay(g, g.cycle_graph[transpose ? 1 : 0][refl ? 1 : 0][full ? 1 : 0], key, s,
+                           [&](hipStream_t q) { cycle_body(q, full); });
         if (!gs.ok()) return gs;
       } else {
-        cycle_body(s);
+        cycle_body(s, full);
       }
       HIPCHK(hipGetLastError());
     }

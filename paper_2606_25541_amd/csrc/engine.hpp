@@ -113,8 +113,8 @@ struct Group {
   double2 *adn = nullptr, *aup = nullptr, *eup = nullptr, *ord = nullptr, *eup2 = nullptr;
   double* rpart = nullptr;
   int rblk = 1;
-  int* h_flags = nullptr;    // the solve flags in mapped, coherent host memory (B), and
-  int* d_flags = nullptr;    // the device's address of it, written by each cycle start
+  HostFlags* h_flags = nullptr;  // the solve flags in mapped, coherent host memory (B), and
+  HostFlags* d_flags = nullptr;  // the device's address of it, written by each cycle start
   hipEvent_t flag_ev[FLAG_SLOTS] = {};
   int* h_run = nullptr;      // pinned host mirrors
   double* h_dbl = nullptr;
@@ -127,7 +127,7 @@ struct Group {
     std::string key;
     bool failed = false;
   };
-  Captured cycle_graph[2][2];   // [transpose][refl]
+  Captured cycle_graph[2][2][2];   // [transpose][refl][restart with b - A x]
   hipStream_t cap_stream = nullptr;  // capture only (launches are not executed there)
   std::vector<void*> owned;
   ~Group();
@@ -136,6 +136,9 @@ struct Group {
 // Whether restart cycles and the server's Arnoldi blocks run as captured HIP
 // graphs (PSFD_GRAPH=0 issues the same launches one by one; read per call).
 bool use_graphs();
+// Whether a solve may leave b - A x out of the restarts that do not use it
+// (PSFD_LITE_RESTARTS=0: every restart launches it; read per call).
+bool lite_restarts();
 // Replays the captured sequence `c` on stream s, capturing `issue(cs)` first when
 // the key differs (cs is the group's capture stream).
 Status replay(Group& g, Group::Captured& c, const std::string& key, hipStream_t s,

@@ -510,14 +510,21 @@ PSFD_D double sum_partials(const double* part, int nblk, int b) {
   return sm[0].x;
 }
 
+// fp64 = false: this restart has no b - A x (the launch sequence left it out);
+// an instance that asked for one keeps its request and starts no cycle
 PSFD_D void cycle_start(GState* st, const double* rnorm2, const double* abs_target, double eta, int m,
-                        double cancel_thr, int every, int* act, int* tres, int* rres, int* run, int* cyc, int b) {
+                        double cancel_thr, int every, int* act, int* tres, int* rres, int* run, int* cyc, int b,
+                        bool fp64 = true) {
   cyc[b] = 0;
   run[b] = 0;
   const bool was_true = tres[b] != 0;
   tres[b] = 0;
   rres[b] = 0;
   if (!act[b]) return;
+  if (was_true && !fp64) {
+    tres[b] = 1;
+    return;
+  }
   GState& S = st[b];
   const double rn = sqrt(rnorm2[b]);
   if (!(rn == rn) || isinf(rn)) { S.status = PSFD_ERR_NONFINITE; act[b] = 0; return; }
@@ -563,22 +570,28 @@ __global__ void k_cycle_start(GState* st, const double* rnorm2, const double* ab
 
 // the same, with ||r||^2 summed here from the partials of b - A x (tpart,
 // RED_BLOCKS per instance) or of the basis residual (lpart, LIN_BLOCKS), in the
-// order of k_sum_part, and stored to rnorm2; act[b] is also written to
-// host_act[b] (host memory mapped for the device, or null)
+// order of k_sum_part, and stored to rnorm2. fp64: whether b - A x was formed
+// at this restart (see cycle_start). With host (host memory mapped for the
+// device) the instance's flags are also written there.
 __global__ void __launch_bounds__(KB) k_cycle_start_sum(GState* st, double* rnorm2, const double* tpart,
                                                         const double* lpart, const double* abs_target, double eta,
                                                         int m, double cancel_thr, int every, int* act, int* tres,
-                                                        int* rres, int* run, int* cyc, int* host_act) {
+                                                        int* rres, int* run, int* cyc, int fp64, HostFlags* host) {
   const int b = blockIdx.x;
   const int t = tres[b], r = rres[b];
-  if (t || r) {
+  const bool have = (t && fp64) || (!t && r);
+  if (have) {
     const double n2 = t ? sum_partials(tpart, RED_BLOCKS, b) : sum_partials(lpart, LIN_BLOCKS, b);
     if (threadIdx.x == 0) rnorm2[b] = n2;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    cycle_start(st, rnorm2, abs_target, eta, m, cancel_thr, every, act, tres, rres, run, cyc, b);
-    if (host_act) host_act[b] = act[b];
+    cycle_start(st, rnorm2, abs_target, eta, m, cancel_thr, every, act, tres, rres, run, cyc, b, fp64 != 0);
+    if (host) {
+      host[b].act = act[b];
+      host[b].want = tres[b];
+      if (have && act[b]) host[b].ratio = abs_target[b] > 0.0 ? sqrt(rnorm2[b]) / abs_target[b] : 0.0;
+    }
   }
 }
 
@@ -591,9 +604,10 @@ void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_targ
 
 void krylov_cycle_start_sum(GState* st, double* rnorm2, const double* tpart, const double* lpart,
                             const double* abs_target, double eta, int m, double cancel_thr, int every, int* act,
-                            int* tres, int* rres, int* run, int* cyc, int nbatch, hipStream_t s, int* host_act) {
+                            int* tres, int* rres, int* run, int* cyc, int nbatch, hipStream_t s, HostFlags* host,
+                            bool fp64) {
   hipLaunchKernelGGL(k_cycle_start_sum, dim3(nbatch), dim3(KB), 0, s, st, rnorm2, tpart, lpart, abs_target, eta, m,
-                     cancel_thr, every, act, tres, rres, run, cyc, host_act);
+                     cancel_thr, every, act, tres, rres, run, cyc, fp64 ? 1 : 0, host);
 }
 
 

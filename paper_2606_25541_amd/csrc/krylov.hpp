@@ -22,6 +22,15 @@ constexpr int PSTR = MAXM + 2;    // partial stride: up to MAXM + 1 dots and ||w
 // kernel that runs them needs at least this many threads per block
 constexpr int GIVENS_THREADS = 256;
 
+// What a solve's cycle start reports to the host per instance, in host memory
+// mapped for the device: still active, b - A x wanted at the next restart, and
+// ||r|| / target at the last restart that formed a residual.
+struct HostFlags {
+  int act;
+  int want;
+  double ratio;
+};
+
 // Device-resident state of one GMRES(m) instance. All scalars are FP64.
 struct GState {
   int j;            // index of the newest basis vector v_j (the column being built)
@@ -149,11 +158,14 @@ void krylov_cycle_start(GState* st, const double* rnorm2, const double* abs_targ
 // krylov_residual / krylov_sum_norm: from the b - A x partials in tpart
 // (RED_BLOCKS per instance) where tres is set, from the basis-residual partials
 // in lpart (LIN_BLOCKS) where rres is; the sum is also stored to rnorm2. With
-// host_act (host memory the device can write), act[b] is also written there.
+// host (host memory the device can write) each instance's HostFlags are
+// written there. fp64 = false: no b - A x was formed for this restart; an
+// instance that asked for one keeps its request and starts no cycle (it waits
+// for a restart with b - A x).
 void krylov_cycle_start_sum(GState* st, double* rnorm2, const double* tpart, const double* lpart,
                             const double* abs_target, double eta, int m, double cancel_thr, int every, int* act,
                             int* tres, int* rres, int* run, int* cyc, int nbatch, hipStream_t s,
-                            int* host_act = nullptr);
+                            HostFlags* host = nullptr, bool fp64 = true);
 // start a cycle from rnorm2[b] = ||r_b||^2 (v0 = r unnormalised, as left by
 // krylov_residual; inv_norm = 1 / ||r||): g = (||r||, 0, ...), j = 0,
 // target = max(abs_target[b], eta ||r||); run[b] = mask[b] && ||r|| > abs_target[b]

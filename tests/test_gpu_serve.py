@@ -350,3 +350,31 @@ def test_graph_replay_equals_eager_launches(n, monkeypatch):
     for e, o, i in runs:
         assert i == i0
         assert torch.equal(e, e0) and torch.equal(o, o0)
+
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_restarts_without_residual_keep_results(n, monkeypatch):
+    """Restarts that leave out the FP64 b - A x they do not use (the default)
+    against restarts that all form it (PSFD_LITE_RESTARTS=0), and against a host
+    blind to the residual ratio (PSFD_NEAR_RATIO=0), whose instances ask for b -
+    A x at restarts without it and wait for one: bitwise equal fields, orders,
+    step and cycle counts."""
+    from paper_2606_25541_amd import api
+    dev = device()
+    p = prob(n, 32 if n == 64 else 8, 6.0, 20.0, 1)
+    de = clips.manhattan(n, n, p.nz, p.lx_nm, p.ly_nm, seed=700 + n)
+    d = torch.from_numpy(de).to(dev)
+    plan = api.Plan(p, rtol=1e-9, precision="mixed", restart=8)
+    res = {}
+    for name, env in (("default", {}), ("blind", {"PSFD_NEAR_RATIO": "0"}),
+                      ("all", {"PSFD_NEAR_RATIO": "0", "PSFD_LITE_RESTARTS": "0"})):
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        res[name] = plan.psfd_solve(d)
+        torch.cuda.synchronize()
+    e0, o0, i0 = res["all"]
+    say("  restarts", {k: v[2]["iters"] for k, v in res.items()})
+    assert i0["status"] == 0
+    for e, o, i in res.values():
+        assert i == i0
+        assert torch.equal(e, e0) and torch.equal(o, o0)
