@@ -927,16 +927,12 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   vec_norm2<double2>(g.b, n3, n3, g.dpart, g.n2b, g.mask, B, s);
   krylov_solve_init(g.st, g.n2b, g.rtol, g.abs_target, o.max_iters, g.mask, B, s);
   const double eta = g.prec == PSFD_MIXED ? o.inner_eta : 0.0;
-  // Each cycle start writes the active flags to mapped host memory, and an event
-  // follows it; the host polls the events without blocking and stops launching
-  // once the flags read after one show no active instance. An instance's flag
-  // only ever goes from 1 to 0, so flags written by a later cycle start than
-  // the event's are as good. The host blocks only when more than FLAG_LAG
-  // events are outstanding, so the GPU queue stays full.
-  // every cycle that starts takes at least one step; restarts without b - A x
-  // can make an instance wait (below) for at most FLAG_LAG + 2 cycles, near
-  // convergence and at the iteration limit
-  const int max_cycles = o.max_iters + 2 + 2 * (FLAG_LAG + 2);
+  // Each cycle start writes the active flags to mapped host memory. The host
+  // reads them before every launch and stops launching once no instance is
+  // active; an instance's flag only ever goes from 1 to 0, so any read is a
+  // valid snapshot. An event after every FLAG_EVERY-th cycle paces the host:
+  // it blocks only when more than FLAG_LAG events are outstanding, so the GPU
+  // queue stays full while few cycles are queued past convergence.
   std::deque<int> pending;                 // snapshot slots in flight, oldest first
   bool done = false;
   volatile HostFlags* hf = g.h_flags;
@@ -958,6 +954,13 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   // overrides NEAR_RATIO (0: requests are only seen in the flags, so that a
   // test can make instances wait).
   const double NEAR_RATIO = env_double("PSFD_NEAR_RATIO", 64.0);
+  // an event every FLAG_EVERY cycles, at most FLAG_LAG of them outstanding
+  // (PSFD_EV_EVERY, PSFD_EV_LAG override them for tuning)
+  const int EV_EVERY = std::max(1, env_int("PSFD_EV_EVERY", FLAG_EVERY)), EV_LAG = env_int("PSFD_EV_LAG", FLAG_LAG);
+  // every cycle that starts takes at least one step; restarts without b - A x
+  // can make an instance wait (below) for as many cycles as the host runs
+  // ahead, near convergence and at the iteration limit
+  const int max_cycles = o.max_iters + 2 + 2 * (EV_EVERY * (EV_LAG + 1) + 2);
   const bool lite_ok = lite_restarts();
   bool near = false;
   auto want_full = [&](int cyc) {
@@ -1000,6 +1003,7 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   const bool graphs = use_graphs();
   const std::string key = launch_key(eta, every);
   for (int b = 0; b < B; ++b) {
+    hf[b].act = act[b] ? 1 : 0;  // until the first cycle start writes it
     hf[b].want = 0;
     hf[b].ratio = 0.0;
   }
@@ -1016,12 +1020,18 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
       }
       HIPCHK(hipGetLastError());
     }
-    const int slot = cyc % FLAG_SLOTS;
-    HIPCHK(hipEventRecord(g.flag_ev[slot], s));
-    pending.push_back(slot);
+    // the flags are valid at any time (an instance's act only goes to 0, and
+    // only once its solve has ended); events every EV_EVERY cycles keep the
+    // host at most FLAG_LAG events ahead
+    if (!snapshot_live()) break;
+    if (cyc % EV_EVERY == 0) {
+      const int slot = (cyc / EV_EVERY) % FLAG_SLOTS;
+      HIPCHK(hipEventRecord(g.flag_ev[slot], s));
+      pending.push_back(slot);
+    }
     while (!pending.empty()) {
       const int old = pending.front();
-      hipError_t q = pending.size() > FLAG_LAG ? hipEventSynchronize(g.flag_ev[old]) : hipEventQuery(g.flag_ev[old]);
+      hipError_t q = pending.size() > EV_LAG ? hipEventSynchronize(g.flag_ev[old]) : hipEventQuery(g.flag_ev[old]);
       if (q == hipErrorNotReady) break;
       if (q != hipSuccess) return hip_status(q, "solve flags");
       pending.pop_front();

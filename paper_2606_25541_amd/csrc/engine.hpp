@@ -73,7 +73,8 @@ Status device_consts(DeviceConsts*& out);
 // outstanding before the host waits for the oldest. Kernels launched for
 // finished instances are no-ops (every kernel tests its flags).
 constexpr int FLAG_SLOTS = 4;
-constexpr int FLAG_LAG = 2;
+constexpr int FLAG_EVERY = 2;  // a solve records an event after every FLAG_EVERY-th cycle
+constexpr int FLAG_LAG = 1;    // and runs at most FLAG_LAG such events ahead of the GPU
 
 // B instances of one grid shape with every device buffer a solve needs.
 struct Group {
