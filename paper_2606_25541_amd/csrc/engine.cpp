@@ -387,7 +387,7 @@ Status group_alloc(Group& g, const Shape& sh, int B, int m, int prec) {
   // the solve flags, written by the cycle-start kernel itself (coherent, mapped)
   HIPCHK(hipHostMalloc((void**)&g.h_flags, sizeof(HostFlags) * B, hipHostMallocCoherent | hipHostMallocMapped));
   HIPCHK(hipHostGetDevicePointer((void**)&g.d_flags, g.h_flags, 0));
-  for (int b = 0; b < B; ++b) g.h_flags[b] = HostFlags{0, 0, 0.0};
+  for (int b = 0; b < B; ++b) g.h_flags[b] = HostFlags{0, 0, 0.0, -1, 0};
   for (int i = 0; i < FLAG_SLOTS; ++i) HIPCHK(hipEventCreateWithFlags(&g.flag_ev[i], hipEventDisableTiming));
   HIPCHK(hipHostMalloc((void**)&g.h_dbl, sizeof(double) * (size_t)B * 2 * std::max(8, g.rblk), hipHostMallocDefault));
   HIPCHK(hipMemset(g.st, 0, sizeof(GState) * B));
@@ -943,16 +943,20 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   };
   // Restarts with and without b - A x. Most restarts take the basis residual,
   // and the launches of an unused b - A x (the FP64 apply and the residual
-  // kernel, ~18 us of launches that return at once) are left out of them. A
-  // restart includes b - A x at every `every`-th cycle (the device's cadence
-  // from the first restart), once any instance's residual is within NEAR_RATIO
-  // of its target (from then on: the device asks for b - A x near convergence
-  // and before it declares convergence), and whenever the flags show a pending
-  // request. An instance whose request meets a restart without b - A x keeps
-  // it and waits (cycle_start), so the choice affects speed, never results.
-  // PSFD_LITE_RESTARTS=0 includes b - A x in every restart; PSFD_NEAR_RATIO
-  // overrides NEAR_RATIO (0: requests are only seen in the flags, so that a
-  // test can make instances wait).
+  // kernel, launches that return at once) are left out of them. A restart
+  // includes b - A x at every `every`-th cycle (the device's cadence from the
+  // first restart), whenever the flags show a pending request, and once any
+  // instance may be near its target: the host runs a few cycles ahead of the
+  // flags, so it extrapolates each instance's ||r|| / target from its last two
+  // readings (per cycle started) to the restart it is about to launch; while an
+  // instance has fewer than two readings, every restart includes b - A x. Near
+  // stays on for the rest of the solve (the device asks for b - A x near convergence and
+  // before it declares convergence). An instance whose request meets a restart
+  // without b - A x keeps it and waits (cycle_start), so the choice affects
+  // speed, never results. PSFD_LITE_RESTARTS=0 includes b - A x in every
+  // restart; PSFD_NEAR_RATIO overrides NEAR_RATIO (0: requests are only seen
+  // in the flags and every instance counts as far, so that a test can make
+  // instances wait).
   const double NEAR_RATIO = env_double("PSFD_NEAR_RATIO", 64.0);
   // an event every FLAG_EVERY cycles, at most FLAG_LAG of them outstanding
   // (PSFD_EV_EVERY, PSFD_EV_LAG override them for tuning)
@@ -963,18 +967,29 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   const int max_cycles = o.max_iters + 2 + 2 * (EV_EVERY * (EV_LAG + 1) + 2);
   const bool lite_ok = lite_restarts();
   bool near = false;
+  struct Reading { int c = -1; double r = 0.0; };
+  std::vector<Reading> last(B), prev(B);
   auto want_full = [&](int cyc) {
-    if (!lite_ok || near || cyc % every == 0) return true;
+    if (!lite_ok || near) return true;
+    bool full = cyc % every == 0;
     for (int b = 0; b < B; ++b) {
       if (!hf[b].act) continue;
-      if (hf[b].want) return true;
+      if (hf[b].want) full = true;
+      const int c = hf[b].cycles;
       const double r = hf[b].ratio;
-      if (r > 0.0 && r <= NEAR_RATIO) {
-        near = true;
-        return true;
+      if (r > 0.0 && c != last[b].c) {
+        prev[b] = last[b];
+        last[b] = Reading{c, r};
       }
+      if (NEAR_RATIO <= 0.0) continue;
+      if (prev[b].c < 0 || last[b].c <= prev[b].c) {
+        full = true;  // fewer than two readings: this restart includes b - A x
+        continue;
+      }
+      const double rate = std::pow(last[b].r / prev[b].r, 1.0 / (last[b].c - prev[b].c));
+      if (last[b].r * std::pow(std::min(rate, 1.0), std::max(0, cyc - last[b].c)) <= NEAR_RATIO) near = true;
     }
-    return false;
+    return full || near;
   };
   const double cancel = cancel_threshold();
   // the restart's residual: b - A x (FP64) where tres is set, the previous
@@ -1006,6 +1021,7 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
     hf[b].act = act[b] ? 1 : 0;  // until the first cycle start writes it
     hf[b].want = 0;
     hf[b].ratio = 0.0;
+    hf[b].cycles = -1;
   }
   cycle_start(s, true);  // the first restart evaluates b - A x
   for (int cyc = 0; cyc < max_cycles && !done; ++cyc) {

@@ -590,7 +590,10 @@ __global__ void __launch_bounds__(KB) k_cycle_start_sum(GState* st, double* rnor
     if (host) {
       host[b].act = act[b];
       host[b].want = tres[b];
-      if (have && act[b]) host[b].ratio = abs_target[b] > 0.0 ? sqrt(rnorm2[b]) / abs_target[b] : 0.0;
+      if (have && act[b]) {
+        host[b].ratio = abs_target[b] > 0.0 ? sqrt(rnorm2[b]) / abs_target[b] : 0.0;
+        host[b].cycles = st[b].cycles;
+      }
     }
   }
 }

@@ -23,12 +23,15 @@ constexpr int PSTR = MAXM + 2;    // partial stride: up to MAXM + 1 dots and ||w
 constexpr int GIVENS_THREADS = 256;
 
 // What a solve's cycle start reports to the host per instance, in host memory
-// mapped for the device: still active, b - A x wanted at the next restart, and
-// ||r|| / target at the last restart that formed a residual.
+// mapped for the device: still active, b - A x wanted at the next restart,
+// ||r|| / target at the last restart that formed a residual, and the cycles
+// started by then.
 struct HostFlags {
   int act;
   int want;
   double ratio;
+  int cycles;
+  int pad;
 };
 
 // Device-resident state of one GMRES(m) instance. All scalars are FP64.
