@@ -933,7 +933,7 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   // valid snapshot. An event after every FLAG_EVERY-th cycle paces the host:
   // it blocks only when more than FLAG_LAG events are outstanding, so the GPU
   // queue stays full while few cycles are queued past convergence.
-  std::deque<int> pending;                 // snapshot slots in flight, oldest first
+  std::deque<int> pending;  // event slots in flight, oldest first
   bool done = false;
   volatile HostFlags* hf = g.h_flags;
   auto snapshot_live = [&]() {
@@ -950,13 +950,13 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
   // flags, so it extrapolates each instance's ||r|| / target from its last two
   // readings (per cycle started) to the restart it is about to launch; while an
   // instance has fewer than two readings, every restart includes b - A x. Near
-  // stays on for the rest of the solve (the device asks for b - A x near convergence and
-  // before it declares convergence). An instance whose request meets a restart
-  // without b - A x keeps it and waits (cycle_start), so the choice affects
-  // speed, never results. PSFD_LITE_RESTARTS=0 includes b - A x in every
-  // restart; PSFD_NEAR_RATIO overrides NEAR_RATIO (0: requests are only seen
-  // in the flags and every instance counts as far, so that a test can make
-  // instances wait).
+  // stays on for the rest of the solve (the device asks for b - A x near
+  // convergence and before it declares convergence). An instance whose request
+  // meets a restart without b - A x keeps it and waits (cycle_start), so the
+  // choice affects speed, never results. PSFD_LITE_RESTARTS=0 includes b - A x
+  // in every restart; PSFD_NEAR_RATIO overrides NEAR_RATIO (0: requests are
+  // only seen in the flags and every instance counts as far, so that a test
+  // can make instances wait).
   const double NEAR_RATIO = env_double("PSFD_NEAR_RATIO", 64.0);
   // an event every FLAG_EVERY cycles, at most FLAG_LAG of them outstanding
   // (PSFD_EV_EVERY, PSFD_EV_LAG override them for tuning)
