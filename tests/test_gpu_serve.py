@@ -378,3 +378,29 @@ def test_restarts_without_residual_keep_results(n, monkeypatch):
     for e, o, i in res.values():
         assert i == i0
         assert torch.equal(e, e0) and torch.equal(o, o0)
+
+
+def test_iteration_limit_with_restarts_without_residual(monkeypatch):
+    """A solve stopped by its iteration limit (11 steps of GMRES(4)) reports
+    NOT_CONVERGED with the same steps, residual and field whether its restarts
+    leave out the unused b - A x (the default), make instances wait for it
+    (PSFD_NEAR_RATIO=0) or all form it (PSFD_LITE_RESTARTS=0)."""
+    from paper_2606_25541_amd import _lib as L, api
+    dev = device()
+    p = prob(64, 32, 6.0, 20.0, 1)
+    de = clips.manhattan(64, 64, p.nz, p.lx_nm, p.ly_nm, seed=901)
+    d = torch.from_numpy(de).to(dev)
+    plan = api.Plan(p, rtol=1e-12, precision="mixed", restart=4, max_iters=11)
+    res = {}
+    for name, env in (("default", {}), ("blind", {"PSFD_NEAR_RATIO": "0"}),
+                      ("all", {"PSFD_NEAR_RATIO": "0", "PSFD_LITE_RESTARTS": "0"})):
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        res[name] = plan.psfd_solve(d)
+        torch.cuda.synchronize()
+    e0, o0, i0 = res["all"]
+    say("  limit", {k: (v[2]["iters"], v[2]["status"]) for k, v in res.items()})
+    assert i0["status"] == L.PSFD_NOT_CONVERGED and 11 <= i0["iters"] <= 12
+    for e, o, i in res.values():
+        assert i == i0
+        assert torch.equal(e, e0) and torch.equal(o, o0)
