@@ -417,11 +417,13 @@ __global__ void __launch_bounds__(KB) k_lincomb_res(T* V, long long ldv, long lo
   double2 acc[1] = {make_double2(0, 0)};
   const int nv = dor ? k + 1 : k;  // slots read: the cycle's basis, and slot k for the residual
   // basis vectors in groups of LG with unconditional (clamped) loads, all in
-  // flight together with the x load (two groups for a restart length of 10).
+  // flight together with the x load: one group for the 9 slots of an FP32
+  // GMRES(8) restart, groups of 8 for FP64 slots (the faster width for each,
+  // as measured).
   // The group loop stays rolled: unrolled, the compiler keeps every coefficient
   // of the LDS tables in registers across the element loop (hundreds of VGPRs,
   // one wavefront per SIMD); rolled, each group reads its coefficients at use.
-  constexpr int LG = 8;
+  constexpr int LG = sizeof(T) == 8 ? 9 : 8;
   for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += (long long)gridDim.x * KB) {
     double2 sx = make_double2(0, 0), sr = make_double2(0, 0);
     const double2 xv = to_d(xb[e]);
