@@ -826,7 +826,7 @@ bool arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh, cons
   // the projections of the new vector where the shape allows (arnoldi_inverse);
   // elsewhere the projection pass follows it.
   const bool lock = jh >= 0;
-  const GivensTask gt{g.st, g.run, g.part, RED_BLOCKS};
+  const GivensTask gt{g.st, g.run, g.part, RED_BLOCKS, 0};
   const double* isc = &g.st[0].inv_norm;
   const long long iss = (long long)(sizeof(GState) / sizeof(double));
   bool upd = false, upd_slots = false;
@@ -867,7 +867,7 @@ bool arnoldi_step(Group& g, int transpose, int refl, hipStream_t s, int jh, cons
       if (jh > 0) launch_tile<T, false, LD_UPD_VX, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
       else launch_tile<T, false, LD_UPD_SLOT, ST_PLAIN>(a, np, g.B, c.full.nthr, c.full.lds, s);
     }
-    const GivensTask gp{g.st, g.run, g.part, np};
+    const GivensTask gp{g.st, g.run, g.part, np, 0};
     apply_stage<T>(g, 1, deps_of<T>(g), vin, vout, (T*)g.wsP, 1, transpose, refl, g.run, s, nullptr, 0,
                    jh > 0 ? &gp : nullptr);
   }
@@ -1047,7 +1047,7 @@ static Status linear_solve(Group& g, const Opts& o, const std::vector<int>& act,
     }
     while (!pending.empty()) {
       const int old = pending.front();
-      hipError_t q = pending.size() > EV_LAG ? hipEventSynchronize(g.flag_ev[old]) : hipEventQuery(g.flag_ev[old]);
+      hipError_t q = (int)pending.size() > EV_LAG ? hipEventSynchronize(g.flag_ev[old]) : hipEventQuery(g.flag_ev[old]);
       if (q == hipErrorNotReady) break;
       if (q != hipSuccess) return hip_status(q, "solve flags");
       pending.pop_front();
